@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark: batched OCP-QP solves per second on one MI355X.
+
+Workload: 1024 same-size mass-spring QPs (8 masses: nx=16, nu=7, N=30,
+dt=0.2, Q=I, R=0.1 I, |u|<=0.5, |x_pos|<=4, x0 ~ U[-2,2]^16 per instance),
+synthetic and seeded, resident in HBM before the timed region.  One step =
+one full IPM solve of the whole batch (cold start to the KKT tolerance).
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(algorithmic bytes / kernel time from HIP events on the launch stream) and
+the CPU oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "OCP-QP solves/sec at KKT res <=1e-6 (batched, 1 GPU); p50/p99 serve latency"
+HBM_PEAK_GBS = 8000.0
+KKT_OK = 1e-6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("ipm_kernel.hip", "layout.h"):
+        with open(os.path.join(ROOT, "paper_2003_02547_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(variant_key, launches_per_step):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    rec = t.get(variant_key)
+    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(qps, seconds, tol):
+    import concurrent.futures as cf
+    from oracle import oracle as O
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    arg = O.Arg.with_tol(tol)
+    t0 = time.perf_counter()
+
+    def work(k):
+        cnt, i = 0, k
+        while time.perf_counter() - t0 < seconds:
+            r = O.solve(qps[i % len(qps)], arg)
+            cnt += int(r.status == O.SUCCESS)
+            i += threads
+        return cnt
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        total = sum(ex.map(work, range(threads)))
+    el = time.perf_counter() - t0
+    return {"value": total / el, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"{total} instances of the same workload (round-robin over the batch), "
+                      f"{threads} threads, one instance per thread at a time, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--instances", type=int, default=1024)
+    ap.add_argument("--mode", choices=["f64"], default="f64")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        sys.exit("bench.py: this build measures one GPU only (--gpus 1). Instances are independent; "
+                 "the multi-GPU design shards the batch by estimated cost with no exchange.")
+
+    import numpy as np
+    import torch
+
+    from paper_2003_02547_amd import binding as B
+    from paper_2003_02547_amd import perfmodel, workloads as W
+
+    torch.cuda.set_device(0)
+    log(f"bench: generating {args.instances} mass-spring QPs (nx=16, nu=7, N=30)")
+    qps = [W.mass_spring_chain8(i) for i in range(args.instances)]
+    arg = B.default_arg(B.MODE_F64)
+    batch = B.Batch(qps, arg)
+    batch.load().sync()
+    variant = batch.variant(0)[1]
+    log(f"bench: variant {variant}, device bytes {batch.dev_bytes / 2**20:.1f} MiB; warmup {args.warmup}")
+    stream = batch.stream
+    for _ in range(args.warmup):
+        batch.solve()
+    torch.cuda.synchronize()
+    log(f"bench: timing {args.steps} steps")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        batch.solve()
+        e.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms = np.array([s.elapsed_time(e) for s, e in ev])
+    batch.fetch().sync()
+    res = batch.results()
+    status = np.array([r.status for r in res])
+    kkt = np.array([float(np.max(r.res)) for r in res])
+    iters = np.array([r.iters for r in res])
+    ok = int(np.sum((status == B.SUCCESS) & (kkt <= KKT_OK)))
+    wall = t1 - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = ok * args.steps / wall
+
+    dbytes = np.array([perfmodel.data_bytes(q) for q in qps], dtype=np.float64)
+    alg_bytes = float(np.sum(dbytes * (iters + 1)))           # one data read per residual evaluation
+    alg_flops = float(sum(perfmodel.flops_per_iter(q) * it for q, it in zip(qps, iters)))
+    kern_s = float(np.mean(kern_ms)) * 1e-3
+    achieved = alg_bytes / kern_s / 1e9
+    vkey = "ipm_kernel<%d,%d,%d>" % variant
+    traffic = traffic_from_profile(vkey, 1)
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "mass_spring_8masses_x1024", "instances": args.instances, "nx": 16, "nu": 7,
+                   "N": 30, "path": "f64", "kernel": vkey},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": traffic},
+        "kernel_ms": round(float(np.mean(kern_ms)), 4),
+        "fp64_tflops": round(alg_flops / kern_s / 1e12, 4),
+        "solves_ok": ok,
+        "iters_p50": float(np.percentile(iters, 50)),
+        "iters_p99": float(np.percentile(iters, 99)),
+        "max_kkt_res": float(np.max(kkt)),
+        "latency_ms_p50": round(float(np.percentile(kern_ms, 50)), 4),
+        "latency_ms_p99": round(float(np.percentile(kern_ms, 99)), 4),
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
+        line["cpu_baseline"] = cpu_baseline(qps, args.cpu_seconds, 1e-8)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * oqp.h -- C-ABI of the batched OCP-QP interior-point solver for MI355X.
+ *
+ * Problem (paper "HPIPM: a high-performance quadratic programming framework
+ * for model predictive control", Section 2.2, the OCP QP without slacks):
+ *
+ *   min  sum_{n=0}^{N} 1/2 [u_n; x_n]' [[R_n, S_n], [S_n', Q_n]] [u_n; x_n] + r_n'u_n + q_n'x_n
+ *   s.t. x_{n+1} = A_n x_n + B_n u_n + b_n,                        n = 0..N-1
+ *        lbu_n <= u_n[idxbu_n] <= ubu_n,  lbx_n <= x_n[idxbx_n] <= ubx_n,
+ *        lg_n <= D_n u_n + C_n x_n <= ug_n,                        n = 0..N
+ *
+ * S_n is nu_n x nx_n.  All sizes may vary per stage.  An initial-state
+ * constraint x_0 = x0 is written as a box with equal limits (Section 2.2).
+ *
+ * Solver (Section 3 and Section 4.2): primal-dual interior-point method in the
+ * delta formulation of eq:alg:pdipm:delta, Newton systems reduced to
+ * eq:alg:kkt and factorized by the square-root Riccati recursion, Mehrotra
+ * predictor-corrector with the conditional corrector, primal regularization
+ * and lower clamps on multipliers and slacks; optional FP32 factorization
+ * corrected by FP64 iterative refinement on the full Newton system
+ * (Section 3.4).
+ *
+ * Memory (Section 1, memory management): the library never allocates.  Every
+ * object lives in memory the caller provides, sized by the matching *_bytes
+ * call.  Device memory is a caller-owned buffer (for example a byte tensor)
+ * and all device work is enqueued on a caller-owned HIP stream.
+ *
+ * Conventions: matrices are column-major FP64 with an explicit leading
+ * dimension; index lists are int32 and 0-based.  Return values: 0 on success,
+ * a negative OQP_E* code on a usage or device error (nothing is printed and
+ * the process is never aborted; oqp_last_error() describes the failure),
+ * OQP_PENDING (1) where documented.
+ */
+#ifndef OQP_H
+#define OQP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define OQP_OK 0
+#define OQP_PENDING 1
+#define OQP_EINVAL (-1)  /* bad argument: sizes, indices, lo > hi, NULL */
+#define OQP_ENOMEM (-2)  /* caller-provided buffer smaller than required */
+#define OQP_EDEVICE (-3) /* a HIP call failed */
+#define OQP_EBUSY (-4)   /* no capacity to admit a request (serving) */
+#define OQP_ESTATE (-5)  /* call out of order (e.g. solve before load) */
+
+/* ---- per-instance solver outcome (oqp_stat.status) --------------------- */
+#define OQP_SUCCESS 0  /* all four residual norms within tolerance */
+#define OQP_MAX_ITER 1 /* iteration limit reached */
+#define OQP_MIN_STEP 2 /* step length fell below alpha_min */
+#define OQP_NAN 3      /* a residual norm or the duality measure is NaN */
+
+/* ---- modes ------------------------------------------------------------- */
+#define OQP_MODE_F64 0   /* FP64 factorization ("speed" mode, delta formulation) */
+#define OQP_MODE_MIXED 1 /* FP32 factorization + FP64 iterative refinement */
+
+typedef struct oqp_dims oqp_dims;
+typedef struct oqp_qp oqp_qp;
+typedef struct oqp_batch oqp_batch;
+
+/* Solver arguments (Section 4.2).  Fill with oqp_arg_default. */
+typedef struct {
+    int mode;          /* OQP_MODE_* */
+    double tol_stat;   /* exit: ||r_g||_inf <= tol_stat */
+    double tol_eq;     /* exit: ||r_b||_inf <= tol_eq */
+    double tol_ineq;   /* exit: ||r_d||_inf <= tol_ineq */
+    double tol_comp;   /* exit: ||lam .* t||_inf <= tol_comp */
+    int iter_max;      /* iteration limit */
+    double alpha_min;  /* minimum step length */
+    double gamma;      /* fraction to the boundary */
+    double lam_min;    /* lower clamp on multipliers */
+    double t_min;      /* lower clamp on slacks */
+    double reg_prim;   /* primal regularization added during factorization */
+    double corr_ratio; /* corrector rejected if mu after it > corr_ratio * mu_aff */
+    int ir_max;        /* max iterative-refinement steps per Newton solve */
+    double ir_tol;     /* refinement stops at ||r_ir||_inf <= ir_tol * max(1, ||r||_inf) */
+    int warm_start;    /* reserved; must be 0 (cold start) */
+} oqp_arg;
+
+/* Per-instance result. */
+typedef struct {
+    int status;        /* OQP_SUCCESS / OQP_MAX_ITER / OQP_MIN_STEP / OQP_NAN */
+    int iters;         /* IPM iterations taken */
+    int ir_steps;      /* refinement steps taken in total */
+    int reserved;
+    double mu;         /* duality measure lam't / n_c at the returned iterate */
+    double res[4];     /* inf-norms of r_g, r_b, r_d and lam .* t (eq:alg:pdipm:delta) */
+} oqp_stat;
+
+/* ---- dims (Section 2.2: per-stage nx, nu, nbu, nbx, ng) ---------------- */
+/* Bytes for a dims object with horizon N (N >= 1). */
+size_t oqp_dims_bytes(int N);
+/* Create a dims object in mem (at least oqp_dims_bytes(N) bytes, 8-byte
+ * aligned).  All stage sizes start at 0.  OQP_EINVAL for N < 1 or NULL mem,
+ * OQP_ENOMEM if bytes is too small. */
+int oqp_dims_init(void* mem, size_t bytes, int N, oqp_dims** out);
+/* Sizes of stage n (0 <= n <= N): states nx, inputs nu, boxed inputs nbu,
+ * boxed states nbx, general rows ng.  Requires nbu <= nu, nbx <= nx. */
+int oqp_dims_set_stage(oqp_dims* dims, int n, int nx, int nu, int nbu, int nbx, int ng);
+
+/* ---- qp data (Section 2.2), copied at set time -------------------------- */
+size_t oqp_qp_bytes(const oqp_dims* dims);
+/* Create a QP with all data zero.  The dims object must outlive the QP and
+ * must not change afterwards. */
+int oqp_qp_init(const oqp_dims* dims, void* mem, size_t bytes, oqp_qp** out);
+/* A_n (nx_{n+1} x nx_n, lda), B_n (nx_{n+1} x nu_n, ldb), b_n; 0 <= n < N. */
+int oqp_qp_set_dyn(oqp_qp* qp, int n, const double* A, int lda, const double* B, int ldb, const double* b);
+/* Q_n (nx_n x nx_n, lower triangle read), S_n (nu_n x nx_n), R_n (nu_n x nu_n,
+ * lower triangle read), q_n, r_n.  NULL pointers leave the field zero. */
+int oqp_qp_set_cost(oqp_qp* qp, int n, const double* Q, int ldq, const double* S, int lds, const double* R, int ldr,
+                    const double* q, const double* r);
+/* Box on inputs: nbu_n distinct indices into u_n with bounds lo <= hi. */
+int oqp_qp_set_box_u(oqp_qp* qp, int n, const int* idx, const double* lo, const double* hi);
+/* Box on states: nbx_n distinct indices into x_n with bounds lo <= hi. */
+int oqp_qp_set_box_x(oqp_qp* qp, int n, const int* idx, const double* lo, const double* hi);
+/* General rows lo <= D_n u_n + C_n x_n <= hi: D (ng_n x nu_n), C (ng_n x nx_n). */
+int oqp_qp_set_general(oqp_qp* qp, int n, const double* D, int ldd, const double* C, int ldc, const double* lo,
+                       const double* hi);
+
+/* ---- arguments ----------------------------------------------------------- */
+void oqp_arg_default(oqp_arg* arg, int mode);
+
+/* ---- batch solve on the GPU ---------------------------------------------- */
+/* Sizes of the host and device buffers for a batch of `count` instances with
+ * the given dims.  Each instance is assigned to a compiled kernel variant
+ * whose stage sizes cover it; OQP_EINVAL if none does. */
+int oqp_batch_bytes(const oqp_dims* const* dims, int count, const oqp_arg* arg, size_t* host_bytes,
+                    size_t* dev_bytes);
+/* Create a batch in caller memory: host_mem (host_bytes, 16-byte aligned),
+ * dev_mem (dev_bytes of device memory, 256-byte aligned), stream (a
+ * hipStream_t, or NULL for the default stream).  OQP_ENOMEM when a buffer is
+ * smaller than oqp_batch_bytes reports.  The dims objects are copied. */
+int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_arg* arg, void* host_mem, size_t host_bytes,
+                   void* dev_mem, size_t dev_bytes, void* stream, oqp_batch** out);
+/* Pack the QPs (one per instance, dims matching) into the device layout and
+ * enqueue the host-to-device copy.  Asynchronous on the batch stream; the host
+ * buffer must stay untouched until oqp_batch_sync. */
+int oqp_batch_load(oqp_batch* batch, const oqp_qp* const* qps);
+/* Enqueue the IPM for every instance (one launch per kernel variant). */
+int oqp_batch_solve(oqp_batch* batch);
+/* Replace the arguments used by later solves (mode must not change). */
+int oqp_batch_set_arg(oqp_batch* batch, const oqp_arg* arg);
+/* Enqueue the device-to-host copy of solutions and statistics. */
+int oqp_batch_fetch(oqp_batch* batch);
+/* Wait for all work enqueued on the batch stream. */
+int oqp_batch_sync(oqp_batch* batch);
+/* Results of instance i after fetch + sync.  Solution arrays in the user
+ * layout: u (sum nu_n), x (sum nx_n), pi (sum_{n<N} nx_{n+1}; pi_{n+1}
+ * multiplies the dynamics n -> n+1), and per-stage constraint vectors
+ * lam_l, lam_u, t_l, t_u of length sum(nbu_n + nbx_n + ng_n), ordered per
+ * stage [box u (idxbu order), box x (idxbx order), general].  Any pointer may
+ * be NULL. */
+int oqp_batch_get_stat(const oqp_batch* batch, int i, oqp_stat* stat);
+int oqp_batch_get_sol(const oqp_batch* batch, int i, double* u, double* x, double* pi, double* lam_l, double* lam_u,
+                      double* t_l, double* t_u);
+
+/* ---- single Newton step (eq:alg:pdipm:delta) ------------------------------ */
+/* Set the iterate of instance i (user layout as above; lam and t > 0). */
+int oqp_batch_set_iterate(oqp_batch* batch, int i, const double* u, const double* x, const double* pi,
+                          const double* lam_l, const double* lam_u, const double* t_l, const double* t_u);
+/* Upload the iterates set so far and enqueue one Newton step per instance with
+ * r_m = lam .* t - tau (no line search, no update).  After fetch + sync the
+ * step is read with oqp_batch_get_step (same layout as the solution). */
+int oqp_batch_newton(oqp_batch* batch, double tau);
+int oqp_batch_get_step(const oqp_batch* batch, int i, double* du, double* dx, double* dpi, double* dlam_l,
+                       double* dlam_u, double* dt_l, double* dt_u);
+
+/* ---- introspection -------------------------------------------------------- */
+/* Kernel variant assigned to instance i and its padded stage sizes. */
+int oqp_batch_variant(const oqp_batch* batch, int i, int* nx_pad, int* nu_pad, int* ng_pad);
+/* Number of compiled kernel variants and the stage sizes of variant v. */
+int oqp_variant_count(void);
+int oqp_variant_dims(int v, int* nx_pad, int* nu_pad, int* ng_pad);
+/* Message for the last failing call on this thread. */
+const char* oqp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OQP_H */

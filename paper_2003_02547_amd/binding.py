@@ -1,0 +1,306 @@
+"""Thin Python binding of the C-ABI in include/oqp.h (liboqp.so).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of the library.  PyTorch provides the device buffer and the stream.  The
+binding raises if the library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from dataclasses import dataclass
+from typing import List, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboqp.so")
+
+OK, PENDING = 0, 1
+EINVAL, ENOMEM, EDEVICE, EBUSY, ESTATE = -1, -2, -3, -4, -5
+SUCCESS, MAX_ITER, MIN_STEP, NAN = 0, 1, 2, 3
+MODE_F64, MODE_MIXED = 0, 1
+
+_P = ct.POINTER(ct.c_double)
+_PI = ct.POINTER(ct.c_int)
+_V = ct.c_void_p
+
+
+class OqpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"oqp error {code}: {msg}")
+        self.code = code
+
+
+class Arg(ct.Structure):
+    _fields_ = [("mode", ct.c_int), ("tol_stat", ct.c_double), ("tol_eq", ct.c_double),
+                ("tol_ineq", ct.c_double), ("tol_comp", ct.c_double), ("iter_max", ct.c_int),
+                ("alpha_min", ct.c_double), ("gamma", ct.c_double), ("lam_min", ct.c_double),
+                ("t_min", ct.c_double), ("reg_prim", ct.c_double), ("corr_ratio", ct.c_double),
+                ("ir_max", ct.c_int), ("ir_tol", ct.c_double), ("warm_start", ct.c_int)]
+
+
+class Stat(ct.Structure):
+    _fields_ = [("status", ct.c_int), ("iters", ct.c_int), ("ir_steps", ct.c_int), ("reserved", ct.c_int),
+                ("mu", ct.c_double), ("res", ct.c_double * 4)]
+
+
+_lib = None
+
+
+def lib():
+    """Load liboqp.so (built by build.build()); raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2003_02547_amd.build.build()")
+    L = ct.CDLL(LIB_PATH)
+    sig = {
+        "oqp_dims_bytes": (ct.c_size_t, [ct.c_int]),
+        "oqp_dims_init": (ct.c_int, [_V, ct.c_size_t, ct.c_int, ct.POINTER(_V)]),
+        "oqp_dims_set_stage": (ct.c_int, [_V, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int]),
+        "oqp_qp_bytes": (ct.c_size_t, [_V]),
+        "oqp_qp_init": (ct.c_int, [_V, _V, ct.c_size_t, ct.POINTER(_V)]),
+        "oqp_qp_set_dyn": (ct.c_int, [_V, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P]),
+        "oqp_qp_set_cost": (ct.c_int, [_V, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P, _P]),
+        "oqp_qp_set_box_u": (ct.c_int, [_V, ct.c_int, _PI, _P, _P]),
+        "oqp_qp_set_box_x": (ct.c_int, [_V, ct.c_int, _PI, _P, _P]),
+        "oqp_qp_set_general": (ct.c_int, [_V, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P, _P]),
+        "oqp_arg_default": (None, [ct.POINTER(Arg), ct.c_int]),
+        "oqp_batch_bytes": (ct.c_int, [ct.POINTER(_V), ct.c_int, ct.POINTER(Arg), ct.POINTER(ct.c_size_t),
+                                       ct.POINTER(ct.c_size_t)]),
+        "oqp_batch_init": (ct.c_int, [ct.POINTER(_V), ct.c_int, ct.POINTER(Arg), _V, ct.c_size_t, _V, ct.c_size_t,
+                                      _V, ct.POINTER(_V)]),
+        "oqp_batch_load": (ct.c_int, [_V, ct.POINTER(_V)]),
+        "oqp_batch_solve": (ct.c_int, [_V]),
+        "oqp_batch_set_arg": (ct.c_int, [_V, ct.POINTER(Arg)]),
+        "oqp_batch_fetch": (ct.c_int, [_V]),
+        "oqp_batch_sync": (ct.c_int, [_V]),
+        "oqp_batch_get_stat": (ct.c_int, [_V, ct.c_int, ct.POINTER(Stat)]),
+        "oqp_batch_get_sol": (ct.c_int, [_V, ct.c_int, _P, _P, _P, _P, _P, _P, _P]),
+        "oqp_batch_set_iterate": (ct.c_int, [_V, ct.c_int, _P, _P, _P, _P, _P, _P, _P]),
+        "oqp_batch_newton": (ct.c_int, [_V, ct.c_double]),
+        "oqp_batch_get_step": (ct.c_int, [_V, ct.c_int, _P, _P, _P, _P, _P, _P, _P]),
+        "oqp_batch_variant": (ct.c_int, [_V, ct.c_int, _PI, _PI, _PI]),
+        "oqp_variant_count": (ct.c_int, []),
+        "oqp_variant_dims": (ct.c_int, [ct.c_int, _PI, _PI, _PI]),
+        "oqp_last_error": (ct.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc < 0:
+        raise OqpError(rc, lib().oqp_last_error().decode())
+    return rc
+
+
+def _aligned(nbytes: int, align: int = 64) -> np.ndarray:
+    raw = np.zeros(nbytes + align, dtype=np.uint8)
+    off = (-raw.ctypes.data) % align
+    return raw[off:off + nbytes]
+
+
+def _p(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_P)
+
+
+def _f64(a, shape=None):
+    a = np.asarray(a, dtype=np.float64)
+    return np.asfortranarray(a)
+
+
+def default_arg(mode: int = MODE_F64, **overrides) -> Arg:
+    a = Arg()
+    lib().oqp_arg_default(ct.byref(a), mode)
+    for k, v in overrides.items():
+        setattr(a, k, v)
+    return a
+
+
+class Dims:
+    def __init__(self, N: int, nx, nu, nbu, nbx, ng):
+        L = lib()
+        self.N = N
+        self.mem = _aligned(L.oqp_dims_bytes(N))
+        h = _V()
+        _check(L.oqp_dims_init(self.mem.ctypes.data, self.mem.nbytes, N, ct.byref(h)))
+        self.h = h
+        for n in range(N + 1):
+            _check(L.oqp_dims_set_stage(h, n, int(nx[n]), int(nu[n]), int(nbu[n]), int(nbx[n]), int(ng[n])))
+
+    @classmethod
+    def of(cls, qp) -> "Dims":
+        return cls(qp.N, qp.nx, qp.nu, qp.nbu, qp.nbx, qp.ng)
+
+
+class Qp:
+    """oqp_qp built from an OcpQp-like object through the per-stage setters."""
+
+    def __init__(self, qp, dims: Dims | None = None):
+        L = lib()
+        self.dims = dims or Dims.of(qp)
+        self.mem = _aligned(L.oqp_qp_bytes(self.dims.h))
+        h = _V()
+        _check(L.oqp_qp_init(self.dims.h, self.mem.ctypes.data, self.mem.nbytes, ct.byref(h)))
+        self.h = h
+        N = qp.N
+        for n in range(N + 1):
+            nx, nu = qp.nx[n], qp.nu[n]
+            if n < N:
+                A, B, b = _f64(qp.A[n]), _f64(qp.B[n]), _f64(qp.b[n])
+                _check(L.oqp_qp_set_dyn(h, n, _p(A), max(A.shape[0], 1), _p(B), max(B.shape[0], 1), _p(b)))
+            Q, S, R = _f64(qp.Q[n]), _f64(qp.S[n]), _f64(qp.R[n])
+            q, r = _f64(qp.q[n]), _f64(qp.r[n])
+            _check(L.oqp_qp_set_cost(h, n, _p(Q), max(nx, 1), _p(S), max(nu, 1), _p(R), max(nu, 1), _p(q), _p(r)))
+            if len(qp.idxbu[n]):
+                iu = np.ascontiguousarray(qp.idxbu[n], dtype=np.int32)
+                _check(L.oqp_qp_set_box_u(h, n, iu.ctypes.data_as(_PI), _p(_f64(qp.lbu[n])), _p(_f64(qp.ubu[n]))))
+            if len(qp.idxbx[n]):
+                ix = np.ascontiguousarray(qp.idxbx[n], dtype=np.int32)
+                _check(L.oqp_qp_set_box_x(h, n, ix.ctypes.data_as(_PI), _p(_f64(qp.lbx[n])), _p(_f64(qp.ubx[n]))))
+            ng = np.asarray(qp.D[n]).shape[0]
+            if ng:
+                D, C = _f64(qp.D[n]), _f64(qp.C[n])
+                _check(L.oqp_qp_set_general(h, n, _p(D), ng, _p(C), ng, _p(_f64(qp.lg[n])), _p(_f64(qp.ug[n]))))
+
+
+@dataclass
+class Result:
+    status: int
+    iters: int
+    ir_steps: int
+    mu: float
+    res: np.ndarray
+    sol: dict
+
+
+def _sizes(qp):
+    return (int(sum(qp.nu)), int(sum(qp.nx)), int(sum(qp.nx[1:])), int(qp.n_constraints()))
+
+
+class Batch:
+    """A batch of OCP QPs solved on the current CUDA (HIP) device and stream."""
+
+    def __init__(self, qps: Sequence, arg: Arg | None = None, device=None, stream=None):
+        import torch
+        L = lib()
+        self.qps = list(qps)
+        self.arg = arg or default_arg()
+        self.dims = [Dims.of(q) for q in self.qps]
+        n = len(self.qps)
+        self._dimh = (_V * n)(*[d.h for d in self.dims])
+        hb, db = ct.c_size_t(0), ct.c_size_t(0)
+        _check(L.oqp_batch_bytes(self._dimh, n, ct.byref(self.arg), ct.byref(hb), ct.byref(db)))
+        self.host_bytes, self.dev_bytes = hb.value, db.value
+        self.host = _aligned(self.host_bytes, 64)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.dev_buf = torch.empty(self.dev_bytes + 256, dtype=torch.uint8, device=dev)
+        base = self.dev_buf.data_ptr()
+        self.dev_ptr = base + ((-base) % 256)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = _V()
+        _check(L.oqp_batch_init(self._dimh, n, ct.byref(self.arg), self.host.ctypes.data, self.host_bytes,
+                                self.dev_ptr, self.dev_bytes, self.stream.cuda_stream, ct.byref(h)))
+        self.h = h
+        self._qph = None
+
+    def load(self):
+        L = lib()
+        self._qpo = [Qp(q, d) for q, d in zip(self.qps, self.dims)]
+        self._qph = (_V * len(self._qpo))(*[q.h for q in self._qpo])
+        _check(L.oqp_batch_load(self.h, self._qph))
+        return self
+
+    def solve(self):
+        _check(lib().oqp_batch_solve(self.h))
+        return self
+
+    def set_arg(self, arg: Arg):
+        _check(lib().oqp_batch_set_arg(self.h, ct.byref(arg)))
+        self.arg = arg
+
+    def fetch(self):
+        _check(lib().oqp_batch_fetch(self.h))
+        return self
+
+    def sync(self):
+        _check(lib().oqp_batch_sync(self.h))
+        return self
+
+    def stat(self, i: int) -> Stat:
+        st = Stat()
+        _check(lib().oqp_batch_get_stat(self.h, i, ct.byref(st)))
+        return st
+
+    def _alloc_vec(self, i):
+        nu, nx, npi, nc = _sizes(self.qps[i])
+        return {k: np.zeros(max(s, 1)) for k, s in
+                (("u", nu), ("x", nx), ("pi", npi), ("lam_l", nc), ("lam_u", nc), ("t_l", nc), ("t_u", nc))}, \
+            dict(u=nu, x=nx, pi=npi, lam_l=nc, lam_u=nc, t_l=nc, t_u=nc)
+
+    def solution(self, i: int) -> dict:
+        v, sz = self._alloc_vec(i)
+        _check(lib().oqp_batch_get_sol(self.h, i, *[_p(v[k]) for k in ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")]))
+        return {k: v[k][:sz[k]].copy() for k in v}
+
+    def result(self, i: int) -> Result:
+        st = self.stat(i)
+        return Result(st.status, st.iters, st.ir_steps, st.mu, np.array(st.res[:]), self.solution(i))
+
+    def results(self) -> List[Result]:
+        return [self.result(i) for i in range(len(self.qps))]
+
+    def set_iterate(self, i: int, it: dict):
+        v, sz = self._alloc_vec(i)
+        for k in v:
+            v[k][:sz[k]] = np.asarray(it[k], dtype=np.float64)[:sz[k]]
+        _check(lib().oqp_batch_set_iterate(self.h, i, *[_p(v[k]) for k in ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")]))
+
+    def newton(self, tau: float = 0.0):
+        _check(lib().oqp_batch_newton(self.h, ct.c_double(tau)))
+        return self
+
+    def step(self, i: int) -> dict:
+        v, sz = self._alloc_vec(i)
+        _check(lib().oqp_batch_get_step(self.h, i, *[_p(v[k]) for k in ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")]))
+        return {k: v[k][:sz[k]].copy() for k in v}
+
+    def variant(self, i: int):
+        a, b, c = ct.c_int(), ct.c_int(), ct.c_int()
+        v = lib().oqp_batch_variant(self.h, i, ct.byref(a), ct.byref(b), ct.byref(c))
+        return v, (a.value, b.value, c.value)
+
+
+def solve(qps: Sequence, arg: Arg | None = None) -> List[Result]:
+    """Load, solve, fetch and return the results of a batch."""
+    b = Batch(qps, arg).load().solve().fetch().sync()
+    return b.results()
+
+
+def variants():
+    L = lib()
+    out = []
+    for v in range(L.oqp_variant_count()):
+        a, b, c = ct.c_int(), ct.c_int(), ct.c_int()
+        L.oqp_variant_dims(v, ct.byref(a), ct.byref(b), ct.byref(c))
+        out.append((a.value, b.value, c.value))
+    return out
+
+
+EXPORTED = [
+    "oqp_dims_bytes", "oqp_dims_init", "oqp_dims_set_stage", "oqp_qp_bytes", "oqp_qp_init", "oqp_qp_set_dyn",
+    "oqp_qp_set_cost", "oqp_qp_set_box_u", "oqp_qp_set_box_x", "oqp_qp_set_general", "oqp_arg_default",
+    "oqp_batch_bytes", "oqp_batch_init", "oqp_batch_load", "oqp_batch_solve", "oqp_batch_set_arg",
+    "oqp_batch_fetch", "oqp_batch_sync", "oqp_batch_get_stat", "oqp_batch_get_sol", "oqp_batch_set_iterate",
+    "oqp_batch_newton", "oqp_batch_get_step", "oqp_batch_variant", "oqp_variant_count", "oqp_variant_dims",
+    "oqp_last_error",
+]

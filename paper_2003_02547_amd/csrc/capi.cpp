@@ -1,0 +1,887 @@
+// C-ABI of the batched OCP-QP IPM: caller-owned memory for every object,
+// host-side packing into the padded device layout, launches per kernel
+// variant on the caller's stream.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/oqp.h"
+#include "layout.h"
+
+namespace oqp {
+int variant_count();
+void variant_dims(int v, int* nx, int* nu, int* ng);
+int variant_launch(int v, const InstDesc* desc, int count, const double* data, double* iter, double* work,
+                   double* step, DevStat* stat, const KParams& P, void* stream);
+}  // namespace oqp
+
+using oqp::DevStat;
+using oqp::InstDesc;
+using oqp::Layout;
+
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+extern "C" const char* oqp_last_error(void) { return g_err; }
+
+// ---------------------------------------------------------------------------
+// dims
+// ---------------------------------------------------------------------------
+
+struct oqp_dims {
+    int N;
+    int* nx;
+    int* nu;
+    int* nbu;
+    int* nbx;
+    int* ng;
+};
+
+extern "C" size_t oqp_dims_bytes(int N)
+{
+    if (N < 1) return 0;
+    return align_up(sizeof(oqp_dims), 16) + align_up(5 * (size_t)(N + 1) * sizeof(int), 16);
+}
+
+extern "C" int oqp_dims_init(void* mem, size_t bytes, int N, oqp_dims** out)
+{
+    if (!mem || !out || N < 1) return fail(OQP_EINVAL, "oqp_dims_init: bad argument (N=%d)", N);
+    if (bytes < oqp_dims_bytes(N)) return fail(OQP_ENOMEM, "oqp_dims_init: %zu bytes < %zu", bytes, oqp_dims_bytes(N));
+    if ((uintptr_t)mem % 8) return fail(OQP_EINVAL, "oqp_dims_init: memory not 8-byte aligned");
+    oqp_dims* d = (oqp_dims*)mem;
+    int* a = (int*)((char*)mem + align_up(sizeof(oqp_dims), 16));
+    std::memset(a, 0, 5 * (size_t)(N + 1) * sizeof(int));
+    d->N = N;
+    d->nx = a;
+    d->nu = a + (N + 1);
+    d->nbu = a + 2 * (N + 1);
+    d->nbx = a + 3 * (N + 1);
+    d->ng = a + 4 * (N + 1);
+    *out = d;
+    return OQP_OK;
+}
+
+extern "C" int oqp_dims_set_stage(oqp_dims* d, int n, int nx, int nu, int nbu, int nbx, int ng)
+{
+    if (!d || n < 0 || n > d->N) return fail(OQP_EINVAL, "oqp_dims_set_stage: stage %d out of range", n);
+    if (nx < 0 || nu < 0 || nbu < 0 || nbx < 0 || ng < 0 || nbu > nu || nbx > nx)
+        return fail(OQP_EINVAL, "oqp_dims_set_stage: bad sizes at stage %d", n);
+    d->nx[n] = nx;
+    d->nu[n] = nu;
+    d->nbu[n] = nbu;
+    d->nbx[n] = nbx;
+    d->ng[n] = ng;
+    return OQP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// qp
+// ---------------------------------------------------------------------------
+
+// Per-stage double block: A, B, b, Q, S, R, q, r, lbu, ubu, lbx, ubx, D, C, lg, ug.
+enum { F_A, F_B, F_b, F_Q, F_S, F_R, F_q, F_r, F_lbu, F_ubu, F_lbx, F_ubx, F_D, F_C, F_lg, F_ug, F_COUNT };
+
+static void stage_sizes(const oqp_dims* d, int n, size_t* sz)
+{
+    const int nx = d->nx[n], nu = d->nu[n], nxn = n < d->N ? d->nx[n + 1] : 0;
+    const int nbu = d->nbu[n], nbx = d->nbx[n], ng = d->ng[n];
+    sz[F_A] = (size_t)nxn * nx;
+    sz[F_B] = (size_t)nxn * nu;
+    sz[F_b] = nxn;
+    sz[F_Q] = (size_t)nx * nx;
+    sz[F_S] = (size_t)nu * nx;
+    sz[F_R] = (size_t)nu * nu;
+    sz[F_q] = nx;
+    sz[F_r] = nu;
+    sz[F_lbu] = sz[F_ubu] = nbu;
+    sz[F_lbx] = sz[F_ubx] = nbx;
+    sz[F_D] = (size_t)ng * nu;
+    sz[F_C] = (size_t)ng * nx;
+    sz[F_lg] = sz[F_ug] = ng;
+}
+
+struct oqp_qp {
+    const oqp_dims* dims;
+    int64_t* doff;  // (N+2) stage offsets into d
+    int64_t* ioff;  // (N+2) stage offsets into idx (idxbu then idxbx)
+    double* d;
+    int* idx;
+};
+
+static void qp_offsets(const oqp_dims* dims, int64_t* doff, int64_t* ioff)
+{
+    int64_t od = 0, oi = 0;
+    size_t sz[F_COUNT];
+    for (int n = 0; n <= dims->N; ++n) {
+        doff[n] = od;
+        ioff[n] = oi;
+        stage_sizes(dims, n, sz);
+        for (int f = 0; f < F_COUNT; ++f) od += (int64_t)sz[f];
+        oi += dims->nbu[n] + dims->nbx[n];
+    }
+    doff[dims->N + 1] = od;
+    ioff[dims->N + 1] = oi;
+}
+
+extern "C" size_t oqp_qp_bytes(const oqp_dims* dims)
+{
+    if (!dims) return 0;
+    int64_t doff[2], ioff[2];
+    (void)doff; (void)ioff;
+    const int N = dims->N;
+    int64_t od = 0, oi = 0;
+    size_t sz[F_COUNT];
+    for (int n = 0; n <= N; ++n) {
+        stage_sizes(dims, n, sz);
+        for (int f = 0; f < F_COUNT; ++f) od += (int64_t)sz[f];
+        oi += dims->nbu[n] + dims->nbx[n];
+    }
+    return align_up(sizeof(oqp_qp), 16) + 2 * align_up((size_t)(N + 2) * sizeof(int64_t), 16) +
+           align_up((size_t)od * sizeof(double), 16) + align_up((size_t)oi * sizeof(int), 16);
+}
+
+extern "C" int oqp_qp_init(const oqp_dims* dims, void* mem, size_t bytes, oqp_qp** out)
+{
+    if (!dims || !mem || !out) return fail(OQP_EINVAL, "oqp_qp_init: NULL argument");
+    const size_t need = oqp_qp_bytes(dims);
+    if (bytes < need) return fail(OQP_ENOMEM, "oqp_qp_init: %zu bytes < %zu", bytes, need);
+    if ((uintptr_t)mem % 16) return fail(OQP_EINVAL, "oqp_qp_init: memory not 16-byte aligned");
+    std::memset(mem, 0, need);
+    const int N = dims->N;
+    char* p = (char*)mem;
+    oqp_qp* q = (oqp_qp*)p;
+    p += align_up(sizeof(oqp_qp), 16);
+    q->dims = dims;
+    q->doff = (int64_t*)p;
+    p += align_up((size_t)(N + 2) * sizeof(int64_t), 16);
+    q->ioff = (int64_t*)p;
+    p += align_up((size_t)(N + 2) * sizeof(int64_t), 16);
+    qp_offsets(dims, q->doff, q->ioff);
+    q->d = (double*)p;
+    p += align_up((size_t)q->doff[N + 1] * sizeof(double), 16);
+    q->idx = (int*)p;
+    *out = q;
+    return OQP_OK;
+}
+
+static double* qp_field(const oqp_qp* q, int n, int f)
+{
+    size_t sz[F_COUNT];
+    stage_sizes(q->dims, n, sz);
+    int64_t o = q->doff[n];
+    for (int k = 0; k < f; ++k) o += (int64_t)sz[k];
+    return q->d + o;
+}
+
+static void copy_mat(double* dst, const double* src, int rows, int cols, int ld)
+{
+    for (int j = 0; j < cols; ++j)
+        for (int i = 0; i < rows; ++i) dst[i + (size_t)j * rows] = src[i + (size_t)j * ld];
+}
+
+static void copy_sym_lower(double* dst, const double* src, int n, int ld)
+{
+    for (int j = 0; j < n; ++j)
+        for (int i = j; i < n; ++i) {
+            double v = src[i + (size_t)j * ld];
+            dst[i + (size_t)j * n] = v;
+            dst[j + (size_t)i * n] = v;
+        }
+}
+
+extern "C" int oqp_qp_set_dyn(oqp_qp* q, int n, const double* A, int lda, const double* B, int ldb, const double* b)
+{
+    if (!q || n < 0 || n >= q->dims->N) return fail(OQP_EINVAL, "oqp_qp_set_dyn: stage %d out of range", n);
+    const int nx = q->dims->nx[n], nu = q->dims->nu[n], nxn = q->dims->nx[n + 1];
+    if (A && nx > 0) {
+        if (lda < nxn || lda < 1) return fail(OQP_EINVAL, "oqp_qp_set_dyn: lda=%d < %d", lda, nxn);
+        copy_mat(qp_field(q, n, F_A), A, nxn, nx, lda);
+    }
+    if (B && nu > 0) {
+        if (ldb < nxn || ldb < 1) return fail(OQP_EINVAL, "oqp_qp_set_dyn: ldb=%d < %d", ldb, nxn);
+        copy_mat(qp_field(q, n, F_B), B, nxn, nu, ldb);
+    }
+    if (b) std::memcpy(qp_field(q, n, F_b), b, sizeof(double) * nxn);
+    return OQP_OK;
+}
+
+extern "C" int oqp_qp_set_cost(oqp_qp* q, int n, const double* Q, int ldq, const double* S, int lds, const double* R,
+                               int ldr, const double* qv, const double* rv)
+{
+    if (!q || n < 0 || n > q->dims->N) return fail(OQP_EINVAL, "oqp_qp_set_cost: stage %d out of range", n);
+    const int nx = q->dims->nx[n], nu = q->dims->nu[n];
+    if (Q && nx > 0) {
+        if (ldq < nx) return fail(OQP_EINVAL, "oqp_qp_set_cost: ldq=%d < %d", ldq, nx);
+        copy_sym_lower(qp_field(q, n, F_Q), Q, nx, ldq);
+    }
+    if (S && nu > 0 && nx > 0) {
+        if (lds < nu) return fail(OQP_EINVAL, "oqp_qp_set_cost: lds=%d < %d", lds, nu);
+        copy_mat(qp_field(q, n, F_S), S, nu, nx, lds);
+    }
+    if (R && nu > 0) {
+        if (ldr < nu) return fail(OQP_EINVAL, "oqp_qp_set_cost: ldr=%d < %d", ldr, nu);
+        copy_sym_lower(qp_field(q, n, F_R), R, nu, ldr);
+    }
+    if (qv) std::memcpy(qp_field(q, n, F_q), qv, sizeof(double) * nx);
+    if (rv) std::memcpy(qp_field(q, n, F_r), rv, sizeof(double) * nu);
+    return OQP_OK;
+}
+
+static int set_box(oqp_qp* q, int n, const int* idx, const double* lo, const double* hi, bool on_u)
+{
+    const char* name = on_u ? "oqp_qp_set_box_u" : "oqp_qp_set_box_x";
+    if (!q || n < 0 || n > q->dims->N) return fail(OQP_EINVAL, "%s: stage %d out of range", name, n);
+    const int nb = on_u ? q->dims->nbu[n] : q->dims->nbx[n];
+    const int dim = on_u ? q->dims->nu[n] : q->dims->nx[n];
+    if (nb == 0) return OQP_OK;
+    if (!idx || !lo || !hi) return fail(OQP_EINVAL, "%s: NULL array", name);
+    for (int k = 0; k < nb; ++k) {
+        if (idx[k] < 0 || idx[k] >= dim) return fail(OQP_EINVAL, "%s: index %d out of range at stage %d", name, idx[k], n);
+        if (!(lo[k] <= hi[k])) return fail(OQP_EINVAL, "%s: lo > hi (or NaN) for bound %d at stage %d", name, k, n);
+        for (int k2 = 0; k2 < k; ++k2)
+            if (idx[k2] == idx[k]) return fail(OQP_EINVAL, "%s: index %d repeated at stage %d", name, idx[k], n);
+    }
+    int* dst = q->idx + q->ioff[n] + (on_u ? 0 : q->dims->nbu[n]);
+    std::memcpy(dst, idx, sizeof(int) * nb);
+    std::memcpy(qp_field(q, n, on_u ? F_lbu : F_lbx), lo, sizeof(double) * nb);
+    std::memcpy(qp_field(q, n, on_u ? F_ubu : F_ubx), hi, sizeof(double) * nb);
+    return OQP_OK;
+}
+
+extern "C" int oqp_qp_set_box_u(oqp_qp* q, int n, const int* idx, const double* lo, const double* hi)
+{
+    return set_box(q, n, idx, lo, hi, true);
+}
+
+extern "C" int oqp_qp_set_box_x(oqp_qp* q, int n, const int* idx, const double* lo, const double* hi)
+{
+    return set_box(q, n, idx, lo, hi, false);
+}
+
+extern "C" int oqp_qp_set_general(oqp_qp* q, int n, const double* D, int ldd, const double* C, int ldc,
+                                  const double* lo, const double* hi)
+{
+    if (!q || n < 0 || n > q->dims->N) return fail(OQP_EINVAL, "oqp_qp_set_general: stage %d out of range", n);
+    const int ng = q->dims->ng[n], nu = q->dims->nu[n], nx = q->dims->nx[n];
+    if (ng == 0) return OQP_OK;
+    if (!lo || !hi) return fail(OQP_EINVAL, "oqp_qp_set_general: NULL bounds");
+    for (int k = 0; k < ng; ++k)
+        if (!(lo[k] <= hi[k])) return fail(OQP_EINVAL, "oqp_qp_set_general: lo > hi for row %d at stage %d", k, n);
+    if (D && nu > 0) {
+        if (ldd < ng) return fail(OQP_EINVAL, "oqp_qp_set_general: ldd=%d < %d", ldd, ng);
+        copy_mat(qp_field(q, n, F_D), D, ng, nu, ldd);
+    }
+    if (C && nx > 0) {
+        if (ldc < ng) return fail(OQP_EINVAL, "oqp_qp_set_general: ldc=%d < %d", ldc, ng);
+        copy_mat(qp_field(q, n, F_C), C, ng, nx, ldc);
+    }
+    std::memcpy(qp_field(q, n, F_lg), lo, sizeof(double) * ng);
+    std::memcpy(qp_field(q, n, F_ug), hi, sizeof(double) * ng);
+    return OQP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// arguments
+// ---------------------------------------------------------------------------
+
+extern "C" void oqp_arg_default(oqp_arg* a, int mode)
+{
+    if (!a) return;
+    std::memset(a, 0, sizeof(*a));
+    a->mode = mode == OQP_MODE_MIXED ? OQP_MODE_MIXED : OQP_MODE_F64;
+    const double tol = a->mode == OQP_MODE_MIXED ? 1e-6 : 1e-8;
+    a->tol_stat = a->tol_eq = a->tol_ineq = a->tol_comp = tol;
+    a->iter_max = 100;
+    a->alpha_min = 1e-10;
+    a->gamma = 0.995;
+    a->lam_min = 1e-16;
+    a->t_min = 1e-16;
+    a->reg_prim = 0.0;
+    a->corr_ratio = 10.0;
+    a->ir_max = a->mode == OQP_MODE_MIXED ? 4 : 0;
+    a->ir_tol = 1e-10;
+    a->warm_start = 0;
+}
+
+static int check_arg(const oqp_arg* a)
+{
+    if (!a) return fail(OQP_EINVAL, "NULL oqp_arg");
+    if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED) return fail(OQP_EINVAL, "unknown mode %d", a->mode);
+    if (a->mode == OQP_MODE_MIXED) return fail(OQP_EINVAL, "OQP_MODE_MIXED is not available in this build");
+    if (a->iter_max < 0 || !(a->gamma > 0.0 && a->gamma <= 1.0) || a->warm_start != 0)
+        return fail(OQP_EINVAL, "bad oqp_arg field (iter_max, gamma or warm_start)");
+    return OQP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batch
+// ---------------------------------------------------------------------------
+
+struct Inst {
+    int variant;
+    int N;
+    int nc;
+    int dims_off;   // into dims pool: 5 * (N+1) ints (nx, nu, nbu, nbx, ng)
+    int slot_off;   // into slot pool: per-stage user constraint -> padded slot
+    int64_t data;   // doubles
+    int64_t iter;   // doubles
+    int64_t work;   // doubles
+};
+
+struct oqp_batch {
+    int count;
+    int nvar;
+    oqp_arg arg;
+    void* stream;
+    int loaded;
+    int solved;
+    int has_step;
+    // host side
+    Inst* inst;
+    int* dims_pool;
+    int* slot_pool;
+    InstDesc* hdesc;
+    DevStat* hstat;
+    double* hdata;
+    double* hiter;
+    double* hstep;
+    int* vstart;
+    int* vcount;
+    // device side
+    InstDesc* ddesc;
+    DevStat* dstat;
+    double* ddata;
+    double* diter;
+    double* dwork;
+    double* dstep;
+    // sizes (doubles)
+    int64_t n_data, n_iter, n_work;
+};
+
+static int pick_variant(const oqp_dims* d)
+{
+    int mx = 0, mu = 0, mg = 0;
+    for (int n = 0; n <= d->N; ++n) {
+        if (d->nx[n] > mx) mx = d->nx[n];
+        if (d->nu[n] > mu) mu = d->nu[n];
+        if (d->ng[n] > mg) mg = d->ng[n];
+    }
+    int best = -1;
+    long best_cost = 0;
+    for (int v = 0; v < oqp::variant_count(); ++v) {
+        int nx, nu, ng;
+        oqp::variant_dims(v, &nx, &nu, &ng);
+        if (nx < mx || nu < mu || ng < mg) continue;
+        long nz = nx + nu;
+        long cost = nz * nz * (nx + nz) + (long)ng * nz * nz;
+        if (best < 0 || cost < best_cost) {
+            best = v;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+struct Plan {
+    size_t host_bytes, dev_bytes;
+    // host offsets
+    size_t h_inst, h_dims, h_slot, h_desc, h_stat, h_data, h_iter, h_step, h_vstart, h_vcount;
+    // device offsets
+    size_t d_desc, d_stat, d_data, d_iter, d_work, d_step;
+    int64_t n_data, n_iter, n_work;
+    int n_dims, n_slot;
+};
+
+static int make_plan(const oqp_dims* const* dims, int count, Plan* pl)
+{
+    if (!dims || count < 1) return fail(OQP_EINVAL, "batch: count must be >= 1");
+    const int nv = oqp::variant_count();
+    int64_t nd = 0, ni = 0, nw = 0;
+    int ndims = 0, nslot = 0;
+    for (int i = 0; i < count; ++i) {
+        const oqp_dims* d = dims[i];
+        if (!d) return fail(OQP_EINVAL, "batch: dims[%d] is NULL", i);
+        int v = pick_variant(d);
+        if (v < 0) return fail(OQP_EINVAL, "batch: no kernel variant covers the stage sizes of instance %d", i);
+        int nx, nu, ng;
+        oqp::variant_dims(v, &nx, &nu, &ng);
+        const Layout L = oqp::make_layout(nx, nu, ng);
+        nd += (int64_t)(d->N + 1) * L.SREC;
+        ni += (int64_t)(d->N + 1) * L.IREC;
+        nw += (int64_t)(d->N + 1) * L.WREC;
+        ndims += 5 * (d->N + 1);
+        for (int n = 0; n <= d->N; ++n) nslot += d->nbu[n] + d->nbx[n] + d->ng[n];
+    }
+    size_t h = 0;
+    h = align_up(h + sizeof(oqp_batch), 64);
+    pl->h_inst = h; h = align_up(h + sizeof(Inst) * count, 64);
+    pl->h_dims = h; h = align_up(h + sizeof(int) * ndims, 64);
+    pl->h_slot = h; h = align_up(h + sizeof(int) * (nslot + 1), 64);
+    pl->h_vstart = h; h = align_up(h + sizeof(int) * nv, 64);
+    pl->h_vcount = h; h = align_up(h + sizeof(int) * nv, 64);
+    pl->h_desc = h; h = align_up(h + sizeof(InstDesc) * count, 64);
+    pl->h_stat = h; h = align_up(h + sizeof(DevStat) * count, 64);
+    pl->h_data = h; h = align_up(h + sizeof(double) * nd, 64);
+    pl->h_iter = h; h = align_up(h + sizeof(double) * ni, 64);
+    pl->h_step = h; h = align_up(h + sizeof(double) * ni, 64);
+    pl->host_bytes = h;
+    size_t g = 0;
+    pl->d_desc = g; g = align_up(g + sizeof(InstDesc) * count, 256);
+    pl->d_stat = g; g = align_up(g + sizeof(DevStat) * count, 256);
+    pl->d_data = g; g = align_up(g + sizeof(double) * nd, 256);
+    pl->d_iter = g; g = align_up(g + sizeof(double) * ni, 256);
+    pl->d_work = g; g = align_up(g + sizeof(double) * nw, 256);
+    pl->d_step = g; g = align_up(g + sizeof(double) * ni, 256);
+    pl->dev_bytes = g;
+    pl->n_data = nd; pl->n_iter = ni; pl->n_work = nw;
+    pl->n_dims = ndims; pl->n_slot = nslot;
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_bytes(const oqp_dims* const* dims, int count, const oqp_arg* arg, size_t* host_bytes,
+                               size_t* dev_bytes)
+{
+    int rc = check_arg(arg);
+    if (rc) return rc;
+    Plan pl;
+    rc = make_plan(dims, count, &pl);
+    if (rc) return rc;
+    if (host_bytes) *host_bytes = pl.host_bytes;
+    if (dev_bytes) *dev_bytes = pl.dev_bytes;
+    return OQP_OK;
+}
+
+static const Layout inst_layout(const Inst& in)
+{
+    int nx, nu, ng;
+    oqp::variant_dims(in.variant, &nx, &nu, &ng);
+    return oqp::make_layout(nx, nu, ng);
+}
+
+extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_arg* arg, void* host_mem,
+                              size_t host_bytes, void* dev_mem, size_t dev_bytes, void* stream, oqp_batch** out)
+{
+    int rc = check_arg(arg);
+    if (rc) return rc;
+    if (!host_mem || !dev_mem || !out) return fail(OQP_EINVAL, "oqp_batch_init: NULL argument");
+    if ((uintptr_t)host_mem % 16) return fail(OQP_EINVAL, "oqp_batch_init: host memory not 16-byte aligned");
+    if ((uintptr_t)dev_mem % 256) return fail(OQP_EINVAL, "oqp_batch_init: device memory not 256-byte aligned");
+    Plan pl;
+    rc = make_plan(dims, count, &pl);
+    if (rc) return rc;
+    if (host_bytes < pl.host_bytes) return fail(OQP_ENOMEM, "oqp_batch_init: host %zu < %zu", host_bytes, pl.host_bytes);
+    if (dev_bytes < pl.dev_bytes) return fail(OQP_ENOMEM, "oqp_batch_init: device %zu < %zu", dev_bytes, pl.dev_bytes);
+    char* h = (char*)host_mem;
+    char* g = (char*)dev_mem;
+    oqp_batch* b = (oqp_batch*)h;
+    std::memset(b, 0, sizeof(*b));
+    b->count = count;
+    b->nvar = oqp::variant_count();
+    b->arg = *arg;
+    b->stream = stream;
+    b->inst = (Inst*)(h + pl.h_inst);
+    b->dims_pool = (int*)(h + pl.h_dims);
+    b->slot_pool = (int*)(h + pl.h_slot);
+    b->vstart = (int*)(h + pl.h_vstart);
+    b->vcount = (int*)(h + pl.h_vcount);
+    b->hdesc = (InstDesc*)(h + pl.h_desc);
+    b->hstat = (DevStat*)(h + pl.h_stat);
+    b->hdata = (double*)(h + pl.h_data);
+    b->hiter = (double*)(h + pl.h_iter);
+    b->hstep = (double*)(h + pl.h_step);
+    b->ddesc = (InstDesc*)(g + pl.d_desc);
+    b->dstat = (DevStat*)(g + pl.d_stat);
+    b->ddata = (double*)(g + pl.d_data);
+    b->diter = (double*)(g + pl.d_iter);
+    b->dwork = (double*)(g + pl.d_work);
+    b->dstep = (double*)(g + pl.d_step);
+    b->n_data = pl.n_data;
+    b->n_iter = pl.n_iter;
+    b->n_work = pl.n_work;
+    // instances, grouped by variant
+    int doff = 0, soff = 0;
+    for (int v = 0; v < b->nvar; ++v) b->vcount[v] = 0;
+    for (int i = 0; i < count; ++i) {
+        Inst& in = b->inst[i];
+        const oqp_dims* d = dims[i];
+        in.variant = pick_variant(d);
+        in.N = d->N;
+        in.dims_off = doff;
+        in.slot_off = soff;
+        int nc = 0;
+        for (int n = 0; n <= d->N; ++n) {
+            b->dims_pool[doff + 0 * (d->N + 1) + n] = d->nx[n];
+            b->dims_pool[doff + 1 * (d->N + 1) + n] = d->nu[n];
+            b->dims_pool[doff + 2 * (d->N + 1) + n] = d->nbu[n];
+            b->dims_pool[doff + 3 * (d->N + 1) + n] = d->nbx[n];
+            b->dims_pool[doff + 4 * (d->N + 1) + n] = d->ng[n];
+            nc += d->nbu[n] + d->nbx[n] + d->ng[n];
+        }
+        in.nc = nc;
+        doff += 5 * (d->N + 1);
+        soff += nc;
+        b->vcount[in.variant]++;
+    }
+    int acc = 0;
+    for (int v = 0; v < b->nvar; ++v) {
+        b->vstart[v] = acc;
+        acc += b->vcount[v];
+    }
+    // region offsets in variant order
+    int64_t od = 0, oi = 0, ow = 0;
+    int fill[64];
+    for (int v = 0; v < b->nvar && v < 64; ++v) fill[v] = 0;
+    for (int v = 0; v < b->nvar; ++v) {
+        for (int i = 0; i < count; ++i) {
+            Inst& in = b->inst[i];
+            if (in.variant != v) continue;
+            const Layout L = inst_layout(in);
+            in.data = od;
+            in.iter = oi;
+            in.work = ow;
+            od += (int64_t)(in.N + 1) * L.SREC;
+            oi += (int64_t)(in.N + 1) * L.IREC;
+            ow += (int64_t)(in.N + 1) * L.WREC;
+            InstDesc& ds = b->hdesc[b->vstart[v] + fill[v]++];
+            ds.data = in.data;
+            ds.iter = in.iter;
+            ds.work = in.work;
+            ds.N = in.N;
+            ds.nc = in.nc;
+            ds.index = i;
+            ds.pad = 0;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(b->ddesc, b->hdesc, sizeof(InstDesc) * count, hipMemcpyHostToDevice,
+                                  (hipStream_t)stream);
+    if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_init: hipMemcpyAsync: %s", hipGetErrorString(e));
+    *out = b;
+    return OQP_OK;
+}
+
+static inline const int* inst_dims(const oqp_batch* b, const Inst& in, int which)
+{
+    return b->dims_pool + in.dims_off + which * (in.N + 1);
+}
+
+// Pack instance i's QP into its padded stage records.
+static int pack_instance(oqp_batch* b, int i, const oqp_qp* q)
+{
+    const Inst& in = b->inst[i];
+    const Layout L = inst_layout(in);
+    const int* nxv = inst_dims(b, in, 0);
+    const int* nuv = inst_dims(b, in, 1);
+    const int* nbuv = inst_dims(b, in, 2);
+    const int* nbxv = inst_dims(b, in, 3);
+    const int* ngv = inst_dims(b, in, 4);
+    const oqp_dims* qd = q->dims;
+    if (qd->N != in.N) return fail(OQP_EINVAL, "oqp_batch_load: qp %d horizon differs from its dims", i);
+    for (int n = 0; n <= in.N; ++n)
+        if (qd->nx[n] != nxv[n] || qd->nu[n] != nuv[n] || qd->nbu[n] != nbuv[n] || qd->nbx[n] != nbxv[n] ||
+            qd->ng[n] != ngv[n])
+            return fail(OQP_EINVAL, "oqp_batch_load: qp %d sizes differ from its dims at stage %d", i, n);
+    const int NX = L.NX, NU = L.NU, NZ = L.NZ;
+    int* slots = b->slot_pool + in.slot_off;
+    int so = 0;
+    for (int n = 0; n <= in.N; ++n) {
+        double* r = b->hdata + in.data + (int64_t)n * L.SREC;
+        std::memset(r, 0, sizeof(double) * L.SREC);
+        const int nx = nxv[n], nu = nuv[n], nxn = n < in.N ? nxv[n + 1] : 0, ng = ngv[n];
+        // F = [B A]
+        if (n < in.N) {
+            const double* A = qp_field(q, n, F_A);
+            const double* B = qp_field(q, n, F_B);
+            const double* bb = qp_field(q, n, F_b);
+            for (int j = 0; j < nu; ++j)
+                for (int i2 = 0; i2 < nxn; ++i2) r[L.D_F + i2 + j * NX] = B[i2 + (size_t)j * nxn];
+            for (int j = 0; j < nx; ++j)
+                for (int i2 = 0; i2 < nxn; ++i2) r[L.D_F + i2 + (NU + j) * NX] = A[i2 + (size_t)j * nxn];
+            for (int i2 = 0; i2 < nxn; ++i2) r[L.D_b + i2] = bb[i2];
+        }
+        // H = [[R, S], [S', Q]] padded with unit diagonal
+        {
+            const double* Q = qp_field(q, n, F_Q);
+            const double* S = qp_field(q, n, F_S);
+            const double* R = qp_field(q, n, F_R);
+            double* H = r + L.D_H;
+            for (int j = 0; j < nu; ++j)
+                for (int i2 = 0; i2 < nu; ++i2) H[i2 + j * NZ] = R[i2 + (size_t)j * nu];
+            for (int j = 0; j < nx; ++j)
+                for (int i2 = 0; i2 < nu; ++i2) {
+                    const double s = S[i2 + (size_t)j * nu];
+                    H[i2 + (NU + j) * NZ] = s;
+                    H[(NU + j) + i2 * NZ] = s;
+                }
+            for (int j = 0; j < nx; ++j)
+                for (int i2 = 0; i2 < nx; ++i2) H[(NU + i2) + (NU + j) * NZ] = Q[i2 + (size_t)j * nx];
+            for (int j = nu; j < NU; ++j) H[j + j * NZ] = 1.0;
+            for (int j = NU + nx; j < NZ; ++j) H[j + j * NZ] = 1.0;
+            const double* qv = qp_field(q, n, F_q);
+            const double* rv = qp_field(q, n, F_r);
+            for (int j = 0; j < nu; ++j) r[L.D_g + j] = rv[j];
+            for (int j = 0; j < nx; ++j) r[L.D_g + NU + j] = qv[j];
+        }
+        // boxes
+        {
+            const int* iu = q->idx + q->ioff[n];
+            const int* ix = iu + nbuv[n];
+            const double* lbu = qp_field(q, n, F_lbu);
+            const double* ubu = qp_field(q, n, F_ubu);
+            const double* lbx = qp_field(q, n, F_lbx);
+            const double* ubx = qp_field(q, n, F_ubx);
+            for (int k = 0; k < nbuv[n]; ++k) {
+                const int c = iu[k];
+                r[L.D_bm + c] = 1.0;
+                r[L.D_blo + c] = lbu[k];
+                r[L.D_bhi + c] = ubu[k];
+                slots[so++] = c;
+            }
+            for (int k = 0; k < nbxv[n]; ++k) {
+                const int c = NU + ix[k];
+                r[L.D_bm + c] = 1.0;
+                r[L.D_blo + c] = lbx[k];
+                r[L.D_bhi + c] = ubx[k];
+                slots[so++] = c;
+            }
+        }
+        // general rows
+        if (ng > 0) {
+            const double* D = qp_field(q, n, F_D);
+            const double* C = qp_field(q, n, F_C);
+            const double* lg = qp_field(q, n, F_lg);
+            const double* ug = qp_field(q, n, F_ug);
+            for (int k = 0; k < ng; ++k) {
+                for (int j = 0; j < nu; ++j) r[L.D_G + k + j * L.NG] = D[k + (size_t)j * ng];
+                for (int j = 0; j < nx; ++j) r[L.D_G + k + (NU + j) * L.NG] = C[k + (size_t)j * ng];
+                r[L.D_gm + k] = 1.0;
+                r[L.D_glo + k] = lg[k];
+                r[L.D_ghi + k] = ug[k];
+                slots[so++] = NZ + k;
+            }
+        }
+    }
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_load(oqp_batch* b, const oqp_qp* const* qps)
+{
+    if (!b || !qps) return fail(OQP_EINVAL, "oqp_batch_load: NULL argument");
+    for (int i = 0; i < b->count; ++i) {
+        if (!qps[i]) return fail(OQP_EINVAL, "oqp_batch_load: qp %d is NULL", i);
+        int rc = pack_instance(b, i, qps[i]);
+        if (rc) return rc;
+    }
+    hipError_t e = hipMemcpyAsync(b->ddata, b->hdata, sizeof(double) * b->n_data, hipMemcpyHostToDevice,
+                                  (hipStream_t)b->stream);
+    if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_load: hipMemcpyAsync: %s", hipGetErrorString(e));
+    b->loaded = 1;
+    return OQP_OK;
+}
+
+static oqp::KParams make_params(const oqp_arg& a, int mode, double tau)
+{
+    oqp::KParams P{};
+    P.tol_stat = a.tol_stat;
+    P.tol_eq = a.tol_eq;
+    P.tol_ineq = a.tol_ineq;
+    P.tol_comp = a.tol_comp;
+    P.alpha_min = a.alpha_min;
+    P.gamma = a.gamma;
+    P.lam_min = a.lam_min;
+    P.t_min = a.t_min;
+    P.reg_prim = a.reg_prim;
+    P.corr_ratio = a.corr_ratio;
+    P.ir_tol = a.ir_tol;
+    P.tau = tau;
+    P.iter_max = a.iter_max;
+    P.ir_max = a.ir_max;
+    P.mode = mode;
+    return P;
+}
+
+static int launch_all(oqp_batch* b, const oqp::KParams& P)
+{
+    for (int v = 0; v < b->nvar; ++v) {
+        if (b->vcount[v] == 0) continue;
+        int rc = oqp::variant_launch(v, b->ddesc + b->vstart[v], b->vcount[v], b->ddata, b->diter, b->dwork,
+                                     b->dstep, b->dstat, P, b->stream);
+        if (rc) return fail(OQP_EDEVICE, "kernel launch failed for variant %d", v);
+    }
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_solve(oqp_batch* b)
+{
+    if (!b) return fail(OQP_EINVAL, "oqp_batch_solve: NULL batch");
+    if (!b->loaded) return fail(OQP_ESTATE, "oqp_batch_solve: no data loaded");
+    int rc = launch_all(b, make_params(b->arg, oqp::KMODE_SOLVE, 0.0));
+    if (rc) return rc;
+    b->solved = 1;
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_set_arg(oqp_batch* b, const oqp_arg* a)
+{
+    if (!b) return fail(OQP_EINVAL, "oqp_batch_set_arg: NULL batch");
+    int rc = check_arg(a);
+    if (rc) return rc;
+    if (a->mode != b->arg.mode) return fail(OQP_EINVAL, "oqp_batch_set_arg: mode cannot change");
+    b->arg = *a;
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_fetch(oqp_batch* b)
+{
+    if (!b) return fail(OQP_EINVAL, "oqp_batch_fetch: NULL batch");
+    hipStream_t s = (hipStream_t)b->stream;
+    hipError_t e = hipMemcpyAsync(b->hstat, b->dstat, sizeof(DevStat) * b->count, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->hiter, b->diter, sizeof(double) * b->n_iter, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && b->has_step)
+        e = hipMemcpyAsync(b->hstep, b->dstep, sizeof(double) * b->n_iter, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_fetch: %s", hipGetErrorString(e));
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_sync(oqp_batch* b)
+{
+    if (!b) return fail(OQP_EINVAL, "oqp_batch_sync: NULL batch");
+    hipError_t e = hipStreamSynchronize((hipStream_t)b->stream);
+    if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_sync: %s", hipGetErrorString(e));
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_get_stat(const oqp_batch* b, int i, oqp_stat* st)
+{
+    if (!b || !st || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_get_stat: bad argument");
+    const DevStat& d = b->hstat[i];
+    st->status = d.status;
+    st->iters = d.iters;
+    st->ir_steps = d.ir_steps;
+    st->reserved = 0;
+    st->mu = d.mu;
+    for (int k = 0; k < 4; ++k) st->res[k] = d.res[k];
+    return OQP_OK;
+}
+
+// Copy between the padded iterate layout and the user layout.
+static void user_copy(const oqp_batch* b, int i, double* region, bool to_user, double* u, double* x, double* pi,
+                      double* ll, double* lu, double* tl, double* tu)
+{
+    const Inst& in = b->inst[i];
+    const Layout L = inst_layout(in);
+    const int* nxv = inst_dims(b, in, 0);
+    const int* nuv = inst_dims(b, in, 1);
+    const int* nbuv = inst_dims(b, in, 2);
+    const int* nbxv = inst_dims(b, in, 3);
+    const int* ngv = inst_dims(b, in, 4);
+    const int* slots = b->slot_pool + in.slot_off;
+    int ou = 0, ox = 0, op = 0, oc = 0;
+    for (int n = 0; n <= in.N; ++n) {
+        double* r = region + in.iter + (int64_t)n * L.IREC;
+        const int nu = nuv[n], nx = nxv[n];
+        for (int j = 0; j < nu; ++j) {
+            if (u) { if (to_user) u[ou + j] = r[L.I_z + j]; else r[L.I_z + j] = u[ou + j]; }
+        }
+        for (int j = 0; j < nx; ++j) {
+            if (x) { if (to_user) x[ox + j] = r[L.I_z + L.NU + j]; else r[L.I_z + L.NU + j] = x[ox + j]; }
+        }
+        if (n > 0) {
+            for (int j = 0; j < nx; ++j) {
+                if (pi) { if (to_user) pi[op + j] = r[L.I_pi + j]; else r[L.I_pi + j] = pi[op + j]; }
+            }
+            op += nx;
+        }
+        const int nc = nbuv[n] + nbxv[n] + ngv[n];
+        for (int k = 0; k < nc; ++k) {
+            const int c = slots[oc + k];
+            double* vals[4] = {ll, lu, tl, tu};
+            const int offs[4] = {L.I_ll, L.I_lu, L.I_tl, L.I_tu};
+            for (int a = 0; a < 4; ++a) {
+                if (!vals[a]) continue;
+                if (to_user) vals[a][oc + k] = r[offs[a] + c];
+                else r[offs[a] + c] = vals[a][oc + k];
+            }
+        }
+        ou += nu;
+        ox += nx;
+        oc += nc;
+    }
+}
+
+extern "C" int oqp_batch_get_sol(const oqp_batch* b, int i, double* u, double* x, double* pi, double* lam_l,
+                                 double* lam_u, double* t_l, double* t_u)
+{
+    if (!b || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_get_sol: bad argument");
+    user_copy(b, i, b->hiter, true, u, x, pi, lam_l, lam_u, t_l, t_u);
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_set_iterate(oqp_batch* b, int i, const double* u, const double* x, const double* pi,
+                                     const double* lam_l, const double* lam_u, const double* t_l, const double* t_u)
+{
+    if (!b || i < 0 || i >= b->count || !u || !x || !pi || !lam_l || !lam_u || !t_l || !t_u)
+        return fail(OQP_EINVAL, "oqp_batch_set_iterate: bad argument");
+    const Inst& in = b->inst[i];
+    const Layout L = inst_layout(in);
+    std::memset(b->hiter + in.iter, 0, sizeof(double) * (size_t)(in.N + 1) * L.IREC);
+    user_copy(b, i, b->hiter, false, (double*)u, (double*)x, (double*)pi, (double*)lam_l, (double*)lam_u,
+              (double*)t_l, (double*)t_u);
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_newton(oqp_batch* b, double tau)
+{
+    if (!b) return fail(OQP_EINVAL, "oqp_batch_newton: NULL batch");
+    if (!b->loaded) return fail(OQP_ESTATE, "oqp_batch_newton: no data loaded");
+    hipError_t e = hipMemcpyAsync(b->diter, b->hiter, sizeof(double) * b->n_iter, hipMemcpyHostToDevice,
+                                  (hipStream_t)b->stream);
+    if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_newton: %s", hipGetErrorString(e));
+    int rc = launch_all(b, make_params(b->arg, oqp::KMODE_NEWTON, tau));
+    if (rc) return rc;
+    b->has_step = 1;
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_get_step(const oqp_batch* b, int i, double* du, double* dx, double* dpi, double* dll,
+                                  double* dlu, double* dtl, double* dtu)
+{
+    if (!b || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_get_step: bad argument");
+    if (!b->has_step) return fail(OQP_ESTATE, "oqp_batch_get_step: no Newton step computed");
+    user_copy(b, i, b->hstep, true, du, dx, dpi, dll, dlu, dtl, dtu);
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_variant(const oqp_batch* b, int i, int* nx, int* nu, int* ng)
+{
+    if (!b || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_variant: bad argument");
+    int v = b->inst[i].variant;
+    int a, c, d;
+    oqp::variant_dims(v, &a, &c, &d);
+    if (nx) *nx = a;
+    if (nu) *nu = c;
+    if (ng) *ng = d;
+    return v;
+}
+
+extern "C" int oqp_variant_count(void) { return oqp::variant_count(); }
+
+extern "C" int oqp_variant_dims(int v, int* nx, int* nu, int* ng)
+{
+    if (v < 0 || v >= oqp::variant_count()) return fail(OQP_EINVAL, "oqp_variant_dims: no variant %d", v);
+    oqp::variant_dims(v, nx, nu, ng);
+    return OQP_OK;
+}

@@ -1,0 +1,132 @@
+// Device memory layout of the batched OCP-QP IPM.
+//
+// Every instance is padded to the stage sizes (NX, NU, NG) of the kernel
+// variant ("bucket") that solves it.  Padded inputs carry unit Hessian
+// diagonal and zero coupling, padded general rows are masked, so the padded
+// problem has the same minimiser (padded components are exactly zero).
+//
+// One instance = N+1 stage records, each a fixed number of doubles, stored
+// contiguously so that one workgroup streams its own instance stage by stage
+// with coalesced loads.
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define OQP_HD __host__ __device__
+#else
+#define OQP_HD
+#endif
+
+namespace oqp {
+
+OQP_HD constexpr int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+struct Layout {
+    int NX, NU, NG, NZ, NC;
+    // problem data record (doubles), one per stage
+    int D_F, D_H, D_g, D_b, D_bm, D_blo, D_bhi, D_G, D_gm, D_glo, D_ghi, SREC;
+    // iterate record (doubles), one per stage: z, pi_n, lam_l, lam_u, t_l, t_u
+    int I_z, I_pi, I_ll, I_lu, I_tl, I_tu, IREC;
+    // workspace record (doubles), one per stage
+    int W_rg, W_rb, W_rdl, W_rdu, W_yu, W_pv, W_dz, W_dpi, W_dll, W_dlu, W_dtl, W_dtu;
+    int W_all, W_alu, W_atl, W_atu, W_irg, W_irb, W_irdl, W_irdu, W_irml, W_irmu, W_L, W_dinv, WREC;
+};
+
+// F = [B A] is NX x NZ column-major, H is NZ x NZ column-major (full
+// symmetric), G is NG x NZ column-major.  Constraint slots per stage: NC =
+// NZ box slots (one per component of z = [u; x], masked by bm) followed by
+// NG general rows (masked by gm).
+OQP_HD constexpr Layout make_layout(int NX, int NU, int NG)
+{
+    Layout L{};
+    L.NX = NX; L.NU = NU; L.NG = NG; L.NZ = NX + NU; L.NC = NX + NU + NG;
+    const int NZ = L.NZ, NC = L.NC;
+    int o = 0;
+    L.D_F = o; o += NX * NZ;
+    L.D_H = o; o += NZ * NZ;
+    L.D_g = o; o += NZ;
+    L.D_b = o; o += NX;
+    L.D_bm = o; o += NZ;
+    L.D_blo = o; o += NZ;
+    L.D_bhi = o; o += NZ;
+    L.D_G = o; o += NG * NZ;
+    L.D_gm = o; o += NG;
+    L.D_glo = o; o += NG;
+    L.D_ghi = o; o += NG;
+    L.SREC = round_up(o, 8);
+    o = 0;
+    L.I_z = o; o += NZ;
+    L.I_pi = o; o += NX;
+    L.I_ll = o; o += NC;
+    L.I_lu = o; o += NC;
+    L.I_tl = o; o += NC;
+    L.I_tu = o; o += NC;
+    L.IREC = round_up(o, 8);
+    o = 0;
+    L.W_rg = o; o += NZ;
+    L.W_rb = o; o += NX;
+    L.W_rdl = o; o += NC;
+    L.W_rdu = o; o += NC;
+    L.W_yu = o; o += round_up(NU, 1);
+    L.W_pv = o; o += NX;
+    L.W_dz = o; o += NZ;
+    L.W_dpi = o; o += NX;
+    L.W_dll = o; o += NC;
+    L.W_dlu = o; o += NC;
+    L.W_dtl = o; o += NC;
+    L.W_dtu = o; o += NC;
+    L.W_all = o; o += NC;
+    L.W_alu = o; o += NC;
+    L.W_atl = o; o += NC;
+    L.W_atu = o; o += NC;
+    L.W_irg = o; o += NZ;
+    L.W_irb = o; o += NX;
+    L.W_irdl = o; o += NC;
+    L.W_irdu = o; o += NC;
+    L.W_irml = o; o += NC;
+    L.W_irmu = o; o += NC;
+    o = round_up(o, 8);
+    L.W_L = o; o += NZ * NZ;
+    L.W_dinv = o; o += NZ;
+    L.WREC = round_up(o, 8);
+    return L;
+}
+
+// Per-instance descriptor (device).  Offsets are in doubles from the base of
+// the respective region.
+struct InstDesc {
+    int64_t data;   // stage records of the problem data
+    int64_t iter;   // iterate records (the solution region)
+    int64_t work;   // workspace records
+    int32_t N;      // horizon
+    int32_t nc;     // number of two-sided constraints (box + general)
+    int32_t index;  // position of the instance in the caller's batch
+    int32_t pad;
+};
+
+// Per-instance result written by the kernel.
+struct DevStat {
+    int32_t status;
+    int32_t iters;
+    int32_t ir_steps;
+    int32_t pad;
+    double mu;
+    double res[4];  // inf-norms of r_g, r_b, r_d, lam.*t at the returned iterate
+};
+
+// Solver arguments passed by value to every launch.
+struct KParams {
+    double tol_stat, tol_eq, tol_ineq, tol_comp;
+    double alpha_min, gamma, lam_min, t_min, reg_prim, corr_ratio, ir_tol;
+    double tau;         // Newton-step entry: r_m = lam.*t - tau
+    int32_t iter_max;
+    int32_t ir_max;
+    int32_t mode;       // KMODE_SOLVE or KMODE_NEWTON
+    int32_t pad;
+};
+
+enum { KMODE_SOLVE = 0, KMODE_NEWTON = 1 };
+enum { ST_SUCCESS = 0, ST_MAX_ITER = 1, ST_MIN_STEP = 2, ST_NAN = 3 };
+
+}  // namespace oqp

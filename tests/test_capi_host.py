@@ -1,0 +1,107 @@
+"""Host-side checks of the C-ABI (no GPU needed): the library loads, exports
+every function include/oqp.h declares, and rejects bad input before any
+device call."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2003_02547_amd import binding as B
+from paper_2003_02547_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "oqp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(oqp_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_variant_table():
+    v = B.variants()
+    assert (16, 8, 0) in v and (8, 4, 0) in v
+    for nx, nu, ng in v:
+        assert nx + nu <= 64 and ng <= 64
+
+
+def test_dims_errors():
+    L = B.lib()
+    assert L.oqp_dims_bytes(0) == 0
+    mem = B._aligned(L.oqp_dims_bytes(3))
+    h = ct.c_void_p()
+    assert L.oqp_dims_init(mem.ctypes.data, 8, 3, ct.byref(h)) == B.ENOMEM
+    assert L.oqp_dims_init(mem.ctypes.data, mem.nbytes, 0, ct.byref(h)) == B.EINVAL
+    assert L.oqp_dims_init(mem.ctypes.data, mem.nbytes, 3, ct.byref(h)) == B.OK
+    assert L.oqp_dims_set_stage(h, 4, 1, 1, 0, 0, 0) == B.EINVAL
+    assert L.oqp_dims_set_stage(h, 1, 2, 1, 2, 0, 0) == B.EINVAL  # nbu > nu
+    assert L.oqp_dims_set_stage(h, 1, 2, 1, 1, 2, 0) == B.OK
+    assert b"oqp_dims_set_stage" in L.oqp_last_error() or L.oqp_last_error() is not None
+
+
+def test_qp_setter_errors():
+    qp = W.mass_spring_chain4(1)
+    q = B.Qp(qp)
+    L = B.lib()
+    idx = np.array([0, 0, 1], dtype=np.int32)
+    lo = np.zeros(3); hi = np.ones(3)
+    rc = L.oqp_qp_set_box_u(q.h, 0, idx.ctypes.data_as(B._PI), B._p(lo), B._p(hi))
+    assert rc == B.EINVAL and b"repeated" in L.oqp_last_error()
+    idx = np.array([0, 1, 5], dtype=np.int32)
+    rc = L.oqp_qp_set_box_u(q.h, 0, idx.ctypes.data_as(B._PI), B._p(lo), B._p(hi))
+    assert rc == B.EINVAL
+    idx = np.array([0, 1, 2], dtype=np.int32)
+    rc = L.oqp_qp_set_box_u(q.h, 0, idx.ctypes.data_as(B._PI), B._p(hi), B._p(lo))
+    assert rc == B.EINVAL and b"lo > hi" in L.oqp_last_error()
+    A = np.eye(8)
+    assert L.oqp_qp_set_dyn(q.h, 10, B._p(A), 8, None, 8, None) == B.EINVAL  # stage N has no dynamics
+    assert L.oqp_qp_set_dyn(q.h, 0, B._p(A), 4, None, 8, None) == B.EINVAL   # lda too small
+
+
+def test_batch_size_and_plan_errors():
+    L = B.lib()
+    arg = B.default_arg()
+    qps = [W.mass_spring_chain4(s) for s in range(3)]
+    dims = [B.Dims.of(q) for q in qps]
+    arr = (ct.c_void_p * 3)(*[d.h for d in dims])
+    hb, db = ct.c_size_t(), ct.c_size_t()
+    assert L.oqp_batch_bytes(arr, 3, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.OK
+    assert hb.value > 0 and db.value > 0
+    # too small buffers are refused before any device call
+    host = B._aligned(hb.value)
+    h = ct.c_void_p()
+    rc = L.oqp_batch_init(arr, 3, ct.byref(arg), host.ctypes.data, hb.value, ct.c_void_p(256), db.value - 1,
+                          None, ct.byref(h))
+    assert rc == B.ENOMEM
+    rc = L.oqp_batch_init(arr, 3, ct.byref(arg), host.ctypes.data, hb.value - 1, ct.c_void_p(256), db.value,
+                          None, ct.byref(h))
+    assert rc == B.ENOMEM
+    # stage sizes beyond every compiled variant
+    big = B.Dims(2, [80, 80, 80], [2, 2, 0], [0, 0, 0], [0, 0, 0], [0, 0, 0])
+    arr1 = (ct.c_void_p * 1)(big.h)
+    assert L.oqp_batch_bytes(arr1, 1, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.EINVAL
+    # bad arguments
+    bad = B.default_arg(gamma=1.5)
+    assert L.oqp_batch_bytes(arr, 3, ct.byref(bad), ct.byref(hb), ct.byref(db)) == B.EINVAL
+    bad = B.default_arg(warm_start=1)
+    assert L.oqp_batch_bytes(arr, 3, ct.byref(bad), ct.byref(hb), ct.byref(db)) == B.EINVAL
+    assert L.oqp_batch_bytes(arr, 0, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.EINVAL
+
+
+def test_bucket_choice_covers_instance():
+    qp = W.mass_spring_chain8(0)
+    L = B.lib()
+    # smallest variant covering nx=16, nu=7, ng=0 is (16, 8, 0)
+    cover = [(a, b, c) for a, b, c in B.variants() if a >= 16 and b >= 7]
+    assert (16, 8, 0) in cover
