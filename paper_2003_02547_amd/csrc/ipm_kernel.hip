@@ -1,9 +1,10 @@
 // Batched OCP-QP primal-dual interior-point method on gfx950.
 //
-// One 64-lane workgroup solves one instance end to end (the whole IPM loop
-// runs inside the launch).  Stage blocks are compile-time sized (NX, NU, NG)
-// and staged through LDS; per-stage data is streamed from HBM in the stage
-// order of each sweep.
+// One 64-lane workgroup (one wave) solves one instance end to end: the whole
+// IPM loop runs inside the launch.  Stage blocks are compile-time sized
+// (NX, NU, NG) and staged through LDS; each sweep streams its stage records
+// from HBM one stage ahead (register prefetch), so the global-memory latency
+// of the next stage overlaps the arithmetic of the current one.
 //
 // Method (paper: "HPIPM: a high-performance quadratic programming framework
 // for model predictive control"):
@@ -26,6 +27,12 @@
 //   dpi_{n+1} = L_{n+1} L_{n+1}' dx_{n+1} + p_{n+1}
 // with gt = r_g - C'(W r_d - T^{-1} r_m), dt = C dy - r_d,
 // dlam = -T^{-1}(r_m + Lam dt), C = [G; -G] the stacked two-sided rows.
+//
+// Passes per IPM iteration: A (backward: apply the previous step, residuals,
+// barrier terms, factorization, predictor right-hand side), B (forward:
+// predictor step, step length, affine duality measure), C (backward:
+// corrector right-hand side), B again (corrector step); C and B once more
+// only when the conditional corrector is rejected.
 #include <hip/hip_runtime.h>
 
 #include "layout.h"
@@ -34,8 +41,23 @@ namespace oqp {
 
 constexpr int WAVE = 64;
 
+__host__ __device__ constexpr int ru8(int v) { return (v + 7) / 8 * 8; }
+__host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Ordering point for LDS traffic inside one wave.  Every workgroup of this
+// kernel is a single wave, and the LDS operations of a wave execute in
+// order, so a compiler-level barrier is all that is needed.
+__device__ __forceinline__ void wsync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ double nmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
+// xor-butterfly reductions: every lane ends with the same bits (each step
+// combines two equal-valued halves with a commutative operation)
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll
@@ -66,6 +88,22 @@ __device__ __forceinline__ double bcast(double v, int src)
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// 1/sqrt(x) to double precision: hardware estimate and one Newton step.
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x * y;
+    return y * (1.5 - h * y);
+}
+
+// 1/x to double precision: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * (2.0 - x * y);
+    return y * (2.0 - x * y);
+}
+
 // Right-hand-side variants of the complementarity row r_m.
 enum { RM_SHIFT = 0,      // r_m = lam.*t - shift
        RM_CORRECTOR = 1,  // r_m = lam.*t + dlam_aff.*dt_aff - shift
@@ -77,27 +115,40 @@ struct Ipm {
     static constexpr int NZ = NX + NU;
     static constexpr int NC = NZ + NG;
     static constexpr int NV = NX + NG;
-    static constexpr int LDZ = NZ | 1;
-    static constexpr int LDX = NX | 1;
-    static constexpr int LDV = NV | 1;
+    static constexpr int NZP = ru8(NZ);
+    static constexpr int NXP = ru8(NX);
+    static constexpr int NVP = ru8(NV);
+    static constexpr int LDZ = NZP + 1;
+    static constexpr int LDX = NXP + 1;
+    static constexpr int LDV = NVP + 1;
     static constexpr int LDG = NG > 0 ? (NG | 1) : 1;
-    static constexpr int NCP = NC > WAVE ? 2 * WAVE : WAVE;  // LDS vector length for slot vectors
-    static_assert(NZ <= WAVE && NX <= WAVE && NG <= WAVE, "stage block must fit one wave");
+    static constexpr int NCT = cdiv(NC, WAVE);                   // constraint slots per lane
+    static constexpr int EH = cdiv(NZ * NZ, WAVE);               // H elements per lane
+    static constexpr int EF = cdiv(NX * NZ, WAVE);               // F elements per lane
+    static constexpr int EG = NG > 0 ? cdiv(NG * NZ, WAVE) : 1;
+    static constexpr int EL = NU > 0 ? cdiv(NZ * NU, WAVE) : 1;  // factor u-columns per lane
+    static constexpr int EX = cdiv(NX * NX, WAVE);               // factor (x, x) block per lane
+    static constexpr int NU1 = NU > 0 ? NU : 1;
+    static constexpr int TZ = NZP / 8;                           // register tile extents
+    static constexpr int TX = NXP / 8;
+    static_assert(NZ <= WAVE && NG <= WAVE, "stage block must fit one wave");
 
     struct Smem {
-        double M[LDZ * NZ];      // stage matrix / factor (column-major)
-        double Lx[2][LDX * NX];  // L_{n+1} (lower, zero strict upper), by stage parity
-        double F[LDX * NZ];      // [B A] of the stage
-        double V[LDV * NZ];      // [U; sqrt(w) G]
-        double G[LDG * NZ];      // general rows of the stage
-        double col[2][WAVE];     // Cholesky column broadcast
-        double z[WAVE];          // z_n (or dz_n)
-        double t0[WAVE], t1[WAVE], t2[WAVE];
-        double e[NCP];           // reduced-gradient terms per constraint slot
-        double ws[NCP];          // barrier weights per constraint slot
-        double xn[2][WAVE];      // x_{n+1} / dx_{n+1}, by parity
-        double pin[2][WAVE];     // pi_{n+1}, by parity
-        double pn[2][WAVE];      // p_{n+1}, by parity
+        double M[LDZ * NZP];      // stage matrix / factor (column-major)
+        double Lx[2][LDX * NXP];  // L_{n+1} (lower, zero strict upper), by stage parity
+        double F[LDX * NZP];      // [B A] of the stage
+        double V[LDV * NZP];      // [U; sqrt(w) G]
+        double G[LDG * NZP];      // general rows of the stage
+        double z[WAVE];           // z_n or dz_n
+        double rb[WAVE];          // r_b of the stage
+        double t1[WAVE], t2[WAVE];
+        double e[NCT * WAVE];     // reduced-gradient terms per constraint slot
+        double ws[NCT * WAVE];    // barrier weights per constraint slot
+        double xn[2][WAVE];       // x_{n+1} / dx_{n+1}, by parity
+        double pin[2][WAVE];      // pi_{n+1}, by parity
+        double pn[2][WAVE];       // p_{n+1}, by parity
+        double col[WAVE];         // Cholesky column broadcast
+        double Lst[LDZ * NZP];    // factor of the last stage, staged for the copy out
     };
 
     const double* __restrict__ dat;
@@ -106,7 +157,6 @@ struct Ipm {
     int N, nc, lane;
     const KParams& P;
 
-    // The workgroup's LDS block (one instance per workgroup).
     __device__ __forceinline__ static Smem& S()
     {
         __shared__ Smem smem;
@@ -120,45 +170,105 @@ struct Ipm {
     __device__ __forceinline__ double* Ip(int n) const { return itr + (size_t)n * Lo.IREC; }
     __device__ __forceinline__ double* Wp(int n) const { return wk + (size_t)n * Lo.WREC; }
 
-    // global (ld = R) -> LDS (ld = LD), R x C column-major
-    template <int R, int C, int LD>
-    __device__ __forceinline__ void load_mat(double* dst, const double* __restrict__ src) const
+    __device__ __forceinline__ int slot(int t) const { return lane + WAVE * t; }
+
+    // per-lane loads of an R x C column-major block (element e = lane + 64 t)
+    template <int R, int C, int E>
+    __device__ __forceinline__ void fetch(double (&r)[E], const double* __restrict__ src) const
     {
-        Smem& s = S();
-        (void)s;
 #pragma unroll
-        for (int e0 = 0; e0 < R * C; e0 += WAVE) {
-            int e = e0 + lane;
-            if (e < R * C) {
-                int i = e % R, j = e / R;
-                dst[i + j * LD] = src[e];
-            }
+        for (int t = 0; t < E; ++t) {
+            const int e = lane + WAVE * t;
+            r[t] = (e < R * C) ? src[e] : 0.0;
+        }
+    }
+    template <int R, int C, int E>
+    __device__ __forceinline__ void commit(double* dst, int ld, const double (&r)[E]) const
+    {
+#pragma unroll
+        for (int t = 0; t < E; ++t) {
+            const int e = lane + WAVE * t;
+            if (e < R * C) dst[(e % R) + (e / R) * ld] = r[t];
         }
     }
 
-    __device__ __forceinline__ static double slot_mask(const double* d, int c)
+    // constraint slot data: mask, lower, upper
+    __device__ __forceinline__ void slot_bounds(const double* d, int c, double& m, double& lo, double& hi) const
     {
-        return c < NZ ? d[Lo.D_bm + c] : d[Lo.D_gm + (c - NZ)];
+        if (c < NZ) {
+            m = d[Lo.D_bm + c];
+            lo = d[Lo.D_blo + c];
+            hi = d[Lo.D_bhi + c];
+        } else if (c < NC) {
+            m = d[Lo.D_gm + (c - NZ)];
+            lo = d[Lo.D_glo + (c - NZ)];
+            hi = d[Lo.D_ghi + (c - NZ)];
+        } else {
+            m = 0.0;
+            lo = 0.0;
+            hi = 0.0;
+        }
     }
 
-    // r_m for slot c of stage record (ir, w), lower and upper.
-    __device__ __forceinline__ void rm_of(int rmode, double shift, const double* ir, const double* w, int c, double& rml,
-                          double& rmu) const
+    // ------------------------------------------------------------------
+    // Register-blocked products on LDS blocks (lanes as an 8 x 8 grid)
+    // ------------------------------------------------------------------
+
+    // V[i][k] = sum_l L[l][i] F[l][k], i < NX, k < NZP (L lower, zero strict upper)
+    __device__ __forceinline__ void trmm_LtF(const double* __restrict__ Lx) const
     {
         Smem& s = S();
-        (void)s;
-        if (rmode == RM_IR) {
-            rml = w[Lo.W_irml + c];
-            rmu = w[Lo.W_irmu + c];
-            return;
+        const int a = lane & 7, b = lane >> 3;
+        double acc[TX][TZ];
+#pragma unroll
+        for (int p = 0; p < TX; ++p)
+#pragma unroll
+            for (int q = 0; q < TZ; ++q) acc[p][q] = 0.0;
+#pragma unroll 4
+        for (int l = 0; l < NX; ++l) {
+            double lv[TX], fv[TZ];
+#pragma unroll
+            for (int p = 0; p < TX; ++p) lv[p] = Lx[l + (a + 8 * p) * LDX];
+#pragma unroll
+            for (int q = 0; q < TZ; ++q) fv[q] = s.F[l + (b + 8 * q) * LDX];
+#pragma unroll
+            for (int p = 0; p < TX; ++p)
+#pragma unroll
+                for (int q = 0; q < TZ; ++q) acc[p][q] += lv[p] * fv[q];
         }
-        double ll = ir[Lo.I_ll + c], lu = ir[Lo.I_lu + c], tl = ir[Lo.I_tl + c], tu = ir[Lo.I_tu + c];
-        rml = ll * tl - shift;
-        rmu = lu * tu - shift;
-        if (rmode == RM_CORRECTOR) {
-            rml += w[Lo.W_all + c] * w[Lo.W_atl + c];
-            rmu += w[Lo.W_alu + c] * w[Lo.W_atu + c];
+#pragma unroll
+        for (int p = 0; p < TX; ++p)
+#pragma unroll
+            for (int q = 0; q < TZ; ++q)
+                if (a + 8 * p < NX) s.V[(a + 8 * p) + (b + 8 * q) * LDV] = acc[p][q];
+    }
+
+    // M[i][k] += sum_{r0 <= r < NV} V[r][i] V[r][k] for i, k < NZP
+    __device__ __forceinline__ void syrk_VtV(int r0) const
+    {
+        Smem& s = S();
+        const int a = lane & 7, b = lane >> 3;
+        double acc[TZ][TZ];
+#pragma unroll
+        for (int p = 0; p < TZ; ++p)
+#pragma unroll
+            for (int q = 0; q < TZ; ++q) acc[p][q] = 0.0;
+#pragma unroll 4
+        for (int r = r0; r < NV; ++r) {
+            double vi[TZ], vk[TZ];
+#pragma unroll
+            for (int p = 0; p < TZ; ++p) vi[p] = s.V[r + (a + 8 * p) * LDV];
+#pragma unroll
+            for (int q = 0; q < TZ; ++q) vk[q] = s.V[r + (b + 8 * q) * LDV];
+#pragma unroll
+            for (int p = 0; p < TZ; ++p)
+#pragma unroll
+                for (int q = 0; q < TZ; ++q) acc[p][q] += vi[p] * vk[q];
         }
+#pragma unroll
+        for (int p = 0; p < TZ; ++p)
+#pragma unroll
+            for (int q = 0; q < TZ; ++q) s.M[(a + 8 * p) + (b + 8 * q) * LDZ] += acc[p][q];
     }
 
     // ------------------------------------------------------------------
@@ -168,30 +278,31 @@ struct Ipm {
     __device__ __forceinline__ void cholesky(double (&r)[NZ], double& dinv) const
     {
         Smem& s = S();
-        (void)s;
 #pragma unroll
         for (int k = 0; k < NZ; ++k) r[k] = lane < NZ ? s.M[lane + k * LDZ] : 0.0;
         dinv = 0.0;
+        // Updates are not masked: lane i only ever needs r[k] for k <= i, and
+        // the entries above the diagonal absorb harmless garbage.
 #pragma unroll
         for (int j = 0; j < NZ; ++j) {
-            double piv = bcast(r[j], j);
-            double ljj = sqrt(piv);
-            double inv = 1.0 / ljj;
-            double lij = r[j] * inv;
-            if (lane == j) {
-                r[j] = ljj;
-                dinv = inv;
-            } else if (lane > j) {
-                r[j] = lij;
-            }
+            const double inv = rsqrt_nr(bcast(r[j], j));
+            const double lij = r[j] * inv;
+            if (lane == j) dinv = inv;
+            if (lane >= j) r[j] = lij;  // on lane j: pivot / sqrt(pivot) = sqrt(pivot)
             if (j + 1 < NZ) {
-                s.col[j & 1][lane] = lij;
-                __syncthreads();
-#pragma unroll
-                for (int k = j + 1; k < NZ; ++k) {
-                    double lkj = s.col[j & 1][k];
-                    if (lane >= k) r[k] -= lij * lkj;
+                s.col[lane] = lij;
+                // the entries needed by the next two columns go through the
+                // scalar unit (critical path), the rest through LDS
+                const double l1 = bcast(lij, j + 1);
+                r[j + 1] -= lij * l1;
+                if (j + 2 < NZ) {
+                    const double l2 = bcast(lij, j + 2);
+                    r[j + 2] -= lij * l2;
                 }
+                wsync();
+#pragma unroll
+                for (int k = j + 3; k < NZ; ++k) r[k] -= lij * s.col[k];
+                wsync();
             }
         }
     }
@@ -202,541 +313,717 @@ struct Ipm {
     template <int CNT>
     __device__ __forceinline__ double fwd_subst_u(double m, const double (&rowL)[CNT], double dinv) const
     {
-        Smem& s = S();
-        (void)s;
 #pragma unroll
         for (int j = 0; j < NU; ++j) {
-            double y = bcast(m, j) * bcast(dinv, j);
+            const double y = bcast(m, j) * bcast(dinv, j);
             if (lane == j) m = y;
             else if (lane > j) m -= rowL[j] * y;
         }
         return m;
     }
 
-    // ------------------------------------------------------------------
-    // Backward pass: residuals at the iterate, barrier terms, square-root
-    // Riccati factorization and the right-hand-side sweep for r_m = lam.*t -
-    // shift.  Returns per-wave residual norms and lam't.
-    // ------------------------------------------------------------------
-    __device__ __forceinline__ void backward_factor(double shift, bool factor, double& n_g, double& n_b, double& n_d, double& n_m,
-                                    double& s_lt)
+    // m += F'(Lx (Lx' rb) + p_{n+1}) with rb in s.rb and Lx = L_{n+1}.
+    __device__ __forceinline__ double add_cost_to_go(double m, const double* __restrict__ Lx,
+                                                     const double* __restrict__ pnext) const
     {
         Smem& s = S();
-        (void)s;
-        double mg = 0.0, mb = 0.0, md = 0.0, mm = 0.0, slt = 0.0;
-        for (int n = N; n >= 0; --n) {
-            const int cur = n & 1, nxt = (n + 1) & 1;
-            const double* d = Dp(n);
-            double* ir = Ip(n);
-            double* w = Wp(n);
-            load_mat<NZ, NZ, LDZ>(s.M, d + Lo.D_H);
-            if (n < N) load_mat<NX, NZ, LDX>(s.F, d + Lo.D_F);
-            if constexpr (NG > 0) load_mat<NG, NZ, LDG>(s.G, d + Lo.D_G);
-            double zj = 0.0;
-            if (lane < NZ) {
-                zj = ir[Lo.I_z + lane];
-                s.z[lane] = zj;
-            }
-            if (lane < NX) s.t0[lane] = ir[Lo.I_pi + lane];  // pi_n
-            if constexpr (NG > 0) {
-                if (lane < NG)
-                    s.t1[lane] = d[Lo.D_gm + lane] * (ir[Lo.I_ll + NZ + lane] - ir[Lo.I_lu + NZ + lane]);
-            }
-            if (n == N) {
-                if (lane < NX) {
-                    s.xn[nxt][lane] = 0.0;
-                    s.pin[nxt][lane] = 0.0;
-                    s.pn[nxt][lane] = 0.0;
+        if (lane < NX) {
+            double acc = 0.0;
+#pragma unroll
+            for (int l = 0; l < NX; ++l) acc += Lx[l + lane * LDX] * s.rb[l];
+            s.t1[lane] = acc;
+        }
+        wsync();
+        if (lane < NX) {
+            double acc = pnext[lane];
+#pragma unroll
+            for (int l = 0; l < NX; ++l) acc += Lx[lane + l * LDX] * s.t1[l];
+            s.t2[lane] = acc;
+        }
+        wsync();
+        if (lane < NZ) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < NX; ++i) acc += s.F[i + lane * LDX] * s.t2[i];
+            m += acc;
+        }
+        return m;
+    }
+
+    // ==================================================================
+    // Pass A: apply the previous step (optional), residuals at the iterate,
+    // barrier terms, factorization, right-hand-side sweep for r_m = lam.*t -
+    // shift.  Returns the residual norms and lam't of the (updated) iterate.
+    // ==================================================================
+    struct PreA {
+        double H[EH], F[EF], G[EG];
+        double g, z, dz, b, pi, dpi;
+        double m[NCT], lo[NCT], hi[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
+        double dll[NCT], dlu[NCT], dtl[NCT], dtu[NCT];
+    };
+
+    __device__ __forceinline__ void loadA(PreA& p, int n, bool upd) const
+    {
+        const double* d = Dp(n);
+        const double* ir = Ip(n);
+        const double* w = Wp(n);
+        fetch<NZ, NZ, EH>(p.H, d + Lo.D_H);
+        if (n < N) fetch<NX, NZ, EF>(p.F, d + Lo.D_F);
+        if constexpr (NG > 0) fetch<NG, NZ, EG>(p.G, d + Lo.D_G);
+        p.g = p.z = p.dz = p.b = p.pi = p.dpi = 0.0;
+        if (lane < NZ) {
+            p.g = d[Lo.D_g + lane];
+            p.z = ir[Lo.I_z + lane];
+            if (upd) p.dz = w[Lo.W_dz + lane];
+        }
+        if (lane < NX) {
+            if (n < N) p.b = d[Lo.D_b + lane];
+            p.pi = ir[Lo.I_pi + lane];
+            if (upd) p.dpi = w[Lo.W_dpi + lane];
+        }
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+            const int c = slot(t);
+            slot_bounds(d, c, p.m[t], p.lo[t], p.hi[t]);
+            p.ll[t] = p.lu[t] = p.tl[t] = p.tu[t] = 0.0;
+            p.dll[t] = p.dlu[t] = p.dtl[t] = p.dtu[t] = 0.0;
+            if (c < NC) {
+                p.ll[t] = ir[Lo.I_ll + c];
+                p.lu[t] = ir[Lo.I_lu + c];
+                p.tl[t] = ir[Lo.I_tl + c];
+                p.tu[t] = ir[Lo.I_tu + c];
+                if (upd) {
+                    p.dll[t] = w[Lo.W_dll + c];
+                    p.dlu[t] = w[Lo.W_dlu + c];
+                    p.dtl[t] = w[Lo.W_dtl + c];
+                    p.dtu[t] = w[Lo.W_dtu + c];
                 }
             }
-            __syncthreads();
+        }
+    }
+
+    // Outputs of one stage of pass A, written to global memory at the top of
+    // the next stage (before that stage's prefetch is issued), so that the
+    // loop body itself holds no global memory operation: the single wait per
+    // stage then covers loads and stores issued a whole stage earlier.
+    struct OutA {
+        double z, pi, rg, rb, dinv, mv;
+        double ll[NCT], lu[NCT], tl[NCT], tu[NCT], rdl[NCT], rdu[NCT], m[NCT];
+    };
+
+    __device__ __forceinline__ void flushA(int n, bool upd, bool factor, const OutA& o) const
+    {
+        Smem& s = S();
+        double* ir = Ip(n);
+        double* w = Wp(n);
+        if (upd) {
+            if (lane < NZ) ir[Lo.I_z + lane] = o.z;
+            if (lane < NX && n > 0) ir[Lo.I_pi + lane] = o.pi;
+        }
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+            const int c = slot(t);
+            if (c < NC) {
+                if (upd && o.m[t] != 0.0) {
+                    ir[Lo.I_ll + c] = o.ll[t];
+                    ir[Lo.I_lu + c] = o.lu[t];
+                    ir[Lo.I_tl + c] = o.tl[t];
+                    ir[Lo.I_tu + c] = o.tu[t];
+                }
+                w[Lo.W_rdl + c] = o.rdl[t];
+                w[Lo.W_rdu + c] = o.rdu[t];
+            }
+        }
+        if (lane < NZ) w[Lo.W_rg + lane] = o.rg;
+        if (n < N && lane < NX) w[Lo.W_rb + lane] = o.rb;
+        if (factor) {
+            // factor staged in LDS (column-major), coalesced copy out
+#pragma unroll
+            for (int t = 0; t < EH; ++t) {
+                const int e = lane + WAVE * t;
+                if (e < NZ * NZ) w[Lo.W_L + e] = s.Lst[(e % NZ) + (e / NZ) * LDZ];
+            }
+            if (lane < NZ) w[Lo.W_dinv + lane] = o.dinv;
+            if (lane < NU) w[Lo.W_yu + lane] = o.mv;
+            else if (lane < NZ) w[Lo.W_pv + lane - NU] = o.mv;
+        }
+    }
+
+    __device__ __forceinline__ void passA(bool upd, double alpha, double shift, bool factor, double& o_g,
+                                          double& o_b, double& o_d, double& o_m, double& o_lt) const
+    {
+        Smem& s = S();
+        double mg = 0.0, mb = 0.0, md = 0.0, mm = 0.0, slt = 0.0;
+        PreA p;
+        OutA o;
+        loadA(p, N, upd);
+        for (int n = N; n >= 0; --n) {
+            const int cur = n & 1, nxt = cur ^ 1;
+            commit<NZ, NZ, EH>(s.M, LDZ, p.H);
+            if (n < N) commit<NX, NZ, EF>(s.F, LDX, p.F);
+            if constexpr (NG > 0) commit<NG, NZ, EG>(s.G, LDG, p.G);
+            const double g = p.g, b = p.b, dz = p.dz, dpi = p.dpi;
+            double z = p.z, pi = p.pi;
+            double m[NCT], lo[NCT], hi[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) {
+                m[t] = p.m[t];
+                lo[t] = p.lo[t];
+                hi[t] = p.hi[t];
+                ll[t] = p.ll[t];
+                lu[t] = p.lu[t];
+                tl[t] = p.tl[t];
+                tu[t] = p.tu[t];
+                if (upd && m[t] != 0.0) {
+                    ll[t] = fmax(ll[t] + alpha * p.dll[t], P.lam_min);
+                    lu[t] = fmax(lu[t] + alpha * p.dlu[t], P.lam_min);
+                    tl[t] = fmax(tl[t] + alpha * p.dtl[t], P.t_min);
+                    tu[t] = fmax(tu[t] + alpha * p.dtu[t], P.t_min);
+                }
+            }
+            if (n < N) flushA(n + 1, upd, factor, o);  // outputs of the previous stage
+            if (n > 0) loadA(p, n - 1, upd);           // prefetch the next stage of the sweep
+
+            if (upd) {
+                z += alpha * dz;
+                if (n > 0) pi += alpha * dpi;
+            }
+            if (n == N && lane < NX) {
+                s.xn[nxt][lane] = 0.0;
+                s.pin[nxt][lane] = 0.0;
+                s.pn[nxt][lane] = 0.0;
+            }
+            if (lane < NZ) s.z[lane] = z;
+            if (lane < NX) s.t2[lane] = pi;
+            if constexpr (NG > 0) {
+#pragma unroll
+                for (int t = 0; t < NCT; ++t) {
+                    const int c = slot(t);
+                    if (c >= NZ && c < NC) s.t1[c - NZ] = m[t] * (ll[t] - lu[t]);
+                }
+            }
+            wsync();
 
             // r_g = H z + g + F' pi_{n+1} - [0; pi_n] - C' lam
             double rg = 0.0;
             if (lane < NZ) {
                 const int j = lane;
-                double acc = d[Lo.D_g + j];
+                double acc = g;
 #pragma unroll
                 for (int k = 0; k < NZ; ++k) acc += s.M[j + k * LDZ] * s.z[k];
                 if (n < N) {
 #pragma unroll
                     for (int i = 0; i < NX; ++i) acc += s.F[i + j * LDX] * s.pin[nxt][i];
                 }
-                if (j >= NU) acc -= s.t0[j - NU];
-                acc -= d[Lo.D_bm + j] * (ir[Lo.I_ll + j] - ir[Lo.I_lu + j]);
+                if (j >= NU) acc -= s.t2[j - NU];
+                acc -= m[0] * (ll[0] - lu[0]);
                 if constexpr (NG > 0) {
 #pragma unroll
                     for (int r = 0; r < NG; ++r) acc -= s.G[r + j * LDG] * s.t1[r];
                 }
                 rg = acc;
-                w[Lo.W_rg + j] = rg;
                 mg = nmax(mg, fabs(rg));
             }
             // r_b = F z + b - x_{n+1}
             double rb = 0.0;
             if (n < N && lane < NX) {
-                const int i = lane;
-                double acc = d[Lo.D_b + i];
+                double acc = b;
 #pragma unroll
-                for (int k = 0; k < NZ; ++k) acc += s.F[i + k * LDX] * s.z[k];
-                acc -= s.xn[nxt][i];
-                rb = acc;
-                w[Lo.W_rb + i] = rb;
+                for (int k = 0; k < NZ; ++k) acc += s.F[lane + k * LDX] * s.z[k];
+                rb = acc - s.xn[nxt][lane];
                 mb = nmax(mb, fabs(rb));
             }
-            // r_d, complementarity, weights and reduced-gradient terms per slot
-            for (int c = lane; c < NC; c += WAVE) {
-                double m, lo, hi, gz;
-                if (c < NZ) {
-                    m = d[Lo.D_bm + c];
-                    lo = d[Lo.D_blo + c];
-                    hi = d[Lo.D_bhi + c];
-                    gz = s.z[c];
-                } else {
-                    const int r = c - NZ;
-                    m = d[Lo.D_gm + r];
-                    lo = d[Lo.D_glo + r];
-                    hi = d[Lo.D_ghi + r];
-                    gz = 0.0;
+            // r_d, complementarity, barrier weights, reduced-gradient terms
+            double e0 = 0.0, ws0 = 0.0;
 #pragma unroll
-                    for (int k = 0; k < NZ; ++k) gz += s.G[r + k * LDG] * s.z[k];
+            for (int t = 0; t < NCT; ++t) {
+                const int c = slot(t);
+                double e = 0.0, wsum = 0.0, rdl = 0.0, rdu = 0.0;
+                if (c < NC) {
+                    if (m[t] != 0.0) {
+                        double gz;
+                        if (c < NZ) {
+                            gz = z;
+                        } else {
+                            const int r = c - NZ;
+                            gz = 0.0;
+#pragma unroll
+                            for (int k = 0; k < NZ; ++k) gz += s.G[r + k * LDG] * s.z[k];
+                        }
+                        rdl = -gz + tl[t] + lo[t];
+                        rdu = gz + tu[t] - hi[t];
+                        md = nmax(md, nmax(fabs(rdl), fabs(rdu)));
+                        const double a1 = ll[t] * tl[t], a2 = lu[t] * tu[t];
+                        mm = nmax(mm, nmax(a1, a2));
+                        slt += a1 + a2;
+                        const double itl = rcp_nr(tl[t]), itu = rcp_nr(tu[t]);
+                        const double wl = ll[t] * itl, wu = lu[t] * itu;
+                        wsum = wl + wu;
+                        e = (wl * rdl - (ll[t] - shift * itl)) - (wu * rdu - (lu[t] - shift * itu));
+                    }
+                    s.e[c] = e;
+                    s.ws[c] = wsum;
                 }
-                double rdl = 0.0, rdu = 0.0, e = 0.0, wsum = 0.0;
-                if (m != 0.0) {
-                    const double ll = ir[Lo.I_ll + c], lu = ir[Lo.I_lu + c];
-                    const double tl = ir[Lo.I_tl + c], tu = ir[Lo.I_tu + c];
-                    rdl = -gz + tl + lo;
-                    rdu = gz + tu - hi;
-                    md = nmax(md, nmax(fabs(rdl), fabs(rdu)));
-                    const double a = ll * tl, b = lu * tu;
-                    mm = nmax(mm, nmax(a, b));
-                    slt += a + b;
-                    const double wl = ll / tl, wu = lu / tu;
-                    wsum = wl + wu;
-                    const double rml = a - shift, rmu = b - shift;
-                    e = (wl * rdl - rml / tl) - (wu * rdu - rmu / tu);
+                o.rdl[t] = rdl;
+                o.rdu[t] = rdu;
+                o.ll[t] = ll[t];
+                o.lu[t] = lu[t];
+                o.tl[t] = tl[t];
+                o.tu[t] = tu[t];
+                o.m[t] = m[t];
+                if (t == 0) {
+                    e0 = e;
+                    ws0 = wsum;
                 }
-                w[Lo.W_rdl + c] = rdl;
-                w[Lo.W_rdu + c] = rdu;
-                s.e[c] = e;
-                s.ws[c] = wsum;
             }
-            if (!factor) {
-                // residual-only pass: carry x_n and pi_n to stage n-1
-                __syncthreads();
-                if (lane >= NU && lane < NZ) s.xn[cur][lane - NU] = zj;
-                if (lane < NX) s.pin[cur][lane] = s.t0[lane];
-                __syncthreads();
-                continue;
-            }
-            if (lane < NX) s.t2[lane] = rb;
-            __syncthreads();
+            if (lane < NX) s.rb[lane] = rb;
+            o.z = z;
+            o.pi = pi;
+            o.rg = rg;
+            o.rb = rb;
 
-            // Phi = H + diag(box weights) + reg I ; V = [L_{n+1}' F ; sqrt(w_g) G]
-            if (lane < NZ) s.M[lane + lane * LDZ] += s.ws[lane] + P.reg_prim;
-            if constexpr (NG > 0) {
+            if (factor) {
+                // Phi = H + diag(box weights) + reg I ; V = [L_{n+1}' F ; sqrt(w_g) G]
+                if (lane < NZ) s.M[lane + lane * LDZ] += ws0 + P.reg_prim;
+                wsync();
+                if constexpr (NG > 0) {
 #pragma unroll
-                for (int e0 = 0; e0 < NG * NZ; e0 += WAVE) {
-                    int e = e0 + lane;
-                    if (e < NG * NZ) {
-                        int r = e % NG, k = e / NG;
-                        s.V[NX + r + k * LDV] = sqrt(s.ws[NZ + r]) * s.G[r + k * LDG];
-                    }
-                }
-            }
-            if (n < N) {
-                // trmm: V[i][k] = sum_l L[l][i] F[l][k]  (L lower, zero strict upper)
-                const double* Lx = s.Lx[nxt];
-#pragma unroll
-                for (int e0 = 0; e0 < NX * NZ; e0 += WAVE) {
-                    int e = e0 + lane;
-                    if (e < NX * NZ) {
-                        int i = e % NX, k = e / NX;
-                        double acc = 0.0;
-#pragma unroll
-                        for (int l = 0; l < NX; ++l) acc += Lx[l + i * LDX] * s.F[l + k * LDX];
-                        s.V[i + k * LDV] = acc;
-                    }
-                }
-            }
-            __syncthreads();
-            // syrk: M += V'V over the rows present at this stage
-            {
-                constexpr int R0 = 0;
-                const int r_begin = (n < N) ? R0 : NX;
-                if (r_begin < NV) {
-#pragma unroll
-                    for (int e0 = 0; e0 < NZ * NZ; e0 += WAVE) {
-                        int e = e0 + lane;
-                        if (e < NZ * NZ) {
-                            int i = e % NZ, k = e / NZ;
-                            double acc = 0.0;
-                            for (int r = r_begin; r < NV; ++r) acc += s.V[r + i * LDV] * s.V[r + k * LDV];
-                            s.M[i + k * LDZ] += acc;
+                    for (int t = 0; t < EG; ++t) {
+                        const int e = lane + WAVE * t;
+                        if (e < NG * NZ) {
+                            const int r = e % NG, k = e / NG;
+                            s.V[NX + r + k * LDV] = sqrt(s.ws[NZ + r]) * s.G[r + k * LDG];
                         }
                     }
                 }
-            }
-            __syncthreads();
+                if (n < N) trmm_LtF(s.Lx[nxt]);
+                wsync();
+                if (n < N || NG > 0) syrk_VtV(n < N ? 0 : NX);
+                wsync();
 
-            double rowL[NZ];
-            double dinv;
-            cholesky(rowL, dinv);
-            if (lane < NZ) {
-#pragma unroll
-                for (int k = 0; k < NZ; ++k) w[Lo.W_L + lane + k * NZ] = (k <= lane) ? rowL[k] : 0.0;
-                w[Lo.W_dinv + lane] = dinv;
-            }
-
-            // reduced gradient gt = r_g - C'(e)
-            double m = 0.0;
-            if (lane < NZ) {
-                double acc = rg - s.e[lane];
-                if constexpr (NG > 0) {
-#pragma unroll
-                    for (int r = 0; r < NG; ++r) acc -= s.G[r + lane * LDG] * s.e[NZ + r];
-                }
-                m = acc;
-            }
-            if (n < N) {
-                const double* Lx = s.Lx[nxt];
-                // t1 = L' rb
-                if (lane < NX) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int l = 0; l < NX; ++l) acc += Lx[l + lane * LDX] * s.t2[l];
-                    s.t1[lane] = acc;
-                }
-                __syncthreads();
-                // t0 = L t1 + p_{n+1}
-                if (lane < NX) {
-                    double acc = s.pn[nxt][lane];
-#pragma unroll
-                    for (int l = 0; l < NX; ++l) acc += Lx[lane + l * LDX] * s.t1[l];
-                    s.t2[lane] = acc;
-                }
-                __syncthreads();
+                double rowL[NZ];
+                double dinv;
+                cholesky(rowL, dinv);
                 if (lane < NZ) {
-                    double acc = 0.0;
 #pragma unroll
-                    for (int i = 0; i < NX; ++i) acc += s.F[i + lane * LDX] * s.t2[i];
-                    m += acc;
+                    for (int k = 0; k < NZ; ++k) s.Lst[lane + k * LDZ] = (k <= lane) ? rowL[k] : 0.0;
+                }
+                o.dinv = dinv;
+
+                // reduced gradient and cost-to-go terms, then forward substitution
+                double mv = 0.0;
+                if (lane < NZ) {
+                    double acc = rg - e0;
+                    if constexpr (NG > 0) {
+#pragma unroll
+                        for (int r = 0; r < NG; ++r) acc -= s.G[r + lane * LDG] * s.e[NZ + r];
+                    }
+                    mv = acc;
+                }
+                if (n < N) mv = add_cost_to_go(mv, s.Lx[nxt], s.pn[nxt]);
+                mv = fwd_subst_u<NZ>(mv, rowL, dinv);
+                o.mv = mv;
+                if (lane >= NU && lane < NZ) {
+                    const int i = lane - NU;
+                    s.pn[cur][i] = mv;
+#pragma unroll
+                    for (int k = 0; k < NX; ++k) s.Lx[cur][i + k * LDX] = (k <= i) ? rowL[NU + k] : 0.0;
                 }
             }
-            m = fwd_subst_u<NZ>(m, rowL, dinv);
-            if (lane < NU) w[Lo.W_yu + lane] = m;
-            if (lane >= NU && lane < NZ) {
-                w[Lo.W_pv + lane - NU] = m;
-                s.pn[cur][lane - NU] = m;
-                s.xn[cur][lane - NU] = zj;
-                const int i = lane - NU;
-#pragma unroll
-                for (int k = 0; k < NX; ++k) s.Lx[cur][i + k * LDX] = (k <= i) ? rowL[NU + k] : 0.0;
-            }
-            if (lane < NX) s.pin[cur][lane] = s.t0[lane];
-            __syncthreads();
+            if (lane >= NU && lane < NZ) s.xn[cur][lane - NU] = z;
+            if (lane < NX) s.pin[cur][lane] = pi;
+            wsync();
         }
-        n_g = wave_max(mg);
-        n_b = wave_max(mb);
-        n_d = wave_max(md);
-        n_m = wave_max(mm);
-        s_lt = wave_sum(slt);
+        flushA(0, upd, factor, o);
+        o_g = wave_max(mg);
+        o_b = wave_max(mb);
+        o_d = wave_max(md);
+        o_m = wave_max(mm);
+        o_lt = wave_sum(slt);
     }
 
-    // ------------------------------------------------------------------
-    // Backward right-hand-side sweep with stored factors.
-    // RHS: r_g / r_b / r_d from offsets og, ob, odl, odu; r_m per rmode.
-    // ------------------------------------------------------------------
-    __device__ __forceinline__ void backward_vec(int rmode, double shift, int og, int ob, int odl, int odu)
+    // slot values used by the right-hand-side sweeps
+    __device__ __forceinline__ void load_slots_rm(int rmode, const double* d, const double* ir, const double* w,
+                                                  int odl, int odu, double (&m)[NCT], double (&rdl)[NCT],
+                                                  double (&rdu)[NCT], double (&ll)[NCT], double (&lu)[NCT],
+                                                  double (&tl)[NCT], double (&tu)[NCT], double (&a1)[NCT],
+                                                  double (&a2)[NCT], double (&a3)[NCT], double (&a4)[NCT]) const
+    {
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+            const int c = slot(t);
+            double lo_, hi_;
+            slot_bounds(d, c, m[t], lo_, hi_);
+            rdl[t] = rdu[t] = ll[t] = lu[t] = tl[t] = tu[t] = 0.0;
+            a1[t] = a2[t] = a3[t] = a4[t] = 0.0;
+            if (c < NC) {
+                rdl[t] = w[odl + c];
+                rdu[t] = w[odu + c];
+                ll[t] = ir[Lo.I_ll + c];
+                lu[t] = ir[Lo.I_lu + c];
+                tl[t] = ir[Lo.I_tl + c];
+                tu[t] = ir[Lo.I_tu + c];
+                if (rmode == RM_CORRECTOR) {
+                    a1[t] = w[Lo.W_all + c];
+                    a2[t] = w[Lo.W_alu + c];
+                    a3[t] = w[Lo.W_atl + c];
+                    a4[t] = w[Lo.W_atu + c];
+                } else if (rmode == RM_IR) {
+                    a1[t] = w[Lo.W_irml + c];
+                    a2[t] = w[Lo.W_irmu + c];
+                }
+            }
+        }
+    }
+
+    // r_m (lower, upper) of a slot from the loaded values
+    __device__ __forceinline__ static void rm_value(int rmode, double shift, double ll, double lu, double tl,
+                                                    double tu, double a1, double a2, double a3, double a4,
+                                                    double& rml, double& rmu)
+    {
+        if (rmode == RM_IR) {
+            rml = a1;
+            rmu = a2;
+            return;
+        }
+        rml = ll * tl - shift;
+        rmu = lu * tu - shift;
+        if (rmode == RM_CORRECTOR) {
+            rml += a1 * a3;
+            rmu += a2 * a4;
+        }
+    }
+
+    // ==================================================================
+    // Pass C: backward right-hand-side sweep with the stored factors for
+    // the RHS (r_g, r_b, r_d) at offsets og, ob, odl, odu and r_m per rmode.
+    // ==================================================================
+    struct PreC {
+        double Lxx[EX], F[EF], G[EG];
+        double rowL[NU1];
+        double dinv, rg, rb;
+        double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
+        double a1[NCT], a2[NCT], a3[NCT], a4[NCT];
+    };
+
+    __device__ __forceinline__ void loadC(PreC& p, int n, int rmode, int og, int ob, int odl, int odu) const
+    {
+        const double* d = Dp(n);
+        const double* ir = Ip(n);
+        const double* w = Wp(n);
+#pragma unroll
+        for (int t = 0; t < EX; ++t) {
+            const int e = lane + WAVE * t;
+            p.Lxx[t] = (e < NX * NX) ? w[Lo.W_L + (NU + e % NX) + (NU + e / NX) * NZ] : 0.0;
+        }
+        if (n < N) fetch<NX, NZ, EF>(p.F, d + Lo.D_F);
+        if constexpr (NG > 0) fetch<NG, NZ, EG>(p.G, d + Lo.D_G);
+#pragma unroll
+        for (int k = 0; k < NU1; ++k) p.rowL[k] = (lane < NZ && k < NU) ? w[Lo.W_L + lane + k * NZ] : 0.0;
+        p.dinv = lane < NZ ? w[Lo.W_dinv + lane] : 0.0;
+        p.rg = lane < NZ ? w[og + lane] : 0.0;
+        p.rb = (n < N && lane < NX) ? w[ob + lane] : 0.0;
+        load_slots_rm(rmode, d, ir, w, odl, odu, p.m, p.rdl, p.rdu, p.ll, p.lu, p.tl, p.tu, p.a1, p.a2, p.a3, p.a4);
+    }
+
+    __device__ __forceinline__ void flushC(int n, double mv) const
+    {
+        double* w = Wp(n);
+        if (lane < NU) w[Lo.W_yu + lane] = mv;
+        else if (lane < NZ) w[Lo.W_pv + lane - NU] = mv;
+    }
+
+    __device__ __forceinline__ void passC(int rmode, double shift, int og, int ob, int odl, int odu) const
     {
         Smem& s = S();
-        (void)s;
+        PreC p;
+        double out_mv = 0.0;
+        loadC(p, N, rmode, og, ob, odl, odu);
         for (int n = N; n >= 0; --n) {
-            const int cur = n & 1, nxt = (n + 1) & 1;
-            const double* d = Dp(n);
-            double* ir = Ip(n);
-            double* w = Wp(n);
-            if (n < N) load_mat<NX, NZ, LDX>(s.F, d + Lo.D_F);
-            if constexpr (NG > 0) load_mat<NG, NZ, LDG>(s.G, d + Lo.D_G);
-            if (n == N && lane < NX) s.pn[nxt][lane] = 0.0;
-            // factor rows (first NU columns) in registers; (x, x) block to LDS
-            double rowL[NU > 0 ? NU : 1];
+            const int cur = n & 1, nxt = cur ^ 1;
+            // (x, x) block of this stage's factor becomes L_{n+1} of stage n-1
 #pragma unroll
-            for (int k = 0; k < (NU > 0 ? NU : 1); ++k) rowL[k] = 0.0;
-            double dinv = 0.0;
-            if (lane < NZ) {
-#pragma unroll
-                for (int k = 0; k < NU; ++k) rowL[k] = w[Lo.W_L + lane + k * NZ];
-                dinv = w[Lo.W_dinv + lane];
-            }
-            if (lane >= NU && lane < NZ) {
-                const int i = lane - NU;
-#pragma unroll
-                for (int k = 0; k < NX; ++k) s.Lx[cur][i + k * LDX] = w[Lo.W_L + lane + (NU + k) * NZ];
-            }
-            for (int c = lane; c < NC; c += WAVE) {
-                double e = 0.0;
-                if (slot_mask(d, c) != 0.0) {
-                    double rml, rmu;
-                    rm_of(rmode, shift, ir, w, c, rml, rmu);
-                    const double ll = ir[Lo.I_ll + c], lu = ir[Lo.I_lu + c];
-                    const double tl = ir[Lo.I_tl + c], tu = ir[Lo.I_tu + c];
-                    e = ((ll / tl) * w[odl + c] - rml / tl) - ((lu / tu) * w[odu + c] - rmu / tu);
+            for (int t = 0; t < EX; ++t) {
+                const int e = lane + WAVE * t;
+                if (e < NX * NX) {
+                    const int i = e % NX, k = e / NX;
+                    s.Lx[cur][i + k * LDX] = (k <= i) ? p.Lxx[t] : 0.0;
                 }
-                s.e[c] = e;
             }
-            if (n < N && lane < NX) s.t2[lane] = w[ob + lane];
-            __syncthreads();
-            double m = 0.0;
+            if (n < N) commit<NX, NZ, EF>(s.F, LDX, p.F);
+            if constexpr (NG > 0) commit<NG, NZ, EG>(s.G, LDG, p.G);
+            double rowL[NU1];
+#pragma unroll
+            for (int k = 0; k < NU1; ++k) rowL[k] = p.rowL[k];
+            const double dinv = p.dinv, rg = p.rg, rb = p.rb;
+            double e0 = 0.0;
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) {
+                const int c = slot(t);
+                double e = 0.0;
+                if (c < NC && p.m[t] != 0.0) {
+                    double rml, rmu;
+                    rm_value(rmode, shift, p.ll[t], p.lu[t], p.tl[t], p.tu[t], p.a1[t], p.a2[t], p.a3[t], p.a4[t],
+                             rml, rmu);
+                    const double itl = rcp_nr(p.tl[t]), itu = rcp_nr(p.tu[t]);
+                    e = (p.ll[t] * p.rdl[t] - rml) * itl - (p.lu[t] * p.rdu[t] - rmu) * itu;
+                }
+                if (c < NC) s.e[c] = e;
+                if (t == 0) e0 = e;
+            }
+            if (n == N && lane < NX) s.pn[nxt][lane] = 0.0;
+            if (lane < NX) s.rb[lane] = rb;
+            if (n < N) flushC(n + 1, out_mv);
+            if (n > 0) loadC(p, n - 1, rmode, og, ob, odl, odu);
+            wsync();
+            double mv = 0.0;
             if (lane < NZ) {
-                double acc = w[og + lane] - s.e[lane];
+                double acc = rg - e0;
                 if constexpr (NG > 0) {
 #pragma unroll
                     for (int r = 0; r < NG; ++r) acc -= s.G[r + lane * LDG] * s.e[NZ + r];
                 }
-                m = acc;
+                mv = acc;
             }
-            if (n < N) {
-                const double* Lx = s.Lx[nxt];
-                if (lane < NX) {
-                    double acc = 0.0;
+            if (n < N) mv = add_cost_to_go(mv, s.Lx[nxt], s.pn[nxt]);
+            mv = fwd_subst_u<NU1>(mv, rowL, dinv);
+            out_mv = mv;
+            if (lane >= NU && lane < NZ) s.pn[cur][lane - NU] = mv;
+            wsync();
+        }
+        flushC(0, out_mv);
+    }
+
+    // ==================================================================
+    // Pass B: forward substitution and recovery of dt, dlam for the RHS of
+    // pass A / C.  Writes dz, dpi to (oz, opi) and dlam, dt to (oll, olu,
+    // otl, otu).  Returns the largest alpha keeping lam, t >= 0 (uncapped;
+    // HUGE_VAL if unblocked) and the sums s1 = sum(lam dt + dlam t), s2 =
+    // sum(dlam dt), so that the duality measure after a step of length a is
+    // (lam't + a s1 + a^2 s2) / n_c.
+    // ==================================================================
+    struct PreB {
+        double L[EL], Lxx[EX], F[EF], G[EG];
+        double dinv, yu, rb, pn;
+        double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
+        double a1[NCT], a2[NCT], a3[NCT], a4[NCT];
+    };
+
+    __device__ __forceinline__ void loadB(PreB& p, int n, int rmode, int ob, int odl, int odu) const
+    {
+        const double* d = Dp(n);
+        const double* ir = Ip(n);
+        const double* w = Wp(n);
+        if constexpr (NU > 0) fetch<NZ, NU, EL>(p.L, w + Lo.W_L);
+        p.dinv = lane < NU ? w[Lo.W_dinv + lane] : 0.0;
+        p.yu = lane < NU ? w[Lo.W_yu + lane] : 0.0;
+        p.rb = p.pn = 0.0;
+        if (n < N) {
+            const double* w1 = Wp(n + 1);
 #pragma unroll
-                    for (int l = 0; l < NX; ++l) acc += Lx[l + lane * LDX] * s.t2[l];
-                    s.t1[lane] = acc;
-                }
-                __syncthreads();
-                if (lane < NX) {
-                    double acc = s.pn[nxt][lane];
-#pragma unroll
-                    for (int l = 0; l < NX; ++l) acc += Lx[lane + l * LDX] * s.t1[l];
-                    s.t2[lane] = acc;
-                }
-                __syncthreads();
-                if (lane < NZ) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int i = 0; i < NX; ++i) acc += s.F[i + lane * LDX] * s.t2[i];
-                    m += acc;
-                }
+            for (int t = 0; t < EX; ++t) {
+                const int e = lane + WAVE * t;
+                p.Lxx[t] = (e < NX * NX) ? w1[Lo.W_L + (NU + e % NX) + (NU + e / NX) * NZ] : 0.0;
             }
-            m = fwd_subst_u<NU>(m, rowL, dinv);
-            if (lane < NU) w[Lo.W_yu + lane] = m;
-            if (lane >= NU && lane < NZ) {
-                w[Lo.W_pv + lane - NU] = m;
-                s.pn[cur][lane - NU] = m;
+            fetch<NX, NZ, EF>(p.F, d + Lo.D_F);
+            if (lane < NX) {
+                p.rb = w[ob + lane];
+                p.pn = w1[Lo.W_pv + lane];
             }
-            __syncthreads();
+        }
+        if constexpr (NG > 0) fetch<NG, NZ, EG>(p.G, d + Lo.D_G);
+        load_slots_rm(rmode, d, ir, w, odl, odu, p.m, p.rdl, p.rdu, p.ll, p.lu, p.tl, p.tu, p.a1, p.a2, p.a3, p.a4);
+    }
+
+    struct OutB {
+        double dz, dpi;
+        double dll[NCT], dlu[NCT], dtl[NCT], dtu[NCT];
+    };
+
+    __device__ __forceinline__ void flushB(int n, const OutB& o, int oz, int opi, int oll, int olu, int otl,
+                                           int otu) const
+    {
+        double* w = Wp(n);
+        if (lane < NZ) w[oz + lane] = o.dz;
+        if (n < N && lane < NX) Wp(n + 1)[opi + lane] = o.dpi;
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+            const int c = slot(t);
+            if (c < NC) {
+                w[oll + c] = o.dll[t];
+                w[olu + c] = o.dlu[t];
+                w[otl + c] = o.dtl[t];
+                w[otu + c] = o.dtu[t];
+            }
         }
     }
 
-    // ------------------------------------------------------------------
-    // Forward substitution and recovery of dt, dlam.  Writes the step into
-    // the (oz, opi, oll, olu, otl, otu) workspace offsets and returns the
-    // largest alpha keeping lam, t >= 0 (uncapped; HUGE_VAL if unblocked).
-    // ------------------------------------------------------------------
-    __device__ __forceinline__ double forward(int rmode, double shift, int odl, int odu, int ob, int oz, int opi, int oll, int olu,
-                              int otl, int otu)
+    __device__ __forceinline__ double passB(int rmode, double shift, int ob, int odl, int odu, int oz, int opi,
+                                            int oll, int olu, int otl, int otu, double& o_s1, double& o_s2) const
     {
         Smem& s = S();
-        (void)s;
-        double amin = HUGE_VAL;
+        double amin = HUGE_VAL, s1 = 0.0, s2 = 0.0;
+        PreB p;
+        OutB o;
+        loadB(p, 0, rmode, ob, odl, odu);
         // dx_0 = -(L0 L0')^{-1} p_0 with L0 the (x, x) block of stage 0
         {
             double* w0 = Wp(0);
-            if (lane < NX) {
 #pragma unroll
-                for (int k = 0; k < NX; ++k) s.Lx[0][lane + k * LDX] = w0[Lo.W_L + (NU + lane) + (NU + k) * NZ];
+            for (int t = 0; t < EX; ++t) {
+                const int e = lane + WAVE * t;
+                if (e < NX * NX)
+                    s.Lx[0][(e % NX) + (e / NX) * LDX] = w0[Lo.W_L + (NU + e % NX) + (NU + e / NX) * NZ];
             }
             double v = (lane < NX) ? -w0[Lo.W_pv + lane] : 0.0;
-            double di = (lane < NX) ? w0[Lo.W_dinv + NU + lane] : 0.0;
-            __syncthreads();
+            const double di = (lane < NX) ? w0[Lo.W_dinv + NU + lane] : 0.0;
+            if (lane < NX) w0[opi + lane] = 0.0;
+            wsync();
 #pragma unroll
             for (int j = 0; j < NX; ++j) {
-                double y = bcast(v, j) * bcast(di, j);
+                const double y = bcast(v, j) * bcast(di, j);
                 if (lane == j) v = y;
                 else if (lane > j && lane < NX) v -= s.Lx[0][lane + j * LDX] * y;
             }
 #pragma unroll
             for (int j = NX - 1; j >= 0; --j) {
-                double x = bcast(v, j) * bcast(di, j);
+                const double x = bcast(v, j) * bcast(di, j);
                 if (lane == j) v = x;
                 else if (lane < j) v -= s.Lx[0][j + lane * LDX] * x;
             }
+            wsync();
             if (lane < NX) s.xn[0][lane] = v;
-            if (lane < NX) w0[opi + lane] = 0.0;
-            __syncthreads();
+            wsync();
         }
         for (int n = 0; n <= N; ++n) {
-            const int cur = n & 1, nxt = (n + 1) & 1;
-            const double* d = Dp(n);
-            double* ir = Ip(n);
-            double* w = Wp(n);
-            // factor columns 0..NU-1 of stage n into s.M (column-major)
-#pragma unroll
-            for (int e0 = 0; e0 < NZ * NU; e0 += WAVE) {
-                int e = e0 + lane;
-                if (e < NZ * NU) {
-                    int i = e % NZ, j = e / NZ;
-                    s.M[i + j * LDZ] = w[Lo.W_L + i + j * NZ];
-                }
-            }
-            if (lane < NU) s.t0[lane] = w[Lo.W_dinv + lane];
+            const int cur = n & 1, nxt = cur ^ 1;
+            if constexpr (NU > 0) commit<NZ, NU, EL>(s.M, LDZ, p.L);
             if (n < N) {
-                double* w1 = Wp(n + 1);
-                load_mat<NX, NZ, LDX>(s.F, d + Lo.D_F);
-                if (lane < NX) {
 #pragma unroll
-                    for (int k = 0; k < NX; ++k)
-                        s.Lx[nxt][lane + k * LDX] = w1[Lo.W_L + (NU + lane) + (NU + k) * NZ];
-                    s.pn[nxt][lane] = w1[Lo.W_pv + lane];
+                for (int t = 0; t < EX; ++t) {
+                    const int e = lane + WAVE * t;
+                    if (e < NX * NX) s.Lx[nxt][(e % NX) + (e / NX) * LDX] = p.Lxx[t];
                 }
+                commit<NX, NZ, EF>(s.F, LDX, p.F);
             }
-            if constexpr (NG > 0) load_mat<NG, NZ, LDG>(s.G, d + Lo.D_G);
-            __syncthreads();
+            if constexpr (NG > 0) commit<NG, NZ, EG>(s.G, LDG, p.G);
+            const double dv = p.dinv, yu = p.yu, rb = p.rb, pn = p.pn;
+            double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
+            double rml[NCT], rmu[NCT];
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) {
+                m[t] = p.m[t];
+                rdl[t] = p.rdl[t];
+                rdu[t] = p.rdu[t];
+                ll[t] = p.ll[t];
+                lu[t] = p.lu[t];
+                tl[t] = p.tl[t];
+                tu[t] = p.tu[t];
+                rm_value(rmode, shift, ll[t], lu[t], tl[t], tu[t], p.a1[t], p.a2[t], p.a3[t], p.a4[t], rml[t],
+                         rmu[t]);
+            }
+            if (n > 0) flushB(n - 1, o, oz, opi, oll, olu, otl, otu);
+            if (n < N) loadB(p, n + 1, rmode, ob, odl, odu);
+            wsync();
             // v = y_u + L_xu' dx ; back-substitution with L_uu'
             double v = 0.0;
             if (lane < NU) {
-                double acc = w[Lo.W_yu + lane];
+                double acc = yu;
 #pragma unroll
                 for (int i = 0; i < NX; ++i) acc += s.M[(NU + i) + lane * LDZ] * s.xn[cur][i];
                 v = acc;
             }
-            const double dv = (lane < NU) ? s.t0[lane] : 0.0;
 #pragma unroll
             for (int j = NU - 1; j >= 0; --j) {
-                double x = bcast(v, j) * bcast(dv, j);
+                const double x = bcast(v, j) * bcast(dv, j);
                 if (lane == j) v = x;
                 else if (lane < j) v -= s.M[j + lane * LDZ] * x;
             }
-            // dz = [-w; dx]
-            double dzj = 0.0;
-            if (lane < NU) dzj = -v;
-            else if (lane < NZ) dzj = s.xn[cur][lane - NU];
-            if (lane < NZ) {
-                s.z[lane] = dzj;
-                w[oz + lane] = dzj;
-            }
-            __syncthreads();
+            double dz = 0.0;
+            if (lane < NU) dz = -v;
+            else if (lane < NZ) dz = s.xn[cur][lane - NU];
+            if (lane < NZ) s.z[lane] = dz;
+            o.dz = dz;
+            wsync();
+            o.dpi = 0.0;
             if (n < N) {
-                // dx_{n+1} = F dz + rb
-                double* w1 = Wp(n + 1);
                 const double* Lx = s.Lx[nxt];
                 if (lane < NX) {
-                    double acc = w[ob + lane];
+                    double acc = rb;
 #pragma unroll
                     for (int k = 0; k < NZ; ++k) acc += s.F[lane + k * LDX] * s.z[k];
                     s.xn[nxt][lane] = acc;
                 }
-                __syncthreads();
+                wsync();
                 if (lane < NX) {
                     double acc = 0.0;
 #pragma unroll
                     for (int l = 0; l < NX; ++l) acc += Lx[l + lane * LDX] * s.xn[nxt][l];
                     s.t1[lane] = acc;
                 }
-                __syncthreads();
+                wsync();
                 if (lane < NX) {
-                    double acc = s.pn[nxt][lane];
+                    double acc = pn;
 #pragma unroll
                     for (int l = 0; l < NX; ++l) acc += Lx[lane + l * LDX] * s.t1[l];
-                    w1[opi + lane] = acc;
+                    o.dpi = acc;
                 }
             }
-            // constraint steps
-            for (int c = lane; c < NC; c += WAVE) {
+            // constraint steps, step length, duality-measure sums
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) {
+                const int c = slot(t);
                 double dll = 0.0, dlu = 0.0, dtl = 0.0, dtu = 0.0;
-                if (slot_mask(d, c) != 0.0) {
+                if (c < NC && m[t] != 0.0) {
                     double gdz;
                     if (c < NZ) {
-                        gdz = s.z[c];
+                        gdz = dz;
                     } else {
                         const int r = c - NZ;
                         gdz = 0.0;
 #pragma unroll
                         for (int k = 0; k < NZ; ++k) gdz += s.G[r + k * LDG] * s.z[k];
                     }
-                    double rml, rmu;
-                    rm_of(rmode, shift, ir, w, c, rml, rmu);
-                    const double ll = ir[Lo.I_ll + c], lu = ir[Lo.I_lu + c];
-                    const double tl = ir[Lo.I_tl + c], tu = ir[Lo.I_tu + c];
-                    dtl = gdz - w[odl + c];
-                    dtu = -gdz - w[odu + c];
-                    dll = -(rml + ll * dtl) / tl;
-                    dlu = -(rmu + lu * dtu) / tu;
-                    if (dll < 0.0) amin = fmin(amin, -ll / dll);
-                    if (dlu < 0.0) amin = fmin(amin, -lu / dlu);
-                    if (dtl < 0.0) amin = fmin(amin, -tl / dtl);
-                    if (dtu < 0.0) amin = fmin(amin, -tu / dtu);
+                    dtl = gdz - rdl[t];
+                    dtu = -gdz - rdu[t];
+                    dll = -(rml[t] + ll[t] * dtl) * rcp_nr(tl[t]);
+                    dlu = -(rmu[t] + lu[t] * dtu) * rcp_nr(tu[t]);
+                    // step to the boundary; approximate reciprocals suffice for a
+                    // length that is scaled by gamma < 1 afterwards
+                    if (dll < 0.0) amin = fmin(amin, -ll[t] * __builtin_amdgcn_rcp(dll));
+                    if (dlu < 0.0) amin = fmin(amin, -lu[t] * __builtin_amdgcn_rcp(dlu));
+                    if (dtl < 0.0) amin = fmin(amin, -tl[t] * __builtin_amdgcn_rcp(dtl));
+                    if (dtu < 0.0) amin = fmin(amin, -tu[t] * __builtin_amdgcn_rcp(dtu));
+                    s1 += ll[t] * dtl + dll * tl[t] + lu[t] * dtu + dlu * tu[t];
+                    s2 += dll * dtl + dlu * dtu;
                 }
-                w[oll + c] = dll;
-                w[olu + c] = dlu;
-                w[otl + c] = dtl;
-                w[otu + c] = dtu;
+                o.dll[t] = dll;
+                o.dlu[t] = dlu;
+                o.dtl[t] = dtl;
+                o.dtu[t] = dtu;
             }
-            __syncthreads();
+            wsync();
         }
+        flushB(N, o, oz, opi, oll, olu, otl, otu);
+        o_s1 = wave_sum(s1);
+        o_s2 = wave_sum(s2);
         return wave_min(amin);
     }
 
-    // mean complementarity after a step of length alpha along (oll, olu, otl, otu)
-    __device__ __forceinline__ double mu_after(double alpha, int oll, int olu, int otl, int otu) const
-    {
-        Smem& s = S();
-        (void)s;
-        double acc = 0.0;
-        for (int n = 0; n <= N; ++n) {
-            const double* d = Dp(n);
-            const double* ir = Ip(n);
-            const double* w = Wp(n);
-            for (int c = lane; c < NC; c += WAVE) {
-                if (slot_mask(d, c) != 0.0) {
-                    acc += (ir[Lo.I_ll + c] + alpha * w[oll + c]) * (ir[Lo.I_tl + c] + alpha * w[otl + c]);
-                    acc += (ir[Lo.I_lu + c] + alpha * w[olu + c]) * (ir[Lo.I_tu + c] + alpha * w[otu + c]);
-                }
-            }
-        }
-        return wave_sum(acc) / (2.0 * nc);
-    }
-
-    __device__ __forceinline__ void update(double alpha)
-    {
-        Smem& s = S();
-        (void)s;
-        for (int n = 0; n <= N; ++n) {
-            const double* d = Dp(n);
-            double* ir = Ip(n);
-            const double* w = Wp(n);
-            if (lane < NZ) ir[Lo.I_z + lane] += alpha * w[Lo.W_dz + lane];
-            if (n > 0 && lane < NX) ir[Lo.I_pi + lane] += alpha * w[Lo.W_dpi + lane];
-            for (int c = lane; c < NC; c += WAVE) {
-                if (slot_mask(d, c) != 0.0) {
-                    ir[Lo.I_ll + c] = fmax(ir[Lo.I_ll + c] + alpha * w[Lo.W_dll + c], P.lam_min);
-                    ir[Lo.I_lu + c] = fmax(ir[Lo.I_lu + c] + alpha * w[Lo.W_dlu + c], P.lam_min);
-                    ir[Lo.I_tl + c] = fmax(ir[Lo.I_tl + c] + alpha * w[Lo.W_dtl + c], P.t_min);
-                    ir[Lo.I_tu + c] = fmax(ir[Lo.I_tu + c] + alpha * w[Lo.W_dtu + c], P.t_min);
-                }
-            }
-        }
-        __syncthreads();
-    }
-
     // cold start: y = 0, pi = 0, t = max(C y - d, 1), lam = 1 (masked slots 0)
-    __device__ __forceinline__ void init()
+    __device__ __forceinline__ void init() const
     {
-        Smem& s = S();
-        (void)s;
         for (int n = 0; n <= N; ++n) {
             const double* d = Dp(n);
             double* ir = Ip(n);
             if (lane < NZ) ir[Lo.I_z + lane] = 0.0;
             if (lane < NX) ir[Lo.I_pi + lane] = 0.0;
-            for (int c = lane; c < NC; c += WAVE) {
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) {
+                const int c = slot(t);
+                if (c >= NC) continue;
                 double m, lo, hi;
-                if (c < NZ) {
-                    m = d[Lo.D_bm + c]; lo = d[Lo.D_blo + c]; hi = d[Lo.D_bhi + c];
-                } else {
-                    m = d[Lo.D_gm + c - NZ]; lo = d[Lo.D_glo + c - NZ]; hi = d[Lo.D_ghi + c - NZ];
-                }
+                slot_bounds(d, c, m, lo, hi);
                 const bool on = m != 0.0;
                 ir[Lo.I_ll + c] = on ? 1.0 : 0.0;
                 ir[Lo.I_lu + c] = on ? 1.0 : 0.0;
@@ -749,14 +1036,15 @@ struct Ipm {
 
     __device__ __forceinline__ void copy_step_out(double* out) const
     {
-        Smem& s = S();
-        (void)s;
         for (int n = 0; n <= N; ++n) {
             double* o = out + (size_t)n * Lo.IREC;
             const double* w = Wp(n);
             if (lane < NZ) o[Lo.I_z + lane] = w[Lo.W_dz + lane];
             if (lane < NX) o[Lo.I_pi + lane] = w[Lo.W_dpi + lane];
-            for (int c = lane; c < NC; c += WAVE) {
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) {
+                const int c = slot(t);
+                if (c >= NC) continue;
                 o[Lo.I_ll + c] = w[Lo.W_dll + c];
                 o[Lo.I_lu + c] = w[Lo.W_dlu + c];
                 o[Lo.I_tl + c] = w[Lo.W_dtl + c];
@@ -766,81 +1054,93 @@ struct Ipm {
     }
 
     // ------------------------------------------------------------------
-    __device__ __forceinline__ void solve(DevStat* st)
+    // Driver.  Solve mode: the IPM from a cold start.  Newton mode: one
+    // Newton step at the stored iterate with r_m = lam.*t - tau.  Every pass
+    // has a single call site so that its code is emitted once.
+    // ------------------------------------------------------------------
+    __device__ __forceinline__ void run(DevStat* st, double* step_out) const
     {
-        Smem& s = S();
-        (void)s;
-        init();
+        const bool newton_mode = P.mode == KMODE_NEWTON;
+        if (!newton_mode) init();
         int status = ST_MAX_ITER, k = 0;
-        double ng = 0, nb = 0, nd = 0, nm = 0, mu = 0.0;
+        double ng = 0, nb = 0, nd = 0, nm = 0, mu = 0.0, slt = 0.0;
         const double inv2nc = nc > 0 ? 1.0 / (2.0 * nc) : 0.0;
+        const double shift0 = newton_mode ? P.tau : 0.0;
+        bool upd = false, rejected = false;
+        double alpha = 0.0;
         for (k = 0;; ++k) {
-            double slt;
-            backward_factor(0.0, true, ng, nb, nd, nm, slt);
+            // residuals at the (updated) iterate; factorization unless the
+            // last step was rejected as too short
+            passA(upd, alpha, shift0, !rejected, ng, nb, nd, nm, slt);
+            __syncthreads();
             mu = slt * inv2nc;
-            if (ng != ng || nb != nb || nd != nd || nm != nm || mu != mu) { status = ST_NAN; break; }
-            if (ng <= P.tol_stat && nb <= P.tol_eq && nd <= P.tol_ineq && nm <= P.tol_comp) {
-                status = ST_SUCCESS;
-                break;
-            }
-            if (k >= P.iter_max) { status = ST_MAX_ITER; break; }
-            // predictor: dlam/dt into the affine slots, dz/dpi into the step slots
-            double amax = forward(RM_SHIFT, 0.0, Lo.W_rdl, Lo.W_rdu, Lo.W_rb, Lo.W_dz, Lo.W_dpi, Lo.W_all, Lo.W_alu,
-                                  Lo.W_atl, Lo.W_atu);
-            int oll = Lo.W_all, olu = Lo.W_alu, otl = Lo.W_atl, otu = Lo.W_atu;
-            if (nc > 0) {
-                const double a_aff = fmin(amax, 1.0);
-                const double mu_aff = mu_after(a_aff, Lo.W_all, Lo.W_alu, Lo.W_atl, Lo.W_atu);
-                const double ratio = mu > 0.0 ? mu_aff / mu : 0.0;
-                const double smu = ratio * ratio * ratio * mu;
-                backward_vec(RM_CORRECTOR, smu, Lo.W_rg, Lo.W_rb, Lo.W_rdl, Lo.W_rdu);
-                amax = forward(RM_CORRECTOR, smu, Lo.W_rdl, Lo.W_rdu, Lo.W_rb, Lo.W_dz, Lo.W_dpi, Lo.W_dll,
-                               Lo.W_dlu, Lo.W_dtl, Lo.W_dtu);
-                const double mu_c = mu_after(fmin(amax, 1.0), Lo.W_dll, Lo.W_dlu, Lo.W_dtl, Lo.W_dtu);
-                if (mu_c > P.corr_ratio * mu_aff) {
-                    backward_vec(RM_SHIFT, smu, Lo.W_rg, Lo.W_rb, Lo.W_rdl, Lo.W_rdu);
-                    amax = forward(RM_SHIFT, smu, Lo.W_rdl, Lo.W_rdu, Lo.W_rb, Lo.W_dz, Lo.W_dpi, Lo.W_dll, Lo.W_dlu,
-                                   Lo.W_dtl, Lo.W_dtu);
-                }
-                oll = Lo.W_dll; olu = Lo.W_dlu; otl = Lo.W_dtl; otu = Lo.W_dtu;
-            }
-            (void)oll; (void)olu; (void)otl; (void)otu;
-            const double alpha = fmin(1.0, P.gamma * amax);
-            update(alpha);
-            if (alpha < P.alpha_min) {
-                double slt2;
-                backward_factor(0.0, false, ng, nb, nd, nm, slt2);
-                mu = slt2 * inv2nc;
+            if (rejected) {
                 status = ST_MIN_STEP;
-                ++k;
                 break;
             }
+            if (!newton_mode) {
+                if (ng != ng || nb != nb || nd != nd || nm != nm || mu != mu) {
+                    status = ST_NAN;
+                    break;
+                }
+                if (ng <= P.tol_stat && nb <= P.tol_eq && nd <= P.tol_ineq && nm <= P.tol_comp) {
+                    status = ST_SUCCESS;
+                    break;
+                }
+                if (k >= P.iter_max) {
+                    status = ST_MAX_ITER;
+                    break;
+                }
+            }
+            // round 0: predictor (affine step; in Newton mode the step itself)
+            // round 1: Mehrotra corrector; round 2: predictor-centering step
+            // when the conditional corrector is rejected (Section 4.2)
+            double amax = HUGE_VAL, mu_aff = 0.0, smu = 0.0;
+            for (int round = 0; round < 3; ++round) {
+                const int rmode = round == 1 ? RM_CORRECTOR : RM_SHIFT;
+                const double shift = round == 0 ? shift0 : smu;
+                const bool aff = round == 0 && !newton_mode;
+                if (round > 0) {
+                    passC(rmode, shift, Lo.W_rg, Lo.W_rb, Lo.W_rdl, Lo.W_rdu);
+                    __syncthreads();
+                }
+                double s1, s2;
+                amax = passB(rmode, shift, Lo.W_rb, Lo.W_rdl, Lo.W_rdu, Lo.W_dz, Lo.W_dpi,
+                             aff ? Lo.W_all : Lo.W_dll, aff ? Lo.W_alu : Lo.W_dlu, aff ? Lo.W_atl : Lo.W_dtl,
+                             aff ? Lo.W_atu : Lo.W_dtu, s1, s2);
+                __syncthreads();
+                if (newton_mode || nc == 0) break;
+                const double a = fmin(amax, 1.0);
+                const double mu_a = (slt + a * s1 + a * a * s2) * inv2nc;
+                if (round == 0) {
+                    mu_aff = fmax(0.0, mu_a);
+                    const double ratio = mu > 0.0 ? mu_aff / mu : 0.0;
+                    smu = ratio * ratio * ratio * mu;
+                } else if (round == 1) {
+                    if (!(mu_a > P.corr_ratio * mu_aff)) break;
+                } else {
+                    break;
+                }
+            }
+            if (newton_mode) break;
+            alpha = fmin(1.0, P.gamma * amax);
+            upd = true;
+            rejected = alpha < P.alpha_min;
+        }
+        if (newton_mode) {
+            copy_step_out(step_out);
+            status = ST_SUCCESS;
+            k = 0;
         }
         if (lane == 0) {
             st->status = status;
             st->iters = k;
             st->ir_steps = 0;
             st->mu = mu;
-            st->res[0] = ng; st->res[1] = nb; st->res[2] = nd; st->res[3] = nm;
-        }
-    }
-
-    __device__ __forceinline__ void newton(DevStat* st, double* step_out)
-    {
-        Smem& s = S();
-        (void)s;
-        double ng, nb, nd, nm, slt;
-        backward_factor(P.tau, true, ng, nb, nd, nm, slt);
-        forward(RM_SHIFT, P.tau, Lo.W_rdl, Lo.W_rdu, Lo.W_rb, Lo.W_dz, Lo.W_dpi, Lo.W_dll, Lo.W_dlu, Lo.W_dtl,
-                Lo.W_dtu);
-        __syncthreads();
-        copy_step_out(step_out);
-        if (lane == 0) {
-            st->status = ST_SUCCESS;
-            st->iters = 0;
-            st->ir_steps = 0;
-            st->mu = nc > 0 ? slt / (2.0 * nc) : 0.0;
-            st->res[0] = ng; st->res[1] = nb; st->res[2] = nd; st->res[3] = nm;
+            st->res[0] = ng;
+            st->res[1] = nb;
+            st->res[2] = nd;
+            st->res[3] = nm;
         }
     }
 };
@@ -855,11 +1155,8 @@ __global__ __launch_bounds__(WAVE) void ipm_kernel(const InstDesc* __restrict__ 
     const int b = blockIdx.x;
     if (b >= count) return;
     const InstDesc ds = desc[b];
-    S ipm(data + ds.data, iter + ds.iter, work + ds.work, ds.N, ds.nc, P);
-    if (P.mode == KMODE_NEWTON)
-        ipm.newton(stat + ds.index, step_out + ds.iter);
-    else
-        ipm.solve(stat + ds.index);
+    const S ipm(data + ds.data, iter + ds.iter, work + ds.work, ds.N, ds.nc, P);
+    ipm.run(stat + ds.index, step_out + ds.iter);
 }
 
 // ---------------------------------------------------------------------------
@@ -889,17 +1186,15 @@ static const Variant kVariants[] = {
 };
 #undef OQP_VARIANT
 
-}  // namespace oqp
-
-// Host-side access to the variant table (used by the C-ABI implementation).
-namespace oqp {
 int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+
 void variant_dims(int v, int* nx, int* nu, int* ng)
 {
     *nx = kVariants[v].NX;
     *nu = kVariants[v].NU;
     *ng = kVariants[v].NG;
 }
+
 int variant_launch(int v, const InstDesc* desc, int count, const double* data, double* iter, double* work,
                    double* step, DevStat* stat, const KParams& P, void* stream)
 {
@@ -907,4 +1202,5 @@ int variant_launch(int v, const InstDesc* desc, int count, const double* data, d
     kVariants[v].fn(desc, count, data, iter, work, step, stat, P, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
+
 }  // namespace oqp
