@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--mode", choices=["f64"], default="f64")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.exit("bench.py: this build measures one GPU only (--gpus 1). Instances are independent; "
@@ -91,6 +93,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        torch.cuda.set_device(0)
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
+        return
 
     from paper_2003_02547_amd import binding as B
     from paper_2003_02547_amd import perfmodel, workloads as W
@@ -158,7 +171,8 @@ def main():
         "solves_ok": ok,
         "iters_p50": float(np.percentile(iters, 50)),
         "iters_p99": float(np.percentile(iters, 99)),
-        "max_kkt_res": float(np.max(kkt)),
+        "max_kkt_res": float(np.max(kkt[status == B.SUCCESS])) if ok else None,
+        "non_success": int(np.sum(status != B.SUCCESS)),
         "latency_ms_p50": round(float(np.percentile(kern_ms, 50)), 4),
         "latency_ms_p99": round(float(np.percentile(kern_ms, 99)), 4),
     }
