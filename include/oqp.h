@@ -88,7 +88,9 @@ typedef struct {
     int status;        /* OQP_SUCCESS / OQP_MAX_ITER / OQP_MIN_STEP / OQP_NAN */
     int iters;         /* IPM iterations taken */
     int ir_steps;      /* refinement steps taken in total */
-    int reserved;
+    int fell_back_f64; /* mixed path only: 1 if the FP32 factorization broke down (or the mixed
+                          IPM stopped on NaN / a too-short step) and the instance was re-solved
+                          from a cold start by the FP64 kernel */
     double mu;         /* duality measure lam't / n_c at the returned iterate */
     double res[4];     /* inf-norms of r_g, r_b, r_d and lam .* t (eq:alg:pdipm:delta) */
 } oqp_stat;

@@ -41,7 +41,7 @@ class Arg(ct.Structure):
 
 
 class Stat(ct.Structure):
-    _fields_ = [("status", ct.c_int), ("iters", ct.c_int), ("ir_steps", ct.c_int), ("reserved", ct.c_int),
+    _fields_ = [("status", ct.c_int), ("iters", ct.c_int), ("ir_steps", ct.c_int), ("fell_back_f64", ct.c_int),
                 ("mu", ct.c_double), ("res", ct.c_double * 4)]
 
 
@@ -181,6 +181,7 @@ class Result:
     mu: float
     res: np.ndarray
     sol: dict
+    fell_back_f64: int = 0
 
 
 def _sizes(qp):
@@ -254,7 +255,7 @@ class Batch:
 
     def result(self, i: int) -> Result:
         st = self.stat(i)
-        return Result(st.status, st.iters, st.ir_steps, st.mu, np.array(st.res[:]), self.solution(i))
+        return Result(st.status, st.iters, st.ir_steps, st.mu, np.array(st.res[:]), self.solution(i), st.fell_back_f64)
 
     def results(self) -> List[Result]:
         return [self.result(i) for i in range(len(self.qps))]

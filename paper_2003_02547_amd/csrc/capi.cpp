@@ -14,7 +14,7 @@
 namespace oqp {
 int variant_count();
 void variant_dims(int v, int* nx, int* nu, int* ng);
-int variant_launch(int v, const InstDesc* desc, int count, const double* data, double* iter, double* work,
+int variant_launch(int v, int mixed, const InstDesc* desc, int count, const double* data, double* iter, double* work,
                    double* step, DevStat* stat, const KParams& P, void* stream);
 }  // namespace oqp
 
@@ -320,8 +320,7 @@ static int check_arg(const oqp_arg* a)
 {
     if (!a) return fail(OQP_EINVAL, "NULL oqp_arg");
     if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED) return fail(OQP_EINVAL, "unknown mode %d", a->mode);
-    if (a->mode == OQP_MODE_MIXED) return fail(OQP_EINVAL, "OQP_MODE_MIXED is not available in this build");
-    if (a->iter_max < 0 || !(a->gamma > 0.0 && a->gamma <= 1.0) || a->warm_start != 0)
+    if (a->iter_max < 0 || !(a->gamma > 0.0 && a->gamma <= 1.0) || a->warm_start != 0 || a->ir_max < 0)
         return fail(OQP_EINVAL, "bad oqp_arg field (iter_max, gamma or warm_start)");
     return OQP_OK;
 }
@@ -714,11 +713,23 @@ static oqp::KParams make_params(const oqp_arg& a, int mode, double tau)
 
 static int launch_all(oqp_batch* b, const oqp::KParams& P)
 {
+    const int mixed = b->arg.mode == OQP_MODE_MIXED;
     for (int v = 0; v < b->nvar; ++v) {
         if (b->vcount[v] == 0) continue;
-        int rc = oqp::variant_launch(v, b->ddesc + b->vstart[v], b->vcount[v], b->ddata, b->diter, b->dwork,
+        int rc = oqp::variant_launch(v, mixed, b->ddesc + b->vstart[v], b->vcount[v], b->ddata, b->diter, b->dwork,
                                      b->dstep, b->dstat, P, b->stream);
         if (rc) return fail(OQP_EDEVICE, "kernel launch failed for variant %d", v);
+    }
+    if (mixed && P.mode == oqp::KMODE_SOLVE) {
+        // FP64 kernels pick up the instances the mixed kernels handed over
+        oqp::KParams Pf = P;
+        Pf.mode = oqp::KMODE_FALLBACK;
+        for (int v = 0; v < b->nvar; ++v) {
+            if (b->vcount[v] == 0) continue;
+            int rc = oqp::variant_launch(v, 0, b->ddesc + b->vstart[v], b->vcount[v], b->ddata, b->diter, b->dwork,
+                                         b->dstep, b->dstat, Pf, b->stream);
+            if (rc) return fail(OQP_EDEVICE, "fallback launch failed for variant %d", v);
+        }
     }
     return OQP_OK;
 }
@@ -771,7 +782,7 @@ extern "C" int oqp_batch_get_stat(const oqp_batch* b, int i, oqp_stat* st)
     st->status = d.status;
     st->iters = d.iters;
     st->ir_steps = d.ir_steps;
-    st->reserved = 0;
+    st->fell_back_f64 = d.fell_back;
     st->mu = d.mu;
     for (int k = 0; k < 4; ++k) st->res[k] = d.res[k];
     return OQP_OK;

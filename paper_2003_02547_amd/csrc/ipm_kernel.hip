@@ -35,6 +35,8 @@
 // only when the conditional corrector is rejected.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "layout.h"
 
 namespace oqp {
@@ -109,8 +111,11 @@ enum { RM_SHIFT = 0,      // r_m = lam.*t - shift
        RM_CORRECTOR = 1,  // r_m = lam.*t + dlam_aff.*dt_aff - shift
        RM_IR = 2 };       // r_m taken from the refinement residual arrays
 
-template <int NX, int NU, int NG>
+template <int NX, int NU, int NG, bool MIXED>
 struct Ipm {
+    // arithmetic type of the factorization and of the right-hand-side sweeps
+    // (FP32 in the mixed path; pivots, residuals and refinement stay FP64)
+    using TS = typename std::conditional<MIXED, float, double>::type;
     static constexpr Layout Lo = make_layout(NX, NU, NG);
     static constexpr int NZ = NX + NU;
     static constexpr int NC = NZ + NG;
@@ -219,18 +224,18 @@ struct Ipm {
     {
         Smem& s = S();
         const int a = lane & 7, b = lane >> 3;
-        double acc[TX][TZ];
+        TS acc[TX][TZ];
 #pragma unroll
         for (int p = 0; p < TX; ++p)
 #pragma unroll
-            for (int q = 0; q < TZ; ++q) acc[p][q] = 0.0;
+            for (int q = 0; q < TZ; ++q) acc[p][q] = 0;
 #pragma unroll 4
         for (int l = 0; l < NX; ++l) {
-            double lv[TX], fv[TZ];
+            TS lv[TX], fv[TZ];
 #pragma unroll
-            for (int p = 0; p < TX; ++p) lv[p] = Lx[l + (a + 8 * p) * LDX];
+            for (int p = 0; p < TX; ++p) lv[p] = (TS)Lx[l + (a + 8 * p) * LDX];
 #pragma unroll
-            for (int q = 0; q < TZ; ++q) fv[q] = s.F[l + (b + 8 * q) * LDX];
+            for (int q = 0; q < TZ; ++q) fv[q] = (TS)s.F[l + (b + 8 * q) * LDX];
 #pragma unroll
             for (int p = 0; p < TX; ++p)
 #pragma unroll
@@ -240,7 +245,7 @@ struct Ipm {
         for (int p = 0; p < TX; ++p)
 #pragma unroll
             for (int q = 0; q < TZ; ++q)
-                if (a + 8 * p < NX) s.V[(a + 8 * p) + (b + 8 * q) * LDV] = acc[p][q];
+                if (a + 8 * p < NX) s.V[(a + 8 * p) + (b + 8 * q) * LDV] = (double)acc[p][q];
     }
 
     // M[i][k] += sum_{r0 <= r < NV} V[r][i] V[r][k] for i, k < NZP
@@ -248,18 +253,18 @@ struct Ipm {
     {
         Smem& s = S();
         const int a = lane & 7, b = lane >> 3;
-        double acc[TZ][TZ];
+        TS acc[TZ][TZ];
 #pragma unroll
         for (int p = 0; p < TZ; ++p)
 #pragma unroll
-            for (int q = 0; q < TZ; ++q) acc[p][q] = 0.0;
+            for (int q = 0; q < TZ; ++q) acc[p][q] = 0;
 #pragma unroll 4
         for (int r = r0; r < NV; ++r) {
-            double vi[TZ], vk[TZ];
+            TS vi[TZ], vk[TZ];
 #pragma unroll
-            for (int p = 0; p < TZ; ++p) vi[p] = s.V[r + (a + 8 * p) * LDV];
+            for (int p = 0; p < TZ; ++p) vi[p] = (TS)s.V[r + (a + 8 * p) * LDV];
 #pragma unroll
-            for (int q = 0; q < TZ; ++q) vk[q] = s.V[r + (b + 8 * q) * LDV];
+            for (int q = 0; q < TZ; ++q) vk[q] = (TS)s.V[r + (b + 8 * q) * LDV];
 #pragma unroll
             for (int p = 0; p < TZ; ++p)
 #pragma unroll
@@ -268,56 +273,78 @@ struct Ipm {
 #pragma unroll
         for (int p = 0; p < TZ; ++p)
 #pragma unroll
-            for (int q = 0; q < TZ; ++q) s.M[(a + 8 * p) + (b + 8 * q) * LDZ] += acc[p][q];
+            for (int q = 0; q < TZ; ++q) s.M[(a + 8 * p) + (b + 8 * q) * LDZ] += (double)acc[p][q];
     }
 
     // ------------------------------------------------------------------
     // Right-looking Cholesky of s.M (NZ x NZ), one row per lane, rows held in
     // registers.  On return lane i < NZ holds row i of L in r[0..i] and 1/L_ii.
     // ------------------------------------------------------------------
-    __device__ __forceinline__ void cholesky(double (&r)[NZ], double& dinv) const
+    // rounding to the sweep type
+    __device__ __forceinline__ static double rnd(double x) { return (double)(TS)x; }
+
+    // Returns false when a pivot is not positive (or NaN).
+    __device__ __forceinline__ bool cholesky(double (&r)[NZ], double& dinv) const
     {
         Smem& s = S();
 #pragma unroll
         for (int k = 0; k < NZ; ++k) r[k] = lane < NZ ? s.M[lane + k * LDZ] : 0.0;
         dinv = 0.0;
+        // Mixed path: off-diagonal entries and their updates in FP32, the
+        // diagonal of every row accumulated in FP64 (FP64 pivots).
+        double dd = 0.0;
+        if constexpr (MIXED) {
+            dd = lane < NZ ? s.M[lane + lane * LDZ] : 1.0;
+#pragma unroll
+            for (int k = 0; k < NZ; ++k) r[k] = rnd(r[k]);
+        }
+        bool ok = true;
         // Updates are not masked: lane i only ever needs r[k] for k <= i, and
         // the entries above the diagonal absorb harmless garbage.
 #pragma unroll
         for (int j = 0; j < NZ; ++j) {
-            const double inv = rsqrt_nr(bcast(r[j], j));
-            const double lij = r[j] * inv;
-            if (lane == j) dinv = inv;
-            if (lane >= j) r[j] = lij;  // on lane j: pivot / sqrt(pivot) = sqrt(pivot)
+            const double piv = MIXED ? bcast(dd, j) : bcast(r[j], j);
+            ok = ok && (piv > 0.0);
+            const double inv = rsqrt_nr(piv);
+            const double lij = MIXED ? rnd(r[j] * inv) : r[j] * inv;
+            if (lane == j) {
+                dinv = inv;
+                r[j] = piv * inv;  // sqrt(pivot)
+            } else if (lane > j) {
+                r[j] = lij;
+                if constexpr (MIXED) dd -= lij * lij;
+            }
             if (j + 1 < NZ) {
                 s.col[lane] = lij;
                 // the entries needed by the next two columns go through the
                 // scalar unit (critical path), the rest through LDS
                 const double l1 = bcast(lij, j + 1);
-                r[j + 1] -= lij * l1;
+                r[j + 1] = (double)((TS)r[j + 1] - (TS)lij * (TS)l1);
                 if (j + 2 < NZ) {
                     const double l2 = bcast(lij, j + 2);
-                    r[j + 2] -= lij * l2;
+                    r[j + 2] = (double)((TS)r[j + 2] - (TS)lij * (TS)l2);
                 }
                 wsync();
 #pragma unroll
-                for (int k = j + 3; k < NZ; ++k) r[k] -= lij * s.col[k];
+                for (int k = j + 3; k < NZ; ++k) r[k] = (double)((TS)r[k] - (TS)lij * (TS)s.col[k]);
                 wsync();
             }
         }
+        return ok;
     }
 
     // Forward substitution with the (u, u) block, fused with the x rows:
     // lanes i < NU end with y = L_uu^{-1} m_u, lanes NU <= i < NZ with
-    // p = m_x - L_xu y.  rowL[j] = L[i][j] for j < NU; dinv is 1/L_ii.
+    // p = m_x - L_xu y.  rowL[j] = L[i][j] for j < NU; dinv is 1/L_ii (FP64).
     template <int CNT>
     __device__ __forceinline__ double fwd_subst_u(double m, const double (&rowL)[CNT], double dinv) const
     {
+        m = rnd(m);
 #pragma unroll
         for (int j = 0; j < NU; ++j) {
-            const double y = bcast(m, j) * bcast(dinv, j);
+            const double y = rnd(bcast(m, j) * bcast(dinv, j));
             if (lane == j) m = y;
-            else if (lane > j) m -= rowL[j] * y;
+            else if (lane > j) m = (double)((TS)m - (TS)rowL[j] * (TS)y);
         }
         return m;
     }
@@ -328,24 +355,24 @@ struct Ipm {
     {
         Smem& s = S();
         if (lane < NX) {
-            double acc = 0.0;
+            TS acc = 0;
 #pragma unroll
-            for (int l = 0; l < NX; ++l) acc += Lx[l + lane * LDX] * s.rb[l];
-            s.t1[lane] = acc;
+            for (int l = 0; l < NX; ++l) acc += (TS)Lx[l + lane * LDX] * (TS)s.rb[l];
+            s.t1[lane] = (double)acc;
         }
         wsync();
         if (lane < NX) {
-            double acc = pnext[lane];
+            TS acc = (TS)pnext[lane];
 #pragma unroll
-            for (int l = 0; l < NX; ++l) acc += Lx[lane + l * LDX] * s.t1[l];
-            s.t2[lane] = acc;
+            for (int l = 0; l < NX; ++l) acc += (TS)Lx[lane + l * LDX] * (TS)s.t1[l];
+            s.t2[lane] = (double)acc;
         }
         wsync();
         if (lane < NZ) {
-            double acc = 0.0;
+            TS acc = (TS)m;
 #pragma unroll
-            for (int i = 0; i < NX; ++i) acc += s.F[i + lane * LDX] * s.t2[i];
-            m += acc;
+            for (int i = 0; i < NX; ++i) acc += (TS)s.F[i + lane * LDX] * (TS)s.t2[i];
+            m = (double)acc;
         }
         return m;
     }
@@ -449,11 +476,12 @@ struct Ipm {
         }
     }
 
-    __device__ __forceinline__ void passA(bool upd, double alpha, double shift, bool factor, double& o_g,
+    __device__ __forceinline__ bool passA(bool upd, double alpha, double shift, bool factor, double& o_g,
                                           double& o_b, double& o_d, double& o_m, double& o_lt) const
     {
         Smem& s = S();
         double mg = 0.0, mb = 0.0, md = 0.0, mm = 0.0, slt = 0.0;
+        bool fact_ok = true;
         PreA p;
         OutA o;
         loadA(p, N, upd);
@@ -603,7 +631,7 @@ struct Ipm {
 
                 double rowL[NZ];
                 double dinv;
-                cholesky(rowL, dinv);
+                fact_ok = cholesky(rowL, dinv) && fact_ok;
                 if (lane < NZ) {
 #pragma unroll
                     for (int k = 0; k < NZ; ++k) s.Lst[lane + k * LDZ] = (k <= lane) ? rowL[k] : 0.0;
@@ -640,6 +668,7 @@ struct Ipm {
         o_d = wave_max(md);
         o_m = wave_max(mm);
         o_lt = wave_sum(slt);
+        return fact_ok;
     }
 
     // slot values used by the right-hand-side sweeps
@@ -879,17 +908,18 @@ struct Ipm {
             const double di = (lane < NX) ? w0[Lo.W_dinv + NU + lane] : 0.0;
             if (lane < NX) w0[opi + lane] = 0.0;
             wsync();
+            v = rnd(v);
 #pragma unroll
             for (int j = 0; j < NX; ++j) {
-                const double y = bcast(v, j) * bcast(di, j);
+                const double y = rnd(bcast(v, j) * bcast(di, j));
                 if (lane == j) v = y;
-                else if (lane > j && lane < NX) v -= s.Lx[0][lane + j * LDX] * y;
+                else if (lane > j && lane < NX) v = (double)((TS)v - (TS)s.Lx[0][lane + j * LDX] * (TS)y);
             }
 #pragma unroll
             for (int j = NX - 1; j >= 0; --j) {
-                const double x = bcast(v, j) * bcast(di, j);
+                const double x = rnd(bcast(v, j) * bcast(di, j));
                 if (lane == j) v = x;
-                else if (lane < j) v -= s.Lx[0][j + lane * LDX] * x;
+                else if (lane < j) v = (double)((TS)v - (TS)s.Lx[0][j + lane * LDX] * (TS)x);
             }
             wsync();
             if (lane < NX) s.xn[0][lane] = v;
@@ -928,16 +958,16 @@ struct Ipm {
             // v = y_u + L_xu' dx ; back-substitution with L_uu'
             double v = 0.0;
             if (lane < NU) {
-                double acc = yu;
+                TS acc = (TS)yu;
 #pragma unroll
-                for (int i = 0; i < NX; ++i) acc += s.M[(NU + i) + lane * LDZ] * s.xn[cur][i];
-                v = acc;
+                for (int i = 0; i < NX; ++i) acc += (TS)s.M[(NU + i) + lane * LDZ] * (TS)s.xn[cur][i];
+                v = (double)acc;
             }
 #pragma unroll
             for (int j = NU - 1; j >= 0; --j) {
-                const double x = bcast(v, j) * bcast(dv, j);
+                const double x = rnd(bcast(v, j) * bcast(dv, j));
                 if (lane == j) v = x;
-                else if (lane < j) v -= s.M[j + lane * LDZ] * x;
+                else if (lane < j) v = (double)((TS)v - (TS)s.M[j + lane * LDZ] * (TS)x);
             }
             double dz = 0.0;
             if (lane < NU) dz = -v;
@@ -949,24 +979,24 @@ struct Ipm {
             if (n < N) {
                 const double* Lx = s.Lx[nxt];
                 if (lane < NX) {
-                    double acc = rb;
+                    TS acc = (TS)rb;
 #pragma unroll
-                    for (int k = 0; k < NZ; ++k) acc += s.F[lane + k * LDX] * s.z[k];
-                    s.xn[nxt][lane] = acc;
+                    for (int k = 0; k < NZ; ++k) acc += (TS)s.F[lane + k * LDX] * (TS)s.z[k];
+                    s.xn[nxt][lane] = (double)acc;
                 }
                 wsync();
                 if (lane < NX) {
-                    double acc = 0.0;
+                    TS acc = 0;
 #pragma unroll
-                    for (int l = 0; l < NX; ++l) acc += Lx[l + lane * LDX] * s.xn[nxt][l];
-                    s.t1[lane] = acc;
+                    for (int l = 0; l < NX; ++l) acc += (TS)Lx[l + lane * LDX] * (TS)s.xn[nxt][l];
+                    s.t1[lane] = (double)acc;
                 }
                 wsync();
                 if (lane < NX) {
-                    double acc = pn;
+                    TS acc = (TS)pn;
 #pragma unroll
-                    for (int l = 0; l < NX; ++l) acc += Lx[lane + l * LDX] * s.t1[l];
-                    o.dpi = acc;
+                    for (int l = 0; l < NX; ++l) acc += (TS)Lx[lane + l * LDX] * (TS)s.t1[l];
+                    o.dpi = (double)acc;
                 }
             }
             // constraint steps, step length, duality-measure sums
@@ -1008,6 +1038,245 @@ struct Ipm {
         o_s1 = wave_sum(s1);
         o_s2 = wave_sum(s2);
         return wave_min(amin);
+    }
+
+    // ==================================================================
+    // Pass R (mixed path): residual of the Newton system for the step at
+    // offsets (oz, opi, oll, olu, otl, otu), in FP64 (Section 3.4):
+    //   r_ir = K step + r,  r = (r_g, r_b, r_d, r_m) with r_m per rmode.
+    // Writes r_ir to the refinement arrays and returns its inf-norm.
+    // ==================================================================
+    struct PreR {
+        double H[EH], F[EF], G[EG];
+        double dz, dpi, rg, rb;
+        double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
+        double a1[NCT], a2[NCT], a3[NCT], a4[NCT];
+        double sll[NCT], slu[NCT], stl[NCT], stu[NCT];
+    };
+
+    __device__ __forceinline__ void loadR(PreR& p, int n, int rmode, int oz, int opi, int oll, int olu, int otl,
+                                          int otu) const
+    {
+        const double* d = Dp(n);
+        const double* ir = Ip(n);
+        const double* w = Wp(n);
+        fetch<NZ, NZ, EH>(p.H, d + Lo.D_H);
+        if (n < N) fetch<NX, NZ, EF>(p.F, d + Lo.D_F);
+        if constexpr (NG > 0) fetch<NG, NZ, EG>(p.G, d + Lo.D_G);
+        p.dz = lane < NZ ? w[oz + lane] : 0.0;
+        p.rg = lane < NZ ? w[Lo.W_rg + lane] : 0.0;
+        p.dpi = (lane < NX && n > 0) ? w[opi + lane] : 0.0;
+        p.rb = (lane < NX && n < N) ? w[Lo.W_rb + lane] : 0.0;
+        load_slots_rm(rmode, d, ir, w, Lo.W_rdl, Lo.W_rdu, p.m, p.rdl, p.rdu, p.ll, p.lu, p.tl, p.tu, p.a1, p.a2,
+                      p.a3, p.a4);
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+            const int c = slot(t);
+            p.sll[t] = p.slu[t] = p.stl[t] = p.stu[t] = 0.0;
+            if (c < NC) {
+                p.sll[t] = w[oll + c];
+                p.slu[t] = w[olu + c];
+                p.stl[t] = w[otl + c];
+                p.stu[t] = w[otu + c];
+            }
+        }
+    }
+
+    struct OutR {
+        double rg, rb, rdl[NCT], rdu[NCT], rml[NCT], rmu[NCT];
+    };
+
+    __device__ __forceinline__ void flushR(int n, const OutR& o) const
+    {
+        double* w = Wp(n);
+        if (lane < NZ) w[Lo.W_irg + lane] = o.rg;
+        if (n < N && lane < NX) w[Lo.W_irb + lane] = o.rb;
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) {
+            const int c = slot(t);
+            if (c < NC) {
+                w[Lo.W_irdl + c] = o.rdl[t];
+                w[Lo.W_irdu + c] = o.rdu[t];
+                w[Lo.W_irml + c] = o.rml[t];
+                w[Lo.W_irmu + c] = o.rmu[t];
+            }
+        }
+    }
+
+    __device__ __forceinline__ double passR(int rmode, double shift, int oz, int opi, int oll, int olu, int otl,
+                                            int otu) const
+    {
+        Smem& s = S();
+        double nr = 0.0;
+        PreR p;
+        OutR o;
+        loadR(p, N, rmode, oz, opi, oll, olu, otl, otu);
+        for (int n = N; n >= 0; --n) {
+            const int cur = n & 1, nxt = cur ^ 1;
+            commit<NZ, NZ, EH>(s.M, LDZ, p.H);
+            if (n < N) commit<NX, NZ, EF>(s.F, LDX, p.F);
+            if constexpr (NG > 0) commit<NG, NZ, EG>(s.G, LDG, p.G);
+            const double dz = p.dz, dpi = p.dpi, rg = p.rg, rb = p.rb;
+            double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT], rml[NCT], rmu[NCT];
+            double sll[NCT], slu[NCT], stl[NCT], stu[NCT];
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) {
+                m[t] = p.m[t];
+                rdl[t] = p.rdl[t];
+                rdu[t] = p.rdu[t];
+                ll[t] = p.ll[t];
+                lu[t] = p.lu[t];
+                tl[t] = p.tl[t];
+                tu[t] = p.tu[t];
+                sll[t] = p.sll[t];
+                slu[t] = p.slu[t];
+                stl[t] = p.stl[t];
+                stu[t] = p.stu[t];
+                rm_value(rmode, shift, ll[t], lu[t], tl[t], tu[t], p.a1[t], p.a2[t], p.a3[t], p.a4[t], rml[t],
+                         rmu[t]);
+            }
+            if (n < N) flushR(n + 1, o);
+            if (n > 0) loadR(p, n - 1, rmode, oz, opi, oll, olu, otl, otu);
+            if (n == N && lane < NX) {
+                s.xn[nxt][lane] = 0.0;
+                s.pin[nxt][lane] = 0.0;
+            }
+            if (lane < NZ) s.z[lane] = dz;
+            if (lane < NX) s.t2[lane] = dpi;
+            if constexpr (NG > 0) {
+#pragma unroll
+                for (int t = 0; t < NCT; ++t) {
+                    const int c = slot(t);
+                    if (c >= NZ && c < NC) s.t1[c - NZ] = m[t] * (sll[t] - slu[t]);
+                }
+            }
+            wsync();
+            // g row: H dz + F' dpi_{n+1} - [0; dpi_n] - C' dlam + r_g
+            o.rg = 0.0;
+            if (lane < NZ) {
+                const int j = lane;
+                double acc = rg;
+#pragma unroll
+                for (int k = 0; k < NZ; ++k) acc += s.M[j + k * LDZ] * s.z[k];
+                if (n < N) {
+#pragma unroll
+                    for (int i = 0; i < NX; ++i) acc += s.F[i + j * LDX] * s.pin[nxt][i];
+                }
+                if (j >= NU) acc -= s.t2[j - NU];
+                acc -= m[0] * (sll[0] - slu[0]);
+                if constexpr (NG > 0) {
+#pragma unroll
+                    for (int r = 0; r < NG; ++r) acc -= s.G[r + j * LDG] * s.t1[r];
+                }
+                o.rg = acc;
+                nr = nmax(nr, fabs(acc));
+            }
+            // b row: F dz - dx_{n+1} + r_b
+            o.rb = 0.0;
+            if (n < N && lane < NX) {
+                double acc = rb;
+#pragma unroll
+                for (int k = 0; k < NZ; ++k) acc += s.F[lane + k * LDX] * s.z[k];
+                o.rb = acc - s.xn[nxt][lane];
+                nr = nmax(nr, fabs(o.rb));
+            }
+            // d rows: -C dz + dt + r_d ; m rows: T dlam + Lam dt + r_m
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) {
+                const int c = slot(t);
+                o.rdl[t] = o.rdu[t] = o.rml[t] = o.rmu[t] = 0.0;
+                if (c < NC && m[t] != 0.0) {
+                    double gz;
+                    if (c < NZ) {
+                        gz = dz;
+                    } else {
+                        const int r = c - NZ;
+                        gz = 0.0;
+#pragma unroll
+                        for (int k = 0; k < NZ; ++k) gz += s.G[r + k * LDG] * s.z[k];
+                    }
+                    o.rdl[t] = -gz + stl[t] + rdl[t];
+                    o.rdu[t] = gz + stu[t] + rdu[t];
+                    o.rml[t] = tl[t] * sll[t] + ll[t] * stl[t] + rml[t];
+                    o.rmu[t] = tu[t] * slu[t] + lu[t] * stu[t] + rmu[t];
+                    nr = nmax(nr, nmax(nmax(fabs(o.rdl[t]), fabs(o.rdu[t])), nmax(fabs(o.rml[t]), fabs(o.rmu[t]))));
+                }
+            }
+            if (lane >= NU && lane < NZ) s.xn[cur][lane - NU] = dz;
+            if (lane < NX) s.pin[cur][lane] = dpi;
+            wsync();
+        }
+        flushR(0, o);
+        return wave_max(nr);
+    }
+
+    // ==================================================================
+    // Pass X (mixed path): step += correction, then the step length and the
+    // duality-measure sums of pass B for the corrected step.
+    // ==================================================================
+    __device__ __forceinline__ double passX(int oz, int opi, int oll, int olu, int otl, int otu, double& o_s1,
+                                            double& o_s2) const
+    {
+        double amin = HUGE_VAL, s1 = 0.0, s2 = 0.0;
+        for (int n = 0; n <= N; ++n) {
+            const double* d = Dp(n);
+            const double* ir = Ip(n);
+            double* w = Wp(n);
+            if (lane < NZ) w[oz + lane] += w[Lo.W_edz + lane];
+            if (lane < NX && n > 0) w[opi + lane] += w[Lo.W_edpi + lane];
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) {
+                const int c = slot(t);
+                if (c >= NC) continue;
+                double m, lo_, hi_;
+                slot_bounds(d, c, m, lo_, hi_);
+                if (m == 0.0) continue;
+                const double dll = w[oll + c] + w[Lo.W_edll + c];
+                const double dlu = w[olu + c] + w[Lo.W_edlu + c];
+                const double dtl = w[otl + c] + w[Lo.W_edtl + c];
+                const double dtu = w[otu + c] + w[Lo.W_edtu + c];
+                w[oll + c] = dll;
+                w[olu + c] = dlu;
+                w[otl + c] = dtl;
+                w[otu + c] = dtu;
+                const double ll = ir[Lo.I_ll + c], lu = ir[Lo.I_lu + c], tl = ir[Lo.I_tl + c], tu = ir[Lo.I_tu + c];
+                if (dll < 0.0) amin = fmin(amin, -ll * __builtin_amdgcn_rcp(dll));
+                if (dlu < 0.0) amin = fmin(amin, -lu * __builtin_amdgcn_rcp(dlu));
+                if (dtl < 0.0) amin = fmin(amin, -tl * __builtin_amdgcn_rcp(dtl));
+                if (dtu < 0.0) amin = fmin(amin, -tu * __builtin_amdgcn_rcp(dtu));
+                s1 += ll * dtl + dll * tl + lu * dtu + dlu * tu;
+                s2 += dll * dtl + dlu * dtu;
+            }
+        }
+        o_s1 = wave_sum(s1);
+        o_s2 = wave_sum(s2);
+        return wave_min(amin);
+    }
+
+    // Iterative refinement of the step at the given offsets (mixed path).
+    // Stops when ||r_ir|| <= ir_tol * max(1, ||r||), when it stops
+    // decreasing, or after ir_max corrections.  Updates amax, s1, s2.
+    __device__ __forceinline__ int refine(int rmode, double shift, double rnorm, int oz, int opi, int oll, int olu,
+                                          int otl, int otu, double& amax, double& s1, double& s2) const
+    {
+        int steps = 0;
+        double prev = HUGE_VAL;
+        for (int it = 0; it <= P.ir_max; ++it) {
+            const double nir = passR(rmode, shift, oz, opi, oll, olu, otl, otu);
+            __syncthreads();
+            if (!(nir > P.ir_tol * rnorm) || !(nir < prev) || it == P.ir_max) break;
+            prev = nir;
+            passC(RM_IR, 0.0, Lo.W_irg, Lo.W_irb, Lo.W_irdl, Lo.W_irdu);
+            __syncthreads();
+            double t1, t2;
+            passB(RM_IR, 0.0, Lo.W_irb, Lo.W_irdl, Lo.W_irdu, Lo.W_edz, Lo.W_edpi, Lo.W_edll, Lo.W_edlu, Lo.W_edtl,
+                  Lo.W_edtu, t1, t2);
+            __syncthreads();
+            amax = passX(oz, opi, oll, olu, otl, otu, s1, s2);
+            __syncthreads();
+            ++steps;
+        }
+        return steps;
     }
 
     // cold start: y = 0, pi = 0, t = max(C y - d, 1), lam = 1 (masked slots 0)
@@ -1058,7 +1327,7 @@ struct Ipm {
     // Newton step at the stored iterate with r_m = lam.*t - tau.  Every pass
     // has a single call site so that its code is emitted once.
     // ------------------------------------------------------------------
-    __device__ __forceinline__ void run(DevStat* st, double* step_out) const
+    __device__ __forceinline__ void run(DevStat* st, double* step_out, int fell_back) const
     {
         const bool newton_mode = P.mode == KMODE_NEWTON;
         if (!newton_mode) init();
@@ -1068,14 +1337,19 @@ struct Ipm {
         const double shift0 = newton_mode ? P.tau : 0.0;
         bool upd = false, rejected = false;
         double alpha = 0.0;
+        int ir_steps = 0;
         for (k = 0;; ++k) {
             // residuals at the (updated) iterate; factorization unless the
             // last step was rejected as too short
-            passA(upd, alpha, shift0, !rejected, ng, nb, nd, nm, slt);
+            const bool fact_ok = passA(upd, alpha, shift0, !rejected, ng, nb, nd, nm, slt);
             __syncthreads();
             mu = slt * inv2nc;
             if (rejected) {
                 status = ST_MIN_STEP;
+                break;
+            }
+            if (MIXED && !newton_mode && !fact_ok) {
+                status = ST_FALLBACK;  // FP32 factorization broke down
                 break;
             }
             if (!newton_mode) {
@@ -1105,10 +1379,14 @@ struct Ipm {
                     __syncthreads();
                 }
                 double s1, s2;
-                amax = passB(rmode, shift, Lo.W_rb, Lo.W_rdl, Lo.W_rdu, Lo.W_dz, Lo.W_dpi,
-                             aff ? Lo.W_all : Lo.W_dll, aff ? Lo.W_alu : Lo.W_dlu, aff ? Lo.W_atl : Lo.W_dtl,
-                             aff ? Lo.W_atu : Lo.W_dtu, s1, s2);
+                const int oll = aff ? Lo.W_all : Lo.W_dll, olu = aff ? Lo.W_alu : Lo.W_dlu;
+                const int otl = aff ? Lo.W_atl : Lo.W_dtl, otu = aff ? Lo.W_atu : Lo.W_dtu;
+                amax = passB(rmode, shift, Lo.W_rb, Lo.W_rdl, Lo.W_rdu, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, s1, s2);
                 __syncthreads();
+                if constexpr (MIXED) {
+                    const double rnorm = fmax(1.0, fmax(fmax(ng, nb), fmax(nd, nm)));
+                    ir_steps += refine(rmode, shift, rnorm, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, amax, s1, s2);
+                }
                 if (newton_mode || nc == 0) break;
                 const double a = fmin(amax, 1.0);
                 const double mu_a = (slt + a * s1 + a * a * s2) * inv2nc;
@@ -1132,10 +1410,13 @@ struct Ipm {
             status = ST_SUCCESS;
             k = 0;
         }
+        // the mixed path hands instances it could not finish to the FP64 kernel
+        if (MIXED && !newton_mode && (status == ST_NAN || status == ST_MIN_STEP)) status = ST_FALLBACK;
         if (lane == 0) {
             st->status = status;
             st->iters = k;
-            st->ir_steps = 0;
+            st->ir_steps = ir_steps;
+            st->fell_back = fell_back;
             st->mu = mu;
             st->res[0] = ng;
             st->res[1] = nb;
@@ -1145,18 +1426,24 @@ struct Ipm {
     }
 };
 
-template <int NX, int NU, int NG>
+template <int NX, int NU, int NG, bool MIXED>
 __global__ __launch_bounds__(WAVE) void ipm_kernel(const InstDesc* __restrict__ desc, int count,
                                                     const double* __restrict__ data, double* __restrict__ iter,
                                                     double* __restrict__ work, double* __restrict__ step_out,
                                                     DevStat* __restrict__ stat, KParams P)
 {
-    using S = Ipm<NX, NU, NG>;
+    using S = Ipm<NX, NU, NG, MIXED>;
     const int b = blockIdx.x;
     if (b >= count) return;
     const InstDesc ds = desc[b];
+    int fell_back = 0;
+    if (P.mode == KMODE_FALLBACK) {
+        // second launch after the mixed kernel: only instances it handed over
+        if (stat[ds.index].status != ST_FALLBACK) return;
+        fell_back = 1;
+    }
     const S ipm(data + ds.data, iter + ds.iter, work + ds.work, ds.N, ds.nc, P);
-    ipm.run(stat + ds.index, step_out + ds.iter);
+    ipm.run(stat + ds.index, step_out + ds.iter, fell_back);
 }
 
 // ---------------------------------------------------------------------------
@@ -1166,20 +1453,20 @@ __global__ __launch_bounds__(WAVE) void ipm_kernel(const InstDesc* __restrict__ 
 typedef void (*launch_fn)(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams,
                           hipStream_t);
 
-template <int NX, int NU, int NG>
+template <int NX, int NU, int NG, bool MIXED>
 static void launch(const InstDesc* desc, int count, const double* data, double* iter, double* work, double* step,
                    DevStat* stat, KParams P, hipStream_t stream)
 {
-    hipLaunchKernelGGL((ipm_kernel<NX, NU, NG>), dim3(count), dim3(WAVE), 0, stream, desc, count, data, iter, work,
-                       step, stat, P);
+    hipLaunchKernelGGL((ipm_kernel<NX, NU, NG, MIXED>), dim3(count), dim3(WAVE), 0, stream, desc, count, data, iter,
+                       work, step, stat, P);
 }
 
 struct Variant {
     int NX, NU, NG;
-    launch_fn fn;
+    launch_fn fn[2];  // FP64 path, mixed path
 };
 
-#define OQP_VARIANT(x, u, g) {x, u, g, &launch<x, u, g>}
+#define OQP_VARIANT(x, u, g) {x, u, g, {&launch<x, u, g, false>, &launch<x, u, g, true>}}
 static const Variant kVariants[] = {
     OQP_VARIANT(4, 4, 0),  OQP_VARIANT(4, 4, 4),  OQP_VARIANT(8, 4, 0),  OQP_VARIANT(8, 8, 0),
     OQP_VARIANT(16, 8, 0), OQP_VARIANT(16, 16, 0), OQP_VARIANT(24, 8, 0), OQP_VARIANT(32, 16, 0),
@@ -1195,11 +1482,11 @@ void variant_dims(int v, int* nx, int* nu, int* ng)
     *ng = kVariants[v].NG;
 }
 
-int variant_launch(int v, const InstDesc* desc, int count, const double* data, double* iter, double* work,
+int variant_launch(int v, int mixed, const InstDesc* desc, int count, const double* data, double* iter, double* work,
                    double* step, DevStat* stat, const KParams& P, void* stream)
 {
     if (count <= 0) return 0;
-    kVariants[v].fn(desc, count, data, iter, work, step, stat, P, (hipStream_t)stream);
+    kVariants[v].fn[mixed ? 1 : 0](desc, count, data, iter, work, step, stat, P, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -30,7 +30,8 @@ struct Layout {
     int I_z, I_pi, I_ll, I_lu, I_tl, I_tu, IREC;
     // workspace record (doubles), one per stage
     int W_rg, W_rb, W_rdl, W_rdu, W_yu, W_pv, W_dz, W_dpi, W_dll, W_dlu, W_dtl, W_dtu;
-    int W_all, W_alu, W_atl, W_atu, W_irg, W_irb, W_irdl, W_irdu, W_irml, W_irmu, W_L, W_dinv, WREC;
+    int W_all, W_alu, W_atl, W_atu, W_irg, W_irb, W_irdl, W_irdu, W_irml, W_irmu;
+    int W_edz, W_edpi, W_edll, W_edlu, W_edtl, W_edtu, W_L, W_dinv, WREC;
 };
 
 // F = [B A] is NX x NZ column-major, H is NZ x NZ column-major (full
@@ -86,6 +87,12 @@ OQP_HD constexpr Layout make_layout(int NX, int NU, int NG)
     L.W_irdu = o; o += NC;
     L.W_irml = o; o += NC;
     L.W_irmu = o; o += NC;
+    L.W_edz = o; o += NZ;
+    L.W_edpi = o; o += NX;
+    L.W_edll = o; o += NC;
+    L.W_edlu = o; o += NC;
+    L.W_edtl = o; o += NC;
+    L.W_edtu = o; o += NC;
     o = round_up(o, 8);
     L.W_L = o; o += NZ * NZ;
     L.W_dinv = o; o += NZ;
@@ -110,7 +117,7 @@ struct DevStat {
     int32_t status;
     int32_t iters;
     int32_t ir_steps;
-    int32_t pad;
+    int32_t fell_back;  // the mixed path handed the instance to the FP64 kernel
     double mu;
     double res[4];  // inf-norms of r_g, r_b, r_d, lam.*t at the returned iterate
 };
@@ -126,7 +133,7 @@ struct KParams {
     int32_t pad;
 };
 
-enum { KMODE_SOLVE = 0, KMODE_NEWTON = 1 };
-enum { ST_SUCCESS = 0, ST_MAX_ITER = 1, ST_MIN_STEP = 2, ST_NAN = 3 };
+enum { KMODE_SOLVE = 0, KMODE_NEWTON = 1, KMODE_FALLBACK = 2 };
+enum { ST_SUCCESS = 0, ST_MAX_ITER = 1, ST_MIN_STEP = 2, ST_NAN = 3, ST_FALLBACK = 4 };
 
 }  // namespace oqp
