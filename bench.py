@@ -111,51 +111,60 @@ def main():
     torch.cuda.set_device(0)
     log(f"bench: generating {args.instances} mass-spring QPs (nx=16, nu=7, N=30)")
     qps = [W.mass_spring_chain8(i) for i in range(args.instances)]
-    arg = B.default_arg(B.MODE_F64)
-    batch = B.Batch(qps, arg)
-    batch.load().sync()
-    variant = batch.variant(0)[1]
-    log(f"bench: variant {variant}, device bytes {batch.dev_bytes / 2**20:.1f} MiB; warmup {args.warmup}")
-    stream = batch.stream
-    for _ in range(args.warmup):
-        batch.solve()
-    torch.cuda.synchronize()
-    log(f"bench: timing {args.steps} steps")
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s, e in ev:
-        s.record(stream)
-        batch.solve()
-        e.record(stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern_ms = np.array([s.elapsed_time(e) for s, e in ev])
-    batch.fetch().sync()
-    res = batch.results()
-    status = np.array([r.status for r in res])
-    kkt = np.array([float(np.max(r.res)) for r in res])
-    iters = np.array([r.iters for r in res])
-    ok = int(np.sum((status == B.SUCCESS) & (kkt <= KKT_OK)))
-    wall = t1 - t0
-    ms_per_step = 1e3 * wall / args.steps
-    value = ok * args.steps / wall
-
     dbytes = np.array([perfmodel.data_bytes(q) for q in qps], dtype=np.float64)
-    alg_bytes = float(np.sum(dbytes * (iters + 1)))           # one data read per residual evaluation
-    alg_flops = float(sum(perfmodel.flops_per_iter(q) * it for q, it in zip(qps, iters)))
-    kern_s = float(np.mean(kern_ms)) * 1e-3
-    achieved = alg_bytes / kern_s / 1e9
-    vkey = "ipm_kernel<%d,%d,%d>" % variant
+    fpi = np.array([perfmodel.flops_per_iter(q) for q in qps], dtype=np.float64)
+
+    def time_path(mode, steps, warmup):
+        arg = B.default_arg(mode)
+        batch = B.Batch(qps, arg)
+        batch.load().sync()
+        variant = batch.variant(0)[1]
+        stream = batch.stream
+        for _ in range(warmup):
+            batch.solve()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s_, e_ in ev:
+            s_.record(stream)
+            batch.solve()
+            e_.record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kern_ms = np.array([s_.elapsed_time(e_) for s_, e_ in ev])
+        batch.fetch().sync()
+        res = batch.results()
+        status = np.array([r.status for r in res])
+        kkt = np.array([float(np.max(r.res)) for r in res])
+        iters = np.array([r.iters for r in res])
+        irs = np.array([r.ir_steps for r in res])
+        fb = np.array([r.fell_back_f64 for r in res])
+        ok = int(np.sum((status == B.SUCCESS) & (kkt <= KKT_OK)))
+        wall = t1 - t0
+        kern_s = float(np.mean(kern_ms)) * 1e-3
+        nres = iters + 1 + irs  # residual evaluations: one per iteration, the final check, one per refinement
+        alg_bytes = float(np.sum(dbytes * nres))
+        return dict(variant=variant, ok=ok, wall=wall, steps=steps, kern_ms=kern_ms, kern_s=kern_s,
+                    status=status, kkt=kkt, iters=iters, irs=irs, fb=fb,
+                    achieved=alg_bytes / kern_s / 1e9, flops=float(np.sum(fpi * iters)) / kern_s / 1e12,
+                    value=ok * steps / wall, del_batch=batch)
+
+    log(f"bench: FP64 path, warmup {args.warmup}, {args.steps} steps")
+    f = time_path(B.MODE_F64, args.steps, args.warmup)
+    log(f"bench: mixed path, warmup {args.warmup}, {args.steps} steps")
+    m = time_path(B.MODE_MIXED, args.steps, args.warmup)
+    vkey = "ipm_kernel<%d,%d,%d>" % f["variant"]
     traffic = traffic_from_profile(vkey, 1)
+    okmask = f["status"] == B.SUCCESS
     line = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": round(f["value"], 1),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(1e3 * f["wall"] / args.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -163,18 +172,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": "mass_spring_8masses_x1024", "instances": args.instances, "nx": 16, "nu": 7,
                    "N": 30, "path": "f64", "kernel": vkey},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic},
-        "kernel_ms": round(float(np.mean(kern_ms)), 4),
-        "fp64_tflops": round(alg_flops / kern_s / 1e12, 4),
-        "solves_ok": ok,
-        "iters_p50": float(np.percentile(iters, 50)),
-        "iters_p99": float(np.percentile(iters, 99)),
-        "max_kkt_res": float(np.max(kkt[status == B.SUCCESS])) if ok else None,
-        "non_success": int(np.sum(status != B.SUCCESS)),
-        "latency_ms_p50": round(float(np.percentile(kern_ms, 50)), 4),
-        "latency_ms_p99": round(float(np.percentile(kern_ms, 99)), 4),
+        "roofline": {"bound": "hbm", "achieved": round(f["achieved"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(f["achieved"] / HBM_PEAK_GBS, 5), "traffic": traffic},
+        "kernel_ms": round(float(np.mean(f["kern_ms"])), 4),
+        "fp64_tflops": round(f["flops"], 4),
+        "solves_ok": f["ok"],
+        "non_success": int(np.sum(~okmask)),
+        "iters_p50": float(np.percentile(f["iters"], 50)),
+        "iters_p99": float(np.percentile(f["iters"], 99)),
+        "max_kkt_res": float(np.max(f["kkt"][okmask])) if okmask.any() else None,
+        "latency_ms_p50": round(float(np.percentile(f["kern_ms"], 50)), 4),
+        "latency_ms_p99": round(float(np.percentile(f["kern_ms"], 99)), 4),
+        "mixed": {"value": round(m["value"], 1), "unit": "solves/s", "dtype": "f32 factor+sweeps, f64 pivots/residuals/refinement",
+                  "ms_per_step": round(1e3 * m["wall"] / args.steps, 4), "solves_ok": m["ok"],
+                  "iters_p50": float(np.percentile(m["iters"], 50)),
+                  "ir_steps_mean": round(float(np.mean(m["irs"])), 2),
+                  "fell_back_f64": int(np.sum(m["fb"])),
+                  "max_kkt_res": float(np.max(m["kkt"][m["status"] == B.SUCCESS])),
+                  "vs_f64": round(m["value"] / f["value"], 3)},
     }
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")

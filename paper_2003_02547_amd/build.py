@@ -1,33 +1,56 @@
-"""Build the HIP library liboqp.so (gfx950) in-tree."""
+"""Build the HIP library liboqp.so (gfx950) in-tree.
+
+Kernel variants are instantiated in several translation units that are
+compiled in parallel, then linked with the C-ABI implementation.
+"""
 from __future__ import annotations
 
+import concurrent.futures as cf
+import glob
 import os
 import subprocess
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liboqp.so")
-SOURCES = [os.path.join(CSRC, "ipm_kernel.hip"), os.path.join(CSRC, "capi.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into liboqp.so (always recompiles)."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *SOURCES]
-    res = subprocess.run(cmd, capture_output=True, text=True)
+def sources():
+    units = sorted(glob.glob(os.path.join(CSRC, "ipm_v*.hip")))
+    return units + [os.path.join(CSRC, "ipm_registry.hip"), os.path.join(CSRC, "capi.cpp")]
+
+
+def _compile(src, obj):
+    res = subprocess.run([HIPCC, *FLAGS, "-c", "-o", obj, src], capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    if verbose:
-        print(res.stderr)
-    os.replace(tmp, LIB)
+        raise RuntimeError(f"hipcc failed on {os.path.basename(src)}:\n" + res.stdout + res.stderr)
+    return obj
+
+
+def build(verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile every HIP source and link liboqp.so (always recompiles)."""
+    jobs = jobs or max(1, min(16, os.cpu_count() or 1))
+    with tempfile.TemporaryDirectory(prefix="oqp_build_") as tmp:
+        srcs = sources()
+        objs = [os.path.join(tmp, os.path.basename(s) + ".o") for s in srcs]
+        with cf.ThreadPoolExecutor(jobs) as ex:
+            list(ex.map(_compile, srcs, objs))
+        out = LIB + ".tmp"
+        res = subprocess.run([HIPCC, *FLAGS, "-shared", "-o", out, *objs], capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("link failed:\n" + res.stdout + res.stderr)
+        if verbose:
+            print(res.stderr)
+        os.replace(out, LIB)
     return LIB
 
 

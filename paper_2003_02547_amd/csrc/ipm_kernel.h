@@ -33,10 +33,13 @@
 // predictor step, step length, affine duality measure), C (backward:
 // corrector right-hand side), B again (corrector step); C and B once more
 // only when the conditional corrector is rejected.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
 
+#include "ipm_launch.h"
 #include "layout.h"
 
 namespace oqp {
@@ -134,6 +137,10 @@ struct Ipm {
     static constexpr int EL = NU > 0 ? cdiv(NZ * NU, WAVE) : 1;  // factor u-columns per lane
     static constexpr int EX = cdiv(NX * NX, WAVE);               // factor (x, x) block per lane
     static constexpr int NU1 = NU > 0 ? NU : 1;
+    // Stage matrices go through registers (prefetched one stage ahead) only
+    // for small stage blocks; larger ones are loaded into LDS at stage start.
+    static constexpr bool PM = NZ <= 32;
+    static constexpr int EHr = PM ? EH : 1, EFr = PM ? EF : 1, EGr = PM ? EG : 1, EXr = PM ? EX : 1;
     static constexpr int TZ = NZP / 8;                           // register tile extents
     static constexpr int TX = NXP / 8;
     static_assert(NZ <= WAVE && NG <= WAVE, "stage block must fit one wave");
@@ -177,9 +184,37 @@ struct Ipm {
 
     __device__ __forceinline__ int slot(int t) const { return lane + WAVE * t; }
 
-    // per-lane loads of an R x C column-major block (element e = lane + 64 t)
+    // per-lane loads of an R x C column-major block (element e = lane + 64 t);
+    // with PM off only the source is remembered and commit reads it directly
     template <int R, int C, int E>
-    __device__ __forceinline__ void fetch(double (&r)[E], const double* __restrict__ src) const
+    __device__ __forceinline__ void fetch(double (&r)[E], const double* __restrict__ src, const double*& keep) const
+    {
+        keep = src;
+        if constexpr (PM) {
+#pragma unroll
+            for (int t = 0; t < E; ++t) {
+                const int e = lane + WAVE * t;
+                r[t] = (e < R * C) ? src[e] : 0.0;
+            }
+        }
+    }
+    template <int R, int C, int E>
+    __device__ __forceinline__ void commit(double* dst, int ld, const double (&r)[E], const double* src) const
+    {
+        if constexpr (PM) {
+#pragma unroll
+            for (int t = 0; t < E; ++t) {
+                const int e = lane + WAVE * t;
+                if (e < R * C) dst[(e % R) + (e / R) * ld] = r[t];
+            }
+        } else {
+#pragma unroll 4
+            for (int e = lane; e < R * C; e += WAVE) dst[(e % R) + (e / R) * ld] = src[e];
+        }
+    }
+    // small blocks that always go through registers
+    template <int R, int C, int E>
+    __device__ __forceinline__ void fetch_r(double (&r)[E], const double* __restrict__ src) const
     {
 #pragma unroll
         for (int t = 0; t < E; ++t) {
@@ -188,12 +223,44 @@ struct Ipm {
         }
     }
     template <int R, int C, int E>
-    __device__ __forceinline__ void commit(double* dst, int ld, const double (&r)[E]) const
+    __device__ __forceinline__ void commit_r(double* dst, int ld, const double (&r)[E]) const
     {
 #pragma unroll
         for (int t = 0; t < E; ++t) {
             const int e = lane + WAVE * t;
             if (e < R * C) dst[(e % R) + (e / R) * ld] = r[t];
+        }
+    }
+    // (x, x) block of a stage factor (rows/cols NU.., column-major NZ x NZ)
+    // into an NX x NX LDS block, optionally with the strict upper part zeroed
+    __device__ __forceinline__ void fetch_lxx(double (&r)[EXr], const double* __restrict__ wl, const double*& keep) const
+    {
+        keep = wl;
+        if constexpr (PM) {
+#pragma unroll
+            for (int t = 0; t < EX; ++t) {
+                const int e = lane + WAVE * t;
+                r[t] = (e < NX * NX) ? wl[(NU + e % NX) + (NU + e / NX) * NZ] : 0.0;
+            }
+        }
+    }
+    __device__ __forceinline__ void commit_lxx(double* dst, const double (&r)[EXr], const double* wl, bool lower) const
+    {
+        if constexpr (PM) {
+#pragma unroll
+            for (int t = 0; t < EX; ++t) {
+                const int e = lane + WAVE * t;
+                if (e < NX * NX) {
+                    const int i = e % NX, k = e / NX;
+                    dst[i + k * LDX] = (!lower || k <= i) ? r[t] : 0.0;
+                }
+            }
+        } else {
+#pragma unroll 4
+            for (int e = lane; e < NX * NX; e += WAVE) {
+                const int i = e % NX, k = e / NX;
+                dst[i + k * LDX] = (!lower || k <= i) ? wl[(NU + i) + (NU + k) * NZ] : 0.0;
+            }
         }
     }
 
@@ -383,7 +450,8 @@ struct Ipm {
     // shift.  Returns the residual norms and lam't of the (updated) iterate.
     // ==================================================================
     struct PreA {
-        double H[EH], F[EF], G[EG];
+        double H[EHr], F[EFr], G[EGr];
+        const double *sH, *sF, *sG;
         double g, z, dz, b, pi, dpi;
         double m[NCT], lo[NCT], hi[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
         double dll[NCT], dlu[NCT], dtl[NCT], dtu[NCT];
@@ -394,9 +462,9 @@ struct Ipm {
         const double* d = Dp(n);
         const double* ir = Ip(n);
         const double* w = Wp(n);
-        fetch<NZ, NZ, EH>(p.H, d + Lo.D_H);
-        if (n < N) fetch<NX, NZ, EF>(p.F, d + Lo.D_F);
-        if constexpr (NG > 0) fetch<NG, NZ, EG>(p.G, d + Lo.D_G);
+        fetch<NZ, NZ, EHr>(p.H, d + Lo.D_H, p.sH);
+        if (n < N) fetch<NX, NZ, EFr>(p.F, d + Lo.D_F, p.sF);
+        if constexpr (NG > 0) fetch<NG, NZ, EGr>(p.G, d + Lo.D_G, p.sG);
         p.g = p.z = p.dz = p.b = p.pi = p.dpi = 0.0;
         if (lane < NZ) {
             p.g = d[Lo.D_g + lane];
@@ -487,9 +555,9 @@ struct Ipm {
         loadA(p, N, upd);
         for (int n = N; n >= 0; --n) {
             const int cur = n & 1, nxt = cur ^ 1;
-            commit<NZ, NZ, EH>(s.M, LDZ, p.H);
-            if (n < N) commit<NX, NZ, EF>(s.F, LDX, p.F);
-            if constexpr (NG > 0) commit<NG, NZ, EG>(s.G, LDG, p.G);
+            commit<NZ, NZ, EHr>(s.M, LDZ, p.H, p.sH);
+            if (n < N) commit<NX, NZ, EFr>(s.F, LDX, p.F, p.sF);
+            if constexpr (NG > 0) commit<NG, NZ, EGr>(s.G, LDG, p.G, p.sG);
             const double g = p.g, b = p.b, dz = p.dz, dpi = p.dpi;
             double z = p.z, pi = p.pi;
             double m[NCT], lo[NCT], hi[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
@@ -728,7 +796,8 @@ struct Ipm {
     // the RHS (r_g, r_b, r_d) at offsets og, ob, odl, odu and r_m per rmode.
     // ==================================================================
     struct PreC {
-        double Lxx[EX], F[EF], G[EG];
+        double Lxx[EXr], F[EFr], G[EGr];
+        const double *sLxx, *sF, *sG;
         double rowL[NU1];
         double dinv, rg, rb;
         double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
@@ -740,13 +809,9 @@ struct Ipm {
         const double* d = Dp(n);
         const double* ir = Ip(n);
         const double* w = Wp(n);
-#pragma unroll
-        for (int t = 0; t < EX; ++t) {
-            const int e = lane + WAVE * t;
-            p.Lxx[t] = (e < NX * NX) ? w[Lo.W_L + (NU + e % NX) + (NU + e / NX) * NZ] : 0.0;
-        }
-        if (n < N) fetch<NX, NZ, EF>(p.F, d + Lo.D_F);
-        if constexpr (NG > 0) fetch<NG, NZ, EG>(p.G, d + Lo.D_G);
+        fetch_lxx(p.Lxx, w + Lo.W_L, p.sLxx);
+        if (n < N) fetch<NX, NZ, EFr>(p.F, d + Lo.D_F, p.sF);
+        if constexpr (NG > 0) fetch<NG, NZ, EGr>(p.G, d + Lo.D_G, p.sG);
 #pragma unroll
         for (int k = 0; k < NU1; ++k) p.rowL[k] = (lane < NZ && k < NU) ? w[Lo.W_L + lane + k * NZ] : 0.0;
         p.dinv = lane < NZ ? w[Lo.W_dinv + lane] : 0.0;
@@ -771,16 +836,9 @@ struct Ipm {
         for (int n = N; n >= 0; --n) {
             const int cur = n & 1, nxt = cur ^ 1;
             // (x, x) block of this stage's factor becomes L_{n+1} of stage n-1
-#pragma unroll
-            for (int t = 0; t < EX; ++t) {
-                const int e = lane + WAVE * t;
-                if (e < NX * NX) {
-                    const int i = e % NX, k = e / NX;
-                    s.Lx[cur][i + k * LDX] = (k <= i) ? p.Lxx[t] : 0.0;
-                }
-            }
-            if (n < N) commit<NX, NZ, EF>(s.F, LDX, p.F);
-            if constexpr (NG > 0) commit<NG, NZ, EG>(s.G, LDG, p.G);
+            commit_lxx(s.Lx[cur], p.Lxx, p.sLxx, true);
+            if (n < N) commit<NX, NZ, EFr>(s.F, LDX, p.F, p.sF);
+            if constexpr (NG > 0) commit<NG, NZ, EGr>(s.G, LDG, p.G, p.sG);
             double rowL[NU1];
 #pragma unroll
             for (int k = 0; k < NU1; ++k) rowL[k] = p.rowL[k];
@@ -832,7 +890,8 @@ struct Ipm {
     // (lam't + a s1 + a^2 s2) / n_c.
     // ==================================================================
     struct PreB {
-        double L[EL], Lxx[EX], F[EF], G[EG];
+        double L[EL], Lxx[EXr], F[EFr], G[EGr];
+        const double *sLxx, *sF, *sG;
         double dinv, yu, rb, pn;
         double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
         double a1[NCT], a2[NCT], a3[NCT], a4[NCT];
@@ -843,24 +902,20 @@ struct Ipm {
         const double* d = Dp(n);
         const double* ir = Ip(n);
         const double* w = Wp(n);
-        if constexpr (NU > 0) fetch<NZ, NU, EL>(p.L, w + Lo.W_L);
+        if constexpr (NU > 0) fetch_r<NZ, NU, EL>(p.L, w + Lo.W_L);
         p.dinv = lane < NU ? w[Lo.W_dinv + lane] : 0.0;
         p.yu = lane < NU ? w[Lo.W_yu + lane] : 0.0;
         p.rb = p.pn = 0.0;
         if (n < N) {
             const double* w1 = Wp(n + 1);
-#pragma unroll
-            for (int t = 0; t < EX; ++t) {
-                const int e = lane + WAVE * t;
-                p.Lxx[t] = (e < NX * NX) ? w1[Lo.W_L + (NU + e % NX) + (NU + e / NX) * NZ] : 0.0;
-            }
-            fetch<NX, NZ, EF>(p.F, d + Lo.D_F);
+            fetch_lxx(p.Lxx, w1 + Lo.W_L, p.sLxx);
+            fetch<NX, NZ, EFr>(p.F, d + Lo.D_F, p.sF);
             if (lane < NX) {
                 p.rb = w[ob + lane];
                 p.pn = w1[Lo.W_pv + lane];
             }
         }
-        if constexpr (NG > 0) fetch<NG, NZ, EG>(p.G, d + Lo.D_G);
+        if constexpr (NG > 0) fetch<NG, NZ, EGr>(p.G, d + Lo.D_G, p.sG);
         load_slots_rm(rmode, d, ir, w, odl, odu, p.m, p.rdl, p.rdu, p.ll, p.lu, p.tl, p.tu, p.a1, p.a2, p.a3, p.a4);
     }
 
@@ -927,16 +982,12 @@ struct Ipm {
         }
         for (int n = 0; n <= N; ++n) {
             const int cur = n & 1, nxt = cur ^ 1;
-            if constexpr (NU > 0) commit<NZ, NU, EL>(s.M, LDZ, p.L);
+            if constexpr (NU > 0) commit_r<NZ, NU, EL>(s.M, LDZ, p.L);
             if (n < N) {
-#pragma unroll
-                for (int t = 0; t < EX; ++t) {
-                    const int e = lane + WAVE * t;
-                    if (e < NX * NX) s.Lx[nxt][(e % NX) + (e / NX) * LDX] = p.Lxx[t];
-                }
-                commit<NX, NZ, EF>(s.F, LDX, p.F);
+                commit_lxx(s.Lx[nxt], p.Lxx, p.sLxx, false);
+                commit<NX, NZ, EFr>(s.F, LDX, p.F, p.sF);
             }
-            if constexpr (NG > 0) commit<NG, NZ, EG>(s.G, LDG, p.G);
+            if constexpr (NG > 0) commit<NG, NZ, EGr>(s.G, LDG, p.G, p.sG);
             const double dv = p.dinv, yu = p.yu, rb = p.rb, pn = p.pn;
             double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
             double rml[NCT], rmu[NCT];
@@ -1047,7 +1098,8 @@ struct Ipm {
     // Writes r_ir to the refinement arrays and returns its inf-norm.
     // ==================================================================
     struct PreR {
-        double H[EH], F[EF], G[EG];
+        double H[EHr], F[EFr], G[EGr];
+        const double *sH, *sF, *sG;
         double dz, dpi, rg, rb;
         double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
         double a1[NCT], a2[NCT], a3[NCT], a4[NCT];
@@ -1060,9 +1112,9 @@ struct Ipm {
         const double* d = Dp(n);
         const double* ir = Ip(n);
         const double* w = Wp(n);
-        fetch<NZ, NZ, EH>(p.H, d + Lo.D_H);
-        if (n < N) fetch<NX, NZ, EF>(p.F, d + Lo.D_F);
-        if constexpr (NG > 0) fetch<NG, NZ, EG>(p.G, d + Lo.D_G);
+        fetch<NZ, NZ, EHr>(p.H, d + Lo.D_H, p.sH);
+        if (n < N) fetch<NX, NZ, EFr>(p.F, d + Lo.D_F, p.sF);
+        if constexpr (NG > 0) fetch<NG, NZ, EGr>(p.G, d + Lo.D_G, p.sG);
         p.dz = lane < NZ ? w[oz + lane] : 0.0;
         p.rg = lane < NZ ? w[Lo.W_rg + lane] : 0.0;
         p.dpi = (lane < NX && n > 0) ? w[opi + lane] : 0.0;
@@ -1113,9 +1165,9 @@ struct Ipm {
         loadR(p, N, rmode, oz, opi, oll, olu, otl, otu);
         for (int n = N; n >= 0; --n) {
             const int cur = n & 1, nxt = cur ^ 1;
-            commit<NZ, NZ, EH>(s.M, LDZ, p.H);
-            if (n < N) commit<NX, NZ, EF>(s.F, LDX, p.F);
-            if constexpr (NG > 0) commit<NG, NZ, EG>(s.G, LDG, p.G);
+            commit<NZ, NZ, EHr>(s.M, LDZ, p.H, p.sH);
+            if (n < N) commit<NX, NZ, EFr>(s.F, LDX, p.F, p.sF);
+            if constexpr (NG > 0) commit<NG, NZ, EGr>(s.G, LDG, p.G, p.sG);
             const double dz = p.dz, dpi = p.dpi, rg = p.rg, rb = p.rb;
             double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT], rml[NCT], rmu[NCT];
             double sll[NCT], slu[NCT], stl[NCT], stu[NCT];
@@ -1426,8 +1478,12 @@ struct Ipm {
     }
 };
 
+// Occupancy: small stage blocks fit two waves per SIMD; larger ones get the
+// whole register file (256 VGPRs + 256 AGPRs) of one wave instead of spilling.
+__host__ __device__ constexpr int ipm_max_waves(int nz, bool mixed) { return (nz > 24 || (mixed && nz > 16)) ? 1 : 2; }
+
 template <int NX, int NU, int NG, bool MIXED>
-__global__ __launch_bounds__(WAVE) void ipm_kernel(const InstDesc* __restrict__ desc, int count,
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, ipm_max_waves(NX + NU, MIXED)))) void ipm_kernel(const InstDesc* __restrict__ desc, int count,
                                                     const double* __restrict__ data, double* __restrict__ iter,
                                                     double* __restrict__ work, double* __restrict__ step_out,
                                                     DevStat* __restrict__ stat, KParams P)
@@ -1446,48 +1502,12 @@ __global__ __launch_bounds__(WAVE) void ipm_kernel(const InstDesc* __restrict__ 
     ipm.run(stat + ds.index, step_out + ds.iter, fell_back);
 }
 
-// ---------------------------------------------------------------------------
-// Variant table
-// ---------------------------------------------------------------------------
-
-typedef void (*launch_fn)(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams,
-                          hipStream_t);
-
 template <int NX, int NU, int NG, bool MIXED>
-static void launch(const InstDesc* desc, int count, const double* data, double* iter, double* work, double* step,
-                   DevStat* stat, KParams P, hipStream_t stream)
+void launch_ipm(const InstDesc* desc, int count, const double* data, double* iter, double* work, double* step,
+                DevStat* stat, KParams P, hipStream_t stream)
 {
     hipLaunchKernelGGL((ipm_kernel<NX, NU, NG, MIXED>), dim3(count), dim3(WAVE), 0, stream, desc, count, data, iter,
                        work, step, stat, P);
-}
-
-struct Variant {
-    int NX, NU, NG;
-    launch_fn fn[2];  // FP64 path, mixed path
-};
-
-#define OQP_VARIANT(x, u, g) {x, u, g, {&launch<x, u, g, false>, &launch<x, u, g, true>}}
-static const Variant kVariants[] = {
-    OQP_VARIANT(4, 4, 0),  OQP_VARIANT(4, 4, 4),  OQP_VARIANT(8, 4, 0),  OQP_VARIANT(8, 8, 0),
-    OQP_VARIANT(16, 8, 0), OQP_VARIANT(16, 16, 0), OQP_VARIANT(24, 8, 0), OQP_VARIANT(32, 16, 0),
-};
-#undef OQP_VARIANT
-
-int variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
-
-void variant_dims(int v, int* nx, int* nu, int* ng)
-{
-    *nx = kVariants[v].NX;
-    *nu = kVariants[v].NU;
-    *ng = kVariants[v].NG;
-}
-
-int variant_launch(int v, int mixed, const InstDesc* desc, int count, const double* data, double* iter, double* work,
-                   double* step, DevStat* stat, const KParams& P, void* stream)
-{
-    if (count <= 0) return 0;
-    kVariants[v].fn[mixed ? 1 : 0](desc, count, data, iter, work, step, stat, P, (hipStream_t)stream);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace oqp

@@ -1,0 +1,12 @@
+// Explicit instantiations of ipm_kernel variants (one of several units
+// compiled in parallel).
+#include "ipm_kernel.h"
+
+namespace oqp {
+template void launch_ipm<24, 16, 0, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<24, 16, 0, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<24, 8, 0, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<24, 8, 0, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<8, 4, 0, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<8, 4, 0, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+}  // namespace oqp

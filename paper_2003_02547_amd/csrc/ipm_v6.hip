@@ -1,0 +1,16 @@
+// Explicit instantiations of ipm_kernel variants (one of several units
+// compiled in parallel).
+#include "ipm_kernel.h"
+
+namespace oqp {
+template void launch_ipm<32, 8, 0, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<32, 8, 0, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<24, 4, 0, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<24, 4, 0, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<8, 8, 0, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<8, 8, 0, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<4, 4, 0, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<4, 4, 0, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<4, 4, 4, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<4, 4, 4, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+}  // namespace oqp

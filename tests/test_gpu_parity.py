@@ -240,3 +240,45 @@ def test_first_iterations_track_oracle():
     for q, r in zip(qps, res):
         o = O.solve(q)
         assert abs(r.iters - o.iters) <= 1, (r.iters, o.iters)
+
+
+# ---------------------------------------------------------------------------
+# Uneven batches: random stable systems of different sizes in one batch
+# ---------------------------------------------------------------------------
+
+def test_uneven_random_batch_sampled():
+    """Instances of the uneven workload (nx 4..48, nu 1..16, N 10..100) in one
+    batch, spread over many kernel variants; sampled ones vs the oracle."""
+    qps = [W.random_uneven(i) for i in range(96)]
+    say("solve: uneven x96")
+    b = B.Batch(qps).load().solve().fetch().sync()
+    res = b.results()
+    variants = {b.variant(i)[1] for i in range(len(qps))}
+    assert len(variants) >= 6, variants
+    for i in range(0, len(qps), 6):
+        ref = O.solve(qps[i], O.Arg.with_tol(1e-8))
+        if ref.status != O.SUCCESS:
+            assert res[i].status != B.SUCCESS
+            continue
+        assert res[i].status == B.SUCCESS, (i, res[i].status, res[i].res, b.variant(i))
+        assert O.kkt_res(qps[i], res[i].sol) <= KKT_TOL + 1e-12
+        assert primal_err(res[i].sol, ref.sol) <= PRIMAL_TOL, (i, b.variant(i))
+    ok = sum(r.status == B.SUCCESS for r in res)
+    assert ok >= 90, ok
+
+
+def test_uneven_large_bucket_newton_step():
+    """Newton step parity in the largest buckets (stage block up to 64)."""
+    qps = [q for q in (W.random_uneven(i) for i in range(200)) if q.nx[1] > 36][:6]
+    rng = np.random.default_rng(5)
+    its = [random_interior_iterate(q, rng, scale=0.3) for q in qps]
+    say("newton: large buckets")
+    b = B.Batch(qps).load()
+    for i, it in enumerate(its):
+        b.set_iterate(i, it)
+    b.newton(0.02).fetch().sync()
+    for i, (q, it) in enumerate(zip(qps, its)):
+        ref = O.newton_step(q, it, 0.02)
+        got = b.step(i)
+        for k in KEYS:
+            assert rel(got[k], ref[k]) <= 1e-8, (i, k, rel(got[k], ref[k]), b.variant(i))
