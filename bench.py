@@ -31,7 +31,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("ipm_kernel.hip", "layout.h"):
+    for f in ("ipm_kernel.h", "layout.h"):
         with open(os.path.join(ROOT, "paper_2003_02547_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

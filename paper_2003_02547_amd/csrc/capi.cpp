@@ -9,14 +9,8 @@
 #include <cstring>
 
 #include "../../include/oqp.h"
+#include "internal.h"
 #include "layout.h"
-
-namespace oqp {
-int variant_count();
-void variant_dims(int v, int* nx, int* nu, int* ng);
-int variant_launch(int v, int mixed, const InstDesc* desc, int count, const double* data, double* iter, double* work,
-                   double* step, DevStat* stat, const KParams& P, void* stream);
-}  // namespace oqp
 
 using oqp::DevStat;
 using oqp::InstDesc;
@@ -24,7 +18,7 @@ using oqp::Layout;
 
 static thread_local char g_err[512] = "";
 
-static int fail(int code, const char* fmt, ...)
+int fail(int code, const char* fmt, ...)
 {
     va_list ap;
     va_start(ap, fmt);
@@ -33,22 +27,13 @@ static int fail(int code, const char* fmt, ...)
     return code;
 }
 
-static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 extern "C" const char* oqp_last_error(void) { return g_err; }
 
 // ---------------------------------------------------------------------------
 // dims
 // ---------------------------------------------------------------------------
-
-struct oqp_dims {
-    int N;
-    int* nx;
-    int* nu;
-    int* nbu;
-    int* nbx;
-    int* ng;
-};
 
 extern "C" size_t oqp_dims_bytes(int N)
 {
@@ -91,8 +76,6 @@ extern "C" int oqp_dims_set_stage(oqp_dims* d, int n, int nx, int nu, int nbu, i
 // qp
 // ---------------------------------------------------------------------------
 
-// Per-stage double block: A, B, b, Q, S, R, q, r, lbu, ubu, lbx, ubx, D, C, lg, ug.
-enum { F_A, F_B, F_b, F_Q, F_S, F_R, F_q, F_r, F_lbu, F_ubu, F_lbx, F_ubx, F_D, F_C, F_lg, F_ug, F_COUNT };
 
 static void stage_sizes(const oqp_dims* d, int n, size_t* sz)
 {
@@ -112,14 +95,6 @@ static void stage_sizes(const oqp_dims* d, int n, size_t* sz)
     sz[F_C] = (size_t)ng * nx;
     sz[F_lg] = sz[F_ug] = ng;
 }
-
-struct oqp_qp {
-    const oqp_dims* dims;
-    int64_t* doff;  // (N+2) stage offsets into d
-    int64_t* ioff;  // (N+2) stage offsets into idx (idxbu then idxbx)
-    double* d;
-    int* idx;
-};
 
 static void qp_offsets(const oqp_dims* dims, int64_t* doff, int64_t* ioff)
 {
@@ -177,7 +152,7 @@ extern "C" int oqp_qp_init(const oqp_dims* dims, void* mem, size_t bytes, oqp_qp
     return OQP_OK;
 }
 
-static double* qp_field(const oqp_qp* q, int n, int f)
+double* qp_field(const oqp_qp* q, int n, int f)
 {
     size_t sz[F_COUNT];
     stage_sizes(q->dims, n, sz);
@@ -316,7 +291,7 @@ extern "C" void oqp_arg_default(oqp_arg* a, int mode)
     a->warm_start = 0;
 }
 
-static int check_arg(const oqp_arg* a)
+int check_arg(const oqp_arg* a)
 {
     if (!a) return fail(OQP_EINVAL, "NULL oqp_arg");
     if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED) return fail(OQP_EINVAL, "unknown mode %d", a->mode);
@@ -370,7 +345,7 @@ struct oqp_batch {
     int64_t n_data, n_iter, n_work;
 };
 
-static int pick_variant(const oqp_dims* d)
+int pick_variant(const oqp_dims* d)
 {
     int mx = 0, mu = 0, mg = 0;
     for (int n = 0; n <= d->N; ++n) {
@@ -577,30 +552,21 @@ static inline const int* inst_dims(const oqp_batch* b, const Inst& in, int which
 }
 
 // Pack instance i's QP into its padded stage records.
-static int pack_instance(oqp_batch* b, int i, const oqp_qp* q)
+// Pack a QP into N+1 padded stage records (L.SREC doubles each) at dst and
+// fill the map from user constraint order to padded slot (nc entries).
+int pack_records(const oqp_qp* q, const Layout& L, double* dst, int* slots)
 {
-    const Inst& in = b->inst[i];
-    const Layout L = inst_layout(in);
-    const int* nxv = inst_dims(b, in, 0);
-    const int* nuv = inst_dims(b, in, 1);
-    const int* nbuv = inst_dims(b, in, 2);
-    const int* nbxv = inst_dims(b, in, 3);
-    const int* ngv = inst_dims(b, in, 4);
     const oqp_dims* qd = q->dims;
-    if (qd->N != in.N) return fail(OQP_EINVAL, "oqp_batch_load: qp %d horizon differs from its dims", i);
-    for (int n = 0; n <= in.N; ++n)
-        if (qd->nx[n] != nxv[n] || qd->nu[n] != nuv[n] || qd->nbu[n] != nbuv[n] || qd->nbx[n] != nbxv[n] ||
-            qd->ng[n] != ngv[n])
-            return fail(OQP_EINVAL, "oqp_batch_load: qp %d sizes differ from its dims at stage %d", i, n);
+    const int N = qd->N;
     const int NX = L.NX, NU = L.NU, NZ = L.NZ;
-    int* slots = b->slot_pool + in.slot_off;
     int so = 0;
-    for (int n = 0; n <= in.N; ++n) {
-        double* r = b->hdata + in.data + (int64_t)n * L.SREC;
+    for (int n = 0; n <= N; ++n) {
+        double* r = dst + (int64_t)n * L.SREC;
         std::memset(r, 0, sizeof(double) * L.SREC);
-        const int nx = nxv[n], nu = nuv[n], nxn = n < in.N ? nxv[n + 1] : 0, ng = ngv[n];
+        const int nx = qd->nx[n], nu = qd->nu[n], nxn = n < N ? qd->nx[n + 1] : 0, ng = qd->ng[n];
+        if (nx > NX || nu > NU || ng > L.NG || nxn > NX) return fail(OQP_EINVAL, "pack: stage %d exceeds the variant", n);
         // F = [B A]
-        if (n < in.N) {
+        if (n < N) {
             const double* A = qp_field(q, n, F_A);
             const double* B = qp_field(q, n, F_B);
             const double* bb = qp_field(q, n, F_b);
@@ -620,9 +586,9 @@ static int pack_instance(oqp_batch* b, int i, const oqp_qp* q)
                 for (int i2 = 0; i2 < nu; ++i2) H[i2 + j * NZ] = R[i2 + (size_t)j * nu];
             for (int j = 0; j < nx; ++j)
                 for (int i2 = 0; i2 < nu; ++i2) {
-                    const double s = S[i2 + (size_t)j * nu];
-                    H[i2 + (NU + j) * NZ] = s;
-                    H[(NU + j) + i2 * NZ] = s;
+                    const double sv = S[i2 + (size_t)j * nu];
+                    H[i2 + (NU + j) * NZ] = sv;
+                    H[(NU + j) + i2 * NZ] = sv;
                 }
             for (int j = 0; j < nx; ++j)
                 for (int i2 = 0; i2 < nx; ++i2) H[(NU + i2) + (NU + j) * NZ] = Q[i2 + (size_t)j * nx];
@@ -635,20 +601,21 @@ static int pack_instance(oqp_batch* b, int i, const oqp_qp* q)
         }
         // boxes
         {
+            const int nbu = qd->nbu[n], nbx = qd->nbx[n];
             const int* iu = q->idx + q->ioff[n];
-            const int* ix = iu + nbuv[n];
+            const int* ix = iu + nbu;
             const double* lbu = qp_field(q, n, F_lbu);
             const double* ubu = qp_field(q, n, F_ubu);
             const double* lbx = qp_field(q, n, F_lbx);
             const double* ubx = qp_field(q, n, F_ubx);
-            for (int k = 0; k < nbuv[n]; ++k) {
+            for (int k = 0; k < nbu; ++k) {
                 const int c = iu[k];
                 r[L.D_bm + c] = 1.0;
                 r[L.D_blo + c] = lbu[k];
                 r[L.D_bhi + c] = ubu[k];
                 slots[so++] = c;
             }
-            for (int k = 0; k < nbxv[n]; ++k) {
+            for (int k = 0; k < nbx; ++k) {
                 const int c = NU + ix[k];
                 r[L.D_bm + c] = 1.0;
                 r[L.D_blo + c] = lbx[k];
@@ -675,6 +642,24 @@ static int pack_instance(oqp_batch* b, int i, const oqp_qp* q)
     return OQP_OK;
 }
 
+static int pack_instance(oqp_batch* b, int i, const oqp_qp* q)
+{
+    const Inst& in = b->inst[i];
+    const Layout L = inst_layout(in);
+    const int* nxv = inst_dims(b, in, 0);
+    const int* nuv = inst_dims(b, in, 1);
+    const int* nbuv = inst_dims(b, in, 2);
+    const int* nbxv = inst_dims(b, in, 3);
+    const int* ngv = inst_dims(b, in, 4);
+    const oqp_dims* qd = q->dims;
+    if (qd->N != in.N) return fail(OQP_EINVAL, "oqp_batch_load: qp %d horizon differs from its dims", i);
+    for (int n = 0; n <= in.N; ++n)
+        if (qd->nx[n] != nxv[n] || qd->nu[n] != nuv[n] || qd->nbu[n] != nbuv[n] || qd->nbx[n] != nbxv[n] ||
+            qd->ng[n] != ngv[n])
+            return fail(OQP_EINVAL, "oqp_batch_load: qp %d sizes differ from its dims at stage %d", i, n);
+    return pack_records(q, L, b->hdata + in.data, b->slot_pool + in.slot_off);
+}
+
 extern "C" int oqp_batch_load(oqp_batch* b, const oqp_qp* const* qps)
 {
     if (!b || !qps) return fail(OQP_EINVAL, "oqp_batch_load: NULL argument");
@@ -690,7 +675,7 @@ extern "C" int oqp_batch_load(oqp_batch* b, const oqp_qp* const* qps)
     return OQP_OK;
 }
 
-static oqp::KParams make_params(const oqp_arg& a, int mode, double tau)
+oqp::KParams make_params(const oqp_arg& a, int mode, double tau)
 {
     oqp::KParams P{};
     P.tol_stat = a.tol_stat;
@@ -788,21 +773,19 @@ extern "C" int oqp_batch_get_stat(const oqp_batch* b, int i, oqp_stat* st)
     return OQP_OK;
 }
 
-// Copy between the padded iterate layout and the user layout.
-static void user_copy(const oqp_batch* b, int i, double* region, bool to_user, double* u, double* x, double* pi,
-                      double* ll, double* lu, double* tl, double* tu)
+// Copy between padded iterate records (N+1 of L.IREC doubles at rec) and the
+// user layout; dims5 holds nx, nu, nbu, nbx, ng, each N+1 entries.
+void iterate_user_copy(const int* dims5, int N, const int* slots, const Layout& L, double* rec, bool to_user,
+                       double* u, double* x, double* pi, double* ll, double* lu, double* tl, double* tu)
 {
-    const Inst& in = b->inst[i];
-    const Layout L = inst_layout(in);
-    const int* nxv = inst_dims(b, in, 0);
-    const int* nuv = inst_dims(b, in, 1);
-    const int* nbuv = inst_dims(b, in, 2);
-    const int* nbxv = inst_dims(b, in, 3);
-    const int* ngv = inst_dims(b, in, 4);
-    const int* slots = b->slot_pool + in.slot_off;
+    const int* nxv = dims5;
+    const int* nuv = dims5 + (N + 1);
+    const int* nbuv = dims5 + 2 * (N + 1);
+    const int* nbxv = dims5 + 3 * (N + 1);
+    const int* ngv = dims5 + 4 * (N + 1);
     int ou = 0, ox = 0, op = 0, oc = 0;
-    for (int n = 0; n <= in.N; ++n) {
-        double* r = region + in.iter + (int64_t)n * L.IREC;
+    for (int n = 0; n <= N; ++n) {
+        double* r = rec + (int64_t)n * L.IREC;
         const int nu = nuv[n], nx = nxv[n];
         for (int j = 0; j < nu; ++j) {
             if (u) { if (to_user) u[ou + j] = r[L.I_z + j]; else r[L.I_z + j] = u[ou + j]; }
@@ -821,16 +804,24 @@ static void user_copy(const oqp_batch* b, int i, double* region, bool to_user, d
             const int c = slots[oc + k];
             double* vals[4] = {ll, lu, tl, tu};
             const int offs[4] = {L.I_ll, L.I_lu, L.I_tl, L.I_tu};
-            for (int a = 0; a < 4; ++a) {
-                if (!vals[a]) continue;
-                if (to_user) vals[a][oc + k] = r[offs[a] + c];
-                else r[offs[a] + c] = vals[a][oc + k];
+            for (int a2 = 0; a2 < 4; ++a2) {
+                if (!vals[a2]) continue;
+                if (to_user) vals[a2][oc + k] = r[offs[a2] + c];
+                else r[offs[a2] + c] = vals[a2][oc + k];
             }
         }
         ou += nu;
         ox += nx;
         oc += nc;
     }
+}
+
+static void user_copy(const oqp_batch* b, int i, double* region, bool to_user, double* u, double* x, double* pi,
+                      double* ll, double* lu, double* tl, double* tu)
+{
+    const Inst& in = b->inst[i];
+    iterate_user_copy(b->dims_pool + in.dims_off, in.N, b->slot_pool + in.slot_off, inst_layout(in),
+                      region + in.iter, to_user, u, x, pi, ll, lu, tl, tu);
 }
 
 extern "C" int oqp_batch_get_sol(const oqp_batch* b, int i, double* u, double* x, double* pi, double* lam_l,

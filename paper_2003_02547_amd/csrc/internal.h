@@ -1,0 +1,45 @@
+// Internal declarations shared by the C-ABI implementation units.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/oqp.h"
+#include "layout.h"
+
+struct oqp_dims {
+    int N;
+    int* nx;
+    int* nu;
+    int* nbu;
+    int* nbx;
+    int* ng;
+};
+
+// Per-stage double block of a host QP: A, B, b, Q, S, R, q, r, lbu, ubu, lbx, ubx, D, C, lg, ug.
+enum { F_A, F_B, F_b, F_Q, F_S, F_R, F_q, F_r, F_lbu, F_ubu, F_lbx, F_ubx, F_D, F_C, F_lg, F_ug, F_COUNT };
+
+struct oqp_qp {
+    const oqp_dims* dims;
+    int64_t* doff;  // (N+2) stage offsets into d
+    int64_t* ioff;  // (N+2) stage offsets into idx (idxbu then idxbx)
+    double* d;
+    int* idx;
+};
+
+namespace oqp {
+int variant_count();
+void variant_dims(int v, int* nx, int* nu, int* ng);
+int variant_launch(int v, int mixed, const InstDesc* desc, int count, const double* data, double* iter, double* work,
+                   double* step, DevStat* stat, const KParams& P, void* stream);
+}  // namespace oqp
+
+int fail(int code, const char* fmt, ...);
+size_t align_up(size_t v, size_t a);
+int check_arg(const oqp_arg* a);
+int pick_variant(const oqp_dims* d);
+double* qp_field(const oqp_qp* q, int n, int f);
+oqp::KParams make_params(const oqp_arg& a, int mode, double tau);
+int pack_records(const oqp_qp* q, const oqp::Layout& L, double* dst, int* slots);
+void iterate_user_copy(const int* dims5, int N, const int* slots, const oqp::Layout& L, double* rec, bool to_user,
+                       double* u, double* x, double* pi, double* ll, double* lu, double* tl, double* tu);
