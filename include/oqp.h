@@ -63,6 +63,7 @@ extern "C" {
 typedef struct oqp_dims oqp_dims;
 typedef struct oqp_qp oqp_qp;
 typedef struct oqp_batch oqp_batch;
+typedef struct oqp_server oqp_server;
 
 /* Solver arguments (Section 4.2).  Fill with oqp_arg_default. */
 typedef struct {
@@ -172,6 +173,88 @@ int oqp_batch_set_iterate(oqp_batch* batch, int i, const double* u, const double
 int oqp_batch_newton(oqp_batch* batch, double tau);
 int oqp_batch_get_step(const oqp_batch* batch, int i, double* du, double* dx, double* dpi, double* dlam_l,
                        double* dlam_u, double* dt_l, double* dt_u);
+
+/* ---- packed requests ------------------------------------------------------ */
+/* A QP packed once into a relocatable blob in the device record layout of the
+ * kernel variant that covers its stage sizes (header, per-stage sizes,
+ * constraint slot map, stage records).  The blob is what a serving client
+ * hands to oqp_server_submit.  OQP_EINVAL if no variant covers the QP. */
+int oqp_pack_bytes(const oqp_qp* qp, size_t* bytes);
+/* Pack into mem (64-byte aligned, at least oqp_pack_bytes).  Keep the blob in
+ * page-locked memory for asynchronous uploads. */
+int oqp_pack(const oqp_qp* qp, void* mem, size_t bytes);
+/* Device bytes a packed request occupies while admitted (data, iterate and
+ * workspace records: its HBM footprint) and its kernel variant. */
+int oqp_pack_footprint(const void* packed, size_t* dev_bytes, int* variant);
+
+/* ---- continuous-batching server (device-resident IPM state) --------------- */
+/* Requests (packed QPs of any covered size) are admitted when a block of the
+ * device arena large enough for their footprint is free (first-fit; freed on
+ * release), otherwise submit returns OQP_EBUSY and the caller retries later.
+ * oqp_server_progress retires finished launches and launches every admitted
+ * request, grouped by kernel variant (at most max_launch per launch), on the
+ * least-loaded of streams[1..nstreams-1], so requests that arrive while others
+ * run start without waiting for them.  streams[0] serves oqp_server_get_sol.
+ * The solver arguments (mode included) are fixed at init.  A server is used
+ * from one host thread at a time. */
+#define OQP_SERVER_MAX_STREAMS 32
+typedef struct {
+    int max_requests;     /* requests admitted at once (queued, running or finished, not released) */
+    int max_launch;       /* requests per kernel launch (1 = one launch per request) */
+    int max_groups;       /* launches in flight at once */
+    size_t staging_bytes; /* host staging for oqp_server_get_sol: the largest padded iterate */
+} oqp_server_cfg;
+
+typedef struct {
+    uint64_t submitted;   /* requests admitted */
+    uint64_t rejected;    /* submit calls refused with OQP_EBUSY */
+    uint64_t completed;   /* requests finished */
+    uint64_t launches;    /* kernel launch groups */
+    int queued, running, done; /* requests in each state now */
+    size_t dev_arena;     /* device bytes available to requests */
+    size_t dev_used;      /* device bytes held by admitted requests now */
+    size_t dev_peak;      /* high-water mark of dev_used */
+} oqp_server_counters;
+
+void oqp_server_cfg_default(oqp_server_cfg* cfg);
+/* Host bytes for the server and the fixed device part (launch descriptors and
+ * status blocks); the rest of the device buffer given to init is the arena. */
+int oqp_server_bytes(const oqp_server_cfg* cfg, size_t* host_bytes, size_t* dev_fixed_bytes);
+/* host_mem: page-locked (hipHostMalloc), 64-byte aligned, >= host_bytes
+ * (OQP_EINVAL if it is pageable).  dev_mem: 256-byte aligned device buffer.
+ * streams: 2..OQP_SERVER_MAX_STREAMS hipStream_t handles owned by the caller.
+ * Creates one HIP event per launch slot (released by oqp_server_destroy). */
+int oqp_server_init(const oqp_server_cfg* cfg, const oqp_arg* arg, void* host_mem, size_t host_bytes, void* dev_mem,
+                    size_t dev_bytes, void* const* streams, int nstreams, oqp_server** out);
+/* Wait for all work on the server's streams and destroy its events. */
+int oqp_server_destroy(oqp_server* server);
+/* Admit a packed request (the blob must stay unchanged until release).
+ * OQP_EBUSY when no request slot or device block is free now; OQP_ENOMEM if
+ * the request can never fit the arena. */
+int oqp_server_submit(oqp_server* server, const void* packed, uint64_t* ticket);
+/* Retire finished launches and launch admitted requests; *completed (may be
+ * NULL) receives the number of requests finished by this call. */
+int oqp_server_progress(oqp_server* server, int* completed);
+/* OQP_PENDING until the request has finished, then OQP_OK and its stat. */
+int oqp_server_poll(const oqp_server* server, uint64_t ticket, oqp_stat* stat);
+/* Seconds from submit to the progress call that saw the request finish. */
+int oqp_server_latency(const oqp_server* server, uint64_t ticket, double* seconds);
+/* Solution of a finished request (layout as oqp_batch_get_sol); copies the
+ * padded iterate from the device on streams[0] and waits for that copy. */
+int oqp_server_get_sol(oqp_server* server, uint64_t ticket, double* u, double* x, double* pi, double* lam_l,
+                       double* lam_u, double* t_l, double* t_u);
+/* Free a finished request's device block and slot; the ticket becomes invalid. */
+int oqp_server_release(oqp_server* server, uint64_t ticket);
+int oqp_server_stats(const oqp_server* server, oqp_server_counters* stats);
+/* Replay an arrival schedule in real time on an idle server: request i is
+ * submitted once arrival[i] seconds (non-decreasing) have passed since the
+ * call began (later while admission is refused), progress is driven in a busy
+ * loop, and each finished request is released.  latency[i] = finish time -
+ * scheduled arrival.  stat (may be NULL) receives each outcome, wall_s (may be
+ * NULL) the elapsed time.  OQP_EDEVICE if no request finishes for timeout_s
+ * seconds while some are in flight. */
+int oqp_server_replay(oqp_server* server, const void* const* packed, const double* arrival, int count,
+                      double timeout_s, double* latency, oqp_stat* stat, double* wall_s);
 
 /* ---- introspection -------------------------------------------------------- */
 /* Kernel variant assigned to instance i and its padded stage sizes. */

@@ -45,6 +45,17 @@ class Stat(ct.Structure):
                 ("mu", ct.c_double), ("res", ct.c_double * 4)]
 
 
+class ServerCfg(ct.Structure):
+    _fields_ = [("max_requests", ct.c_int), ("max_launch", ct.c_int), ("max_groups", ct.c_int),
+                ("staging_bytes", ct.c_size_t)]
+
+
+class Counters(ct.Structure):
+    _fields_ = [("submitted", ct.c_uint64), ("rejected", ct.c_uint64), ("completed", ct.c_uint64),
+                ("launches", ct.c_uint64), ("queued", ct.c_int), ("running", ct.c_int), ("done", ct.c_int),
+                ("dev_arena", ct.c_size_t), ("dev_used", ct.c_size_t), ("dev_peak", ct.c_size_t)]
+
+
 _lib = None
 
 
@@ -83,6 +94,22 @@ def lib():
         "oqp_batch_newton": (ct.c_int, [_V, ct.c_double]),
         "oqp_batch_get_step": (ct.c_int, [_V, ct.c_int, _P, _P, _P, _P, _P, _P, _P]),
         "oqp_batch_variant": (ct.c_int, [_V, ct.c_int, _PI, _PI, _PI]),
+        "oqp_pack_bytes": (ct.c_int, [_V, ct.POINTER(ct.c_size_t)]),
+        "oqp_pack": (ct.c_int, [_V, _V, ct.c_size_t]),
+        "oqp_pack_footprint": (ct.c_int, [_V, ct.POINTER(ct.c_size_t), _PI]),
+        "oqp_server_cfg_default": (None, [ct.POINTER(ServerCfg)]),
+        "oqp_server_bytes": (ct.c_int, [ct.POINTER(ServerCfg), ct.POINTER(ct.c_size_t), ct.POINTER(ct.c_size_t)]),
+        "oqp_server_init": (ct.c_int, [ct.POINTER(ServerCfg), ct.POINTER(Arg), _V, ct.c_size_t, _V, ct.c_size_t,
+                                       ct.POINTER(_V), ct.c_int, ct.POINTER(_V)]),
+        "oqp_server_destroy": (ct.c_int, [_V]),
+        "oqp_server_submit": (ct.c_int, [_V, _V, ct.POINTER(ct.c_uint64)]),
+        "oqp_server_progress": (ct.c_int, [_V, _PI]),
+        "oqp_server_poll": (ct.c_int, [_V, ct.c_uint64, ct.POINTER(Stat)]),
+        "oqp_server_latency": (ct.c_int, [_V, ct.c_uint64, _P]),
+        "oqp_server_get_sol": (ct.c_int, [_V, ct.c_uint64, _P, _P, _P, _P, _P, _P, _P]),
+        "oqp_server_release": (ct.c_int, [_V, ct.c_uint64]),
+        "oqp_server_stats": (ct.c_int, [_V, ct.POINTER(Counters)]),
+        "oqp_server_replay": (ct.c_int, [_V, ct.POINTER(_V), _P, ct.c_int, ct.c_double, _P, ct.POINTER(Stat), _P]),
         "oqp_variant_count": (ct.c_int, []),
         "oqp_variant_dims": (ct.c_int, [ct.c_int, _PI, _PI, _PI]),
         "oqp_last_error": (ct.c_char_p, []),
@@ -287,6 +314,137 @@ def solve(qps: Sequence, arg: Arg | None = None) -> List[Result]:
     return b.results()
 
 
+_KEYS = ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")
+
+
+def _sol_buffers(qp):
+    nu, nx, npi, nc = _sizes(qp)
+    sz = dict(u=nu, x=nx, pi=npi, lam_l=nc, lam_u=nc, t_l=nc, t_u=nc)
+    return {k: np.zeros(max(sz[k], 1)) for k in _KEYS}, sz
+
+
+class Packed:
+    """A QP packed once into the relocatable request blob (oqp_pack).
+
+    pinned=True places the blob in page-locked host memory (a pinned torch
+    tensor) so that the server's uploads are asynchronous DMA copies."""
+
+    def __init__(self, qp, pinned: bool = False):
+        L = lib()
+        self.qp = qp
+        q = Qp(qp)
+        nb = ct.c_size_t()
+        _check(L.oqp_pack_bytes(q.h, ct.byref(nb)))
+        self.nbytes = nb.value
+        if pinned:
+            import torch
+            self._mem = torch.empty(self.nbytes + 64, dtype=torch.uint8, pin_memory=True)
+            base = self._mem.data_ptr()
+        else:
+            self._mem = np.zeros(self.nbytes + 64, dtype=np.uint8)
+            base = self._mem.ctypes.data
+        self.ptr = base + ((-base) % 64)
+        _check(L.oqp_pack(q.h, self.ptr, self.nbytes))
+        fb, v = ct.c_size_t(), ct.c_int()
+        _check(L.oqp_pack_footprint(self.ptr, ct.byref(fb), ct.byref(v)))
+        self.footprint, self.variant = fb.value, v.value
+
+
+class Server:
+    """Continuous-batching server on the current device (oqp_server_*).
+
+    Streams are created here with the default priority; the server's host
+    memory is a pinned torch tensor, its device arena a byte tensor."""
+
+    def __init__(self, arg: Arg | None = None, dev_bytes: int = 1 << 30, nstreams: int = 8, device=None, **cfg):
+        import torch
+        L = lib()
+        self.arg = arg or default_arg()
+        c = ServerCfg()
+        L.oqp_server_cfg_default(ct.byref(c))
+        for k, v in cfg.items():
+            setattr(c, k, v)
+        self.cfg = c
+        hb, fb = ct.c_size_t(), ct.c_size_t()
+        _check(L.oqp_server_bytes(ct.byref(c), ct.byref(hb), ct.byref(fb)))
+        self.host_bytes = hb.value
+        self.dev_bytes = int(dev_bytes) + fb.value
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self._host = torch.empty(self.host_bytes + 64, dtype=torch.uint8, pin_memory=True)
+        hp = self._host.data_ptr() + ((-self._host.data_ptr()) % 64)
+        self._dev = torch.empty(self.dev_bytes + 256, dtype=torch.uint8, device=dev)
+        dp = self._dev.data_ptr() + ((-self._dev.data_ptr()) % 256)
+        self.streams = [torch.cuda.Stream(dev) for _ in range(nstreams)]
+        self._sh = (_V * nstreams)(*[st.cuda_stream for st in self.streams])
+        h = _V()
+        _check(L.oqp_server_init(ct.byref(c), ct.byref(self.arg), hp, self.host_bytes, dp, self.dev_bytes, self._sh,
+                                 nstreams, ct.byref(h)))
+        self.h = h
+        self._tickets = {}
+
+    def submit(self, packed: Packed):
+        """Ticket, or None when admission is refused (OQP_EBUSY)."""
+        t = ct.c_uint64()
+        rc = lib().oqp_server_submit(self.h, packed.ptr, ct.byref(t))
+        if rc == EBUSY:
+            return None
+        _check(rc)
+        self._tickets[t.value] = packed
+        return t.value
+
+    def progress(self) -> int:
+        n = ct.c_int()
+        _check(lib().oqp_server_progress(self.h, ct.byref(n)))
+        return n.value
+
+    def poll(self, ticket):
+        st = Stat()
+        rc = _check(lib().oqp_server_poll(self.h, ticket, ct.byref(st)))
+        return None if rc == PENDING else st
+
+    def latency(self, ticket) -> float:
+        v = ct.c_double()
+        _check(lib().oqp_server_latency(self.h, ticket, ct.byref(v)))
+        return v.value
+
+    def solution(self, ticket) -> dict:
+        v, sz = _sol_buffers(self._tickets[ticket].qp)
+        _check(lib().oqp_server_get_sol(self.h, ticket, *[_p(v[k]) for k in _KEYS]))
+        return {k: v[k][:sz[k]].copy() for k in _KEYS}
+
+    def result(self, ticket) -> Result:
+        st = self.poll(ticket)
+        return Result(st.status, st.iters, st.ir_steps, st.mu, np.array(st.res[:]), self.solution(ticket),
+                      st.fell_back_f64)
+
+    def release(self, ticket):
+        _check(lib().oqp_server_release(self.h, ticket))
+        self._tickets.pop(ticket, None)
+
+    def stats(self) -> dict:
+        c = Counters()
+        _check(lib().oqp_server_stats(self.h, ct.byref(c)))
+        return {k: getattr(c, k) for k, _ in Counters._fields_}
+
+    def replay(self, packed: Sequence[Packed], arrival, timeout: float = 60.0):
+        """Native real-time replay of an arrival schedule; returns
+        (latency seconds, per-request Stat list, wall seconds)."""
+        n = len(packed)
+        arr = np.ascontiguousarray(arrival, dtype=np.float64)
+        ptrs = (_V * n)(*[p.ptr for p in packed])
+        lat = np.zeros(max(n, 1))
+        stats = (Stat * max(n, 1))()
+        wall = ct.c_double()
+        _check(lib().oqp_server_replay(self.h, ptrs, _p(arr), n, ct.c_double(timeout), _p(lat), stats,
+                                       ct.byref(wall)))
+        return lat[:n], list(stats)[:n], wall.value
+
+    def close(self):
+        if self.h:
+            _check(lib().oqp_server_destroy(self.h))
+            self.h = None
+
+
 def variants():
     L = lib()
     out = []
@@ -303,5 +461,8 @@ EXPORTED = [
     "oqp_batch_bytes", "oqp_batch_init", "oqp_batch_load", "oqp_batch_solve", "oqp_batch_set_arg",
     "oqp_batch_fetch", "oqp_batch_sync", "oqp_batch_get_stat", "oqp_batch_get_sol", "oqp_batch_set_iterate",
     "oqp_batch_newton", "oqp_batch_get_step", "oqp_batch_variant", "oqp_variant_count", "oqp_variant_dims",
-    "oqp_last_error",
+    "oqp_last_error", "oqp_pack_bytes", "oqp_pack", "oqp_pack_footprint", "oqp_server_cfg_default",
+    "oqp_server_bytes", "oqp_server_init", "oqp_server_destroy", "oqp_server_submit", "oqp_server_progress",
+    "oqp_server_poll", "oqp_server_latency", "oqp_server_get_sol", "oqp_server_release", "oqp_server_stats",
+    "oqp_server_replay",
 ]

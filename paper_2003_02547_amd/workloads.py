@@ -272,17 +272,20 @@ def random_large_stage(i: int) -> OcpQp:
     return qp
 
 
-def serving_stream(rate: float, duration: float, seed: int = 4):
-    """Poisson arrival times (seconds) at `rate` per second over `duration`
-    and the instance index each arrival draws from the uneven distribution."""
-    rng = np.random.default_rng(seed)
+def serving_stream(rate: float, duration: float, pool: int, seed: int = 4):
+    """Poisson arrivals at `rate` per second over `duration` seconds
+    (exponential inter-arrival times) and, per arrival, the index of the
+    request it sends, drawn uniformly from a pool of `pool` pre-generated
+    instances of the uneven distribution."""
+    rng = np.random.default_rng(np.random.SeedSequence([4, seed]))
     t, times = 0.0, []
     while True:
         t += rng.exponential(1.0 / rate)
         if t >= duration:
             break
         times.append(t)
-    return np.asarray(times)
+    idx = rng.integers(0, pool, size=len(times))
+    return np.asarray(times), idx
 
 
 def random_tiny(rng: np.random.Generator, N: int, nx_range=(1, 4), nu_range=(0, 3),
