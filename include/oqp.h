@@ -131,8 +131,8 @@ void oqp_arg_default(oqp_arg* arg, int mode);
 
 /* ---- batch solve on the GPU ---------------------------------------------- */
 /* Sizes of the host and device buffers for a batch of `count` instances with
- * the given dims.  Each instance is assigned to a compiled kernel variant
- * whose stage sizes cover it; OQP_EINVAL if none does. */
+ * the given dims.  Each instance is assigned a kernel (see oqp_set_wave_max);
+ * OQP_EINVAL if none covers it. */
 int oqp_batch_bytes(const oqp_dims* const* dims, int count, const oqp_arg* arg, size_t* host_bytes,
                     size_t* dev_bytes);
 /* Create a batch in caller memory: host_mem (host_bytes, 16-byte aligned),
@@ -145,7 +145,9 @@ int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_arg* arg, v
  * enqueue the host-to-device copy.  Asynchronous on the batch stream; the host
  * buffer must stay untouched until oqp_batch_sync. */
 int oqp_batch_load(oqp_batch* batch, const oqp_qp* const* qps);
-/* Enqueue the IPM for every instance (one launch per kernel variant). */
+/* Enqueue the IPM for every instance (one launch per kernel group present;
+ * the block kernel solves its instances of all sizes in one launch, largest
+ * first). */
 int oqp_batch_solve(oqp_batch* batch);
 /* Replace the arguments used by later solves (mode must not change). */
 int oqp_batch_set_arg(oqp_batch* batch, const oqp_arg* arg);
@@ -256,10 +258,20 @@ int oqp_server_stats(const oqp_server* server, oqp_server_counters* stats);
 int oqp_server_replay(oqp_server* server, const void* const* packed, const double* arrival, int count,
                       double timeout_s, double* latency, oqp_stat* stat, double* wall_s);
 
-/* ---- introspection -------------------------------------------------------- */
-/* Kernel variant assigned to instance i and its padded stage sizes. */
+/* ---- kernels and introspection ---------------------------------------------- */
+/* Two kernel families solve an instance: one-wave kernels compiled for fixed
+ * padded stage sizes (the "variants"), and a 256-thread block kernel with
+ * runtime stage sizes (stage blocks nu + nx up to 64, up to 64 general rows per
+ * stage).  An instance goes to the cheapest covering variant when that
+ * variant's stage block nx_pad + nu_pad is at most the wave bound, else to the
+ * block kernel, padded only to its own largest stage.  The bound is process
+ * wide and applies to batches and packed requests created after the call. */
+int oqp_set_wave_max(int nz); /* 0..64; 0 sends every instance to the block kernel */
+int oqp_get_wave_max(void);
+/* Kernel group of instance i (a variant index < oqp_variant_count(), or a
+ * block-kernel build at or above it) and its padded stage sizes. */
 int oqp_batch_variant(const oqp_batch* batch, int i, int* nx_pad, int* nu_pad, int* ng_pad);
-/* Number of compiled kernel variants and the stage sizes of variant v. */
+/* Number of compiled one-wave variants and the stage sizes of variant v. */
 int oqp_variant_count(void);
 int oqp_variant_dims(int v, int* nx_pad, int* nu_pad, int* ng_pad);
 /* Message for the last failing call on this thread. */

@@ -110,6 +110,8 @@ def lib():
         "oqp_server_release": (ct.c_int, [_V, ct.c_uint64]),
         "oqp_server_stats": (ct.c_int, [_V, ct.POINTER(Counters)]),
         "oqp_server_replay": (ct.c_int, [_V, ct.POINTER(_V), _P, ct.c_int, ct.c_double, _P, ct.POINTER(Stat), _P]),
+        "oqp_set_wave_max": (ct.c_int, [ct.c_int]),
+        "oqp_get_wave_max": (ct.c_int, []),
         "oqp_variant_count": (ct.c_int, []),
         "oqp_variant_dims": (ct.c_int, [ct.c_int, _PI, _PI, _PI]),
         "oqp_last_error": (ct.c_char_p, []),
@@ -445,6 +447,15 @@ class Server:
             self.h = None
 
 
+def set_wave_max(nz: int) -> int:
+    """Largest stage block (nx + nu, padded) solved by the one-wave kernels;
+    larger instances go to the block kernel.  Returns the previous bound."""
+    L = lib()
+    old = L.oqp_get_wave_max()
+    _check(L.oqp_set_wave_max(int(nz)))
+    return old
+
+
 def variants():
     L = lib()
     out = []
@@ -464,5 +475,5 @@ EXPORTED = [
     "oqp_last_error", "oqp_pack_bytes", "oqp_pack", "oqp_pack_footprint", "oqp_server_cfg_default",
     "oqp_server_bytes", "oqp_server_init", "oqp_server_destroy", "oqp_server_submit", "oqp_server_progress",
     "oqp_server_poll", "oqp_server_latency", "oqp_server_get_sol", "oqp_server_release", "oqp_server_stats",
-    "oqp_server_replay",
+    "oqp_server_replay", "oqp_set_wave_max", "oqp_get_wave_max",
 ]

@@ -3,6 +3,7 @@
 // variant on the caller's stream.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -305,7 +306,8 @@ int check_arg(const oqp_arg* a)
 // ---------------------------------------------------------------------------
 
 struct Inst {
-    int variant;
+    int variant;    // kernel group (see select_kernel)
+    int nx, nu, ng; // padded stage sizes of the device records
     int N;
     int nc;
     int dims_off;   // into dims pool: 5 * (N+1) ints (nx, nu, nbu, nbx, ng)
@@ -369,6 +371,75 @@ int pick_variant(const oqp_dims* d)
     return best;
 }
 
+// Kernel groups: 0..variant_count()-1 are the one-wave variants; the block
+// kernel builds follow (stage-block bound 32 or 64, without or with general
+// rows).  One-wave variants are used up to a stage block of g_wave_max_nz,
+// larger instances go to the block kernel, padded only to their own maximum
+// stage sizes.
+static int g_wave_max_nz = 24;
+static const int kBlockZ[4] = {32, 32, 64, 64};
+static const int kBlockG[4] = {0, 64, 0, 64};
+static constexpr size_t kMaxLds = 160 * 1024;
+
+int group_count() { return oqp::variant_count() + 4; }
+
+int select_kernel(const oqp_dims* d, KSel* out)
+{
+    int mx = 0, mu = 0, mg = 0;
+    for (int n = 0; n <= d->N; ++n) {
+        if (d->nx[n] > mx) mx = d->nx[n];
+        if (d->nu[n] > mu) mu = d->nu[n];
+        if (d->ng[n] > mg) mg = d->ng[n];
+    }
+    const int v = pick_variant(d);
+    if (v >= 0) {
+        int nx, nu, ng;
+        oqp::variant_dims(v, &nx, &nu, &ng);
+        if (nx + nu <= g_wave_max_nz) {
+            *out = KSel{v, nx, nu, ng};
+            return OQP_OK;
+        }
+    }
+    if (mx < 1) mx = 1;
+    const int zm = oqp::block_zmax(mx + mu);
+    if (zm == 0 || mg > 64) return -1;
+    if ((size_t)oqp::block_lds_bytes(mx, mu, mg) > kMaxLds) return -1;
+    const int b = (zm == 64 ? 2 : 0) + (mg > 0 ? 1 : 0);
+    *out = KSel{oqp::variant_count() + b, mx, mu, mg};
+    return OQP_OK;
+}
+
+extern "C" int oqp_set_wave_max(int nz)
+{
+    if (nz < 0 || nz > 64) return fail(OQP_EINVAL, "oqp_set_wave_max: stage block bound must be in [0, 64]");
+    g_wave_max_nz = nz;
+    return OQP_OK;
+}
+
+extern "C" int oqp_get_wave_max(void) { return g_wave_max_nz; }
+
+// Launch the instances [desc, desc + count) of kernel group g.
+int group_launch(int g, int mixed, const InstDesc* desc, const InstDesc* hdesc, int count, const double* data,
+                 double* iter, double* work, double* step, DevStat* stat, const oqp::KParams& P, void* stream)
+{
+    const int nv = oqp::variant_count();
+    if (g < nv) return oqp::variant_launch(g, mixed, desc, count, data, iter, work, step, stat, P, stream);
+    size_t lds = 0;
+    for (int i = 0; i < count; ++i) {
+        const size_t b = (size_t)oqp::block_lds_bytes(hdesc[i].nx, hdesc[i].nu, hdesc[i].ng);
+        if (b > lds) lds = b;
+    }
+    return oqp::block_launch(kBlockZ[g - nv], kBlockG[g - nv], mixed, desc, count, data, iter, work, step, stat, P,
+                             lds, stream);
+}
+
+// relative cost of an instance, for ordering a launch largest first
+double inst_cost(int N, int nx, int nu)
+{
+    const double nz = nx + nu;
+    return (N + 1.0) * nz * nz * (nx + nz);
+}
+
 struct Plan {
     size_t host_bytes, dev_bytes;
     // host offsets
@@ -382,17 +453,15 @@ struct Plan {
 static int make_plan(const oqp_dims* const* dims, int count, Plan* pl)
 {
     if (!dims || count < 1) return fail(OQP_EINVAL, "batch: count must be >= 1");
-    const int nv = oqp::variant_count();
+    const int nv = group_count();
     int64_t nd = 0, ni = 0, nw = 0;
     int ndims = 0, nslot = 0;
     for (int i = 0; i < count; ++i) {
         const oqp_dims* d = dims[i];
         if (!d) return fail(OQP_EINVAL, "batch: dims[%d] is NULL", i);
-        int v = pick_variant(d);
-        if (v < 0) return fail(OQP_EINVAL, "batch: no kernel variant covers the stage sizes of instance %d", i);
-        int nx, nu, ng;
-        oqp::variant_dims(v, &nx, &nu, &ng);
-        const Layout L = oqp::make_layout(nx, nu, ng);
+        KSel ks;
+        if (select_kernel(d, &ks)) return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d", i);
+        const Layout L = oqp::make_layout(ks.nx, ks.nu, ks.ng);
         nd += (int64_t)(d->N + 1) * L.SREC;
         ni += (int64_t)(d->N + 1) * L.IREC;
         nw += (int64_t)(d->N + 1) * L.WREC;
@@ -438,12 +507,7 @@ extern "C" int oqp_batch_bytes(const oqp_dims* const* dims, int count, const oqp
     return OQP_OK;
 }
 
-static const Layout inst_layout(const Inst& in)
-{
-    int nx, nu, ng;
-    oqp::variant_dims(in.variant, &nx, &nu, &ng);
-    return oqp::make_layout(nx, nu, ng);
-}
+static const Layout inst_layout(const Inst& in) { return oqp::make_layout(in.nx, in.nu, in.ng); }
 
 extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_arg* arg, void* host_mem,
                               size_t host_bytes, void* dev_mem, size_t dev_bytes, void* stream, oqp_batch** out)
@@ -463,7 +527,7 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
     oqp_batch* b = (oqp_batch*)h;
     std::memset(b, 0, sizeof(*b));
     b->count = count;
-    b->nvar = oqp::variant_count();
+    b->nvar = group_count();
     b->arg = *arg;
     b->stream = stream;
     b->inst = (Inst*)(h + pl.h_inst);
@@ -491,7 +555,12 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
     for (int i = 0; i < count; ++i) {
         Inst& in = b->inst[i];
         const oqp_dims* d = dims[i];
-        in.variant = pick_variant(d);
+        KSel ks;
+        select_kernel(d, &ks);
+        in.variant = ks.group;
+        in.nx = ks.nx;
+        in.nu = ks.nu;
+        in.ng = ks.ng;
         in.N = d->N;
         in.dims_off = doff;
         in.slot_off = soff;
@@ -514,14 +583,21 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
         b->vstart[v] = acc;
         acc += b->vcount[v];
     }
-    // region offsets in variant order
+    // region offsets in group order; within a group, largest instances first
     int64_t od = 0, oi = 0, ow = 0;
-    int fill[64];
-    for (int v = 0; v < b->nvar && v < 64; ++v) fill[v] = 0;
+    int* order = (int*)b->hstat;  // count ints of scratch: the status block is only filled by a fetch
     for (int v = 0; v < b->nvar; ++v) {
-        for (int i = 0; i < count; ++i) {
+        int k = 0;
+        for (int i = 0; i < count; ++i)
+            if (b->inst[i].variant == v) order[k++] = i;
+        std::stable_sort(order, order + k, [&](int x, int y) {
+            const Inst& a = b->inst[x];
+            const Inst& c = b->inst[y];
+            return inst_cost(a.N, a.nx, a.nu) > inst_cost(c.N, c.nx, c.nu);
+        });
+        for (int q = 0; q < k; ++q) {
+            const int i = order[q];
             Inst& in = b->inst[i];
-            if (in.variant != v) continue;
             const Layout L = inst_layout(in);
             in.data = od;
             in.iter = oi;
@@ -529,7 +605,7 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
             od += (int64_t)(in.N + 1) * L.SREC;
             oi += (int64_t)(in.N + 1) * L.IREC;
             ow += (int64_t)(in.N + 1) * L.WREC;
-            InstDesc& ds = b->hdesc[b->vstart[v] + fill[v]++];
+            InstDesc& ds = b->hdesc[b->vstart[v] + q];
             ds.data = in.data;
             ds.iter = in.iter;
             ds.work = in.work;
@@ -537,6 +613,10 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
             ds.nc = in.nc;
             ds.index = i;
             ds.pad = 0;
+            ds.nx = in.nx;
+            ds.nu = in.nu;
+            ds.ng = in.ng;
+            ds.pad2 = 0;
         }
     }
     hipError_t e = hipMemcpyAsync(b->ddesc, b->hdesc, sizeof(InstDesc) * count, hipMemcpyHostToDevice,
@@ -551,7 +631,6 @@ static inline const int* inst_dims(const oqp_batch* b, const Inst& in, int which
     return b->dims_pool + in.dims_off + which * (in.N + 1);
 }
 
-// Pack instance i's QP into its padded stage records.
 // Pack a QP into N+1 padded stage records (L.SREC doubles each) at dst and
 // fill the map from user constraint order to padded slot (nc entries).
 int pack_records(const oqp_qp* q, const Layout& L, double* dst, int* slots)
@@ -699,21 +778,20 @@ oqp::KParams make_params(const oqp_arg& a, int mode, double tau)
 static int launch_all(oqp_batch* b, const oqp::KParams& P)
 {
     const int mixed = b->arg.mode == OQP_MODE_MIXED;
-    for (int v = 0; v < b->nvar; ++v) {
-        if (b->vcount[v] == 0) continue;
-        int rc = oqp::variant_launch(v, mixed, b->ddesc + b->vstart[v], b->vcount[v], b->ddata, b->diter, b->dwork,
-                                     b->dstep, b->dstat, P, b->stream);
-        if (rc) return fail(OQP_EDEVICE, "kernel launch failed for variant %d", v);
-    }
-    if (mixed && P.mode == oqp::KMODE_SOLVE) {
-        // FP64 kernels pick up the instances the mixed kernels handed over
-        oqp::KParams Pf = P;
-        Pf.mode = oqp::KMODE_FALLBACK;
-        for (int v = 0; v < b->nvar; ++v) {
+    // block-kernel groups first: they hold the largest instances
+    for (int pass = 0; pass < 2; ++pass) {
+        oqp::KParams Pp = P;
+        if (pass == 1) {
+            if (!(mixed && P.mode == oqp::KMODE_SOLVE)) break;
+            // FP64 kernels pick up the instances the mixed kernels handed over
+            Pp.mode = oqp::KMODE_FALLBACK;
+        }
+        for (int k = 0; k < b->nvar; ++k) {
+            const int v = b->nvar - 1 - k;
             if (b->vcount[v] == 0) continue;
-            int rc = oqp::variant_launch(v, 0, b->ddesc + b->vstart[v], b->vcount[v], b->ddata, b->diter, b->dwork,
-                                         b->dstep, b->dstat, Pf, b->stream);
-            if (rc) return fail(OQP_EDEVICE, "fallback launch failed for variant %d", v);
+            int rc = group_launch(v, pass == 0 ? mixed : 0, b->ddesc + b->vstart[v], b->hdesc + b->vstart[v],
+                                  b->vcount[v], b->ddata, b->diter, b->dwork, b->dstep, b->dstat, Pp, b->stream);
+            if (rc) return fail(OQP_EDEVICE, "kernel launch failed for group %d", v);
         }
     }
     return OQP_OK;
@@ -870,13 +948,11 @@ extern "C" int oqp_batch_get_step(const oqp_batch* b, int i, double* du, double*
 extern "C" int oqp_batch_variant(const oqp_batch* b, int i, int* nx, int* nu, int* ng)
 {
     if (!b || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_variant: bad argument");
-    int v = b->inst[i].variant;
-    int a, c, d;
-    oqp::variant_dims(v, &a, &c, &d);
-    if (nx) *nx = a;
-    if (nu) *nu = c;
-    if (ng) *ng = d;
-    return v;
+    const Inst& in = b->inst[i];
+    if (nx) *nx = in.nx;
+    if (nu) *nu = in.nu;
+    if (ng) *ng = in.ng;
+    return in.variant;
 }
 
 extern "C" int oqp_variant_count(void) { return oqp::variant_count(); }

@@ -32,7 +32,24 @@ int variant_count();
 void variant_dims(int v, int* nx, int* nu, int* ng);
 int variant_launch(int v, int mixed, const InstDesc* desc, int count, const double* data, double* iter, double* work,
                    double* step, DevStat* stat, const KParams& P, void* stream);
+int block_lds_bytes(int nx, int nu, int ng);
+int block_zmax(int nz);
+int block_launch(int zm, int gm, int mixed, const InstDesc* desc, int count, const double* data, double* iter,
+                 double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
 }  // namespace oqp
+
+// Kernel chosen for an instance: group (a one-wave variant index, or a block
+// kernel build after them) and the padded stage sizes of its device records.
+struct KSel {
+    int group;
+    int nx, nu, ng;
+};
+int group_count();
+int select_kernel(const oqp_dims* d, KSel* out);
+int group_launch(int g, int mixed, const oqp::InstDesc* desc, const oqp::InstDesc* hdesc, int count,
+                 const double* data, double* iter, double* work, double* step, oqp::DevStat* stat,
+                 const oqp::KParams& P, void* stream);
+double inst_cost(int N, int nx, int nu);
 
 int fail(int code, const char* fmt, ...);
 size_t align_up(size_t v, size_t a);

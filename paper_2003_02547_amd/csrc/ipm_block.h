@@ -1,0 +1,1316 @@
+// Block kernel of the batched OCP-QP interior-point method: one 256-thread
+// workgroup (four waves) per instance, for stage blocks too large for the
+// one-wave kernel to hold in registers.
+//
+// The method, passes and Riccati equations are those of the one-wave kernel
+// (square-root Riccati recursion of Section 3.3 on the reduced system
+// eq:alg:kkt, Mehrotra predictor-corrector of Section 4.2, FP64 iterative
+// refinement of Section 3.4 in the mixed path), with the same device record
+// layout, so the two kernels are interchangeable per instance.  What differs
+// is the mapping onto the hardware:
+//   * stage sizes are runtime values read from the instance descriptor, so
+//     one launch solves instances of different sizes (the host orders them
+//     by estimated cost, largest first);
+//   * the stage matrices of the sweep go through registers spread over all
+//     256 threads, prefetched one stage ahead, and are staged in LDS;
+//   * the products U = L_{n+1}' [B A] and M += V'V run on all four waves with
+//     4 x 4 register tiles; row-wise work (residual rows, constraint slots)
+//     takes one thread per row or slot;
+//   * the Cholesky factorization and the triangular solves run on wave 0
+//     with one row per lane (rows of the factor held in registers up to the
+//     compile-time bound ZM on the stage block).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "dev_common.h"
+#include "layout.h"
+
+namespace oqp {
+
+constexpr int BT = 256;    // threads per instance
+constexpr int BGMAX = 64;  // general rows per stage supported by the block kernel
+
+// LDS plan (offsets in doubles) for padded stage sizes NX, NU, NG.
+struct BLds {
+    int ldm, ldf, ldg, ldx, ldv;  // odd leading dimensions: column-strided access spreads over the banks
+    int oM, oF, oG, oLx, oV, oz, orb, ot1, ot2, oe, ows, oxn, opin, opn, odv, ocol, ored, oflag, total;
+};
+
+OQP_HD constexpr int bmaxi(int a, int b) { return a > b ? a : b; }
+
+OQP_HD constexpr BLds make_blds(int NX, int NU, int NG)
+{
+    const int NZ = NX + NU, NC = NZ + NG, NV = NX + NG;
+    BLds s{};
+    s.ldm = NZ | 1;
+    s.ldf = NX | 1;
+    s.ldg = NG | 1;
+    s.ldx = NX | 1;
+    s.ldv = NV | 1;
+    int o = 0;
+    s.oM = o; o += s.ldm * NZ;                       // H / stage matrix / factor; factor columns in the forward sweeps
+    s.oF = o; o += s.ldf * NZ;                       // [B A]
+    s.oG = o; o += NG > 0 ? s.ldg * NZ : 0;          // G
+    s.oLx = o; o += s.ldx * NX;                      // L_{n+1} (lower, zero strict upper)
+    s.oV = o; o += s.ldv * NZ;                       // [U; sqrt(w) G]
+    s.oz = o; o += NZ;
+    s.orb = o; o += bmaxi(NX, 1);
+    s.ot1 = o; o += bmaxi(bmaxi(NX, NG), 1);
+    s.ot2 = o; o += bmaxi(NX, 1);
+    s.oe = o; o += NC;
+    s.ows = o; o += NC;
+    s.oxn = o; o += 2 * bmaxi(NX, 1);
+    s.opin = o; o += 2 * bmaxi(NX, 1);
+    s.opn = o; o += 2 * bmaxi(NX, 1);
+    s.odv = o; o += NZ;
+    s.ocol = o; o += 64;
+    s.ored = o; o += 32;
+    s.oflag = o; o += 2;
+    s.total = o;
+    return s;
+}
+
+// Position (row r, column c) of element e = start + BT t of a column-major
+// block with R rows, advanced without a division per element.
+struct Walk {
+    int r, c, sr, sc, R;
+    __device__ __forceinline__ Walk(int R_, int start) : R(R_)
+    {
+        const int q = R_ > 0 ? R_ : 1;
+        r = start % q;
+        c = start / q;
+        sr = BT % q;
+        sc = BT / q;
+    }
+    __device__ __forceinline__ void next()
+    {
+        r += sr;
+        c += sc;
+        if (r >= R) {
+            r -= R;
+            ++c;
+        }
+    }
+};
+
+__device__ __forceinline__ double* blds()
+{
+    extern __shared__ double oqp_blds_dyn[];
+    return oqp_blds_dyn;
+}
+
+template <bool MIXED, int ZM, int GM>
+struct Blk {
+    using TS = typename std::conditional<MIXED, float, double>::type;
+    Layout Lo;
+    BLds S;
+    int NX, NU, NG, NZ, NC, NV;
+    const double* __restrict__ dat;
+    double* __restrict__ itr;
+    double* __restrict__ wk;
+    int N, nc, tid, lane, wid;
+    const KParams& P;
+
+    __device__ __forceinline__ Blk(const InstDesc& ds, const double* d, double* i, double* w, const KParams& P_)
+        : Lo(make_layout(ds.nx, ds.nu, ds.ng)), S(make_blds(ds.nx, ds.nu, ds.ng)), NX(ds.nx), NU(ds.nu), NG(ds.ng),
+          NZ(ds.nx + ds.nu), NC(ds.nx + ds.nu + ds.ng), NV(ds.nx + ds.ng), dat(d + ds.data), itr(i + ds.iter),
+          wk(w + ds.work), N(ds.N), nc(ds.nc), tid((int)threadIdx.x), lane((int)threadIdx.x & 63),
+          wid((int)threadIdx.x >> 6), P(P_)
+    {
+    }
+
+    __device__ __forceinline__ const double* Dp(int n) const { return dat + (size_t)n * Lo.SREC; }
+    __device__ __forceinline__ double* Ip(int n) const { return itr + (size_t)n * Lo.IREC; }
+    __device__ __forceinline__ double* Wp(int n) const { return wk + (size_t)n * Lo.WREC; }
+
+    // LDS arrays
+    __device__ __forceinline__ double* M() const { return blds() + S.oM; }
+    __device__ __forceinline__ double* F() const { return blds() + S.oF; }
+    __device__ __forceinline__ double* G() const { return blds() + S.oG; }
+    __device__ __forceinline__ double* Lx() const { return blds() + S.oLx; }
+    __device__ __forceinline__ double* V() const { return blds() + S.oV; }
+    __device__ __forceinline__ double* z() const { return blds() + S.oz; }
+    __device__ __forceinline__ double* rbv() const { return blds() + S.orb; }
+    __device__ __forceinline__ double* t1() const { return blds() + S.ot1; }
+    __device__ __forceinline__ double* t2() const { return blds() + S.ot2; }
+    __device__ __forceinline__ double* ev() const { return blds() + S.oe; }
+    __device__ __forceinline__ double* wsv() const { return blds() + S.ows; }
+    __device__ __forceinline__ double* xn(int p) const { return blds() + S.oxn + p * (NX > 0 ? NX : 1); }
+    __device__ __forceinline__ double* pin(int p) const { return blds() + S.opin + p * (NX > 0 ? NX : 1); }
+    __device__ __forceinline__ double* pn(int p) const { return blds() + S.opn + p * (NX > 0 ? NX : 1); }
+    __device__ __forceinline__ double* dv() const { return blds() + S.odv; }
+    __device__ __forceinline__ double* col() const { return blds() + S.ocol; }
+    __device__ __forceinline__ double* red() const { return blds() + S.ored; }
+    __device__ __forceinline__ double* flag() const { return blds() + S.oflag; }
+
+    __device__ __forceinline__ static double rnd(double x) { return (double)(TS)x; }
+
+    // Thread index re-materialised inside a loop body: the empty volatile asm
+    // keeps the compiler from hoisting per-thread address arithmetic of every
+    // pass to the top of the kernel, where it would stay live (and occupy
+    // registers) for the whole solve.
+    __device__ __forceinline__ static int opq(int v)
+    {
+        asm volatile("" : "+v"(v));
+        return v;
+    }
+
+    // sum_{k < n} a[k sa] b[k sb] in type T with four independent partial
+    // sums, so that several LDS reads are in flight at once
+    template <typename T>
+    __device__ __forceinline__ static T dot(const double* a, int sa, const double* b, int sb, int n)
+    {
+        T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        int k = 0;
+#pragma unroll 2
+        for (; k + 4 <= n; k += 4) {
+            const double a0 = a[k * sa], a1 = a[(k + 1) * sa], a2 = a[(k + 2) * sa], a3 = a[(k + 3) * sa];
+            const double b0 = b[k * sb], b1 = b[(k + 1) * sb], b2 = b[(k + 2) * sb], b3 = b[(k + 3) * sb];
+            s0 += (T)a0 * (T)b0;
+            s1 += (T)a1 * (T)b1;
+            s2 += (T)a2 * (T)b2;
+            s3 += (T)a3 * (T)b3;
+        }
+        for (; k < n; ++k) s0 += (T)a[k * sa] * (T)b[k * sb];
+        return (s0 + s1) + (s2 + s3);
+    }
+
+    // ------------------------------------------------------------------
+    // block reductions (fixed combination order: identical in every thread)
+    // ------------------------------------------------------------------
+    __device__ __forceinline__ void reduce4(double& a, double& b, double& c, double& d, double& e) const
+    {
+        a = wave_max(a);
+        b = wave_max(b);
+        c = wave_max(c);
+        d = wave_max(d);
+        e = wave_sum(e);
+        double* r = red();
+        __syncthreads();
+        if (lane == 0) {
+            r[wid * 5 + 0] = a;
+            r[wid * 5 + 1] = b;
+            r[wid * 5 + 2] = c;
+            r[wid * 5 + 3] = d;
+            r[wid * 5 + 4] = e;
+        }
+        __syncthreads();
+        a = nmax(nmax(r[0], r[5]), nmax(r[10], r[15]));
+        b = nmax(nmax(r[1], r[6]), nmax(r[11], r[16]));
+        c = nmax(nmax(r[2], r[7]), nmax(r[12], r[17]));
+        d = nmax(nmax(r[3], r[8]), nmax(r[13], r[18]));
+        e = (r[4] + r[9]) + (r[14] + r[19]);
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ double bmin_sum2(double amin, double& s1, double& s2) const
+    {
+        amin = wave_min(amin);
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        double* r = red();
+        __syncthreads();
+        if (lane == 0) {
+            r[wid * 3 + 0] = amin;
+            r[wid * 3 + 1] = s1;
+            r[wid * 3 + 2] = s2;
+        }
+        __syncthreads();
+        amin = fmin(fmin(r[0], r[3]), fmin(r[6], r[9]));
+        s1 = (r[1] + r[4]) + (r[7] + r[10]);
+        s2 = (r[2] + r[5]) + (r[8] + r[11]);
+        __syncthreads();
+        return amin;
+    }
+
+    __device__ __forceinline__ double bmax1(double v) const
+    {
+        v = wave_max(v);
+        double* r = red();
+        __syncthreads();
+        if (lane == 0) r[wid] = v;
+        __syncthreads();
+        v = nmax(nmax(r[0], r[1]), nmax(r[2], r[3]));
+        __syncthreads();
+        return v;
+    }
+
+    // ------------------------------------------------------------------
+    // stage prefetch: three flat blocks of global memory (element e = tid +
+    // BT t of each) into registers, committed to LDS at the next stage
+    // ------------------------------------------------------------------
+    static constexpr int EA = (ZM * ZM + BT - 1) / BT;           // H, or the factor columns
+    static constexpr int EF = (ZM * ZM + BT - 1) / BT;           // F
+    static constexpr int EG = GM > 0 ? (GM * ZM + BT - 1) / BT : 1;
+
+    struct Pre {
+        double a[EA], f[EF], g[EG];
+        const double* sa;   // block a (or, for the factor columns, its first part)
+        const double* sa2;  // second part of block a from element na1 on
+        const double* sf;
+        const double* sg;
+        int na1, na, nf, ng;
+    };
+
+    __device__ __forceinline__ void fetch(Pre& p) const
+    {
+#pragma unroll
+        for (int t = 0; t < EA; ++t) {
+            const int e = tid + BT * t;
+            const double* src = e < p.na1 ? p.sa : p.sa2;
+            p.a[t] = e < p.na ? src[e] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < EF; ++t) {
+            const int e = tid + BT * t;
+            p.f[t] = e < p.nf ? p.sf[e] : 0.0;
+        }
+        if constexpr (GM > 0) {
+#pragma unroll
+            for (int t = 0; t < EG; ++t) {
+                const int e = tid + BT * t;
+                p.g[t] = e < p.ng ? p.sg[e] : 0.0;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void commit(const Pre& p, double* da, double* df, double* dg) const
+    {
+        {
+            Walk q(NZ, tid);
+#pragma unroll
+            for (int t = 0; t < EA; ++t) {
+                const int e = tid + BT * t;
+                if (e < p.na) da[q.r + q.c * S.ldm] = p.a[t];
+                q.next();
+            }
+        }
+        {
+            Walk q(NX, tid);
+#pragma unroll
+            for (int t = 0; t < EF; ++t) {
+                const int e = tid + BT * t;
+                if (e < p.nf) df[q.r + q.c * S.ldf] = p.f[t];
+                q.next();
+            }
+        }
+        if constexpr (GM > 0) {
+            Walk q(NG, tid);
+#pragma unroll
+            for (int t = 0; t < EG; ++t) {
+                const int e = tid + BT * t;
+                if (e < p.ng) dg[q.r + q.c * S.ldg] = p.g[t];
+                q.next();
+            }
+        }
+    }
+
+    // H, F, G of stage n (passes A and R)
+    __device__ __forceinline__ void seg_hfg(Pre& p, int n) const
+    {
+        const double* d = Dp(n);
+        p.sa = p.sa2 = d + Lo.D_H;
+        p.na1 = p.na = NZ * NZ;
+        p.sf = d + Lo.D_F;
+        p.nf = n < N ? NX * NZ : 0;
+        p.sg = d + Lo.D_G;
+        p.ng = NG * NZ;
+    }
+
+    // factor columns (u-columns of stage n, x-columns of stage n + 1, both
+    // in the NZ x NZ column-major factor layout), F and G of stage n
+    // (passes B and C)
+    __device__ __forceinline__ void seg_lfg(Pre& p, int n) const
+    {
+        const double* d = Dp(n);
+        p.sa = Wp(n) + Lo.W_L;
+        p.sa2 = n < N ? Wp(n + 1) + Lo.W_L : p.sa;
+        p.na1 = NZ * NU;
+        p.na = n < N ? NZ * NZ : NZ * NU;
+        p.sf = d + Lo.D_F;
+        p.nf = n < N ? NX * NZ : 0;
+        p.sg = d + Lo.D_G;
+        p.ng = NG * NZ;
+    }
+
+    // constraint slot data: mask, lower, upper (slot c: box on z_c for c <
+    // NZ, general row c - NZ otherwise)
+    __device__ __forceinline__ void slot_bounds(const double* d, int c, double& m, double& lo, double& hi) const
+    {
+        if (c < NZ) {
+            m = d[Lo.D_bm + c];
+            lo = d[Lo.D_blo + c];
+            hi = d[Lo.D_bhi + c];
+        } else if (c < NC) {
+            m = d[Lo.D_gm + (c - NZ)];
+            lo = d[Lo.D_glo + (c - NZ)];
+            hi = d[Lo.D_ghi + (c - NZ)];
+        } else {
+            m = lo = hi = 0.0;
+        }
+    }
+
+    // ------------------------------------------------------------------
+    // dense kernels on LDS blocks
+    // ------------------------------------------------------------------
+
+    // V[i][k] = sum_l Lx[l][i] F[l][k] (i < NX, k < NZ); Lx lower with zero
+    // strict upper part.  4 x 4 output tiles, one per thread.
+    __device__ __forceinline__ void trmm_LtF() const
+    {
+        const int TI = (NX + 3) >> 2, TK = (NZ + 3) >> 2;
+        const double* L = Lx();
+        const double* f = F();
+        double* v = V();
+        for (int t = opq(tid); t < TI * TK; t += BT) {
+            const int i0 = 4 * (t % TI), k0 = 4 * (t / TI);
+            int ic[4], kc[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                ic[p] = min(i0 + p, NX - 1);
+                kc[p] = min(k0 + p, NZ - 1);
+            }
+            TS acc[4][4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] = 0;
+#pragma unroll 2
+            for (int l = i0; l < NX; ++l) {
+                TS lv[4], fv[4];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) lv[p] = (TS)L[l + ic[p] * S.ldx];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fv[q] = (TS)f[l + kc[q] * S.ldf];
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[p][q] += lv[p] * fv[q];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (i0 + p < NX && k0 + q < NZ) v[(i0 + p) + (k0 + q) * S.ldv] = (double)acc[p][q];
+        }
+    }
+
+    // M[i][k] += sum_{r0 <= r < NV} V[r][i] V[r][k] on the lower triangle
+    // (tiles on and below the diagonal)
+    __device__ __forceinline__ void syrk_VtV(int r0) const
+    {
+        const int TZ = (NZ + 3) >> 2;
+        const double* v = V();
+        double* m = M();
+        for (int t = opq(tid); t < TZ * TZ; t += BT) {
+            const int ti = t % TZ, tk = t / TZ;
+            if (ti < tk) continue;
+            const int i0 = 4 * ti, k0 = 4 * tk;
+            int ic[4], kc[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                ic[p] = min(i0 + p, NZ - 1);
+                kc[p] = min(k0 + p, NZ - 1);
+            }
+            TS acc[4][4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[p][q] = 0;
+#pragma unroll 2
+            for (int r = r0; r < NV; ++r) {
+                TS vi[4], vk[4];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) vi[p] = (TS)v[r + ic[p] * S.ldv];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) vk[q] = (TS)v[r + kc[q] * S.ldv];
+#pragma unroll
+                for (int p = 0; p < 4; ++p)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[p][q] += vi[p] * vk[q];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (i0 + p < NZ && k0 + q < NZ) m[(i0 + p) + (k0 + q) * S.ldm] += (double)acc[p][q];
+        }
+    }
+
+    // Blocked right-looking Cholesky of M (NZ x NZ <= 64 x 64, lower triangle
+    // read), panels of PW columns: wave 0 factors a panel with one row per
+    // lane (panel rows in registers), then all four waves apply the panel to
+    // the trailing lower triangle with 4 x 4 register tiles.  Writes L back
+    // into M (each panel write-back zeroes the rows above the diagonal of its
+    // columns) and 1/L_ii into dv.  Every thread calls
+    // it; returns false (in every thread) when a pivot is not positive.
+    // Mixed path: FP32 entries and updates, each row's diagonal accumulated
+    // in FP64 (FP64 pivots).
+    static constexpr int PW = 16;
+
+    __device__ __forceinline__ bool cholesky() const
+    {
+        double* m = M();
+        double dd = 0.0;  // wave 0: FP64 running diagonal of row `lane` (mixed path)
+        bool ok = true;
+        if (wid == 0 && MIXED) dd = lane < NZ ? m[lane + lane * S.ldm] : 1.0;
+        for (int p0 = 0; p0 < NZ; p0 += PW) {
+            const int pw = min(PW, NZ - p0);
+            if (wid == 0) {
+                double r[PW];
+#pragma unroll
+                for (int q = 0; q < PW; ++q) {
+                    r[q] = (lane >= p0 && lane < NZ && q < pw) ? m[lane + (p0 + q) * S.ldm] : 0.0;
+                    if constexpr (MIXED) r[q] = rnd(r[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < PW; ++q) {
+                    if (q >= pw) continue;
+                    const int j = p0 + q;
+                    const double piv = MIXED ? bcast(dd, j) : bcast(r[q], j);
+                    ok = ok && (piv > 0.0);
+                    const double inv = rsqrt_nr(piv);
+                    const double lij = MIXED ? rnd(r[q] * inv) : r[q] * inv;
+                    if (lane == j) {
+                        dv()[j] = inv;
+                        r[q] = piv * inv;
+                    } else if (lane > j) {
+                        r[q] = lij;
+                        if constexpr (MIXED) dd -= lij * lij;
+                    } else {
+                        r[q] = 0.0;
+                    }
+                    // rank-1 update of the rest of the panel; column entries
+                    // come from the lanes that hold them (readlane)
+#pragma unroll
+                    for (int q2 = q + 1; q2 < PW; ++q2)
+                        if (q2 < pw) r[q2] = (double)((TS)r[q2] - (TS)lij * (TS)bcast(lij, p0 + q2));
+                }
+                if (lane < NZ) {
+#pragma unroll
+                    for (int q = 0; q < PW; ++q)
+                        if (q < pw) m[lane + (p0 + q) * S.ldm] = r[q];
+                }
+            }
+            __syncthreads();
+            // trailing update of rows/columns p1.. with the panel
+            const int p1 = p0 + pw;
+            const int nt = NZ - p1;
+            if (nt > 0) {
+                const int TZ = (nt + 3) >> 2;
+                for (int t = opq(tid); t < TZ * TZ; t += BT) {
+                    const int ti = t % TZ, tk = t / TZ;
+                    if (ti < tk) continue;
+                    const int i0 = p1 + 4 * ti, k0 = p1 + 4 * tk;
+                    int ic[4], kc[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        ic[a] = min(i0 + a, NZ - 1);
+                        kc[a] = min(k0 + a, NZ - 1);
+                    }
+                    TS acc[4][4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[a][c] = 0;
+#pragma unroll 2
+                    for (int q = p0; q < p1; ++q) {
+                        TS li[4], lk[4];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) li[a] = (TS)m[ic[a] + q * S.ldm];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) lk[c] = (TS)m[kc[c] + q * S.ldm];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) acc[a][c] += li[a] * lk[c];
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            if (i0 + a < NZ && k0 + c < NZ && k0 + c <= i0 + a) {
+                                double* e = m + (i0 + a) + (k0 + c) * S.ldm;
+                                *e = (double)((TS)*e - acc[a][c]);
+                            }
+                }
+                __syncthreads();
+            }
+        }
+        if (wid == 0 && lane == 0) flag()[0] = 1.0;
+        __syncthreads();
+        if (wid == 0 && !ok && lane == 0) flag()[0] = 0.0;
+        __syncthreads();
+        return flag()[0] != 0.0;
+    }
+
+    // wave 0: forward substitution with the (u, u) block of the factor in M,
+    // fused with the x rows: lanes j < NU end with y = L_uu^{-1} m_u, lanes
+    // NU <= j < NZ with p = m_x - L_xu y.  di = 1/L_jj of lane j.
+    __device__ __forceinline__ double fwd_subst_u(double mv, double di) const
+    {
+        const double* m = M();
+        mv = rnd(mv);
+        for (int j = 0; j < NU; ++j) {
+            const double y = rnd(bcast(mv, j) * bcast(di, j));
+            if (lane == j) mv = y;
+            else if (lane > j && lane < NZ) mv = (double)((TS)mv - (TS)m[lane + j * S.ldm] * (TS)y);
+        }
+        return mv;
+    }
+
+    // ==================================================================
+    // Pass A: apply the previous step (optional), residuals at the iterate,
+    // barrier terms, factorization and the right-hand-side sweep for r_m =
+    // lam.*t - shift.  Returns whether every pivot was positive.
+    // ==================================================================
+    __device__ __forceinline__ bool passA(bool upd, double alpha, double shift, bool factor, double& o_g, double& o_b, double& o_d,
+                          double& o_m, double& o_lt) const
+    {
+        double mg = 0.0, mb = 0.0, md = 0.0, mm = 0.0, slt = 0.0;
+        bool fact_ok = true;
+        Pre pre;
+        seg_hfg(pre, N);
+        fetch(pre);
+        for (int n = N; n >= 0; --n) {
+            const int cur = n & 1, nxt = cur ^ 1;
+            commit(pre, M(), F(), G());
+            const double* d = Dp(n);
+            double* ir = Ip(n);
+            double* w = Wp(n);
+            // row j = tid (< NZ), state row i = tid (< NX), slot c = tid (< NC)
+            const int j = opq(tid);
+            double g = 0.0, zz = 0.0, dz = 0.0, b = 0.0, pi = 0.0, dpi = 0.0;
+            if (j < NZ) {
+                g = d[Lo.D_g + j];
+                zz = ir[Lo.I_z + j];
+                if (upd) dz = w[Lo.W_dz + j];
+            }
+            if (j < NX) {
+                if (n < N) b = d[Lo.D_b + j];
+                pi = ir[Lo.I_pi + j];
+                if (upd && n > 0) dpi = w[Lo.W_dpi + j];
+            }
+            double m = 0.0, lo = 0.0, hi = 0.0, ll = 0.0, lu = 0.0, tl = 0.0, tu = 0.0;
+            if (j < NC) {
+                slot_bounds(d, j, m, lo, hi);
+                ll = ir[Lo.I_ll + j];
+                lu = ir[Lo.I_lu + j];
+                tl = ir[Lo.I_tl + j];
+                tu = ir[Lo.I_tu + j];
+                if (upd && m != 0.0) {
+                    ll = fmax(ll + alpha * w[Lo.W_dll + j], P.lam_min);
+                    lu = fmax(lu + alpha * w[Lo.W_dlu + j], P.lam_min);
+                    tl = fmax(tl + alpha * w[Lo.W_dtl + j], P.t_min);
+                    tu = fmax(tu + alpha * w[Lo.W_dtu + j], P.t_min);
+                }
+            }
+            if (n > 0) {
+                seg_hfg(pre, n - 1);
+                fetch(pre);  // next stage of the sweep
+            }
+            if (upd) {
+                zz += alpha * dz;
+                if (n > 0) pi += alpha * dpi;
+            }
+            if (n == N && j < NX) {
+                xn(nxt)[j] = 0.0;
+                pin(nxt)[j] = 0.0;
+                pn(nxt)[j] = 0.0;
+            }
+            if (j < NZ) z()[j] = zz;
+            if (j < NX) t2()[j] = pi;
+            if (j >= NZ && j < NC) t1()[j - NZ] = m * (ll - lu);
+            __syncthreads();
+
+            // r_g = H z + g + F' pi_{n+1} - [0; pi_n] - C' lam
+            double rg = 0.0;
+            if (j < NZ) {
+                const double* mh = M();
+                const double* zv = z();
+                double acc = g + dot<double>(mh + j, S.ldm, zv, 1, NZ);
+                if (n < N) acc += dot<double>(F() + j * S.ldf, 1, pin(nxt), 1, NX);
+                if (j >= NU) acc -= t2()[j - NU];
+                acc -= m * (ll - lu);
+                acc -= dot<double>(G() + j * S.ldg, 1, t1(), 1, NG);
+                rg = acc;
+                mg = nmax(mg, fabs(rg));
+            }
+            // r_b = F z + b - x_{n+1}
+            double rb = 0.0;
+            if (n < N && j < NX) {
+                const double acc = b + dot<double>(F() + j, S.ldf, z(), 1, NZ);
+                rb = acc - xn(nxt)[j];
+                mb = nmax(mb, fabs(rb));
+            }
+            // r_d, complementarity, barrier weights, reduced-gradient terms
+            double rdl = 0.0, rdu = 0.0;
+            if (j < NC) {
+                double e = 0.0, wsum = 0.0;
+                if (m != 0.0) {
+                    double gz;
+                    if (j < NZ) {
+                        gz = zz;
+                    } else {
+                        gz = dot<double>(G() + (j - NZ), S.ldg, z(), 1, NZ);
+                    }
+                    rdl = -gz + tl + lo;
+                    rdu = gz + tu - hi;
+                    md = nmax(md, nmax(fabs(rdl), fabs(rdu)));
+                    const double a1 = ll * tl, a2 = lu * tu;
+                    mm = nmax(mm, nmax(a1, a2));
+                    slt += a1 + a2;
+                    const double itl = rcp_nr(tl), itu = rcp_nr(tu);
+                    const double wl = ll * itl, wu = lu * itu;
+                    wsum = wl + wu;
+                    e = (wl * rdl - (ll - shift * itl)) - (wu * rdu - (lu - shift * itu));
+                }
+                ev()[j] = e;
+                wsv()[j] = wsum;
+                if (upd && m != 0.0) {
+                    ir[Lo.I_ll + j] = ll;
+                    ir[Lo.I_lu + j] = lu;
+                    ir[Lo.I_tl + j] = tl;
+                    ir[Lo.I_tu + j] = tu;
+                }
+                w[Lo.W_rdl + j] = rdl;
+                w[Lo.W_rdu + j] = rdu;
+            }
+            if (j < NX) rbv()[j] = rb;
+            if (upd) {
+                if (j < NZ) ir[Lo.I_z + j] = zz;
+                if (j < NX && n > 0) ir[Lo.I_pi + j] = pi;
+            }
+            if (j < NZ) w[Lo.W_rg + j] = rg;
+            if (n < N && j < NX) w[Lo.W_rb + j] = rb;
+            __syncthreads();
+
+            if (factor) {
+                // Phi = H + diag(box weights) + reg I ; V = [L_{n+1}' F ; sqrt(w_g) G]
+                if (j < NZ) M()[j + j * S.ldm] += wsv()[j] + P.reg_prim;
+                {
+                    const double* gg = G();
+                    const double* wv = wsv();
+                    double* v = V();
+                    for (int e = tid; e < NG * NZ; e += BT) {
+                        const int r = e % NG, k = e / NG;
+                        v[NX + r + k * S.ldv] = sqrt(wv[NZ + r]) * gg[r + k * S.ldg];
+                    }
+                }
+                if (n < N) trmm_LtF();
+                __syncthreads();
+                if (n < N || NG > 0) syrk_VtV(n < N ? 0 : NX);
+                __syncthreads();
+                fact_ok = cholesky() && fact_ok;
+
+                // reduced gradient and cost-to-go terms
+                double mv = 0.0;
+                if (j < NZ) {
+                    mv = rg - ev()[j] - dot<double>(G() + j * S.ldg, 1, ev() + NZ, 1, NG);
+                }
+                if (n < N) {
+                    const double* L = Lx();
+                    if (j < NX) t1()[j] = (double)dot<TS>(L + j + j * S.ldx, 1, rbv() + j, 1, NX - j);
+                    __syncthreads();
+                    if (j < NX) t2()[j] = (double)((TS)pn(nxt)[j] + dot<TS>(L + j, S.ldx, t1(), 1, j + 1));
+                    __syncthreads();
+                    if (j < NZ) mv = (double)((TS)mv + dot<TS>(F() + j * S.ldf, 1, t2(), 1, NX));
+                }
+                if (wid == 0) {
+                    const double di = lane < NZ ? dv()[lane] : 0.0;
+                    mv = fwd_subst_u(mv, di);
+                    if (lane < NZ) w[Lo.W_dinv + lane] = di;
+                    if (lane < NU) w[Lo.W_yu + lane] = mv;
+                    else if (lane < NZ) {
+                        w[Lo.W_pv + lane - NU] = mv;
+                        pn(cur)[lane - NU] = mv;
+                    }
+                }
+                // factor to global memory; its (x, x) block becomes L_{n+1} of
+                // the next stage of the sweep
+                {
+                    const double* mf = M();
+                    double* wl = w + Lo.W_L;
+                    Walk q(NZ, tid);
+                    for (int e = tid; e < NZ * NZ; e += BT) {
+                        wl[e] = mf[q.r + q.c * S.ldm];
+                        q.next();
+                    }
+                    double* L = Lx();
+                    Walk qx(NX, tid);
+                    for (int e = tid; e < NX * NX; e += BT) {
+                        L[qx.r + qx.c * S.ldx] = mf[(NU + qx.r) + (NU + qx.c) * S.ldm];
+                        qx.next();
+                    }
+                }
+            }
+            if (j >= NU && j < NZ) xn(cur)[j - NU] = zz;
+            if (j < NX) pin(cur)[j] = pi;
+            __syncthreads();
+        }
+        reduce4(mg, mb, md, mm, slt);
+        o_g = mg;
+        o_b = mb;
+        o_d = md;
+        o_m = mm;
+        o_lt = slt;
+        return fact_ok;
+    }
+
+    // slot values used by the right-hand-side sweeps: r_m (lower, upper) of
+    // slot c per rmode
+    __device__ __forceinline__ void slot_rm(int rmode, double shift, const double* w, int c, double ll, double lu,
+                                            double tl, double tu, double& rml, double& rmu) const
+    {
+        if (rmode == RM_IR) {
+            rml = w[Lo.W_irml + c];
+            rmu = w[Lo.W_irmu + c];
+            return;
+        }
+        rml = ll * tl - shift;
+        rmu = lu * tu - shift;
+        if (rmode == RM_CORRECTOR) {
+            rml += w[Lo.W_all + c] * w[Lo.W_atl + c];
+            rmu += w[Lo.W_alu + c] * w[Lo.W_atu + c];
+        }
+    }
+
+    // cost-to-go of the right-hand side: returns mv + F'(Lxx (Lxx' rb) + pn)
+    // for row j, with Lxx(i, k) = xc[(NU + i) + k ldm] (xc: first x-column of
+    // the next stage's factor) and rb, pn in LDS; every thread must call it
+    __device__ __forceinline__ double cost_to_go_x(double mv, const double* xc, const double* pnv) const
+    {
+        const int j = opq(tid);
+        if (j < NX) t1()[j] = (double)dot<TS>(xc + (NU + j) + j * S.ldm, 1, rbv() + j, 1, NX - j);
+        __syncthreads();
+        if (j < NX) t2()[j] = (double)((TS)pnv[j] + dot<TS>(xc + (NU + j), S.ldm, t1(), 1, j + 1));
+        __syncthreads();
+        if (j < NZ) mv = (double)((TS)mv + dot<TS>(F() + j * S.ldf, 1, t2(), 1, NX));
+        return mv;
+    }
+
+    // ==================================================================
+    // Pass C: backward right-hand-side sweep with the stored factors for the
+    // RHS (r_g, r_b, r_d) at offsets og, ob, odl, odu and r_m per rmode.
+    // ==================================================================
+    __device__ __forceinline__ void passC(int rmode, double shift, int og, int ob, int odl, int odu) const
+    {
+        Pre pre;
+        seg_lfg(pre, N);
+        fetch(pre);
+        for (int n = N; n >= 0; --n) {
+            const int cur = n & 1, nxt = cur ^ 1;
+            commit(pre, M(), F(), G());
+            const double* d = Dp(n);
+            const double* ir = Ip(n);
+            const double* w = Wp(n);
+            const int j = opq(tid);
+            const double di = j < NU ? w[Lo.W_dinv + j] : 0.0;
+            const double rg = j < NZ ? w[og + j] : 0.0;
+            const double rb = (j < NX && n < N) ? w[ob + j] : 0.0;
+            if (j < NC) {
+                double m, lo, hi;
+                slot_bounds(d, j, m, lo, hi);
+                double e = 0.0;
+                if (m != 0.0) {
+                    const double ll = ir[Lo.I_ll + j], lu = ir[Lo.I_lu + j];
+                    const double tl = ir[Lo.I_tl + j], tu = ir[Lo.I_tu + j];
+                    double rml, rmu;
+                    slot_rm(rmode, shift, w, j, ll, lu, tl, tu, rml, rmu);
+                    const double itl = rcp_nr(tl), itu = rcp_nr(tu);
+                    e = (ll * w[odl + j] - rml) * itl - (lu * w[odu + j] - rmu) * itu;
+                }
+                ev()[j] = e;
+            }
+            if (n == N && j < NX) pn(nxt)[j] = 0.0;
+            if (j < NX) rbv()[j] = rb;
+            if (n > 0) {
+                seg_lfg(pre, n - 1);
+                fetch(pre);
+            }
+            __syncthreads();
+            double mv = 0.0;
+            if (j < NZ) {
+                mv = rg - ev()[j] - dot<double>(G() + j * S.ldg, 1, ev() + NZ, 1, NG);
+            }
+            if (n < N) mv = cost_to_go_x(mv, M() + NU * S.ldm, pn(nxt));
+            if (wid == 0) {
+                mv = fwd_subst_u(mv, di);
+                double* wo = Wp(n);
+                if (lane < NU) wo[Lo.W_yu + lane] = mv;
+                else if (lane < NZ) {
+                    wo[Lo.W_pv + lane - NU] = mv;
+                    pn(cur)[lane - NU] = mv;
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // ==================================================================
+    // Pass B: forward substitution and recovery of dt, dlam.  Writes dz, dpi
+    // to (oz, opi) and dlam, dt to (oll, olu, otl, otu).  Returns the largest
+    // alpha keeping lam, t >= 0 (uncapped; HUGE_VAL if unblocked) and s1 =
+    // sum(lam dt + dlam t), s2 = sum(dlam dt).
+    // ==================================================================
+    __device__ __forceinline__ double passB(int rmode, double shift, int ob, int odl, int odu, int oz, int opi, int oll, int olu,
+                            int otl, int otu, double& o_s1, double& o_s2) const
+    {
+        double amin = HUGE_VAL, s1 = 0.0, s2 = 0.0;
+        // dx_0 = -(L0 L0')^{-1} p_0 with L0 the (x, x) block of stage 0
+        {
+            const int j = tid;
+            double* w0 = Wp(0);
+            double* L = Lx();
+            Walk qx(NX, tid);
+            for (int e = tid; e < NX * NX; e += BT) {
+                L[qx.r + qx.c * S.ldx] = w0[Lo.W_L + (NU + qx.r) + (NU + qx.c) * NZ];
+                qx.next();
+            }
+            double v = j < NX ? -w0[Lo.W_pv + j] : 0.0;
+            const double di = j < NX ? w0[Lo.W_dinv + NU + j] : 0.0;
+            if (j < NX) w0[opi + j] = 0.0;
+            __syncthreads();
+            if (wid == 0) {
+                v = rnd(v);
+                for (int c = 0; c < NX; ++c) {
+                    const double y = rnd(bcast(v, c) * bcast(di, c));
+                    if (lane == c) v = y;
+                    else if (lane > c && lane < NX) v = (double)((TS)v - (TS)L[lane + c * S.ldx] * (TS)y);
+                }
+                for (int c = NX - 1; c >= 0; --c) {
+                    const double x = rnd(bcast(v, c) * bcast(di, c));
+                    if (lane == c) v = x;
+                    else if (lane < c) v = (double)((TS)v - (TS)L[c + lane * S.ldx] * (TS)x);
+                }
+                if (lane < NX) xn(0)[lane] = v;
+            }
+            __syncthreads();
+        }
+        Pre pre;
+        seg_lfg(pre, 0);
+        fetch(pre);
+        for (int n = 0; n <= N; ++n) {
+            const int cur = n & 1, nxt = cur ^ 1;
+            commit(pre, M(), F(), G());
+            const double* d = Dp(n);
+            const double* ir = Ip(n);
+            double* w = Wp(n);
+            const int j = opq(tid);
+            const double di = j < NU ? w[Lo.W_dinv + j] : 0.0;
+            const double yu = j < NU ? w[Lo.W_yu + j] : 0.0;
+            const double rb = (j < NX && n < N) ? w[ob + j] : 0.0;
+            const double pnx = (j < NX && n < N) ? Wp(n + 1)[Lo.W_pv + j] : 0.0;
+            double m = 0.0, rdl = 0.0, rdu = 0.0, ll = 0.0, lu = 0.0, tl = 0.0, tu = 0.0, rml = 0.0, rmu = 0.0;
+            if (j < NC) {
+                double lo, hi;
+                slot_bounds(d, j, m, lo, hi);
+                if (m != 0.0) {
+                    rdl = w[odl + j];
+                    rdu = w[odu + j];
+                    ll = ir[Lo.I_ll + j];
+                    lu = ir[Lo.I_lu + j];
+                    tl = ir[Lo.I_tl + j];
+                    tu = ir[Lo.I_tu + j];
+                    slot_rm(rmode, shift, w, j, ll, lu, tl, tu, rml, rmu);
+                }
+            }
+            if (n < N) {
+                seg_lfg(pre, n + 1);
+                fetch(pre);
+            }
+            __syncthreads();
+            // v = y_u + L_xu' dx ; back-substitution with L_uu'
+            if (wid == 0) {
+                const double* mu = M();
+                const double* x = xn(cur);
+                double v = 0.0;
+                if (lane < NU) v = (double)((TS)yu + dot<TS>(mu + NU + lane * S.ldm, 1, x, 1, NX));
+                for (int c = NU - 1; c >= 0; --c) {
+                    const double xv = rnd(bcast(v, c) * bcast(di, c));
+                    if (lane == c) v = xv;
+                    else if (lane < c) v = (double)((TS)v - (TS)mu[c + lane * S.ldm] * (TS)xv);
+                }
+                double dz = 0.0;
+                if (lane < NU) dz = -v;
+                else if (lane < NZ) dz = x[lane - NU];
+                if (lane < NZ) {
+                    z()[lane] = dz;
+                    w[oz + lane] = dz;
+                }
+            }
+            __syncthreads();
+            if (n < N) {
+                const double* xc = M() + NU * S.ldm;
+                if (j < NX) xn(nxt)[j] = (double)((TS)rb + dot<TS>(F() + j, S.ldf, z(), 1, NZ));
+                __syncthreads();
+                if (j < NX) t1()[j] = (double)dot<TS>(xc + (NU + j) + j * S.ldm, 1, xn(nxt) + j, 1, NX - j);
+                __syncthreads();
+                if (j < NX) Wp(n + 1)[opi + j] = (double)((TS)pnx + dot<TS>(xc + (NU + j), S.ldm, t1(), 1, j + 1));
+            }
+            // constraint steps, step length, duality-measure sums
+            if (j < NC) {
+                double dll = 0.0, dlu = 0.0, dtl = 0.0, dtu = 0.0;
+                if (m != 0.0) {
+                    double gdz;
+                    if (j < NZ) {
+                        gdz = z()[j];
+                    } else {
+                        gdz = dot<double>(G() + (j - NZ), S.ldg, z(), 1, NZ);
+                    }
+                    dtl = gdz - rdl;
+                    dtu = -gdz - rdu;
+                    dll = -(rml + ll * dtl) * rcp_nr(tl);
+                    dlu = -(rmu + lu * dtu) * rcp_nr(tu);
+                    if (dll < 0.0) amin = fmin(amin, -ll * __builtin_amdgcn_rcp(dll));
+                    if (dlu < 0.0) amin = fmin(amin, -lu * __builtin_amdgcn_rcp(dlu));
+                    if (dtl < 0.0) amin = fmin(amin, -tl * __builtin_amdgcn_rcp(dtl));
+                    if (dtu < 0.0) amin = fmin(amin, -tu * __builtin_amdgcn_rcp(dtu));
+                    s1 += ll * dtl + dll * tl + lu * dtu + dlu * tu;
+                    s2 += dll * dtl + dlu * dtu;
+                }
+                w[oll + j] = dll;
+                w[olu + j] = dlu;
+                w[otl + j] = dtl;
+                w[otu + j] = dtu;
+            }
+            __syncthreads();
+        }
+        amin = bmin_sum2(amin, s1, s2);
+        o_s1 = s1;
+        o_s2 = s2;
+        return amin;
+    }
+
+    // ==================================================================
+    // Pass R (mixed path): FP64 residual r_ir = K step + r of the Newton
+    // system for the step at (oz, opi, oll, olu, otl, otu); written to the
+    // refinement arrays.  Returns its inf-norm.
+    // ==================================================================
+    __device__ __forceinline__ double passR(int rmode, double shift, int oz, int opi, int oll, int olu, int otl, int otu) const
+    {
+        double nr = 0.0;
+        Pre pre;
+        seg_hfg(pre, N);
+        fetch(pre);
+        for (int n = N; n >= 0; --n) {
+            const int cur = n & 1, nxt = cur ^ 1;
+            commit(pre, M(), F(), G());
+            const double* d = Dp(n);
+            const double* ir = Ip(n);
+            double* w = Wp(n);
+            const int j = opq(tid);
+            const double dz = j < NZ ? w[oz + j] : 0.0;
+            const double rg = j < NZ ? w[Lo.W_rg + j] : 0.0;
+            const double dpi = (j < NX && n > 0) ? w[opi + j] : 0.0;
+            const double rb = (j < NX && n < N) ? w[Lo.W_rb + j] : 0.0;
+            double m = 0.0, rdl = 0.0, rdu = 0.0, ll = 0.0, lu = 0.0, tl = 0.0, tu = 0.0, rml = 0.0, rmu = 0.0;
+            double sll = 0.0, slu = 0.0, stl = 0.0, stu = 0.0;
+            if (j < NC) {
+                double lo, hi;
+                slot_bounds(d, j, m, lo, hi);
+                if (m != 0.0) {
+                    rdl = w[Lo.W_rdl + j];
+                    rdu = w[Lo.W_rdu + j];
+                    ll = ir[Lo.I_ll + j];
+                    lu = ir[Lo.I_lu + j];
+                    tl = ir[Lo.I_tl + j];
+                    tu = ir[Lo.I_tu + j];
+                    slot_rm(rmode, shift, w, j, ll, lu, tl, tu, rml, rmu);
+                    sll = w[oll + j];
+                    slu = w[olu + j];
+                    stl = w[otl + j];
+                    stu = w[otu + j];
+                }
+            }
+            if (n > 0) {
+                seg_hfg(pre, n - 1);
+                fetch(pre);
+            }
+            if (n == N && j < NX) {
+                xn(nxt)[j] = 0.0;
+                pin(nxt)[j] = 0.0;
+            }
+            if (j < NZ) z()[j] = dz;
+            if (j < NX) t2()[j] = dpi;
+            if (j >= NZ && j < NC) t1()[j - NZ] = m * (sll - slu);
+            __syncthreads();
+            // g row: H dz + F' dpi_{n+1} - [0; dpi_n] - C' dlam + r_g
+            double org = 0.0, orb = 0.0;
+            if (j < NZ) {
+                const double* mh = M();
+                const double* zv = z();
+                double acc = rg + dot<double>(mh + j, S.ldm, zv, 1, NZ);
+                if (n < N) acc += dot<double>(F() + j * S.ldf, 1, pin(nxt), 1, NX);
+                if (j >= NU) acc -= t2()[j - NU];
+                acc -= m * (sll - slu);
+                acc -= dot<double>(G() + j * S.ldg, 1, t1(), 1, NG);
+                org = acc;
+                nr = nmax(nr, fabs(acc));
+                w[Lo.W_irg + j] = org;
+            }
+            // b row: F dz - dx_{n+1} + r_b
+            if (n < N && j < NX) {
+                const double acc = rb + dot<double>(F() + j, S.ldf, z(), 1, NZ);
+                orb = acc - xn(nxt)[j];
+                nr = nmax(nr, fabs(orb));
+                w[Lo.W_irb + j] = orb;
+            }
+            // d rows: -C dz + dt + r_d ; m rows: T dlam + Lam dt + r_m
+            if (j < NC) {
+                double ordl = 0.0, ordu = 0.0, orml = 0.0, ormu = 0.0;
+                if (m != 0.0) {
+                    double gz;
+                    if (j < NZ) {
+                        gz = dz;
+                    } else {
+                        gz = dot<double>(G() + (j - NZ), S.ldg, z(), 1, NZ);
+                    }
+                    ordl = -gz + stl + rdl;
+                    ordu = gz + stu + rdu;
+                    orml = tl * sll + ll * stl + rml;
+                    ormu = tu * slu + lu * stu + rmu;
+                    nr = nmax(nr, nmax(nmax(fabs(ordl), fabs(ordu)), nmax(fabs(orml), fabs(ormu))));
+                }
+                w[Lo.W_irdl + j] = ordl;
+                w[Lo.W_irdu + j] = ordu;
+                w[Lo.W_irml + j] = orml;
+                w[Lo.W_irmu + j] = ormu;
+            }
+            if (j >= NU && j < NZ) xn(cur)[j - NU] = dz;
+            if (j < NX) pin(cur)[j] = dpi;
+            __syncthreads();
+        }
+        return bmax1(nr);
+    }
+
+    // ==================================================================
+    // Pass X (mixed path): step += correction, then the step length and the
+    // duality-measure sums of pass B for the corrected step.  Stages are
+    // independent here, so the loop runs over all (stage, row) pairs.
+    // ==================================================================
+    __device__ __forceinline__ double passX(int oz, int opi, int oll, int olu, int otl, int otu, double& o_s1, double& o_s2) const
+    {
+        double amin = HUGE_VAL, s1 = 0.0, s2 = 0.0;
+        for (int e = tid; e < (N + 1) * NZ; e += BT) {
+            double* w = Wp(e / NZ);
+            const int j = e % NZ;
+            w[oz + j] += w[Lo.W_edz + j];
+        }
+        for (int e = tid; e < N * NX; e += BT) {
+            double* w = Wp(1 + e / NX);
+            const int i = e % NX;
+            w[opi + i] += w[Lo.W_edpi + i];
+        }
+        for (int e = tid; e < (N + 1) * NC; e += BT) {
+            const int n = e / NC, c = e % NC;
+            const double* d = Dp(n);
+            const double* ir = Ip(n);
+            double* w = Wp(n);
+            double m, lo_, hi_;
+            slot_bounds(d, c, m, lo_, hi_);
+            if (m == 0.0) continue;
+            const double dll = w[oll + c] + w[Lo.W_edll + c];
+            const double dlu = w[olu + c] + w[Lo.W_edlu + c];
+            const double dtl = w[otl + c] + w[Lo.W_edtl + c];
+            const double dtu = w[otu + c] + w[Lo.W_edtu + c];
+            w[oll + c] = dll;
+            w[olu + c] = dlu;
+            w[otl + c] = dtl;
+            w[otu + c] = dtu;
+            const double ll = ir[Lo.I_ll + c], lu = ir[Lo.I_lu + c], tl = ir[Lo.I_tl + c], tu = ir[Lo.I_tu + c];
+            if (dll < 0.0) amin = fmin(amin, -ll * __builtin_amdgcn_rcp(dll));
+            if (dlu < 0.0) amin = fmin(amin, -lu * __builtin_amdgcn_rcp(dlu));
+            if (dtl < 0.0) amin = fmin(amin, -tl * __builtin_amdgcn_rcp(dtl));
+            if (dtu < 0.0) amin = fmin(amin, -tu * __builtin_amdgcn_rcp(dtu));
+            s1 += ll * dtl + dll * tl + lu * dtu + dlu * tu;
+            s2 += dll * dtl + dlu * dtu;
+        }
+        amin = bmin_sum2(amin, s1, s2);
+        o_s1 = s1;
+        o_s2 = s2;
+        return amin;
+    }
+
+    // Iterative refinement of the step at the given offsets (mixed path).
+    __device__ __forceinline__ int refine(int rmode, double shift, double rnorm, int oz, int opi, int oll, int olu, int otl, int otu,
+                          double& amax, double& s1, double& s2) const
+    {
+        int steps = 0;
+        double prev = HUGE_VAL;
+        for (int it = 0; it <= P.ir_max; ++it) {
+            const double nir = passR(rmode, shift, oz, opi, oll, olu, otl, otu);
+            __syncthreads();
+            if (!(nir > P.ir_tol * rnorm) || !(nir < prev) || it == P.ir_max) break;
+            prev = nir;
+            passC(RM_IR, 0.0, Lo.W_irg, Lo.W_irb, Lo.W_irdl, Lo.W_irdu);
+            __syncthreads();
+            double t1v, t2v;
+            passB(RM_IR, 0.0, Lo.W_irb, Lo.W_irdl, Lo.W_irdu, Lo.W_edz, Lo.W_edpi, Lo.W_edll, Lo.W_edlu, Lo.W_edtl,
+                  Lo.W_edtu, t1v, t2v);
+            __syncthreads();
+            amax = passX(oz, opi, oll, olu, otl, otu, s1, s2);
+            __syncthreads();
+            ++steps;
+        }
+        return steps;
+    }
+
+    // cold start: y = 0, pi = 0, t = max(C y - d, 1), lam = 1 (masked slots 0)
+    __device__ __forceinline__ void init() const
+    {
+        for (int e = tid; e < (N + 1) * NZ; e += BT) Ip(e / NZ)[Lo.I_z + e % NZ] = 0.0;
+        for (int e = tid; e < (N + 1) * NX; e += BT) Ip(e / NX)[Lo.I_pi + e % NX] = 0.0;
+        for (int e = tid; e < (N + 1) * NC; e += BT) {
+            const int n = e / NC, c = e % NC;
+            double m, lo, hi;
+            slot_bounds(Dp(n), c, m, lo, hi);
+            const bool on = m != 0.0;
+            double* ir = Ip(n);
+            ir[Lo.I_ll + c] = on ? 1.0 : 0.0;
+            ir[Lo.I_lu + c] = on ? 1.0 : 0.0;
+            ir[Lo.I_tl + c] = on ? fmax(-lo, 1.0) : 0.0;
+            ir[Lo.I_tu + c] = on ? fmax(hi, 1.0) : 0.0;
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void copy_step_out(double* out) const
+    {
+        for (int e = tid; e < (N + 1) * NZ; e += BT) {
+            const int n = e / NZ, j = e % NZ;
+            out[(size_t)n * Lo.IREC + Lo.I_z + j] = Wp(n)[Lo.W_dz + j];
+        }
+        for (int e = tid; e < (N + 1) * NX; e += BT) {
+            const int n = e / NX, i = e % NX;
+            out[(size_t)n * Lo.IREC + Lo.I_pi + i] = Wp(n)[Lo.W_dpi + i];
+        }
+        for (int e = tid; e < (N + 1) * NC; e += BT) {
+            const int n = e / NC, c = e % NC;
+            double* o = out + (size_t)n * Lo.IREC;
+            const double* w = Wp(n);
+            o[Lo.I_ll + c] = w[Lo.W_dll + c];
+            o[Lo.I_lu + c] = w[Lo.W_dlu + c];
+            o[Lo.I_tl + c] = w[Lo.W_dtl + c];
+            o[Lo.I_tu + c] = w[Lo.W_dtu + c];
+        }
+    }
+
+    // ------------------------------------------------------------------
+    // Driver (same iteration logic as the one-wave kernel).
+    // ------------------------------------------------------------------
+    __device__ __forceinline__ void run(DevStat* st, double* step_out, int fell_back) const
+    {
+        const bool newton_mode = P.mode == KMODE_NEWTON;
+        if (!newton_mode) init();
+        int status = ST_MAX_ITER, k = 0;
+        double ng = 0, nb = 0, nd = 0, nm = 0, mu = 0.0, slt = 0.0;
+        const double inv2nc = nc > 0 ? 1.0 / (2.0 * nc) : 0.0;
+        const double shift0 = newton_mode ? P.tau : 0.0;
+        bool upd = false, rejected = false;
+        double alpha = 0.0;
+        int ir_steps = 0;
+        for (k = 0;; ++k) {
+            const bool fact_ok = passA(upd, alpha, shift0, !rejected, ng, nb, nd, nm, slt);
+            __syncthreads();
+            mu = slt * inv2nc;
+            if (rejected) {
+                status = ST_MIN_STEP;
+                break;
+            }
+            if (MIXED && !newton_mode && !fact_ok) {
+                status = ST_FALLBACK;
+                break;
+            }
+            if (!newton_mode) {
+                if (ng != ng || nb != nb || nd != nd || nm != nm || mu != mu) {
+                    status = ST_NAN;
+                    break;
+                }
+                if (ng <= P.tol_stat && nb <= P.tol_eq && nd <= P.tol_ineq && nm <= P.tol_comp) {
+                    status = ST_SUCCESS;
+                    break;
+                }
+                if (k >= P.iter_max) {
+                    status = ST_MAX_ITER;
+                    break;
+                }
+            }
+            double amax = HUGE_VAL, mu_aff = 0.0, smu = 0.0;
+            for (int round = 0; round < 3; ++round) {
+                const int rmode = round == 1 ? RM_CORRECTOR : RM_SHIFT;
+                const double shift = round == 0 ? shift0 : smu;
+                const bool aff = round == 0 && !newton_mode;
+                if (round > 0) {
+                    passC(rmode, shift, Lo.W_rg, Lo.W_rb, Lo.W_rdl, Lo.W_rdu);
+                    __syncthreads();
+                }
+                double s1, s2;
+                const int oll = aff ? Lo.W_all : Lo.W_dll, olu = aff ? Lo.W_alu : Lo.W_dlu;
+                const int otl = aff ? Lo.W_atl : Lo.W_dtl, otu = aff ? Lo.W_atu : Lo.W_dtu;
+                amax = passB(rmode, shift, Lo.W_rb, Lo.W_rdl, Lo.W_rdu, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, s1, s2);
+                __syncthreads();
+                if constexpr (MIXED) {
+                    const double rnorm = fmax(1.0, fmax(fmax(ng, nb), fmax(nd, nm)));
+                    ir_steps += refine(rmode, shift, rnorm, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, amax, s1, s2);
+                }
+                if (newton_mode || nc == 0) break;
+                const double a = fmin(amax, 1.0);
+                const double mu_a = (slt + a * s1 + a * a * s2) * inv2nc;
+                if (round == 0) {
+                    mu_aff = fmax(0.0, mu_a);
+                    const double ratio = mu > 0.0 ? mu_aff / mu : 0.0;
+                    smu = ratio * ratio * ratio * mu;
+                } else if (round == 1) {
+                    if (!(mu_a > P.corr_ratio * mu_aff)) break;
+                } else {
+                    break;
+                }
+            }
+            if (newton_mode) break;
+            alpha = fmin(1.0, P.gamma * amax);
+            upd = true;
+            rejected = alpha < P.alpha_min;
+        }
+        if (newton_mode) {
+            copy_step_out(step_out);
+            status = ST_SUCCESS;
+            k = 0;
+        }
+        if (MIXED && !newton_mode && (status == ST_NAN || status == ST_MIN_STEP)) status = ST_FALLBACK;
+        if (tid == 0) {
+            st->status = status;
+            st->iters = k;
+            st->ir_steps = ir_steps;
+            st->fell_back = fell_back;
+            st->mu = mu;
+            st->res[0] = ng;
+            st->res[1] = nb;
+            st->res[2] = nd;
+            st->res[3] = nm;
+        }
+    }
+};
+
+template <bool MIXED, int ZM, int GM>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1, 1))) void ipm_block_kernel(
+    const InstDesc* __restrict__ desc, int count, const double* __restrict__ data, double* __restrict__ iter,
+    double* __restrict__ work, double* __restrict__ step_out, DevStat* __restrict__ stat, KParams P)
+{
+    const int b = blockIdx.x;
+    if (b >= count) return;
+    const InstDesc ds = desc[b];
+    int fell_back = 0;
+    if (P.mode == KMODE_FALLBACK) {
+        if (stat[ds.index].status != ST_FALLBACK) return;
+        fell_back = 1;
+    }
+    const Blk<MIXED, ZM, GM> ipm(ds, data, iter, work, P);
+    ipm.run(stat + ds.index, step_out + ds.iter, fell_back);
+}
+
+}  // namespace oqp

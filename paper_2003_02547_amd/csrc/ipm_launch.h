@@ -6,32 +6,29 @@
 
 #include "layout.h"
 
-// X(NX, NU, NG) for every compiled variant; the host picks the cheapest one
-// that covers an instance.
+// X(NX, NU, NG) for every compiled variant of the one-wave kernel; the host
+// picks the cheapest one that covers an instance.  Larger stage blocks go to
+// the runtime-sized block kernel.
 #define OQP_VARIANTS(X) \
-    X(4, 4, 0)          \
-    X(4, 4, 4)          \
-    X(8, 4, 0)          \
-    X(8, 8, 0)          \
-    X(8, 16, 0)         \
-    X(16, 4, 0)         \
-    X(16, 8, 0)         \
-    X(16, 16, 0)        \
-    X(24, 4, 0)         \
-    X(24, 8, 0)         \
-    X(24, 16, 0)        \
-    X(32, 4, 0)         \
-    X(32, 8, 0)         \
-    X(32, 16, 0)        \
-    X(40, 8, 0)         \
-    X(40, 16, 0)        \
-    X(48, 8, 0)         \
-    X(48, 16, 0)
+    X(4, 4, 0) \
+    X(4, 4, 4) \
+    X(8, 4, 0) \
+    X(8, 8, 0) \
+    X(8, 16, 0) \
+    X(16, 4, 0) \
+    X(16, 8, 0)
 
 namespace oqp {
 
 template <int NX, int NU, int NG, bool MIXED>
 void launch_ipm(const InstDesc* desc, int count, const double* data, double* iter, double* work, double* step,
                 DevStat* stat, KParams P, hipStream_t stream);
+
+// block kernel (runtime stage sizes, 256 threads per instance)
+int block_lds_bytes(int nx, int nu, int ng);
+int block_zmax(int nz);  // compile-time bound used for a stage block of nz (0: too large)
+// general rows: kernels for ng == 0 and for 0 < ng <= 64
+int block_launch(int zm, int gm, int mixed, const InstDesc* desc, int count, const double* data, double* iter,
+                 double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
 
 }  // namespace oqp

@@ -110,6 +110,8 @@ struct InstDesc {
     int32_t nc;     // number of two-sided constraints (box + general)
     int32_t index;  // position of the instance in the caller's batch
     int32_t pad;
+    int32_t nx, nu, ng;  // padded stage sizes (read by the runtime-sized block kernel)
+    int32_t pad2;
 };
 
 // Per-instance result written by the kernel.

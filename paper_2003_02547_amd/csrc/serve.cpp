@@ -36,9 +36,10 @@ constexpr uint32_t kPackMagic = 0x4f515031u;  // "OQP1"
 // Header of a packed request; offsets in bytes from the blob start.
 struct PackHdr {
     uint32_t magic;
-    int32_t variant;
+    int32_t variant;  // kernel group
     int32_t N;
     int32_t nc;
+    int32_t nx, nu, ng, pad;  // padded stage sizes of the records
     int64_t data_doubles, iter_doubles, work_doubles;
     int64_t dims_off, slots_off, data_off;
     int64_t total;
@@ -56,7 +57,7 @@ int read_hdr(const void* packed, const PackHdr** out)
     if ((uintptr_t)packed % 8) return fail(OQP_EINVAL, "packed request not 8-byte aligned");
     const PackHdr* h = (const PackHdr*)packed;
     if (h->magic != kPackMagic) return fail(OQP_EINVAL, "not a packed request (bad magic)");
-    if (h->variant < 0 || h->variant >= oqp::variant_count()) return fail(OQP_EINVAL, "packed request: bad variant");
+    if (h->variant < 0 || h->variant >= group_count()) return fail(OQP_EINVAL, "packed request: bad kernel group");
     *out = h;
     return OQP_OK;
 }
@@ -247,6 +248,10 @@ int launch_group(oqp_server* s, int v, int gi)
         d.nc = h->nc;
         d.index = cnt;
         d.pad = 0;
+        d.nx = h->nx;
+        d.nu = h->nu;
+        d.ng = h->ng;
+        d.pad2 = 0;
         hipError_t e = hipMemcpyAsync(s->arena + q.dev_off, (const char*)h + h->data_off,
                                       sizeof(double) * h->data_doubles, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return fail(OQP_EDEVICE, "server: request upload: %s", hipGetErrorString(e));
@@ -266,12 +271,12 @@ int launch_group(oqp_server* s, int v, int gi)
     if (e != hipSuccess) return fail(OQP_EDEVICE, "server: descriptor upload: %s", hipGetErrorString(e));
     const int mixed = s->arg.mode == OQP_MODE_MIXED;
     oqp::KParams P = make_params(s->arg, oqp::KMODE_SOLVE, 0.0);
-    if (oqp::variant_launch(v, mixed, g.ddesc, cnt, base, base, base, base, g.dstat, P, st))
-        return fail(OQP_EDEVICE, "server: kernel launch failed for variant %d", v);
+    if (group_launch(v, mixed, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
+        return fail(OQP_EDEVICE, "server: kernel launch failed for group %d", v);
     if (mixed) {
         P.mode = oqp::KMODE_FALLBACK;
-        if (oqp::variant_launch(v, 0, g.ddesc, cnt, base, base, base, base, g.dstat, P, st))
-            return fail(OQP_EDEVICE, "server: fallback launch failed for variant %d", v);
+        if (group_launch(v, 0, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
+            return fail(OQP_EDEVICE, "server: fallback launch failed for group %d", v);
     }
     e = hipMemcpyAsync(g.hstat, g.dstat, sizeof(DevStat) * cnt, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipEventRecord(g.ev, st);
@@ -291,19 +296,20 @@ int launch_group(oqp_server* s, int v, int gi)
 // packing
 // ---------------------------------------------------------------------------
 
-static void pack_sizes(const oqp_qp* q, int v, PackHdr* h)
+static void pack_sizes(const oqp_qp* q, const KSel& ks, PackHdr* h)
 {
     const oqp_dims* d = q->dims;
-    int nx, nu, ng;
-    oqp::variant_dims(v, &nx, &nu, &ng);
-    const Layout L = oqp::make_layout(nx, nu, ng);
+    const Layout L = oqp::make_layout(ks.nx, ks.nu, ks.ng);
     int nc = 0;
     for (int n = 0; n <= d->N; ++n) nc += d->nbu[n] + d->nbx[n] + d->ng[n];
     std::memset(h, 0, sizeof(*h));
     h->magic = kPackMagic;
-    h->variant = v;
+    h->variant = ks.group;
     h->N = d->N;
     h->nc = nc;
+    h->nx = ks.nx;
+    h->nu = ks.nu;
+    h->ng = ks.ng;
     h->data_doubles = (int64_t)(d->N + 1) * L.SREC;
     h->iter_doubles = (int64_t)(d->N + 1) * L.IREC;
     h->work_doubles = (int64_t)(d->N + 1) * L.WREC;
@@ -320,10 +326,10 @@ static void pack_sizes(const oqp_qp* q, int v, PackHdr* h)
 extern "C" int oqp_pack_bytes(const oqp_qp* qp, size_t* bytes)
 {
     if (!qp || !bytes) return fail(OQP_EINVAL, "oqp_pack_bytes: NULL argument");
-    const int v = pick_variant(qp->dims);
-    if (v < 0) return fail(OQP_EINVAL, "oqp_pack_bytes: no kernel variant covers the stage sizes");
+    KSel ks;
+    if (select_kernel(qp->dims, &ks)) return fail(OQP_EINVAL, "oqp_pack_bytes: no kernel covers the stage sizes");
     PackHdr h;
-    pack_sizes(qp, v, &h);
+    pack_sizes(qp, ks, &h);
     *bytes = (size_t)h.total;
     return OQP_OK;
 }
@@ -332,10 +338,10 @@ extern "C" int oqp_pack(const oqp_qp* qp, void* mem, size_t bytes)
 {
     if (!qp || !mem) return fail(OQP_EINVAL, "oqp_pack: NULL argument");
     if ((uintptr_t)mem % 64) return fail(OQP_EINVAL, "oqp_pack: memory not 64-byte aligned");
-    const int v = pick_variant(qp->dims);
-    if (v < 0) return fail(OQP_EINVAL, "oqp_pack: no kernel variant covers the stage sizes");
+    KSel ks;
+    if (select_kernel(qp->dims, &ks)) return fail(OQP_EINVAL, "oqp_pack: no kernel covers the stage sizes");
     PackHdr h;
-    pack_sizes(qp, v, &h);
+    pack_sizes(qp, ks, &h);
     if (bytes < (size_t)h.total) return fail(OQP_ENOMEM, "oqp_pack: %zu < %lld bytes", bytes, (long long)h.total);
     char* b = (char*)mem;
     std::memset(b, 0, (size_t)h.data_off);
@@ -349,9 +355,7 @@ extern "C" int oqp_pack(const oqp_qp* qp, void* mem, size_t bytes)
         dims5[3 * (d->N + 1) + n] = d->nbx[n];
         dims5[4 * (d->N + 1) + n] = d->ng[n];
     }
-    int nx, nu, ng;
-    oqp::variant_dims(v, &nx, &nu, &ng);
-    return pack_records(qp, oqp::make_layout(nx, nu, ng), (double*)(b + h.data_off), (int*)(b + h.slots_off));
+    return pack_records(qp, oqp::make_layout(h.nx, h.nu, h.ng), (double*)(b + h.data_off), (int*)(b + h.slots_off));
 }
 
 extern "C" int oqp_pack_footprint(const void* packed, size_t* dev_bytes, int* variant)
@@ -416,7 +420,7 @@ extern "C" int oqp_server_init(const oqp_server_cfg* cfg, const oqp_arg* arg, vo
     std::memset(s, 0, sizeof(*s));
     s->cfg = *cfg;
     s->arg = *arg;
-    s->nvar = oqp::variant_count();
+    s->nvar = group_count();
     s->nstreams = nstreams;
     for (int k = 0; k < nstreams; ++k) s->streams[k] = (hipStream_t)streams[k];
     s->req = (Request*)(h + p.h_req);
@@ -565,10 +569,8 @@ extern "C" int oqp_server_get_sol(oqp_server* s, uint64_t ticket, double* u, dou
     hipError_t e = hipMemcpyAsync(s->staging, s->arena + r.dev_off + db, bytes, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_server_get_sol: %s", hipGetErrorString(e));
-    int nx, nu, ng;
-    oqp::variant_dims(h->variant, &nx, &nu, &ng);
     iterate_user_copy((const int*)((const char*)h + h->dims_off), h->N, (const int*)((const char*)h + h->slots_off),
-                      oqp::make_layout(nx, nu, ng), s->staging, true, u, x, pi, lam_l, lam_u, t_l, t_u);
+                      oqp::make_layout(h->nx, h->nu, h->ng), s->staging, true, u, x, pi, lam_l, lam_u, t_l, t_u);
     return OQP_OK;
 }
 
