@@ -1,10 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark: batched OCP-QP solves per second on one MI355X.
 
-Workload: 1024 same-size mass-spring QPs (8 masses: nx=16, nu=7, N=30,
-dt=0.2, Q=I, R=0.1 I, |u|<=0.5, |x_pos|<=4, x0 ~ U[-2,2]^16 per instance),
-synthetic and seeded, resident in HBM before the timed region.  One step =
-one full IPM solve of the whole batch (cold start to the KKT tolerance).
+Workload (the headline value): 1024 same-size mass-spring QPs (8 masses:
+nx=16, nu=7, N=30, dt=0.2, Q=I, R=0.1 I, |u|<=0.5, |x_pos|<=4, x0 ~
+U[-2,2]^16 per instance), synthetic and seeded, resident in HBM before the
+timed region.  One step = one full IPM solve of the whole batch (cold start
+to the KKT tolerance), FP64 path; the mixed path is timed beside it.
+
+Further legs on the same line (context, not the headline):
+  * uneven: a batch of random stable OCP QPs with nx ~ U{4..48},
+    nu ~ U{1..16}, N ~ U{10..100} (one-wave variants plus the block kernel);
+  * serve: the continuous-batching server replaying Poisson arrivals over a
+    pool of uneven instances: saturated throughput at the offered rate, then
+    p50/p99 latency at a sustainable rate, for the grouped FP64 and mixed
+    paths and the plain per-request FP64 path (one launch per request).
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
 (algorithmic bytes / kernel time from HIP events on the launch stream) and
@@ -31,7 +40,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("ipm_kernel.h", "layout.h"):
+    for f in ("ipm_kernel.h", "dev_common.h", "layout.h"):
         with open(os.path.join(ROOT, "paper_2003_02547_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -75,6 +84,78 @@ def cpu_baseline(qps, seconds, tol):
                       f"{threads} threads, one instance per thread at a time, {el:.1f} s"}
 
 
+def leg_uneven(B, W, torch, np, count, steps, seed0=0):
+    """Uneven batch: every instance solved in one batch solve (one launch per
+    kernel group on the batch stream)."""
+    qps = [W.random_uneven(seed0 + i) for i in range(count)]
+    out = {}
+    for name, mode in (("f64", B.MODE_F64), ("mixed", B.MODE_MIXED)):
+        batch = B.Batch(qps, B.default_arg(mode)).load().sync()
+        batch.solve()
+        torch.cuda.synchronize()
+        st = batch.stream
+        ms = []
+        for _ in range(steps):
+            s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s_.record(st)
+            batch.solve()
+            e_.record(st)
+            torch.cuda.synchronize()
+            ms.append(s_.elapsed_time(e_))
+        batch.fetch().sync()
+        stats = [batch.stat(i) for i in range(count)]
+        ok = sum(1 for x in stats if x.status == B.SUCCESS and max(x.res[:]) <= KKT_OK)
+        groups = sorted({batch.variant(i)[0] for i in range(count)})
+        nv = B.lib().oqp_variant_count()
+        out[name] = {"value": round(ok / (float(np.median(ms)) * 1e-3), 1), "unit": "solves/s",
+                     "ms_per_step": round(float(np.median(ms)), 3), "solves_ok": ok,
+                     "block_kernel_instances": sum(1 for i in range(count) if batch.variant(i)[0] >= nv),
+                     "kernel_groups": len(groups)}
+        del batch
+    out["instances"] = count
+    out["sizes"] = "nx~U{4..48}, nu~U{1..16}, N~U{10..100}, boxes on all u and x"
+    return out
+
+
+def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_seconds, per_req_seconds, log):
+    """Continuous-batching server, native real-time replay of Poisson
+    arrivals over a pool of pre-packed uneven instances (page-locked host
+    memory; each request's data is uploaded on admission)."""
+    pool = [W.random_uneven(100000 + i) for i in range(pool_n)]
+    packed = [B.Packed(q, pinned=True) for q in pool]
+    dev_bytes = int(min(64 << 30, 2 * sum(p.footprint for p in packed) + (1 << 30)))
+    tol = dict(tol_stat=KKT_OK, tol_eq=KKT_OK, tol_ineq=KKT_OK, tol_comp=KKT_OK)
+
+    def run(mode, max_launch, rate, seconds, seed):
+        srv = B.Server(B.default_arg(mode, **tol), dev_bytes=dev_bytes, nstreams=5, max_launch=max_launch,
+                       max_requests=4096, max_groups=1024)
+        try:
+            times, idx = W.serving_stream(rate, seconds, pool_n, seed=seed)
+            lat, stats, wall = srv.replay([packed[i] for i in idx], times, timeout=120.0)
+            c = srv.stats()
+        finally:
+            srv.close()
+        ok = sum(1 for x in stats if x.status == B.SUCCESS)
+        return {"offered_per_s": rate, "requests": len(times), "served_per_s": round(ok / wall, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "launches": int(c["launches"]),
+                "dev_peak_mb": round(c["dev_peak"] / 2**20, 1), "wall_s": round(wall, 2)}
+
+    log(f"bench: serve warm-up and saturation at {offered:.0f} req/s offered")
+    run(B.MODE_F64, 256, offered, 0.05, 1)
+    sat = run(B.MODE_F64, 256, offered, sat_seconds, 2)
+    rate = max(10.0, round(sus_frac * sat["served_per_s"], -1))
+    out = {"pool": pool_n, "saturated_f64": sat, "sustained_rate_per_s": rate}
+    for name, mode, ml in (("f64", B.MODE_F64, 256), ("mixed", B.MODE_MIXED, 256)):
+        log(f"bench: serve {name} at {rate:.0f} req/s for {sus_seconds:.0f} s")
+        out[name] = run(mode, ml, rate, sus_seconds, 3)
+    # plain per-request FP64 path (one launch per request): same offered rate
+    # over a shorter window, since it saturates far below that rate
+    log(f"bench: serve f64_per_request at {rate:.0f} req/s for {per_req_seconds:.2f} s")
+    out["f64_per_request"] = run(B.MODE_F64, 1, rate, per_req_seconds, 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +165,14 @@ def main():
     ap.add_argument("--mode", choices=["f64"], default="f64")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--uneven", type=int, default=4096, help="instances of the uneven leg (0: skip)")
+    ap.add_argument("--uneven-steps", type=int, default=3)
+    ap.add_argument("--serve-pool", type=int, default=256, help="distinct instances in the serving pool (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=20000.0, help="offered Poisson rate for the saturation run")
+    ap.add_argument("--serve-sat-seconds", type=float, default=0.25)
+    ap.add_argument("--serve-frac", type=float, default=0.5, help="sustained rate as a fraction of saturated throughput")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-per-request-seconds", type=float, default=0.2)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -191,6 +280,13 @@ def main():
                   "max_kkt_res": float(np.max(m["kkt"][m["status"] == B.SUCCESS])),
                   "vs_f64": round(m["value"] / f["value"], 3)},
     }
+    del f["del_batch"], m["del_batch"]
+    if args.uneven > 0:
+        log(f"bench: uneven leg, {args.uneven} instances")
+        line["uneven"] = leg_uneven(B, W, torch, np, args.uneven, args.uneven_steps)
+    if args.serve_pool > 0:
+        line["serve"] = leg_serve(B, W, torch, np, args.serve_pool, args.serve_rate, args.serve_sat_seconds,
+                                  args.serve_frac, args.serve_seconds, args.serve_per_request_seconds, log)
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         line["cpu_baseline"] = cpu_baseline(qps, args.cpu_seconds, 1e-8)

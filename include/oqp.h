@@ -193,10 +193,12 @@ int oqp_pack_footprint(const void* packed, size_t* dev_bytes, int* variant);
 /* Requests (packed QPs of any covered size) are admitted when a block of the
  * device arena large enough for their footprint is free (first-fit; freed on
  * release), otherwise submit returns OQP_EBUSY and the caller retries later.
- * oqp_server_progress retires finished launches and launches every admitted
- * request, grouped by kernel variant (at most max_launch per launch), on the
- * least-loaded of streams[1..nstreams-1], so requests that arrive while others
- * run start without waiting for them.  streams[0] serves oqp_server_get_sol.
+ * oqp_server_progress retires finished launches and, on each idle stream of
+ * streams[1..nstreams-1] (one with no launch in flight), launches the queued
+ * requests of one kernel group (the oldest request's, at most max_launch per
+ * launch): requests that arrive while the device is busy join the next
+ * launch, so launches grow with the load and several run at once.
+ * streams[0] serves oqp_server_get_sol.
  * The solver arguments (mode included) are fixed at init.  A server is used
  * from one host thread at a time. */
 #define OQP_SERVER_MAX_STREAMS 32

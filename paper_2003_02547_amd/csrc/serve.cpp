@@ -5,9 +5,10 @@
 // the caller's device buffer large enough for its data, iterate and
 // workspace records is free (first-fit, coalescing on release), so admission
 // is by HBM footprint.  oqp_server_progress retires finished launches (one
-// event per launch) and launches the admitted requests grouped by kernel
-// variant on the least-loaded of the caller's streams, so requests that
-// arrive while earlier launches run start at once and overlap on the device.
+// event per launch) and, on every idle stream, launches the queued requests
+// of one kernel group together: a request that arrives while the device is
+// busy joins the next launch, launches run concurrently on the caller's
+// streams, and their size follows the load.
 // The IPM state of a request stays in its device block from admission to
 // release; every IPM iteration runs inside one kernel launch.
 //
@@ -208,20 +209,22 @@ int free_group(const oqp_server* s)
     return -1;
 }
 
+// An idle launch stream (none of its launches in flight), or -1.  Stream 0
+// is kept for solution fetches.  A launch therefore never queues behind
+// another one: while every stream is busy, arriving requests accumulate and
+// the next idle stream takes all of them (of one kernel group) at once, so
+// launches grow with the load.
 int pick_stream(const oqp_server* s)
 {
-    // stream 0 is kept for solution fetches
-    int best = 1;
-    for (int k = 2; k < s->nstreams; ++k)
-        if (s->sq_len[k] < s->sq_len[best]) best = k;
-    return best;
+    for (int k = 1; k < s->nstreams; ++k)
+        if (s->sq_len[k] == 0) return k;
+    return -1;
 }
 
 // Launch one group: the queued requests of variant v, oldest first.
-int launch_group(oqp_server* s, int v, int gi)
+int launch_group(oqp_server* s, int v, int gi, int k)
 {
     Group& g = s->grp[gi];
-    const int k = pick_stream(s);
     hipStream_t st = s->streams[k];
     double* base = (double*)s->arena;
     int cnt = 0;
@@ -513,11 +516,14 @@ extern "C" int oqp_server_progress(oqp_server* s, int* ncompleted)
     if (ncompleted) *ncompleted = 0;
     int rc = retire(s, ncompleted);
     if (rc) return rc;
-    // launch queued requests, one group per variant present, oldest first
+    // launch queued requests on idle streams: the kernel group of the oldest
+    // queued request, all of its queued requests up to max_launch
     while (s->q_head >= 0) {
+        const int k = pick_stream(s);
+        if (k < 0) break;
         const int gi = free_group(s);
         if (gi < 0) break;
-        rc = launch_group(s, s->req[s->q_head].hdr->variant, gi);
+        rc = launch_group(s, s->req[s->q_head].hdr->variant, gi, k);
         if (rc) return rc;
     }
     return OQP_OK;
