@@ -1367,8 +1367,14 @@ struct Ipm {
                 amax = passB(rmode, shift, Lo.W_rb, Lo.W_rdl, Lo.W_rdu, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, s1, s2);
                 __syncthreads();
                 if constexpr (MIXED) {
-                    const double rnorm = fmax(1.0, fmax(fmax(ng, nb), fmax(nd, nm)));
-                    ir_steps += refine(rmode, shift, rnorm, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, amax, s1, s2);
+                    // refinement of the prediction-centering-correction
+                    // direction (Section 4.2); the affine predictor only
+                    // feeds the centering parameter and the corrector
+                    // right-hand side and is used unrefined
+                    if (round > 0 || newton_mode || nc == 0) {
+                        const double rnorm = fmax(1.0, fmax(fmax(ng, nb), fmax(nd, nm)));
+                        ir_steps += refine(rmode, shift, rnorm, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, amax, s1, s2);
+                    }
                 }
                 if (newton_mode || nc == 0) break;
                 const double a = fmin(amax, 1.0);
