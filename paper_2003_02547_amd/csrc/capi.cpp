@@ -377,11 +377,11 @@ int pick_variant(const oqp_dims* d)
 // larger instances go to the block kernel, padded only to their own maximum
 // stage sizes.
 static int g_wave_max_nz = 24;
-static const int kBlockZ[4] = {32, 32, 64, 64};
-static const int kBlockG[4] = {0, 64, 0, 64};
+static const int kBlockZ[6] = {32, 32, 64, 64, 256, 256};
+static const int kBlockG[6] = {0, 64, 0, 64, 0, 64};
 static constexpr size_t kMaxLds = 160 * 1024;
 
-int group_count() { return oqp::variant_count() + 4; }
+int group_count() { return oqp::variant_count() + 6; }
 
 int select_kernel(const oqp_dims* d, KSel* out)
 {
@@ -402,9 +402,11 @@ int select_kernel(const oqp_dims* d, KSel* out)
     }
     if (mx < 1) mx = 1;
     const int zm = oqp::block_zmax(mx + mu);
-    if (zm == 0 || mg > 64) return -1;
+    // one thread per row and per constraint slot; the u block is solved on
+    // one wave
+    if (zm == 0 || mg > 64 || mu > 64 || mx + mu + mg > 256) return -1;
     if ((size_t)oqp::block_lds_bytes(mx, mu, mg) > kMaxLds) return -1;
-    const int b = (zm == 64 ? 2 : 0) + (mg > 0 ? 1 : 0);
+    const int b = (zm == 256 ? 4 : (zm == 64 ? 2 : 0)) + (mg > 0 ? 1 : 0);
     *out = KSel{oqp::variant_count() + b, mx, mu, mg};
     return OQP_OK;
 }

@@ -36,14 +36,21 @@ constexpr int BGMAX = 64;  // general rows per stage supported by the block kern
 // LDS plan (offsets in doubles) for padded stage sizes NX, NU, NG.
 struct BLds {
     int ldm, ldf, ldg, ldx, ldv;  // odd leading dimensions: column-strided access spreads over the banks
-    int oM, oF, oG, oLx, oV, oz, orb, ot1, ot2, oe, ows, oxn, opin, opn, odv, ocol, ored, oflag, total;
+    int oM, oF, oG, oLx, oV, oz, orb, ot1, ot2, oe, ows, oxn, opin, opn, odv, odd, ol11, ocol, ored, oflag, total;
 };
 
 OQP_HD constexpr int bmaxi(int a, int b) { return a > b ? a : b; }
 
+// Global-memory mode (stage blocks above 64): the stage matrix and its
+// factor live in the instance's factor record, F and G are read in place,
+// U' = [L_{n+1}' F; sqrt(w) G] goes to a workspace block, and LDS holds only
+// vectors.
+OQP_HD constexpr bool block_global(int NX, int NU) { return NX + NU > 64; }
+
 OQP_HD constexpr BLds make_blds(int NX, int NU, int NG)
 {
     const int NZ = NX + NU, NC = NZ + NG, NV = NX + NG;
+    const bool gl = block_global(NX, NU);
     BLds s{};
     s.ldm = NZ | 1;
     s.ldf = NX | 1;
@@ -51,11 +58,11 @@ OQP_HD constexpr BLds make_blds(int NX, int NU, int NG)
     s.ldx = NX | 1;
     s.ldv = NV | 1;
     int o = 0;
-    s.oM = o; o += s.ldm * NZ;                       // H / stage matrix / factor; factor columns in the forward sweeps
-    s.oF = o; o += s.ldf * NZ;                       // [B A]
-    s.oG = o; o += NG > 0 ? s.ldg * NZ : 0;          // G
-    s.oLx = o; o += s.ldx * NX;                      // L_{n+1} (lower, zero strict upper)
-    s.oV = o; o += s.ldv * NZ;                       // [U; sqrt(w) G]
+    s.oM = o; o += gl ? 0 : s.ldm * NZ;              // H / stage matrix / factor; factor columns in the forward sweeps
+    s.oF = o; o += gl ? 0 : s.ldf * NZ;              // [B A]
+    s.oG = o; o += (gl || NG == 0) ? 0 : s.ldg * NZ; // G
+    s.oLx = o; o += gl ? 0 : s.ldx * NX;             // L_{n+1} (lower, zero strict upper)
+    s.oV = o; o += gl ? 0 : s.ldv * NZ;              // [U; sqrt(w) G]
     s.oz = o; o += NZ;
     s.orb = o; o += bmaxi(NX, 1);
     s.ot1 = o; o += bmaxi(bmaxi(NX, NG), 1);
@@ -66,6 +73,8 @@ OQP_HD constexpr BLds make_blds(int NX, int NU, int NG)
     s.opin = o; o += 2 * bmaxi(NX, 1);
     s.opn = o; o += 2 * bmaxi(NX, 1);
     s.odv = o; o += NZ;
+    s.odd = o; o += NZ;                              // FP64 running diagonal (mixed Cholesky)
+    s.ol11 = o; o += 16 * 16;                        // diagonal block of the current Cholesky panel
     s.ocol = o; o += 64;
     s.ored = o; o += 32;
     s.oflag = o; o += 2;
@@ -102,7 +111,7 @@ __device__ __forceinline__ double* blds()
     return oqp_blds_dyn;
 }
 
-template <bool MIXED, int ZM, int GM>
+template <bool MIXED, int ZM, int GM, bool GL>
 struct Blk {
     using TS = typename std::conditional<MIXED, float, double>::type;
     Layout Lo;
@@ -113,6 +122,16 @@ struct Blk {
     double* __restrict__ wk;
     int N, nc, tid, lane, wid;
     const KParams& P;
+    // leading dimensions of the stage blocks (LDS copies, or the records in
+    // global-memory mode)
+    int ldm, ldf, ldg, ldx, ldv;
+    // global-memory mode: stage blocks of the current stage
+    mutable double* cM;
+    mutable const double* cF;
+    mutable const double* cG;
+    mutable const double* cLx;
+    mutable const double* cXC;
+    mutable double* cV;
 
     __device__ __forceinline__ Blk(const InstDesc& ds, const double* d, double* i, double* w, const KParams& P_)
         : Lo(make_layout(ds.nx, ds.nu, ds.ng)), S(make_blds(ds.nx, ds.nu, ds.ng)), NX(ds.nx), NU(ds.nu), NG(ds.ng),
@@ -120,18 +139,37 @@ struct Blk {
           wk(w + ds.work), N(ds.N), nc(ds.nc), tid((int)threadIdx.x), lane((int)threadIdx.x & 63),
           wid((int)threadIdx.x >> 6), P(P_)
     {
+        if constexpr (GL) {
+            ldm = NZ;
+            ldf = NX;
+            ldg = NG;
+            ldx = NZ;
+            ldv = NV;
+        } else {
+            ldm = S.ldm;
+            ldf = S.ldf;
+            ldg = S.ldg;
+            ldx = S.ldx;
+            ldv = S.ldv;
+        }
+        cM = cV = nullptr;
+        cF = cG = cLx = cXC = nullptr;
     }
 
     __device__ __forceinline__ const double* Dp(int n) const { return dat + (size_t)n * Lo.SREC; }
     __device__ __forceinline__ double* Ip(int n) const { return itr + (size_t)n * Lo.IREC; }
     __device__ __forceinline__ double* Wp(int n) const { return wk + (size_t)n * Lo.WREC; }
 
-    // LDS arrays
-    __device__ __forceinline__ double* M() const { return blds() + S.oM; }
-    __device__ __forceinline__ double* F() const { return blds() + S.oF; }
-    __device__ __forceinline__ double* G() const { return blds() + S.oG; }
-    __device__ __forceinline__ double* Lx() const { return blds() + S.oLx; }
-    __device__ __forceinline__ double* V() const { return blds() + S.oV; }
+    // stage blocks: LDS copies, or the records themselves in global-memory mode
+    __device__ __forceinline__ double* M() const { return GL ? cM : blds() + S.oM; }
+    __device__ __forceinline__ double* F() const { return GL ? const_cast<double*>(cF) : blds() + S.oF; }
+    __device__ __forceinline__ double* G() const { return GL ? const_cast<double*>(cG) : blds() + S.oG; }
+    __device__ __forceinline__ double* Lx() const { return GL ? const_cast<double*>(cLx) : blds() + S.oLx; }
+    __device__ __forceinline__ double* V() const { return GL ? cV : blds() + S.oV; }
+    // first x-column of the next stage's factor (passes B and C)
+    __device__ __forceinline__ const double* XC() const { return GL ? cXC : blds() + S.oM + NU * ldm; }
+    __device__ __forceinline__ double* ddv() const { return blds() + S.odd; }
+    __device__ __forceinline__ double* l11() const { return blds() + S.ol11; }
     __device__ __forceinline__ double* z() const { return blds() + S.oz; }
     __device__ __forceinline__ double* rbv() const { return blds() + S.orb; }
     __device__ __forceinline__ double* t1() const { return blds() + S.ot1; }
@@ -242,9 +280,9 @@ struct Blk {
     // stage prefetch: three flat blocks of global memory (element e = tid +
     // BT t of each) into registers, committed to LDS at the next stage
     // ------------------------------------------------------------------
-    static constexpr int EA = (ZM * ZM + BT - 1) / BT;           // H, or the factor columns
-    static constexpr int EF = (ZM * ZM + BT - 1) / BT;           // F
-    static constexpr int EG = GM > 0 ? (GM * ZM + BT - 1) / BT : 1;
+    static constexpr int EA = GL ? 1 : (ZM * ZM + BT - 1) / BT;           // H, or the factor columns
+    static constexpr int EF = GL ? 1 : (ZM * ZM + BT - 1) / BT;           // F
+    static constexpr int EG = (GL || GM == 0) ? 1 : (GM * ZM + BT - 1) / BT;
 
     struct Pre {
         double a[EA], f[EF], g[EG];
@@ -257,6 +295,7 @@ struct Blk {
 
     __device__ __forceinline__ void fetch(Pre& p) const
     {
+        if constexpr (GL) return;
 #pragma unroll
         for (int t = 0; t < EA; ++t) {
             const int e = tid + BT * t;
@@ -279,12 +318,13 @@ struct Blk {
 
     __device__ __forceinline__ void commit(const Pre& p, double* da, double* df, double* dg) const
     {
+        if constexpr (GL) return;
         {
             Walk q(NZ, tid);
 #pragma unroll
             for (int t = 0; t < EA; ++t) {
                 const int e = tid + BT * t;
-                if (e < p.na) da[q.r + q.c * S.ldm] = p.a[t];
+                if (e < p.na) da[q.r + q.c * ldm] = p.a[t];
                 q.next();
             }
         }
@@ -293,7 +333,7 @@ struct Blk {
 #pragma unroll
             for (int t = 0; t < EF; ++t) {
                 const int e = tid + BT * t;
-                if (e < p.nf) df[q.r + q.c * S.ldf] = p.f[t];
+                if (e < p.nf) df[q.r + q.c * ldf] = p.f[t];
                 q.next();
             }
         }
@@ -302,7 +342,7 @@ struct Blk {
 #pragma unroll
             for (int t = 0; t < EG; ++t) {
                 const int e = tid + BT * t;
-                if (e < p.ng) dg[q.r + q.c * S.ldg] = p.g[t];
+                if (e < p.ng) dg[q.r + q.c * ldg] = p.g[t];
                 q.next();
             }
         }
@@ -334,6 +374,44 @@ struct Blk {
         p.nf = n < N ? NX * NZ : 0;
         p.sg = d + Lo.D_G;
         p.ng = NG * NZ;
+    }
+
+    // global-memory mode: point the stage blocks at the records of stage n.
+    // Pass A builds the stage matrix in the stage's factor record (H copied
+    // in first; the factor then stays there) with L_{n+1} read from the next
+    // stage's record; pass R reads H in place; passes B and C read the u
+    // columns of this stage's factor and the x columns of the next one's.
+    __device__ __forceinline__ void stage_A(int n) const
+    {
+        if constexpr (GL) {
+            const double* d = Dp(n);
+            cM = Wp(n) + Lo.W_L;
+            cF = d + Lo.D_F;
+            cG = d + Lo.D_G;
+            cLx = n < N ? Wp(n + 1) + Lo.W_L + NU + NU * NZ : cM;
+            cV = Wp(n) + Lo.W_V;
+            const double* h = d + Lo.D_H;
+            for (int e = opq(tid); e < NZ * NZ; e += BT) cM[e] = h[e];
+        }
+    }
+    __device__ __forceinline__ void stage_R(int n) const
+    {
+        if constexpr (GL) {
+            const double* d = Dp(n);
+            cM = const_cast<double*>(d + Lo.D_H);
+            cF = d + Lo.D_F;
+            cG = d + Lo.D_G;
+        }
+    }
+    __device__ __forceinline__ void stage_BC(int n) const
+    {
+        if constexpr (GL) {
+            const double* d = Dp(n);
+            cM = Wp(n) + Lo.W_L;
+            cXC = n < N ? Wp(n + 1) + Lo.W_L + NU * NZ : cM;
+            cF = d + Lo.D_F;
+            cG = d + Lo.D_G;
+        }
     }
 
     // constraint slot data: mask, lower, upper (slot c: box on z_c for c <
@@ -382,9 +460,9 @@ struct Blk {
             for (int l = i0; l < NX; ++l) {
                 TS lv[4], fv[4];
 #pragma unroll
-                for (int p = 0; p < 4; ++p) lv[p] = (TS)L[l + ic[p] * S.ldx];
+                for (int p = 0; p < 4; ++p) lv[p] = (TS)L[l + ic[p] * ldx];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) fv[q] = (TS)f[l + kc[q] * S.ldf];
+                for (int q = 0; q < 4; ++q) fv[q] = (TS)f[l + kc[q] * ldf];
 #pragma unroll
                 for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -394,7 +472,7 @@ struct Blk {
             for (int p = 0; p < 4; ++p)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (i0 + p < NX && k0 + q < NZ) v[(i0 + p) + (k0 + q) * S.ldv] = (double)acc[p][q];
+                    if (i0 + p < NX && k0 + q < NZ) v[(i0 + p) + (k0 + q) * ldv] = (double)acc[p][q];
         }
     }
 
@@ -424,9 +502,9 @@ struct Blk {
             for (int r = r0; r < NV; ++r) {
                 TS vi[4], vk[4];
 #pragma unroll
-                for (int p = 0; p < 4; ++p) vi[p] = (TS)v[r + ic[p] * S.ldv];
+                for (int p = 0; p < 4; ++p) vi[p] = (TS)v[r + ic[p] * ldv];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) vk[q] = (TS)v[r + kc[q] * S.ldv];
+                for (int q = 0; q < 4; ++q) vk[q] = (TS)v[r + kc[q] * ldv];
 #pragma unroll
                 for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -436,68 +514,108 @@ struct Blk {
             for (int p = 0; p < 4; ++p)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (i0 + p < NZ && k0 + q < NZ) m[(i0 + p) + (k0 + q) * S.ldm] += (double)acc[p][q];
+                    if (i0 + p < NZ && k0 + q < NZ) m[(i0 + p) + (k0 + q) * ldm] += (double)acc[p][q];
         }
     }
 
-    // Blocked right-looking Cholesky of M (NZ x NZ <= 64 x 64, lower triangle
-    // read), panels of PW columns: wave 0 factors a panel with one row per
-    // lane (panel rows in registers), then all four waves apply the panel to
-    // the trailing lower triangle with 4 x 4 register tiles.  Writes L back
-    // into M (each panel write-back zeroes the rows above the diagonal of its
-    // columns) and 1/L_ii into dv.  Every thread calls
-    // it; returns false (in every thread) when a pivot is not positive.
-    // Mixed path: FP32 entries and updates, each row's diagonal accumulated
-    // in FP64 (FP64 pivots).
+    // Blocked right-looking Cholesky of M (NZ x NZ, lower triangle read) with
+    // panels of PW columns: wave 0 factors the PW x PW diagonal block (one
+    // row per lane, rows in registers, column entries by readlane) and copies
+    // it to LDS; every thread then solves one row of the block below it
+    // against that factor (L21 = M21 L11^{-T}), and all threads apply the
+    // panel to the trailing lower triangle with 4 x 4 register tiles.  Writes
+    // L (zero strict upper part) back into M and 1/L_ii into dv.  Every
+    // thread calls it; returns false (in every thread) when a pivot is not
+    // positive.  Mixed path: FP32 entries and updates, each row's diagonal
+    // accumulated in FP64 (FP64 pivots).
     static constexpr int PW = 16;
 
     __device__ __forceinline__ bool cholesky() const
     {
         double* m = M();
-        double dd = 0.0;  // wave 0: FP64 running diagonal of row `lane` (mixed path)
+        double* dd = ddv();
+        double* lb = l11();
         bool ok = true;
-        if (wid == 0 && MIXED) dd = lane < NZ ? m[lane + lane * S.ldm] : 1.0;
+        if constexpr (MIXED) {
+            for (int i = opq(tid); i < NZ; i += BT) dd[i] = m[i + i * ldm];
+            __syncthreads();
+        }
         for (int p0 = 0; p0 < NZ; p0 += PW) {
             const int pw = min(PW, NZ - p0);
+            const int p1 = p0 + pw;
+            // diagonal block on wave 0: lane q holds row p0 + q
             if (wid == 0) {
+                const bool act = lane < pw;
+                const int i = p0 + min(lane, pw - 1);
                 double r[PW];
 #pragma unroll
                 for (int q = 0; q < PW; ++q) {
-                    r[q] = (lane >= p0 && lane < NZ && q < pw) ? m[lane + (p0 + q) * S.ldm] : 0.0;
-                    if constexpr (MIXED) r[q] = rnd(r[q]);
+                    const double v = m[i + (p0 + min(q, pw - 1)) * ldm];
+                    r[q] = (act && q < pw) ? (MIXED ? rnd(v) : v) : 0.0;
                 }
+                double d = (MIXED && act) ? dd[i] : 1.0;
 #pragma unroll
                 for (int q = 0; q < PW; ++q) {
                     if (q >= pw) continue;
-                    const int j = p0 + q;
-                    const double piv = MIXED ? bcast(dd, j) : bcast(r[q], j);
+                    const double piv = MIXED ? bcast(d, q) : bcast(r[q], q);
                     ok = ok && (piv > 0.0);
                     const double inv = rsqrt_nr(piv);
                     const double lij = MIXED ? rnd(r[q] * inv) : r[q] * inv;
-                    if (lane == j) {
-                        dv()[j] = inv;
+                    if (lane == q) {
+                        dv()[p0 + q] = inv;
                         r[q] = piv * inv;
-                    } else if (lane > j) {
+                    } else if (lane > q) {
                         r[q] = lij;
-                        if constexpr (MIXED) dd -= lij * lij;
+                        if constexpr (MIXED) d -= lij * lij;
                     } else {
                         r[q] = 0.0;
                     }
-                    // rank-1 update of the rest of the panel; column entries
-                    // come from the lanes that hold them (readlane)
 #pragma unroll
                     for (int q2 = q + 1; q2 < PW; ++q2)
-                        if (q2 < pw) r[q2] = (double)((TS)r[q2] - (TS)lij * (TS)bcast(lij, p0 + q2));
+                        if (q2 < pw) r[q2] = (double)((TS)r[q2] - (TS)lij * (TS)bcast(lij, q2));
                 }
-                if (lane < NZ) {
+                if (act) {
 #pragma unroll
                     for (int q = 0; q < PW; ++q)
-                        if (q < pw) m[lane + (p0 + q) * S.ldm] = r[q];
+                        if (q < pw) {
+                            m[i + (p0 + q) * ldm] = r[q];
+                            lb[lane + q * PW] = r[q];
+                        }
+                    if constexpr (MIXED) dd[i] = d;
                 }
             }
             __syncthreads();
+            // rows below the block: L21 = M21 L11^{-T}, one row per thread;
+            // rows above it get zeros in the panel columns
+            for (int i = opq(tid); i < NZ; i += BT) {
+                if (i < p0) {
+                    for (int q = 0; q < pw; ++q) m[i + (p0 + q) * ldm] = 0.0;
+                    continue;
+                }
+                if (i < p1) continue;
+                double r[PW];
+#pragma unroll
+                for (int q = 0; q < PW; ++q) {
+                    const double v = m[i + (p0 + min(q, pw - 1)) * ldm];
+                    r[q] = MIXED ? rnd(v) : v;
+                }
+                double d = MIXED ? dd[i] : 0.0;
+#pragma unroll
+                for (int q = 0; q < PW; ++q) {
+                    if (q >= pw) continue;
+                    TS acc = (TS)r[q];
+#pragma unroll
+                    for (int c = 0; c < q; ++c) acc -= (TS)r[c] * (TS)lb[q + c * PW];
+                    r[q] = MIXED ? rnd((double)acc * dv()[p0 + q]) : (double)acc * dv()[p0 + q];
+                    if constexpr (MIXED) d -= r[q] * r[q];
+                }
+#pragma unroll
+                for (int q = 0; q < PW; ++q)
+                    if (q < pw) m[i + (p0 + q) * ldm] = r[q];
+                if constexpr (MIXED) dd[i] = d;
+            }
+            __syncthreads();
             // trailing update of rows/columns p1.. with the panel
-            const int p1 = p0 + pw;
             const int nt = NZ - p1;
             if (nt > 0) {
                 const int TZ = (nt + 3) >> 2;
@@ -520,9 +638,9 @@ struct Blk {
                     for (int q = p0; q < p1; ++q) {
                         TS li[4], lk[4];
 #pragma unroll
-                        for (int a = 0; a < 4; ++a) li[a] = (TS)m[ic[a] + q * S.ldm];
+                        for (int a = 0; a < 4; ++a) li[a] = (TS)m[ic[a] + q * ldm];
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) lk[c] = (TS)m[kc[c] + q * S.ldm];
+                        for (int c = 0; c < 4; ++c) lk[c] = (TS)m[kc[c] + q * ldm];
 #pragma unroll
                         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -533,33 +651,88 @@ struct Blk {
 #pragma unroll
                         for (int c = 0; c < 4; ++c)
                             if (i0 + a < NZ && k0 + c < NZ && k0 + c <= i0 + a) {
-                                double* e = m + (i0 + a) + (k0 + c) * S.ldm;
+                                double* e = m + (i0 + a) + (k0 + c) * ldm;
                                 *e = (double)((TS)*e - acc[a][c]);
                             }
                 }
                 __syncthreads();
             }
         }
-        if (wid == 0 && lane == 0) flag()[0] = 1.0;
+        if (wid == 0 && lane == 0) flag()[0] = ok ? 1.0 : 0.0;
         __syncthreads();
-        if (wid == 0 && !ok && lane == 0) flag()[0] = 0.0;
+        const bool res = flag()[0] != 0.0;
         __syncthreads();
-        return flag()[0] != 0.0;
+        return res;
     }
 
-    // wave 0: forward substitution with the (u, u) block of the factor in M,
-    // fused with the x rows: lanes j < NU end with y = L_uu^{-1} m_u, lanes
-    // NU <= j < NZ with p = m_x - L_xu y.  di = 1/L_jj of lane j.
+    // Forward substitution with the (u, u) block of the factor in M (u
+    // columns): wave 0 solves y = L_uu^{-1} m_u (rows j < NU, one per lane,
+    // di = 1/L_jj), then every thread of rows NU <= i < NZ forms
+    // p_i = m_i - L_xu(i, :) y.  mv is this thread's row value (row tid);
+    // returns y_tid or p_tid.  Every thread calls it; uses ev() as scratch.
     __device__ __forceinline__ double fwd_subst_u(double mv, double di) const
     {
         const double* m = M();
+        double* yv = ev();
         mv = rnd(mv);
-        for (int j = 0; j < NU; ++j) {
-            const double y = rnd(bcast(mv, j) * bcast(di, j));
-            if (lane == j) mv = y;
-            else if (lane > j && lane < NZ) mv = (double)((TS)mv - (TS)m[lane + j * S.ldm] * (TS)y);
+        if (wid == 0) {
+            double v = mv;
+            for (int j = 0; j < NU; ++j) {
+                const double y = rnd(bcast(v, j) * bcast(di, j));
+                if (lane == j) v = y;
+                else if (lane > j && lane < NU) v = (double)((TS)v - (TS)m[lane + j * ldm] * (TS)y);
+            }
+            if (lane < NU) yv[lane] = v;
         }
-        return mv;
+        __syncthreads();
+        const int i = opq(tid);
+        if (i < NU) return yv[i];
+        if (i < NZ) return (double)((TS)mv - dot<TS>(m + i, ldm, yv, 1, NU));
+        return 0.0;
+    }
+
+    // Blocked triangular solves with a lower-triangular n x n block L (leading
+    // dimension ld) and 1/L_ii in di (LDS), on a vector x in LDS: wave 0
+    // solves each 64-row diagonal block (one row per lane), all threads
+    // update the remaining rows.  Every thread calls them.
+    __device__ __forceinline__ void trsv_lower(const double* L, int ld, int n, double* x, const double* di) const
+    {
+        for (int b0 = 0; b0 < n; b0 += 64) {
+            const int bn = min(64, n - b0);
+            if (wid == 0) {
+                double v = lane < bn ? rnd(x[b0 + lane]) : 0.0;
+                for (int c = 0; c < bn; ++c) {
+                    const double y = rnd(bcast(v, c) * di[b0 + c]);
+                    if (lane == c) v = y;
+                    else if (lane > c && lane < bn) v = (double)((TS)v - (TS)L[(b0 + lane) + (b0 + c) * ld] * (TS)y);
+                }
+                if (lane < bn) x[b0 + lane] = v;
+            }
+            __syncthreads();
+            for (int i = b0 + bn + opq(tid); i < n; i += BT)
+                x[i] = (double)((TS)x[i] - dot<TS>(L + i + b0 * ld, ld, x + b0, 1, bn));
+            __syncthreads();
+        }
+    }
+
+    __device__ __forceinline__ void trsv_lower_t(const double* L, int ld, int n, double* x, const double* di) const
+    {
+        for (int b1 = n; b1 > 0; b1 -= 64) {
+            const int b0 = max(0, b1 - 64), bn = b1 - b0;
+            if (wid == 0) {
+                double v = lane < bn ? rnd(x[b0 + lane]) : 0.0;
+                for (int c = bn - 1; c >= 0; --c) {
+                    const double xv = rnd(bcast(v, c) * di[b0 + c]);
+                    if (lane == c) v = xv;
+                    else if (lane < c) v = (double)((TS)v - (TS)L[(b0 + c) + (b0 + lane) * ld] * (TS)xv);
+                }
+                if (lane < bn) x[b0 + lane] = v;
+            }
+            __syncthreads();
+            for (int i = opq(tid); i < b0; i += BT)
+                x[i] = (double)((TS)x[i] - dot<TS>(L + b0 + i * ld, 1, x + b0, 1, bn));
+            __syncthreads();
+        }
     }
 
     // ==================================================================
@@ -578,6 +751,7 @@ struct Blk {
         for (int n = N; n >= 0; --n) {
             const int cur = n & 1, nxt = cur ^ 1;
             commit(pre, M(), F(), G());
+            stage_A(n);
             const double* d = Dp(n);
             double* ir = Ip(n);
             double* w = Wp(n);
@@ -631,18 +805,18 @@ struct Blk {
             if (j < NZ) {
                 const double* mh = M();
                 const double* zv = z();
-                double acc = g + dot<double>(mh + j, S.ldm, zv, 1, NZ);
-                if (n < N) acc += dot<double>(F() + j * S.ldf, 1, pin(nxt), 1, NX);
+                double acc = g + dot<double>(mh + j, ldm, zv, 1, NZ);
+                if (n < N) acc += dot<double>(F() + j * ldf, 1, pin(nxt), 1, NX);
                 if (j >= NU) acc -= t2()[j - NU];
                 acc -= m * (ll - lu);
-                acc -= dot<double>(G() + j * S.ldg, 1, t1(), 1, NG);
+                acc -= dot<double>(G() + j * ldg, 1, t1(), 1, NG);
                 rg = acc;
                 mg = nmax(mg, fabs(rg));
             }
             // r_b = F z + b - x_{n+1}
             double rb = 0.0;
             if (n < N && j < NX) {
-                const double acc = b + dot<double>(F() + j, S.ldf, z(), 1, NZ);
+                const double acc = b + dot<double>(F() + j, ldf, z(), 1, NZ);
                 rb = acc - xn(nxt)[j];
                 mb = nmax(mb, fabs(rb));
             }
@@ -655,7 +829,7 @@ struct Blk {
                     if (j < NZ) {
                         gz = zz;
                     } else {
-                        gz = dot<double>(G() + (j - NZ), S.ldg, z(), 1, NZ);
+                        gz = dot<double>(G() + (j - NZ), ldg, z(), 1, NZ);
                     }
                     rdl = -gz + tl + lo;
                     rdu = gz + tu - hi;
@@ -690,14 +864,14 @@ struct Blk {
 
             if (factor) {
                 // Phi = H + diag(box weights) + reg I ; V = [L_{n+1}' F ; sqrt(w_g) G]
-                if (j < NZ) M()[j + j * S.ldm] += wsv()[j] + P.reg_prim;
+                if (j < NZ) M()[j + j * ldm] += wsv()[j] + P.reg_prim;
                 {
                     const double* gg = G();
                     const double* wv = wsv();
                     double* v = V();
                     for (int e = tid; e < NG * NZ; e += BT) {
                         const int r = e % NG, k = e / NG;
-                        v[NX + r + k * S.ldv] = sqrt(wv[NZ + r]) * gg[r + k * S.ldg];
+                        v[NX + r + k * ldv] = sqrt(wv[NZ + r]) * gg[r + k * ldg];
                     }
                 }
                 if (n < N) trmm_LtF();
@@ -709,40 +883,41 @@ struct Blk {
                 // reduced gradient and cost-to-go terms
                 double mv = 0.0;
                 if (j < NZ) {
-                    mv = rg - ev()[j] - dot<double>(G() + j * S.ldg, 1, ev() + NZ, 1, NG);
+                    mv = rg - ev()[j] - dot<double>(G() + j * ldg, 1, ev() + NZ, 1, NG);
                 }
                 if (n < N) {
                     const double* L = Lx();
-                    if (j < NX) t1()[j] = (double)dot<TS>(L + j + j * S.ldx, 1, rbv() + j, 1, NX - j);
+                    if (j < NX) t1()[j] = (double)dot<TS>(L + j + j * ldx, 1, rbv() + j, 1, NX - j);
                     __syncthreads();
-                    if (j < NX) t2()[j] = (double)((TS)pn(nxt)[j] + dot<TS>(L + j, S.ldx, t1(), 1, j + 1));
+                    if (j < NX) t2()[j] = (double)((TS)pn(nxt)[j] + dot<TS>(L + j, ldx, t1(), 1, j + 1));
                     __syncthreads();
-                    if (j < NZ) mv = (double)((TS)mv + dot<TS>(F() + j * S.ldf, 1, t2(), 1, NX));
+                    if (j < NZ) mv = (double)((TS)mv + dot<TS>(F() + j * ldf, 1, t2(), 1, NX));
                 }
-                if (wid == 0) {
-                    const double di = lane < NZ ? dv()[lane] : 0.0;
+                {
+                    const double di = j < NZ ? dv()[j] : 0.0;
                     mv = fwd_subst_u(mv, di);
-                    if (lane < NZ) w[Lo.W_dinv + lane] = di;
-                    if (lane < NU) w[Lo.W_yu + lane] = mv;
-                    else if (lane < NZ) {
-                        w[Lo.W_pv + lane - NU] = mv;
-                        pn(cur)[lane - NU] = mv;
+                    if (j < NZ) w[Lo.W_dinv + j] = di;
+                    if (j < NU) w[Lo.W_yu + j] = mv;
+                    else if (j < NZ) {
+                        w[Lo.W_pv + j - NU] = mv;
+                        pn(cur)[j - NU] = mv;
                     }
                 }
                 // factor to global memory; its (x, x) block becomes L_{n+1} of
-                // the next stage of the sweep
-                {
+                // the next stage of the sweep (in global-memory mode the
+                // factor is already in its record and is read from there)
+                if constexpr (!GL) {
                     const double* mf = M();
                     double* wl = w + Lo.W_L;
                     Walk q(NZ, tid);
                     for (int e = tid; e < NZ * NZ; e += BT) {
-                        wl[e] = mf[q.r + q.c * S.ldm];
+                        wl[e] = mf[q.r + q.c * ldm];
                         q.next();
                     }
                     double* L = Lx();
                     Walk qx(NX, tid);
                     for (int e = tid; e < NX * NX; e += BT) {
-                        L[qx.r + qx.c * S.ldx] = mf[(NU + qx.r) + (NU + qx.c) * S.ldm];
+                        L[qx.r + qx.c * ldx] = mf[(NU + qx.r) + (NU + qx.c) * ldm];
                         qx.next();
                     }
                 }
@@ -784,11 +959,11 @@ struct Blk {
     __device__ __forceinline__ double cost_to_go_x(double mv, const double* xc, const double* pnv) const
     {
         const int j = opq(tid);
-        if (j < NX) t1()[j] = (double)dot<TS>(xc + (NU + j) + j * S.ldm, 1, rbv() + j, 1, NX - j);
+        if (j < NX) t1()[j] = (double)dot<TS>(xc + (NU + j) + j * ldm, 1, rbv() + j, 1, NX - j);
         __syncthreads();
-        if (j < NX) t2()[j] = (double)((TS)pnv[j] + dot<TS>(xc + (NU + j), S.ldm, t1(), 1, j + 1));
+        if (j < NX) t2()[j] = (double)((TS)pnv[j] + dot<TS>(xc + (NU + j), ldm, t1(), 1, j + 1));
         __syncthreads();
-        if (j < NZ) mv = (double)((TS)mv + dot<TS>(F() + j * S.ldf, 1, t2(), 1, NX));
+        if (j < NZ) mv = (double)((TS)mv + dot<TS>(F() + j * ldf, 1, t2(), 1, NX));
         return mv;
     }
 
@@ -804,6 +979,7 @@ struct Blk {
         for (int n = N; n >= 0; --n) {
             const int cur = n & 1, nxt = cur ^ 1;
             commit(pre, M(), F(), G());
+            stage_BC(n);
             const double* d = Dp(n);
             const double* ir = Ip(n);
             const double* w = Wp(n);
@@ -834,16 +1010,16 @@ struct Blk {
             __syncthreads();
             double mv = 0.0;
             if (j < NZ) {
-                mv = rg - ev()[j] - dot<double>(G() + j * S.ldg, 1, ev() + NZ, 1, NG);
+                mv = rg - ev()[j] - dot<double>(G() + j * ldg, 1, ev() + NZ, 1, NG);
             }
-            if (n < N) mv = cost_to_go_x(mv, M() + NU * S.ldm, pn(nxt));
-            if (wid == 0) {
-                mv = fwd_subst_u(mv, di);
+            if (n < N) mv = cost_to_go_x(mv, XC(), pn(nxt));
+            mv = fwd_subst_u(mv, di);
+            {
                 double* wo = Wp(n);
-                if (lane < NU) wo[Lo.W_yu + lane] = mv;
-                else if (lane < NZ) {
-                    wo[Lo.W_pv + lane - NU] = mv;
-                    pn(cur)[lane - NU] = mv;
+                if (j < NU) wo[Lo.W_yu + j] = mv;
+                else if (j < NZ) {
+                    wo[Lo.W_pv + j - NU] = mv;
+                    pn(cur)[j - NU] = mv;
                 }
             }
             __syncthreads();
@@ -864,31 +1040,29 @@ struct Blk {
         {
             const int j = tid;
             double* w0 = Wp(0);
-            double* L = Lx();
-            Walk qx(NX, tid);
-            for (int e = tid; e < NX * NX; e += BT) {
-                L[qx.r + qx.c * S.ldx] = w0[Lo.W_L + (NU + qx.r) + (NU + qx.c) * NZ];
-                qx.next();
+            const double* L;
+            int ld;
+            if constexpr (GL) {
+                L = w0 + Lo.W_L + NU + NU * NZ;
+                ld = NZ;
+            } else {
+                double* Ls = Lx();
+                Walk qx(NX, tid);
+                for (int e = tid; e < NX * NX; e += BT) {
+                    Ls[qx.r + qx.c * ldx] = w0[Lo.W_L + (NU + qx.r) + (NU + qx.c) * NZ];
+                    qx.next();
+                }
+                L = Ls;
+                ld = ldx;
             }
-            double v = j < NX ? -w0[Lo.W_pv + j] : 0.0;
-            const double di = j < NX ? w0[Lo.W_dinv + NU + j] : 0.0;
-            if (j < NX) w0[opi + j] = 0.0;
-            __syncthreads();
-            if (wid == 0) {
-                v = rnd(v);
-                for (int c = 0; c < NX; ++c) {
-                    const double y = rnd(bcast(v, c) * bcast(di, c));
-                    if (lane == c) v = y;
-                    else if (lane > c && lane < NX) v = (double)((TS)v - (TS)L[lane + c * S.ldx] * (TS)y);
-                }
-                for (int c = NX - 1; c >= 0; --c) {
-                    const double x = rnd(bcast(v, c) * bcast(di, c));
-                    if (lane == c) v = x;
-                    else if (lane < c) v = (double)((TS)v - (TS)L[c + lane * S.ldx] * (TS)x);
-                }
-                if (lane < NX) xn(0)[lane] = v;
+            if (j < NX) {
+                xn(0)[j] = -w0[Lo.W_pv + j];
+                dv()[j] = w0[Lo.W_dinv + NU + j];
+                w0[opi + j] = 0.0;
             }
             __syncthreads();
+            trsv_lower(L, ld, NX, xn(0), dv());
+            trsv_lower_t(L, ld, NX, xn(0), dv());
         }
         Pre pre;
         seg_lfg(pre, 0);
@@ -896,6 +1070,7 @@ struct Blk {
         for (int n = 0; n <= N; ++n) {
             const int cur = n & 1, nxt = cur ^ 1;
             commit(pre, M(), F(), G());
+            stage_BC(n);
             const double* d = Dp(n);
             const double* ir = Ip(n);
             double* w = Wp(n);
@@ -928,28 +1103,30 @@ struct Blk {
                 const double* mu = M();
                 const double* x = xn(cur);
                 double v = 0.0;
-                if (lane < NU) v = (double)((TS)yu + dot<TS>(mu + NU + lane * S.ldm, 1, x, 1, NX));
+                if (lane < NU) v = (double)((TS)yu + dot<TS>(mu + NU + lane * ldm, 1, x, 1, NX));
                 for (int c = NU - 1; c >= 0; --c) {
                     const double xv = rnd(bcast(v, c) * bcast(di, c));
                     if (lane == c) v = xv;
-                    else if (lane < c) v = (double)((TS)v - (TS)mu[c + lane * S.ldm] * (TS)xv);
+                    else if (lane < c) v = (double)((TS)v - (TS)mu[c + lane * ldm] * (TS)xv);
                 }
-                double dz = 0.0;
-                if (lane < NU) dz = -v;
-                else if (lane < NZ) dz = x[lane - NU];
-                if (lane < NZ) {
-                    z()[lane] = dz;
-                    w[oz + lane] = dz;
+                if (lane < NU) {
+                    z()[lane] = -v;
+                    w[oz + lane] = -v;
                 }
+            }
+            if (j >= NU && j < NZ) {
+                const double dz = xn(cur)[j - NU];
+                z()[j] = dz;
+                w[oz + j] = dz;
             }
             __syncthreads();
             if (n < N) {
-                const double* xc = M() + NU * S.ldm;
-                if (j < NX) xn(nxt)[j] = (double)((TS)rb + dot<TS>(F() + j, S.ldf, z(), 1, NZ));
+                const double* xc = XC();
+                if (j < NX) xn(nxt)[j] = (double)((TS)rb + dot<TS>(F() + j, ldf, z(), 1, NZ));
                 __syncthreads();
-                if (j < NX) t1()[j] = (double)dot<TS>(xc + (NU + j) + j * S.ldm, 1, xn(nxt) + j, 1, NX - j);
+                if (j < NX) t1()[j] = (double)dot<TS>(xc + (NU + j) + j * ldm, 1, xn(nxt) + j, 1, NX - j);
                 __syncthreads();
-                if (j < NX) Wp(n + 1)[opi + j] = (double)((TS)pnx + dot<TS>(xc + (NU + j), S.ldm, t1(), 1, j + 1));
+                if (j < NX) Wp(n + 1)[opi + j] = (double)((TS)pnx + dot<TS>(xc + (NU + j), ldm, t1(), 1, j + 1));
             }
             // constraint steps, step length, duality-measure sums
             if (j < NC) {
@@ -959,7 +1136,7 @@ struct Blk {
                     if (j < NZ) {
                         gdz = z()[j];
                     } else {
-                        gdz = dot<double>(G() + (j - NZ), S.ldg, z(), 1, NZ);
+                        gdz = dot<double>(G() + (j - NZ), ldg, z(), 1, NZ);
                     }
                     dtl = gdz - rdl;
                     dtu = -gdz - rdu;
@@ -999,6 +1176,7 @@ struct Blk {
         for (int n = N; n >= 0; --n) {
             const int cur = n & 1, nxt = cur ^ 1;
             commit(pre, M(), F(), G());
+            stage_R(n);
             const double* d = Dp(n);
             const double* ir = Ip(n);
             double* w = Wp(n);
@@ -1043,18 +1221,18 @@ struct Blk {
             if (j < NZ) {
                 const double* mh = M();
                 const double* zv = z();
-                double acc = rg + dot<double>(mh + j, S.ldm, zv, 1, NZ);
-                if (n < N) acc += dot<double>(F() + j * S.ldf, 1, pin(nxt), 1, NX);
+                double acc = rg + dot<double>(mh + j, ldm, zv, 1, NZ);
+                if (n < N) acc += dot<double>(F() + j * ldf, 1, pin(nxt), 1, NX);
                 if (j >= NU) acc -= t2()[j - NU];
                 acc -= m * (sll - slu);
-                acc -= dot<double>(G() + j * S.ldg, 1, t1(), 1, NG);
+                acc -= dot<double>(G() + j * ldg, 1, t1(), 1, NG);
                 org = acc;
                 nr = nmax(nr, fabs(acc));
                 w[Lo.W_irg + j] = org;
             }
             // b row: F dz - dx_{n+1} + r_b
             if (n < N && j < NX) {
-                const double acc = rb + dot<double>(F() + j, S.ldf, z(), 1, NZ);
+                const double acc = rb + dot<double>(F() + j, ldf, z(), 1, NZ);
                 orb = acc - xn(nxt)[j];
                 nr = nmax(nr, fabs(orb));
                 w[Lo.W_irb + j] = orb;
@@ -1067,7 +1245,7 @@ struct Blk {
                     if (j < NZ) {
                         gz = dz;
                     } else {
-                        gz = dot<double>(G() + (j - NZ), S.ldg, z(), 1, NZ);
+                        gz = dot<double>(G() + (j - NZ), ldg, z(), 1, NZ);
                     }
                     ordl = -gz + stl + rdl;
                     ordu = gz + stu + rdu;
@@ -1302,6 +1480,7 @@ struct Blk {
     }
 };
 
+// ZM > 64 selects the global-memory mode.
 template <bool MIXED, int ZM, int GM>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1, 1))) void ipm_block_kernel(
     const InstDesc* __restrict__ desc, int count, const double* __restrict__ data, double* __restrict__ iter,
@@ -1315,7 +1494,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1, 1))) void
         if (stat[ds.index].status != ST_FALLBACK) return;
         fell_back = 1;
     }
-    const Blk<MIXED, ZM, GM> ipm(ds, data, iter, work, P);
+    const Blk<MIXED, ZM, GM, (ZM > 64)> ipm(ds, data, iter, work, P);
     ipm.run(stat + ds.index, step_out + ds.iter, fell_back);
 }
 

@@ -1,5 +1,7 @@
 // Instantiations of the block kernel: FP64 and mixed, for stage blocks up to
-// 32 and up to 64 (the bound sizes the factor rows held in registers).
+// 32 and up to 64 (LDS-resident stage blocks, the bound sizes the prefetch
+// registers), and above 64 (global-memory mode), each without and with
+// general rows.
 #include "ipm_block.h"
 #include "ipm_launch.h"
 
@@ -16,7 +18,7 @@ static int launch_block_t(const InstDesc* desc, int count, const double* data, d
 
 int block_lds_bytes(int nx, int nu, int ng) { return (int)(sizeof(double) * make_blds(nx, nu, ng).total); }
 
-int block_zmax(int nz) { return nz <= 32 ? 32 : (nz <= 64 ? 64 : 0); }
+int block_zmax(int nz) { return nz <= 32 ? 32 : (nz <= 64 ? 64 : (nz <= 256 ? 256 : 0)); }
 
 int block_launch(int zm, int gm, int mixed, const InstDesc* desc, int count, const double* data, double* iter,
                  double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream)
@@ -30,6 +32,8 @@ int block_launch(int zm, int gm, int mixed, const InstDesc* desc, int count, con
     OQP_BLK(32, 64)
     OQP_BLK(64, 0)
     OQP_BLK(64, 64)
+    OQP_BLK(256, 0)
+    OQP_BLK(256, 64)
 #undef OQP_BLK
     return -1;
 }

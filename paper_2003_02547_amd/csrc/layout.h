@@ -31,7 +31,7 @@ struct Layout {
     // workspace record (doubles), one per stage
     int W_rg, W_rb, W_rdl, W_rdu, W_yu, W_pv, W_dz, W_dpi, W_dll, W_dlu, W_dtl, W_dtu;
     int W_all, W_alu, W_atl, W_atu, W_irg, W_irb, W_irdl, W_irdu, W_irml, W_irmu;
-    int W_edz, W_edpi, W_edll, W_edlu, W_edtl, W_edtu, W_L, W_dinv, WREC;
+    int W_edz, W_edpi, W_edll, W_edlu, W_edtl, W_edtu, W_L, W_dinv, W_V, WREC;
 };
 
 // F = [B A] is NX x NZ column-major, H is NZ x NZ column-major (full
@@ -96,6 +96,9 @@ OQP_HD constexpr Layout make_layout(int NX, int NU, int NG)
     o = round_up(o, 8);
     L.W_L = o; o += NZ * NZ;
     L.W_dinv = o; o += NZ;
+    // [L_{n+1}' F; sqrt(w) G] of the stage, used only by the global-memory
+    // mode of the block kernel (stage blocks above 64)
+    L.W_V = o; o += NX + NU > 64 ? (NX + NG) * NZ : 0;
     L.WREC = round_up(o, 8);
     return L;
 }

@@ -87,10 +87,16 @@ def test_batch_size_and_plan_errors():
     rc = L.oqp_batch_init(arr, 3, ct.byref(arg), host.ctypes.data, hb.value - 1, ct.c_void_p(256), db.value,
                           None, ct.byref(h))
     assert rc == B.ENOMEM
-    # stage sizes beyond every compiled variant
-    big = B.Dims(2, [80, 80, 80], [2, 2, 0], [0, 0, 0], [0, 0, 0], [0, 0, 0])
-    arr1 = (ct.c_void_p * 1)(big.h)
-    assert L.oqp_batch_bytes(arr1, 1, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.EINVAL
+    # stage sizes beyond every kernel: more than 256 rows per stage block, or
+    # more than 64 inputs, or more than 64 general rows
+    for nx, nu, ng in ((250, 10, 0), (80, 70, 0), (40, 8, 70)):
+        big = B.Dims(2, [nx] * 3, [nu, nu, 0], [0, 0, 0], [0, 0, 0], [ng, ng, 0])
+        arr1 = (ct.c_void_p * 1)(big.h)
+        assert L.oqp_batch_bytes(arr1, 1, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.EINVAL, (nx, nu, ng)
+    # a large stage block is accepted (global-memory mode of the block kernel)
+    ok = B.Dims(2, [128] * 3, [32, 32, 0], [0, 0, 0], [0, 0, 0], [32, 32, 0])
+    arr1 = (ct.c_void_p * 1)(ok.h)
+    assert L.oqp_batch_bytes(arr1, 1, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.OK
     # bad arguments
     bad = B.default_arg(gamma=1.5)
     assert L.oqp_batch_bytes(arr, 3, ct.byref(bad), ct.byref(hb), ct.byref(db)) == B.EINVAL

@@ -56,7 +56,7 @@ def test_pack_errors():
     junk = B._aligned(256, 64)
     assert L.oqp_pack_footprint(junk.ctypes.data, ct.byref(fb), ct.byref(v)) == B.EINVAL
     # stage sizes beyond every compiled variant
-    d = B.Dims(2, [100, 100, 100], [2, 2, 0], [0, 0, 0], [0, 0, 0], [0, 0, 0])
+    d = B.Dims(2, [300, 300, 300], [2, 2, 0], [0, 0, 0], [0, 0, 0], [0, 0, 0])
     qb = ct.c_void_p()
     qmem = B._aligned(L.oqp_qp_bytes(d.h))
     assert L.oqp_qp_init(d.h, qmem.ctypes.data, qmem.nbytes, ct.byref(qb)) == B.OK
