@@ -117,6 +117,40 @@ def leg_uneven(B, W, torch, np, count, steps, seed0=0):
     return out
 
 
+def leg_large(B, W, torch, np, perfmodel, count, steps):
+    """Large-stage batch (nx = 128, nu = 32, N = 50, 32 general rows per
+    stage): the block kernel's global-memory mode, FP64 and mixed."""
+    qps = [W.random_large_stage(i) for i in range(count)]
+    fpi = np.array([perfmodel.flops_per_iter(q) for q in qps])
+    out = {"instances": count, "sizes": "nx=128, nu=32, N=50, ng=32 (C=0)", "tol": KKT_OK}
+    tol = dict(tol_stat=KKT_OK, tol_eq=KKT_OK, tol_ineq=KKT_OK, tol_comp=KKT_OK)
+    for name, mode in (("f64", B.MODE_F64), ("mixed", B.MODE_MIXED)):
+        # both paths to the metric's tolerance: about half of these instances
+        # stall before 1e-8 (the oracle as well)
+        batch = B.Batch(qps, B.default_arg(mode, **tol)).load().sync()
+        batch.solve()
+        torch.cuda.synchronize()
+        st = batch.stream
+        ms = []
+        for _ in range(steps):
+            s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s_.record(st)
+            batch.solve()
+            e_.record(st)
+            torch.cuda.synchronize()
+            ms.append(s_.elapsed_time(e_))
+        batch.fetch().sync()
+        stats = [batch.stat(i) for i in range(count)]
+        ok = sum(1 for x in stats if x.status == B.SUCCESS and max(x.res[:]) <= KKT_OK)
+        its = np.array([x.iters for x in stats])
+        t = float(np.median(ms)) * 1e-3
+        out[name] = {"value": round(ok / t, 1), "unit": "solves/s", "ms_per_step": round(t * 1e3, 3),
+                     "solves_ok": ok, "iters_p50": float(np.median(its)),
+                     "flop_rate_tflops": round(float(np.sum(fpi * its)) / t / 1e12, 3)}
+        del batch
+    return out
+
+
 def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_seconds, per_req_seconds, log):
     """Continuous-batching server, native real-time replay of Poisson
     arrivals over a pool of pre-packed uneven instances (page-locked host
@@ -167,6 +201,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uneven", type=int, default=4096, help="instances of the uneven leg (0: skip)")
     ap.add_argument("--uneven-steps", type=int, default=3)
+    ap.add_argument("--large", type=int, default=256, help="instances of the large-stage leg (0: skip)")
+    ap.add_argument("--large-steps", type=int, default=2)
     ap.add_argument("--serve-pool", type=int, default=256, help="distinct instances in the serving pool (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="offered Poisson rate for the saturation run")
     ap.add_argument("--serve-sat-seconds", type=float, default=0.25)
@@ -284,6 +320,9 @@ def main():
     if args.uneven > 0:
         log(f"bench: uneven leg, {args.uneven} instances")
         line["uneven"] = leg_uneven(B, W, torch, np, args.uneven, args.uneven_steps)
+    if args.large > 0:
+        log(f"bench: large-stage leg, {args.large} instances")
+        line["large"] = leg_large(B, W, torch, np, perfmodel, args.large, args.large_steps)
     if args.serve_pool > 0:
         line["serve"] = leg_serve(B, W, torch, np, args.serve_pool, args.serve_rate, args.serve_sat_seconds,
                                   args.serve_frac, args.serve_seconds, args.serve_per_request_seconds, log)

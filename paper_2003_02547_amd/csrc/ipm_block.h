@@ -519,19 +519,122 @@ struct Blk {
     }
 
     // Blocked right-looking Cholesky of M (NZ x NZ, lower triangle read) with
-    // panels of PW columns: wave 0 factors the PW x PW diagonal block (one
-    // row per lane, rows in registers, column entries by readlane) and copies
-    // it to LDS; every thread then solves one row of the block below it
-    // against that factor (L21 = M21 L11^{-T}), and all threads apply the
-    // panel to the trailing lower triangle with 4 x 4 register tiles.  Writes
-    // L (zero strict upper part) back into M and 1/L_ii into dv.  Every
-    // thread calls it; returns false (in every thread) when a pivot is not
-    // positive.  Mixed path: FP32 entries and updates, each row's diagonal
-    // accumulated in FP64 (FP64 pivots).
+    // panels of PW columns.  Writes L (zero strict upper part) back into M and
+    // 1/L_ii into dv.  Every thread calls it; returns false (in every thread)
+    // when a pivot is not positive.  Mixed path: FP32 entries and updates,
+    // each row's diagonal accumulated in FP64 (FP64 pivots).
+    //
+    // Stage blocks above 64 (global-memory mode): wave 0 factors the PW x PW
+    // diagonal block (one row per lane, rows in registers, column entries by
+    // readlane) and copies it to LDS; every thread then solves one row of the
+    // block below it against that factor (L21 = M21 L11^{-T}), and all
+    // threads apply the panel to the trailing lower triangle with 4 x 4
+    // register tiles.
     static constexpr int PW = 16;
+
+    // Stage blocks up to 64 (LDS mode): wave 0 holds every row of a panel
+    // (one row per lane, rows in registers) and applies each column to the
+    // rows below it in lock-step; all waves then apply the panel to the
+    // trailing lower triangle.
+    __device__ __forceinline__ bool cholesky_wave() const
+    {
+        double* m = M();
+        double dd = 0.0;  // wave 0: FP64 running diagonal of row `lane` (mixed path)
+        bool ok = true;
+        if (wid == 0 && MIXED) dd = lane < NZ ? m[lane + lane * ldm] : 1.0;
+        for (int p0 = 0; p0 < NZ; p0 += PW) {
+            const int pw = min(PW, NZ - p0);
+            if (wid == 0) {
+                double r[PW];
+#pragma unroll
+                for (int q = 0; q < PW; ++q) {
+                    r[q] = (lane >= p0 && lane < NZ && q < pw) ? m[lane + (p0 + q) * ldm] : 0.0;
+                    if constexpr (MIXED) r[q] = rnd(r[q]);
+                }
+#pragma unroll
+                for (int q = 0; q < PW; ++q) {
+                    if (q >= pw) continue;
+                    const int j = p0 + q;
+                    const double piv = MIXED ? bcast(dd, j) : bcast(r[q], j);
+                    ok = ok && (piv > 0.0);
+                    const double inv = rsqrt_nr(piv);
+                    const double lij = MIXED ? rnd(r[q] * inv) : r[q] * inv;
+                    if (lane == j) {
+                        dv()[j] = inv;
+                        r[q] = piv * inv;
+                    } else if (lane > j) {
+                        r[q] = lij;
+                        if constexpr (MIXED) dd -= lij * lij;
+                    } else {
+                        r[q] = 0.0;
+                    }
+                    // rank-1 update of the rest of the panel; column entries
+                    // come from the lanes that hold them (readlane)
+#pragma unroll
+                    for (int q2 = q + 1; q2 < PW; ++q2)
+                        if (q2 < pw) r[q2] = (double)((TS)r[q2] - (TS)lij * (TS)bcast(lij, p0 + q2));
+                }
+                if (lane < NZ) {
+#pragma unroll
+                    for (int q = 0; q < PW; ++q)
+                        if (q < pw) m[lane + (p0 + q) * ldm] = r[q];
+                }
+            }
+            __syncthreads();
+            // trailing update of rows/columns p1.. with the panel
+            const int p1 = p0 + pw;
+            const int nt = NZ - p1;
+            if (nt > 0) {
+                const int TZ = (nt + 3) >> 2;
+                for (int t = opq(tid); t < TZ * TZ; t += BT) {
+                    const int ti = t % TZ, tk = t / TZ;
+                    if (ti < tk) continue;
+                    const int i0 = p1 + 4 * ti, k0 = p1 + 4 * tk;
+                    int ic[4], kc[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        ic[a] = min(i0 + a, NZ - 1);
+                        kc[a] = min(k0 + a, NZ - 1);
+                    }
+                    TS acc[4][4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[a][c] = 0;
+#pragma unroll 2
+                    for (int q = p0; q < p1; ++q) {
+                        TS li[4], lk[4];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) li[a] = (TS)m[ic[a] + q * ldm];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) lk[c] = (TS)m[kc[c] + q * ldm];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a)
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) acc[a][c] += li[a] * lk[c];
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            if (i0 + a < NZ && k0 + c < NZ && k0 + c <= i0 + a) {
+                                double* e = m + (i0 + a) + (k0 + c) * ldm;
+                                *e = (double)((TS)*e - acc[a][c]);
+                            }
+                }
+                __syncthreads();
+            }
+        }
+        if (wid == 0 && lane == 0) flag()[0] = 1.0;
+        __syncthreads();
+        if (wid == 0 && !ok && lane == 0) flag()[0] = 0.0;
+        __syncthreads();
+        return flag()[0] != 0.0;
+    }
 
     __device__ __forceinline__ bool cholesky() const
     {
+        if constexpr (!GL) return cholesky_wave();
         double* m = M();
         double* dd = ddv();
         double* lb = l11();
