@@ -435,87 +435,69 @@ struct Blk {
     // dense kernels on LDS blocks
     // ------------------------------------------------------------------
 
-    // V[i][k] = sum_l Lx[l][i] F[l][k] (i < NX, k < NZ); Lx lower with zero
-    // strict upper part.  4 x 4 output tiles, one per thread.
-    __device__ __forceinline__ void trmm_LtF() const
+    // C(i, j) op= sum_{k < K} A(k, i) B(k, j) for i < m, j < n (only j <= i
+    // when `lower`), with A(k, i) = A[k sak + i sai] and B(k, j) = B[k sbk +
+    // j sbj], on the matrix cores: 16 x 16 output tiles spread over the four
+    // waves, K in steps of 4 (v_mfma_f64_16x16x4f64; in the mixed path FP32
+    // operands and accumulation, v_mfma_f32_16x16x4f32).  Operand lanes:
+    // A(k0 + lane / 16, i0 + lane % 16), B(k0 + lane / 16, j0 + lane % 16);
+    // result register r of a lane: row i0 + 4 r + lane / 16 (FP64) or
+    // i0 + 4 (lane / 16) + r (FP32), column j0 + lane % 16.  Loads use
+    // clamped in-range indices and zero out-of-range operands, so every lane
+    // stays active.  op: 0 store, 1 add, -1 subtract.
+    __device__ __forceinline__ void mma_tn(const double* A, int sak, int sai, const double* B, int sbk, int sbj, int m,
+                                           int n, int K, double* C, int ldc, int op, bool lower) const
     {
-        const int TI = (NX + 3) >> 2, TK = (NZ + 3) >> 2;
-        const double* L = Lx();
-        const double* f = F();
-        double* v = V();
-        for (int t = opq(tid); t < TI * TK; t += BT) {
-            const int i0 = 4 * (t % TI), k0 = 4 * (t / TI);
-            int ic[4], kc[4];
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                ic[p] = min(i0 + p, NX - 1);
-                kc[p] = min(k0 + p, NZ - 1);
-            }
-            TS acc[4][4];
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] = 0;
-#pragma unroll 2
-            for (int l = i0; l < NX; ++l) {
-                TS lv[4], fv[4];
-#pragma unroll
-                for (int p = 0; p < 4; ++p) lv[p] = (TS)L[l + ic[p] * ldx];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) fv[q] = (TS)f[l + kc[q] * ldf];
-#pragma unroll
-                for (int p = 0; p < 4; ++p)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[p][q] += lv[p] * fv[q];
+        using V4 = TS __attribute__((ext_vector_type(4)));
+        if (m <= 0 || n <= 0 || K <= 0) return;
+        const int TM = (m + 15) >> 4, TN = (n + 15) >> 4;
+        const int l16 = lane & 15, lk = lane >> 4;
+        for (int t = opq(wid); t < TM * TN; t += BT / 64) {
+            const int ti = t % TM, tj = t / TM;
+            if (lower && ti < tj) continue;
+            const int i = 16 * ti + l16, j = 16 * tj + l16;
+            const bool iv = i < m, jv = j < n;
+            const double* pa = A + min(i, m - 1) * sai;
+            const double* pb = B + min(j, n - 1) * sbj;
+            V4 acc = {0, 0, 0, 0};
+#pragma unroll 4
+            for (int k0 = 0; k0 < K; k0 += 4) {
+                const int k = k0 + lk;
+                const int kc = min(k, K - 1);
+                const double av = pa[kc * sak], bv = pb[kc * sbk];
+                const bool kv = k < K;
+                const TS a = (iv && kv) ? (TS)av : (TS)0;
+                const TS b = (jv && kv) ? (TS)bv : (TS)0;
+                if constexpr (MIXED)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+                else
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
             }
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (i0 + p < NX && k0 + q < NZ) v[(i0 + p) + (k0 + q) * ldv] = (double)acc[p][q];
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * ti + (MIXED ? 4 * lk + r : 4 * r + lk);
+                const int col = 16 * tj + l16;
+                if (row < m && col < n && (!lower || col <= row)) {
+                    double* c = C + row + col * ldc;
+                    if (op == 0) *c = (double)acc[r];
+                    else if (op > 0) *c += (double)acc[r];
+                    else *c = MIXED ? (double)((TS)*c - acc[r]) : *c - (double)acc[r];
+                }
+            }
         }
     }
 
+    // V[i][k] = sum_l Lx[l][i] F[l][k] (i < NX, k < NZ); Lx lower with zero
+    // strict upper part
+    __device__ __forceinline__ void trmm_LtF() const
+    {
+        mma_tn(Lx(), 1, ldx, F(), 1, ldf, NX, NZ, NX, V(), ldv, 0, false);
+    }
+
     // M[i][k] += sum_{r0 <= r < NV} V[r][i] V[r][k] on the lower triangle
-    // (tiles on and below the diagonal)
     __device__ __forceinline__ void syrk_VtV(int r0) const
     {
-        const int TZ = (NZ + 3) >> 2;
-        const double* v = V();
-        double* m = M();
-        for (int t = opq(tid); t < TZ * TZ; t += BT) {
-            const int ti = t % TZ, tk = t / TZ;
-            if (ti < tk) continue;
-            const int i0 = 4 * ti, k0 = 4 * tk;
-            int ic[4], kc[4];
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                ic[p] = min(i0 + p, NZ - 1);
-                kc[p] = min(k0 + p, NZ - 1);
-            }
-            TS acc[4][4];
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[p][q] = 0;
-#pragma unroll 2
-            for (int r = r0; r < NV; ++r) {
-                TS vi[4], vk[4];
-#pragma unroll
-                for (int p = 0; p < 4; ++p) vi[p] = (TS)v[r + ic[p] * ldv];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) vk[q] = (TS)v[r + kc[q] * ldv];
-#pragma unroll
-                for (int p = 0; p < 4; ++p)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[p][q] += vi[p] * vk[q];
-            }
-#pragma unroll
-            for (int p = 0; p < 4; ++p)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (i0 + p < NZ && k0 + q < NZ) m[(i0 + p) + (k0 + q) * ldm] += (double)acc[p][q];
-        }
+        mma_tn(V() + r0, 1, ldv, V() + r0, 1, ldv, NZ, NZ, NV - r0, M(), ldm, 1, true);
     }
 
     // Blocked right-looking Cholesky of M (NZ x NZ, lower triangle read) with
@@ -585,43 +567,8 @@ struct Blk {
             const int p1 = p0 + pw;
             const int nt = NZ - p1;
             if (nt > 0) {
-                const int TZ = (nt + 3) >> 2;
-                for (int t = opq(tid); t < TZ * TZ; t += BT) {
-                    const int ti = t % TZ, tk = t / TZ;
-                    if (ti < tk) continue;
-                    const int i0 = p1 + 4 * ti, k0 = p1 + 4 * tk;
-                    int ic[4], kc[4];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        ic[a] = min(i0 + a, NZ - 1);
-                        kc[a] = min(k0 + a, NZ - 1);
-                    }
-                    TS acc[4][4];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) acc[a][c] = 0;
-#pragma unroll 2
-                    for (int q = p0; q < p1; ++q) {
-                        TS li[4], lk[4];
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) li[a] = (TS)m[ic[a] + q * ldm];
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) lk[c] = (TS)m[kc[c] + q * ldm];
-#pragma unroll
-                        for (int a = 0; a < 4; ++a)
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) acc[a][c] += li[a] * lk[c];
-                    }
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c)
-                            if (i0 + a < NZ && k0 + c < NZ && k0 + c <= i0 + a) {
-                                double* e = m + (i0 + a) + (k0 + c) * ldm;
-                                *e = (double)((TS)*e - acc[a][c]);
-                            }
-                }
+                mma_tn(m + p1 + p0 * ldm, ldm, 1, m + p1 + p0 * ldm, ldm, 1, nt, nt, pw, m + p1 + p1 * ldm, ldm, -1,
+                       true);
                 __syncthreads();
             }
         }
@@ -721,43 +668,8 @@ struct Blk {
             // trailing update of rows/columns p1.. with the panel
             const int nt = NZ - p1;
             if (nt > 0) {
-                const int TZ = (nt + 3) >> 2;
-                for (int t = opq(tid); t < TZ * TZ; t += BT) {
-                    const int ti = t % TZ, tk = t / TZ;
-                    if (ti < tk) continue;
-                    const int i0 = p1 + 4 * ti, k0 = p1 + 4 * tk;
-                    int ic[4], kc[4];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        ic[a] = min(i0 + a, NZ - 1);
-                        kc[a] = min(k0 + a, NZ - 1);
-                    }
-                    TS acc[4][4];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) acc[a][c] = 0;
-#pragma unroll 2
-                    for (int q = p0; q < p1; ++q) {
-                        TS li[4], lk[4];
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) li[a] = (TS)m[ic[a] + q * ldm];
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) lk[c] = (TS)m[kc[c] + q * ldm];
-#pragma unroll
-                        for (int a = 0; a < 4; ++a)
-#pragma unroll
-                            for (int c = 0; c < 4; ++c) acc[a][c] += li[a] * lk[c];
-                    }
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int c = 0; c < 4; ++c)
-                            if (i0 + a < NZ && k0 + c < NZ && k0 + c <= i0 + a) {
-                                double* e = m + (i0 + a) + (k0 + c) * ldm;
-                                *e = (double)((TS)*e - acc[a][c]);
-                            }
-                }
+                mma_tn(m + p1 + p0 * ldm, ldm, 1, m + p1 + p0 * ldm, ldm, 1, nt, nt, pw, m + p1 + p1 * ldm, ldm, -1,
+                       true);
                 __syncthreads();
             }
         }
