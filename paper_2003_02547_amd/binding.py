@@ -66,6 +66,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2003_02547_amd.build.build()")
+    # load torch's HIP runtime first so that the library binds to the same
+    # one (device memory and streams come from torch)
+    import torch  # noqa: F401
     L = ct.CDLL(LIB_PATH)
     sig = {
         "oqp_dims_bytes": (ct.c_size_t, [ct.c_int]),
