@@ -117,6 +117,38 @@ def leg_uneven(B, W, torch, np, count, steps, seed0=0):
     return out
 
 
+def leg_single(B, W, torch, np, reps):
+    """Latency of one 4-mass QP (nx = 8, nu = 3, N = 10, dt = 0.5; seed 1) in
+    a batch of one: one launch, FP64 to 1e-8, median over reps; the oracle on
+    one host thread beside it."""
+    from oracle import oracle as O
+    qp = W.mass_spring_chain4(1)
+    batch = B.Batch([qp], B.default_arg()).load().sync()
+    batch.solve()
+    torch.cuda.synchronize()
+    st = batch.stream
+    ms = []
+    for _ in range(reps):
+        s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s_.record(st)
+        batch.solve()
+        e_.record(st)
+        torch.cuda.synchronize()
+        ms.append(s_.elapsed_time(e_))
+    batch.fetch().sync()
+    r = batch.result(0)
+    arg = O.Arg.with_tol(1e-8)
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < 1.0:
+        o = O.solve(qp, arg)
+        n += 1
+    cpu_us = (time.perf_counter() - t0) / n * 1e6
+    return {"workload": "mass_spring_4masses_N10", "gpu_us_p50": round(float(np.median(ms)) * 1e3, 1),
+            "iters": int(r.iters), "status": int(r.status), "oracle_1thread_us": round(cpu_us, 1),
+            "oracle_iters": int(o.iters)}
+
+
 def leg_large(B, W, torch, np, perfmodel, count, steps):
     """Large-stage batch (nx = 128, nu = 32, N = 50, 32 general rows per
     stage): the block kernel's global-memory mode, FP64 and mixed."""
@@ -317,6 +349,8 @@ def main():
                   "vs_f64": round(m["value"] / f["value"], 3)},
     }
     del f["del_batch"], m["del_batch"]
+    log("bench: single-instance latency (4 masses, N = 10)")
+    line["single"] = leg_single(B, W, torch, np, 20)
     if args.uneven > 0:
         log(f"bench: uneven leg, {args.uneven} instances")
         line["uneven"] = leg_uneven(B, W, torch, np, args.uneven, args.uneven_steps)

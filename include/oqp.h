@@ -64,6 +64,7 @@ typedef struct oqp_dims oqp_dims;
 typedef struct oqp_qp oqp_qp;
 typedef struct oqp_batch oqp_batch;
 typedef struct oqp_server oqp_server;
+typedef struct oqp_sol oqp_sol;
 
 /* Solver arguments (Section 4.2).  Fill with oqp_arg_default. */
 typedef struct {
@@ -164,6 +165,39 @@ int oqp_batch_sync(oqp_batch* batch);
 int oqp_batch_get_stat(const oqp_batch* batch, int i, oqp_stat* stat);
 int oqp_batch_get_sol(const oqp_batch* batch, int i, double* u, double* x, double* pi, double* lam_l, double* lam_u,
                       double* t_l, double* t_u);
+
+/* ---- solution object with per-stage getters (Section 1) ------------------ */
+/* Caller memory (16-byte aligned, oqp_sol_bytes) for the solution of a QP with
+ * the given dims; the dims object must outlive it. */
+size_t oqp_sol_bytes(const oqp_dims* dims);
+int oqp_sol_init(const oqp_dims* dims, void* mem, size_t bytes, oqp_sol** out);
+/* Copy the result of batch instance i (after fetch + sync) or of a finished
+ * server request into sol.  OQP_EINVAL if the stage sizes differ. */
+int oqp_batch_fill_sol(const oqp_batch* batch, int i, oqp_sol* sol);
+int oqp_server_fill_sol(oqp_server* server, uint64_t ticket, oqp_sol* sol);
+/* Stage-n blocks (OQP_ESTATE before a fill): u_n (nu_n), x_n (nx_n), pi (n < N:
+ * nx_{n+1} entries, the multiplier of the dynamics n -> n+1); multipliers and
+ * slacks of the lower/upper input boxes (nbu_n, idxbu order), state boxes
+ * (nbx_n, idxbx order) and general rows (ng_n). */
+int oqp_sol_get_u(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_x(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_pi(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_lam_lb_u(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_lam_ub_u(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_lam_lb_x(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_lam_ub_x(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_lam_lg(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_lam_ug(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_t_lb_u(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_t_ub_u(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_t_lb_x(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_t_ub_x(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_t_lg(const oqp_sol* sol, int n, double* out);
+int oqp_sol_get_t_ug(const oqp_sol* sol, int n, double* out);
+/* Outcome of the filled solve, and its residual norms (stat.res: inf-norms of
+ * r_g, r_b, r_d and lam .* t, eq:alg:pdipm:delta). */
+int oqp_sol_get_stat(const oqp_sol* sol, oqp_stat* stat);
+int oqp_res_get_norms(const oqp_sol* sol, double out[4]);
 
 /* ---- single Newton step (eq:alg:pdipm:delta) ------------------------------ */
 /* Set the iterate of instance i (user layout as above; lam and t > 0). */

@@ -113,6 +113,27 @@ def lib():
         "oqp_server_release": (ct.c_int, [_V, ct.c_uint64]),
         "oqp_server_stats": (ct.c_int, [_V, ct.POINTER(Counters)]),
         "oqp_server_replay": (ct.c_int, [_V, ct.POINTER(_V), _P, ct.c_int, ct.c_double, _P, ct.POINTER(Stat), _P]),
+        "oqp_sol_bytes": (ct.c_size_t, [_V]),
+        "oqp_sol_init": (ct.c_int, [_V, _V, ct.c_size_t, ct.POINTER(_V)]),
+        "oqp_batch_fill_sol": (ct.c_int, [_V, ct.c_int, _V]),
+        "oqp_server_fill_sol": (ct.c_int, [_V, ct.c_uint64, _V]),
+        "oqp_sol_get_stat": (ct.c_int, [_V, ct.POINTER(Stat)]),
+        "oqp_res_get_norms": (ct.c_int, [_V, _P]),
+        "oqp_sol_get_u": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_x": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_pi": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_lam_lb_u": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_lam_ub_u": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_lam_lb_x": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_lam_ub_x": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_lam_lg": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_lam_ug": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_t_lb_u": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_t_ub_u": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_t_lb_x": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_t_ub_x": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_t_lg": (ct.c_int, [_V, ct.c_int, _P]),
+        "oqp_sol_get_t_ug": (ct.c_int, [_V, ct.c_int, _P]),
         "oqp_set_wave_max": (ct.c_int, [ct.c_int]),
         "oqp_get_wave_max": (ct.c_int, []),
         "oqp_variant_count": (ct.c_int, []),
@@ -321,6 +342,39 @@ def solve(qps: Sequence, arg: Arg | None = None) -> List[Result]:
 
 _KEYS = ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")
 
+SOL_FIELDS = ("u", "x", "pi", "lam_lb_u", "lam_ub_u", "lam_lb_x", "lam_ub_x", "lam_lg", "lam_ug", "t_lb_u", "t_ub_u",
+              "t_lb_x", "t_ub_x", "t_lg", "t_ug")
+
+
+class Sol:
+    """oqp_sol in caller memory with the per-stage getters."""
+
+    def __init__(self, dims: "Dims"):
+        L = lib()
+        self.dims = dims
+        self.mem = _aligned(L.oqp_sol_bytes(dims.h), 64)
+        h = _V()
+        _check(L.oqp_sol_init(dims.h, self.mem.ctypes.data, self.mem.nbytes, ct.byref(h)))
+        self.h = h
+
+    def fill_from_batch(self, batch: "Batch", i: int):
+        _check(lib().oqp_batch_fill_sol(batch.h, i, self.h))
+        return self
+
+    def fill_from_server(self, server: "Server", ticket: int):
+        _check(lib().oqp_server_fill_sol(server.h, ticket, self.h))
+        return self
+
+    def get(self, field: str, n: int, size: int) -> np.ndarray:
+        out = np.zeros(max(size, 1))
+        _check(getattr(lib(), "oqp_sol_get_" + field)(self.h, n, _p(out)))
+        return out[:size].copy()
+
+    def norms(self) -> np.ndarray:
+        out = np.zeros(4)
+        _check(lib().oqp_res_get_norms(self.h, _p(out)))
+        return out
+
 
 def _sol_buffers(qp):
     nu, nx, npi, nc = _sizes(qp)
@@ -478,5 +532,6 @@ EXPORTED = [
     "oqp_last_error", "oqp_pack_bytes", "oqp_pack", "oqp_pack_footprint", "oqp_server_cfg_default",
     "oqp_server_bytes", "oqp_server_init", "oqp_server_destroy", "oqp_server_submit", "oqp_server_progress",
     "oqp_server_poll", "oqp_server_latency", "oqp_server_get_sol", "oqp_server_release", "oqp_server_stats",
-    "oqp_server_replay", "oqp_set_wave_max", "oqp_get_wave_max",
-]
+    "oqp_server_replay", "oqp_set_wave_max", "oqp_get_wave_max", "oqp_sol_bytes", "oqp_sol_init",
+    "oqp_batch_fill_sol", "oqp_server_fill_sol", "oqp_sol_get_stat", "oqp_res_get_norms",
+] + ["oqp_sol_get_" + g for g in SOL_FIELDS]

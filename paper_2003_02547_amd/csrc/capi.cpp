@@ -904,6 +904,23 @@ static void user_copy(const oqp_batch* b, int i, double* region, bool to_user, d
                       region + in.iter, to_user, u, x, pi, ll, lu, tl, tu);
 }
 
+bool dims5_match(const int* d5, int N, const oqp_dims* d)
+{
+    if (!d || d->N != N) return false;
+    for (int n = 0; n <= N; ++n)
+        if (d5[n] != d->nx[n] || d5[(N + 1) + n] != d->nu[n] || d5[2 * (N + 1) + n] != d->nbu[n] ||
+            d5[3 * (N + 1) + n] != d->nbx[n] || d5[4 * (N + 1) + n] != d->ng[n])
+            return false;
+    return true;
+}
+
+bool batch_dims_match(const oqp_batch* b, int i, const oqp_dims* d)
+{
+    if (!b || i < 0 || i >= b->count) return false;
+    const Inst& in = b->inst[i];
+    return dims5_match(b->dims_pool + in.dims_off, in.N, d);
+}
+
 extern "C" int oqp_batch_get_sol(const oqp_batch* b, int i, double* u, double* x, double* pi, double* lam_l,
                                  double* lam_u, double* t_l, double* t_u)
 {

@@ -50,6 +50,10 @@ int group_launch(int g, int mixed, const oqp::InstDesc* desc, const oqp::InstDes
                  const double* data, double* iter, double* work, double* step, oqp::DevStat* stat,
                  const oqp::KParams& P, void* stream);
 double inst_cost(int N, int nx, int nu);
+// stage sizes (dims5: nx, nu, nbu, nbx, ng, each N+1 entries) equal to dims
+bool dims5_match(const int* dims5, int N, const oqp_dims* dims);
+bool batch_dims_match(const oqp_batch* b, int i, const oqp_dims* dims);
+bool server_dims_match(const oqp_server* s, uint64_t ticket, const oqp_dims* dims);
 
 int fail(int code, const char* fmt, ...);
 size_t align_up(size_t v, size_t a);

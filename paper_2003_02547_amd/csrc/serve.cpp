@@ -580,6 +580,14 @@ extern "C" int oqp_server_get_sol(oqp_server* s, uint64_t ticket, double* u, dou
     return OQP_OK;
 }
 
+bool server_dims_match(const oqp_server* s, uint64_t ticket, const oqp_dims* d)
+{
+    const int slot = ticket_slot(s, ticket);
+    if (slot < 0) return false;
+    const PackHdr* h = s->req[slot].hdr;
+    return dims5_match((const int*)((const char*)h + h->dims_off), h->N, d);
+}
+
 extern "C" int oqp_server_release(oqp_server* s, uint64_t ticket)
 {
     if (!s) return fail(OQP_EINVAL, "oqp_server_release: NULL server");

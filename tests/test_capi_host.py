@@ -111,3 +111,21 @@ def test_bucket_choice_covers_instance():
     # smallest variant covering nx=16, nu=7, ng=0 is (16, 8, 0)
     cover = [(a, b, c) for a, b, c in B.variants() if a >= 16 and b >= 7]
     assert (16, 8, 0) in cover
+
+
+def test_sol_object_host_errors():
+    L = B.lib()
+    qp = W.random_tiny(np.random.default_rng(3), 3, ng_max=2)
+    d = B.Dims.of(qp)
+    assert L.oqp_sol_bytes(None) == 0
+    nb = L.oqp_sol_bytes(d.h)
+    mem = B._aligned(nb, 64)
+    h = ct.c_void_p()
+    assert L.oqp_sol_init(d.h, mem.ctypes.data, nb - 8, ct.byref(h)) == B.ENOMEM
+    assert L.oqp_sol_init(d.h, mem.ctypes.data + 8, nb, ct.byref(h)) == B.EINVAL
+    assert L.oqp_sol_init(d.h, mem.ctypes.data, nb, ct.byref(h)) == B.OK
+    out = np.zeros(16)
+    assert L.oqp_sol_get_x(h, 0, B._p(out)) == B.ESTATE  # not filled yet
+    assert L.oqp_sol_get_x(h, qp.N + 1, B._p(out)) == B.EINVAL
+    st = B.Stat()
+    assert L.oqp_sol_get_stat(h, ct.byref(st)) == B.ESTATE
