@@ -83,6 +83,8 @@ typedef struct {
     int ir_max;        /* max iterative-refinement steps per Newton solve */
     double ir_tol;     /* refinement stops at ||r_ir||_inf <= ir_tol * max(1, ||r||_inf) */
     int warm_start;    /* reserved; must be 0 (cold start) */
+    int cond_N;        /* batch only: solve after partial condensing to this horizon
+                          (Section 3.5; min(cond_N, N) stages per instance); 0 = off */
 } oqp_arg;
 
 /* Per-instance result. */
@@ -127,6 +129,16 @@ int oqp_qp_set_box_x(oqp_qp* qp, int n, const int* idx, const double* lo, const 
 int oqp_qp_set_general(oqp_qp* qp, int n, const double* D, int ldd, const double* C, int ldc, const double* lo,
                        const double* hi);
 
+/* Getters, the mirror of the setters (Section 1): copies into caller arrays
+ * with the given leading dimensions; Q and R are returned in full, box index
+ * lists in their stored order.  NULL pointers skip a field. */
+int oqp_qp_get_dyn(const oqp_qp* qp, int n, double* A, int lda, double* B, int ldb, double* b);
+int oqp_qp_get_cost(const oqp_qp* qp, int n, double* Q, int ldq, double* S, int lds, double* R, int ldr, double* q,
+                    double* r);
+int oqp_qp_get_box_u(const oqp_qp* qp, int n, int* idx, double* lo, double* hi);
+int oqp_qp_get_box_x(const oqp_qp* qp, int n, int* idx, double* lo, double* hi);
+int oqp_qp_get_general(const oqp_qp* qp, int n, double* D, int ldd, double* C, int ldc, double* lo, double* hi);
+
 /* ---- arguments ----------------------------------------------------------- */
 void oqp_arg_default(oqp_arg* arg, int mode);
 
@@ -165,6 +177,32 @@ int oqp_batch_sync(oqp_batch* batch);
 int oqp_batch_get_stat(const oqp_batch* batch, int i, oqp_stat* stat);
 int oqp_batch_get_sol(const oqp_batch* batch, int i, double* u, double* x, double* pi, double* lam_l, double* lam_u,
                       double* t_l, double* t_u);
+
+/* ---- partial condensing (Section 3.5) ------------------------------------ */
+/* A batch whose arg has cond_N > 0 condenses each instance on the GPU (after
+ * oqp_batch_load) into an OCP QP with N2 = min(cond_N, N) stages and solves
+ * that; oqp_batch_solve ends with the expansion, so oqp_batch_get_sol and
+ * oqp_batch_fill_sol return the solution of the original QP.  Blocks: the
+ * stages [s_b, s_{b+1}) with N = q N2 + r, the first r blocks one stage
+ * longer; stage N is the condensed terminal stage.  Condensed stage b has
+ * u = [u_{s_b}; ...; u_{s_{b+1}-1}] and x = x_{s_b}; its box list holds the
+ * input boxes at their offsets and the box of x_{s_b}, in increasing
+ * component order; its general rows are, stage by stage, the state boxes of
+ * the later stages of the block (increasing component) and the stage's own
+ * general rows.  oqp_batch_get_stat reports the solve of the condensed QP
+ * (its residual norms).  The single-Newton-step entries are not available on
+ * such a batch (OQP_ESTATE), nor is condensing in the server.
+ *
+ * Dims of the condensed QP of an instance (caller memory of
+ * oqp_pcond_dims_bytes, 8-byte aligned). */
+size_t oqp_pcond_dims_bytes(const oqp_dims* dims, int cond_N);
+int oqp_pcond_dims(const oqp_dims* dims, int cond_N, void* mem, size_t bytes, oqp_dims** out);
+/* Enqueue the device-to-host copy of the condensed QPs of a loaded batch;
+ * after oqp_batch_sync, oqp_batch_get_cond_qp fills a QP created on the dims
+ * oqp_pcond_dims reports (OQP_EINVAL if they differ, OQP_ESTATE on a batch
+ * without condensing or before the copy). */
+int oqp_batch_fetch_cond(oqp_batch* batch);
+int oqp_batch_get_cond_qp(const oqp_batch* batch, int i, oqp_qp* out);
 
 /* ---- solution object with per-stage getters (Section 1) ------------------ */
 /* Caller memory (16-byte aligned, oqp_sol_bytes) for the solution of a QP with

@@ -37,7 +37,7 @@ class Arg(ct.Structure):
                 ("tol_ineq", ct.c_double), ("tol_comp", ct.c_double), ("iter_max", ct.c_int),
                 ("alpha_min", ct.c_double), ("gamma", ct.c_double), ("lam_min", ct.c_double),
                 ("t_min", ct.c_double), ("reg_prim", ct.c_double), ("corr_ratio", ct.c_double),
-                ("ir_max", ct.c_int), ("ir_tol", ct.c_double), ("warm_start", ct.c_int)]
+                ("ir_max", ct.c_int), ("ir_tol", ct.c_double), ("warm_start", ct.c_int), ("cond_N", ct.c_int)]
 
 
 class Stat(ct.Structure):
@@ -81,6 +81,15 @@ def lib():
         "oqp_qp_set_box_u": (ct.c_int, [_V, ct.c_int, _PI, _P, _P]),
         "oqp_qp_set_box_x": (ct.c_int, [_V, ct.c_int, _PI, _P, _P]),
         "oqp_qp_set_general": (ct.c_int, [_V, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P, _P]),
+        "oqp_qp_get_dyn": (ct.c_int, [_V, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P]),
+        "oqp_qp_get_cost": (ct.c_int, [_V, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P, _P]),
+        "oqp_qp_get_box_u": (ct.c_int, [_V, ct.c_int, _PI, _P, _P]),
+        "oqp_qp_get_box_x": (ct.c_int, [_V, ct.c_int, _PI, _P, _P]),
+        "oqp_qp_get_general": (ct.c_int, [_V, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P, _P]),
+        "oqp_pcond_dims_bytes": (ct.c_size_t, [_V, ct.c_int]),
+        "oqp_pcond_dims": (ct.c_int, [_V, ct.c_int, _V, ct.c_size_t, ct.POINTER(_V)]),
+        "oqp_batch_fetch_cond": (ct.c_int, [_V]),
+        "oqp_batch_get_cond_qp": (ct.c_int, [_V, ct.c_int, _V]),
         "oqp_arg_default": (None, [ct.POINTER(Arg), ct.c_int]),
         "oqp_batch_bytes": (ct.c_int, [ct.POINTER(_V), ct.c_int, ct.POINTER(Arg), ct.POINTER(ct.c_size_t),
                                        ct.POINTER(ct.c_size_t)]),
@@ -179,6 +188,10 @@ def default_arg(mode: int = MODE_F64, **overrides) -> Arg:
     return a
 
 
+class _DimsC(ct.Structure):
+    _fields_ = [("N", ct.c_int)] + [(k, ct.POINTER(ct.c_int)) for k in ("nx", "nu", "nbu", "nbx", "ng")]
+
+
 class Dims:
     def __init__(self, N: int, nx, nu, nbu, nbx, ng):
         L = lib()
@@ -193,6 +206,23 @@ class Dims:
     @classmethod
     def of(cls, qp) -> "Dims":
         return cls(qp.N, qp.nx, qp.nu, qp.nbu, qp.nbx, qp.ng)
+
+    @classmethod
+    def condensed(cls, qp, cond_N: int) -> "Dims":
+        """Dims of the partially condensed QP (oqp_pcond_dims)."""
+        L = lib()
+        src = Dims.of(qp)
+        mem = _aligned(L.oqp_pcond_dims_bytes(src.h, int(cond_N)))
+        h = _V()
+        _check(L.oqp_pcond_dims(src.h, int(cond_N), mem.ctypes.data, mem.nbytes, ct.byref(h)))
+        c = ct.cast(h, ct.POINTER(_DimsC)).contents
+        N = c.N
+        sizes = {k: [getattr(c, k)[n] for n in range(N + 1)] for k in ("nx", "nu", "nbu", "nbx", "ng")}
+        return cls(N, **sizes)
+
+    def sizes(self):
+        c = ct.cast(self.h, ct.POINTER(_DimsC)).contents
+        return {k: [getattr(c, k)[n] for n in range(self.N + 1)] for k in ("nx", "nu", "nbu", "nbx", "ng")}
 
 
 class Qp:
@@ -332,6 +362,52 @@ class Batch:
         a, b, c = ct.c_int(), ct.c_int(), ct.c_int()
         v = lib().oqp_batch_variant(self.h, i, ct.byref(a), ct.byref(b), ct.byref(c))
         return v, (a.value, b.value, c.value)
+
+    def fetch_cond(self):
+        _check(lib().oqp_batch_fetch_cond(self.h))
+        return self
+
+    def cond_qp(self, i: int):
+        """The condensed QP of instance i (after fetch_cond + sync), with the
+        field names of an OcpQp."""
+        d = Dims.condensed(self.qps[i], self.arg.cond_N)
+        L = lib()
+        mem = _aligned(L.oqp_qp_bytes(d.h))
+        h = _V()
+        _check(L.oqp_qp_init(d.h, mem.ctypes.data, mem.nbytes, ct.byref(h)))
+        _check(L.oqp_batch_get_cond_qp(self.h, i, h))
+        return qp_fields(h, d)
+
+
+def qp_fields(h, dims: Dims):
+    """Read an oqp_qp back through the getters into OcpQp field lists."""
+    L = lib()
+    sz = dims.sizes()
+    N = dims.N
+    out = {k: [] for k in ("A", "B", "b", "Q", "S", "R", "q", "r", "idxbu", "lbu", "ubu", "idxbx", "lbx", "ubx",
+                           "D", "C", "lg", "ug")}
+    for n in range(N + 1):
+        nx, nu, nbu, nbx, ng = (sz[k][n] for k in ("nx", "nu", "nbu", "nbx", "ng"))
+        if n < N:
+            nxn = sz["nx"][n + 1]
+            A, B, b = np.zeros((nxn, nx), order="F"), np.zeros((nxn, nu), order="F"), np.zeros(nxn)
+            _check(L.oqp_qp_get_dyn(h, n, _p(A), max(nxn, 1), _p(B), max(nxn, 1), _p(b)))
+            out["A"].append(A); out["B"].append(B); out["b"].append(b)
+        Q, S, R = np.zeros((nx, nx), order="F"), np.zeros((nu, nx), order="F"), np.zeros((nu, nu), order="F")
+        q, r = np.zeros(nx), np.zeros(nu)
+        _check(L.oqp_qp_get_cost(h, n, _p(Q), max(nx, 1), _p(S), max(nu, 1), _p(R), max(nu, 1), _p(q), _p(r)))
+        out["Q"].append(Q); out["S"].append(S); out["R"].append(R); out["q"].append(q); out["r"].append(r)
+        for key, nb, fn in (("u", nbu, L.oqp_qp_get_box_u), ("x", nbx, L.oqp_qp_get_box_x)):
+            idx, lo, hi = np.zeros(max(nb, 1), dtype=np.int32), np.zeros(max(nb, 1)), np.zeros(max(nb, 1))
+            _check(fn(h, n, idx.ctypes.data_as(_PI), _p(lo), _p(hi)))
+            out["idxb" + key].append(idx[:nb].copy()); out["lb" + key].append(lo[:nb].copy())
+            out["ub" + key].append(hi[:nb].copy())
+        D, C = np.zeros((ng, nu), order="F"), np.zeros((ng, nx), order="F")
+        lg, ug = np.zeros(max(ng, 1)), np.zeros(max(ng, 1))
+        _check(L.oqp_qp_get_general(h, n, _p(D), max(ng, 1), _p(C), max(ng, 1), _p(lg), _p(ug)))
+        out["D"].append(D); out["C"].append(C); out["lg"].append(lg[:ng].copy()); out["ug"].append(ug[:ng].copy())
+    import types
+    return types.SimpleNamespace(N=N, nx=sz["nx"], nu=sz["nu"], **out)
 
 
 def solve(qps: Sequence, arg: Arg | None = None) -> List[Result]:
@@ -534,4 +610,6 @@ EXPORTED = [
     "oqp_server_poll", "oqp_server_latency", "oqp_server_get_sol", "oqp_server_release", "oqp_server_stats",
     "oqp_server_replay", "oqp_set_wave_max", "oqp_get_wave_max", "oqp_sol_bytes", "oqp_sol_init",
     "oqp_batch_fill_sol", "oqp_server_fill_sol", "oqp_sol_get_stat", "oqp_res_get_norms",
+    "oqp_qp_get_dyn", "oqp_qp_get_cost", "oqp_qp_get_box_u", "oqp_qp_get_box_x", "oqp_qp_get_general",
+    "oqp_pcond_dims_bytes", "oqp_pcond_dims", "oqp_batch_fetch_cond", "oqp_batch_get_cond_qp",
 ] + ["oqp_sol_get_" + g for g in SOL_FIELDS]

@@ -26,7 +26,7 @@ FLAGS = [
 
 def sources():
     units = sorted(glob.glob(os.path.join(CSRC, "ipm_v*.hip"))) + [os.path.join(CSRC, "ipm_block.hip")]
-    return units + [os.path.join(CSRC, f) for f in ("ipm_registry.hip", "capi.cpp", "serve.cpp", "sol.cpp")]
+    return units + [os.path.join(CSRC, f) for f in ("ipm_registry.hip", "pcond.hip", "capi.cpp", "serve.cpp", "sol.cpp")]
 
 
 def _compile(src, obj):

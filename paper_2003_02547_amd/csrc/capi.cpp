@@ -269,6 +269,98 @@ extern "C" int oqp_qp_set_general(oqp_qp* q, int n, const double* D, int ldd, co
     return OQP_OK;
 }
 
+// Getters mirror the setters: column-major copies into caller arrays with
+// the given leading dimensions (Q and R in full); NULL skips a field.
+static void copy_out(double* dst, int ld, const double* src, int rows, int cols)
+{
+    for (int j = 0; j < cols; ++j)
+        for (int i = 0; i < rows; ++i) dst[i + (size_t)j * ld] = src[i + (size_t)j * rows];
+}
+
+static int check_ld(const char* name, int ld, int rows)
+{
+    return ld < rows || ld < 1 ? fail(OQP_EINVAL, "%s: leading dimension %d < %d", name, ld, rows) : OQP_OK;
+}
+
+extern "C" int oqp_qp_get_dyn(const oqp_qp* q, int n, double* A, int lda, double* B, int ldb, double* b)
+{
+    if (!q || n < 0 || n >= q->dims->N) return fail(OQP_EINVAL, "oqp_qp_get_dyn: stage %d out of range", n);
+    const int nx = q->dims->nx[n], nu = q->dims->nu[n], nxn = q->dims->nx[n + 1];
+    if (A && nx > 0) {
+        if (check_ld("oqp_qp_get_dyn", lda, nxn)) return OQP_EINVAL;
+        copy_out(A, lda, qp_field(q, n, F_A), nxn, nx);
+    }
+    if (B && nu > 0) {
+        if (check_ld("oqp_qp_get_dyn", ldb, nxn)) return OQP_EINVAL;
+        copy_out(B, ldb, qp_field(q, n, F_B), nxn, nu);
+    }
+    if (b) std::memcpy(b, qp_field(q, n, F_b), sizeof(double) * nxn);
+    return OQP_OK;
+}
+
+extern "C" int oqp_qp_get_cost(const oqp_qp* q, int n, double* Q, int ldq, double* S, int lds, double* R, int ldr,
+                               double* qv, double* rv)
+{
+    if (!q || n < 0 || n > q->dims->N) return fail(OQP_EINVAL, "oqp_qp_get_cost: stage %d out of range", n);
+    const int nx = q->dims->nx[n], nu = q->dims->nu[n];
+    if (Q && nx > 0) {
+        if (check_ld("oqp_qp_get_cost", ldq, nx)) return OQP_EINVAL;
+        copy_out(Q, ldq, qp_field(q, n, F_Q), nx, nx);
+    }
+    if (S && nu > 0 && nx > 0) {
+        if (check_ld("oqp_qp_get_cost", lds, nu)) return OQP_EINVAL;
+        copy_out(S, lds, qp_field(q, n, F_S), nu, nx);
+    }
+    if (R && nu > 0) {
+        if (check_ld("oqp_qp_get_cost", ldr, nu)) return OQP_EINVAL;
+        copy_out(R, ldr, qp_field(q, n, F_R), nu, nu);
+    }
+    if (qv) std::memcpy(qv, qp_field(q, n, F_q), sizeof(double) * nx);
+    if (rv) std::memcpy(rv, qp_field(q, n, F_r), sizeof(double) * nu);
+    return OQP_OK;
+}
+
+static int get_box(const oqp_qp* q, int n, int* idx, double* lo, double* hi, bool on_u)
+{
+    if (!q || n < 0 || n > q->dims->N)
+        return fail(OQP_EINVAL, "%s: stage %d out of range", on_u ? "oqp_qp_get_box_u" : "oqp_qp_get_box_x", n);
+    const int nb = on_u ? q->dims->nbu[n] : q->dims->nbx[n];
+    const int* src = q->idx + q->ioff[n] + (on_u ? 0 : q->dims->nbu[n]);
+    if (idx) std::memcpy(idx, src, sizeof(int) * nb);
+    if (lo) std::memcpy(lo, qp_field(q, n, on_u ? F_lbu : F_lbx), sizeof(double) * nb);
+    if (hi) std::memcpy(hi, qp_field(q, n, on_u ? F_ubu : F_ubx), sizeof(double) * nb);
+    return OQP_OK;
+}
+
+extern "C" int oqp_qp_get_box_u(const oqp_qp* q, int n, int* idx, double* lo, double* hi)
+{
+    return get_box(q, n, idx, lo, hi, true);
+}
+
+extern "C" int oqp_qp_get_box_x(const oqp_qp* q, int n, int* idx, double* lo, double* hi)
+{
+    return get_box(q, n, idx, lo, hi, false);
+}
+
+extern "C" int oqp_qp_get_general(const oqp_qp* q, int n, double* D, int ldd, double* C, int ldc, double* lo,
+                                  double* hi)
+{
+    if (!q || n < 0 || n > q->dims->N) return fail(OQP_EINVAL, "oqp_qp_get_general: stage %d out of range", n);
+    const int ng = q->dims->ng[n], nu = q->dims->nu[n], nx = q->dims->nx[n];
+    if (ng == 0) return OQP_OK;
+    if (D && nu > 0) {
+        if (check_ld("oqp_qp_get_general", ldd, ng)) return OQP_EINVAL;
+        copy_out(D, ldd, qp_field(q, n, F_D), ng, nu);
+    }
+    if (C && nx > 0) {
+        if (check_ld("oqp_qp_get_general", ldc, ng)) return OQP_EINVAL;
+        copy_out(C, ldc, qp_field(q, n, F_C), ng, nx);
+    }
+    if (lo) std::memcpy(lo, qp_field(q, n, F_lg), sizeof(double) * ng);
+    if (hi) std::memcpy(hi, qp_field(q, n, F_ug), sizeof(double) * ng);
+    return OQP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // arguments
 // ---------------------------------------------------------------------------
@@ -290,14 +382,16 @@ extern "C" void oqp_arg_default(oqp_arg* a, int mode)
     a->ir_max = a->mode == OQP_MODE_MIXED ? 4 : 0;
     a->ir_tol = 1e-10;
     a->warm_start = 0;
+    a->cond_N = 0;
 }
 
 int check_arg(const oqp_arg* a)
 {
     if (!a) return fail(OQP_EINVAL, "NULL oqp_arg");
     if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED) return fail(OQP_EINVAL, "unknown mode %d", a->mode);
-    if (a->iter_max < 0 || !(a->gamma > 0.0 && a->gamma <= 1.0) || a->warm_start != 0 || a->ir_max < 0)
-        return fail(OQP_EINVAL, "bad oqp_arg field (iter_max, gamma or warm_start)");
+    if (a->iter_max < 0 || !(a->gamma > 0.0 && a->gamma <= 1.0) || a->warm_start != 0 || a->ir_max < 0 ||
+        a->cond_N < 0)
+        return fail(OQP_EINVAL, "bad oqp_arg field (iter_max, gamma, warm_start or cond_N)");
     return OQP_OK;
 }
 
@@ -305,16 +399,23 @@ int check_arg(const oqp_arg* a)
 // batch
 // ---------------------------------------------------------------------------
 
+// An instance as solved (the QP itself, or its condensed QP) and as given
+// (the original horizon and record sizes; equal to the solved ones without
+// condensing).
 struct Inst {
     int variant;    // kernel group (see select_kernel)
     int nx, nu, ng; // padded stage sizes of the device records
-    int N;
+    int N;          // horizon of the solved QP
     int nc;
-    int dims_off;   // into dims pool: 5 * (N+1) ints (nx, nu, nbu, nbx, ng)
-    int slot_off;   // into slot pool: per-stage user constraint -> padded slot
+    int dims_off;   // into dims pool: 5 * (oN+1) ints (nx, nu, nbu, nbx, ng) of the original QP
+    int slot_off;   // into slot pool: per-stage user constraint -> padded slot (original records)
     int64_t data;   // doubles
     int64_t iter;   // doubles
     int64_t work;   // doubles
+    int oN;              // horizon of the original QP
+    int onx, onu, ong;   // record sizes of the original QP
+    int64_t odata;       // original data records (into hdata/ddata, or the condensing regions)
+    int64_t oiter;       // original-layout iterate records
 };
 
 struct oqp_batch {
@@ -345,16 +446,27 @@ struct oqp_batch {
     double* dstep;
     // sizes (doubles)
     int64_t n_data, n_iter, n_work;
+    // partial condensing (cond != 0): original QPs, expanded iterates, the
+    // stage tables and work items of the condensing kernels
+    int cond;
+    int cond_fetched;
+    int n_items;
+    size_t cond_lds;
+    int64_t n_odata, n_oiter;
+    double* hodata;
+    double* hoiter;
+    oqp::CondDesc* hcdesc;
+    oqp::CondItem* hitems;
+    int* htab;
+    double* dodata;
+    double* doiter;
+    oqp::CondDesc* dcdesc;
+    oqp::CondItem* ditems;
+    int* dtab;
 };
 
-int pick_variant(const oqp_dims* d)
+static int pick_variant_max(int mx, int mu, int mg)
 {
-    int mx = 0, mu = 0, mg = 0;
-    for (int n = 0; n <= d->N; ++n) {
-        if (d->nx[n] > mx) mx = d->nx[n];
-        if (d->nu[n] > mu) mu = d->nu[n];
-        if (d->ng[n] > mg) mg = d->ng[n];
-    }
     int best = -1;
     long best_cost = 0;
     for (int v = 0; v < oqp::variant_count(); ++v) {
@@ -371,6 +483,17 @@ int pick_variant(const oqp_dims* d)
     return best;
 }
 
+int pick_variant(const oqp_dims* d)
+{
+    int mx = 0, mu = 0, mg = 0;
+    for (int n = 0; n <= d->N; ++n) {
+        if (d->nx[n] > mx) mx = d->nx[n];
+        if (d->nu[n] > mu) mu = d->nu[n];
+        if (d->ng[n] > mg) mg = d->ng[n];
+    }
+    return pick_variant_max(mx, mu, mg);
+}
+
 // Kernel groups: 0..variant_count()-1 are the one-wave variants; the block
 // kernel builds follow (stage-block bound 32 or 64, without or with general
 // rows).  One-wave variants are used up to a stage block of g_wave_max_nz,
@@ -383,15 +506,20 @@ static constexpr size_t kMaxLds = 160 * 1024;
 
 int group_count() { return oqp::variant_count() + 6; }
 
-int select_kernel(const oqp_dims* d, KSel* out)
+static void dims_max(const oqp_dims* d, int* mx, int* mu, int* mg)
 {
-    int mx = 0, mu = 0, mg = 0;
+    *mx = *mu = *mg = 0;
     for (int n = 0; n <= d->N; ++n) {
-        if (d->nx[n] > mx) mx = d->nx[n];
-        if (d->nu[n] > mu) mu = d->nu[n];
-        if (d->ng[n] > mg) mg = d->ng[n];
+        if (d->nx[n] > *mx) *mx = d->nx[n];
+        if (d->nu[n] > *mu) *mu = d->nu[n];
+        if (d->ng[n] > *mg) *mg = d->ng[n];
     }
-    const int v = pick_variant(d);
+}
+
+// kernel for an instance whose largest stage sizes are mx, mu, mg
+static int select_kernel_max(int mx, int mu, int mg, KSel* out)
+{
+    const int v = pick_variant_max(mx, mu, mg);
     if (v >= 0) {
         int nx, nu, ng;
         oqp::variant_dims(v, &nx, &nu, &ng);
@@ -408,6 +536,108 @@ int select_kernel(const oqp_dims* d, KSel* out)
     if ((size_t)oqp::block_lds_bytes(mx, mu, mg) > kMaxLds) return -1;
     const int b = (zm == 256 ? 4 : (zm == 64 ? 2 : 0)) + (mg > 0 ? 1 : 0);
     *out = KSel{oqp::variant_count() + b, mx, mu, mg};
+    return OQP_OK;
+}
+
+int select_kernel(const oqp_dims* d, KSel* out)
+{
+    int mx, mu, mg;
+    dims_max(d, &mx, &mu, &mg);
+    return select_kernel_max(mx, mu, mg, out);
+}
+
+// ---------------------------------------------------------------------------
+// partial condensing: blocks and condensed stage sizes (Section 3.5)
+// ---------------------------------------------------------------------------
+
+static int cond_horizon(int N, int cond_N) { return cond_N < N ? cond_N : N; }
+
+// first stage of block b of N2 (block N2 starts at N): near-equal blocks, the
+// first N mod N2 of them one stage longer
+static int cond_start(int N, int N2, int b)
+{
+    const int q = N / N2, r = N % N2;
+    return b * q + (b < r ? b : r);
+}
+
+struct CStage {
+    int nx, nu, nbu, nbx, ng;
+};
+
+// sizes of condensed stage b (b = N2: the terminal stage N)
+static CStage cond_stage(const oqp_dims* d, int N2, int b)
+{
+    const int s0 = b < N2 ? cond_start(d->N, N2, b) : d->N;
+    const int s1 = b < N2 ? cond_start(d->N, N2, b + 1) : d->N + 1;
+    CStage c{d->nx[s0], 0, 0, d->nbx[s0], 0};
+    for (int n = s0; n < s1; ++n) {
+        c.nu += d->nu[n];
+        c.nbu += d->nbu[n];
+        c.ng += d->ng[n] + (n > s0 ? d->nbx[n] : 0);
+    }
+    return c;
+}
+
+extern "C" size_t oqp_pcond_dims_bytes(const oqp_dims* d, int cond_N)
+{
+    if (!d || cond_N < 1) return 0;
+    return oqp_dims_bytes(cond_horizon(d->N, cond_N));
+}
+
+extern "C" int oqp_pcond_dims(const oqp_dims* d, int cond_N, void* mem, size_t bytes, oqp_dims** out)
+{
+    if (!d || !out || cond_N < 1) return fail(OQP_EINVAL, "oqp_pcond_dims: bad argument (cond_N=%d)", cond_N);
+    const int N2 = cond_horizon(d->N, cond_N);
+    oqp_dims* c;
+    int rc = oqp_dims_init(mem, bytes, N2, &c);
+    if (rc) return rc;
+    for (int b = 0; b <= N2; ++b) {
+        const CStage s = cond_stage(d, N2, b);
+        c->nx[b] = s.nx;
+        c->nu[b] = s.nu;
+        c->nbu[b] = s.nbu;
+        c->nbx[b] = s.nbx;
+        c->ng[b] = s.ng;
+    }
+    *out = c;
+    return OQP_OK;
+}
+
+// The QP solved for an instance: the QP itself or, with cond_N > 0, its
+// condensed QP; plus the record sizes of the original QP.
+struct SolveShape {
+    int N;
+    KSel ks;
+    int onx, onu, ong;
+};
+
+static constexpr size_t kMaxCondLds = 64 * 1024;
+
+static int solve_shape(const oqp_dims* d, int cond_N, SolveShape* sh, int i)
+{
+    if (cond_N <= 0) {
+        sh->N = d->N;
+        if (select_kernel(d, &sh->ks)) return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d", i);
+        sh->onx = sh->ks.nx;
+        sh->onu = sh->ks.nu;
+        sh->ong = sh->ks.ng;
+        return OQP_OK;
+    }
+    dims_max(d, &sh->onx, &sh->onu, &sh->ong);
+    const int N2 = cond_horizon(d->N, cond_N);
+    int cx = 0, cu = 0, cg = 0;
+    for (int b = 0; b <= N2; ++b) {
+        const CStage c = cond_stage(d, N2, b);
+        if (c.nx > cx) cx = c.nx;
+        if (c.nu > cu) cu = c.nu;
+        if (c.ng > cg) cg = c.ng;
+    }
+    sh->N = N2;
+    if (select_kernel_max(cx, cu, cg, &sh->ks))
+        return fail(OQP_EINVAL, "batch: no kernel covers the condensed stage sizes of instance %d (nx %d, nu %d, ng %d)",
+                    i, cx, cu, cg);
+    if ((size_t)oqp::cond_lds_bytes(sh->onx, sh->onu, sh->ks.nx + sh->ks.nu) > kMaxCondLds)
+        return fail(OQP_EINVAL, "batch: condensed stage of instance %d too large for the condensing kernel", i);
     return OQP_OK;
 }
 
@@ -446,29 +676,44 @@ struct Plan {
     size_t host_bytes, dev_bytes;
     // host offsets
     size_t h_inst, h_dims, h_slot, h_desc, h_stat, h_data, h_iter, h_step, h_vstart, h_vcount;
+    size_t h_odata, h_oiter, h_cdesc, h_items, h_tab;
     // device offsets
     size_t d_desc, d_stat, d_data, d_iter, d_work, d_step;
-    int64_t n_data, n_iter, n_work;
-    int n_dims, n_slot;
+    size_t d_odata, d_oiter, d_cdesc, d_items, d_tab;
+    int64_t n_data, n_iter, n_work, n_odata, n_oiter;
+    int n_dims, n_slot, n_items, n_tab;
+    size_t cond_lds;
 };
 
-static int make_plan(const oqp_dims* const* dims, int count, Plan* pl)
+static int make_plan(const oqp_dims* const* dims, int count, int cond_N, Plan* pl)
 {
     if (!dims || count < 1) return fail(OQP_EINVAL, "batch: count must be >= 1");
     const int nv = group_count();
-    int64_t nd = 0, ni = 0, nw = 0;
-    int ndims = 0, nslot = 0;
+    const int cond = cond_N > 0;
+    int64_t nd = 0, ni = 0, nw = 0, nod = 0, noi = 0;
+    int ndims = 0, nslot = 0, nitems = 0, ntab = 0;
+    size_t clds = 0;
     for (int i = 0; i < count; ++i) {
         const oqp_dims* d = dims[i];
         if (!d) return fail(OQP_EINVAL, "batch: dims[%d] is NULL", i);
-        KSel ks;
-        if (select_kernel(d, &ks)) return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d", i);
-        const Layout L = oqp::make_layout(ks.nx, ks.nu, ks.ng);
-        nd += (int64_t)(d->N + 1) * L.SREC;
-        ni += (int64_t)(d->N + 1) * L.IREC;
-        nw += (int64_t)(d->N + 1) * L.WREC;
+        SolveShape sh;
+        int rc = solve_shape(d, cond_N, &sh, i);
+        if (rc) return rc;
+        const Layout L = oqp::make_layout(sh.ks.nx, sh.ks.nu, sh.ks.ng);
+        nd += (int64_t)(sh.N + 1) * L.SREC;
+        ni += (int64_t)(sh.N + 1) * L.IREC;
+        nw += (int64_t)(sh.N + 1) * L.WREC;
         ndims += 5 * (d->N + 1);
         for (int n = 0; n <= d->N; ++n) nslot += d->nbu[n] + d->nbx[n] + d->ng[n];
+        if (cond) {
+            const Layout Lo = oqp::make_layout(sh.onx, sh.onu, sh.ong);
+            nod += (int64_t)(d->N + 1) * Lo.SREC;
+            noi += (int64_t)(d->N + 1) * Lo.IREC;
+            nitems += sh.N + 1;
+            ntab += 4 * (d->N + 1) + sh.N + 1;
+            const size_t lb = (size_t)oqp::cond_lds_bytes(sh.onx, sh.onu, sh.ks.nx + sh.ks.nu);
+            if (lb > clds) clds = lb;
+        }
     }
     size_t h = 0;
     h = align_up(h + sizeof(oqp_batch), 64);
@@ -482,6 +727,11 @@ static int make_plan(const oqp_dims* const* dims, int count, Plan* pl)
     pl->h_data = h; h = align_up(h + sizeof(double) * nd, 64);
     pl->h_iter = h; h = align_up(h + sizeof(double) * ni, 64);
     pl->h_step = h; h = align_up(h + sizeof(double) * ni, 64);
+    pl->h_odata = h; h = align_up(h + sizeof(double) * nod, 64);
+    pl->h_oiter = h; h = align_up(h + sizeof(double) * noi, 64);
+    pl->h_cdesc = h; h = align_up(h + sizeof(oqp::CondDesc) * (cond ? count : 0), 64);
+    pl->h_items = h; h = align_up(h + sizeof(oqp::CondItem) * nitems, 64);
+    pl->h_tab = h; h = align_up(h + sizeof(int) * ntab, 64);
     pl->host_bytes = h;
     size_t g = 0;
     pl->d_desc = g; g = align_up(g + sizeof(InstDesc) * count, 256);
@@ -490,9 +740,17 @@ static int make_plan(const oqp_dims* const* dims, int count, Plan* pl)
     pl->d_iter = g; g = align_up(g + sizeof(double) * ni, 256);
     pl->d_work = g; g = align_up(g + sizeof(double) * nw, 256);
     pl->d_step = g; g = align_up(g + sizeof(double) * ni, 256);
+    pl->d_odata = g; g = align_up(g + sizeof(double) * nod, 256);
+    pl->d_oiter = g; g = align_up(g + sizeof(double) * noi, 256);
+    pl->d_cdesc = g; g = align_up(g + sizeof(oqp::CondDesc) * (cond ? count : 0), 256);
+    pl->d_items = g; g = align_up(g + sizeof(oqp::CondItem) * nitems, 256);
+    pl->d_tab = g; g = align_up(g + sizeof(int) * ntab, 256);
     pl->dev_bytes = g;
     pl->n_data = nd; pl->n_iter = ni; pl->n_work = nw;
+    pl->n_odata = nod; pl->n_oiter = noi;
     pl->n_dims = ndims; pl->n_slot = nslot;
+    pl->n_items = nitems; pl->n_tab = ntab;
+    pl->cond_lds = clds;
     return OQP_OK;
 }
 
@@ -502,7 +760,7 @@ extern "C" int oqp_batch_bytes(const oqp_dims* const* dims, int count, const oqp
     int rc = check_arg(arg);
     if (rc) return rc;
     Plan pl;
-    rc = make_plan(dims, count, &pl);
+    rc = make_plan(dims, count, arg->cond_N, &pl);
     if (rc) return rc;
     if (host_bytes) *host_bytes = pl.host_bytes;
     if (dev_bytes) *dev_bytes = pl.dev_bytes;
@@ -510,6 +768,8 @@ extern "C" int oqp_batch_bytes(const oqp_dims* const* dims, int count, const oqp
 }
 
 static const Layout inst_layout(const Inst& in) { return oqp::make_layout(in.nx, in.nu, in.ng); }
+// records of the QP as given (the solved records without condensing)
+static const Layout orig_layout(const Inst& in) { return oqp::make_layout(in.onx, in.onu, in.ong); }
 
 extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_arg* arg, void* host_mem,
                               size_t host_bytes, void* dev_mem, size_t dev_bytes, void* stream, oqp_batch** out)
@@ -520,7 +780,7 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
     if ((uintptr_t)host_mem % 16) return fail(OQP_EINVAL, "oqp_batch_init: host memory not 16-byte aligned");
     if ((uintptr_t)dev_mem % 256) return fail(OQP_EINVAL, "oqp_batch_init: device memory not 256-byte aligned");
     Plan pl;
-    rc = make_plan(dims, count, &pl);
+    rc = make_plan(dims, count, arg->cond_N, &pl);
     if (rc) return rc;
     if (host_bytes < pl.host_bytes) return fail(OQP_ENOMEM, "oqp_batch_init: host %zu < %zu", host_bytes, pl.host_bytes);
     if (dev_bytes < pl.dev_bytes) return fail(OQP_ENOMEM, "oqp_batch_init: device %zu < %zu", dev_bytes, pl.dev_bytes);
@@ -551,19 +811,39 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
     b->n_data = pl.n_data;
     b->n_iter = pl.n_iter;
     b->n_work = pl.n_work;
+    b->cond = arg->cond_N > 0;
+    b->n_items = pl.n_items;
+    b->cond_lds = pl.cond_lds;
+    b->n_odata = pl.n_odata;
+    b->n_oiter = pl.n_oiter;
+    b->hodata = (double*)(h + pl.h_odata);
+    b->hoiter = (double*)(h + pl.h_oiter);
+    b->hcdesc = (oqp::CondDesc*)(h + pl.h_cdesc);
+    b->hitems = (oqp::CondItem*)(h + pl.h_items);
+    b->htab = (int*)(h + pl.h_tab);
+    b->dodata = (double*)(g + pl.d_odata);
+    b->doiter = (double*)(g + pl.d_oiter);
+    b->dcdesc = (oqp::CondDesc*)(g + pl.d_cdesc);
+    b->ditems = (oqp::CondItem*)(g + pl.d_items);
+    b->dtab = (int*)(g + pl.d_tab);
     // instances, grouped by variant
     int doff = 0, soff = 0;
     for (int v = 0; v < b->nvar; ++v) b->vcount[v] = 0;
     for (int i = 0; i < count; ++i) {
         Inst& in = b->inst[i];
         const oqp_dims* d = dims[i];
-        KSel ks;
-        select_kernel(d, &ks);
+        SolveShape sh;
+        solve_shape(d, arg->cond_N, &sh, i);
+        const KSel& ks = sh.ks;
         in.variant = ks.group;
         in.nx = ks.nx;
         in.nu = ks.nu;
         in.ng = ks.ng;
-        in.N = d->N;
+        in.N = sh.N;
+        in.oN = d->N;
+        in.onx = sh.onx;
+        in.onu = sh.onu;
+        in.ong = sh.ong;
         in.dims_off = doff;
         in.slot_off = soff;
         int nc = 0;
@@ -621,8 +901,53 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
             ds.pad2 = 0;
         }
     }
-    hipError_t e = hipMemcpyAsync(b->ddesc, b->hdesc, sizeof(InstDesc) * count, hipMemcpyHostToDevice,
-                                  (hipStream_t)stream);
+    // original records: the solved ones, or (condensing) regions of their own
+    int64_t ood = 0, ooi = 0;
+    int ot = 0, oit = 0;
+    for (int i = 0; i < count; ++i) {
+        Inst& in = b->inst[i];
+        if (!b->cond) {
+            in.odata = in.data;
+            in.oiter = in.iter;
+            continue;
+        }
+        const Layout Lo = orig_layout(in);
+        in.odata = ood;
+        in.oiter = ooi;
+        ood += (int64_t)(in.oN + 1) * Lo.SREC;
+        ooi += (int64_t)(in.oN + 1) * Lo.IREC;
+        oqp::CondDesc& cd = b->hcdesc[i];
+        std::memset(&cd, 0, sizeof(cd));
+        cd.odata = in.odata;
+        cd.oiter = in.oiter;
+        cd.cdata = in.data;
+        cd.citer = in.iter;
+        cd.N = in.oN;
+        cd.N2 = in.N;
+        cd.tab = ot;
+        cd.onx = in.onx;
+        cd.onu = in.onu;
+        cd.ong = in.ong;
+        cd.cnx = in.nx;
+        cd.cnu = in.nu;
+        cd.cng = in.ng;
+        const oqp_dims* d = dims[i];
+        for (int n = 0; n <= in.oN; ++n) {
+            b->htab[ot++] = d->nx[n];
+            b->htab[ot++] = d->nu[n];
+            b->htab[ot++] = d->nbx[n];
+            b->htab[ot++] = d->ng[n];
+        }
+        for (int c = 0; c <= in.N; ++c) b->htab[ot++] = c < in.N ? cond_start(in.oN, in.N, c) : in.oN;
+        for (int c = 0; c <= in.N; ++c) b->hitems[oit++] = oqp::CondItem{i, c};
+    }
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(b->ddesc, b->hdesc, sizeof(InstDesc) * count, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && b->cond)
+        e = hipMemcpyAsync(b->dcdesc, b->hcdesc, sizeof(oqp::CondDesc) * count, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && b->cond)
+        e = hipMemcpyAsync(b->ditems, b->hitems, sizeof(oqp::CondItem) * oit, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && b->cond) e = hipMemcpyAsync(b->dtab, b->htab, sizeof(int) * ot, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_init: hipMemcpyAsync: %s", hipGetErrorString(e));
     *out = b;
     return OQP_OK;
@@ -630,7 +955,7 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
 
 static inline const int* inst_dims(const oqp_batch* b, const Inst& in, int which)
 {
-    return b->dims_pool + in.dims_off + which * (in.N + 1);
+    return b->dims_pool + in.dims_off + which * (in.oN + 1);
 }
 
 // Pack a QP into N+1 padded stage records (L.SREC doubles each) at dst and
@@ -726,19 +1051,19 @@ int pack_records(const oqp_qp* q, const Layout& L, double* dst, int* slots)
 static int pack_instance(oqp_batch* b, int i, const oqp_qp* q)
 {
     const Inst& in = b->inst[i];
-    const Layout L = inst_layout(in);
+    const Layout L = orig_layout(in);
     const int* nxv = inst_dims(b, in, 0);
     const int* nuv = inst_dims(b, in, 1);
     const int* nbuv = inst_dims(b, in, 2);
     const int* nbxv = inst_dims(b, in, 3);
     const int* ngv = inst_dims(b, in, 4);
     const oqp_dims* qd = q->dims;
-    if (qd->N != in.N) return fail(OQP_EINVAL, "oqp_batch_load: qp %d horizon differs from its dims", i);
-    for (int n = 0; n <= in.N; ++n)
+    if (qd->N != in.oN) return fail(OQP_EINVAL, "oqp_batch_load: qp %d horizon differs from its dims", i);
+    for (int n = 0; n <= in.oN; ++n)
         if (qd->nx[n] != nxv[n] || qd->nu[n] != nuv[n] || qd->nbu[n] != nbuv[n] || qd->nbx[n] != nbxv[n] ||
             qd->ng[n] != ngv[n])
             return fail(OQP_EINVAL, "oqp_batch_load: qp %d sizes differ from its dims at stage %d", i, n);
-    return pack_records(q, L, b->hdata + in.data, b->slot_pool + in.slot_off);
+    return pack_records(q, L, (b->cond ? b->hodata : b->hdata) + in.odata, b->slot_pool + in.slot_off);
 }
 
 extern "C" int oqp_batch_load(oqp_batch* b, const oqp_qp* const* qps)
@@ -749,10 +1074,16 @@ extern "C" int oqp_batch_load(oqp_batch* b, const oqp_qp* const* qps)
         int rc = pack_instance(b, i, qps[i]);
         if (rc) return rc;
     }
-    hipError_t e = hipMemcpyAsync(b->ddata, b->hdata, sizeof(double) * b->n_data, hipMemcpyHostToDevice,
-                                  (hipStream_t)b->stream);
+    hipError_t e = b->cond ? hipMemcpyAsync(b->dodata, b->hodata, sizeof(double) * b->n_odata,
+                                            hipMemcpyHostToDevice, (hipStream_t)b->stream)
+                           : hipMemcpyAsync(b->ddata, b->hdata, sizeof(double) * b->n_data, hipMemcpyHostToDevice,
+                                            (hipStream_t)b->stream);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_load: hipMemcpyAsync: %s", hipGetErrorString(e));
+    if (b->cond && oqp::cond_launch(0, b->dcdesc, b->ditems, b->n_items, b->dtab, b->dodata, b->ddata, nullptr,
+                                    nullptr, b->cond_lds, b->stream))
+        return fail(OQP_EDEVICE, "oqp_batch_load: condensing kernel launch failed");
     b->loaded = 1;
+    b->cond_fetched = 0;
     return OQP_OK;
 }
 
@@ -805,6 +1136,9 @@ extern "C" int oqp_batch_solve(oqp_batch* b)
     if (!b->loaded) return fail(OQP_ESTATE, "oqp_batch_solve: no data loaded");
     int rc = launch_all(b, make_params(b->arg, oqp::KMODE_SOLVE, 0.0));
     if (rc) return rc;
+    if (b->cond && oqp::cond_launch(1, b->dcdesc, b->ditems, b->n_items, b->dtab, b->dodata, nullptr, b->diter,
+                                    b->doiter, 0, b->stream))
+        return fail(OQP_EDEVICE, "oqp_batch_solve: expansion kernel launch failed");
     b->solved = 1;
     return OQP_OK;
 }
@@ -815,6 +1149,7 @@ extern "C" int oqp_batch_set_arg(oqp_batch* b, const oqp_arg* a)
     int rc = check_arg(a);
     if (rc) return rc;
     if (a->mode != b->arg.mode) return fail(OQP_EINVAL, "oqp_batch_set_arg: mode cannot change");
+    if (a->cond_N != b->arg.cond_N) return fail(OQP_EINVAL, "oqp_batch_set_arg: cond_N cannot change");
     b->arg = *a;
     return OQP_OK;
 }
@@ -825,7 +1160,8 @@ extern "C" int oqp_batch_fetch(oqp_batch* b)
     hipStream_t s = (hipStream_t)b->stream;
     hipError_t e = hipMemcpyAsync(b->hstat, b->dstat, sizeof(DevStat) * b->count, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->hiter, b->diter, sizeof(double) * b->n_iter, hipMemcpyDeviceToHost, s);
+        e = b->cond ? hipMemcpyAsync(b->hoiter, b->doiter, sizeof(double) * b->n_oiter, hipMemcpyDeviceToHost, s)
+                    : hipMemcpyAsync(b->hiter, b->diter, sizeof(double) * b->n_iter, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && b->has_step)
         e = hipMemcpyAsync(b->hstep, b->dstep, sizeof(double) * b->n_iter, hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_fetch: %s", hipGetErrorString(e));
@@ -896,12 +1232,13 @@ void iterate_user_copy(const int* dims5, int N, const int* slots, const Layout& 
     }
 }
 
+// region: original-layout iterate records (hiter/hstep, or hoiter with condensing)
 static void user_copy(const oqp_batch* b, int i, double* region, bool to_user, double* u, double* x, double* pi,
                       double* ll, double* lu, double* tl, double* tu)
 {
     const Inst& in = b->inst[i];
-    iterate_user_copy(b->dims_pool + in.dims_off, in.N, b->slot_pool + in.slot_off, inst_layout(in),
-                      region + in.iter, to_user, u, x, pi, ll, lu, tl, tu);
+    iterate_user_copy(b->dims_pool + in.dims_off, in.oN, b->slot_pool + in.slot_off, orig_layout(in),
+                      region + in.oiter, to_user, u, x, pi, ll, lu, tl, tu);
 }
 
 bool dims5_match(const int* d5, int N, const oqp_dims* d)
@@ -918,14 +1255,14 @@ bool batch_dims_match(const oqp_batch* b, int i, const oqp_dims* d)
 {
     if (!b || i < 0 || i >= b->count) return false;
     const Inst& in = b->inst[i];
-    return dims5_match(b->dims_pool + in.dims_off, in.N, d);
+    return dims5_match(b->dims_pool + in.dims_off, in.oN, d);
 }
 
 extern "C" int oqp_batch_get_sol(const oqp_batch* b, int i, double* u, double* x, double* pi, double* lam_l,
                                  double* lam_u, double* t_l, double* t_u)
 {
     if (!b || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_get_sol: bad argument");
-    user_copy(b, i, b->hiter, true, u, x, pi, lam_l, lam_u, t_l, t_u);
+    user_copy(b, i, b->cond ? b->hoiter : b->hiter, true, u, x, pi, lam_l, lam_u, t_l, t_u);
     return OQP_OK;
 }
 
@@ -934,6 +1271,7 @@ extern "C" int oqp_batch_set_iterate(oqp_batch* b, int i, const double* u, const
 {
     if (!b || i < 0 || i >= b->count || !u || !x || !pi || !lam_l || !lam_u || !t_l || !t_u)
         return fail(OQP_EINVAL, "oqp_batch_set_iterate: bad argument");
+    if (b->cond) return fail(OQP_ESTATE, "oqp_batch_set_iterate: not available with partial condensing");
     const Inst& in = b->inst[i];
     const Layout L = inst_layout(in);
     std::memset(b->hiter + in.iter, 0, sizeof(double) * (size_t)(in.N + 1) * L.IREC);
@@ -946,6 +1284,7 @@ extern "C" int oqp_batch_newton(oqp_batch* b, double tau)
 {
     if (!b) return fail(OQP_EINVAL, "oqp_batch_newton: NULL batch");
     if (!b->loaded) return fail(OQP_ESTATE, "oqp_batch_newton: no data loaded");
+    if (b->cond) return fail(OQP_ESTATE, "oqp_batch_newton: not available with partial condensing");
     hipError_t e = hipMemcpyAsync(b->diter, b->hiter, sizeof(double) * b->n_iter, hipMemcpyHostToDevice,
                                   (hipStream_t)b->stream);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_newton: %s", hipGetErrorString(e));
@@ -961,6 +1300,107 @@ extern "C" int oqp_batch_get_step(const oqp_batch* b, int i, double* du, double*
     if (!b || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_get_step: bad argument");
     if (!b->has_step) return fail(OQP_ESTATE, "oqp_batch_get_step: no Newton step computed");
     user_copy(b, i, b->hstep, true, du, dx, dpi, dll, dlu, dtl, dtu);
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_fetch_cond(oqp_batch* b)
+{
+    if (!b) return fail(OQP_EINVAL, "oqp_batch_fetch_cond: NULL batch");
+    if (!b->cond) return fail(OQP_ESTATE, "oqp_batch_fetch_cond: the batch does not condense");
+    if (!b->loaded) return fail(OQP_ESTATE, "oqp_batch_fetch_cond: no data loaded");
+    hipError_t e = hipMemcpyAsync(b->hdata, b->ddata, sizeof(double) * b->n_data, hipMemcpyDeviceToHost,
+                                  (hipStream_t)b->stream);
+    if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_fetch_cond: %s", hipGetErrorString(e));
+    b->cond_fetched = 1;
+    return OQP_OK;
+}
+
+// Unpack the condensed records of instance i (host copy) into a QP with the
+// condensed dims: the inverse of pack_records for one record layout.
+extern "C" int oqp_batch_get_cond_qp(const oqp_batch* b, int i, oqp_qp* q)
+{
+    if (!b || !q || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_get_cond_qp: bad argument");
+    if (!b->cond || !b->cond_fetched) return fail(OQP_ESTATE, "oqp_batch_get_cond_qp: no condensed QP fetched");
+    const Inst& in = b->inst[i];
+    const oqp_dims* qd = q->dims;
+    const int N2 = in.N, N = in.oN;
+    const int* d5 = b->dims_pool + in.dims_off;
+    oqp_dims od{N, (int*)d5, (int*)d5 + (N + 1), (int*)d5 + 2 * (N + 1), (int*)d5 + 3 * (N + 1),
+                (int*)d5 + 4 * (N + 1)};
+    if (qd->N != N2) return fail(OQP_EINVAL, "oqp_batch_get_cond_qp: horizon %d, expected %d", qd->N, N2);
+    for (int c = 0; c <= N2; ++c) {
+        const CStage cs = cond_stage(&od, N2, c);
+        if (qd->nx[c] != cs.nx || qd->nu[c] != cs.nu || qd->nbu[c] != cs.nbu || qd->nbx[c] != cs.nbx ||
+            qd->ng[c] != cs.ng)
+            return fail(OQP_EINVAL, "oqp_batch_get_cond_qp: stage %d sizes differ from the condensed QP", c);
+    }
+    const Layout L = inst_layout(in);
+    const int NU = L.NU, NZ = L.NZ, NX = L.NX, NG = L.NG;
+    for (int n = 0; n <= N2; ++n) {
+        const double* r = b->hdata + in.data + (int64_t)n * L.SREC;
+        const int nx = qd->nx[n], nu = qd->nu[n], ng = qd->ng[n], nxn = n < N2 ? qd->nx[n + 1] : 0;
+        if (n < N2) {
+            double* A = qp_field(q, n, F_A);
+            double* B = qp_field(q, n, F_B);
+            double* bb = qp_field(q, n, F_b);
+            for (int j = 0; j < nx; ++j)
+                for (int k = 0; k < nxn; ++k) A[k + (size_t)j * nxn] = r[L.D_F + k + (NU + j) * NX];
+            for (int j = 0; j < nu; ++j)
+                for (int k = 0; k < nxn; ++k) B[k + (size_t)j * nxn] = r[L.D_F + k + j * NX];
+            for (int k = 0; k < nxn; ++k) bb[k] = r[L.D_b + k];
+        }
+        double* Q = qp_field(q, n, F_Q);
+        double* S = qp_field(q, n, F_S);
+        double* R = qp_field(q, n, F_R);
+        const double* H = r + L.D_H;
+        for (int j = 0; j < nu; ++j)
+            for (int k = 0; k < nu; ++k) R[k + (size_t)j * nu] = H[k + j * NZ];
+        for (int j = 0; j < nx; ++j)
+            for (int k = 0; k < nu; ++k) S[k + (size_t)j * nu] = H[k + (NU + j) * NZ];
+        for (int j = 0; j < nx; ++j)
+            for (int k = 0; k < nx; ++k) Q[k + (size_t)j * nx] = H[(NU + k) + (NU + j) * NZ];
+        double* rv = qp_field(q, n, F_r);
+        double* qv = qp_field(q, n, F_q);
+        for (int j = 0; j < nu; ++j) rv[j] = r[L.D_g + j];
+        for (int j = 0; j < nx; ++j) qv[j] = r[L.D_g + NU + j];
+        // boxes in increasing component order
+        int* iu = q->idx + q->ioff[n];
+        int* ix = iu + qd->nbu[n];
+        double* lbu = qp_field(q, n, F_lbu);
+        double* ubu = qp_field(q, n, F_ubu);
+        double* lbx = qp_field(q, n, F_lbx);
+        double* ubx = qp_field(q, n, F_ubx);
+        int k = 0;
+        for (int j = 0; j < nu; ++j)
+            if (r[L.D_bm + j] != 0.0) {
+                if (k == qd->nbu[n]) return fail(OQP_EINVAL, "oqp_batch_get_cond_qp: input boxes exceed nbu");
+                iu[k] = j;
+                lbu[k] = r[L.D_blo + j];
+                ubu[k] = r[L.D_bhi + j];
+                ++k;
+            }
+        k = 0;
+        for (int j = 0; j < nx; ++j)
+            if (r[L.D_bm + NU + j] != 0.0) {
+                if (k == qd->nbx[n]) return fail(OQP_EINVAL, "oqp_batch_get_cond_qp: state boxes exceed nbx");
+                ix[k] = j;
+                lbx[k] = r[L.D_blo + NU + j];
+                ubx[k] = r[L.D_bhi + NU + j];
+                ++k;
+            }
+        if (ng > 0) {
+            double* D = qp_field(q, n, F_D);
+            double* C = qp_field(q, n, F_C);
+            double* lg = qp_field(q, n, F_lg);
+            double* ug = qp_field(q, n, F_ug);
+            for (int g = 0; g < ng; ++g) {
+                for (int j = 0; j < nu; ++j) D[g + (size_t)j * ng] = r[L.D_G + g + j * NG];
+                for (int j = 0; j < nx; ++j) C[g + (size_t)j * ng] = r[L.D_G + g + (NU + j) * NG];
+                lg[g] = r[L.D_glo + g];
+                ug[g] = r[L.D_ghi + g];
+            }
+        }
+    }
     return OQP_OK;
 }
 

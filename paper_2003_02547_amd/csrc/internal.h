@@ -36,6 +36,12 @@ int block_lds_bytes(int nx, int nu, int ng);
 int block_zmax(int nz);
 int block_launch(int zm, int gm, int mixed, const InstDesc* desc, int count, const double* data, double* iter,
                  double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
+// partial condensing (expand = 0: original data -> condensed data records;
+// expand = 1: condensed iterate -> original-layout iterate records)
+int cond_lds_bytes(int onx, int onu, int cnz);
+int cond_launch(int expand, const CondDesc* cds, const CondItem* items, int nitems, const int* tab,
+                const double* odata, double* cdata, const double* citer, double* oiter, size_t lds_bytes,
+                void* stream);
 }  // namespace oqp
 
 // Kernel chosen for an instance: group (a one-wave variant index, or a block

@@ -117,6 +117,30 @@ struct InstDesc {
     int32_t pad2;
 };
 
+// Partial condensing (Section 3.5), one descriptor per instance.  Offsets
+// are in doubles; the original QP keeps its own record layout (stage sizes
+// onx, onu, ong), the condensed QP uses the layout of the kernel that solves
+// it (cnx, cnu, cng).
+struct CondDesc {
+    int64_t odata;   // original data records (N + 1)
+    int64_t oiter;   // expanded iterate records (N + 1), original layout
+    int64_t cdata;   // condensed data records (N2 + 1)
+    int64_t citer;   // condensed iterate records (N2 + 1)
+    int32_t N, N2;   // original and condensed horizon
+    int32_t tab;     // int offset of the stage table: (nx, nu, nbx, ng) per
+                     // original stage, then the N2 + 1 block starts
+    int32_t onx, onu, ong;
+    int32_t cnx, cnu, cng;
+    int32_t pad;
+};
+
+// One workgroup of the condensing and expansion kernels: block b of
+// instance inst (b = N2 is the terminal stage).
+struct CondItem {
+    int32_t inst;
+    int32_t block;
+};
+
 // Per-instance result written by the kernel.
 struct DevStat {
     int32_t status;
