@@ -8,6 +8,8 @@ timed region.  One step = one full IPM solve of the whole batch (cold start
 to the KKT tolerance), FP64 path; the mixed path is timed beside it.
 
 Further legs on the same line (context, not the headline):
+  * pcond: the same batch solved through partial condensing to a shorter
+    horizon (condensing and expansion inside the timed solve);
   * uneven: a batch of random stable OCP QPs with nx ~ U{4..48},
     nu ~ U{1..16}, N ~ U{10..100} (one-wave variants plus the block kernel);
   * serve: the continuous-batching server replaying Poisson arrivals over a
@@ -114,6 +116,39 @@ def leg_uneven(B, W, torch, np, count, steps, seed0=0):
         del batch
     out["instances"] = count
     out["sizes"] = "nx~U{4..48}, nu~U{1..16}, N~U{10..100}, boxes on all u and x"
+    return out
+
+
+def leg_pcond(B, W, torch, np, qps, n2s, steps):
+    """The headline batch solved through partial condensing (Section 3.5) to
+    N2 stages: condensing, IPM on the condensed QPs and expansion, all inside
+    each timed solve.  A solve counts when the condensed solve reports success
+    with residual norms within the KKT tolerance."""
+    out = {}
+    for N2 in n2s:
+        batch = B.Batch(qps, B.default_arg(cond_N=N2)).load().sync()
+        batch.solve()
+        torch.cuda.synchronize()
+        st = batch.stream
+        ms = []
+        for _ in range(steps):
+            s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s_.record(st)
+            batch.solve()
+            e_.record(st)
+            torch.cuda.synchronize()
+            ms.append(s_.elapsed_time(e_))
+        batch.fetch().sync()
+        stats = [batch.stat(i) for i in range(len(qps))]
+        ok = sum(1 for x in stats if x.status == B.SUCCESS and max(x.res[:]) <= KKT_OK)
+        iters = np.array([x.iters for x in stats])
+        v, dims = batch.variant(0)
+        med = float(np.median(ms))
+        out[str(N2)] = {"value": round(ok / (med * 1e-3), 1), "unit": "solves/s", "ms_per_step": round(med, 3),
+                        "solves_ok": ok, "iters_p50": float(np.percentile(iters, 50)),
+                        "iters_p99": float(np.percentile(iters, 99)), "kernel_group": v,
+                        "stage_sizes_padded": list(dims)}
+        del batch
     return out
 
 
@@ -233,6 +268,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uneven", type=int, default=4096, help="instances of the uneven leg (0: skip)")
     ap.add_argument("--uneven-steps", type=int, default=3)
+    ap.add_argument("--pcond", default="5,10,15", help="condensed horizons for the partial-condensing leg ('': skip)")
+    ap.add_argument("--pcond-steps", type=int, default=5)
     ap.add_argument("--large", type=int, default=256, help="instances of the large-stage leg (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2)
     ap.add_argument("--serve-pool", type=int, default=256, help="distinct instances in the serving pool (0: skip)")
@@ -349,6 +386,10 @@ def main():
                   "vs_f64": round(m["value"] / f["value"], 3)},
     }
     del f["del_batch"], m["del_batch"]
+    if args.pcond:
+        n2s = [int(x) for x in args.pcond.split(",") if x]
+        log(f"bench: partial condensing leg, N2 in {n2s}")
+        line["pcond"] = leg_pcond(B, W, torch, np, qps, n2s, args.pcond_steps)
     log("bench: single-instance latency (4 masses, N = 10)")
     line["single"] = leg_single(B, W, torch, np, 20)
     if args.uneven > 0:

@@ -179,10 +179,11 @@ int oqp_batch_get_sol(const oqp_batch* batch, int i, double* u, double* x, doubl
                       double* t_l, double* t_u);
 
 /* ---- partial condensing (Section 3.5) ------------------------------------ */
-/* A batch whose arg has cond_N > 0 condenses each instance on the GPU (after
- * oqp_batch_load) into an OCP QP with N2 = min(cond_N, N) stages and solves
- * that; oqp_batch_solve ends with the expansion, so oqp_batch_get_sol and
- * oqp_batch_fill_sol return the solution of the original QP.  Blocks: the
+/* A batch whose arg has cond_N > 0 solves each instance through partial
+ * condensing: oqp_batch_solve first condenses it on the GPU into an OCP QP
+ * with N2 = min(cond_N, N) stages, solves that and ends with the expansion,
+ * so oqp_batch_get_sol and oqp_batch_fill_sol return the solution of the
+ * original QP.  Blocks: the
  * stages [s_b, s_{b+1}) with N = q N2 + r, the first r blocks one stage
  * longer; stage N is the condensed terminal stage.  Condensed stage b has
  * u = [u_{s_b}; ...; u_{s_{b+1}-1}] and x = x_{s_b}; its box list holds the
@@ -197,7 +198,7 @@ int oqp_batch_get_sol(const oqp_batch* batch, int i, double* u, double* x, doubl
  * oqp_pcond_dims_bytes, 8-byte aligned). */
 size_t oqp_pcond_dims_bytes(const oqp_dims* dims, int cond_N);
 int oqp_pcond_dims(const oqp_dims* dims, int cond_N, void* mem, size_t bytes, oqp_dims** out);
-/* Enqueue the device-to-host copy of the condensed QPs of a loaded batch;
+/* Enqueue the device-to-host copy of the condensed QPs (after a solve);
  * after oqp_batch_sync, oqp_batch_get_cond_qp fills a QP created on the dims
  * oqp_pcond_dims reports (OQP_EINVAL if they differ, OQP_ESTATE on a batch
  * without condensing or before the copy). */

@@ -1079,10 +1079,8 @@ extern "C" int oqp_batch_load(oqp_batch* b, const oqp_qp* const* qps)
                            : hipMemcpyAsync(b->ddata, b->hdata, sizeof(double) * b->n_data, hipMemcpyHostToDevice,
                                             (hipStream_t)b->stream);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_load: hipMemcpyAsync: %s", hipGetErrorString(e));
-    if (b->cond && oqp::cond_launch(0, b->dcdesc, b->ditems, b->n_items, b->dtab, b->dodata, b->ddata, nullptr,
-                                    nullptr, b->cond_lds, b->stream))
-        return fail(OQP_EDEVICE, "oqp_batch_load: condensing kernel launch failed");
     b->loaded = 1;
+    b->solved = 0;
     b->cond_fetched = 0;
     return OQP_OK;
 }
@@ -1134,6 +1132,10 @@ extern "C" int oqp_batch_solve(oqp_batch* b)
 {
     if (!b) return fail(OQP_EINVAL, "oqp_batch_solve: NULL batch");
     if (!b->loaded) return fail(OQP_ESTATE, "oqp_batch_solve: no data loaded");
+    // partial condensing: original records -> condensed records, every solve
+    if (b->cond && oqp::cond_launch(0, b->dcdesc, b->ditems, b->n_items, b->dtab, b->dodata, b->ddata, nullptr,
+                                    nullptr, b->cond_lds, b->stream))
+        return fail(OQP_EDEVICE, "oqp_batch_solve: condensing kernel launch failed");
     int rc = launch_all(b, make_params(b->arg, oqp::KMODE_SOLVE, 0.0));
     if (rc) return rc;
     if (b->cond && oqp::cond_launch(1, b->dcdesc, b->ditems, b->n_items, b->dtab, b->dodata, nullptr, b->diter,
@@ -1307,7 +1309,7 @@ extern "C" int oqp_batch_fetch_cond(oqp_batch* b)
 {
     if (!b) return fail(OQP_EINVAL, "oqp_batch_fetch_cond: NULL batch");
     if (!b->cond) return fail(OQP_ESTATE, "oqp_batch_fetch_cond: the batch does not condense");
-    if (!b->loaded) return fail(OQP_ESTATE, "oqp_batch_fetch_cond: no data loaded");
+    if (!b->solved) return fail(OQP_ESTATE, "oqp_batch_fetch_cond: no solve enqueued");
     hipError_t e = hipMemcpyAsync(b->hdata, b->ddata, sizeof(double) * b->n_data, hipMemcpyDeviceToHost,
                                   (hipStream_t)b->stream);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_fetch_cond: %s", hipGetErrorString(e));

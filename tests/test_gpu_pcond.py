@@ -65,7 +65,7 @@ def test_condensed_qp_matches_oracle():
     say(f"condensed QP vs oracle: {len(cases)} instances, one batch per horizon")
     for N2 in sorted({c[1] for c in cases}):
         qps = [q for q, n2 in cases if n2 == N2]
-        b = B.Batch(qps, B.default_arg(cond_N=N2)).load().fetch_cond().sync()
+        b = B.Batch(qps, B.default_arg(cond_N=N2)).load().solve().fetch_cond().sync()
         for i, qp in enumerate(qps):
             got = b.cond_qp(i)
             ref = PC.condense(qp, N2)
@@ -141,4 +141,5 @@ def test_condensing_batch_invariance_and_state_errors():
     assert L.oqp_batch_newton(b.h, 0.0) == B.ESTATE
     got = B.Qp(qps[0])  # any QP object: the state check comes first
     assert L.oqp_batch_get_cond_qp(b.h, 0, got.h) == B.ESTATE
+    assert L.oqp_batch_fetch_cond(b.h) == B.ESTATE  # nothing solved yet
     b.sync()
