@@ -62,9 +62,21 @@ def traffic_from_profile(variant_key, launches_per_step):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(qps, seconds, tol):
+def cpu_baseline(qps, seconds, tol, single_qp=None):
+    """The oracle, unmodified, on the host cores over the same instances; with
+    single_qp also its one-thread time on that instance (the single-instance
+    latency leg's CPU reference)."""
     import concurrent.futures as cf
     from oracle import oracle as O
+
+    single = None
+    if single_qp is not None:
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < 1.0:
+            o = O.solve(single_qp, O.Arg.with_tol(1e-8))
+            n += 1
+        single = {"oracle_1thread_us": round((time.perf_counter() - t0) / n * 1e6, 1), "oracle_iters": int(o.iters)}
 
     threads = max(1, min(16, os.cpu_count() or 1))
     arg = O.Arg.with_tol(tol)
@@ -81,9 +93,12 @@ def cpu_baseline(qps, seconds, tol):
     with cf.ThreadPoolExecutor(threads) as ex:
         total = sum(ex.map(work, range(threads)))
     el = time.perf_counter() - t0
-    return {"value": total / el, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"{total} instances of the same workload (round-robin over the batch), "
-                      f"{threads} threads, one instance per thread at a time, {el:.1f} s"}
+    out = {"value": total / el, "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"{total} instances of the same workload (round-robin over the batch), "
+                     f"{threads} threads, one instance per thread at a time, {el:.1f} s"}
+    if single is not None:
+        out["single_instance"] = single
+    return out
 
 
 def leg_uneven(B, W, torch, np, count, steps, seed0=0):
@@ -154,9 +169,8 @@ def leg_pcond(B, W, torch, np, qps, n2s, steps):
 
 def leg_single(B, W, torch, np, reps):
     """Latency of one 4-mass QP (nx = 8, nu = 3, N = 10, dt = 0.5; seed 1) in
-    a batch of one: one launch, FP64 to 1e-8, median over reps; the oracle on
-    one host thread beside it."""
-    from oracle import oracle as O
+    a batch of one: one launch, FP64 to 1e-8, median over reps (the CPU
+    baseline times the oracle on the same instance)."""
     qp = W.mass_spring_chain4(1)
     batch = B.Batch([qp], B.default_arg()).load().sync()
     batch.solve()
@@ -172,16 +186,8 @@ def leg_single(B, W, torch, np, reps):
         ms.append(s_.elapsed_time(e_))
     batch.fetch().sync()
     r = batch.result(0)
-    arg = O.Arg.with_tol(1e-8)
-    t0 = time.perf_counter()
-    n = 0
-    while time.perf_counter() - t0 < 1.0:
-        o = O.solve(qp, arg)
-        n += 1
-    cpu_us = (time.perf_counter() - t0) / n * 1e6
     return {"workload": "mass_spring_4masses_N10", "gpu_us_p50": round(float(np.median(ms)) * 1e3, 1),
-            "iters": int(r.iters), "status": int(r.status), "oracle_1thread_us": round(cpu_us, 1),
-            "oracle_iters": int(o.iters)}
+            "iters": int(r.iters), "status": int(r.status)}
 
 
 def leg_large(B, W, torch, np, perfmodel, count, steps):
@@ -308,8 +314,8 @@ def main():
     dbytes = np.array([perfmodel.data_bytes(q) for q in qps], dtype=np.float64)
     fpi = np.array([perfmodel.flops_per_iter(q) for q in qps], dtype=np.float64)
 
-    def time_path(mode, steps, warmup):
-        arg = B.default_arg(mode)
+    def time_path(mode, steps, warmup, **over):
+        arg = B.default_arg(mode, **over)
         batch = B.Batch(qps, arg)
         batch.load().sync()
         variant = batch.variant(0)[1]
@@ -348,6 +354,8 @@ def main():
     f = time_path(B.MODE_F64, args.steps, args.warmup)
     log(f"bench: mixed path, warmup {args.warmup}, {args.steps} steps")
     m = time_path(B.MODE_MIXED, args.steps, args.warmup)
+    log("bench: FP64 path with iter_max 20 (context: the batch time follows its slowest instance)")
+    f20 = time_path(B.MODE_F64, max(3, args.steps // 2), 1, iter_max=20)
     vkey = "ipm_kernel<%d,%d,%d>" % f["variant"]
     traffic = traffic_from_profile(vkey, 1)
     okmask = f["status"] == B.SUCCESS
@@ -385,7 +393,10 @@ def main():
                   "max_kkt_res": float(np.max(m["kkt"][m["status"] == B.SUCCESS])),
                   "vs_f64": round(m["value"] / f["value"], 3)},
     }
-    del f["del_batch"], m["del_batch"]
+    line["iter_max_20"] = {"value": round(f20["value"], 1), "unit": "solves/s",
+                           "ms_per_step": round(1e3 * f20["wall"] / f20["steps"], 4), "solves_ok": f20["ok"],
+                           "iters_max": int(np.max(f20["iters"]))}
+    del f["del_batch"], m["del_batch"], f20["del_batch"]
     if args.pcond:
         n2s = [int(x) for x in args.pcond.split(",") if x]
         log(f"bench: partial condensing leg, N2 in {n2s}")
@@ -403,7 +414,7 @@ def main():
                                   args.serve_frac, args.serve_seconds, args.serve_per_request_seconds, log)
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
-        line["cpu_baseline"] = cpu_baseline(qps, args.cpu_seconds, 1e-8)
+        line["cpu_baseline"] = cpu_baseline(qps, args.cpu_seconds, 1e-8, W.mass_spring_chain4(1))
     print(json.dumps(line), flush=True)
 
 
