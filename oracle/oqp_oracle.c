@@ -51,6 +51,7 @@ typedef struct {
     double tol_stat, tol_eq, tol_ineq, tol_comp;
     int iter_max;
     double alpha_min, gamma, lam_min, t_min, reg_prim, corr_ratio;
+    int warm_start; /* 0 cold; 1 primal guess (u, x); 2 primal and dual guess (Section 4.2) */
 } orc_arg;
 
 /* An iterate, a step or a residual in the user layout: u (sum nu), x (sum nx),
@@ -704,16 +705,36 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
     double *rml = (double *)xcalloc((size_t)nc, sizeof(double));
     double *rmu = (double *)xcalloc((size_t)nc, sizeof(double));
 
-    /* cold start: y = 0, pi = 0, t = max(C y - d, 1), lam = 1 */
-    for (int n = 0; n <= p.N; ++n) {
-        const stage_t *s = &p.st[n];
-        for (int k = 0; k < s->nc; ++k) {
-            int c = p.coff[n] + k;
-            double tl0 = -s->lo[k], tu0 = s->hi[k];
-            v.tl[c] = tl0 > 1.0 ? tl0 : 1.0;
-            v.tu[c] = tu0 > 1.0 ? tu0 : 1.0;
-            v.ll[c] = 1.0;
-            v.lu[c] = 1.0;
+    /* Initial point.  Cold start: y = 0, pi = 0, t = max(C y - d, 1), lam = 1.
+     * Warm start (Section 4.2) from the iterate passed in `sol`: with a primal
+     * guess, y is the guess and the rest is set as in the cold start at that
+     * y; with a primal and dual guess, every block is the guess, multipliers
+     * and slacks clamped below as in the iterate update. */
+    if (arg->warm_start != 0) ivec_from_user(&p, sol, &v);
+    if (arg->warm_start == 2) {
+        for (int i = 0; i < nc; ++i) {
+            if (v.ll[i] < arg->lam_min) v.ll[i] = arg->lam_min;
+            if (v.lu[i] < arg->lam_min) v.lu[i] = arg->lam_min;
+            if (v.tl[i] < arg->t_min) v.tl[i] = arg->t_min;
+            if (v.tu[i] < arg->t_min) v.tu[i] = arg->t_min;
+        }
+    } else {
+        if (arg->warm_start == 0)
+            for (int i = 0; i < p.nv; ++i) v.y[i] = 0.0;
+        for (int i = 0; i < p.neq; ++i) v.pi[i] = 0.0;
+        for (int n = 0; n <= p.N; ++n) {
+            const stage_t *s = &p.st[n];
+            const double *z = v.y + p.zoff[n];
+            for (int k = 0; k < s->nc; ++k) {
+                int c = p.coff[n] + k;
+                double gz = 0.0;
+                for (int j = 0; j < s->nz; ++j) gz += s->G[IX(k, j, s->nc)] * z[j];
+                double tl0 = gz - s->lo[k], tu0 = s->hi[k] - gz;
+                v.tl[c] = tl0 > 1.0 ? tl0 : 1.0;
+                v.tu[c] = tu0 > 1.0 ? tu0 : 1.0;
+                v.ll[c] = 1.0;
+                v.lu[c] = 1.0;
+            }
         }
     }
 

@@ -51,7 +51,7 @@ class _Arg(ct.Structure):
     _fields_ = [("tol_stat", ct.c_double), ("tol_eq", ct.c_double), ("tol_ineq", ct.c_double),
                 ("tol_comp", ct.c_double), ("iter_max", ct.c_int), ("alpha_min", ct.c_double),
                 ("gamma", ct.c_double), ("lam_min", ct.c_double), ("t_min", ct.c_double),
-                ("reg_prim", ct.c_double), ("corr_ratio", ct.c_double)]
+                ("reg_prim", ct.c_double), ("corr_ratio", ct.c_double), ("warm_start", ct.c_int)]
 
 
 class _Vec(ct.Structure):
@@ -95,10 +95,12 @@ class Arg:
     t_min: float = 1e-16
     reg_prim: float = 0.0
     corr_ratio: float = 10.0
+    warm_start: int = 0  # 0 cold; 1 primal guess; 2 primal and dual guess (Section 4.2)
 
     def _c(self):
         return _Arg(self.tol_stat, self.tol_eq, self.tol_ineq, self.tol_comp, int(self.iter_max),
-                    self.alpha_min, self.gamma, self.lam_min, self.t_min, self.reg_prim, self.corr_ratio)
+                    self.alpha_min, self.gamma, self.lam_min, self.t_min, self.reg_prim, self.corr_ratio,
+                    int(self.warm_start))
 
     @staticmethod
     def with_tol(tol: float, **kw) -> "Arg":
@@ -187,12 +189,15 @@ class Result:
     sol: dict         # u, x, pi, lam_l, lam_u, t_l, t_u
 
 
-def solve(qp, arg: Arg | None = None) -> Result:
-    """Run the oracle IPM on one problem."""
+def solve(qp, arg: Arg | None = None, guess: dict | None = None) -> Result:
+    """Run the oracle IPM on one problem; with arg.warm_start != 0 it starts
+    from `guess` (user layout: u, x and, for warm_start = 2, pi, lam, t)."""
     lib = _load()
     arg = arg or Arg()
     pk = _Packed(qp)
     sol = Vec.like(pk)
+    if guess is not None:
+        sol.set(**{k: guess[k] for k in Vec.names if k in guess})
     it = ct.c_int(0)
     res = np.zeros(4)
     mu = ct.c_double(0.0)
