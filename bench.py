@@ -10,6 +10,8 @@ to the KKT tolerance), FP64 path; the mixed path is timed beside it.
 Further legs on the same line (context, not the headline):
   * pcond: the same batch solved through partial condensing to a shorter
     horizon (condensing and expansion inside the timed solve);
+  * warm: the next receding-horizon problem of every solved instance, cold
+    and warm-started from the shifted solution;
   * uneven: a batch of random stable OCP QPs with nx ~ U{4..48},
     nu ~ U{1..16}, N ~ U{10..100} (one-wave variants plus the block kernel);
   * serve: the continuous-batching server replaying Poisson arrivals over a
@@ -167,6 +169,46 @@ def leg_pcond(B, W, torch, np, qps, n2s, steps):
     return out
 
 
+def leg_warm(B, W, torch, np, qps, steps):
+    """Receding horizon on the headline batch: after a cold solve, the next
+    problem of every solved instance (x_0 <- x_1) is solved cold and
+    warm-started (primal-dual guess, Section 4.2) from the shifted solution.
+    The guess upload is inside the timed solve; building it on the host is
+    not."""
+    first = B.Batch(qps, B.default_arg()).load().solve().fetch().sync()
+    res = first.results()
+    del first
+    keep = [i for i, r in enumerate(res) if r.status == B.SUCCESS]
+    pairs = [W.receding_step(qps[i], res[i].sol) for i in keep]
+    nxt, guesses = [p[0] for p in pairs], [p[1] for p in pairs]
+    out = {"instances": len(nxt)}
+    for name, warm in (("cold", 0), ("warm", 2)):
+        b = B.Batch(nxt, B.default_arg(warm_start=warm)).load().sync()
+        ms = []
+        for step in range(steps + 1):
+            if warm:
+                for i, g in enumerate(guesses):
+                    b.set_iterate(i, g)
+            torch.cuda.synchronize()
+            s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s_.record(b.stream)
+            b.solve()
+            e_.record(b.stream)
+            torch.cuda.synchronize()
+            if step > 0:
+                ms.append(s_.elapsed_time(e_))
+        b.fetch().sync()
+        stats = [b.stat(i) for i in range(len(nxt))]
+        ok = sum(1 for x in stats if x.status == B.SUCCESS and max(x.res[:]) <= KKT_OK)
+        iters = np.array([x.iters for x in stats])
+        med = float(np.median(ms))
+        out[name] = {"value": round(ok / (med * 1e-3), 1), "unit": "solves/s", "ms_per_step": round(med, 3),
+                     "solves_ok": ok, "iters_p50": float(np.percentile(iters, 50)), "iters_max": int(iters.max()),
+                     "iters_mean": round(float(iters.mean()), 2)}
+        del b
+    return out
+
+
 def leg_single(B, W, torch, np, reps):
     """Latency of one 4-mass QP (nx = 8, nu = 3, N = 10, dt = 0.5; seed 1) in
     a batch of one: one launch, FP64 to 1e-8, median over reps (the CPU
@@ -276,6 +318,7 @@ def main():
     ap.add_argument("--uneven-steps", type=int, default=3)
     ap.add_argument("--pcond", default="5,10,15", help="condensed horizons for the partial-condensing leg ('': skip)")
     ap.add_argument("--pcond-steps", type=int, default=5)
+    ap.add_argument("--warm-steps", type=int, default=5, help="timed solves of the warm-start leg (0: skip)")
     ap.add_argument("--large", type=int, default=256, help="instances of the large-stage leg (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2)
     ap.add_argument("--serve-pool", type=int, default=256, help="distinct instances in the serving pool (0: skip)")
@@ -401,6 +444,9 @@ def main():
         n2s = [int(x) for x in args.pcond.split(",") if x]
         log(f"bench: partial condensing leg, N2 in {n2s}")
         line["pcond"] = leg_pcond(B, W, torch, np, qps, n2s, args.pcond_steps)
+    if args.warm_steps > 0:
+        log("bench: receding-horizon warm-start leg")
+        line["warm"] = leg_warm(B, W, torch, np, qps, args.warm_steps)
     log("bench: single-instance latency (4 masses, N = 10)")
     line["single"] = leg_single(B, W, torch, np, 20)
     if args.uneven > 0:

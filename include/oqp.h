@@ -82,7 +82,8 @@ typedef struct {
     double corr_ratio; /* corrector rejected if mu after it > corr_ratio * mu_aff */
     int ir_max;        /* max iterative-refinement steps per Newton solve */
     double ir_tol;     /* refinement stops at ||r_ir||_inf <= ir_tol * max(1, ||r||_inf) */
-    int warm_start;    /* reserved; must be 0 (cold start) */
+    int warm_start;    /* batch only (Section 4.2): 0 cold start; 1 primal guess, 2 primal and dual
+                          guess, read from the batch's iterate records (see oqp_batch_solve) */
     int cond_N;        /* batch only: solve after partial condensing to this horizon
                           (Section 3.5; min(cond_N, N) stages per instance); 0 = off */
 } oqp_arg;
@@ -160,7 +161,14 @@ int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_arg* arg, v
 int oqp_batch_load(oqp_batch* batch, const oqp_qp* const* qps);
 /* Enqueue the IPM for every instance (one launch per kernel group present;
  * the block kernel solves its instances of all sizes in one launch, largest
- * first). */
+ * first).  Initial point: cold start (y = 0, pi = 0, t = max(C y - d, 1),
+ * lam = 1), or with arg.warm_start the iterate records: the last solve's
+ * solution, or, if oqp_batch_set_iterate was called since, the host copy of
+ * every instance's iterate (uploaded first; instances not set start from what
+ * that copy holds, the last fetched solution).  warm_start = 1 keeps u, x and
+ * sets the rest as in the cold start at that point; 2 keeps all blocks,
+ * clamping multipliers and slacks below at lam_min and t_min.  The mixed
+ * path's FP64 fallback always starts cold.  Not combinable with cond_N. */
 int oqp_batch_solve(oqp_batch* batch);
 /* Replace the arguments used by later solves (mode must not change). */
 int oqp_batch_set_arg(oqp_batch* batch, const oqp_arg* arg);
@@ -239,7 +247,9 @@ int oqp_sol_get_stat(const oqp_sol* sol, oqp_stat* stat);
 int oqp_res_get_norms(const oqp_sol* sol, double out[4]);
 
 /* ---- single Newton step (eq:alg:pdipm:delta) ------------------------------ */
-/* Set the iterate of instance i (user layout as above; lam and t > 0). */
+/* Set the iterate of instance i on the host (user layout as above; lam and
+ * t > 0): the point of oqp_batch_newton, or the guess of a warm-started
+ * oqp_batch_solve. */
 int oqp_batch_set_iterate(oqp_batch* batch, int i, const double* u, const double* x, const double* pi,
                           const double* lam_l, const double* lam_u, const double* t_l, const double* t_u);
 /* Upload the iterates set so far and enqueue one Newton step per instance with

@@ -389,8 +389,8 @@ int check_arg(const oqp_arg* a)
 {
     if (!a) return fail(OQP_EINVAL, "NULL oqp_arg");
     if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED) return fail(OQP_EINVAL, "unknown mode %d", a->mode);
-    if (a->iter_max < 0 || !(a->gamma > 0.0 && a->gamma <= 1.0) || a->warm_start != 0 || a->ir_max < 0 ||
-        a->cond_N < 0)
+    if (a->iter_max < 0 || !(a->gamma > 0.0 && a->gamma <= 1.0) || a->warm_start < 0 || a->warm_start > 2 ||
+        a->ir_max < 0 || a->cond_N < 0 || (a->warm_start != 0 && a->cond_N != 0))
         return fail(OQP_EINVAL, "bad oqp_arg field (iter_max, gamma, warm_start or cond_N)");
     return OQP_OK;
 }
@@ -426,6 +426,8 @@ struct oqp_batch {
     int loaded;
     int solved;
     int has_step;
+    int iter_dirty;  // host iterate records changed since the last upload
+    int iter_valid;  // the device iterate records hold an iterate (a solve ran, or one was set)
     // host side
     Inst* inst;
     int* dims_pool;
@@ -1103,6 +1105,7 @@ oqp::KParams make_params(const oqp_arg& a, int mode, double tau)
     P.iter_max = a.iter_max;
     P.ir_max = a.ir_max;
     P.mode = mode;
+    P.warm = mode == oqp::KMODE_SOLVE ? a.warm_start : 0;
     return P;
 }
 
@@ -1115,7 +1118,9 @@ static int launch_all(oqp_batch* b, const oqp::KParams& P)
         if (pass == 1) {
             if (!(mixed && P.mode == oqp::KMODE_SOLVE)) break;
             // FP64 kernels pick up the instances the mixed kernels handed over
+            // (from a cold start)
             Pp.mode = oqp::KMODE_FALLBACK;
+            Pp.warm = 0;
         }
         for (int k = 0; k < b->nvar; ++k) {
             const int v = b->nvar - 1 - k;
@@ -1132,6 +1137,15 @@ extern "C" int oqp_batch_solve(oqp_batch* b)
 {
     if (!b) return fail(OQP_EINVAL, "oqp_batch_solve: NULL batch");
     if (!b->loaded) return fail(OQP_ESTATE, "oqp_batch_solve: no data loaded");
+    // warm start from iterates set on the host
+    if (b->arg.warm_start != 0 && !b->iter_valid && !b->iter_dirty)
+        return fail(OQP_ESTATE, "oqp_batch_solve: warm start without an iterate (solve once or set one)");
+    if (b->arg.warm_start != 0 && b->iter_dirty) {
+        hipError_t e = hipMemcpyAsync(b->diter, b->hiter, sizeof(double) * b->n_iter, hipMemcpyHostToDevice,
+                                      (hipStream_t)b->stream);
+        if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_solve: %s", hipGetErrorString(e));
+        b->iter_dirty = 0;
+    }
     // partial condensing: original records -> condensed records, every solve
     if (b->cond && oqp::cond_launch(0, b->dcdesc, b->ditems, b->n_items, b->dtab, b->dodata, b->ddata, nullptr,
                                     nullptr, b->cond_lds, b->stream))
@@ -1142,6 +1156,7 @@ extern "C" int oqp_batch_solve(oqp_batch* b)
                                     b->doiter, 0, b->stream))
         return fail(OQP_EDEVICE, "oqp_batch_solve: expansion kernel launch failed");
     b->solved = 1;
+    b->iter_valid = 1;
     return OQP_OK;
 }
 
@@ -1279,6 +1294,7 @@ extern "C" int oqp_batch_set_iterate(oqp_batch* b, int i, const double* u, const
     std::memset(b->hiter + in.iter, 0, sizeof(double) * (size_t)(in.N + 1) * L.IREC);
     user_copy(b, i, b->hiter, false, (double*)u, (double*)x, (double*)pi, (double*)lam_l, (double*)lam_u,
               (double*)t_l, (double*)t_u);
+    b->iter_dirty = 1;
     return OQP_OK;
 }
 
@@ -1290,6 +1306,8 @@ extern "C" int oqp_batch_newton(oqp_batch* b, double tau)
     hipError_t e = hipMemcpyAsync(b->diter, b->hiter, sizeof(double) * b->n_iter, hipMemcpyHostToDevice,
                                   (hipStream_t)b->stream);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_newton: %s", hipGetErrorString(e));
+    b->iter_dirty = 0;
+    b->iter_valid = 1;
     int rc = launch_all(b, make_params(b->arg, oqp::KMODE_NEWTON, tau));
     if (rc) return rc;
     b->has_step = 1;

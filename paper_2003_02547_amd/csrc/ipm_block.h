@@ -1353,20 +1353,42 @@ struct Blk {
     }
 
     // cold start: y = 0, pi = 0, t = max(C y - d, 1), lam = 1 (masked slots 0)
+    // Initial point (P.warm), as in the one-wave kernel: cold start, primal
+    // guess (y kept, the rest as in the cold start at that y), or primal and
+    // dual guess (kept, multipliers and slacks clamped below).
     __device__ __forceinline__ void init() const
     {
-        for (int e = tid; e < (N + 1) * NZ; e += BT) Ip(e / NZ)[Lo.I_z + e % NZ] = 0.0;
-        for (int e = tid; e < (N + 1) * NX; e += BT) Ip(e / NX)[Lo.I_pi + e % NX] = 0.0;
+        const int warm = P.warm;
+        if (warm == 0)
+            for (int e = tid; e < (N + 1) * NZ; e += BT) Ip(e / NZ)[Lo.I_z + e % NZ] = 0.0;
+        if (warm != 2)
+            for (int e = tid; e < (N + 1) * NX; e += BT) Ip(e / NX)[Lo.I_pi + e % NX] = 0.0;
         for (int e = tid; e < (N + 1) * NC; e += BT) {
             const int n = e / NC, c = e % NC;
             double m, lo, hi;
-            slot_bounds(Dp(n), c, m, lo, hi);
+            const double* d = Dp(n);
+            slot_bounds(d, c, m, lo, hi);
             const bool on = m != 0.0;
             double* ir = Ip(n);
+            if (warm == 2) {
+                ir[Lo.I_ll + c] = on ? fmax(ir[Lo.I_ll + c], P.lam_min) : 0.0;
+                ir[Lo.I_lu + c] = on ? fmax(ir[Lo.I_lu + c], P.lam_min) : 0.0;
+                ir[Lo.I_tl + c] = on ? fmax(ir[Lo.I_tl + c], P.t_min) : 0.0;
+                ir[Lo.I_tu + c] = on ? fmax(ir[Lo.I_tu + c], P.t_min) : 0.0;
+                continue;
+            }
+            double gz = 0.0;
+            if (warm == 1) {
+                if (c < NZ) {
+                    gz = ir[Lo.I_z + c];
+                } else {
+                    for (int j = 0; j < NZ; ++j) gz += d[Lo.D_G + (c - NZ) + j * NG] * ir[Lo.I_z + j];
+                }
+            }
             ir[Lo.I_ll + c] = on ? 1.0 : 0.0;
             ir[Lo.I_lu + c] = on ? 1.0 : 0.0;
-            ir[Lo.I_tl + c] = on ? fmax(-lo, 1.0) : 0.0;
-            ir[Lo.I_tu + c] = on ? fmax(hi, 1.0) : 0.0;
+            ir[Lo.I_tl + c] = on ? (warm == 1 ? fmax(gz - lo, 1.0) : fmax(-lo, 1.0)) : 0.0;
+            ir[Lo.I_tu + c] = on ? (warm == 1 ? fmax(hi - gz, 1.0) : fmax(hi, 1.0)) : 0.0;
         }
         __threadfence_block();
         __syncthreads();

@@ -1263,13 +1263,19 @@ struct Ipm {
     }
 
     // cold start: y = 0, pi = 0, t = max(C y - d, 1), lam = 1 (masked slots 0)
+    // Initial point (P.warm): cold start y = 0, pi = 0, t = max(C y - d, 1),
+    // lam = 1; with a primal guess in the iterate records (warm start of
+    // Section 4.2) y is kept and the rest set as in the cold start at that y;
+    // with a primal and dual guess everything is kept, multipliers and
+    // slacks clamped below as in the iterate update.
     __device__ __forceinline__ void init() const
     {
+        const int warm = P.warm;
         for (int n = 0; n <= N; ++n) {
             const double* d = Dp(n);
             double* ir = Ip(n);
-            if (lane < NZ) ir[Lo.I_z + lane] = 0.0;
-            if (lane < NX) ir[Lo.I_pi + lane] = 0.0;
+            if (warm == 0 && lane < NZ) ir[Lo.I_z + lane] = 0.0;
+            if (warm != 2 && lane < NX) ir[Lo.I_pi + lane] = 0.0;
 #pragma unroll
             for (int t = 0; t < NCT; ++t) {
                 const int c = slot(t);
@@ -1277,10 +1283,25 @@ struct Ipm {
                 double m, lo, hi;
                 slot_bounds(d, c, m, lo, hi);
                 const bool on = m != 0.0;
+                if (warm == 2) {
+                    ir[Lo.I_ll + c] = on ? fmax(ir[Lo.I_ll + c], P.lam_min) : 0.0;
+                    ir[Lo.I_lu + c] = on ? fmax(ir[Lo.I_lu + c], P.lam_min) : 0.0;
+                    ir[Lo.I_tl + c] = on ? fmax(ir[Lo.I_tl + c], P.t_min) : 0.0;
+                    ir[Lo.I_tu + c] = on ? fmax(ir[Lo.I_tu + c], P.t_min) : 0.0;
+                    continue;
+                }
+                double gz = 0.0;
+                if (warm == 1) {
+                    if (c < NZ) {
+                        gz = ir[Lo.I_z + c];
+                    } else {
+                        for (int j = 0; j < NZ; ++j) gz += d[Lo.D_G + (c - NZ) + j * NG] * ir[Lo.I_z + j];
+                    }
+                }
                 ir[Lo.I_ll + c] = on ? 1.0 : 0.0;
                 ir[Lo.I_lu + c] = on ? 1.0 : 0.0;
-                ir[Lo.I_tl + c] = on ? fmax(-lo, 1.0) : 0.0;
-                ir[Lo.I_tu + c] = on ? fmax(hi, 1.0) : 0.0;
+                ir[Lo.I_tl + c] = on ? (warm == 1 ? fmax(gz - lo, 1.0) : fmax(-lo, 1.0)) : 0.0;
+                ir[Lo.I_tu + c] = on ? (warm == 1 ? fmax(hi - gz, 1.0) : fmax(hi, 1.0)) : 0.0;
             }
         }
         __syncthreads();

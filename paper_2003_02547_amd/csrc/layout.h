@@ -159,7 +159,7 @@ struct KParams {
     int32_t iter_max;
     int32_t ir_max;
     int32_t mode;       // KMODE_SOLVE or KMODE_NEWTON
-    int32_t pad;
+    int32_t warm;       // initial point of a solve: 0 cold, 1 primal guess, 2 primal and dual guess
 };
 
 enum { KMODE_SOLVE = 0, KMODE_NEWTON = 1, KMODE_FALLBACK = 2 };

@@ -288,6 +288,26 @@ def serving_stream(rate: float, duration: float, pool: int, seed: int = 4):
     return np.asarray(times), idx
 
 
+def receding_step(qp: OcpQp, sol: dict):
+    """The next problem of a receding-horizon loop on a chain QP (same stage
+    sizes at stages 0..N-1, x_0 fixed by an equal-limit box) and its guess:
+    x_0 <- x_1 of `sol`; the guess takes stage n + 1 of `sol` at stage n (the
+    last stage repeated), multipliers and slacks pushed to at least 1.
+    Data handling only."""
+    N, nx, nu = qp.N, qp.nx[1], qp.nu[0]
+    nxt = qp.copy()
+    x1 = np.asarray(sol["x"][nx:2 * nx], dtype=np.float64)
+    nxt.lbx[0], nxt.ubx[0] = x1.copy(), x1.copy()
+    u = np.asarray(sol["u"]).reshape(N, nu)
+    x = np.asarray(sol["x"]).reshape(N + 1, nx)
+    pi = np.asarray(sol["pi"]).reshape(N, nx)
+    guess = {"u": np.concatenate([u[1:], u[-1:]]).ravel(), "x": np.concatenate([x[1:], x[-1:]]).ravel(),
+             "pi": np.concatenate([pi[1:], pi[-1:]]).ravel()}
+    for k in ("lam_l", "lam_u", "t_l", "t_u"):
+        guess[k] = np.maximum(np.asarray(sol[k], dtype=np.float64), 1.0)
+    return nxt, guess
+
+
 def random_tiny(rng: np.random.Generator, N: int, nx_range=(1, 4), nu_range=(0, 3),
                 nb_frac: float = 0.5, ng_max: int = 1, x0_mode: str = "box",
                 time_varying: bool = True) -> OcpQp:

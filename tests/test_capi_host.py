@@ -100,8 +100,12 @@ def test_batch_size_and_plan_errors():
     # bad arguments
     bad = B.default_arg(gamma=1.5)
     assert L.oqp_batch_bytes(arr, 3, ct.byref(bad), ct.byref(hb), ct.byref(db)) == B.EINVAL
-    bad = B.default_arg(warm_start=1)
+    bad = B.default_arg(warm_start=3)
     assert L.oqp_batch_bytes(arr, 3, ct.byref(bad), ct.byref(hb), ct.byref(db)) == B.EINVAL
+    bad = B.default_arg(warm_start=2, cond_N=2)  # warm start does not combine with condensing
+    assert L.oqp_batch_bytes(arr, 3, ct.byref(bad), ct.byref(hb), ct.byref(db)) == B.EINVAL
+    ok = B.default_arg(warm_start=2)
+    assert L.oqp_batch_bytes(arr, 3, ct.byref(ok), ct.byref(hb), ct.byref(db)) == B.OK
     assert L.oqp_batch_bytes(arr, 0, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.EINVAL
 
 

@@ -98,33 +98,16 @@ def test_warm_started_solve_reaches_brute_force_minimiser(seed):
         assert O.kkt_res(qp, r.sol) <= 1e-10
 
 
-def shifted_guess(qp, sol):
-    """Receding-horizon guess for the chain problems: stage n takes stage
-    n + 1 of the previous solution (the last stage repeated); multipliers and
-    slacks pushed to at least 1."""
-    N, nx, nu = qp.N, qp.nx[1], qp.nu[0]
-    u = sol["u"].reshape(N, nu)
-    x = sol["x"].reshape(N + 1, nx)
-    pi = sol["pi"].reshape(N, nx)
-    g = {"u": np.concatenate([u[1:], u[-1:]]).ravel(), "x": np.concatenate([x[1:], x[-1:]]).ravel(),
-         "pi": np.concatenate([pi[1:], pi[-1:]]).ravel()}
-    for k in ("lam_l", "lam_u", "t_l", "t_u"):
-        g[k] = np.maximum(sol[k], 1.0)
-    return g
-
-
 def test_receding_horizon_warm_start_reaches_cold_minimiser():
     for i in range(4):
         qp = W.mass_spring_chain8(i)
         first = O.solve(qp, O.Arg.with_tol(1e-8))
         if first.status != O.SUCCESS:
             continue
-        nxt = qp.copy()
-        x1 = first.sol["x"][16:32]
-        nxt.lbx[0], nxt.ubx[0] = x1.copy(), x1.copy()
+        nxt, guess = W.receding_step(qp, first.sol)
         # tight tolerance: at KKT 1e-8 two points may differ by ~1e-5 (reading of the exit test)
         cold = O.solve(nxt, O.Arg.with_tol(1e-10))
-        warm = O.solve(nxt, O.Arg.with_tol(1e-10, warm_start=2), guess=shifted_guess(qp, first.sol))
+        warm = O.solve(nxt, O.Arg.with_tol(1e-10, warm_start=2), guess=guess)
         assert cold.status == O.SUCCESS and warm.status == O.SUCCESS
         assert O.kkt_res(nxt, warm.sol) <= 1e-10
         for k in ("u", "x"):
