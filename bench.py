@@ -104,12 +104,13 @@ def cpu_baseline(qps, seconds, tol, single_qp=None):
 
 
 def leg_uneven(B, W, torch, np, count, steps, seed0=0):
-    """Uneven batch: every instance solved in one batch solve (one launch per
-    kernel group on the batch stream)."""
+    """Uneven batch: every instance solved in one batch solve, one launch per
+    kernel group, the groups spread over the batch stream and 3 extra
+    streams (and, for comparison, all on the batch stream)."""
     qps = [W.random_uneven(seed0 + i) for i in range(count)]
     out = {}
-    for name, mode in (("f64", B.MODE_F64), ("mixed", B.MODE_MIXED)):
-        batch = B.Batch(qps, B.default_arg(mode)).load().sync()
+    for name, mode, streams in (("f64", B.MODE_F64, 3), ("mixed", B.MODE_MIXED, 3), ("f64_one_stream", B.MODE_F64, 0)):
+        batch = B.Batch(qps, B.default_arg(mode), streams=streams).load().sync()
         batch.solve()
         torch.cuda.synchronize()
         st = batch.stream
@@ -129,7 +130,7 @@ def leg_uneven(B, W, torch, np, count, steps, seed0=0):
         out[name] = {"value": round(ok / (float(np.median(ms)) * 1e-3), 1), "unit": "solves/s",
                      "ms_per_step": round(float(np.median(ms)), 3), "solves_ok": ok,
                      "block_kernel_instances": sum(1 for i in range(count) if batch.variant(i)[0] >= nv),
-                     "kernel_groups": len(groups)}
+                     "kernel_groups": len(groups), "extra_streams": streams}
         del batch
     out["instances"] = count
     out["sizes"] = "nx~U{4..48}, nu~U{1..16}, N~U{10..100}, boxes on all u and x"

@@ -170,6 +170,16 @@ int oqp_batch_load(oqp_batch* batch, const oqp_qp* const* qps);
  * clamping multipliers and slacks below at lam_min and t_min.  The mixed
  * path's FP64 fallback always starts cold.  Not combinable with cond_N. */
 int oqp_batch_solve(oqp_batch* batch);
+/* Extra streams (default priority, caller-owned, at most OQP_BATCH_MAX_AUX)
+ * for running kernel groups concurrently: a solve then forks from the batch
+ * stream to them and joins back, so its completion is still ordered on the
+ * batch stream.  The first group launched stays on the batch stream.  Creates
+ * one HIP event per stream plus one; n = 0 returns to a single stream.
+ * oqp_batch_release waits for the batch stream and destroys those events (call
+ * it before freeing the batch memory when streams were set). */
+#define OQP_BATCH_MAX_AUX 8
+int oqp_batch_set_streams(oqp_batch* batch, void* const* streams, int n);
+int oqp_batch_release(oqp_batch* batch);
 /* Replace the arguments used by later solves (mode must not change). */
 int oqp_batch_set_arg(oqp_batch* batch, const oqp_arg* arg);
 /* Enqueue the device-to-host copy of solutions and statistics. */

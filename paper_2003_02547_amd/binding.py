@@ -89,6 +89,8 @@ def lib():
         "oqp_pcond_dims_bytes": (ct.c_size_t, [_V, ct.c_int]),
         "oqp_pcond_dims": (ct.c_int, [_V, ct.c_int, _V, ct.c_size_t, ct.POINTER(_V)]),
         "oqp_batch_fetch_cond": (ct.c_int, [_V]),
+        "oqp_batch_set_streams": (ct.c_int, [_V, ct.POINTER(_V), ct.c_int]),
+        "oqp_batch_release": (ct.c_int, [_V]),
         "oqp_batch_get_cond_qp": (ct.c_int, [_V, ct.c_int, _V]),
         "oqp_arg_default": (None, [ct.POINTER(Arg), ct.c_int]),
         "oqp_batch_bytes": (ct.c_int, [ct.POINTER(_V), ct.c_int, ct.POINTER(Arg), ct.POINTER(ct.c_size_t),
@@ -274,7 +276,7 @@ def _sizes(qp):
 class Batch:
     """A batch of OCP QPs solved on the current CUDA (HIP) device and stream."""
 
-    def __init__(self, qps: Sequence, arg: Arg | None = None, device=None, stream=None):
+    def __init__(self, qps: Sequence, arg: Arg | None = None, device=None, stream=None, streams: int = 0):
         import torch
         L = lib()
         self.qps = list(qps)
@@ -296,6 +298,19 @@ class Batch:
                                 self.dev_ptr, self.dev_bytes, self.stream.cuda_stream, ct.byref(h)))
         self.h = h
         self._qph = None
+        self.aux = []
+        if streams > 0:
+            # extra streams (default priority) for concurrent kernel groups
+            self.aux = [torch.cuda.Stream(device=dev) for _ in range(int(streams))]
+            arr = (_V * len(self.aux))(*[s.cuda_stream for s in self.aux])
+            _check(L.oqp_batch_set_streams(self.h, arr, len(self.aux)))
+
+    def __del__(self):
+        try:
+            if getattr(self, "aux", None) and self.h:
+                lib().oqp_batch_release(self.h)
+        except Exception:
+            pass
 
     def load(self):
         L = lib()
@@ -612,4 +627,5 @@ EXPORTED = [
     "oqp_batch_fill_sol", "oqp_server_fill_sol", "oqp_sol_get_stat", "oqp_res_get_norms",
     "oqp_qp_get_dyn", "oqp_qp_get_cost", "oqp_qp_get_box_u", "oqp_qp_get_box_x", "oqp_qp_get_general",
     "oqp_pcond_dims_bytes", "oqp_pcond_dims", "oqp_batch_fetch_cond", "oqp_batch_get_cond_qp",
+    "oqp_batch_set_streams", "oqp_batch_release",
 ] + ["oqp_sol_get_" + g for g in SOL_FIELDS]

@@ -427,6 +427,11 @@ struct oqp_batch {
     int solved;
     int has_step;
     int iter_dirty;  // host iterate records changed since the last upload
+    // extra caller streams for concurrent kernel groups, with fork/join events
+    int naux;
+    void* aux[OQP_BATCH_MAX_AUX];
+    void* ev_fork;
+    void* ev_join[OQP_BATCH_MAX_AUX];
     int iter_valid;  // the device iterate records hold an iterate (a solve ran, or one was set)
     // host side
     Inst* inst;
@@ -1109,9 +1114,27 @@ oqp::KParams make_params(const oqp_arg& a, int mode, double tau)
     return P;
 }
 
+// Stream of kernel group v: the first non-empty group (in launch order) on
+// the batch stream, the others round-robin over the extra streams.
+static void* group_stream(const oqp_batch* b, int v)
+{
+    if (b->naux == 0) return b->stream;
+    int k = 0;
+    for (int u = b->nvar - 1; u > v; --u)
+        if (b->vcount[u] > 0) ++k;
+    return k == 0 ? b->stream : b->aux[(k - 1) % b->naux];
+}
+
 static int launch_all(oqp_batch* b, const oqp::KParams& P)
 {
     const int mixed = b->arg.mode == OQP_MODE_MIXED;
+    hipError_t e = hipSuccess;
+    if (b->naux > 0) {
+        e = hipEventRecord((hipEvent_t)b->ev_fork, (hipStream_t)b->stream);
+        for (int k = 0; k < b->naux && e == hipSuccess; ++k)
+            e = hipStreamWaitEvent((hipStream_t)b->aux[k], (hipEvent_t)b->ev_fork, 0);
+        if (e != hipSuccess) return fail(OQP_EDEVICE, "batch fork: %s", hipGetErrorString(e));
+    }
     // block-kernel groups first: they hold the largest instances
     for (int pass = 0; pass < 2; ++pass) {
         oqp::KParams Pp = P;
@@ -1126,10 +1149,53 @@ static int launch_all(oqp_batch* b, const oqp::KParams& P)
             const int v = b->nvar - 1 - k;
             if (b->vcount[v] == 0) continue;
             int rc = group_launch(v, pass == 0 ? mixed : 0, b->ddesc + b->vstart[v], b->hdesc + b->vstart[v],
-                                  b->vcount[v], b->ddata, b->diter, b->dwork, b->dstep, b->dstat, Pp, b->stream);
+                                  b->vcount[v], b->ddata, b->diter, b->dwork, b->dstep, b->dstat, Pp,
+                                  group_stream(b, v));
             if (rc) return fail(OQP_EDEVICE, "kernel launch failed for group %d", v);
         }
     }
+    // join: later work on the batch stream waits for every extra stream
+    for (int k = 0; k < b->naux && e == hipSuccess; ++k) {
+        e = hipEventRecord((hipEvent_t)b->ev_join[k], (hipStream_t)b->aux[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)b->stream, (hipEvent_t)b->ev_join[k], 0);
+    }
+    if (e != hipSuccess) return fail(OQP_EDEVICE, "batch join: %s", hipGetErrorString(e));
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_set_streams(oqp_batch* b, void* const* streams, int n)
+{
+    if (!b || n < 0 || n > OQP_BATCH_MAX_AUX || (n > 0 && !streams))
+        return fail(OQP_EINVAL, "oqp_batch_set_streams: bad argument (n=%d, at most %d)", n, OQP_BATCH_MAX_AUX);
+    int rc = oqp_batch_release(b);
+    if (rc) return rc;
+    if (n == 0) return OQP_OK;
+    hipError_t e = hipEventCreateWithFlags((hipEvent_t*)&b->ev_fork, hipEventDisableTiming);
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+        b->ev_join[k] = nullptr;
+        e = hipEventCreateWithFlags((hipEvent_t*)&b->ev_join[k], hipEventDisableTiming);
+        b->aux[k] = streams[k];
+        b->naux = k + 1;
+    }
+    if (e != hipSuccess) {
+        oqp_batch_release(b);
+        return fail(OQP_EDEVICE, "oqp_batch_set_streams: %s", hipGetErrorString(e));
+    }
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_release(oqp_batch* b)
+{
+    if (!b) return fail(OQP_EINVAL, "oqp_batch_release: NULL batch");
+    if (b->naux > 0 || b->ev_fork) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)b->stream);
+        if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_release: %s", hipGetErrorString(e));
+    }
+    for (int k = 0; k < b->naux; ++k)
+        if (b->ev_join[k]) hipEventDestroy((hipEvent_t)b->ev_join[k]);
+    if (b->ev_fork) hipEventDestroy((hipEvent_t)b->ev_fork);
+    b->ev_fork = nullptr;
+    b->naux = 0;
     return OQP_OK;
 }
 

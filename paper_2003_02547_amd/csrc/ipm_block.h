@@ -1517,9 +1517,16 @@ struct Blk {
     }
 };
 
+// Waves per SIMD the register budget is sized for: two where the kernel
+// fits 256 registers without spilling (stage blocks up to 32 without general
+// rows, and the global-memory mode), so that two instances share a CU and
+// hide each other's latency; one elsewhere (the prefetch registers of
+// 64-wide stage blocks need the whole register file).
+__host__ __device__ constexpr int block_waves(int zm, int gm) { return (zm > 64 || (zm == 32 && gm == 0)) ? 2 : 1; }
+
 // ZM > 64 selects the global-memory mode.
 template <bool MIXED, int ZM, int GM>
-__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(1, 1))) void ipm_block_kernel(
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(block_waves(ZM, GM), block_waves(ZM, GM)))) void ipm_block_kernel(
     const InstDesc* __restrict__ desc, int count, const double* __restrict__ data, double* __restrict__ iter,
     double* __restrict__ work, double* __restrict__ step_out, DevStat* __restrict__ stat, KParams P)
 {
