@@ -52,6 +52,7 @@ typedef struct {
     int iter_max;
     double alpha_min, gamma, lam_min, t_min, reg_prim, corr_ratio;
     int warm_start; /* 0 cold; 1 primal guess (u, x); 2 primal and dual guess (Section 4.2) */
+    int abs_form;   /* 1: absolute formulation (eq:alg:pdipm:abs), exit on the duality measure */
 } orc_arg;
 
 /* An iterate, a step or a residual in the user layout: u (sum nu), x (sum nx),
@@ -303,13 +304,10 @@ static void kkt_apply(const prob_t *p, const ivec_t *v, int with_H,
     }
 }
 
-/* IPM residuals at an iterate: constants g, b, d = [lo; -hi]. */
-static void residuals(const prob_t *p, const ivec_t *v, double *rg, double *rb, double *rdl, double *rdu)
+/* The constant part of the residual function: g, b and d = [lo; -hi]
+ * (the residual at y = 0, pi = 0, lam = 0, t = 0). */
+static void data_terms(const prob_t *p, double *cg, double *cb, double *cdl, double *cdu)
 {
-    double *cg = (double *)xcalloc((size_t)p->nv, sizeof(double));
-    double *cb = (double *)xcalloc((size_t)p->neq, sizeof(double));
-    double *cdl = (double *)xcalloc((size_t)p->ncon, sizeof(double));
-    double *cdu = (double *)xcalloc((size_t)p->ncon, sizeof(double));
     for (int n = 0; n <= p->N; ++n) {
         const stage_t *s = &p->st[n];
         for (int i = 0; i < s->nz; ++i) cg[p->zoff[n] + i] = s->g[i];
@@ -319,6 +317,16 @@ static void residuals(const prob_t *p, const ivec_t *v, double *rg, double *rb, 
             cdu[p->coff[n] + k] = -s->hi[k];
         }
     }
+}
+
+/* IPM residuals at an iterate: constants g, b, d = [lo; -hi]. */
+static void residuals(const prob_t *p, const ivec_t *v, double *rg, double *rb, double *rdl, double *rdu)
+{
+    double *cg = (double *)xcalloc((size_t)p->nv, sizeof(double));
+    double *cb = (double *)xcalloc((size_t)p->neq, sizeof(double));
+    double *cdl = (double *)xcalloc((size_t)p->ncon, sizeof(double));
+    double *cdu = (double *)xcalloc((size_t)p->ncon, sizeof(double));
+    data_terms(p, cg, cb, cdl, cdu);
     kkt_apply(p, v, 1, cg, cb, cdl, cdu, rg, rb, rdl, rdu);
     free(cg); free(cb); free(cdl); free(cdu);
 }
@@ -589,6 +597,39 @@ static void newton_solve(const prob_t *p, const fac_t *f, const ivec_t *v,
     free(gt);
 }
 
+/* Newton step in the absolute formulation (Section 3.2, eq:alg:pdipm:abs):
+ * the same matrix with right-hand side -[g; b; d; rm - 2 Lam T e] (the
+ * first three blocks linear in the iterate, so only their constant part
+ * remains; rm is the delta formulation's complementarity term, e.g. lam.*t -
+ * tau), whose solution is the full-step iterate; the step is its difference
+ * with the current iterate (eq:alg:pdipm:step). */
+static void newton_solve_abs(const prob_t *p, const fac_t *f, const ivec_t *v, const double *rml, const double *rmu,
+                             ivec_t *d)
+{
+    int nc = p->ncon;
+    double *cg = (double *)xcalloc((size_t)p->nv, sizeof(double));
+    double *cb = (double *)xcalloc((size_t)p->neq, sizeof(double));
+    double *cdl = (double *)xcalloc((size_t)nc, sizeof(double));
+    double *cdu = (double *)xcalloc((size_t)nc, sizeof(double));
+    double *al = (double *)xcalloc((size_t)nc, sizeof(double));
+    double *au = (double *)xcalloc((size_t)nc, sizeof(double));
+    data_terms(p, cg, cb, cdl, cdu);
+    for (int i = 0; i < nc; ++i) {
+        al[i] = rml[i] - 2.0 * v->ll[i] * v->tl[i];
+        au[i] = rmu[i] - 2.0 * v->lu[i] * v->tu[i];
+    }
+    newton_solve(p, f, v, cg, cb, cdl, cdu, al, au, d);
+    for (int i = 0; i < p->nv; ++i) d->y[i] -= v->y[i];
+    for (int i = 0; i < p->neq; ++i) d->pi[i] -= v->pi[i];
+    for (int i = 0; i < nc; ++i) {
+        d->ll[i] -= v->ll[i];
+        d->lu[i] -= v->lu[i];
+        d->tl[i] -= v->tl[i];
+        d->tu[i] -= v->tu[i];
+    }
+    free(cg); free(cb); free(cdl); free(cdu); free(al); free(au);
+}
+
 /* Largest alpha (uncapped; HUGE_VAL if no component blocks) keeping
  * lam + alpha dlam >= 0 and t + alpha dt >= 0. */
 static double max_step(const prob_t *p, const ivec_t *v, const ivec_t *d)
@@ -656,8 +697,9 @@ int orc_residuals(const orc_qp *qp, const orc_vec *it, orc_vec *res, double *nor
 }
 
 /* Newton step of eq:alg:pdipm:delta at the iterate `it` with r_m = lam.*t - tau,
- * factorized with regularization `reg`.  Returns the step in user layout. */
-int orc_newton_step(const orc_qp *qp, const orc_vec *it, double tau, double reg, orc_vec *step)
+ * factorized with regularization `reg`; with abs_form, the same step through
+ * the absolute formulation.  Returns the step in user layout. */
+int orc_newton_step(const orc_qp *qp, const orc_vec *it, double tau, double reg, int abs_form, orc_vec *step)
 {
     prob_t p;
     int rc = prob_build(qp, &p);
@@ -678,7 +720,8 @@ int orc_newton_step(const orc_qp *qp, const orc_vec *it, double tau, double reg,
     memset(&f, 0, sizeof(f));
     rc = factorize(&p, wl, wu, reg, &f);
     if (rc == 0) {
-        newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, r.tl, r.tu, &d);
+        if (abs_form) newton_solve_abs(&p, &f, &v, r.tl, r.tu, &d);
+        else newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, r.tl, r.tu, &d);
         ivec_to_user(&p, &d, step);
     }
     fac_free(&f);
@@ -740,8 +783,11 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
 
     int status = ORC_MAX_ITER, k = 0;
     double norms[4] = {0, 0, 0, 0}, mu = 0.0;
+    const int absf = arg->abs_form != 0;
     for (k = 0;; ++k) {
-        residuals(&p, &v, r.y, r.pi, r.ll, r.lu);
+        /* absolute formulation (Section 4.2, mode speed_abs): no residuals in
+         * the loop, exit on the duality measure alone */
+        if (!absf) residuals(&p, &v, r.y, r.pi, r.ll, r.lu);
         double lt = 0.0, comp = 0.0;
         for (int i = 0; i < nc; ++i) {
             double a = v.ll[i] * v.tl[i], b2 = v.lu[i] * v.tu[i];
@@ -750,19 +796,24 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
             if (b2 > comp) comp = b2;
         }
         mu = nc ? lt / (2.0 * nc) : 0.0;
-        double dl = inf_norm(r.ll, nc), du = inf_norm(r.lu, nc);
-        norms[0] = inf_norm(r.y, p.nv);
-        norms[1] = inf_norm(r.pi, p.neq);
-        norms[2] = du > dl ? du : dl;
-        norms[3] = comp;
-        if (norms[0] != norms[0] || norms[1] != norms[1] || norms[2] != norms[2] || mu != mu) {
-            status = ORC_NAN;
-            break;
-        }
-        if (norms[0] <= arg->tol_stat && norms[1] <= arg->tol_eq && norms[2] <= arg->tol_ineq &&
-            norms[3] <= arg->tol_comp) {
-            status = ORC_SUCCESS;
-            break;
+        if (absf) {
+            if (mu != mu) { status = ORC_NAN; break; }
+            if (mu <= arg->tol_comp) { status = ORC_SUCCESS; break; }
+        } else {
+            double dl = inf_norm(r.ll, nc), du = inf_norm(r.lu, nc);
+            norms[0] = inf_norm(r.y, p.nv);
+            norms[1] = inf_norm(r.pi, p.neq);
+            norms[2] = du > dl ? du : dl;
+            norms[3] = comp;
+            if (norms[0] != norms[0] || norms[1] != norms[1] || norms[2] != norms[2] || mu != mu) {
+                status = ORC_NAN;
+                break;
+            }
+            if (norms[0] <= arg->tol_stat && norms[1] <= arg->tol_eq && norms[2] <= arg->tol_ineq &&
+                norms[3] <= arg->tol_comp) {
+                status = ORC_SUCCESS;
+                break;
+            }
         }
         if (k >= arg->iter_max) { status = ORC_MAX_ITER; break; }
 
@@ -773,7 +824,8 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
 
         /* predictor (affine): r_m = lam.*t */
         for (int i = 0; i < nc; ++i) { rml[i] = v.ll[i] * v.tl[i]; rmu[i] = v.lu[i] * v.tu[i]; }
-        newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, rml, rmu, &d);
+        if (absf) newton_solve_abs(&p, &f, &v, rml, rmu, &d);
+        else newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, rml, rmu, &d);
         ivec_t *step = &d;
         if (nc > 0) {
             double a_aff = max_step(&p, &v, &d);
@@ -785,7 +837,8 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
                 rml[i] = v.ll[i] * v.tl[i] + d.ll[i] * d.tl[i] - sigma * mu;
                 rmu[i] = v.lu[i] * v.tu[i] + d.lu[i] * d.tu[i] - sigma * mu;
             }
-            newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, rml, rmu, &dc);
+            if (absf) newton_solve_abs(&p, &f, &v, rml, rmu, &dc);
+            else newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, rml, rmu, &dc);
             double a_c = max_step(&p, &v, &dc);
             if (a_c > 1.0) a_c = 1.0;
             double mu_c = mu_after(&p, &v, &dc, a_c);
@@ -795,7 +848,8 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
                     rml[i] = v.ll[i] * v.tl[i] - sigma * mu;
                     rmu[i] = v.lu[i] * v.tu[i] - sigma * mu;
                 }
-                newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, rml, rmu, &dc);
+                if (absf) newton_solve_abs(&p, &f, &v, rml, rmu, &dc);
+                else newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, rml, rmu, &dc);
             }
             step = &dc;
         }
@@ -836,6 +890,21 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
             ++k;
             break;
         }
+    }
+    if (absf && status != ORC_NAN) {
+        /* residuals only before returning */
+        residuals(&p, &v, r.y, r.pi, r.ll, r.lu);
+        double comp3 = 0.0;
+        for (int i = 0; i < nc; ++i) {
+            double a = v.ll[i] * v.tl[i], b2 = v.lu[i] * v.tu[i];
+            if (a > comp3) comp3 = a;
+            if (b2 > comp3) comp3 = b2;
+        }
+        double dl3 = inf_norm(r.ll, nc), du3 = inf_norm(r.lu, nc);
+        norms[0] = inf_norm(r.y, p.nv);
+        norms[1] = inf_norm(r.pi, p.neq);
+        norms[2] = du3 > dl3 ? du3 : dl3;
+        norms[3] = comp3;
     }
     if (iters) *iters = k;
     if (res_norms) for (int i = 0; i < 4; ++i) res_norms[i] = norms[i];

@@ -51,7 +51,8 @@ class _Arg(ct.Structure):
     _fields_ = [("tol_stat", ct.c_double), ("tol_eq", ct.c_double), ("tol_ineq", ct.c_double),
                 ("tol_comp", ct.c_double), ("iter_max", ct.c_int), ("alpha_min", ct.c_double),
                 ("gamma", ct.c_double), ("lam_min", ct.c_double), ("t_min", ct.c_double),
-                ("reg_prim", ct.c_double), ("corr_ratio", ct.c_double), ("warm_start", ct.c_int)]
+                ("reg_prim", ct.c_double), ("corr_ratio", ct.c_double), ("warm_start", ct.c_int),
+                ("abs_form", ct.c_int)]
 
 
 class _Vec(ct.Structure):
@@ -71,7 +72,7 @@ def _load():
         lib.orc_solve.restype = ct.c_int
         lib.orc_residuals.argtypes = [ct.POINTER(_Qp), ct.POINTER(_Vec), ct.POINTER(_Vec), _P, _P]
         lib.orc_residuals.restype = ct.c_int
-        lib.orc_newton_step.argtypes = [ct.POINTER(_Qp), ct.POINTER(_Vec), ct.c_double, ct.c_double,
+        lib.orc_newton_step.argtypes = [ct.POINTER(_Qp), ct.POINTER(_Vec), ct.c_double, ct.c_double, ct.c_int,
                                         ct.POINTER(_Vec)]
         lib.orc_newton_step.restype = ct.c_int
         lib.orc_ir_residual.argtypes = [ct.POINTER(_Qp), ct.POINTER(_Vec), ct.POINTER(_Vec),
@@ -96,11 +97,12 @@ class Arg:
     reg_prim: float = 0.0
     corr_ratio: float = 10.0
     warm_start: int = 0  # 0 cold; 1 primal guess; 2 primal and dual guess (Section 4.2)
+    abs_form: int = 0    # 1: absolute formulation (eq:alg:pdipm:abs), exit on the duality measure
 
     def _c(self):
         return _Arg(self.tol_stat, self.tol_eq, self.tol_ineq, self.tol_comp, int(self.iter_max),
                     self.alpha_min, self.gamma, self.lam_min, self.t_min, self.reg_prim, self.corr_ratio,
-                    int(self.warm_start))
+                    int(self.warm_start), int(self.abs_form))
 
     @staticmethod
     def with_tol(tol: float, **kw) -> "Arg":
@@ -233,14 +235,17 @@ def residuals(qp, iterate: dict):
     return out.view(), norms, mu.value
 
 
-def newton_step(qp, iterate: dict, tau: float = 0.0, reg: float = 0.0) -> dict:
-    """Newton step of eq:alg:pdipm:delta at `iterate`, r_m = lam.*t - tau."""
+def newton_step(qp, iterate: dict, tau: float = 0.0, reg: float = 0.0, abs_form: bool = False) -> dict:
+    """Newton step of eq:alg:pdipm:delta at `iterate`, r_m = lam.*t - tau; with
+    abs_form the same step through the absolute formulation (eq:alg:pdipm:abs
+    and eq:alg:pdipm:step)."""
     lib = _load()
     pk = _Packed(qp)
     it = _vec_from(pk, iterate)
     out = Vec.like(pk)
     itc, outc = it.c(), out.c()
-    rc = lib.orc_newton_step(ct.byref(pk.c), ct.byref(itc), ct.c_double(tau), ct.c_double(reg), ct.byref(outc))
+    rc = lib.orc_newton_step(ct.byref(pk.c), ct.byref(itc), ct.c_double(tau), ct.c_double(reg), int(abs_form),
+                             ct.byref(outc))
     if rc != 0:
         raise ValueError(f"oracle Newton step failed (code {rc})")
     return out.view()
