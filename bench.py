@@ -10,6 +10,7 @@ to the KKT tolerance), FP64 path; the mixed path is timed beside it.
 Further legs on the same line (context, not the headline):
   * pcond: the same batch solved through partial condensing to a shorter
     horizon (condensing and expansion inside the timed solve);
+  * abs: the same batch in the absolute formulation (mode speed_abs);
   * warm: the next receding-horizon problem of every solved instance, cold
     and warm-started from the shifted solution;
   * uneven: a batch of random stable OCP QPs with nx ~ U{4..48},
@@ -210,6 +211,38 @@ def leg_warm(B, W, torch, np, qps, steps):
     return out
 
 
+def leg_abs(B, torch, np, qps, steps):
+    """The headline batch in the absolute formulation (mode speed_abs: no
+    residuals in the loop, exit on the duality measure, residual norms of
+    the returned point reported).  Cancellation near the solution keeps its
+    residuals above the delta path's, so it is reported with both counts: the
+    solves that exit on the duality measure and those that also meet the KKT
+    tolerance."""
+    b = B.Batch(qps, B.default_arg(B.MODE_ABS)).load().sync()
+    b.solve()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(steps):
+        s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s_.record(b.stream)
+        b.solve()
+        e_.record(b.stream)
+        torch.cuda.synchronize()
+        ms.append(s_.elapsed_time(e_))
+    b.fetch().sync()
+    stats = [b.stat(i) for i in range(len(qps))]
+    exit_ok = sum(1 for x in stats if x.status == B.SUCCESS)
+    kkt_ok = sum(1 for x in stats if x.status == B.SUCCESS and max(x.res[:]) <= KKT_OK)
+    iters = np.array([x.iters for x in stats])
+    res = np.array([max(x.res[:]) for x in stats if x.status == B.SUCCESS])
+    med = float(np.median(ms))
+    del b
+    return {"ms_per_step": round(med, 3), "exit_on_mu": exit_ok, "kkt_ok": kkt_ok,
+            "value_exit_on_mu": round(exit_ok / (med * 1e-3), 1), "unit": "solves/s",
+            "iters_p50": float(np.percentile(iters, 50)), "iters_max": int(iters.max()),
+            "kkt_res_p50": float(np.median(res)) if res.size else None, "tol_comp_on_mu": 1e-8}
+
+
 def leg_single(B, W, torch, np, reps):
     """Latency of one 4-mass QP (nx = 8, nu = 3, N = 10, dt = 0.5; seed 1) in
     a batch of one: one launch, FP64 to 1e-8, median over reps (the CPU
@@ -320,6 +353,7 @@ def main():
     ap.add_argument("--pcond", default="5,10,15", help="condensed horizons for the partial-condensing leg ('': skip)")
     ap.add_argument("--pcond-steps", type=int, default=5)
     ap.add_argument("--warm-steps", type=int, default=5, help="timed solves of the warm-start leg (0: skip)")
+    ap.add_argument("--abs-steps", type=int, default=5, help="timed solves of the absolute-formulation leg (0: skip)")
     ap.add_argument("--large", type=int, default=256, help="instances of the large-stage leg (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2)
     ap.add_argument("--serve-pool", type=int, default=256, help="distinct instances in the serving pool (0: skip)")
@@ -445,6 +479,9 @@ def main():
         n2s = [int(x) for x in args.pcond.split(",") if x]
         log(f"bench: partial condensing leg, N2 in {n2s}")
         line["pcond"] = leg_pcond(B, W, torch, np, qps, n2s, args.pcond_steps)
+    if args.abs_steps > 0:
+        log("bench: absolute-formulation leg")
+        line["abs"] = leg_abs(B, torch, np, qps, args.abs_steps)
     if args.warm_steps > 0:
         log("bench: receding-horizon warm-start leg")
         line["warm"] = leg_warm(B, W, torch, np, qps, args.warm_steps)

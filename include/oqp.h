@@ -59,6 +59,10 @@ extern "C" {
 /* ---- modes ------------------------------------------------------------- */
 #define OQP_MODE_F64 0   /* FP64 factorization ("speed" mode, delta formulation) */
 #define OQP_MODE_MIXED 1 /* FP32 factorization + FP64 iterative refinement */
+#define OQP_MODE_ABS 2   /* FP64, absolute formulation (eq:alg:pdipm:abs; mode "speed_abs" of Section 4.2):
+                            right-hand sides from the data, no residuals in the loop, exit when the
+                            duality measure mu <= tol_comp (or on the iteration limit or a too-short
+                            step); stat.res holds the residual norms of the returned point */
 
 typedef struct oqp_dims oqp_dims;
 typedef struct oqp_qp oqp_qp;

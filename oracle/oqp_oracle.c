@@ -905,6 +905,8 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
         norms[1] = inf_norm(r.pi, p.neq);
         norms[2] = du3 > dl3 ? du3 : dl3;
         norms[3] = comp3;
+        if (norms[0] != norms[0] || norms[1] != norms[1] || norms[2] != norms[2] || norms[3] != norms[3])
+            status = ORC_NAN;
     }
     if (iters) *iters = k;
     if (res_norms) for (int i = 0; i < 4; ++i) res_norms[i] = norms[i];

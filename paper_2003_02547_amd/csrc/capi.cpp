@@ -369,7 +369,7 @@ extern "C" void oqp_arg_default(oqp_arg* a, int mode)
 {
     if (!a) return;
     std::memset(a, 0, sizeof(*a));
-    a->mode = mode == OQP_MODE_MIXED ? OQP_MODE_MIXED : OQP_MODE_F64;
+    a->mode = (mode == OQP_MODE_MIXED || mode == OQP_MODE_ABS) ? mode : OQP_MODE_F64;
     const double tol = a->mode == OQP_MODE_MIXED ? 1e-6 : 1e-8;
     a->tol_stat = a->tol_eq = a->tol_ineq = a->tol_comp = tol;
     a->iter_max = 100;
@@ -388,7 +388,8 @@ extern "C" void oqp_arg_default(oqp_arg* a, int mode)
 int check_arg(const oqp_arg* a)
 {
     if (!a) return fail(OQP_EINVAL, "NULL oqp_arg");
-    if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED) return fail(OQP_EINVAL, "unknown mode %d", a->mode);
+    if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED && a->mode != OQP_MODE_ABS)
+        return fail(OQP_EINVAL, "unknown mode %d", a->mode);
     if (a->iter_max < 0 || !(a->gamma > 0.0 && a->gamma <= 1.0) || a->warm_start < 0 || a->warm_start > 2 ||
         a->ir_max < 0 || a->cond_N < 0 || (a->warm_start != 0 && a->cond_N != 0))
         return fail(OQP_EINVAL, "bad oqp_arg field (iter_max, gamma, warm_start or cond_N)");
@@ -658,17 +659,17 @@ extern "C" int oqp_set_wave_max(int nz)
 extern "C" int oqp_get_wave_max(void) { return g_wave_max_nz; }
 
 // Launch the instances [desc, desc + count) of kernel group g.
-int group_launch(int g, int mixed, const InstDesc* desc, const InstDesc* hdesc, int count, const double* data,
+int group_launch(int g, int km, const InstDesc* desc, const InstDesc* hdesc, int count, const double* data,
                  double* iter, double* work, double* step, DevStat* stat, const oqp::KParams& P, void* stream)
 {
     const int nv = oqp::variant_count();
-    if (g < nv) return oqp::variant_launch(g, mixed, desc, count, data, iter, work, step, stat, P, stream);
+    if (g < nv) return oqp::variant_launch(g, km, desc, count, data, iter, work, step, stat, P, stream);
     size_t lds = 0;
     for (int i = 0; i < count; ++i) {
         const size_t b = (size_t)oqp::block_lds_bytes(hdesc[i].nx, hdesc[i].nu, hdesc[i].ng);
         if (b > lds) lds = b;
     }
-    return oqp::block_launch(kBlockZ[g - nv], kBlockG[g - nv], mixed, desc, count, data, iter, work, step, stat, P,
+    return oqp::block_launch(kBlockZ[g - nv], kBlockG[g - nv], km, desc, count, data, iter, work, step, stat, P,
                              lds, stream);
 }
 
@@ -1114,6 +1115,11 @@ oqp::KParams make_params(const oqp_arg& a, int mode, double tau)
     return P;
 }
 
+int kernel_build(int mode)
+{
+    return mode == OQP_MODE_MIXED ? oqp::KM_MIXED : (mode == OQP_MODE_ABS ? oqp::KM_ABS : oqp::KM_F64);
+}
+
 // Stream of kernel group v: the first non-empty group (in launch order) on
 // the batch stream, the others round-robin over the extra streams.
 static void* group_stream(const oqp_batch* b, int v)
@@ -1127,7 +1133,7 @@ static void* group_stream(const oqp_batch* b, int v)
 
 static int launch_all(oqp_batch* b, const oqp::KParams& P)
 {
-    const int mixed = b->arg.mode == OQP_MODE_MIXED;
+    const int km = kernel_build(b->arg.mode);
     hipError_t e = hipSuccess;
     if (b->naux > 0) {
         e = hipEventRecord((hipEvent_t)b->ev_fork, (hipStream_t)b->stream);
@@ -1139,7 +1145,7 @@ static int launch_all(oqp_batch* b, const oqp::KParams& P)
     for (int pass = 0; pass < 2; ++pass) {
         oqp::KParams Pp = P;
         if (pass == 1) {
-            if (!(mixed && P.mode == oqp::KMODE_SOLVE)) break;
+            if (!(km == oqp::KM_MIXED && P.mode == oqp::KMODE_SOLVE)) break;
             // FP64 kernels pick up the instances the mixed kernels handed over
             // (from a cold start)
             Pp.mode = oqp::KMODE_FALLBACK;
@@ -1148,7 +1154,7 @@ static int launch_all(oqp_batch* b, const oqp::KParams& P)
         for (int k = 0; k < b->nvar; ++k) {
             const int v = b->nvar - 1 - k;
             if (b->vcount[v] == 0) continue;
-            int rc = group_launch(v, pass == 0 ? mixed : 0, b->ddesc + b->vstart[v], b->hdesc + b->vstart[v],
+            int rc = group_launch(v, pass == 0 ? km : oqp::KM_F64, b->ddesc + b->vstart[v], b->hdesc + b->vstart[v],
                                   b->vcount[v], b->ddata, b->diter, b->dwork, b->dstep, b->dstat, Pp,
                                   group_stream(b, v));
             if (rc) return fail(OQP_EDEVICE, "kernel launch failed for group %d", v);
@@ -1192,8 +1198,8 @@ extern "C" int oqp_batch_release(oqp_batch* b)
         if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_batch_release: %s", hipGetErrorString(e));
     }
     for (int k = 0; k < b->naux; ++k)
-        if (b->ev_join[k]) hipEventDestroy((hipEvent_t)b->ev_join[k]);
-    if (b->ev_fork) hipEventDestroy((hipEvent_t)b->ev_fork);
+        if (b->ev_join[k]) (void)hipEventDestroy((hipEvent_t)b->ev_join[k]);
+    if (b->ev_fork) (void)hipEventDestroy((hipEvent_t)b->ev_fork);
     b->ev_fork = nullptr;
     b->naux = 0;
     return OQP_OK;

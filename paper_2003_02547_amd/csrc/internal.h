@@ -30,11 +30,11 @@ struct oqp_qp {
 namespace oqp {
 int variant_count();
 void variant_dims(int v, int* nx, int* nu, int* ng);
-int variant_launch(int v, int mixed, const InstDesc* desc, int count, const double* data, double* iter, double* work,
+int variant_launch(int v, int km, const InstDesc* desc, int count, const double* data, double* iter, double* work,
                    double* step, DevStat* stat, const KParams& P, void* stream);
 int block_lds_bytes(int nx, int nu, int ng);
 int block_zmax(int nz);
-int block_launch(int zm, int gm, int mixed, const InstDesc* desc, int count, const double* data, double* iter,
+int block_launch(int zm, int gm, int km, const InstDesc* desc, int count, const double* data, double* iter,
                  double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
 // partial condensing (expand = 0: original data -> condensed data records;
 // expand = 1: condensed iterate -> original-layout iterate records)
@@ -52,10 +52,13 @@ struct KSel {
 };
 int group_count();
 int select_kernel(const oqp_dims* d, KSel* out);
-int group_launch(int g, int mixed, const oqp::InstDesc* desc, const oqp::InstDesc* hdesc, int count,
+// km: kernel build (oqp::KM_F64, KM_MIXED, KM_ABS)
+int group_launch(int g, int km, const oqp::InstDesc* desc, const oqp::InstDesc* hdesc, int count,
                  const double* data, double* iter, double* work, double* step, oqp::DevStat* stat,
                  const oqp::KParams& P, void* stream);
 double inst_cost(int N, int nx, int nu);
+// kernel build of a solver mode
+int kernel_build(int mode);
 // stage sizes (dims5: nx, nu, nbu, nbx, ng, each N+1 entries) equal to dims
 bool dims5_match(const int* dims5, int N, const oqp_dims* dims);
 bool batch_dims_match(const oqp_batch* b, int i, const oqp_dims* dims);

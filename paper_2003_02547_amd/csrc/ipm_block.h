@@ -111,8 +111,10 @@ __device__ __forceinline__ double* blds()
     return oqp_blds_dyn;
 }
 
-template <bool MIXED, int ZM, int GM, bool GL>
+template <int KM, int ZM, int GM, bool GL>
 struct Blk {
+    static constexpr bool MIXED = KM == KM_MIXED;
+    static constexpr bool ABS = KM == KM_ABS;  // absolute formulation (Section 3.2)
     using TS = typename std::conditional<MIXED, float, double>::type;
     Layout Lo;
     BLds S;
@@ -755,8 +757,11 @@ struct Blk {
     // barrier terms, factorization and the right-hand-side sweep for r_m =
     // lam.*t - shift.  Returns whether every pivot was positive.
     // ==================================================================
-    __device__ __forceinline__ bool passA(bool upd, double alpha, double shift, bool factor, double& o_g, double& o_b, double& o_d,
-                          double& o_m, double& o_lt) const
+    // With absf (absolute formulation, Section 3.2) the right-hand side is
+    // built from the data alone, -[g; b; d; r_m - 2 Lam T e]; the residual
+    // products are skipped and their norms not formed.
+    __device__ __forceinline__ bool passA(bool upd, double alpha, double shift, bool factor, bool absf, double& o_g,
+                                          double& o_b, double& o_d, double& o_m, double& o_lt) const
     {
         double mg = 0.0, mb = 0.0, md = 0.0, mm = 0.0, slt = 0.0;
         bool fact_ok = true;
@@ -817,7 +822,9 @@ struct Blk {
 
             // r_g = H z + g + F' pi_{n+1} - [0; pi_n] - C' lam
             double rg = 0.0;
-            if (j < NZ) {
+            if (absf) {
+                if (j < NZ) rg = g;
+            } else if (j < NZ) {
                 const double* mh = M();
                 const double* zv = z();
                 double acc = g + dot<double>(mh + j, ldm, zv, 1, NZ);
@@ -830,7 +837,9 @@ struct Blk {
             }
             // r_b = F z + b - x_{n+1}
             double rb = 0.0;
-            if (n < N && j < NX) {
+            if (absf) {
+                if (n < N && j < NX) rb = b;
+            } else if (n < N && j < NX) {
                 const double acc = b + dot<double>(F() + j, ldf, z(), 1, NZ);
                 rb = acc - xn(nxt)[j];
                 mb = nmax(mb, fabs(rb));
@@ -840,22 +849,30 @@ struct Blk {
             if (j < NC) {
                 double e = 0.0, wsum = 0.0;
                 if (m != 0.0) {
-                    double gz;
-                    if (j < NZ) {
-                        gz = zz;
+                    if (absf) {
+                        rdl = lo;
+                        rdu = -hi;
                     } else {
-                        gz = dot<double>(G() + (j - NZ), ldg, z(), 1, NZ);
+                        double gz;
+                        if (j < NZ) {
+                            gz = zz;
+                        } else {
+                            gz = dot<double>(G() + (j - NZ), ldg, z(), 1, NZ);
+                        }
+                        rdl = -gz + tl + lo;
+                        rdu = gz + tu - hi;
+                        md = nmax(md, nmax(fabs(rdl), fabs(rdu)));
                     }
-                    rdl = -gz + tl + lo;
-                    rdu = gz + tu - hi;
-                    md = nmax(md, nmax(fabs(rdl), fabs(rdu)));
                     const double a1 = ll * tl, a2 = lu * tu;
                     mm = nmax(mm, nmax(a1, a2));
                     slt += a1 + a2;
                     const double itl = rcp_nr(tl), itu = rcp_nr(tu);
                     const double wl = ll * itl, wu = lu * itu;
                     wsum = wl + wu;
-                    e = (wl * rdl - (ll - shift * itl)) - (wu * rdu - (lu - shift * itu));
+                    // r_m / t, with r_m = lam t - shift (delta) or -lam t - shift (absolute)
+                    const double ml = absf ? -ll - shift * itl : ll - shift * itl;
+                    const double mu_ = absf ? -lu - shift * itu : lu - shift * itu;
+                    e = (wl * rdl - ml) - (wu * rdu - mu_);
                 }
                 ev()[j] = e;
                 wsv()[j] = wsum;
@@ -965,6 +982,11 @@ struct Blk {
         if (rmode == RM_CORRECTOR) {
             rml += w[Lo.W_all + c] * w[Lo.W_atl + c];
             rmu += w[Lo.W_alu + c] * w[Lo.W_atu + c];
+        }
+        if (ABS) {
+            // absolute formulation: r_m - 2 lam t
+            rml -= 2.0 * ll * tl;
+            rmu -= 2.0 * lu * tu;
         }
     }
 
@@ -1126,13 +1148,13 @@ struct Blk {
                 }
                 if (lane < NU) {
                     z()[lane] = -v;
-                    w[oz + lane] = -v;
+                    w[oz + lane] = ABS ? -v - ir[Lo.I_z + lane] : -v;
                 }
             }
             if (j >= NU && j < NZ) {
                 const double dz = xn(cur)[j - NU];
                 z()[j] = dz;
-                w[oz + j] = dz;
+                w[oz + j] = ABS ? dz - ir[Lo.I_z + j] : dz;
             }
             __syncthreads();
             if (n < N) {
@@ -1141,7 +1163,10 @@ struct Blk {
                 __syncthreads();
                 if (j < NX) t1()[j] = (double)dot<TS>(xc + (NU + j) + j * ldm, 1, xn(nxt) + j, 1, NX - j);
                 __syncthreads();
-                if (j < NX) Wp(n + 1)[opi + j] = (double)((TS)pnx + dot<TS>(xc + (NU + j), ldm, t1(), 1, j + 1));
+                if (j < NX) {
+                    const double pv = (double)((TS)pnx + dot<TS>(xc + (NU + j), ldm, t1(), 1, j + 1));
+                    Wp(n + 1)[opi + j] = ABS ? pv - Ip(n + 1)[Lo.I_pi + j] : pv;
+                }
             }
             // constraint steps, step length, duality-measure sums
             if (j < NC) {
@@ -1157,6 +1182,14 @@ struct Blk {
                     dtu = -gdz - rdu;
                     dll = -(rml + ll * dtl) * rcp_nr(tl);
                     dlu = -(rmu + lu * dtu) * rcp_nr(tu);
+                    if (ABS) {
+                        // absolute formulation: full-step iterate minus the
+                        // current one (eq:alg:pdipm:step)
+                        dtl -= tl;
+                        dtu -= tu;
+                        dll -= ll;
+                        dlu -= lu;
+                    }
                     if (dll < 0.0) amin = fmin(amin, -ll * __builtin_amdgcn_rcp(dll));
                     if (dlu < 0.0) amin = fmin(amin, -lu * __builtin_amdgcn_rcp(dlu));
                     if (dtl < 0.0) amin = fmin(amin, -tl * __builtin_amdgcn_rcp(dtl));
@@ -1421,6 +1454,7 @@ struct Blk {
     __device__ __forceinline__ void run(DevStat* st, double* step_out, int fell_back) const
     {
         const bool newton_mode = P.mode == KMODE_NEWTON;
+        const bool absf = ABS;
         if (!newton_mode) init();
         int status = ST_MAX_ITER, k = 0;
         double ng = 0, nb = 0, nd = 0, nm = 0, mu = 0.0, slt = 0.0;
@@ -1429,19 +1463,50 @@ struct Blk {
         bool upd = false, rejected = false;
         double alpha = 0.0;
         int ir_steps = 0;
+        // absolute formulation: once the loop ends, one more pass A (delta
+        // form, no update, no factorization) evaluates the residuals at the
+        // returned iterate, through the single call site of pass A
+        bool final_pass = false;
+        int k_exit = 0;
         for (k = 0;; ++k) {
-            const bool fact_ok = passA(upd, alpha, shift0, !rejected, ng, nb, nd, nm, slt);
+            const bool fact_ok =
+                passA(upd, alpha, shift0, !rejected && !final_pass, absf && !final_pass, ng, nb, nd, nm, slt);
             __syncthreads();
             mu = slt * inv2nc;
+            if (final_pass) {
+                k = k_exit;
+                if (ng != ng || nb != nb || nd != nd || nm != nm) status = ST_NAN;
+                break;
+            }
             if (rejected) {
                 status = ST_MIN_STEP;
+                if (absf) {
+                    final_pass = true;
+                    k_exit = k;
+                    upd = false;
+                    continue;
+                }
                 break;
             }
             if (MIXED && !newton_mode && !fact_ok) {
                 status = ST_FALLBACK;
                 break;
             }
-            if (!newton_mode) {
+            if (!newton_mode && absf) {
+                // absolute formulation (mode speed_abs): exit on the duality
+                // measure alone
+                if (mu != mu) {
+                    status = ST_NAN;
+                    break;
+                }
+                if (mu <= P.tol_comp || k >= P.iter_max) {
+                    status = mu <= P.tol_comp ? ST_SUCCESS : ST_MAX_ITER;
+                    final_pass = true;
+                    k_exit = k;
+                    upd = false;
+                    continue;
+                }
+            } else if (!newton_mode) {
                 if (ng != ng || nb != nb || nd != nd || nm != nm || mu != mu) {
                     status = ST_NAN;
                     break;
@@ -1525,7 +1590,7 @@ struct Blk {
 __host__ __device__ constexpr int block_waves(int zm, int gm) { return (zm > 64 || (zm == 32 && gm == 0)) ? 2 : 1; }
 
 // ZM > 64 selects the global-memory mode.
-template <bool MIXED, int ZM, int GM>
+template <int KM, int ZM, int GM>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(block_waves(ZM, GM), block_waves(ZM, GM)))) void ipm_block_kernel(
     const InstDesc* __restrict__ desc, int count, const double* __restrict__ data, double* __restrict__ iter,
     double* __restrict__ work, double* __restrict__ step_out, DevStat* __restrict__ stat, KParams P)
@@ -1538,7 +1603,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(block_waves(
         if (stat[ds.index].status != ST_FALLBACK) return;
         fell_back = 1;
     }
-    const Blk<MIXED, ZM, GM, (ZM > 64)> ipm(ds, data, iter, work, P);
+    const Blk<KM, ZM, GM, (ZM > 64)> ipm(ds, data, iter, work, P);
     ipm.run(stat + ds.index, step_out + ds.iter, fell_back);
 }
 

@@ -7,11 +7,11 @@
 
 namespace oqp {
 
-template <bool MIXED, int ZM, int GM>
+template <int KM, int ZM, int GM>
 static int launch_block_t(const InstDesc* desc, int count, const double* data, double* iter, double* work,
                           double* step, DevStat* stat, const KParams& P, size_t lds_bytes, hipStream_t stream)
 {
-    hipLaunchKernelGGL((ipm_block_kernel<MIXED, ZM, GM>), dim3(count), dim3(BT), lds_bytes, stream, desc, count, data,
+    hipLaunchKernelGGL((ipm_block_kernel<KM, ZM, GM>), dim3(count), dim3(BT), lds_bytes, stream, desc, count, data,
                        iter, work, step, stat, P);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -20,14 +20,18 @@ int block_lds_bytes(int nx, int nu, int ng) { return (int)(sizeof(double) * make
 
 int block_zmax(int nz) { return nz <= 32 ? 32 : (nz <= 64 ? 64 : (nz <= 256 ? 256 : 0)); }
 
-int block_launch(int zm, int gm, int mixed, const InstDesc* desc, int count, const double* data, double* iter,
+int block_launch(int zm, int gm, int km, const InstDesc* desc, int count, const double* data, double* iter,
                  double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
 #define OQP_BLK(Z, G)                                                                                             \
-    if (zm == Z && gm == G)                                                                                         \
-        return mixed ? launch_block_t<true, Z, G>(desc, count, data, iter, work, step, stat, P, lds_bytes, s)     \
-                     : launch_block_t<false, Z, G>(desc, count, data, iter, work, step, stat, P, lds_bytes, s);
+    if (zm == Z && gm == G) {                                                                                       \
+        if (km == KM_MIXED) return launch_block_t<KM_MIXED, Z, G>(desc, count, data, iter, work, step, stat, P,   \
+                                                                  lds_bytes, s);                                    \
+        if (km == KM_ABS) return launch_block_t<KM_ABS, Z, G>(desc, count, data, iter, work, step, stat, P,       \
+                                                              lds_bytes, s);                                        \
+        return launch_block_t<KM_F64, Z, G>(desc, count, data, iter, work, step, stat, P, lds_bytes, s);          \
+    }
     OQP_BLK(32, 0)
     OQP_BLK(32, 64)
     OQP_BLK(64, 0)

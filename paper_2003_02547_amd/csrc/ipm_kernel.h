@@ -45,8 +45,10 @@
 
 namespace oqp {
 
-template <int NX, int NU, int NG, bool MIXED>
+template <int NX, int NU, int NG, int KM>
 struct Ipm {
+    static constexpr bool MIXED = KM == KM_MIXED;
+    static constexpr bool ABS = KM == KM_ABS;  // absolute formulation (Section 3.2)
     // arithmetic type of the factorization and of the right-hand-side sweeps
     // (FP32 in the mixed path; pivots, residuals and refinement stay FP64)
     using TS = typename std::conditional<MIXED, float, double>::type;
@@ -475,7 +477,10 @@ struct Ipm {
         }
     }
 
-    __device__ __forceinline__ bool passA(bool upd, double alpha, double shift, bool factor, double& o_g,
+    // With absf (absolute formulation, Section 3.2) the right-hand side is
+    // built from the data alone, -[g; b; d; r_m - 2 Lam T e]: the residual
+    // matrix-vector products are skipped and their norms are not formed.
+    __device__ __forceinline__ bool passA(bool upd, double alpha, double shift, bool factor, bool absf, double& o_g,
                                           double& o_b, double& o_d, double& o_m, double& o_lt) const
     {
         Smem& s = S();
@@ -533,7 +538,9 @@ struct Ipm {
 
             // r_g = H z + g + F' pi_{n+1} - [0; pi_n] - C' lam
             double rg = 0.0;
-            if (lane < NZ) {
+            if (absf) {
+                if (lane < NZ) rg = g;
+            } else if (lane < NZ) {
                 const int j = lane;
                 double acc = g;
 #pragma unroll
@@ -553,7 +560,9 @@ struct Ipm {
             }
             // r_b = F z + b - x_{n+1}
             double rb = 0.0;
-            if (n < N && lane < NX) {
+            if (absf) {
+                if (n < N && lane < NX) rb = b;
+            } else if (n < N && lane < NX) {
                 double acc = b;
 #pragma unroll
                 for (int k = 0; k < NZ; ++k) acc += s.F[lane + k * LDX] * s.z[k];
@@ -568,25 +577,33 @@ struct Ipm {
                 double e = 0.0, wsum = 0.0, rdl = 0.0, rdu = 0.0;
                 if (c < NC) {
                     if (m[t] != 0.0) {
-                        double gz;
-                        if (c < NZ) {
-                            gz = z;
+                        if (absf) {
+                            rdl = lo[t];
+                            rdu = -hi[t];
                         } else {
-                            const int r = c - NZ;
-                            gz = 0.0;
+                            double gz;
+                            if (c < NZ) {
+                                gz = z;
+                            } else {
+                                const int r = c - NZ;
+                                gz = 0.0;
 #pragma unroll
-                            for (int k = 0; k < NZ; ++k) gz += s.G[r + k * LDG] * s.z[k];
+                                for (int k = 0; k < NZ; ++k) gz += s.G[r + k * LDG] * s.z[k];
+                            }
+                            rdl = -gz + tl[t] + lo[t];
+                            rdu = gz + tu[t] - hi[t];
+                            md = nmax(md, nmax(fabs(rdl), fabs(rdu)));
                         }
-                        rdl = -gz + tl[t] + lo[t];
-                        rdu = gz + tu[t] - hi[t];
-                        md = nmax(md, nmax(fabs(rdl), fabs(rdu)));
                         const double a1 = ll[t] * tl[t], a2 = lu[t] * tu[t];
                         mm = nmax(mm, nmax(a1, a2));
                         slt += a1 + a2;
                         const double itl = rcp_nr(tl[t]), itu = rcp_nr(tu[t]);
                         const double wl = ll[t] * itl, wu = lu[t] * itu;
                         wsum = wl + wu;
-                        e = (wl * rdl - (ll[t] - shift * itl)) - (wu * rdu - (lu[t] - shift * itu));
+                        // r_m / t, with r_m = lam t - shift (delta) or -lam t - shift (absolute)
+                        const double ml = absf ? -ll[t] - shift * itl : ll[t] - shift * itl;
+                        const double mu_ = absf ? -lu[t] - shift * itu : lu[t] - shift * itu;
+                        e = (wl * rdl - ml) - (wu * rdu - mu_);
                     }
                     s.e[c] = e;
                     s.ws[c] = wsum;
@@ -705,9 +722,10 @@ struct Ipm {
     }
 
     // r_m (lower, upper) of a slot from the loaded values
-    __device__ __forceinline__ static void rm_value(int rmode, double shift, double ll, double lu, double tl,
-                                                    double tu, double a1, double a2, double a3, double a4,
-                                                    double& rml, double& rmu)
+    // (absolute formulation: r_m - 2 lam t, the right-hand side of the full-step iterate)
+    __device__ __forceinline__ void rm_value(int rmode, double shift, double ll, double lu, double tl, double tu,
+                                             double a1, double a2, double a3, double a4, double& rml,
+                                             double& rmu) const
     {
         if (rmode == RM_IR) {
             rml = a1;
@@ -719,6 +737,10 @@ struct Ipm {
         if (rmode == RM_CORRECTOR) {
             rml += a1 * a3;
             rmu += a2 * a4;
+        }
+        if (ABS) {
+            rml -= 2.0 * ll * tl;
+            rmu -= 2.0 * lu * tu;
         }
     }
 
@@ -824,6 +846,7 @@ struct Ipm {
         double L[EL], Lxx[EXr], F[EFr], G[EGr];
         const double *sLxx, *sF, *sG;
         double dinv, yu, rb, pn;
+        double zc, pic;  // current z_n, pi_{n+1} (absolute formulation: step = solution - iterate)
         double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
         double a1[NCT], a2[NCT], a3[NCT], a4[NCT];
     };
@@ -837,6 +860,8 @@ struct Ipm {
         p.dinv = lane < NU ? w[Lo.W_dinv + lane] : 0.0;
         p.yu = lane < NU ? w[Lo.W_yu + lane] : 0.0;
         p.rb = p.pn = 0.0;
+        p.zc = p.pic = 0.0;
+        if (ABS && lane < NZ) p.zc = ir[Lo.I_z + lane];
         if (n < N) {
             const double* w1 = Wp(n + 1);
             fetch_lxx(p.Lxx, w1 + Lo.W_L, p.sLxx);
@@ -844,6 +869,7 @@ struct Ipm {
             if (lane < NX) {
                 p.rb = w[ob + lane];
                 p.pn = w1[Lo.W_pv + lane];
+                if (ABS) p.pic = Ip(n + 1)[Lo.I_pi + lane];
             }
         }
         if constexpr (NG > 0) fetch<NG, NZ, EGr>(p.G, d + Lo.D_G, p.sG);
@@ -919,7 +945,7 @@ struct Ipm {
                 commit<NX, NZ, EFr>(s.F, LDX, p.F, p.sF);
             }
             if constexpr (NG > 0) commit<NG, NZ, EGr>(s.G, LDG, p.G, p.sG);
-            const double dv = p.dinv, yu = p.yu, rb = p.rb, pn = p.pn;
+            const double dv = p.dinv, yu = p.yu, rb = p.rb, pn = p.pn, zc = p.zc, pic = p.pic;
             double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
             double rml[NCT], rmu[NCT];
 #pragma unroll
@@ -955,7 +981,7 @@ struct Ipm {
             if (lane < NU) dz = -v;
             else if (lane < NZ) dz = s.xn[cur][lane - NU];
             if (lane < NZ) s.z[lane] = dz;
-            o.dz = dz;
+            o.dz = ABS ? dz - zc : dz;
             wsync();
             o.dpi = 0.0;
             if (n < N) {
@@ -978,7 +1004,7 @@ struct Ipm {
                     TS acc = (TS)pn;
 #pragma unroll
                     for (int l = 0; l < NX; ++l) acc += (TS)Lx[lane + l * LDX] * (TS)s.t1[l];
-                    o.dpi = (double)acc;
+                    o.dpi = ABS ? (double)acc - pic : (double)acc;
                 }
             }
             // constraint steps, step length, duality-measure sums
@@ -1000,6 +1026,14 @@ struct Ipm {
                     dtu = -gdz - rdu[t];
                     dll = -(rml[t] + ll[t] * dtl) * rcp_nr(tl[t]);
                     dlu = -(rmu[t] + lu[t] * dtu) * rcp_nr(tu[t]);
+                    if (ABS) {
+                        // absolute formulation: the step is the full-step
+                        // iterate minus the current one (eq:alg:pdipm:step)
+                        dtl -= tl[t];
+                        dtu -= tu[t];
+                        dll -= ll[t];
+                        dlu -= lu[t];
+                    }
                     // step to the boundary; approximate reciprocals suffice for a
                     // length that is scaled by gamma < 1 afterwards
                     if (dll < 0.0) amin = fmin(amin, -ll[t] * __builtin_amdgcn_rcp(dll));
@@ -1334,6 +1368,7 @@ struct Ipm {
     __device__ __forceinline__ void run(DevStat* st, double* step_out, int fell_back) const
     {
         const bool newton_mode = P.mode == KMODE_NEWTON;
+        const bool absf = ABS;
         if (!newton_mode) init();
         int status = ST_MAX_ITER, k = 0;
         double ng = 0, nb = 0, nd = 0, nm = 0, mu = 0.0, slt = 0.0;
@@ -1342,21 +1377,52 @@ struct Ipm {
         bool upd = false, rejected = false;
         double alpha = 0.0;
         int ir_steps = 0;
+        // absolute formulation: once the loop ends, one more pass A (delta
+        // form, no update, no factorization) evaluates the residuals at the
+        // returned iterate; it reuses the single call site of pass A
+        bool final_pass = false;
+        int k_exit = 0;
         for (k = 0;; ++k) {
             // residuals at the (updated) iterate; factorization unless the
             // last step was rejected as too short
-            const bool fact_ok = passA(upd, alpha, shift0, !rejected, ng, nb, nd, nm, slt);
+            const bool fact_ok =
+                passA(upd, alpha, shift0, !rejected && !final_pass, absf && !final_pass, ng, nb, nd, nm, slt);
             __syncthreads();
             mu = slt * inv2nc;
+            if (final_pass) {
+                k = k_exit;
+                if (ng != ng || nb != nb || nd != nd || nm != nm) status = ST_NAN;
+                break;
+            }
             if (rejected) {
                 status = ST_MIN_STEP;
+                if (absf) {
+                    final_pass = true;
+                    k_exit = k;
+                    upd = false;
+                    continue;
+                }
                 break;
             }
             if (MIXED && !newton_mode && !fact_ok) {
                 status = ST_FALLBACK;  // FP32 factorization broke down
                 break;
             }
-            if (!newton_mode) {
+            if (!newton_mode && absf) {
+                // absolute formulation (mode speed_abs): exit on the duality
+                // measure alone
+                if (mu != mu) {
+                    status = ST_NAN;
+                    break;
+                }
+                if (mu <= P.tol_comp || k >= P.iter_max) {
+                    status = mu <= P.tol_comp ? ST_SUCCESS : ST_MAX_ITER;
+                    final_pass = true;
+                    k_exit = k;
+                    upd = false;
+                    continue;
+                }
+            } else if (!newton_mode) {
                 if (ng != ng || nb != nb || nd != nd || nm != nm || mu != mu) {
                     status = ST_NAN;
                     break;
@@ -1440,13 +1506,13 @@ struct Ipm {
 // whole register file (256 VGPRs + 256 AGPRs) of one wave instead of spilling.
 __host__ __device__ constexpr int ipm_max_waves(int nz, bool mixed) { return (nz > 24 || (mixed && nz > 16)) ? 1 : 2; }
 
-template <int NX, int NU, int NG, bool MIXED>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, ipm_max_waves(NX + NU, MIXED)))) void ipm_kernel(const InstDesc* __restrict__ desc, int count,
+template <int NX, int NU, int NG, int KM>
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, ipm_max_waves(NX + NU, KM == KM_MIXED)))) void ipm_kernel(const InstDesc* __restrict__ desc, int count,
                                                     const double* __restrict__ data, double* __restrict__ iter,
                                                     double* __restrict__ work, double* __restrict__ step_out,
                                                     DevStat* __restrict__ stat, KParams P)
 {
-    using S = Ipm<NX, NU, NG, MIXED>;
+    using S = Ipm<NX, NU, NG, KM>;
     const int b = blockIdx.x;
     if (b >= count) return;
     const InstDesc ds = desc[b];
@@ -1460,11 +1526,11 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, ipm_max
     ipm.run(stat + ds.index, step_out + ds.iter, fell_back);
 }
 
-template <int NX, int NU, int NG, bool MIXED>
+template <int NX, int NU, int NG, int KM>
 void launch_ipm(const InstDesc* desc, int count, const double* data, double* iter, double* work, double* step,
                 DevStat* stat, KParams P, hipStream_t stream)
 {
-    hipLaunchKernelGGL((ipm_kernel<NX, NU, NG, MIXED>), dim3(count), dim3(WAVE), 0, stream, desc, count, data, iter,
+    hipLaunchKernelGGL((ipm_kernel<NX, NU, NG, KM>), dim3(count), dim3(WAVE), 0, stream, desc, count, data, iter,
                        work, step, stat, P);
 }
 

@@ -20,7 +20,7 @@
 
 namespace oqp {
 
-template <int NX, int NU, int NG, bool MIXED>
+template <int NX, int NU, int NG, int KM>
 void launch_ipm(const InstDesc* desc, int count, const double* data, double* iter, double* work, double* step,
                 DevStat* stat, KParams P, hipStream_t stream);
 
@@ -28,7 +28,7 @@ void launch_ipm(const InstDesc* desc, int count, const double* data, double* ite
 int block_lds_bytes(int nx, int nu, int ng);
 int block_zmax(int nz);  // compile-time bound used for a stage block of nz (0: too large)
 // general rows: kernels for ng == 0 and for 0 < ng <= 64
-int block_launch(int zm, int gm, int mixed, const InstDesc* desc, int count, const double* data, double* iter,
+int block_launch(int zm, int gm, int km, const InstDesc* desc, int count, const double* data, double* iter,
                  double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
 
 }  // namespace oqp

@@ -3,23 +3,24 @@
 
 namespace oqp {
 
-#define OQP_EXTERN(x, u, g)                                                                                           \
-    extern template void launch_ipm<x, u, g, false>(const InstDesc*, int, const double*, double*, double*, double*, \
-                                                    DevStat*, KParams, hipStream_t);                                 \
-    extern template void launch_ipm<x, u, g, true>(const InstDesc*, int, const double*, double*, double*, double*,  \
-                                                   DevStat*, KParams, hipStream_t);
+#define OQP_EXTERN1(x, u, g, km)                                                                                     \
+    extern template void launch_ipm<x, u, g, km>(const InstDesc*, int, const double*, double*, double*, double*,    \
+                                                 DevStat*, KParams, hipStream_t);
+#define OQP_EXTERN(x, u, g) OQP_EXTERN1(x, u, g, KM_F64) OQP_EXTERN1(x, u, g, KM_MIXED) OQP_EXTERN1(x, u, g, KM_ABS)
 OQP_VARIANTS(OQP_EXTERN)
 #undef OQP_EXTERN
+#undef OQP_EXTERN1
 
 typedef void (*launch_fn)(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams,
                           hipStream_t);
 
 struct Variant {
     int NX, NU, NG;
-    launch_fn fn[2];  // FP64 path, mixed path
+    launch_fn fn[3];  // indexed by kernel build (KM_F64, KM_MIXED, KM_ABS)
 };
 
-#define OQP_ENTRY(x, u, g) {x, u, g, {&launch_ipm<x, u, g, false>, &launch_ipm<x, u, g, true>}},
+#define OQP_ENTRY(x, u, g) \
+    {x, u, g, {&launch_ipm<x, u, g, KM_F64>, &launch_ipm<x, u, g, KM_MIXED>, &launch_ipm<x, u, g, KM_ABS>}},
 static const Variant kVariants[] = {OQP_VARIANTS(OQP_ENTRY)};
 #undef OQP_ENTRY
 
@@ -32,11 +33,12 @@ void variant_dims(int v, int* nx, int* nu, int* ng)
     *ng = kVariants[v].NG;
 }
 
-int variant_launch(int v, int mixed, const InstDesc* desc, int count, const double* data, double* iter, double* work,
+int variant_launch(int v, int km, const InstDesc* desc, int count, const double* data, double* iter, double* work,
                    double* step, DevStat* stat, const KParams& P, void* stream)
 {
     if (count <= 0) return 0;
-    kVariants[v].fn[mixed ? 1 : 0](desc, count, data, iter, work, step, stat, P, (hipStream_t)stream);
+    if (km < KM_F64 || km > KM_ABS) return -1;
+    kVariants[v].fn[km](desc, count, data, iter, work, step, stat, P, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -3,8 +3,8 @@
 #include "ipm_kernel.h"
 
 namespace oqp {
-template void launch_ipm<16, 4, 0, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
-template void launch_ipm<16, 4, 0, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
-template void launch_ipm<4, 4, 4, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
-template void launch_ipm<4, 4, 4, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<16, 4, 0, KM_F64>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<16, 4, 0, KM_MIXED>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<4, 4, 4, KM_F64>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<4, 4, 4, KM_MIXED>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
 }  // namespace oqp

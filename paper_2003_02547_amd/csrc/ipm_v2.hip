@@ -3,6 +3,6 @@
 #include "ipm_kernel.h"
 
 namespace oqp {
-template void launch_ipm<8, 16, 0, false>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
-template void launch_ipm<8, 16, 0, true>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<8, 16, 0, KM_F64>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
+template void launch_ipm<8, 16, 0, KM_MIXED>(const InstDesc*, int, const double*, double*, double*, double*, DevStat*, KParams, hipStream_t);
 }  // namespace oqp

@@ -272,13 +272,13 @@ int launch_group(oqp_server* s, int v, int gi, int k)
     g.next = -1;
     hipError_t e = hipMemcpyAsync(g.ddesc, g.hdesc, sizeof(InstDesc) * cnt, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "server: descriptor upload: %s", hipGetErrorString(e));
-    const int mixed = s->arg.mode == OQP_MODE_MIXED;
+    const int km = kernel_build(s->arg.mode);
     oqp::KParams P = make_params(s->arg, oqp::KMODE_SOLVE, 0.0);
-    if (group_launch(v, mixed, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
+    if (group_launch(v, km, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
         return fail(OQP_EDEVICE, "server: kernel launch failed for group %d", v);
-    if (mixed) {
+    if (km == oqp::KM_MIXED) {
         P.mode = oqp::KMODE_FALLBACK;
-        if (group_launch(v, 0, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
+        if (group_launch(v, oqp::KM_F64, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
             return fail(OQP_EDEVICE, "server: fallback launch failed for group %d", v);
     }
     e = hipMemcpyAsync(g.hstat, g.dstat, sizeof(DevStat) * cnt, hipMemcpyDeviceToHost, st);
