@@ -11,6 +11,7 @@ Further legs on the same line (context, not the headline):
   * pcond: the same batch solved through partial condensing to a shorter
     horizon (condensing and expansion inside the timed solve);
   * abs: the same batch in the absolute formulation (mode speed_abs);
+  * robust: the same batch with the QR-based factorization (mode robust);
   * warm: the next receding-horizon problem of every solved instance, cold
     and warm-started from the shifted solution;
   * uneven: a batch of random stable OCP QPs with nx ~ U{4..48},
@@ -243,6 +244,30 @@ def leg_abs(B, torch, np, qps, steps):
             "kkt_res_p50": float(np.median(res)) if res.size else None, "tol_comp_on_mu": 1e-8}
 
 
+def leg_robust(B, torch, np, qps, steps):
+    """The headline batch with the QR-based factorization (mode robust):
+    same iterations as the Cholesky path, factors from an array algorithm."""
+    b = B.Batch(qps, B.default_arg(B.MODE_ROBUST)).load().sync()
+    b.solve()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(steps):
+        s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s_.record(b.stream)
+        b.solve()
+        e_.record(b.stream)
+        torch.cuda.synchronize()
+        ms.append(s_.elapsed_time(e_))
+    b.fetch().sync()
+    stats = [b.stat(i) for i in range(len(qps))]
+    ok = sum(1 for x in stats if x.status == B.SUCCESS and max(x.res[:]) <= KKT_OK)
+    iters = np.array([x.iters for x in stats])
+    med = float(np.median(ms))
+    del b
+    return {"value": round(ok / (med * 1e-3), 1), "unit": "solves/s", "ms_per_step": round(med, 3), "solves_ok": ok,
+            "iters_p50": float(np.percentile(iters, 50)), "iters_max": int(iters.max())}
+
+
 def leg_single(B, W, torch, np, reps):
     """Latency of one 4-mass QP (nx = 8, nu = 3, N = 10, dt = 0.5; seed 1) in
     a batch of one: one launch, FP64 to 1e-8, median over reps (the CPU
@@ -354,6 +379,7 @@ def main():
     ap.add_argument("--pcond-steps", type=int, default=5)
     ap.add_argument("--warm-steps", type=int, default=5, help="timed solves of the warm-start leg (0: skip)")
     ap.add_argument("--abs-steps", type=int, default=5, help="timed solves of the absolute-formulation leg (0: skip)")
+    ap.add_argument("--robust-steps", type=int, default=5, help="timed solves of the QR-factorization leg (0: skip)")
     ap.add_argument("--large", type=int, default=256, help="instances of the large-stage leg (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2)
     ap.add_argument("--serve-pool", type=int, default=256, help="distinct instances in the serving pool (0: skip)")
@@ -479,6 +505,9 @@ def main():
         n2s = [int(x) for x in args.pcond.split(",") if x]
         log(f"bench: partial condensing leg, N2 in {n2s}")
         line["pcond"] = leg_pcond(B, W, torch, np, qps, n2s, args.pcond_steps)
+    if args.robust_steps > 0:
+        log("bench: QR-based factorization (robust mode) leg")
+        line["robust"] = leg_robust(B, torch, np, qps, args.robust_steps)
     if args.abs_steps > 0:
         log("bench: absolute-formulation leg")
         line["abs"] = leg_abs(B, torch, np, qps, args.abs_steps)

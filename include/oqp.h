@@ -63,6 +63,10 @@ extern "C" {
                             right-hand sides from the data, no residuals in the loop, exit when the
                             duality measure mu <= tol_comp (or on the iteration limit or a too-short
                             step); stat.res holds the residual norms of the returned point */
+#define OQP_MODE_ROBUST 3 /* FP64, delta formulation, Riccati factors from an array algorithm (QR of
+                             [chol(Phi)'; U]) instead of the Cholesky factor of the normal matrix
+                             Phi + U'U (mode "robust" of Section 4.2); batch only, for stage blocks
+                             covered by a one-wave variant (nx + nu up to 24 after padding) */
 
 typedef struct oqp_dims oqp_dims;
 typedef struct oqp_qp oqp_qp;

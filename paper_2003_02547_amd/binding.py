@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "liboqp.so")
 OK, PENDING = 0, 1
 EINVAL, ENOMEM, EDEVICE, EBUSY, ESTATE = -1, -2, -3, -4, -5
 SUCCESS, MAX_ITER, MIN_STEP, NAN = 0, 1, 2, 3
-MODE_F64, MODE_MIXED, MODE_ABS = 0, 1, 2
+MODE_F64, MODE_MIXED, MODE_ABS, MODE_ROBUST = 0, 1, 2, 3
 
 _P = ct.POINTER(ct.c_double)
 _PI = ct.POINTER(ct.c_int)

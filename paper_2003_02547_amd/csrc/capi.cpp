@@ -369,7 +369,7 @@ extern "C" void oqp_arg_default(oqp_arg* a, int mode)
 {
     if (!a) return;
     std::memset(a, 0, sizeof(*a));
-    a->mode = (mode == OQP_MODE_MIXED || mode == OQP_MODE_ABS) ? mode : OQP_MODE_F64;
+    a->mode = (mode == OQP_MODE_MIXED || mode == OQP_MODE_ABS || mode == OQP_MODE_ROBUST) ? mode : OQP_MODE_F64;
     const double tol = a->mode == OQP_MODE_MIXED ? 1e-6 : 1e-8;
     a->tol_stat = a->tol_eq = a->tol_ineq = a->tol_comp = tol;
     a->iter_max = 100;
@@ -388,7 +388,7 @@ extern "C" void oqp_arg_default(oqp_arg* a, int mode)
 int check_arg(const oqp_arg* a)
 {
     if (!a) return fail(OQP_EINVAL, "NULL oqp_arg");
-    if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED && a->mode != OQP_MODE_ABS)
+    if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED && a->mode != OQP_MODE_ABS && a->mode != OQP_MODE_ROBUST)
         return fail(OQP_EINVAL, "unknown mode %d", a->mode);
     if (a->iter_max < 0 || !(a->gamma > 0.0 && a->gamma <= 1.0) || a->warm_start < 0 || a->warm_start > 2 ||
         a->ir_max < 0 || a->cond_N < 0 || (a->warm_start != 0 && a->cond_N != 0))
@@ -621,11 +621,29 @@ struct SolveShape {
 
 static constexpr size_t kMaxCondLds = 64 * 1024;
 
-static int solve_shape(const oqp_dims* d, int cond_N, SolveShape* sh, int i)
+// Kernel for the largest stage sizes under a solver mode: the QR-based
+// factorization is built for the one-wave variants only, which then cover
+// the instance whatever the one-wave bound.
+static int select_for_mode(int mx, int mu, int mg, int mode, KSel* out)
+{
+    if (mode != OQP_MODE_ROBUST) return select_kernel_max(mx, mu, mg, out);
+    const int v = pick_variant_max(mx, mu, mg);
+    if (v < 0) return -1;
+    int nx, nu, ng;
+    oqp::variant_dims(v, &nx, &nu, &ng);
+    *out = KSel{v, nx, nu, ng};
+    return OQP_OK;
+}
+
+static int solve_shape(const oqp_dims* d, int cond_N, int mode, SolveShape* sh, int i)
 {
     if (cond_N <= 0) {
         sh->N = d->N;
-        if (select_kernel(d, &sh->ks)) return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d", i);
+        int mx, mu, mg;
+        dims_max(d, &mx, &mu, &mg);
+        if (select_for_mode(mx, mu, mg, mode, &sh->ks))
+            return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d%s", i,
+                        mode == OQP_MODE_ROBUST ? " (robust mode: one-wave variants only)" : "");
         sh->onx = sh->ks.nx;
         sh->onu = sh->ks.nu;
         sh->ong = sh->ks.ng;
@@ -641,7 +659,7 @@ static int solve_shape(const oqp_dims* d, int cond_N, SolveShape* sh, int i)
         if (c.ng > cg) cg = c.ng;
     }
     sh->N = N2;
-    if (select_kernel_max(cx, cu, cg, &sh->ks))
+    if (select_for_mode(cx, cu, cg, mode, &sh->ks))
         return fail(OQP_EINVAL, "batch: no kernel covers the condensed stage sizes of instance %d (nx %d, nu %d, ng %d)",
                     i, cx, cu, cg);
     if ((size_t)oqp::cond_lds_bytes(sh->onx, sh->onu, sh->ks.nx + sh->ks.nu) > kMaxCondLds)
@@ -693,8 +711,9 @@ struct Plan {
     size_t cond_lds;
 };
 
-static int make_plan(const oqp_dims* const* dims, int count, int cond_N, Plan* pl)
+static int make_plan(const oqp_dims* const* dims, int count, const oqp_arg* arg, Plan* pl)
 {
+    const int cond_N = arg->cond_N;
     if (!dims || count < 1) return fail(OQP_EINVAL, "batch: count must be >= 1");
     const int nv = group_count();
     const int cond = cond_N > 0;
@@ -705,7 +724,7 @@ static int make_plan(const oqp_dims* const* dims, int count, int cond_N, Plan* p
         const oqp_dims* d = dims[i];
         if (!d) return fail(OQP_EINVAL, "batch: dims[%d] is NULL", i);
         SolveShape sh;
-        int rc = solve_shape(d, cond_N, &sh, i);
+        int rc = solve_shape(d, cond_N, arg->mode, &sh, i);
         if (rc) return rc;
         const Layout L = oqp::make_layout(sh.ks.nx, sh.ks.nu, sh.ks.ng);
         nd += (int64_t)(sh.N + 1) * L.SREC;
@@ -768,7 +787,7 @@ extern "C" int oqp_batch_bytes(const oqp_dims* const* dims, int count, const oqp
     int rc = check_arg(arg);
     if (rc) return rc;
     Plan pl;
-    rc = make_plan(dims, count, arg->cond_N, &pl);
+    rc = make_plan(dims, count, arg, &pl);
     if (rc) return rc;
     if (host_bytes) *host_bytes = pl.host_bytes;
     if (dev_bytes) *dev_bytes = pl.dev_bytes;
@@ -788,7 +807,7 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
     if ((uintptr_t)host_mem % 16) return fail(OQP_EINVAL, "oqp_batch_init: host memory not 16-byte aligned");
     if ((uintptr_t)dev_mem % 256) return fail(OQP_EINVAL, "oqp_batch_init: device memory not 256-byte aligned");
     Plan pl;
-    rc = make_plan(dims, count, arg->cond_N, &pl);
+    rc = make_plan(dims, count, arg, &pl);
     if (rc) return rc;
     if (host_bytes < pl.host_bytes) return fail(OQP_ENOMEM, "oqp_batch_init: host %zu < %zu", host_bytes, pl.host_bytes);
     if (dev_bytes < pl.dev_bytes) return fail(OQP_ENOMEM, "oqp_batch_init: device %zu < %zu", dev_bytes, pl.dev_bytes);
@@ -841,7 +860,7 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
         Inst& in = b->inst[i];
         const oqp_dims* d = dims[i];
         SolveShape sh;
-        solve_shape(d, arg->cond_N, &sh, i);
+        solve_shape(d, arg->cond_N, arg->mode, &sh, i);
         const KSel& ks = sh.ks;
         in.variant = ks.group;
         in.nx = ks.nx;
@@ -1117,7 +1136,10 @@ oqp::KParams make_params(const oqp_arg& a, int mode, double tau)
 
 int kernel_build(int mode)
 {
-    return mode == OQP_MODE_MIXED ? oqp::KM_MIXED : (mode == OQP_MODE_ABS ? oqp::KM_ABS : oqp::KM_F64);
+    if (mode == OQP_MODE_MIXED) return oqp::KM_MIXED;
+    if (mode == OQP_MODE_ABS) return oqp::KM_ABS;
+    if (mode == OQP_MODE_ROBUST) return oqp::KM_ROBUST;
+    return oqp::KM_F64;
 }
 
 // Stream of kernel group v: the first non-empty group (in launch order) on

@@ -30,7 +30,9 @@ int block_launch(int zm, int gm, int km, const InstDesc* desc, int count, const 
                                                                   lds_bytes, s);                                    \
         if (km == KM_ABS) return launch_block_t<KM_ABS, Z, G>(desc, count, data, iter, work, step, stat, P,       \
                                                               lds_bytes, s);                                        \
-        return launch_block_t<KM_F64, Z, G>(desc, count, data, iter, work, step, stat, P, lds_bytes, s);          \
+        if (km == KM_F64) return launch_block_t<KM_F64, Z, G>(desc, count, data, iter, work, step, stat, P,       \
+                                                              lds_bytes, s);                                        \
+        return -1; /* the QR-based factorization is built for the one-wave kernels only */                         \
     }
     OQP_BLK(32, 0)
     OQP_BLK(32, 64)

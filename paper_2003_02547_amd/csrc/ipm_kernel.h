@@ -49,6 +49,9 @@ template <int NX, int NU, int NG, int KM>
 struct Ipm {
     static constexpr bool MIXED = KM == KM_MIXED;
     static constexpr bool ABS = KM == KM_ABS;  // absolute formulation (Section 3.2)
+    // factorization by an array algorithm (QR) instead of the Cholesky factor
+    // of the normal matrix (Section 4.2, mode robust)
+    static constexpr bool ROBUST = KM == KM_ROBUST;
     // arithmetic type of the factorization and of the right-hand-side sweeps
     // (FP32 in the mixed path; pivots, residuals and refinement stay FP64)
     using TS = typename std::conditional<MIXED, float, double>::type;
@@ -77,6 +80,7 @@ struct Ipm {
     static constexpr int TZ = NZP / 8;                           // register tile extents
     static constexpr int TX = NXP / 8;
     static_assert(NZ <= WAVE && NG <= WAVE, "stage block must fit one wave");
+    static_assert(NV < WAVE, "reflector broadcast buffer");
 
     struct Smem {
         double M[LDZ * NZP];      // stage matrix / factor (column-major)
@@ -331,6 +335,61 @@ struct Ipm {
             }
         }
         return ok;
+    }
+
+    // Array-algorithm factorization (Section 4.2, mode robust): with R_0 the
+    // upper Cholesky factor of Phi (R_0' = the factor in rowL) and V = [U;
+    // sqrt(w) G] (rows r0.. of s.V), the upper triangular R of the QR
+    // decomposition of [R_0; V] satisfies R'R = Phi + V'V = M, so L = R'
+    // without forming the normal matrix V'V.  Householder reflections, one
+    // per column; lane k holds column k of [R; V]: R(j, k) = rowL[j] (j <= k,
+    // the layout of a row of L) and V(:, k) in registers.  Reflector of
+    // column j: beta = |[a; x]|, v0 = a - beta (in the cancellation-free form
+    // -|x|^2 / (a + beta) for a > 0), u = [1; x / v0], tau = 2 v0^2 / (|x|^2 +
+    // v0^2); beta > 0 keeps the diagonal of R positive.  On return rowL, dinv
+    // hold the factor of M as the Cholesky routine leaves it.
+    __device__ __forceinline__ void qr_update(double (&rowL)[NZ], double& dinv, int r0) const
+    {
+        Smem& s = S();
+        double vr[NV];
+#pragma unroll
+        for (int r = 0; r < NV; ++r) vr[r] = (lane < NZ && r >= r0) ? s.V[r + lane * LDV] : 0.0;
+        wsync();
+#pragma unroll
+        for (int j = 0; j < NZ; ++j) {
+            if (lane == j) {
+                const double a = rowL[j];
+                double sg = 0.0;
+#pragma unroll
+                for (int r = 0; r < NV; ++r) sg += vr[r] * vr[r];
+                const double beta = sqrt(a * a + sg);
+                const double v0 = a <= 0.0 ? a - beta : -sg / (a + beta);
+                const double tau = sg == 0.0 ? 0.0 : 2.0 * v0 * v0 / (sg + v0 * v0);
+                const double iv0 = sg == 0.0 ? 0.0 : 1.0 / v0;
+#pragma unroll
+                for (int r = 0; r < NV; ++r) s.col[r] = vr[r] * iv0;
+                s.col[NV] = tau;
+                rowL[j] = beta;
+#pragma unroll
+                for (int r = 0; r < NV; ++r) vr[r] = 0.0;
+            }
+            wsync();
+            if (lane > j && lane < NZ) {
+                const double tau = s.col[NV];
+                double sd = rowL[j];
+#pragma unroll
+                for (int r = 0; r < NV; ++r) sd += s.col[r] * vr[r];
+                const double ts = tau * sd;
+                rowL[j] -= ts;
+#pragma unroll
+                for (int r = 0; r < NV; ++r) vr[r] -= ts * s.col[r];
+            }
+            wsync();
+        }
+        dinv = 0.0;
+#pragma unroll
+        for (int j = 0; j < NZ; ++j)
+            if (lane == j) dinv = 1.0 / rowL[j];
     }
 
     // Forward substitution with the (u, u) block, fused with the x rows:
@@ -642,12 +701,18 @@ struct Ipm {
                 }
                 if (n < N) trmm_LtF(s.Lx[nxt]);
                 wsync();
-                if (n < N || NG > 0) syrk_VtV(n < N ? 0 : NX);
-                wsync();
+                if constexpr (!ROBUST) {
+                    if (n < N || NG > 0) syrk_VtV(n < N ? 0 : NX);
+                    wsync();
+                }
 
                 double rowL[NZ];
                 double dinv;
                 fact_ok = cholesky(rowL, dinv) && fact_ok;
+                if constexpr (ROBUST) {
+                    // M = Phi + V'V factored without forming V'V
+                    if (n < N || NG > 0) qr_update(rowL, dinv, n < N ? 0 : NX);
+                }
                 if (lane < NZ) {
 #pragma unroll
                     for (int k = 0; k < NZ; ++k) s.Lst[lane + k * LDZ] = (k <= lane) ? rowL[k] : 0.0;

@@ -164,8 +164,9 @@ struct KParams {
 
 enum { KMODE_SOLVE = 0, KMODE_NEWTON = 1, KMODE_FALLBACK = 2 };
 // Compiled kernel builds: FP64 delta formulation, mixed (FP32 factorization
-// and sweeps, FP64 refinement), FP64 absolute formulation.
-enum { KM_F64 = 0, KM_MIXED = 1, KM_ABS = 2 };
+// and sweeps, FP64 refinement), FP64 absolute formulation, FP64 with the
+// QR-based (array algorithm) factorization.
+enum { KM_F64 = 0, KM_MIXED = 1, KM_ABS = 2, KM_ROBUST = 3 };
 enum { ST_SUCCESS = 0, ST_MAX_ITER = 1, ST_MIN_STEP = 2, ST_NAN = 3, ST_FALLBACK = 4 };
 
 }  // namespace oqp

@@ -402,8 +402,8 @@ extern "C" int oqp_server_init(const oqp_server_cfg* cfg, const oqp_arg* arg, vo
     if (rc) return rc;
     rc = check_arg(arg);
     if (rc) return rc;
-    if (arg->cond_N != 0 || arg->warm_start != 0)
-        return fail(OQP_EINVAL, "oqp_server_init: partial condensing and warm start are batch options");
+    if (arg->cond_N != 0 || arg->warm_start != 0 || arg->mode == OQP_MODE_ROBUST)
+        return fail(OQP_EINVAL, "oqp_server_init: partial condensing, warm start and robust mode are batch options");
     if (!host_mem || !dev_mem || !streams || !out) return fail(OQP_EINVAL, "oqp_server_init: NULL argument");
     if (nstreams < 2 || nstreams > OQP_SERVER_MAX_STREAMS)
         return fail(OQP_EINVAL, "oqp_server_init: need 2..%d streams", OQP_SERVER_MAX_STREAMS);

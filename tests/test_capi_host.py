@@ -106,6 +106,17 @@ def test_batch_size_and_plan_errors():
     assert L.oqp_batch_bytes(arr, 3, ct.byref(bad), ct.byref(hb), ct.byref(db)) == B.EINVAL
     ok = B.default_arg(warm_start=2)
     assert L.oqp_batch_bytes(arr, 3, ct.byref(ok), ct.byref(hb), ct.byref(db)) == B.OK
+    # robust mode: the QR-based factorization is built for the one-wave variants
+    rob = B.default_arg(B.MODE_ROBUST)
+    assert L.oqp_batch_bytes(arr, 3, ct.byref(rob), ct.byref(hb), ct.byref(db)) == B.OK
+    big = B.Dims(2, [40] * 3, [8, 8, 0], [0, 0, 0], [0, 0, 0], [0, 0, 0])
+    arr1 = (ct.c_void_p * 1)(big.h)
+    assert L.oqp_batch_bytes(arr1, 1, ct.byref(B.default_arg()), ct.byref(hb), ct.byref(db)) == B.OK
+    assert L.oqp_batch_bytes(arr1, 1, ct.byref(rob), ct.byref(hb), ct.byref(db)) == B.EINVAL
+    assert b"robust" in L.oqp_last_error()
+    unknown = B.default_arg()
+    unknown.mode = 4
+    assert L.oqp_batch_bytes(arr, 3, ct.byref(unknown), ct.byref(hb), ct.byref(db)) == B.EINVAL
     assert L.oqp_batch_bytes(arr, 0, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.EINVAL
 
 
