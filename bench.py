@@ -375,11 +375,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uneven", type=int, default=4096, help="instances of the uneven leg (0: skip)")
     ap.add_argument("--uneven-steps", type=int, default=3)
-    ap.add_argument("--pcond", default="5,10,15", help="condensed horizons for the partial-condensing leg ('': skip)")
+    ap.add_argument("--pcond", default="5,10,15", help="condensed horizons for the partial-condensing leg (0: skip)")
     ap.add_argument("--pcond-steps", type=int, default=5)
     ap.add_argument("--warm-steps", type=int, default=5, help="timed solves of the warm-start leg (0: skip)")
     ap.add_argument("--abs-steps", type=int, default=5, help="timed solves of the absolute-formulation leg (0: skip)")
     ap.add_argument("--robust-steps", type=int, default=5, help="timed solves of the QR-factorization leg (0: skip)")
+    ap.add_argument("--iter20-steps", type=int, default=5, help="timed solves of the iter_max 20 context line (0: skip)")
     ap.add_argument("--large", type=int, default=256, help="instances of the large-stage leg (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2)
     ap.add_argument("--serve-pool", type=int, default=256, help="distinct instances in the serving pool (0: skip)")
@@ -458,8 +459,10 @@ def main():
     f = time_path(B.MODE_F64, args.steps, args.warmup)
     log(f"bench: mixed path, warmup {args.warmup}, {args.steps} steps")
     m = time_path(B.MODE_MIXED, args.steps, args.warmup)
-    log("bench: FP64 path with iter_max 20 (context: the batch time follows its slowest instance)")
-    f20 = time_path(B.MODE_F64, max(3, args.steps // 2), 1, iter_max=20)
+    f20 = None
+    if args.iter20_steps > 0:
+        log("bench: FP64 path with iter_max 20 (context: the batch time follows its slowest instance)")
+        f20 = time_path(B.MODE_F64, args.iter20_steps, 1, iter_max=20)
     vkey = "ipm_kernel<%d,%d,%d>" % f["variant"]
     traffic = traffic_from_profile(vkey, 1)
     okmask = f["status"] == B.SUCCESS
@@ -497,12 +500,14 @@ def main():
                   "max_kkt_res": float(np.max(m["kkt"][m["status"] == B.SUCCESS])),
                   "vs_f64": round(m["value"] / f["value"], 3)},
     }
-    line["iter_max_20"] = {"value": round(f20["value"], 1), "unit": "solves/s",
-                           "ms_per_step": round(1e3 * f20["wall"] / f20["steps"], 4), "solves_ok": f20["ok"],
-                           "iters_max": int(np.max(f20["iters"]))}
-    del f["del_batch"], m["del_batch"], f20["del_batch"]
-    if args.pcond:
-        n2s = [int(x) for x in args.pcond.split(",") if x]
+    if f20 is not None:
+        line["iter_max_20"] = {"value": round(f20["value"], 1), "unit": "solves/s",
+                               "ms_per_step": round(1e3 * f20["wall"] / f20["steps"], 4), "solves_ok": f20["ok"],
+                               "iters_max": int(np.max(f20["iters"]))}
+        del f20["del_batch"]
+    del f["del_batch"], m["del_batch"]
+    n2s = [int(x) for x in args.pcond.split(",") if x.strip() and int(x) > 0]
+    if n2s:
         log(f"bench: partial condensing leg, N2 in {n2s}")
         line["pcond"] = leg_pcond(B, W, torch, np, qps, n2s, args.pcond_steps)
     if args.robust_steps > 0:
