@@ -45,6 +45,14 @@ typedef struct {
     const int *idxbu, *idxbx;            /* concatenated index lists */
     const double *lbu, *ubu, *lbx, *ubx;
     const double *D, *C, *lg, *ug;       /* D: ng x nu, C: ng x nx, col-major */
+    /* Soft constraints (Section 2.2, the slack variables): stage n has ns[n]
+     * slacks; slack j relaxes row idxs[j] of the stage's rows [box u, box x,
+     * general] on both sides (lower row + s^l, upper row - s^u), with
+     * diagonal Hessians Zl, Zu, gradients zl, zu and lower bounds lls, lus
+     * (s^l >= lls, s^u >= lus).  ns == NULL: no slacks. */
+    const int *ns;
+    const int *idxs;
+    const double *Zl, *Zu, *zl, *zu, *lls, *lus;
 } orc_qp;
 
 typedef struct {
@@ -60,6 +68,9 @@ typedef struct {
  * [box u, box x, general] (sum over n of nbu+nbx+ng). */
 typedef struct {
     double *u, *x, *pi, *lam_l, *lam_u, *t_l, *t_u;
+    /* slacks s^l, s^u and the multipliers and slacks of their lower bounds
+     * (sum over n of ns); may be NULL when the problem has no slacks */
+    double *s_l, *s_u, *lam_sl, *lam_su, *t_sl, *t_su;
 } orc_vec;
 
 enum { ORC_SUCCESS = 0, ORC_MAX_ITER = 1, ORC_MIN_STEP = 2, ORC_NAN = 3, ORC_EINVAL = -1, ORC_ENOMEM = -2 };
@@ -76,13 +87,17 @@ typedef struct {
     double *bb;                 /* nxn */
     double *G;                  /* nc x nz: rows [J^{b,u} 0; 0 J^{b,x}; D C] */
     double *lo, *hi;            /* nc */
+    int ns;                     /* slacks of the stage */
+    int *srow;                  /* nc: slack of row k, -1 for a hard row */
+    double *Zl, *Zu, *zl, *zu, *lls, *lus; /* ns */
 } stage_t;
 
 typedef struct {
     int N;
     stage_t *st;
-    int *zoff, *poff, *coff, *uoff, *xoff;
+    int *zoff, *poff, *coff, *uoff, *xoff, *soff;
     int nv, neq, ncon;          /* sizes of y, pi, and of the one-sided constraint count / 2 */
+    int nsoft;                  /* number of slacks (each with a lower and an upper copy) */
 } prob_t;
 
 #define IX(i, j, ld) ((size_t)(j) * (size_t)(ld) + (size_t)(i))
@@ -95,8 +110,9 @@ static void prob_free(prob_t *p)
     for (int n = 0; n <= p->N; ++n) {
         stage_t *s = &p->st[n];
         free(s->H); free(s->g); free(s->F); free(s->bb); free(s->G); free(s->lo); free(s->hi);
+        free(s->srow); free(s->Zl); free(s->Zu); free(s->zl); free(s->zu); free(s->lls); free(s->lus);
     }
-    free(p->st); free(p->zoff); free(p->poff); free(p->coff); free(p->uoff); free(p->xoff);
+    free(p->st); free(p->zoff); free(p->poff); free(p->coff); free(p->uoff); free(p->xoff); free(p->soff);
     memset(p, 0, sizeof(*p));
 }
 
@@ -112,6 +128,8 @@ static int prob_build(const orc_qp *qp, prob_t *p)
     p->coff = (int *)xcalloc((size_t)N + 2, sizeof(int));
     p->uoff = (int *)xcalloc((size_t)N + 2, sizeof(int));
     p->xoff = (int *)xcalloc((size_t)N + 2, sizeof(int));
+    p->soff = (int *)xcalloc((size_t)N + 2, sizeof(int));
+    size_t os = 0;
     size_t oA = 0, oB = 0, ob = 0, oQ = 0, oS = 0, oR = 0, oq = 0, or_ = 0;
     size_t oiu = 0, oix = 0, oD = 0, oC = 0, og = 0;
     for (int n = 0; n <= N; ++n) {
@@ -172,6 +190,29 @@ static int prob_build(const orc_qp *qp, prob_t *p)
         }
         for (int k = 0; k < nc; ++k)
             if (!(s->lo[k] <= s->hi[k])) { prob_free(p); return ORC_EINVAL; }
+        /* slacks */
+        int ns = qp->ns ? qp->ns[n] : 0;
+        if (ns < 0 || ns > nc) { prob_free(p); return ORC_EINVAL; }
+        s->ns = ns;
+        s->srow = (int *)xcalloc((size_t)nc, sizeof(int));
+        for (int k = 0; k < nc; ++k) s->srow[k] = -1;
+        s->Zl = (double *)xcalloc((size_t)ns, sizeof(double));
+        s->Zu = (double *)xcalloc((size_t)ns, sizeof(double));
+        s->zl = (double *)xcalloc((size_t)ns, sizeof(double));
+        s->zu = (double *)xcalloc((size_t)ns, sizeof(double));
+        s->lls = (double *)xcalloc((size_t)ns, sizeof(double));
+        s->lus = (double *)xcalloc((size_t)ns, sizeof(double));
+        for (int j = 0; j < ns; ++j) {
+            int k = qp->idxs[os + j];
+            if (k < 0 || k >= nc || s->srow[k] >= 0) { prob_free(p); return ORC_EINVAL; }
+            s->srow[k] = j;
+            s->Zl[j] = qp->Zl[os + j]; s->Zu[j] = qp->Zu[os + j];
+            s->zl[j] = qp->zl[os + j]; s->zu[j] = qp->zu[os + j];
+            s->lls[j] = qp->lls[os + j]; s->lus[j] = qp->lus[os + j];
+            if (!(s->Zl[j] >= 0.0) || !(s->Zu[j] >= 0.0)) { prob_free(p); return ORC_EINVAL; }
+        }
+        os += ns;
+        p->soff[n + 1] = p->soff[n] + ns;
         oiu += nbu; oix += nbx; oD += (size_t)ng * nu; oC += (size_t)ng * nx; og += ng;
         p->zoff[n + 1] = p->zoff[n] + nz;
         p->poff[n + 1] = p->poff[n] + nxn;
@@ -182,6 +223,7 @@ static int prob_build(const orc_qp *qp, prob_t *p)
     p->nv = p->zoff[N + 1];
     p->neq = p->poff[N + 1];
     p->ncon = p->coff[N + 1];
+    p->nsoft = p->soff[N + 1];
     return 0;
 }
 
@@ -189,6 +231,9 @@ static int prob_build(const orc_qp *qp, prob_t *p)
  * and four constraint vectors (ncon each). */
 typedef struct {
     double *y, *pi, *ll, *lu, *tl, *tu;
+    /* slacks (nsoft each): s^l, s^u, multipliers and slacks of s^l >= lls,
+     * s^u >= lus */
+    double *sl, *su, *lsl, *lsu, *tsl, *tsu;
 } ivec_t;
 
 static int ivec_alloc(const prob_t *p, ivec_t *v)
@@ -199,12 +244,20 @@ static int ivec_alloc(const prob_t *p, ivec_t *v)
     v->lu = (double *)xcalloc((size_t)p->ncon, sizeof(double));
     v->tl = (double *)xcalloc((size_t)p->ncon, sizeof(double));
     v->tu = (double *)xcalloc((size_t)p->ncon, sizeof(double));
-    return (v->y && v->pi && v->ll && v->lu && v->tl && v->tu) ? 0 : ORC_ENOMEM;
+    v->sl = (double *)xcalloc((size_t)p->nsoft, sizeof(double));
+    v->su = (double *)xcalloc((size_t)p->nsoft, sizeof(double));
+    v->lsl = (double *)xcalloc((size_t)p->nsoft, sizeof(double));
+    v->lsu = (double *)xcalloc((size_t)p->nsoft, sizeof(double));
+    v->tsl = (double *)xcalloc((size_t)p->nsoft, sizeof(double));
+    v->tsu = (double *)xcalloc((size_t)p->nsoft, sizeof(double));
+    return (v->y && v->pi && v->ll && v->lu && v->tl && v->tu && v->sl && v->su && v->lsl && v->lsu && v->tsl &&
+            v->tsu) ? 0 : ORC_ENOMEM;
 }
 
 static void ivec_free(ivec_t *v)
 {
     free(v->y); free(v->pi); free(v->ll); free(v->lu); free(v->tl); free(v->tu);
+    free(v->sl); free(v->su); free(v->lsl); free(v->lsu); free(v->tsl); free(v->tsu);
     memset(v, 0, sizeof(*v));
 }
 
@@ -220,6 +273,12 @@ static void ivec_from_user(const prob_t *p, const orc_vec *in, ivec_t *v)
     memcpy(v->lu, in->lam_u, sizeof(double) * (size_t)p->ncon);
     memcpy(v->tl, in->t_l, sizeof(double) * (size_t)p->ncon);
     memcpy(v->tu, in->t_u, sizeof(double) * (size_t)p->ncon);
+    if (p->nsoft > 0) {
+        size_t b = sizeof(double) * (size_t)p->nsoft;
+        memcpy(v->sl, in->s_l, b); memcpy(v->su, in->s_u, b);
+        memcpy(v->lsl, in->lam_sl, b); memcpy(v->lsu, in->lam_su, b);
+        memcpy(v->tsl, in->t_sl, b); memcpy(v->tsu, in->t_su, b);
+    }
 }
 
 static void ivec_to_user(const prob_t *p, const ivec_t *v, orc_vec *out)
@@ -234,6 +293,12 @@ static void ivec_to_user(const prob_t *p, const ivec_t *v, orc_vec *out)
     memcpy(out->lam_u, v->lu, sizeof(double) * (size_t)p->ncon);
     memcpy(out->t_l, v->tl, sizeof(double) * (size_t)p->ncon);
     memcpy(out->t_u, v->tu, sizeof(double) * (size_t)p->ncon);
+    if (p->nsoft > 0) {
+        size_t b = sizeof(double) * (size_t)p->nsoft;
+        memcpy(out->s_l, v->sl, b); memcpy(out->s_u, v->su, b);
+        memcpy(out->lam_sl, v->lsl, b); memcpy(out->lam_su, v->lsu, b);
+        memcpy(out->t_sl, v->tsl, b); memcpy(out->t_su, v->tsu, b);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -293,13 +358,17 @@ static void kkt_apply(const prob_t *p, const ivec_t *v, int with_H,
                 rb[i] = acc - zn1[i];
             }
         }
-        /* r_d */
+        /* r_d; a soft row holds its slack: lower row G z + s^l, upper row
+         * -G z + s^u */
         const double *tl = v->tl + p->coff[n], *tu = v->tu + p->coff[n];
         for (int k = 0; k < s->nc; ++k) {
             double gz = 0.0;
             for (int j = 0; j < s->nz; ++j) gz += s->G[IX(k, j, s->nc)] * z[j];
-            odl[p->coff[n] + k] = -gz + tl[k] + (cdl ? cdl[p->coff[n] + k] : 0.0);
-            odu[p->coff[n] + k] = gz + tu[k] + (cdu ? cdu[p->coff[n] + k] : 0.0);
+            const int js = s->srow[k];
+            const double sl = js >= 0 ? v->sl[p->soff[n] + js] : 0.0;
+            const double su = js >= 0 ? v->su[p->soff[n] + js] : 0.0;
+            odl[p->coff[n] + k] = -gz - sl + tl[k] + (cdl ? cdl[p->coff[n] + k] : 0.0);
+            odu[p->coff[n] + k] = gz - su + tu[k] + (cdu ? cdu[p->coff[n] + k] : 0.0);
         }
     }
 }
@@ -319,15 +388,38 @@ static void data_terms(const prob_t *p, double *cg, double *cb, double *cdl, dou
     }
 }
 
-/* IPM residuals at an iterate: constants g, b, d = [lo; -hi]. */
-static void residuals(const prob_t *p, const ivec_t *v, double *rg, double *rb, double *rdl, double *rdu)
+/* Slack rows of the residual function (soft constraints, Section 2.2):
+ *   r_s^l = Z^l s^l + z^l - lam_l(row) - lam_sl,
+ *   r_s^u = Z^u s^u + z^u - lam_u(row) - lam_su,
+ *   r_d of the slack bounds: -s^l + t_sl + lls,  -s^u + t_su + lus.
+ * Written to r->sl, r->su (stationarity) and r->lsl, r->lsu (r_d). */
+static void soft_residuals(const prob_t *p, const ivec_t *v, ivec_t *r)
+{
+    for (int n = 0; n <= p->N; ++n) {
+        const stage_t *s = &p->st[n];
+        for (int k = 0; k < s->nc; ++k) {
+            const int js = s->srow[k];
+            if (js < 0) continue;
+            const int J = p->soff[n] + js, c = p->coff[n] + k;
+            r->sl[J] = s->Zl[js] * v->sl[J] + s->zl[js] - v->ll[c] - v->lsl[J];
+            r->su[J] = s->Zu[js] * v->su[J] + s->zu[js] - v->lu[c] - v->lsu[J];
+            r->lsl[J] = -v->sl[J] + v->tsl[J] + s->lls[js];
+            r->lsu[J] = -v->su[J] + v->tsu[J] + s->lus[js];
+        }
+    }
+}
+
+/* IPM residuals at an iterate: constants g, b, d = [lo; -hi]; r_g, r_b,
+ * r_d in r->y, r->pi, r->ll, r->lu, the slack rows as in soft_residuals. */
+static void residuals(const prob_t *p, const ivec_t *v, ivec_t *r)
 {
     double *cg = (double *)xcalloc((size_t)p->nv, sizeof(double));
     double *cb = (double *)xcalloc((size_t)p->neq, sizeof(double));
     double *cdl = (double *)xcalloc((size_t)p->ncon, sizeof(double));
     double *cdu = (double *)xcalloc((size_t)p->ncon, sizeof(double));
     data_terms(p, cg, cb, cdl, cdu);
-    kkt_apply(p, v, 1, cg, cb, cdl, cdu, rg, rb, rdl, rdu);
+    kkt_apply(p, v, 1, cg, cb, cdl, cdu, r->y, r->pi, r->ll, r->lu);
+    soft_residuals(p, v, r);
     free(cg); free(cb); free(cdl); free(cdu);
 }
 
@@ -340,6 +432,44 @@ static double inf_norm(const double *v, int n)
         if (a > m) m = a;
     }
     return m;
+}
+
+static double max2(double a, double b) { return (b > a || b != b) ? b : a; }
+
+/* Duality measure mu = lam't / (2 (ncon + nsoft)) over every one-sided row
+ * (the two sides of each constraint row and of each slack bound), and the
+ * largest lam_i t_i. */
+static double duality(const prob_t *p, const ivec_t *v, double *comp)
+{
+    double lt = 0.0, cm = 0.0;
+    for (int i = 0; i < p->ncon; ++i) {
+        double a = v->ll[i] * v->tl[i], b = v->lu[i] * v->tu[i];
+        lt += a + b;
+        cm = max2(max2(cm, a), b);
+    }
+    for (int i = 0; i < p->nsoft; ++i) {
+        double a = v->lsl[i] * v->tsl[i], b = v->lsu[i] * v->tsu[i];
+        lt += a + b;
+        cm = max2(max2(cm, a), b);
+    }
+    if (comp) *comp = cm;
+    int m = p->ncon + p->nsoft;
+    return m ? lt / (2.0 * m) : 0.0;
+}
+
+/* The four residual inf-norms (stationarity incl. the slack rows, equality,
+ * inequality incl. the slack bounds, complementarity) and mu at iterate v
+ * with residuals r. */
+static double norms_at(const prob_t *p, const ivec_t *v, const ivec_t *r, double *norms)
+{
+    double comp = 0.0;
+    double mu = duality(p, v, &comp);
+    norms[0] = max2(inf_norm(r->y, p->nv), max2(inf_norm(r->sl, p->nsoft), inf_norm(r->su, p->nsoft)));
+    norms[1] = inf_norm(r->pi, p->neq);
+    norms[2] = max2(max2(inf_norm(r->ll, p->ncon), inf_norm(r->lu, p->ncon)),
+                    max2(inf_norm(r->lsl, p->nsoft), inf_norm(r->lsu, p->nsoft)));
+    norms[3] = comp;
+    return mu;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -558,29 +688,82 @@ static void riccati_solve(const prob_t *p, const fac_t *f, const double *gt, con
     free(pv); free(kv);
 }
 
-/* Full Newton step of eq:alg:pdipm:delta given the residuals (rg, rb, rdl,
- * rdu, rml, rmu) at iterate v and a factorization built from w = lam / t.
+/* Barrier weights of the reduced system eq:alg:kkt per constraint row: w =
+ * lam / t on each side.  A soft row's slack is eliminated together with its
+ * lower bound (a diagonal block, so the cost is linear in the number of
+ * slacks, Section 2.2): with D = Z + w + w_s, w_s = lam_s / t_s, the weight
+ * the row puts on G z becomes w - w^2 / D = w (Z + w_s) / D. */
+static void barrier_weights(const prob_t *p, const ivec_t *v, double *wl, double *wu)
+{
+    for (int n = 0; n <= p->N; ++n) {
+        const stage_t *s = &p->st[n];
+        for (int k = 0; k < s->nc; ++k) {
+            const int c = p->coff[n] + k, js = s->srow[k];
+            wl[c] = v->ll[c] / v->tl[c];
+            wu[c] = v->lu[c] / v->tu[c];
+            if (js < 0) continue;
+            const int J = p->soff[n] + js;
+            const double wsl = v->lsl[J] / v->tsl[J], wsu = v->lsu[J] / v->tsu[J];
+            wl[c] = wl[c] * (s->Zl[js] + wsl) / (s->Zl[js] + wl[c] + wsl);
+            wu[c] = wu[c] * (s->Zu[js] + wsu) / (s->Zu[js] + wu[c] + wsu);
+        }
+    }
+}
+
+/* Slack elimination terms of soft row c (slack J of the stage): the
+ * diagonals D = Z + w + w_s and the slack rows of the reduced gradient
+ * g_s = r_s - e - e_s, with e = w r_d - r_m / t of the row side and e_s the
+ * same of the slack bound. */
+static void soft_terms(const stage_t *s, int js, int J, int c, const ivec_t *v, const ivec_t *r, double *Dl,
+                       double *gl, double *Du, double *gu)
+{
+    const double wl = v->ll[c] / v->tl[c], wu = v->lu[c] / v->tu[c];
+    const double el = wl * r->ll[c] - r->tl[c] / v->tl[c];
+    const double eu = wu * r->lu[c] - r->tu[c] / v->tu[c];
+    const double wsl = v->lsl[J] / v->tsl[J], wsu = v->lsu[J] / v->tsu[J];
+    const double esl = wsl * r->lsl[J] - r->tsl[J] / v->tsl[J];
+    const double esu = wsu * r->lsu[J] - r->tsu[J] / v->tsu[J];
+    *Dl = s->Zl[js] + wl + wsl;
+    *gl = r->sl[J] - el - esl;
+    *Du = s->Zu[js] + wu + wsu;
+    *gu = r->su[J] - eu - esu;
+}
+
+/* Full Newton step of eq:alg:pdipm:delta at iterate v, given the right-hand
+ * side r (r_g, r_b, r_d in r->y, r->pi, r->ll/lu; r_m in r->tl/tu; the slack
+ * rows r_s in r->sl/su, r_d of the slack bounds in r->lsl/lsu and their r_m
+ * in r->tsl/tsu) and a factorization built from barrier_weights.
  * Elimination of dt then dlam (Section 3.3):
  *   gt = rg - C'(W rd - T^{-1} rm)
- *   dt = C dy - rd,    dlam = -T^{-1}(rm + Lam dt). */
-static void newton_solve(const prob_t *p, const fac_t *f, const ivec_t *v,
-                         const double *rg, const double *rb, const double *rdl, const double *rdu,
-                         const double *rml, const double *rmu, ivec_t *d)
+ *   dt = C dy - rd,    dlam = -T^{-1}(rm + Lam dt).
+ * A soft row first eliminates its slack: the slack rows read
+ *   D ds^l + w G dz = -g_s^l,  D ds^u - w G dz = -g_s^u,
+ * so the row's term e becomes e + w g_s / D (the weight change is in the
+ * factorization), and after the Riccati solve ds = -(g_s +- w G dz) / D. */
+static void newton_solve(const prob_t *p, const fac_t *f, const ivec_t *v, const ivec_t *r, ivec_t *d)
 {
     double *gt = (double *)xcalloc((size_t)p->nv, sizeof(double));
-    for (int i = 0; i < p->nv; ++i) gt[i] = rg[i];
+    for (int i = 0; i < p->nv; ++i) gt[i] = r->y[i];
     for (int n = 0; n <= p->N; ++n) {
         const stage_t *s = &p->st[n];
         int c0 = p->coff[n];
         for (int k = 0; k < s->nc; ++k) {
             int c = c0 + k;
-            double el = (v->ll[c] / v->tl[c]) * rdl[c] - rml[c] / v->tl[c];
-            double eu = (v->lu[c] / v->tu[c]) * rdu[c] - rmu[c] / v->tu[c];
+            double wl = v->ll[c] / v->tl[c], wu = v->lu[c] / v->tu[c];
+            double el = wl * r->ll[c] - r->tl[c] / v->tl[c];
+            double eu = wu * r->lu[c] - r->tu[c] / v->tu[c];
+            const int js = s->srow[k];
+            if (js >= 0) {
+                double Dl, gl, Du, gu;
+                soft_terms(s, js, p->soff[n] + js, c, v, r, &Dl, &gl, &Du, &gu);
+                el += wl * gl / Dl;
+                eu += wu * gu / Du;
+            }
             /* C'(e) with C = [G; -G]: G'(el) - G'(eu) */
             for (int j = 0; j < s->nz; ++j) gt[p->zoff[n] + j] -= s->G[IX(k, j, s->nc)] * (el - eu);
         }
     }
-    riccati_solve(p, f, gt, rb, d->y, d->pi);
+    riccati_solve(p, f, gt, r->pi, d->y, d->pi);
     for (int n = 0; n <= p->N; ++n) {
         const stage_t *s = &p->st[n];
         const double *dz = d->y + p->zoff[n];
@@ -588,10 +771,25 @@ static void newton_solve(const prob_t *p, const fac_t *f, const ivec_t *v,
             int c = p->coff[n] + k;
             double gdz = 0.0;
             for (int j = 0; j < s->nz; ++j) gdz += s->G[IX(k, j, s->nc)] * dz[j];
-            d->tl[c] = gdz - rdl[c];
-            d->tu[c] = -gdz - rdu[c];
-            d->ll[c] = -(rml[c] + v->ll[c] * d->tl[c]) / v->tl[c];
-            d->lu[c] = -(rmu[c] + v->lu[c] * d->tu[c]) / v->tu[c];
+            double dsl = 0.0, dsu = 0.0;
+            const int js = s->srow[k];
+            if (js >= 0) {
+                const int J = p->soff[n] + js;
+                double Dl, gl, Du, gu;
+                soft_terms(s, js, J, c, v, r, &Dl, &gl, &Du, &gu);
+                dsl = -(gl + (v->ll[c] / v->tl[c]) * gdz) / Dl;
+                dsu = -(gu - (v->lu[c] / v->tu[c]) * gdz) / Du;
+                d->sl[J] = dsl;
+                d->su[J] = dsu;
+                d->tsl[J] = dsl - r->lsl[J];
+                d->tsu[J] = dsu - r->lsu[J];
+                d->lsl[J] = -(r->tsl[J] + v->lsl[J] * d->tsl[J]) / v->tsl[J];
+                d->lsu[J] = -(r->tsu[J] + v->lsu[J] * d->tsu[J]) / v->tsu[J];
+            }
+            d->tl[c] = gdz + dsl - r->ll[c];
+            d->tu[c] = -gdz + dsu - r->lu[c];
+            d->ll[c] = -(r->tl[c] + v->ll[c] * d->tl[c]) / v->tl[c];
+            d->lu[c] = -(r->tu[c] + v->lu[c] * d->tu[c]) / v->tu[c];
         }
     }
     free(gt);
@@ -601,24 +799,20 @@ static void newton_solve(const prob_t *p, const fac_t *f, const ivec_t *v,
  * the same matrix with right-hand side -[g; b; d; rm - 2 Lam T e] (the
  * first three blocks linear in the iterate, so only their constant part
  * remains; rm is the delta formulation's complementarity term, e.g. lam.*t -
- * tau), whose solution is the full-step iterate; the step is its difference
- * with the current iterate (eq:alg:pdipm:step). */
-static void newton_solve_abs(const prob_t *p, const fac_t *f, const ivec_t *v, const double *rml, const double *rmu,
-                             ivec_t *d)
+ * tau, passed in r->tl/tu), whose solution is the full-step iterate; the
+ * step is its difference with the current iterate (eq:alg:pdipm:step).
+ * Problems with slacks are not taken by this formulation. */
+static void newton_solve_abs(const prob_t *p, const fac_t *f, const ivec_t *v, const ivec_t *rm, ivec_t *d)
 {
     int nc = p->ncon;
-    double *cg = (double *)xcalloc((size_t)p->nv, sizeof(double));
-    double *cb = (double *)xcalloc((size_t)p->neq, sizeof(double));
-    double *cdl = (double *)xcalloc((size_t)nc, sizeof(double));
-    double *cdu = (double *)xcalloc((size_t)nc, sizeof(double));
-    double *al = (double *)xcalloc((size_t)nc, sizeof(double));
-    double *au = (double *)xcalloc((size_t)nc, sizeof(double));
-    data_terms(p, cg, cb, cdl, cdu);
+    ivec_t c;
+    ivec_alloc(p, &c);
+    data_terms(p, c.y, c.pi, c.ll, c.lu);
     for (int i = 0; i < nc; ++i) {
-        al[i] = rml[i] - 2.0 * v->ll[i] * v->tl[i];
-        au[i] = rmu[i] - 2.0 * v->lu[i] * v->tu[i];
+        c.tl[i] = rm->tl[i] - 2.0 * v->ll[i] * v->tl[i];
+        c.tu[i] = rm->tu[i] - 2.0 * v->lu[i] * v->tu[i];
     }
-    newton_solve(p, f, v, cg, cb, cdl, cdu, al, au, d);
+    newton_solve(p, f, v, &c, d);
     for (int i = 0; i < p->nv; ++i) d->y[i] -= v->y[i];
     for (int i = 0; i < p->neq; ++i) d->pi[i] -= v->pi[i];
     for (int i = 0; i < nc; ++i) {
@@ -627,22 +821,25 @@ static void newton_solve_abs(const prob_t *p, const fac_t *f, const ivec_t *v, c
         d->tl[i] -= v->tl[i];
         d->tu[i] -= v->tu[i];
     }
-    free(cg); free(cb); free(cdl); free(cdu); free(al); free(au);
+    ivec_free(&c);
 }
 
-/* Largest alpha (uncapped; HUGE_VAL if no component blocks) keeping
- * lam + alpha dlam >= 0 and t + alpha dt >= 0. */
+/* Largest alpha (uncapped; HUGE_VAL if no component blocks) keeping every
+ * lam + alpha dlam >= 0 and t + alpha dt >= 0 (constraint rows and slack
+ * bounds). */
 static double max_step(const prob_t *p, const ivec_t *v, const ivec_t *d)
 {
     double a = HUGE_VAL;
-    const double *vv[4] = {v->ll, v->lu, v->tl, v->tu};
-    const double *dd[4] = {d->ll, d->lu, d->tl, d->tu};
-    for (int s = 0; s < 4; ++s)
-        for (int i = 0; i < p->ncon; ++i)
+    const double *vv[8] = {v->ll, v->lu, v->tl, v->tu, v->lsl, v->lsu, v->tsl, v->tsu};
+    const double *dd[8] = {d->ll, d->lu, d->tl, d->tu, d->lsl, d->lsu, d->tsl, d->tsu};
+    for (int s = 0; s < 8; ++s) {
+        const int m = s < 4 ? p->ncon : p->nsoft;
+        for (int i = 0; i < m; ++i)
             if (dd[s][i] < 0.0) {
                 double r = -vv[s][i] / dd[s][i];
                 if (r < a) a = r;
             }
+    }
     return a;
 }
 
@@ -653,7 +850,26 @@ static double mu_after(const prob_t *p, const ivec_t *v, const ivec_t *d, double
         acc += (v->ll[i] + alpha * d->ll[i]) * (v->tl[i] + alpha * d->tl[i]);
         acc += (v->lu[i] + alpha * d->lu[i]) * (v->tu[i] + alpha * d->tu[i]);
     }
-    return acc / (2.0 * p->ncon);
+    for (int i = 0; i < p->nsoft; ++i) {
+        acc += (v->lsl[i] + alpha * d->lsl[i]) * (v->tsl[i] + alpha * d->tsl[i]);
+        acc += (v->lsu[i] + alpha * d->lsu[i]) * (v->tsu[i] + alpha * d->tsu[i]);
+    }
+    return acc / (2.0 * (p->ncon + p->nsoft));
+}
+
+/* r_m = lam.*t + a.*b - shift on every one-sided row, written to r->tl/tu
+ * and r->tsl/tsu (a, b: the affine step's dlam and dt for the corrector, or
+ * NULL). */
+static void set_rm(const prob_t *p, const ivec_t *v, const ivec_t *aff, double shift, ivec_t *r)
+{
+    for (int i = 0; i < p->ncon; ++i) {
+        r->tl[i] = v->ll[i] * v->tl[i] - shift + (aff ? aff->ll[i] * aff->tl[i] : 0.0);
+        r->tu[i] = v->lu[i] * v->tu[i] - shift + (aff ? aff->lu[i] * aff->tu[i] : 0.0);
+    }
+    for (int i = 0; i < p->nsoft; ++i) {
+        r->tsl[i] = v->lsl[i] * v->tsl[i] - shift + (aff ? aff->lsl[i] * aff->tsl[i] : 0.0);
+        r->tsu[i] = v->lsu[i] * v->tsu[i] - shift + (aff ? aff->lsu[i] * aff->tsu[i] : 0.0);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -662,8 +878,11 @@ static double mu_after(const prob_t *p, const ivec_t *v, const ivec_t *d, double
 
 /* Residuals at a user-layout iterate.  Outputs in the user layout of a
  * step (u / x slots hold r_g split by stage, pi slot holds r_b, lam_l/lam_u
- * slots hold r_d lower / upper, t_l/t_u slots hold lam_l*t_l, lam_u*t_u).
- * norms: inf-norms of r_g, r_b, r_d and lam.*t; mu = lam't / n_c. */
+ * slots hold r_d lower / upper, t_l/t_u slots hold lam_l*t_l, lam_u*t_u;
+ * with slacks, s_l/s_u hold r_s, lam_sl/lam_su the r_d of the slack bounds
+ * and t_sl/t_su their lam*t).  norms: inf-norms of r_g (with r_s), r_b, r_d
+ * (with the slack bounds) and lam.*t; mu = lam't / n_c over every one-sided
+ * row. */
 int orc_residuals(const orc_qp *qp, const orc_vec *it, orc_vec *res, double *norms, double *mu)
 {
     prob_t p;
@@ -672,24 +891,12 @@ int orc_residuals(const orc_qp *qp, const orc_vec *it, orc_vec *res, double *nor
     ivec_t v, r;
     ivec_alloc(&p, &v); ivec_alloc(&p, &r);
     ivec_from_user(&p, it, &v);
-    residuals(&p, &v, r.y, r.pi, r.ll, r.lu);
-    double comp = 0.0, lt = 0.0;
-    for (int i = 0; i < p.ncon; ++i) {
-        r.tl[i] = v.ll[i] * v.tl[i];
-        r.tu[i] = v.lu[i] * v.tu[i];
-        lt += r.tl[i] + r.tu[i];
-    }
-    comp = inf_norm(r.tl, p.ncon);
-    double cu = inf_norm(r.tu, p.ncon);
-    if (cu > comp || cu != cu) comp = cu;
-    if (norms) {
-        double dl = inf_norm(r.ll, p.ncon), du = inf_norm(r.lu, p.ncon);
-        norms[0] = inf_norm(r.y, p.nv);
-        norms[1] = inf_norm(r.pi, p.neq);
-        norms[2] = (du > dl || du != du) ? du : dl;
-        norms[3] = comp;
-    }
-    if (mu) *mu = p.ncon ? lt / (2.0 * p.ncon) : 0.0;
+    residuals(&p, &v, &r);
+    double nrm[4];
+    double m = norms_at(&p, &v, &r, nrm);
+    set_rm(&p, &v, NULL, 0.0, &r);
+    if (norms) for (int i = 0; i < 4; ++i) norms[i] = nrm[i];
+    if (mu) *mu = m;
     if (res) ivec_to_user(&p, &r, res);
     ivec_free(&v); ivec_free(&r);
     prob_free(&p);
@@ -698,30 +905,28 @@ int orc_residuals(const orc_qp *qp, const orc_vec *it, orc_vec *res, double *nor
 
 /* Newton step of eq:alg:pdipm:delta at the iterate `it` with r_m = lam.*t - tau,
  * factorized with regularization `reg`; with abs_form, the same step through
- * the absolute formulation.  Returns the step in user layout. */
+ * the absolute formulation (not for problems with slacks).  Returns the step
+ * in user layout. */
 int orc_newton_step(const orc_qp *qp, const orc_vec *it, double tau, double reg, int abs_form, orc_vec *step)
 {
     prob_t p;
     int rc = prob_build(qp, &p);
     if (rc) return rc;
+    if (abs_form && p.nsoft > 0) { prob_free(&p); return ORC_EINVAL; }
     ivec_t v, r, d;
     ivec_alloc(&p, &v); ivec_alloc(&p, &r); ivec_alloc(&p, &d);
     ivec_from_user(&p, it, &v);
-    residuals(&p, &v, r.y, r.pi, r.ll, r.lu);
+    residuals(&p, &v, &r);
+    set_rm(&p, &v, NULL, tau, &r);
     double *wl = (double *)xcalloc((size_t)p.ncon, sizeof(double));
     double *wu = (double *)xcalloc((size_t)p.ncon, sizeof(double));
-    for (int i = 0; i < p.ncon; ++i) {
-        wl[i] = v.ll[i] / v.tl[i];
-        wu[i] = v.lu[i] / v.tu[i];
-        r.tl[i] = v.ll[i] * v.tl[i] - tau;
-        r.tu[i] = v.lu[i] * v.tu[i] - tau;
-    }
+    barrier_weights(&p, &v, wl, wu);
     fac_t f;
     memset(&f, 0, sizeof(f));
     rc = factorize(&p, wl, wu, reg, &f);
     if (rc == 0) {
-        if (abs_form) newton_solve_abs(&p, &f, &v, r.tl, r.tu, &d);
-        else newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, r.tl, r.tu, &d);
+        if (abs_form) newton_solve_abs(&p, &f, &v, &r, &d);
+        else newton_solve(&p, &f, &v, &r, &d);
         ivec_to_user(&p, &d, step);
     }
     fac_free(&f);
@@ -734,21 +939,22 @@ int orc_newton_step(const orc_qp *qp, const orc_vec *it, double tau, double reg,
 /* The IPM.  On return `sol` holds the final iterate; iters, the number of
  * iterations taken; res_norms the four residual inf-norms at the final
  * iterate; mu_out the final duality measure.  The return value is the
- * solver status (>= 0) or a usage error (< 0). */
+ * solver status (>= 0) or a usage error (< 0).  Problems with slacks take
+ * the delta formulation from a cold start only. */
 int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, double *res_norms, double *mu_out)
 {
     prob_t p;
     int rc = prob_build(qp, &p);
     if (rc) return rc;
+    if (p.nsoft > 0 && (arg->warm_start != 0 || arg->abs_form != 0)) { prob_free(&p); return ORC_EINVAL; }
     ivec_t v, r, d, dc;
     ivec_alloc(&p, &v); ivec_alloc(&p, &r); ivec_alloc(&p, &d); ivec_alloc(&p, &dc);
-    int nc = p.ncon;
+    int nc = p.ncon, nsf = p.nsoft;
     double *wl = (double *)xcalloc((size_t)nc, sizeof(double));
     double *wu = (double *)xcalloc((size_t)nc, sizeof(double));
-    double *rml = (double *)xcalloc((size_t)nc, sizeof(double));
-    double *rmu = (double *)xcalloc((size_t)nc, sizeof(double));
 
-    /* Initial point.  Cold start: y = 0, pi = 0, t = max(C y - d, 1), lam = 1.
+    /* Initial point.  Cold start: y = 0, pi = 0, t = max(C y - d, 1), lam = 1
+     * (slacks s = 0, their bounds' t = max(s - ls, 1), lam = 1).
      * Warm start (Section 4.2) from the iterate passed in `sol`: with a primal
      * guess, y is the guess and the rest is set as in the cold start at that
      * y; with a primal and dual guess, every block is the guess, multipliers
@@ -777,6 +983,16 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
                 v.tu[c] = tu0 > 1.0 ? tu0 : 1.0;
                 v.ll[c] = 1.0;
                 v.lu[c] = 1.0;
+                const int js = s->srow[k];
+                if (js >= 0) {
+                    const int J = p.soff[n] + js;
+                    v.sl[J] = 0.0;
+                    v.su[J] = 0.0;
+                    v.tsl[J] = -s->lls[js] > 1.0 ? -s->lls[js] : 1.0;
+                    v.tsu[J] = -s->lus[js] > 1.0 ? -s->lus[js] : 1.0;
+                    v.lsl[J] = 1.0;
+                    v.lsu[J] = 1.0;
+                }
             }
         }
     }
@@ -787,24 +1003,13 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
     for (k = 0;; ++k) {
         /* absolute formulation (Section 4.2, mode speed_abs): no residuals in
          * the loop, exit on the duality measure alone */
-        if (!absf) residuals(&p, &v, r.y, r.pi, r.ll, r.lu);
-        double lt = 0.0, comp = 0.0;
-        for (int i = 0; i < nc; ++i) {
-            double a = v.ll[i] * v.tl[i], b2 = v.lu[i] * v.tu[i];
-            lt += a + b2;
-            if (a > comp) comp = a;
-            if (b2 > comp) comp = b2;
-        }
-        mu = nc ? lt / (2.0 * nc) : 0.0;
         if (absf) {
+            mu = duality(&p, &v, NULL);
             if (mu != mu) { status = ORC_NAN; break; }
             if (mu <= arg->tol_comp) { status = ORC_SUCCESS; break; }
         } else {
-            double dl = inf_norm(r.ll, nc), du = inf_norm(r.lu, nc);
-            norms[0] = inf_norm(r.y, p.nv);
-            norms[1] = inf_norm(r.pi, p.neq);
-            norms[2] = du > dl ? du : dl;
-            norms[3] = comp;
+            residuals(&p, &v, &r);
+            mu = norms_at(&p, &v, &r, norms);
             if (norms[0] != norms[0] || norms[1] != norms[1] || norms[2] != norms[2] || mu != mu) {
                 status = ORC_NAN;
                 break;
@@ -817,39 +1022,33 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
         }
         if (k >= arg->iter_max) { status = ORC_MAX_ITER; break; }
 
-        for (int i = 0; i < nc; ++i) { wl[i] = v.ll[i] / v.tl[i]; wu[i] = v.lu[i] / v.tu[i]; }
+        barrier_weights(&p, &v, wl, wu);
         fac_t f;
         memset(&f, 0, sizeof(f));
         if (factorize(&p, wl, wu, arg->reg_prim, &f) != 0) { fac_free(&f); status = ORC_NAN; break; }
 
         /* predictor (affine): r_m = lam.*t */
-        for (int i = 0; i < nc; ++i) { rml[i] = v.ll[i] * v.tl[i]; rmu[i] = v.lu[i] * v.tu[i]; }
-        if (absf) newton_solve_abs(&p, &f, &v, rml, rmu, &d);
-        else newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, rml, rmu, &d);
+        set_rm(&p, &v, NULL, 0.0, &r);
+        if (absf) newton_solve_abs(&p, &f, &v, &r, &d);
+        else newton_solve(&p, &f, &v, &r, &d);
         ivec_t *step = &d;
-        if (nc > 0) {
+        if (nc + nsf > 0) {
             double a_aff = max_step(&p, &v, &d);
             if (a_aff > 1.0) a_aff = 1.0;
             double mu_aff = mu_after(&p, &v, &d, a_aff);
             double sigma = mu > 0.0 ? (mu_aff / mu) * (mu_aff / mu) * (mu_aff / mu) : 0.0;
             /* corrector: r_m = lam.*t + dlam_aff.*dt_aff - sigma mu */
-            for (int i = 0; i < nc; ++i) {
-                rml[i] = v.ll[i] * v.tl[i] + d.ll[i] * d.tl[i] - sigma * mu;
-                rmu[i] = v.lu[i] * v.tu[i] + d.lu[i] * d.tu[i] - sigma * mu;
-            }
-            if (absf) newton_solve_abs(&p, &f, &v, rml, rmu, &dc);
-            else newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, rml, rmu, &dc);
+            set_rm(&p, &v, &d, sigma * mu, &r);
+            if (absf) newton_solve_abs(&p, &f, &v, &r, &dc);
+            else newton_solve(&p, &f, &v, &r, &dc);
             double a_c = max_step(&p, &v, &dc);
             if (a_c > 1.0) a_c = 1.0;
             double mu_c = mu_after(&p, &v, &dc, a_c);
             if (mu_c > arg->corr_ratio * mu_aff) {
                 /* conditional corrector rejected: predictor-centering step */
-                for (int i = 0; i < nc; ++i) {
-                    rml[i] = v.ll[i] * v.tl[i] - sigma * mu;
-                    rmu[i] = v.lu[i] * v.tu[i] - sigma * mu;
-                }
-                if (absf) newton_solve_abs(&p, &f, &v, rml, rmu, &dc);
-                else newton_solve(&p, &f, &v, r.y, r.pi, r.ll, r.lu, rml, rmu, &dc);
+                set_rm(&p, &v, NULL, sigma * mu, &r);
+                if (absf) newton_solve_abs(&p, &f, &v, &r, &dc);
+                else newton_solve(&p, &f, &v, &r, &dc);
             }
             step = &dc;
         }
@@ -870,22 +1069,22 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
             if (v.tl[i] < arg->t_min) v.tl[i] = arg->t_min;
             if (v.tu[i] < arg->t_min) v.tu[i] = arg->t_min;
         }
+        for (int i = 0; i < nsf; ++i) {
+            v.sl[i] += alpha * step->sl[i];
+            v.su[i] += alpha * step->su[i];
+            v.lsl[i] += alpha * step->lsl[i];
+            v.lsu[i] += alpha * step->lsu[i];
+            v.tsl[i] += alpha * step->tsl[i];
+            v.tsu[i] += alpha * step->tsu[i];
+            if (v.lsl[i] < arg->lam_min) v.lsl[i] = arg->lam_min;
+            if (v.lsu[i] < arg->lam_min) v.lsu[i] = arg->lam_min;
+            if (v.tsl[i] < arg->t_min) v.tsl[i] = arg->t_min;
+            if (v.tsu[i] < arg->t_min) v.tsu[i] = arg->t_min;
+        }
         if (alpha < arg->alpha_min) {
             /* report the residuals at the point reached */
-            residuals(&p, &v, r.y, r.pi, r.ll, r.lu);
-            double lt2 = 0.0, comp2 = 0.0;
-            for (int i = 0; i < nc; ++i) {
-                double a = v.ll[i] * v.tl[i], b2 = v.lu[i] * v.tu[i];
-                lt2 += a + b2;
-                if (a > comp2) comp2 = a;
-                if (b2 > comp2) comp2 = b2;
-            }
-            mu = nc ? lt2 / (2.0 * nc) : 0.0;
-            double dl2 = inf_norm(r.ll, nc), du2 = inf_norm(r.lu, nc);
-            norms[0] = inf_norm(r.y, p.nv);
-            norms[1] = inf_norm(r.pi, p.neq);
-            norms[2] = du2 > dl2 ? du2 : dl2;
-            norms[3] = comp2;
+            residuals(&p, &v, &r);
+            mu = norms_at(&p, &v, &r, norms);
             status = ORC_MIN_STEP;
             ++k;
             break;
@@ -893,18 +1092,9 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
     }
     if (absf && status != ORC_NAN) {
         /* residuals only before returning */
-        residuals(&p, &v, r.y, r.pi, r.ll, r.lu);
-        double comp3 = 0.0;
-        for (int i = 0; i < nc; ++i) {
-            double a = v.ll[i] * v.tl[i], b2 = v.lu[i] * v.tu[i];
-            if (a > comp3) comp3 = a;
-            if (b2 > comp3) comp3 = b2;
-        }
-        double dl3 = inf_norm(r.ll, nc), du3 = inf_norm(r.lu, nc);
-        norms[0] = inf_norm(r.y, p.nv);
-        norms[1] = inf_norm(r.pi, p.neq);
-        norms[2] = du3 > dl3 ? du3 : dl3;
-        norms[3] = comp3;
+        residuals(&p, &v, &r);
+        double mu3 = norms_at(&p, &v, &r, norms);
+        (void)mu3;
         if (norms[0] != norms[0] || norms[1] != norms[1] || norms[2] != norms[2] || norms[3] != norms[3])
             status = ORC_NAN;
     }
@@ -912,7 +1102,7 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
     if (res_norms) for (int i = 0; i < 4; ++i) res_norms[i] = norms[i];
     if (mu_out) *mu_out = mu;
     ivec_to_user(&p, &v, sol);
-    free(wl); free(wu); free(rml); free(rmu);
+    free(wl); free(wu);
     ivec_free(&v); ivec_free(&r); ivec_free(&d); ivec_free(&dc);
     prob_free(&p);
     return status;
@@ -921,12 +1111,13 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
 /* Iterative-refinement residual of Section 3.4 at iterate `it` for a step
  * `step` and right-hand side r = (rg, rb, rd, rm) given in `rhs` (user
  * layout, lam_l/lam_u slots = rd lower/upper, t_l/t_u slots = rm lower/upper):
- *   r_ir = K step + r. */
+ *   r_ir = K step + r.  Not for problems with slacks. */
 int orc_ir_residual(const orc_qp *qp, const orc_vec *it, const orc_vec *step, const orc_vec *rhs, orc_vec *out)
 {
     prob_t p;
     int rc = prob_build(qp, &p);
     if (rc) return rc;
+    if (p.nsoft > 0) { prob_free(&p); return ORC_EINVAL; }
     ivec_t v, d, c, o;
     ivec_alloc(&p, &v); ivec_alloc(&p, &d); ivec_alloc(&p, &c); ivec_alloc(&p, &o);
     ivec_from_user(&p, it, &v);

@@ -44,7 +44,8 @@ class _Qp(ct.Structure):
     _fields_ = [("N", ct.c_int)] + [(n, _PI) for n in ("nx", "nu", "nbu", "nbx", "ng")] + \
         [(n, _P) for n in ("A", "B", "b", "Q", "S", "R", "q", "r")] + \
         [(n, _PI) for n in ("idxbu", "idxbx")] + \
-        [(n, _P) for n in ("lbu", "ubu", "lbx", "ubx", "D", "C", "lg", "ug")]
+        [(n, _P) for n in ("lbu", "ubu", "lbx", "ubx", "D", "C", "lg", "ug")] + \
+        [("ns", _PI), ("idxs", _PI)] + [(n, _P) for n in ("Zl", "Zu", "zl", "zu", "lls", "lus")]
 
 
 class _Arg(ct.Structure):
@@ -55,8 +56,11 @@ class _Arg(ct.Structure):
                 ("abs_form", ct.c_int)]
 
 
+SOFT_NAMES = ("s_l", "s_u", "lam_sl", "lam_su", "t_sl", "t_su")
+
+
 class _Vec(ct.Structure):
-    _fields_ = [(n, _P) for n in ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")]
+    _fields_ = [(n, _P) for n in ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u") + SOFT_NAMES]
 
 
 _lib = None
@@ -144,6 +148,17 @@ class _Packed:
             setattr(c, k, v.ctypes.data_as(_P))
         c.idxbu = self.idxbu.ctypes.data_as(_PI)
         c.idxbx = self.idxbx.ctypes.data_as(_PI)
+        # soft constraints (Section 2.2): absent unless the problem has idxs
+        self.n_s = 0
+        if getattr(qp, "idxs", None) is not None:
+            self.ns = np.asarray([len(i) for i in qp.idxs], dtype=np.int32)
+            self.idxs = _cat(qp.idxs, np.int32)
+            self.soft = {k: _cat(getattr(qp, k)) for k in ("Zl", "Zu", "zl", "zu", "lls", "lus")}
+            c.ns = self.ns.ctypes.data_as(_PI)
+            c.idxs = self.idxs.ctypes.data_as(_PI)
+            for k, v in self.soft.items():
+                setattr(c, k, v.ctypes.data_as(_P))
+            self.n_s = int(self.ns.sum())
         self.c = c
         self.n_u = int(self.nu.sum())
         self.n_x = int(self.nx.sum())
@@ -153,18 +168,24 @@ class _Packed:
 
 class Vec:
     """Iterate / step / residual in the user layout: u, x, pi and the per-stage
-    constraint vectors ordered [box u, box x, general]."""
-    names = ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")
+    constraint vectors ordered [box u, box x, general]; with soft constraints
+    also the slacks s_l, s_u and the multipliers and slacks of their lower
+    bounds (lam_sl, lam_su, t_sl, t_su), stage by stage in idxs order."""
+    names = ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u") + SOFT_NAMES
 
-    def __init__(self, n_u, n_x, n_pi, n_c):
+    def __init__(self, n_u, n_x, n_pi, n_c, n_s=0):
         self.u = np.zeros(max(n_u, 1)); self.x = np.zeros(max(n_x, 1)); self.pi = np.zeros(max(n_pi, 1))
         self.lam_l = np.zeros(max(n_c, 1)); self.lam_u = np.zeros(max(n_c, 1))
         self.t_l = np.zeros(max(n_c, 1)); self.t_u = np.zeros(max(n_c, 1))
+        for k in SOFT_NAMES:
+            setattr(self, k, np.zeros(max(n_s, 1)))
         self._sizes = dict(u=n_u, x=n_x, pi=n_pi, lam_l=n_c, lam_u=n_c, t_l=n_c, t_u=n_c)
+        self._sizes.update({k: n_s for k in SOFT_NAMES})
+        self.n_s = n_s
 
     @classmethod
     def like(cls, pk: _Packed):
-        return cls(pk.n_u, pk.n_x, pk.n_pi, pk.n_c)
+        return cls(pk.n_u, pk.n_x, pk.n_pi, pk.n_c, pk.n_s)
 
     def c(self):
         v = _Vec()
@@ -173,8 +194,10 @@ class Vec:
         return v
 
     def view(self):
-        """dict of arrays trimmed to their true sizes."""
-        return {n: getattr(self, n)[: self._sizes[n]].copy() for n in self.names}
+        """dict of arrays trimmed to their true sizes (the slack blocks only
+        when the problem has slacks)."""
+        names = self.names if self.n_s else self.names[:7]
+        return {n: getattr(self, n)[: self._sizes[n]].copy() for n in names}
 
     def set(self, **kw):
         for k, v in kw.items():
@@ -188,7 +211,7 @@ class Result:
     iters: int
     res: np.ndarray   # inf-norms: stat, eq, ineq, comp
     mu: float
-    sol: dict         # u, x, pi, lam_l, lam_u, t_l, t_u
+    sol: dict         # u, x, pi, lam_l, lam_u, t_l, t_u (and the slack blocks)
 
 
 def solve(qp, arg: Arg | None = None, guess: dict | None = None) -> Result:
@@ -221,7 +244,9 @@ def _vec_from(pk, d):
 def residuals(qp, iterate: dict):
     """Residuals (eq:alg:pdipm:delta RHS) at `iterate`.  Returns (parts, norms, mu):
     parts has r_g split into 'u'/'x' slots, r_b in 'pi', r_d lower/upper in
-    'lam_l'/'lam_u', lam.*t lower/upper in 't_l'/'t_u'."""
+    'lam_l'/'lam_u', lam.*t lower/upper in 't_l'/'t_u'; with slacks, r_s in
+    's_l'/'s_u', the slack bounds' r_d in 'lam_sl'/'lam_su' and their lam.*t
+    in 't_sl'/'t_su'."""
     lib = _load()
     pk = _Packed(qp)
     it = _vec_from(pk, iterate)

@@ -59,6 +59,18 @@ class OcpQp:
     lg: List[np.ndarray]
     ug: List[np.ndarray]
     meta: dict = field(default_factory=dict)
+    # Soft constraints (Section 2.2, the slack variables), or None: per
+    # stage, the rows relaxed by a slack pair (indices into the stage's rows
+    # [box u, box x, general]; the lower row gains +s^l, the upper row -s^u),
+    # the slacks' diagonal Hessians Zl, Zu, gradients zl, zu and lower
+    # bounds lls, lus (s^l >= lls, s^u >= lus).
+    idxs: Optional[List[np.ndarray]] = None
+    Zl: Optional[List[np.ndarray]] = None
+    Zu: Optional[List[np.ndarray]] = None
+    zl: Optional[List[np.ndarray]] = None
+    zu: Optional[List[np.ndarray]] = None
+    lls: Optional[List[np.ndarray]] = None
+    lus: Optional[List[np.ndarray]] = None
 
     @property
     def nbu(self):
@@ -72,6 +84,10 @@ class OcpQp:
     def ng(self):
         return [d.shape[0] for d in self.D]
 
+    @property
+    def ns(self):
+        return [len(i) for i in self.idxs] if self.idxs is not None else [0] * (self.N + 1)
+
     def n_constraints(self) -> int:
         """Number of two-sided constraint rows (each counted once)."""
         return sum(self.nbu) + sum(self.nbx) + sum(self.ng)
@@ -81,7 +97,32 @@ class OcpQp:
         return OcpQp(self.N, list(self.nx), list(self.nu), cp(self.A), cp(self.B), cp(self.b),
                      cp(self.Q), cp(self.S), cp(self.R), cp(self.q), cp(self.r),
                      cp(self.idxbu), cp(self.lbu), cp(self.ubu), cp(self.idxbx), cp(self.lbx),
-                     cp(self.ubx), cp(self.D), cp(self.C), cp(self.lg), cp(self.ug), dict(self.meta))
+                     cp(self.ubx), cp(self.D), cp(self.C), cp(self.lg), cp(self.ug), dict(self.meta),
+                     *[None if getattr(self, k) is None else cp(getattr(self, k)) for k in SOFT_FIELDS])
+
+
+SOFT_FIELDS = ("idxs", "Zl", "Zu", "zl", "zu", "lls", "lus")
+
+
+def soften(qp: OcpQp, rows, Zl, Zu, zl, zu, lls=0.0, lus=0.0) -> OcpQp:
+    """A copy of `qp` with the constraint rows rows(n, qp) of each stage
+    (indices into [box u, box x, general]) made soft, each slack pair with the
+    scalar penalty weights Zl, Zu (quadratic), zl, zu (linear) and lower
+    bounds lls, lus (Section 2.2)."""
+    out = qp.copy()
+    idxs = [np.asarray(rows(n, qp), dtype=np.int32) for n in range(qp.N + 1)]
+    out.idxs = idxs
+    for k, v in (("Zl", Zl), ("Zu", Zu), ("zl", zl), ("zu", zu), ("lls", lls), ("lus", lus)):
+        setattr(out, k, [np.full(len(i), float(v)) for i in idxs])
+    return out
+
+
+def state_box_rows(n, qp):
+    """The rows of stage n's state boxes, stage 0 excluded (x_0 stays fixed)."""
+    if n == 0:
+        return []
+    nbu = len(qp.idxbu[n])
+    return list(range(nbu, nbu + len(qp.idxbx[n])))
 
 
 def _empty_i():

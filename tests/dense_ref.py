@@ -239,3 +239,138 @@ def random_interior_iterate(qp, rng, scale=1.0):
                 pi=rng.standard_normal(npi) * scale,
                 lam_l=rng.uniform(0.1, 2.0, nc), lam_u=rng.uniform(0.1, 2.0, nc),
                 t_l=rng.uniform(0.1, 2.0, nc), t_u=rng.uniform(0.1, 2.0, nc))
+
+
+class DenseSoftQp:
+    """The OCP QP with soft constraints (Section 2.2) as a generic QP in the
+    augmented variables y' = [y; s^l; s^u], built from the definition with
+    numpy, without eliminating the slacks:
+
+      min 1/2 y'H y + g'y + sum_j 1/2 Zl_j (s^l_j)^2 + zl_j s^l_j + (same for s^u)
+      s.t. Aeq y = beq,
+           G_i y + s^l_j >= lo_i,  -G_i y + s^u_j >= -hi_i   (row i softened by slack j)
+           G_i y >= lo_i,          -G_i y >= -hi_i            (hard rows)
+           s^l >= lls,  s^u >= lus.
+
+    One-sided rows are stacked [lower rows; upper rows; s^l bounds; s^u
+    bounds], matching the user layout (lam_l, lam_u, lam_sl, lam_su) and
+    (t_l, t_u, t_sl, t_su)."""
+
+    def __init__(self, qp):
+        base = DenseQp(qp)
+        self.base = base
+        self.qp = qp
+        m, nv = base.m, base.nv
+        coff = np.concatenate([[0], np.cumsum([qp.nbu[n] + qp.nbx[n] + qp.ng[n] for n in range(qp.N + 1)])])
+        rows = []   # global constraint row of each slack, stage by stage in idxs order
+        Zl, Zu, zl, zu, lls, lus = ([] for _ in range(6))
+        for n in range(qp.N + 1):
+            for j, k in enumerate(qp.idxs[n]):
+                rows.append(int(coff[n] + k))
+                Zl.append(qp.Zl[n][j]); Zu.append(qp.Zu[n][j]); zl.append(qp.zl[n][j]); zu.append(qp.zu[n][j])
+                lls.append(qp.lls[n][j]); lus.append(qp.lus[n][j])
+        ns = len(rows)
+        self.m, self.ns, self.nv0 = m, ns, nv
+        self.nv = nv + 2 * ns
+        self.neq = base.neq
+        self.H = scipy.linalg.block_diag(base.H, np.diag(Zl), np.diag(Zu)) if ns else base.H.copy()
+        self.g = np.concatenate([base.g, zl, zu])
+        self.Aeq = np.hstack([base.Aeq, np.zeros((base.neq, 2 * ns))])
+        self.beq = base.beq
+        C = np.zeros((2 * m + 2 * ns, self.nv))
+        C[:m, :nv] = base.G
+        C[m:2 * m, :nv] = -base.G
+        for j, i in enumerate(rows):
+            C[i, nv + j] = 1.0
+            C[m + i, nv + ns + j] = 1.0
+            C[2 * m + j, nv + j] = 1.0
+            C[2 * m + ns + j, nv + ns + j] = 1.0
+        self.Cin = C
+        self.d = np.concatenate([base.lo, -base.hi, lls, lus])
+        self.soft_rows = rows
+        self.lo, self.hi = base.lo, base.hi
+
+    def stack(self, it):
+        y = np.concatenate([self.base.y_from(it["u"], it["x"]), it["s_l"], it["s_u"]])
+        lam = np.concatenate([it["lam_l"], it["lam_u"], it["lam_sl"], it["lam_su"]])
+        t = np.concatenate([it["t_l"], it["t_u"], it["t_sl"], it["t_su"]])
+        return y, np.asarray(it["pi"], dtype=float), lam, t
+
+    def residual(self, it, tau=0.0):
+        y, pi, lam, t = self.stack(it)
+        rg = self.H @ y + self.g - self.Aeq.T @ pi - self.Cin.T @ lam
+        rb = -self.Aeq @ y + self.beq
+        rd = -self.Cin @ y + t + self.d
+        rm = lam * t - tau
+        return rg, rb, rd, rm
+
+    def split(self, vy, vc):
+        """User-layout dict of a primal-sized and a row-sized vector pair."""
+        m, ns, nv = self.m, self.ns, self.nv0
+        u, x = self.base.ux_from(vy[:nv])
+        return dict(u=u, x=x, s_l=vy[nv:nv + ns], s_u=vy[nv + ns:],
+                    lam_l=vc[:m], lam_u=vc[m:2 * m], lam_sl=vc[2 * m:2 * m + ns], lam_su=vc[2 * m + ns:])
+
+    def newton_step(self, it, tau=0.0):
+        _, _, lam, t = self.stack(it)
+        rg, rb, rd, rm = self.residual(it, tau)
+        nv, ne, nc = self.nv, self.neq, self.Cin.shape[0]
+        K = np.zeros((nv + ne + 2 * nc, nv + ne + 2 * nc))
+        a, b, c = nv, nv + ne, nv + ne + nc
+        K[:a, :a] = self.H
+        K[:a, a:b] = -self.Aeq.T
+        K[:a, b:c] = -self.Cin.T
+        K[a:b, :a] = -self.Aeq
+        K[b:c, :a] = -self.Cin
+        K[b:c, c:] = np.eye(nc)
+        K[c:, b:c] = np.diag(t)
+        K[c:, c:] = np.diag(lam)
+        sol = np.linalg.solve(K, -np.concatenate([rg, rb, rd, rm]))
+        dy, dpi, dlam, dt = sol[:a], sol[a:b], sol[b:c], sol[c:]
+        out = self.split(dy, dlam)
+        tt = self.split(np.zeros(nv), dt)
+        out.update(pi=dpi, t_l=tt["lam_l"], t_u=tt["lam_u"], t_sl=tt["lam_sl"], t_su=tt["lam_su"])
+        return out
+
+    def brute_force(self, tol=1e-9):
+        """Enumerate active sets of the one-sided rows (hard rows with equal
+        limits are equalities with a free-sign multiplier); keep the
+        primal-feasible, dual-feasible equality-QP solutions.  Returns the
+        certified y' (unique for Zl, Zu > 0)."""
+        m, ns = self.m, self.ns
+        soft = set(self.soft_rows)
+        fixed = [i for i in range(m) if i not in soft and self.lo[i] == self.hi[i]]
+        skip = set(fixed) | {m + i for i in fixed}
+        free = [r for r in range(2 * m + 2 * ns) if r not in skip]
+        found = []
+        for states in itertools.product((0, 1), repeat=len(free)):
+            act = [r for r, s in zip(free, states) if s]
+            E = [self.Cin[i] for i in fixed] + [self.Cin[r] for r in act]
+            ev = [self.lo[i] for i in fixed] + [self.d[r] for r in act]
+            Ae = np.vstack([self.Aeq] + ([np.array(E)] if E else []))
+            be = np.concatenate([self.beq, ev])
+            ne = Ae.shape[0]
+            if ne > self.nv or np.linalg.matrix_rank(Ae) < ne:
+                continue
+            K = np.zeros((self.nv + ne, self.nv + ne))
+            K[:self.nv, :self.nv] = self.H
+            K[:self.nv, self.nv:] = -Ae.T
+            K[self.nv:, :self.nv] = Ae
+            s = np.linalg.solve(K, np.concatenate([-self.g, be]))
+            y, mult = s[:self.nv], s[self.nv + self.neq + len(fixed):]
+            if np.any(self.Cin @ y < self.d - tol):
+                continue
+            if np.any(mult < -tol):
+                continue
+            found.append(y)
+        return found
+
+
+def random_interior_iterate_soft(qp, rng, scale=1.0):
+    """random_interior_iterate plus slacks and positive slack-bound pairs."""
+    it = random_interior_iterate(qp, rng, scale)
+    ns = sum(len(i) for i in qp.idxs)
+    it.update(s_l=rng.standard_normal(ns) * scale, s_u=rng.standard_normal(ns) * scale,
+              lam_sl=rng.uniform(0.1, 2.0, ns), lam_su=rng.uniform(0.1, 2.0, ns),
+              t_sl=rng.uniform(0.1, 2.0, ns), t_su=rng.uniform(0.1, 2.0, ns))
+    return it
