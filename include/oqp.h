@@ -118,6 +118,10 @@ int oqp_dims_init(void* mem, size_t bytes, int N, oqp_dims** out);
 /* Sizes of stage n (0 <= n <= N): states nx, inputs nu, boxed inputs nbu,
  * boxed states nbx, general rows ng.  Requires nbu <= nu, nbx <= nx. */
 int oqp_dims_set_stage(oqp_dims* dims, int n, int nx, int nu, int nbu, int nbx, int ng);
+/* Soft constraints of stage n (Section 2.2, the slack variables): ns slack
+ * pairs, 0 <= ns <= nbu + nbx + ng (checked again when a QP or a batch is
+ * created, in case the stage sizes change afterwards).  Default 0. */
+int oqp_dims_set_soft(oqp_dims* dims, int n, int ns);
 
 /* ---- qp data (Section 2.2), copied at set time -------------------------- */
 size_t oqp_qp_bytes(const oqp_dims* dims);
@@ -138,6 +142,17 @@ int oqp_qp_set_box_x(oqp_qp* qp, int n, const int* idx, const double* lo, const 
 int oqp_qp_set_general(oqp_qp* qp, int n, const double* D, int ldd, const double* C, int ldc, const double* lo,
                        const double* hi);
 
+/* Soft constraints of stage n (Section 2.2): slack j relaxes row idxs[j] of
+ * the stage's rows [box u (idxbu order), box x (idxbx order), general] on
+ * both sides, the lower row reading G z + s^l_j >= lo and the upper row
+ * G z - s^u_j <= hi, with s^l_j >= lls[j], s^u_j >= lus[j] and the cost
+ * 1/2 Zl[j] (s^l_j)^2 + zl[j] s^l_j + 1/2 Zu[j] (s^u_j)^2 + zu[j] s^u_j
+ * (diagonal Hessians: L2 penalties; linear terms: L1 penalties).  ns_n
+ * entries each; rows distinct and in range, Zl, Zu >= 0, all finite, else
+ * OQP_EINVAL.  A stage with ns_n = 0 ignores the call. */
+int oqp_qp_set_soft(oqp_qp* qp, int n, const int* idxs, const double* Zl, const double* Zu, const double* zl,
+                    const double* zu, const double* lls, const double* lus);
+
 /* Getters, the mirror of the setters (Section 1): copies into caller arrays
  * with the given leading dimensions; Q and R are returned in full, box index
  * lists in their stored order.  NULL pointers skip a field. */
@@ -147,6 +162,8 @@ int oqp_qp_get_cost(const oqp_qp* qp, int n, double* Q, int ldq, double* S, int 
 int oqp_qp_get_box_u(const oqp_qp* qp, int n, int* idx, double* lo, double* hi);
 int oqp_qp_get_box_x(const oqp_qp* qp, int n, int* idx, double* lo, double* hi);
 int oqp_qp_get_general(const oqp_qp* qp, int n, double* D, int ldd, double* C, int ldc, double* lo, double* hi);
+int oqp_qp_get_soft(const oqp_qp* qp, int n, int* idxs, double* Zl, double* Zu, double* zl, double* zu, double* lls,
+                    double* lus);
 
 /* ---- arguments ----------------------------------------------------------- */
 void oqp_arg_default(oqp_arg* arg, int mode);
@@ -203,6 +220,35 @@ int oqp_batch_sync(oqp_batch* batch);
 int oqp_batch_get_stat(const oqp_batch* batch, int i, oqp_stat* stat);
 int oqp_batch_get_sol(const oqp_batch* batch, int i, double* u, double* x, double* pi, double* lam_l, double* lam_u,
                       double* t_l, double* t_u);
+
+/* ---- soft constraints (Section 2.2) --------------------------------------- */
+/* A batch in which some instance has slacks solves every instance with the
+ * block kernel's soft build: the FP64 delta formulation, each slack pair
+ * eliminated with its bounds row by row (the Riccati recursion sees the row
+ * weight w (Z + w_s) / (Z + w + w_s), the slack step follows from the state
+ * and input step), cost linear in the number of slacks.  Such a batch needs
+ * arg.mode OQP_MODE_F64, warm_start 0 and cond_N 0 (OQP_EINVAL otherwise);
+ * the server and oqp_pack take no slacks.  The duality measure and
+ * oqp_stat.res count the slack rows: r_g includes the slack stationarity
+ * rows, r_d the slack bounds, lam .* t their complementarity.
+ *
+ * Slack blocks of instance i after fetch + sync, each of length sum ns_n,
+ * stage by stage in idxs order: s^l, s^u, the multipliers and slacks of
+ * s^l >= lls and s^u >= lus.  Any pointer may be NULL; a batch without slacks
+ * writes nothing. */
+int oqp_batch_get_soft_sol(const oqp_batch* batch, int i, double* s_l, double* s_u, double* lam_sl, double* lam_su,
+                           double* t_sl, double* t_su);
+/* Slack blocks of the iterate of instance i on the host (after
+ * oqp_batch_set_iterate, which clears them): the point of oqp_batch_newton.
+ * OQP_ESTATE on a batch without slacks. */
+int oqp_batch_set_soft_iterate(oqp_batch* batch, int i, const double* s_l, const double* s_u, const double* lam_sl,
+                               const double* lam_su, const double* t_sl, const double* t_su);
+/* Slack blocks of the Newton step of instance i (after oqp_batch_newton,
+ * fetch + sync). */
+int oqp_batch_get_soft_step(const oqp_batch* batch, int i, double* ds_l, double* ds_u, double* dlam_sl,
+                            double* dlam_su, double* dt_sl, double* dt_su);
+/* Number of slack pairs of instance i (>= 0), or OQP_EINVAL. */
+int oqp_batch_nsoft(const oqp_batch* batch, int i);
 
 /* ---- partial condensing (Section 3.5) ------------------------------------ */
 /* A batch whose arg has cond_N > 0 solves each instance through partial

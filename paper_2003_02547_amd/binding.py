@@ -74,6 +74,13 @@ def lib():
         "oqp_dims_bytes": (ct.c_size_t, [ct.c_int]),
         "oqp_dims_init": (ct.c_int, [_V, ct.c_size_t, ct.c_int, ct.POINTER(_V)]),
         "oqp_dims_set_stage": (ct.c_int, [_V, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int]),
+        "oqp_dims_set_soft": (ct.c_int, [_V, ct.c_int, ct.c_int]),
+        "oqp_qp_set_soft": (ct.c_int, [_V, ct.c_int, _PI, _P, _P, _P, _P, _P, _P]),
+        "oqp_qp_get_soft": (ct.c_int, [_V, ct.c_int, _PI, _P, _P, _P, _P, _P, _P]),
+        "oqp_batch_get_soft_sol": (ct.c_int, [_V, ct.c_int, _P, _P, _P, _P, _P, _P]),
+        "oqp_batch_set_soft_iterate": (ct.c_int, [_V, ct.c_int, _P, _P, _P, _P, _P, _P]),
+        "oqp_batch_get_soft_step": (ct.c_int, [_V, ct.c_int, _P, _P, _P, _P, _P, _P]),
+        "oqp_batch_nsoft": (ct.c_int, [_V, ct.c_int]),
         "oqp_qp_bytes": (ct.c_size_t, [_V]),
         "oqp_qp_init": (ct.c_int, [_V, _V, ct.c_size_t, ct.POINTER(_V)]),
         "oqp_qp_set_dyn": (ct.c_int, [_V, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P]),
@@ -191,11 +198,19 @@ def default_arg(mode: int = MODE_F64, **overrides) -> Arg:
 
 
 class _DimsC(ct.Structure):
-    _fields_ = [("N", ct.c_int)] + [(k, ct.POINTER(ct.c_int)) for k in ("nx", "nu", "nbu", "nbx", "ng")]
+    _fields_ = [("N", ct.c_int)] + [(k, ct.POINTER(ct.c_int)) for k in ("nx", "nu", "nbu", "nbx", "ng", "ns")]
+
+
+SOFT_FIELDS = ("Zl", "Zu", "zl", "zu", "lls", "lus")
+SOFT_KEYS = ("s_l", "s_u", "lam_sl", "lam_su", "t_sl", "t_su")
+
+
+def _has_soft(qp) -> bool:
+    return getattr(qp, "idxs", None) is not None and any(len(i) for i in qp.idxs)
 
 
 class Dims:
-    def __init__(self, N: int, nx, nu, nbu, nbx, ng):
+    def __init__(self, N: int, nx, nu, nbu, nbx, ng, ns=None):
         L = lib()
         self.N = N
         self.mem = _aligned(L.oqp_dims_bytes(N))
@@ -204,10 +219,13 @@ class Dims:
         self.h = h
         for n in range(N + 1):
             _check(L.oqp_dims_set_stage(h, n, int(nx[n]), int(nu[n]), int(nbu[n]), int(nbx[n]), int(ng[n])))
+            if ns is not None:
+                _check(L.oqp_dims_set_soft(h, n, int(ns[n])))
 
     @classmethod
     def of(cls, qp) -> "Dims":
-        return cls(qp.N, qp.nx, qp.nu, qp.nbu, qp.nbx, qp.ng)
+        ns = [len(i) for i in qp.idxs] if getattr(qp, "idxs", None) is not None else None
+        return cls(qp.N, qp.nx, qp.nu, qp.nbu, qp.nbx, qp.ng, ns)
 
     @classmethod
     def condensed(cls, qp, cond_N: int) -> "Dims":
@@ -224,7 +242,7 @@ class Dims:
 
     def sizes(self):
         c = ct.cast(self.h, ct.POINTER(_DimsC)).contents
-        return {k: [getattr(c, k)[n] for n in range(self.N + 1)] for k in ("nx", "nu", "nbu", "nbx", "ng")}
+        return {k: [getattr(c, k)[n] for n in range(self.N + 1)] for k in ("nx", "nu", "nbu", "nbx", "ng", "ns")}
 
 
 class Qp:
@@ -256,6 +274,10 @@ class Qp:
             if ng:
                 D, C = _f64(qp.D[n]), _f64(qp.C[n])
                 _check(L.oqp_qp_set_general(h, n, _p(D), ng, _p(C), ng, _p(_f64(qp.lg[n])), _p(_f64(qp.ug[n]))))
+            if getattr(qp, "idxs", None) is not None and len(qp.idxs[n]):
+                js = np.ascontiguousarray(qp.idxs[n], dtype=np.int32)
+                vals = [_f64(getattr(qp, k)[n]) for k in SOFT_FIELDS]
+                _check(L.oqp_qp_set_soft(h, n, js.ctypes.data_as(_PI), *[_p(v) for v in vals]))
 
 
 @dataclass
@@ -346,10 +368,19 @@ class Batch:
                 (("u", nu), ("x", nx), ("pi", npi), ("lam_l", nc), ("lam_u", nc), ("t_l", nc), ("t_u", nc))}, \
             dict(u=nu, x=nx, pi=npi, lam_l=nc, lam_u=nc, t_l=nc, t_u=nc)
 
+    def _soft_vec(self, i):
+        ns = int(sum(len(j) for j in self.qps[i].idxs)) if _has_soft(self.qps[i]) else 0
+        return ns, {k: np.zeros(max(ns, 1)) for k in SOFT_KEYS}
+
     def solution(self, i: int) -> dict:
         v, sz = self._alloc_vec(i)
         _check(lib().oqp_batch_get_sol(self.h, i, *[_p(v[k]) for k in ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")]))
-        return {k: v[k][:sz[k]].copy() for k in v}
+        out = {k: v[k][:sz[k]].copy() for k in v}
+        if _has_soft(self.qps[i]):
+            ns, sv = self._soft_vec(i)
+            _check(lib().oqp_batch_get_soft_sol(self.h, i, *[_p(sv[k]) for k in SOFT_KEYS]))
+            out.update({k: sv[k][:ns].copy() for k in SOFT_KEYS})
+        return out
 
     def result(self, i: int) -> Result:
         st = self.stat(i)
@@ -363,6 +394,11 @@ class Batch:
         for k in v:
             v[k][:sz[k]] = np.asarray(it[k], dtype=np.float64)[:sz[k]]
         _check(lib().oqp_batch_set_iterate(self.h, i, *[_p(v[k]) for k in ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")]))
+        if _has_soft(self.qps[i]):
+            ns, sv = self._soft_vec(i)
+            for k in SOFT_KEYS:
+                sv[k][:ns] = np.asarray(it[k], dtype=np.float64)[:ns]
+            _check(lib().oqp_batch_set_soft_iterate(self.h, i, *[_p(sv[k]) for k in SOFT_KEYS]))
 
     def newton(self, tau: float = 0.0):
         _check(lib().oqp_batch_newton(self.h, ct.c_double(tau)))
@@ -371,7 +407,12 @@ class Batch:
     def step(self, i: int) -> dict:
         v, sz = self._alloc_vec(i)
         _check(lib().oqp_batch_get_step(self.h, i, *[_p(v[k]) for k in ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")]))
-        return {k: v[k][:sz[k]].copy() for k in v}
+        out = {k: v[k][:sz[k]].copy() for k in v}
+        if _has_soft(self.qps[i]):
+            ns, sv = self._soft_vec(i)
+            _check(lib().oqp_batch_get_soft_step(self.h, i, *[_p(sv[k]) for k in SOFT_KEYS]))
+            out.update({k: sv[k][:ns].copy() for k in SOFT_KEYS})
+        return out
 
     def variant(self, i: int):
         a, b, c = ct.c_int(), ct.c_int(), ct.c_int()
@@ -421,6 +462,13 @@ def qp_fields(h, dims: Dims):
         lg, ug = np.zeros(max(ng, 1)), np.zeros(max(ng, 1))
         _check(L.oqp_qp_get_general(h, n, _p(D), max(ng, 1), _p(C), max(ng, 1), _p(lg), _p(ug)))
         out["D"].append(D); out["C"].append(C); out["lg"].append(lg[:ng].copy()); out["ug"].append(ug[:ng].copy())
+        ns = sz["ns"][n]
+        js = np.zeros(max(ns, 1), dtype=np.int32)
+        sv = [np.zeros(max(ns, 1)) for _ in SOFT_FIELDS]
+        _check(L.oqp_qp_get_soft(h, n, js.ctypes.data_as(_PI), *[_p(v) for v in sv]))
+        out.setdefault("idxs", []).append(js[:ns].copy())
+        for k, v in zip(SOFT_FIELDS, sv):
+            out.setdefault(k, []).append(v[:ns].copy())
     import types
     return types.SimpleNamespace(N=N, nx=sz["nx"], nu=sz["nu"], **out)
 
@@ -627,5 +675,6 @@ EXPORTED = [
     "oqp_batch_fill_sol", "oqp_server_fill_sol", "oqp_sol_get_stat", "oqp_res_get_norms",
     "oqp_qp_get_dyn", "oqp_qp_get_cost", "oqp_qp_get_box_u", "oqp_qp_get_box_x", "oqp_qp_get_general",
     "oqp_pcond_dims_bytes", "oqp_pcond_dims", "oqp_batch_fetch_cond", "oqp_batch_get_cond_qp",
-    "oqp_batch_set_streams", "oqp_batch_release",
+    "oqp_batch_set_streams", "oqp_batch_release", "oqp_dims_set_soft", "oqp_qp_set_soft", "oqp_qp_get_soft",
+    "oqp_batch_get_soft_sol", "oqp_batch_set_soft_iterate", "oqp_batch_get_soft_step", "oqp_batch_nsoft",
 ] + ["oqp_sol_get_" + g for g in SOL_FIELDS]

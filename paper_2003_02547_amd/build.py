@@ -25,7 +25,8 @@ FLAGS = [
 
 
 def sources():
-    units = sorted(glob.glob(os.path.join(CSRC, "ipm_v*.hip"))) + [os.path.join(CSRC, "ipm_block.hip")]
+    units = sorted(glob.glob(os.path.join(CSRC, "ipm_v*.hip"))) + [os.path.join(CSRC, f)
+                                                                    for f in ("ipm_block.hip", "ipm_block_soft.hip")]
     return units + [os.path.join(CSRC, f) for f in ("ipm_registry.hip", "pcond.hip", "capi.cpp", "serve.cpp", "sol.cpp")]
 
 

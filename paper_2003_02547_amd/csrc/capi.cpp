@@ -39,7 +39,7 @@ extern "C" const char* oqp_last_error(void) { return g_err; }
 extern "C" size_t oqp_dims_bytes(int N)
 {
     if (N < 1) return 0;
-    return align_up(sizeof(oqp_dims), 16) + align_up(5 * (size_t)(N + 1) * sizeof(int), 16);
+    return align_up(sizeof(oqp_dims), 16) + align_up(6 * (size_t)(N + 1) * sizeof(int), 16);
 }
 
 extern "C" int oqp_dims_init(void* mem, size_t bytes, int N, oqp_dims** out)
@@ -49,14 +49,42 @@ extern "C" int oqp_dims_init(void* mem, size_t bytes, int N, oqp_dims** out)
     if ((uintptr_t)mem % 8) return fail(OQP_EINVAL, "oqp_dims_init: memory not 8-byte aligned");
     oqp_dims* d = (oqp_dims*)mem;
     int* a = (int*)((char*)mem + align_up(sizeof(oqp_dims), 16));
-    std::memset(a, 0, 5 * (size_t)(N + 1) * sizeof(int));
+    std::memset(a, 0, 6 * (size_t)(N + 1) * sizeof(int));
     d->N = N;
     d->nx = a;
     d->nu = a + (N + 1);
     d->nbu = a + 2 * (N + 1);
     d->nbx = a + 3 * (N + 1);
     d->ng = a + 4 * (N + 1);
+    d->ns = a + 5 * (N + 1);
     *out = d;
+    return OQP_OK;
+}
+
+extern "C" int oqp_dims_set_soft(oqp_dims* d, int n, int ns)
+{
+    if (!d || n < 0 || n > d->N) return fail(OQP_EINVAL, "oqp_dims_set_soft: stage %d out of range", n);
+    if (ns < 0 || ns > d->nbu[n] + d->nbx[n] + d->ng[n])
+        return fail(OQP_EINVAL, "oqp_dims_set_soft: %d slacks at stage %d with %d constraint rows", ns, n,
+                    d->nbu[n] + d->nbx[n] + d->ng[n]);
+    d->ns[n] = ns;
+    return OQP_OK;
+}
+
+bool dims_soft(const oqp_dims* d)
+{
+    for (int n = 0; n <= d->N; ++n)
+        if (d->ns[n] > 0) return true;
+    return false;
+}
+
+// slack counts that no longer fit the stage's rows (stage sizes set after them)
+static int check_soft_dims(const oqp_dims* d, const char* who)
+{
+    for (int n = 0; n <= d->N; ++n)
+        if (d->ns[n] > d->nbu[n] + d->nbx[n] + d->ng[n])
+            return fail(OQP_EINVAL, "%s: %d slacks at stage %d exceed its %d constraint rows", who, d->ns[n], n,
+                        d->nbu[n] + d->nbx[n] + d->ng[n]);
     return OQP_OK;
 }
 
@@ -95,6 +123,7 @@ static void stage_sizes(const oqp_dims* d, int n, size_t* sz)
     sz[F_D] = (size_t)ng * nu;
     sz[F_C] = (size_t)ng * nx;
     sz[F_lg] = sz[F_ug] = ng;
+    sz[F_Zl] = sz[F_Zu] = sz[F_zl] = sz[F_zu] = sz[F_lls] = sz[F_lus] = d->ns[n];
 }
 
 static void qp_offsets(const oqp_dims* dims, int64_t* doff, int64_t* ioff)
@@ -106,7 +135,7 @@ static void qp_offsets(const oqp_dims* dims, int64_t* doff, int64_t* ioff)
         ioff[n] = oi;
         stage_sizes(dims, n, sz);
         for (int f = 0; f < F_COUNT; ++f) od += (int64_t)sz[f];
-        oi += dims->nbu[n] + dims->nbx[n];
+        oi += dims->nbu[n] + dims->nbx[n] + dims->ns[n];
     }
     doff[dims->N + 1] = od;
     ioff[dims->N + 1] = oi;
@@ -123,7 +152,7 @@ extern "C" size_t oqp_qp_bytes(const oqp_dims* dims)
     for (int n = 0; n <= N; ++n) {
         stage_sizes(dims, n, sz);
         for (int f = 0; f < F_COUNT; ++f) od += (int64_t)sz[f];
-        oi += dims->nbu[n] + dims->nbx[n];
+        oi += dims->nbu[n] + dims->nbx[n] + dims->ns[n];
     }
     return align_up(sizeof(oqp_qp), 16) + 2 * align_up((size_t)(N + 2) * sizeof(int64_t), 16) +
            align_up((size_t)od * sizeof(double), 16) + align_up((size_t)oi * sizeof(int), 16);
@@ -135,6 +164,7 @@ extern "C" int oqp_qp_init(const oqp_dims* dims, void* mem, size_t bytes, oqp_qp
     const size_t need = oqp_qp_bytes(dims);
     if (bytes < need) return fail(OQP_ENOMEM, "oqp_qp_init: %zu bytes < %zu", bytes, need);
     if ((uintptr_t)mem % 16) return fail(OQP_EINVAL, "oqp_qp_init: memory not 16-byte aligned");
+    if (int rc = check_soft_dims(dims, "oqp_qp_init")) return rc;
     std::memset(mem, 0, need);
     const int N = dims->N;
     char* p = (char*)mem;
@@ -361,6 +391,45 @@ extern "C" int oqp_qp_get_general(const oqp_qp* q, int n, double* D, int ldd, do
     return OQP_OK;
 }
 
+// Soft constraints of stage n (Section 2.2): ns_n distinct row indices into
+// the stage's rows [box u, box x, general] and the data of each slack pair.
+extern "C" int oqp_qp_set_soft(oqp_qp* q, int n, const int* idxs, const double* Zl, const double* Zu,
+                               const double* zl, const double* zu, const double* lls, const double* lus)
+{
+    if (!q || n < 0 || n > q->dims->N) return fail(OQP_EINVAL, "oqp_qp_set_soft: stage %d out of range", n);
+    const oqp_dims* d = q->dims;
+    const int ns = d->ns[n], nc = d->nbu[n] + d->nbx[n] + d->ng[n];
+    if (ns == 0) return OQP_OK;
+    if (!idxs || !Zl || !Zu || !zl || !zu || !lls || !lus) return fail(OQP_EINVAL, "oqp_qp_set_soft: NULL argument");
+    for (int j = 0; j < ns; ++j) {
+        if (idxs[j] < 0 || idxs[j] >= nc)
+            return fail(OQP_EINVAL, "oqp_qp_set_soft: row %d out of range [0, %d) at stage %d", idxs[j], nc, n);
+        for (int j2 = 0; j2 < j; ++j2)
+            if (idxs[j2] == idxs[j]) return fail(OQP_EINVAL, "oqp_qp_set_soft: row %d repeated at stage %d", idxs[j], n);
+        if (!(Zl[j] >= 0.0) || !(Zu[j] >= 0.0) || !std::isfinite(Zl[j]) || !std::isfinite(Zu[j]))
+            return fail(OQP_EINVAL, "oqp_qp_set_soft: slack Hessian %d at stage %d not finite and >= 0", j, n);
+        if (!std::isfinite(zl[j]) || !std::isfinite(zu[j]) || !std::isfinite(lls[j]) || !std::isfinite(lus[j]))
+            return fail(OQP_EINVAL, "oqp_qp_set_soft: slack data %d at stage %d not finite", j, n);
+    }
+    std::memcpy(q->idx + q->ioff[n] + d->nbu[n] + d->nbx[n], idxs, sizeof(int) * ns);
+    const double* src[6] = {Zl, Zu, zl, zu, lls, lus};
+    for (int f = 0; f < 6; ++f) std::memcpy(qp_field(q, n, F_Zl + f), src[f], sizeof(double) * ns);
+    return OQP_OK;
+}
+
+extern "C" int oqp_qp_get_soft(const oqp_qp* q, int n, int* idxs, double* Zl, double* Zu, double* zl, double* zu,
+                               double* lls, double* lus)
+{
+    if (!q || n < 0 || n > q->dims->N) return fail(OQP_EINVAL, "oqp_qp_get_soft: stage %d out of range", n);
+    const oqp_dims* d = q->dims;
+    const int ns = d->ns[n];
+    if (idxs) std::memcpy(idxs, q->idx + q->ioff[n] + d->nbu[n] + d->nbx[n], sizeof(int) * ns);
+    double* dst[6] = {Zl, Zu, zl, zu, lls, lus};
+    for (int f = 0; f < 6; ++f)
+        if (dst[f]) std::memcpy(dst[f], qp_field(q, n, F_Zl + f), sizeof(double) * ns);
+    return OQP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // arguments
 // ---------------------------------------------------------------------------
@@ -417,6 +486,9 @@ struct Inst {
     int onx, onu, ong;   // record sizes of the original QP
     int64_t odata;       // original data records (into hdata/ddata, or the condensing regions)
     int64_t oiter;       // original-layout iterate records
+    int soft;            // soft layout (the batch has slacks)
+    int nsoft;           // slack pairs of the instance
+    int soft_off;        // into soft pool: ns per stage (oN+1), then the device slot of each slack
 };
 
 struct oqp_batch {
@@ -438,6 +510,8 @@ struct oqp_batch {
     Inst* inst;
     int* dims_pool;
     int* slot_pool;
+    int soft;        // some instance has slacks: every instance solved by the block kernel's soft build
+    int* soft_pool;
     InstDesc* hdesc;
     DevStat* hstat;
     double* hdata;
@@ -524,6 +598,8 @@ static void dims_max(const oqp_dims* d, int* mx, int* mu, int* mg)
     }
 }
 
+static int select_block_max(int mx, int mu, int mg, KSel* out);
+
 // kernel for an instance whose largest stage sizes are mx, mu, mg
 static int select_kernel_max(int mx, int mu, int mg, KSel* out)
 {
@@ -536,6 +612,12 @@ static int select_kernel_max(int mx, int mu, int mg, KSel* out)
             return OQP_OK;
         }
     }
+    return select_block_max(mx, mu, mg, out);
+}
+
+// the block kernel build for the largest stage sizes
+static int select_block_max(int mx, int mu, int mg, KSel* out)
+{
     if (mx < 1) mx = 1;
     const int zm = oqp::block_zmax(mx + mu);
     // one thread per row and per constraint slot; the u block is solved on
@@ -624,8 +706,10 @@ static constexpr size_t kMaxCondLds = 64 * 1024;
 // Kernel for the largest stage sizes under a solver mode: the QR-based
 // factorization is built for the one-wave variants only, which then cover
 // the instance whatever the one-wave bound.
-static int select_for_mode(int mx, int mu, int mg, int mode, KSel* out)
+static int select_for_mode(int mx, int mu, int mg, int mode, int soft, KSel* out)
 {
+    // soft constraints are built into the block kernel only
+    if (soft) return select_block_max(mx, mu, mg, out);
     if (mode != OQP_MODE_ROBUST) return select_kernel_max(mx, mu, mg, out);
     const int v = pick_variant_max(mx, mu, mg);
     if (v < 0) return -1;
@@ -635,15 +719,16 @@ static int select_for_mode(int mx, int mu, int mg, int mode, KSel* out)
     return OQP_OK;
 }
 
-static int solve_shape(const oqp_dims* d, int cond_N, int mode, SolveShape* sh, int i)
+static int solve_shape(const oqp_dims* d, int cond_N, int mode, int soft, SolveShape* sh, int i)
 {
     if (cond_N <= 0) {
         sh->N = d->N;
         int mx, mu, mg;
         dims_max(d, &mx, &mu, &mg);
-        if (select_for_mode(mx, mu, mg, mode, &sh->ks))
+        if (select_for_mode(mx, mu, mg, mode, soft, &sh->ks))
             return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d%s", i,
-                        mode == OQP_MODE_ROBUST ? " (robust mode: one-wave variants only)" : "");
+                        mode == OQP_MODE_ROBUST ? " (robust mode: one-wave variants only)"
+                                                : (soft ? " (soft constraints: block kernel only)" : ""));
         sh->onx = sh->ks.nx;
         sh->onu = sh->ks.nu;
         sh->ong = sh->ks.ng;
@@ -659,7 +744,7 @@ static int solve_shape(const oqp_dims* d, int cond_N, int mode, SolveShape* sh, 
         if (c.ng > cg) cg = c.ng;
     }
     sh->N = N2;
-    if (select_for_mode(cx, cu, cg, mode, &sh->ks))
+    if (select_for_mode(cx, cu, cg, mode, 0, &sh->ks))
         return fail(OQP_EINVAL, "batch: no kernel covers the condensed stage sizes of instance %d (nx %d, nu %d, ng %d)",
                     i, cx, cu, cg);
     if ((size_t)oqp::cond_lds_bytes(sh->onx, sh->onu, sh->ks.nx + sh->ks.nu) > kMaxCondLds)
@@ -709,7 +794,25 @@ struct Plan {
     int64_t n_data, n_iter, n_work, n_odata, n_oiter;
     int n_dims, n_slot, n_items, n_tab;
     size_t cond_lds;
+    int soft;
+    size_t h_soft;
+    int n_soft;
 };
+
+// A batch with slacks anywhere: FP64 delta formulation from a cold start,
+// without condensing.
+static int batch_soft(const oqp_dims* const* dims, int count, const oqp_arg* arg, int* soft)
+{
+    *soft = 0;
+    for (int i = 0; i < count; ++i)
+        if (dims[i] && dims_soft(dims[i])) *soft = 1;
+    if (!*soft) return OQP_OK;
+    if (arg->mode != OQP_MODE_F64 || arg->warm_start != 0 || arg->cond_N != 0)
+        return fail(OQP_EINVAL, "batch: soft constraints need the FP64 mode, a cold start and no condensing");
+    for (int i = 0; i < count; ++i)
+        if (dims[i] && check_soft_dims(dims[i], "batch")) return OQP_EINVAL;
+    return OQP_OK;
+}
 
 static int make_plan(const oqp_dims* const* dims, int count, const oqp_arg* arg, Plan* pl)
 {
@@ -718,15 +821,21 @@ static int make_plan(const oqp_dims* const* dims, int count, const oqp_arg* arg,
     const int nv = group_count();
     const int cond = cond_N > 0;
     int64_t nd = 0, ni = 0, nw = 0, nod = 0, noi = 0;
-    int ndims = 0, nslot = 0, nitems = 0, ntab = 0;
+    int ndims = 0, nslot = 0, nitems = 0, ntab = 0, nsoft = 0;
     size_t clds = 0;
+    int soft = 0;
+    if (int rc = batch_soft(dims, count, arg, &soft)) return rc;
     for (int i = 0; i < count; ++i) {
         const oqp_dims* d = dims[i];
         if (!d) return fail(OQP_EINVAL, "batch: dims[%d] is NULL", i);
         SolveShape sh;
-        int rc = solve_shape(d, cond_N, arg->mode, &sh, i);
+        int rc = solve_shape(d, cond_N, arg->mode, soft, &sh, i);
         if (rc) return rc;
-        const Layout L = oqp::make_layout(sh.ks.nx, sh.ks.nu, sh.ks.ng);
+        const Layout L = oqp::make_layout(sh.ks.nx, sh.ks.nu, sh.ks.ng, soft);
+        if (soft) {
+            nsoft += d->N + 1;
+            for (int n = 0; n <= d->N; ++n) nsoft += d->ns[n];
+        }
         nd += (int64_t)(sh.N + 1) * L.SREC;
         ni += (int64_t)(sh.N + 1) * L.IREC;
         nw += (int64_t)(sh.N + 1) * L.WREC;
@@ -759,6 +868,7 @@ static int make_plan(const oqp_dims* const* dims, int count, const oqp_arg* arg,
     pl->h_cdesc = h; h = align_up(h + sizeof(oqp::CondDesc) * (cond ? count : 0), 64);
     pl->h_items = h; h = align_up(h + sizeof(oqp::CondItem) * nitems, 64);
     pl->h_tab = h; h = align_up(h + sizeof(int) * ntab, 64);
+    pl->h_soft = h; h = align_up(h + sizeof(int) * nsoft, 64);
     pl->host_bytes = h;
     size_t g = 0;
     pl->d_desc = g; g = align_up(g + sizeof(InstDesc) * count, 256);
@@ -778,6 +888,8 @@ static int make_plan(const oqp_dims* const* dims, int count, const oqp_arg* arg,
     pl->n_dims = ndims; pl->n_slot = nslot;
     pl->n_items = nitems; pl->n_tab = ntab;
     pl->cond_lds = clds;
+    pl->soft = soft;
+    pl->n_soft = nsoft;
     return OQP_OK;
 }
 
@@ -794,9 +906,9 @@ extern "C" int oqp_batch_bytes(const oqp_dims* const* dims, int count, const oqp
     return OQP_OK;
 }
 
-static const Layout inst_layout(const Inst& in) { return oqp::make_layout(in.nx, in.nu, in.ng); }
+static const Layout inst_layout(const Inst& in) { return oqp::make_layout(in.nx, in.nu, in.ng, in.soft); }
 // records of the QP as given (the solved records without condensing)
-static const Layout orig_layout(const Inst& in) { return oqp::make_layout(in.onx, in.onu, in.ong); }
+static const Layout orig_layout(const Inst& in) { return oqp::make_layout(in.onx, in.onu, in.ong, in.soft); }
 
 extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_arg* arg, void* host_mem,
                               size_t host_bytes, void* dev_mem, size_t dev_bytes, void* stream, oqp_batch** out)
@@ -853,14 +965,16 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
     b->dcdesc = (oqp::CondDesc*)(g + pl.d_cdesc);
     b->ditems = (oqp::CondItem*)(g + pl.d_items);
     b->dtab = (int*)(g + pl.d_tab);
+    b->soft = pl.soft;
+    b->soft_pool = (int*)(h + pl.h_soft);
     // instances, grouped by variant
-    int doff = 0, soff = 0;
+    int doff = 0, soff = 0, ssoff = 0;
     for (int v = 0; v < b->nvar; ++v) b->vcount[v] = 0;
     for (int i = 0; i < count; ++i) {
         Inst& in = b->inst[i];
         const oqp_dims* d = dims[i];
         SolveShape sh;
-        solve_shape(d, arg->cond_N, arg->mode, &sh, i);
+        solve_shape(d, arg->cond_N, arg->mode, pl.soft, &sh, i);
         const KSel& ks = sh.ks;
         in.variant = ks.group;
         in.nx = ks.nx;
@@ -885,6 +999,16 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
         in.nc = nc;
         doff += 5 * (d->N + 1);
         soff += nc;
+        in.soft = pl.soft;
+        in.nsoft = 0;
+        in.soft_off = ssoff;
+        if (pl.soft) {
+            for (int n = 0; n <= d->N; ++n) {
+                b->soft_pool[ssoff + n] = d->ns[n];
+                in.nsoft += d->ns[n];
+            }
+            ssoff += d->N + 1 + in.nsoft;
+        }
         b->vcount[in.variant]++;
     }
     int acc = 0;
@@ -919,7 +1043,7 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
             ds.iter = in.iter;
             ds.work = in.work;
             ds.N = in.N;
-            ds.nc = in.nc;
+            ds.nc = in.nc + in.nsoft;  // one-sided rows / 2: constraint rows and slack bounds
             ds.index = i;
             ds.pad = 0;
             ds.nx = in.nx;
@@ -987,13 +1111,14 @@ static inline const int* inst_dims(const oqp_batch* b, const Inst& in, int which
 
 // Pack a QP into N+1 padded stage records (L.SREC doubles each) at dst and
 // fill the map from user constraint order to padded slot (nc entries).
-int pack_records(const oqp_qp* q, const Layout& L, double* dst, int* slots)
+int pack_records(const oqp_qp* q, const Layout& L, double* dst, int* slots, int* sslots)
 {
     const oqp_dims* qd = q->dims;
     const int N = qd->N;
     const int NX = L.NX, NU = L.NU, NZ = L.NZ;
-    int so = 0;
+    int so = 0, sso = 0;
     for (int n = 0; n <= N; ++n) {
+        const int so0 = so;
         double* r = dst + (int64_t)n * L.SREC;
         std::memset(r, 0, sizeof(double) * L.SREC);
         const int nx = qd->nx[n], nu = qd->nu[n], nxn = n < N ? qd->nx[n + 1] : 0, ng = qd->ng[n];
@@ -1071,6 +1196,19 @@ int pack_records(const oqp_qp* q, const Layout& L, double* dst, int* slots)
                 slots[so++] = NZ + k;
             }
         }
+        // soft constraints: slot mask and the slack data of each softened slot
+        const int ns = qd->ns[n];
+        if (ns > 0) {
+            if (!L.SOFT) return fail(OQP_EINVAL, "pack: stage %d has slacks but the records have no slack blocks", n);
+            const int* is = q->idx + q->ioff[n] + qd->nbu[n] + qd->nbx[n];
+            const int offs[6] = {L.D_Zl, L.D_Zu, L.D_zl, L.D_zu, L.D_lls, L.D_lus};
+            for (int j = 0; j < ns; ++j) {
+                const int c = slots[so0 + is[j]];
+                r[L.D_sm + c] = 1.0;
+                for (int f = 0; f < 6; ++f) r[offs[f] + c] = qp_field(q, n, F_Zl + f)[j];
+                if (sslots) sslots[sso++] = c;
+            }
+        }
     }
     return OQP_OK;
 }
@@ -1090,7 +1228,12 @@ static int pack_instance(oqp_batch* b, int i, const oqp_qp* q)
         if (qd->nx[n] != nxv[n] || qd->nu[n] != nuv[n] || qd->nbu[n] != nbuv[n] || qd->nbx[n] != nbxv[n] ||
             qd->ng[n] != ngv[n])
             return fail(OQP_EINVAL, "oqp_batch_load: qp %d sizes differ from its dims at stage %d", i, n);
-    return pack_records(q, L, (b->cond ? b->hodata : b->hdata) + in.odata, b->slot_pool + in.slot_off);
+    int* sp = in.soft ? b->soft_pool + in.soft_off : nullptr;
+    for (int n = 0; n <= in.oN; ++n)
+        if (qd->ns[n] != (sp ? sp[n] : 0))
+            return fail(OQP_EINVAL, "oqp_batch_load: qp %d slack count differs from its dims at stage %d", i, n);
+    return pack_records(q, L, (b->cond ? b->hodata : b->hdata) + in.odata, b->slot_pool + in.slot_off,
+                        sp ? sp + in.oN + 1 : nullptr);
 }
 
 extern "C" int oqp_batch_load(oqp_batch* b, const oqp_qp* const* qps)
@@ -1155,7 +1298,7 @@ static void* group_stream(const oqp_batch* b, int v)
 
 static int launch_all(oqp_batch* b, const oqp::KParams& P)
 {
-    const int km = kernel_build(b->arg.mode);
+    const int km = b->soft ? oqp::KM_SOFT : kernel_build(b->arg.mode);
     hipError_t e = hipSuccess;
     if (b->naux > 0) {
         e = hipEventRecord((hipEvent_t)b->ev_fork, (hipStream_t)b->stream);
@@ -1261,6 +1404,8 @@ extern "C" int oqp_batch_set_arg(oqp_batch* b, const oqp_arg* a)
     if (rc) return rc;
     if (a->mode != b->arg.mode) return fail(OQP_EINVAL, "oqp_batch_set_arg: mode cannot change");
     if (a->cond_N != b->arg.cond_N) return fail(OQP_EINVAL, "oqp_batch_set_arg: cond_N cannot change");
+    if (b->soft && a->warm_start != 0)
+        return fail(OQP_EINVAL, "oqp_batch_set_arg: no warm start on a batch with soft constraints");
     b->arg = *a;
     return OQP_OK;
 }
@@ -1390,6 +1535,69 @@ extern "C" int oqp_batch_set_iterate(oqp_batch* b, int i, const double* u, const
               (double*)t_l, (double*)t_u);
     b->iter_dirty = 1;
     return OQP_OK;
+}
+
+// Slack blocks of instance i between its iterate records in `region` and
+// the user layout (stage by stage in idxs order).
+static void soft_user_copy(const oqp_batch* b, int i, double* region, bool to_user, double* const vals[6])
+{
+    const Inst& in = b->inst[i];
+    const Layout L = orig_layout(in);
+    const int* nsv = b->soft_pool + in.soft_off;
+    const int* cs = nsv + in.oN + 1;
+    const int offs[6] = {L.I_sl, L.I_su, L.I_lsl, L.I_lsu, L.I_tsl, L.I_tsu};
+    int o = 0;
+    for (int n = 0; n <= in.oN; ++n) {
+        double* r = region + in.oiter + (int64_t)n * L.IREC;
+        for (int j = 0; j < nsv[n]; ++j, ++o)
+            for (int f = 0; f < 6; ++f) {
+                if (!vals[f]) continue;
+                if (to_user) vals[f][o] = r[offs[f] + cs[o]];
+                else r[offs[f] + cs[o]] = vals[f][o];
+            }
+    }
+}
+
+extern "C" int oqp_batch_get_soft_sol(const oqp_batch* b, int i, double* s_l, double* s_u, double* lam_sl,
+                                      double* lam_su, double* t_sl, double* t_su)
+{
+    if (!b || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_get_soft_sol: bad argument");
+    if (!b->soft) return OQP_OK;
+    double* const v[6] = {s_l, s_u, lam_sl, lam_su, t_sl, t_su};
+    soft_user_copy(b, i, b->hiter, true, v);
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_set_soft_iterate(oqp_batch* b, int i, const double* s_l, const double* s_u,
+                                          const double* lam_sl, const double* lam_su, const double* t_sl,
+                                          const double* t_su)
+{
+    if (!b || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_set_soft_iterate: bad argument");
+    if (!b->soft) return fail(OQP_ESTATE, "oqp_batch_set_soft_iterate: the batch has no slacks");
+    if (b->inst[i].nsoft > 0 && (!s_l || !s_u || !lam_sl || !lam_su || !t_sl || !t_su))
+        return fail(OQP_EINVAL, "oqp_batch_set_soft_iterate: NULL argument");
+    double* const v[6] = {(double*)s_l, (double*)s_u, (double*)lam_sl, (double*)lam_su, (double*)t_sl,
+                          (double*)t_su};
+    soft_user_copy(b, i, b->hiter, false, v);
+    b->iter_dirty = 1;
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_get_soft_step(const oqp_batch* b, int i, double* ds_l, double* ds_u, double* dlam_sl,
+                                       double* dlam_su, double* dt_sl, double* dt_su)
+{
+    if (!b || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_get_soft_step: bad argument");
+    if (!b->has_step) return fail(OQP_ESTATE, "oqp_batch_get_soft_step: no Newton step computed");
+    if (!b->soft) return OQP_OK;
+    double* const v[6] = {ds_l, ds_u, dlam_sl, dlam_su, dt_sl, dt_su};
+    soft_user_copy(b, i, b->hstep, true, v);
+    return OQP_OK;
+}
+
+extern "C" int oqp_batch_nsoft(const oqp_batch* b, int i)
+{
+    if (!b || i < 0 || i >= b->count) return fail(OQP_EINVAL, "oqp_batch_nsoft: bad argument");
+    return b->inst[i].nsoft;
 }
 
 extern "C" int oqp_batch_newton(oqp_batch* b, double tau)

@@ -14,15 +14,18 @@ struct oqp_dims {
     int* nbu;
     int* nbx;
     int* ng;
+    int* ns;  // soft constraints (slack pairs) per stage
 };
 
-// Per-stage double block of a host QP: A, B, b, Q, S, R, q, r, lbu, ubu, lbx, ubx, D, C, lg, ug.
-enum { F_A, F_B, F_b, F_Q, F_S, F_R, F_q, F_r, F_lbu, F_ubu, F_lbx, F_ubx, F_D, F_C, F_lg, F_ug, F_COUNT };
+// Per-stage double block of a host QP: A, B, b, Q, S, R, q, r, lbu, ubu, lbx, ubx, D, C, lg, ug, and the
+// slack data Zl, Zu, zl, zu, lls, lus (ns each).
+enum { F_A, F_B, F_b, F_Q, F_S, F_R, F_q, F_r, F_lbu, F_ubu, F_lbx, F_ubx, F_D, F_C, F_lg, F_ug,
+       F_Zl, F_Zu, F_zl, F_zu, F_lls, F_lus, F_COUNT };
 
 struct oqp_qp {
     const oqp_dims* dims;
     int64_t* doff;  // (N+2) stage offsets into d
-    int64_t* ioff;  // (N+2) stage offsets into idx (idxbu then idxbx)
+    int64_t* ioff;  // (N+2) stage offsets into idx (idxbu, idxbx, then idxs)
     double* d;
     int* idx;
 };
@@ -52,7 +55,7 @@ struct KSel {
 };
 int group_count();
 int select_kernel(const oqp_dims* d, KSel* out);
-// km: kernel build (oqp::KM_F64, KM_MIXED, KM_ABS)
+// km: kernel build (oqp::KM_F64, KM_MIXED, KM_ABS, KM_ROBUST, KM_SOFT)
 int group_launch(int g, int km, const oqp::InstDesc* desc, const oqp::InstDesc* hdesc, int count,
                  const double* data, double* iter, double* work, double* step, oqp::DevStat* stat,
                  const oqp::KParams& P, void* stream);
@@ -70,6 +73,8 @@ int check_arg(const oqp_arg* a);
 int pick_variant(const oqp_dims* d);
 double* qp_field(const oqp_qp* q, int n, int f);
 oqp::KParams make_params(const oqp_arg& a, int mode, double tau);
-int pack_records(const oqp_qp* q, const oqp::Layout& L, double* dst, int* slots);
+// sslots (may be NULL): device slot of each slack, stage by stage in idxs order
+int pack_records(const oqp_qp* q, const oqp::Layout& L, double* dst, int* slots, int* sslots = nullptr);
+bool dims_soft(const oqp_dims* d);
 void iterate_user_copy(const int* dims5, int N, const int* slots, const oqp::Layout& L, double* rec, bool to_user,
                        double* u, double* x, double* pi, double* ll, double* lu, double* tl, double* tu);

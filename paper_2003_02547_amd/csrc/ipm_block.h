@@ -115,6 +115,7 @@ template <int KM, int ZM, int GM, bool GL>
 struct Blk {
     static constexpr bool MIXED = KM == KM_MIXED;
     static constexpr bool ABS = KM == KM_ABS;  // absolute formulation (Section 3.2)
+    static constexpr bool SOFT = KM == KM_SOFT;  // soft constraints (Section 2.2), soft layout
     using TS = typename std::conditional<MIXED, float, double>::type;
     Layout Lo;
     BLds S;
@@ -136,7 +137,7 @@ struct Blk {
     mutable double* cV;
 
     __device__ __forceinline__ Blk(const InstDesc& ds, const double* d, double* i, double* w, const KParams& P_)
-        : Lo(make_layout(ds.nx, ds.nu, ds.ng)), S(make_blds(ds.nx, ds.nu, ds.ng)), NX(ds.nx), NU(ds.nu), NG(ds.ng),
+        : Lo(make_layout(ds.nx, ds.nu, ds.ng, SOFT)), S(make_blds(ds.nx, ds.nu, ds.ng)), NX(ds.nx), NU(ds.nu), NG(ds.ng),
           NZ(ds.nx + ds.nu), NC(ds.nx + ds.nu + ds.ng), NV(ds.nx + ds.ng), dat(d + ds.data), itr(i + ds.iter),
           wk(w + ds.work), N(ds.N), nc(ds.nc), tid((int)threadIdx.x), lane((int)threadIdx.x & 63),
           wid((int)threadIdx.x >> 6), P(P_)
@@ -431,6 +432,48 @@ struct Blk {
         } else {
             m = lo = hi = 0.0;
         }
+    }
+
+    // Slack elimination of a soft slot c (Section 2.2).  The slot's slack
+    // pair (s^l, s^u) enters the lower row as G z + s^l and the upper row as
+    // -G z + s^u, each with its own bound row s >= ls (multiplier lam_s,
+    // slack t_s).  Given the row terms el = (lam_l rd_l - rm_l) / t_l and eu
+    // (same for the upper row) and the barrier weights wl, wu, the slack rows
+    // of the Newton system read
+    //   D_l ds^l + wl G dz = -g_l,   D_u ds^u - wu G dz = -g_u,
+    //   D = Z + w + w_s,  g = r_s - e - e_s,  e_s = (lam_s rd_s - rm_s) / t_s,
+    // so that eliminating ds turns the row terms into e + w g / D (and the
+    // weights into w (Z + w_s) / D, applied in pass A).  r_s, rd_s are read
+    // from the workspace pass A wrote, rm_s per rmode as in slot_rm.
+    struct SoftE {
+        double Dl, Du, gl, gu, lsl, lsu, tsl, tsu, rmsl, rmsu, rdsl, rdsu;
+    };
+    __device__ __forceinline__ SoftE soft_terms(const double* d, const double* ir, const double* w, int c, int rmode,
+                                                double shift, double wl, double wu, double& el, double& eu) const
+    {
+        SoftE q;
+        q.lsl = ir[Lo.I_lsl + c];
+        q.lsu = ir[Lo.I_lsu + c];
+        q.tsl = ir[Lo.I_tsl + c];
+        q.tsu = ir[Lo.I_tsu + c];
+        q.rdsl = w[Lo.W_rdsl + c];
+        q.rdsu = w[Lo.W_rdsu + c];
+        q.rmsl = q.lsl * q.tsl - shift;
+        q.rmsu = q.lsu * q.tsu - shift;
+        if (rmode == RM_CORRECTOR) {
+            q.rmsl += w[Lo.W_alsl + c] * w[Lo.W_atsl + c];
+            q.rmsu += w[Lo.W_alsu + c] * w[Lo.W_atsu + c];
+        }
+        const double itsl = rcp_nr(q.tsl), itsu = rcp_nr(q.tsu);
+        const double esl = (q.lsl * q.rdsl - q.rmsl) * itsl;
+        const double esu = (q.lsu * q.rdsu - q.rmsu) * itsu;
+        q.Dl = d[Lo.D_Zl + c] + wl + q.lsl * itsl;
+        q.Du = d[Lo.D_Zu + c] + wu + q.lsu * itsu;
+        q.gl = w[Lo.W_rsl + c] - el - esl;
+        q.gu = w[Lo.W_rsu + c] - eu - esu;
+        el += wl * q.gl * rcp_nr(q.Dl);
+        eu += wu * q.gu * rcp_nr(q.Du);
+        return q;
     }
 
     // ------------------------------------------------------------------
@@ -802,6 +845,28 @@ struct Blk {
                     tu = fmax(tu + alpha * w[Lo.W_dtu + j], P.t_min);
                 }
             }
+            // slack pair of a soft slot and the multipliers and slacks of its
+            // bounds, after the step (clamped like the rows)
+            double sm = 0.0, sl = 0.0, su = 0.0, lsl = 0.0, lsu = 0.0, tsl = 0.0, tsu = 0.0;
+            if constexpr (SOFT) {
+                if (j < NC) sm = d[Lo.D_sm + j];
+                if (sm != 0.0) {
+                    sl = ir[Lo.I_sl + j];
+                    su = ir[Lo.I_su + j];
+                    lsl = ir[Lo.I_lsl + j];
+                    lsu = ir[Lo.I_lsu + j];
+                    tsl = ir[Lo.I_tsl + j];
+                    tsu = ir[Lo.I_tsu + j];
+                    if (upd) {
+                        sl += alpha * w[Lo.W_dsl + j];
+                        su += alpha * w[Lo.W_dsu + j];
+                        lsl = fmax(lsl + alpha * w[Lo.W_dlsl + j], P.lam_min);
+                        lsu = fmax(lsu + alpha * w[Lo.W_dlsu + j], P.lam_min);
+                        tsl = fmax(tsl + alpha * w[Lo.W_dtsl + j], P.t_min);
+                        tsu = fmax(tsu + alpha * w[Lo.W_dtsu + j], P.t_min);
+                    }
+                }
+            }
             if (n > 0) {
                 seg_hfg(pre, n - 1);
                 fetch(pre);  // next stage of the sweep
@@ -861,6 +926,11 @@ struct Blk {
                         }
                         rdl = -gz + tl + lo;
                         rdu = gz + tu - hi;
+                        if constexpr (SOFT) {
+                            // a soft row holds its slack: G z + s^l, -G z + s^u
+                            rdl -= sl;
+                            rdu -= su;
+                        }
                         md = nmax(md, nmax(fabs(rdl), fabs(rdu)));
                     }
                     const double a1 = ll * tl, a2 = lu * tu;
@@ -873,6 +943,44 @@ struct Blk {
                     const double ml = absf ? -ll - shift * itl : ll - shift * itl;
                     const double mu_ = absf ? -lu - shift * itu : lu - shift * itu;
                     e = (wl * rdl - ml) - (wu * rdu - mu_);
+                    if constexpr (SOFT) {
+                        if (sm != 0.0) {
+                            // slack rows: stationarity r_s = Z s + z - lam_row -
+                            // lam_s, bound rows rd_s = -s + t_s + ls, their
+                            // complementarity; then the slack elimination
+                            const double Zl = d[Lo.D_Zl + j], Zu = d[Lo.D_Zu + j];
+                            const double rsl = Zl * sl + d[Lo.D_zl + j] - ll - lsl;
+                            const double rsu = Zu * su + d[Lo.D_zu + j] - lu - lsu;
+                            const double rdsl = -sl + tsl + d[Lo.D_lls + j];
+                            const double rdsu = -su + tsu + d[Lo.D_lus + j];
+                            mg = nmax(mg, nmax(fabs(rsl), fabs(rsu)));
+                            md = nmax(md, nmax(fabs(rdsl), fabs(rdsu)));
+                            const double a3 = lsl * tsl, a4 = lsu * tsu;
+                            mm = nmax(mm, nmax(a3, a4));
+                            slt += a3 + a4;
+                            const double itsl = rcp_nr(tsl), itsu = rcp_nr(tsu);
+                            const double wsl = lsl * itsl, wsu = lsu * itsu;
+                            const double esl = wsl * rdsl - (lsl - shift * itsl);
+                            const double esu = wsu * rdsu - (lsu - shift * itsu);
+                            const double iDl = rcp_nr(Zl + wl + wsl), iDu = rcp_nr(Zu + wu + wsu);
+                            const double el = wl * rdl - ml, eu = wu * rdu - mu_;
+                            const double gl = rsl - el - esl, gu = rsu - eu - esu;
+                            e = (el + wl * gl * iDl) - (eu + wu * gu * iDu);
+                            wsum = wl * (Zl + wsl) * iDl + wu * (Zu + wsu) * iDu;
+                            w[Lo.W_rsl + j] = rsl;
+                            w[Lo.W_rsu + j] = rsu;
+                            w[Lo.W_rdsl + j] = rdsl;
+                            w[Lo.W_rdsu + j] = rdsu;
+                            if (upd) {
+                                ir[Lo.I_sl + j] = sl;
+                                ir[Lo.I_su + j] = su;
+                                ir[Lo.I_lsl + j] = lsl;
+                                ir[Lo.I_lsu + j] = lsu;
+                                ir[Lo.I_tsl + j] = tsl;
+                                ir[Lo.I_tsu + j] = tsu;
+                            }
+                        }
+                    }
                 }
                 ev()[j] = e;
                 wsv()[j] = wsum;
@@ -1035,6 +1143,13 @@ struct Blk {
                     slot_rm(rmode, shift, w, j, ll, lu, tl, tu, rml, rmu);
                     const double itl = rcp_nr(tl), itu = rcp_nr(tu);
                     e = (ll * w[odl + j] - rml) * itl - (lu * w[odu + j] - rmu) * itu;
+                    if constexpr (SOFT) {
+                        if (d[Lo.D_sm + j] != 0.0) {
+                            double el = (ll * w[odl + j] - rml) * itl, eu = (lu * w[odu + j] - rmu) * itu;
+                            soft_terms(d, ir, w, j, rmode, shift, ll * itl, lu * itu, el, eu);
+                            e = el - eu;
+                        }
+                    }
                 }
                 ev()[j] = e;
             }
@@ -1178,8 +1293,44 @@ struct Blk {
                     } else {
                         gdz = dot<double>(G() + (j - NZ), ldg, z(), 1, NZ);
                     }
-                    dtl = gdz - rdl;
-                    dtu = -gdz - rdu;
+                    double dsl = 0.0, dsu = 0.0;
+                    if constexpr (SOFT) {
+                        if (d[Lo.D_sm + j] != 0.0) {
+                            // slack steps and the steps of their bound rows
+                            const double itl = rcp_nr(tl), itu = rcp_nr(tu);
+                            const double wl = ll * itl, wu = lu * itu;
+                            double el = (ll * rdl - rml) * itl, eu = (lu * rdu - rmu) * itu;
+                            const SoftE q = soft_terms(d, ir, w, j, rmode, shift, wl, wu, el, eu);
+                            dsl = -(q.gl + wl * gdz) * rcp_nr(q.Dl);
+                            dsu = -(q.gu - wu * gdz) * rcp_nr(q.Du);
+                            const double dtsl = dsl - q.rdsl, dtsu = dsu - q.rdsu;
+                            const double dlsl = -(q.rmsl + q.lsl * dtsl) * rcp_nr(q.tsl);
+                            const double dlsu = -(q.rmsu + q.lsu * dtsu) * rcp_nr(q.tsu);
+                            if (dlsl < 0.0) amin = fmin(amin, -q.lsl * __builtin_amdgcn_rcp(dlsl));
+                            if (dlsu < 0.0) amin = fmin(amin, -q.lsu * __builtin_amdgcn_rcp(dlsu));
+                            if (dtsl < 0.0) amin = fmin(amin, -q.tsl * __builtin_amdgcn_rcp(dtsl));
+                            if (dtsu < 0.0) amin = fmin(amin, -q.tsu * __builtin_amdgcn_rcp(dtsu));
+                            s1 += q.lsl * dtsl + dlsl * q.tsl + q.lsu * dtsu + dlsu * q.tsu;
+                            s2 += dlsl * dtsl + dlsu * dtsu;
+                            // the affine step keeps only what the corrector reads
+                            const bool aff = oll == Lo.W_all;
+                            if (!aff) {
+                                w[Lo.W_dsl + j] = dsl;
+                                w[Lo.W_dsu + j] = dsu;
+                            }
+                            w[(aff ? Lo.W_alsl : Lo.W_dlsl) + j] = dlsl;
+                            w[(aff ? Lo.W_alsu : Lo.W_dlsu) + j] = dlsu;
+                            w[(aff ? Lo.W_atsl : Lo.W_dtsl) + j] = dtsl;
+                            w[(aff ? Lo.W_atsu : Lo.W_dtsu) + j] = dtsu;
+                        }
+                    }
+                    if constexpr (SOFT) {
+                        dtl = gdz + dsl - rdl;
+                        dtu = -gdz + dsu - rdu;
+                    } else {
+                        dtl = gdz - rdl;
+                        dtu = -gdz - rdu;
+                    }
                     dll = -(rml + ll * dtl) * rcp_nr(tl);
                     dlu = -(rmu + lu * dtu) * rcp_nr(tu);
                     if (ABS) {
@@ -1422,6 +1573,17 @@ struct Blk {
             ir[Lo.I_lu + c] = on ? 1.0 : 0.0;
             ir[Lo.I_tl + c] = on ? (warm == 1 ? fmax(gz - lo, 1.0) : fmax(-lo, 1.0)) : 0.0;
             ir[Lo.I_tu + c] = on ? (warm == 1 ? fmax(hi - gz, 1.0) : fmax(hi, 1.0)) : 0.0;
+            if constexpr (SOFT) {
+                // slacks s = 0 (cold start only), bound rows t_s = max(s - ls,
+                // 1), lam_s = 1; slots without slacks hold zeros
+                const bool sf = d[Lo.D_sm + c] != 0.0;
+                ir[Lo.I_sl + c] = 0.0;
+                ir[Lo.I_su + c] = 0.0;
+                ir[Lo.I_lsl + c] = sf ? 1.0 : 0.0;
+                ir[Lo.I_lsu + c] = sf ? 1.0 : 0.0;
+                ir[Lo.I_tsl + c] = sf ? fmax(-d[Lo.D_lls + c], 1.0) : 0.0;
+                ir[Lo.I_tsu + c] = sf ? fmax(-d[Lo.D_lus + c], 1.0) : 0.0;
+            }
         }
         __threadfence_block();
         __syncthreads();
@@ -1445,6 +1607,16 @@ struct Blk {
             o[Lo.I_lu + c] = w[Lo.W_dlu + c];
             o[Lo.I_tl + c] = w[Lo.W_dtl + c];
             o[Lo.I_tu + c] = w[Lo.W_dtu + c];
+            if constexpr (SOFT) {
+                if (Dp(n)[Lo.D_sm + c] != 0.0) {
+                    o[Lo.I_sl + c] = w[Lo.W_dsl + c];
+                    o[Lo.I_su + c] = w[Lo.W_dsu + c];
+                    o[Lo.I_lsl + c] = w[Lo.W_dlsl + c];
+                    o[Lo.I_lsu + c] = w[Lo.W_dlsu + c];
+                    o[Lo.I_tsl + c] = w[Lo.W_dtsl + c];
+                    o[Lo.I_tsu + c] = w[Lo.W_dtsu + c];
+                }
+            }
         }
     }
 

@@ -23,6 +23,7 @@ int block_zmax(int nz) { return nz <= 32 ? 32 : (nz <= 64 ? 64 : (nz <= 256 ? 25
 int block_launch(int zm, int gm, int km, const InstDesc* desc, int count, const double* data, double* iter,
                  double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream)
 {
+    if (km == KM_SOFT) return block_launch_soft(zm, gm, desc, count, data, iter, work, step, stat, P, lds_bytes, stream);
     hipStream_t s = (hipStream_t)stream;
 #define OQP_BLK(Z, G)                                                                                             \
     if (zm == Z && gm == G) {                                                                                       \

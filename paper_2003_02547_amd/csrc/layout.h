@@ -24,6 +24,7 @@ OQP_HD constexpr int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 struct Layout {
     int NX, NU, NG, NZ, NC;
+    int SOFT;  // 1: soft layout (slack blocks present)
     // problem data record (doubles), one per stage
     int D_F, D_H, D_g, D_b, D_bm, D_blo, D_bhi, D_G, D_gm, D_glo, D_ghi, SREC;
     // iterate record (doubles), one per stage: z, pi_n, lam_l, lam_u, t_l, t_u
@@ -32,16 +33,26 @@ struct Layout {
     int W_rg, W_rb, W_rdl, W_rdu, W_yu, W_pv, W_dz, W_dpi, W_dll, W_dlu, W_dtl, W_dtu;
     int W_all, W_alu, W_atl, W_atu, W_irg, W_irb, W_irdl, W_irdu, W_irml, W_irmu;
     int W_edz, W_edpi, W_edll, W_edlu, W_edtl, W_edtu, W_L, W_dinv, W_V, WREC;
+    // soft constraints (Section 2.2), present only in a soft layout, one
+    // entry per constraint slot: data (slot mask, slack Hessians Zl, Zu,
+    // gradients zl, zu, lower bounds lls, lus), iterate (slacks s^l, s^u,
+    // multipliers and slacks of their bounds), workspace (slack
+    // stationarity and bound residuals, step, affine step)
+    int D_sm, D_Zl, D_Zu, D_zl, D_zu, D_lls, D_lus;
+    int I_sl, I_su, I_lsl, I_lsu, I_tsl, I_tsu;
+    int W_rsl, W_rsu, W_rdsl, W_rdsu, W_dsl, W_dsu, W_dlsl, W_dlsu, W_dtsl, W_dtsu, W_alsl, W_alsu, W_atsl, W_atsu;
 };
 
 // F = [B A] is NX x NZ column-major, H is NZ x NZ column-major (full
 // symmetric), G is NG x NZ column-major.  Constraint slots per stage: NC =
 // NZ box slots (one per component of z = [u; x], masked by bm) followed by
 // NG general rows (masked by gm).
-OQP_HD constexpr Layout make_layout(int NX, int NU, int NG)
+// A soft layout (soft = true) appends the slack blocks to each record.
+OQP_HD constexpr Layout make_layout(int NX, int NU, int NG, bool soft = false)
 {
     Layout L{};
     L.NX = NX; L.NU = NU; L.NG = NG; L.NZ = NX + NU; L.NC = NX + NU + NG;
+    L.SOFT = soft ? 1 : 0;
     const int NZ = L.NZ, NC = L.NC;
     int o = 0;
     L.D_F = o; o += NX * NZ;
@@ -55,6 +66,16 @@ OQP_HD constexpr Layout make_layout(int NX, int NU, int NG)
     L.D_gm = o; o += NG;
     L.D_glo = o; o += NG;
     L.D_ghi = o; o += NG;
+    {
+        const int ns = soft ? NC : 0;
+        L.D_sm = o; o += ns;
+        L.D_Zl = o; o += ns;
+        L.D_Zu = o; o += ns;
+        L.D_zl = o; o += ns;
+        L.D_zu = o; o += ns;
+        L.D_lls = o; o += ns;
+        L.D_lus = o; o += ns;
+    }
     L.SREC = round_up(o, 8);
     o = 0;
     L.I_z = o; o += NZ;
@@ -63,6 +84,15 @@ OQP_HD constexpr Layout make_layout(int NX, int NU, int NG)
     L.I_lu = o; o += NC;
     L.I_tl = o; o += NC;
     L.I_tu = o; o += NC;
+    {
+        const int ns = soft ? NC : 0;
+        L.I_sl = o; o += ns;
+        L.I_su = o; o += ns;
+        L.I_lsl = o; o += ns;
+        L.I_lsu = o; o += ns;
+        L.I_tsl = o; o += ns;
+        L.I_tsu = o; o += ns;
+    }
     L.IREC = round_up(o, 8);
     o = 0;
     L.W_rg = o; o += NZ;
@@ -99,6 +129,23 @@ OQP_HD constexpr Layout make_layout(int NX, int NU, int NG)
     // [L_{n+1}' F; sqrt(w) G] of the stage, used only by the global-memory
     // mode of the block kernel (stage blocks above 64)
     L.W_V = o; o += NX + NU > 64 ? (NX + NG) * NZ : 0;
+    {
+        const int ns = soft ? NC : 0;
+        L.W_rsl = o; o += ns;
+        L.W_rsu = o; o += ns;
+        L.W_rdsl = o; o += ns;
+        L.W_rdsu = o; o += ns;
+        L.W_dsl = o; o += ns;
+        L.W_dsu = o; o += ns;
+        L.W_dlsl = o; o += ns;
+        L.W_dlsu = o; o += ns;
+        L.W_dtsl = o; o += ns;
+        L.W_dtsu = o; o += ns;
+        L.W_alsl = o; o += ns;
+        L.W_alsu = o; o += ns;
+        L.W_atsl = o; o += ns;
+        L.W_atsu = o; o += ns;
+    }
     L.WREC = round_up(o, 8);
     return L;
 }
@@ -165,8 +212,9 @@ struct KParams {
 enum { KMODE_SOLVE = 0, KMODE_NEWTON = 1, KMODE_FALLBACK = 2 };
 // Compiled kernel builds: FP64 delta formulation, mixed (FP32 factorization
 // and sweeps, FP64 refinement), FP64 absolute formulation, FP64 with the
-// QR-based (array algorithm) factorization.
-enum { KM_F64 = 0, KM_MIXED = 1, KM_ABS = 2, KM_ROBUST = 3 };
+// QR-based (array algorithm) factorization, FP64 delta formulation with
+// soft constraints (block kernel, soft layout).
+enum { KM_F64 = 0, KM_MIXED = 1, KM_ABS = 2, KM_ROBUST = 3, KM_SOFT = 4 };
 enum { ST_SUCCESS = 0, ST_MAX_ITER = 1, ST_MIN_STEP = 2, ST_NAN = 3, ST_FALLBACK = 4 };
 
 }  // namespace oqp

@@ -329,6 +329,7 @@ static void pack_sizes(const oqp_qp* q, const KSel& ks, PackHdr* h)
 extern "C" int oqp_pack_bytes(const oqp_qp* qp, size_t* bytes)
 {
     if (!qp || !bytes) return fail(OQP_EINVAL, "oqp_pack_bytes: NULL argument");
+    if (dims_soft(qp->dims)) return fail(OQP_EINVAL, "oqp_pack_bytes: soft constraints are solved in batches only");
     KSel ks;
     if (select_kernel(qp->dims, &ks)) return fail(OQP_EINVAL, "oqp_pack_bytes: no kernel covers the stage sizes");
     PackHdr h;
@@ -341,6 +342,7 @@ extern "C" int oqp_pack(const oqp_qp* qp, void* mem, size_t bytes)
 {
     if (!qp || !mem) return fail(OQP_EINVAL, "oqp_pack: NULL argument");
     if ((uintptr_t)mem % 64) return fail(OQP_EINVAL, "oqp_pack: memory not 64-byte aligned");
+    if (dims_soft(qp->dims)) return fail(OQP_EINVAL, "oqp_pack: soft constraints are solved in batches only");
     KSel ks;
     if (select_kernel(qp->dims, &ks)) return fail(OQP_EINVAL, "oqp_pack: no kernel covers the stage sizes");
     PackHdr h;

@@ -247,14 +247,15 @@ def _zero_input_rollout_ok(A, x0, N, hx):
 
 
 def random_stable(rng: np.random.Generator, nx: int, nu: int, N: int, ng: int = 0,
-                  max_redraw: int = 10000) -> OcpQp:
+                  max_redraw: int = 10000, redraw: bool = True) -> OcpQp:
     """Random time-invariant OCP QP with a fixed draw order:
     G ~ N(0,1) (nx x nx), A = 0.95 G / rho(G); B ~ N(0,1)/sqrt(nx);
     Q = diag U[0.1,10]; R = diag U[0.1,1]; S = 0, q = r = b = 0;
     box half-widths U[0.5,2] on u and U[2,5] on x (all components boxed);
     if ng > 0: D ~ N(0,1) (ng x nu), C = 0, bounds +-U[1,3] at stages 0..N-1;
     x0 ~ N(0,1), redrawn from the same stream until the zero-input rollout
-    stays inside every state box (so u = 0 is a feasible point)."""
+    stays inside every state box (so u = 0 is a feasible point); with
+    redraw=False the first draw is kept (the problem may be infeasible)."""
     Gm = rng.standard_normal((nx, nx))
     rho = np.max(np.abs(np.linalg.eigvals(Gm)))
     A = Gm * (0.95 / rho)
@@ -269,7 +270,7 @@ def random_stable(rng: np.random.Generator, nx: int, nu: int, N: int, ng: int = 
     redraws = 0
     while True:
         x0 = rng.standard_normal(nx)
-        if _zero_input_rollout_ok(A, x0, N, hx):
+        if not redraw or _zero_input_rollout_ok(A, x0, N, hx):
             break
         redraws += 1
         if redraws >= max_redraw:
@@ -302,6 +303,54 @@ def random_uneven(i: int) -> OcpQp:
     qp = random_stable(rng, nx, nu, N)
     qp.meta["instance"] = i
     return qp
+
+
+# Soft-constraint workloads (Section 2.2): every state box after stage 0
+# softened with an L2 weight of 1 and an L1 weight of 10 per slack.
+SOFT_Z, SOFT_z = 1.0, 10.0
+
+
+def mass_spring_chain8_soft(i: int) -> OcpQp:
+    """Instance i of the 8-mass batch with soft position boxes (every
+    instance feasible, including those whose hard boxes are not)."""
+    return soften(mass_spring_chain8(i), state_box_rows, SOFT_Z, SOFT_Z, SOFT_z, SOFT_z)
+
+
+def random_uneven_soft(i: int) -> OcpQp:
+    """Instance i of the uneven batch with its first x0 draw (no redraw for
+    a feasible zero-input rollout) and soft state boxes."""
+    rng = np.random.default_rng(np.random.SeedSequence([3, i]))
+    nx = int(rng.integers(4, 49))
+    nu = int(rng.integers(1, 17))
+    N = int(rng.integers(10, 101))
+    qp = random_stable(rng, nx, nu, N, redraw=False)
+    qp.meta["instance"] = i
+    return soften(qp, state_box_rows, SOFT_Z, SOFT_Z, SOFT_z, SOFT_z)
+
+
+def soften_random(qp: OcpQp, rng: np.random.Generator, frac: float = 0.6) -> OcpQp:
+    """A random subset (about frac) of each stage's rows made soft, stage 0's
+    state box kept hard, with random weights Zl, Zu ~ U[0.1, 3], zl, zu ~
+    U[0, 2] and slack bounds lls, lus ~ U[0, 0.2]."""
+    out = qp.copy()
+    idxs, vals = [], {k: [] for k in ("Zl", "Zu", "zl", "zu", "lls", "lus")}
+    for n in range(qp.N + 1):
+        nc = qp.nbu[n] + qp.nbx[n] + qp.ng[n]
+        cand = list(range(nc))
+        if n == 0:
+            nbu = qp.nbu[0]
+            cand = [k for k in cand if not (nbu <= k < nbu + qp.nbx[0])]
+        pick = [k for k in cand if rng.uniform() < frac]
+        rng.shuffle(pick)
+        idxs.append(np.asarray(pick, dtype=np.int32))
+        m = len(pick)
+        vals["Zl"].append(rng.uniform(0.1, 3.0, m)); vals["Zu"].append(rng.uniform(0.1, 3.0, m))
+        vals["zl"].append(rng.uniform(0.0, 2.0, m)); vals["zu"].append(rng.uniform(0.0, 2.0, m))
+        vals["lls"].append(rng.uniform(0.0, 0.2, m)); vals["lus"].append(rng.uniform(0.0, 0.2, m))
+    out.idxs = idxs
+    for k, v in vals.items():
+        setattr(out, k, v)
+    return out
 
 
 def random_large_stage(i: int) -> OcpQp:

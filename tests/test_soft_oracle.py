@@ -36,31 +36,12 @@ def _cmp(a, b, tol, what=""):
             assert err <= tol, (what, k, err)
 
 
-def soft_tiny(seed, N=None, nfree_max=None, **kw):
-    """A tiny random QP with a random subset of its rows made soft (random
-    positive quadratic and nonnegative linear weights, slack bounds in
-    [0, 0.2]); stage 0's fixed-x0 rows stay hard."""
+def soft_tiny(seed, N=None, **kw):
+    """A tiny random QP with a random subset of its rows made soft."""
     rng = np.random.default_rng(seed)
     N = N if N is not None else int(rng.integers(1, 5))
     qp = W.random_tiny(rng, N, **kw)
-    idxs, vals = [], {k: [] for k in ("Zl", "Zu", "zl", "zu", "lls", "lus")}
-    for n in range(N + 1):
-        nc = qp.nbu[n] + qp.nbx[n] + qp.ng[n]
-        cand = list(range(nc))
-        if n == 0:
-            nbu = qp.nbu[0]
-            cand = [k for k in cand if not (nbu <= k < nbu + qp.nbx[0])]
-        pick = [k for k in cand if rng.uniform() < 0.6]
-        rng.shuffle(pick)
-        idxs.append(np.asarray(pick, dtype=np.int32))
-        m = len(pick)
-        vals["Zl"].append(rng.uniform(0.1, 3.0, m)); vals["Zu"].append(rng.uniform(0.1, 3.0, m))
-        vals["zl"].append(rng.uniform(0.0, 2.0, m)); vals["zu"].append(rng.uniform(0.0, 2.0, m))
-        vals["lls"].append(rng.uniform(0.0, 0.2, m)); vals["lus"].append(rng.uniform(0.0, 0.2, m))
-    qp.idxs = idxs
-    for k, v in vals.items():
-        setattr(qp, k, v)
-    return qp, rng
+    return W.soften_random(qp, rng), rng
 
 
 @pytest.mark.parametrize("seed", range(12))
