@@ -859,16 +859,16 @@ static double mu_after(const prob_t *p, const ivec_t *v, const ivec_t *d, double
 
 /* r_m = lam.*t + a.*b - shift on every one-sided row, written to r->tl/tu
  * and r->tsl/tsu (a, b: the affine step's dlam and dt for the corrector, or
- * NULL). */
+ * NULL), summed in that order. */
 static void set_rm(const prob_t *p, const ivec_t *v, const ivec_t *aff, double shift, ivec_t *r)
 {
     for (int i = 0; i < p->ncon; ++i) {
-        r->tl[i] = v->ll[i] * v->tl[i] - shift + (aff ? aff->ll[i] * aff->tl[i] : 0.0);
-        r->tu[i] = v->lu[i] * v->tu[i] - shift + (aff ? aff->lu[i] * aff->tu[i] : 0.0);
+        r->tl[i] = (aff ? v->ll[i] * v->tl[i] + aff->ll[i] * aff->tl[i] : v->ll[i] * v->tl[i]) - shift;
+        r->tu[i] = (aff ? v->lu[i] * v->tu[i] + aff->lu[i] * aff->tu[i] : v->lu[i] * v->tu[i]) - shift;
     }
     for (int i = 0; i < p->nsoft; ++i) {
-        r->tsl[i] = v->lsl[i] * v->tsl[i] - shift + (aff ? aff->lsl[i] * aff->tsl[i] : 0.0);
-        r->tsu[i] = v->lsu[i] * v->tsu[i] - shift + (aff ? aff->lsu[i] * aff->tsu[i] : 0.0);
+        r->tsl[i] = (aff ? v->lsl[i] * v->tsl[i] + aff->lsl[i] * aff->tsl[i] : v->lsl[i] * v->tsl[i]) - shift;
+        r->tsu[i] = (aff ? v->lsu[i] * v->tsu[i] + aff->lsu[i] * aff->tsu[i] : v->lsu[i] * v->tsu[i]) - shift;
     }
 }
 
