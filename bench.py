@@ -14,6 +14,9 @@ Further legs on the same line (context, not the headline):
   * robust: the same batch with the QR-based factorization (mode robust);
   * warm: the next receding-horizon problem of every solved instance, cold
     and warm-started from the shifted solution;
+  * soft: the same batch with soft position boxes (every instance
+    solvable), beside it without slacks on the same kernel family, and the
+    uneven batch with its first x0 draws and soft state boxes;
   * uneven: a batch of random stable OCP QPs with nx ~ U{4..48},
     nu ~ U{1..16}, N ~ U{10..100} (one-wave variants plus the block kernel);
   * serve: the continuous-batching server replaying Poisson arrivals over a
@@ -268,6 +271,68 @@ def leg_robust(B, torch, np, qps, steps):
             "iters_p50": float(np.percentile(iters, 50)), "iters_max": int(iters.max())}
 
 
+def _median_solve_ms(b, torch, np, steps):
+    """Median time of `steps` solves of a loaded batch (one untimed solve
+    first), HIP events on the batch stream; fetches the last results."""
+    b.solve()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(steps):
+        s_, e_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s_.record(b.stream)
+        b.solve()
+        e_.record(b.stream)
+        torch.cuda.synchronize()
+        ms.append(s_.elapsed_time(e_))
+    b.fetch().sync()
+    return float(np.median(ms))
+
+
+def leg_soft(B, W, torch, np, qps, steps, uneven_count, uneven_steps):
+    """Soft constraints (Section 2.2): the headline batch with its position
+    boxes soft (per slack an L2 weight of 1 and an L1 weight of 10), which
+    makes every instance solvable, beside the same batch without slacks on
+    the block kernel's FP64 build (the cost of the slack elimination, same
+    kernel family); then the uneven batch with its first x0 draws (no redraw
+    for a feasible zero-input rollout) and soft state boxes."""
+    out = {"weights": f"state boxes after stage 0 soft, Z={W.SOFT_Z}, z={W.SOFT_z} per slack", "tol": 1e-8}
+
+    def summary(b, n, med):
+        stats = [b.stat(i) for i in range(n)]
+        ok = sum(1 for x in stats if x.status == B.SUCCESS and max(x.res[:]) <= KKT_OK)
+        iters = np.array([x.iters for x in stats])
+        return {"value": round(ok / (med * 1e-3), 1), "unit": "solves/s", "ms_per_step": round(med, 3),
+                "solves_ok": ok, "instances": n, "iters_p50": float(np.percentile(iters, 50)),
+                "iters_max": int(iters.max())}
+
+    sq = [W.mass_spring_chain8_soft(i) for i in range(len(qps))]
+    b = B.Batch(sq, B.default_arg()).load().sync()
+    r = summary(b, len(sq), _median_solve_ms(b, torch, np, steps))
+    sols = [b.solution(i) for i in range(len(sq))]
+    r["slack_active"] = sum(1 for x in sols if max(x["s_l"].max(), x["s_u"].max()) > 1e-6)
+    r["kernel"] = "ipm_block_kernel soft build (ZM 32)"
+    out["chain8"] = r
+    del b
+    L = B.lib()
+    wmax = L.oqp_get_wave_max()
+    L.oqp_set_wave_max(0)  # every instance on the block kernel
+    try:
+        b = B.Batch(qps, B.default_arg()).load().sync()
+        out["chain8_hard_block_f64"] = summary(b, len(qps), _median_solve_ms(b, torch, np, steps))
+        del b
+    finally:
+        L.oqp_set_wave_max(wmax)
+    if uneven_count > 0:
+        uq = [W.random_uneven_soft(i) for i in range(uneven_count)]
+        b = B.Batch(uq, B.default_arg(), streams=3).load().sync()
+        r = summary(b, len(uq), _median_solve_ms(b, torch, np, uneven_steps))
+        r["first_draw_infeasible_hard"] = sum(1 for i in range(uneven_count) if W.random_uneven(i).meta["redraws"] > 0)
+        r["extra_streams"] = 3
+        out["uneven"] = r
+        del b
+    return out
+
+
 def leg_single(B, W, torch, np, reps):
     """Latency of one 4-mass QP (nx = 8, nu = 3, N = 10, dt = 0.5; seed 1) in
     a batch of one: one launch, FP64 to 1e-8, median over reps (the CPU
@@ -381,6 +446,8 @@ def main():
     ap.add_argument("--abs-steps", type=int, default=5, help="timed solves of the absolute-formulation leg (0: skip)")
     ap.add_argument("--robust-steps", type=int, default=5, help="timed solves of the QR-factorization leg (0: skip)")
     ap.add_argument("--iter20-steps", type=int, default=5, help="timed solves of the iter_max 20 context line (0: skip)")
+    ap.add_argument("--soft-steps", type=int, default=5, help="timed solves of the soft-constraint leg (0: skip)")
+    ap.add_argument("--soft-uneven", type=int, default=4096, help="instances of the soft uneven batch (0: skip)")
     ap.add_argument("--large", type=int, default=256, help="instances of the large-stage leg (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2)
     ap.add_argument("--serve-pool", type=int, default=256, help="distinct instances in the serving pool (0: skip)")
@@ -521,6 +588,9 @@ def main():
         line["warm"] = leg_warm(B, W, torch, np, qps, args.warm_steps)
     log("bench: single-instance latency (4 masses, N = 10)")
     line["single"] = leg_single(B, W, torch, np, 20)
+    if args.soft_steps > 0:
+        log("bench: soft-constraint leg")
+        line["soft"] = leg_soft(B, W, torch, np, qps, args.soft_steps, args.soft_uneven, args.uneven_steps)
     if args.uneven > 0:
         log(f"bench: uneven leg, {args.uneven} instances")
         line["uneven"] = leg_uneven(B, W, torch, np, args.uneven, args.uneven_steps)
