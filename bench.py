@@ -15,8 +15,9 @@ Further legs on the same line (context, not the headline):
   * warm: the next receding-horizon problem of every solved instance, cold
     and warm-started from the shifted solution;
   * soft: the same batch with soft position boxes (every instance
-    solvable), beside it without slacks on the same kernel family, and the
-    uneven batch with its first x0 draws and soft state boxes;
+    solvable), the same with and without slacks on the block kernel (the
+    cost of the slack elimination), and the uneven batch with its first x0
+    draws and soft state boxes;
   * uneven: a batch of random stable OCP QPs with nx ~ U{4..48},
     nu ~ U{1..16}, N ~ U{10..100} (one-wave variants plus the block kernel);
   * serve: the continuous-batching server replaying Poisson arrivals over a
@@ -291,10 +292,11 @@ def _median_solve_ms(b, torch, np, steps):
 def leg_soft(B, W, torch, np, qps, steps, uneven_count, uneven_steps):
     """Soft constraints (Section 2.2): the headline batch with its position
     boxes soft (per slack an L2 weight of 1 and an L1 weight of 10), which
-    makes every instance solvable, beside the same batch without slacks on
-    the block kernel's FP64 build (the cost of the slack elimination, same
-    kernel family); then the uneven batch with its first x0 draws (no redraw
-    for a feasible zero-input rollout) and soft state boxes."""
+    makes every instance solvable, on the kernels the batch picks (the
+    one-wave kernel's soft build); the cost of the slack elimination within
+    one kernel family, as the same two batches (with and without slacks) on
+    the block kernel; then the uneven batch with its first x0 draws (no
+    redraw for a feasible zero-input rollout) and soft state boxes."""
     out = {"weights": f"state boxes after stage 0 soft, Z={W.SOFT_Z}, z={W.SOFT_z} per slack", "tol": 1e-8}
 
     def summary(b, n, med):
@@ -310,16 +312,18 @@ def leg_soft(B, W, torch, np, qps, steps, uneven_count, uneven_steps):
     r = summary(b, len(sq), _median_solve_ms(b, torch, np, steps))
     sols = [b.solution(i) for i in range(len(sq))]
     r["slack_active"] = sum(1 for x in sols if max(x["s_l"].max(), x["s_u"].max()) > 1e-6)
-    r["kernel"] = "ipm_block_kernel soft build (ZM 32)"
+    v, (nx, nu, ng) = b.variant(0)
+    r["kernel"] = f"ipm_kernel<{nx},{nu},{ng}> soft build"
     out["chain8"] = r
     del b
     L = B.lib()
     wmax = L.oqp_get_wave_max()
     L.oqp_set_wave_max(0)  # every instance on the block kernel
     try:
-        b = B.Batch(qps, B.default_arg()).load().sync()
-        out["chain8_hard_block_f64"] = summary(b, len(qps), _median_solve_ms(b, torch, np, steps))
-        del b
+        for key, batch in (("chain8_block_soft", sq), ("chain8_block_f64_no_slacks", qps)):
+            b = B.Batch(batch, B.default_arg()).load().sync()
+            out[key] = summary(b, len(batch), _median_solve_ms(b, torch, np, steps))
+            del b
     finally:
         L.oqp_set_wave_max(wmax)
     if uneven_count > 0:

@@ -223,7 +223,8 @@ int oqp_batch_get_sol(const oqp_batch* batch, int i, double* u, double* x, doubl
 
 /* ---- soft constraints (Section 2.2) --------------------------------------- */
 /* A batch in which some instance has slacks solves every instance with the
- * block kernel's soft build: the FP64 delta formulation, each slack pair
+ * soft builds of the kernels (the one-wave variants and the block kernel,
+ * chosen by stage size as usual): the FP64 delta formulation, each slack pair
  * eliminated with its bounds row by row (the Riccati recursion sees the row
  * weight w (Z + w_s) / (Z + w + w_s), the slack step follows from the state
  * and input step), cost linear in the number of slacks.  Such a batch needs

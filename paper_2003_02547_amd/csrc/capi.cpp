@@ -510,7 +510,7 @@ struct oqp_batch {
     Inst* inst;
     int* dims_pool;
     int* slot_pool;
-    int soft;        // some instance has slacks: every instance solved by the block kernel's soft build
+    int soft;        // some instance has slacks: every instance solved by the soft kernel builds
     int* soft_pool;
     InstDesc* hdesc;
     DevStat* hstat;
@@ -708,9 +708,7 @@ static constexpr size_t kMaxCondLds = 64 * 1024;
 // the instance whatever the one-wave bound.
 static int select_for_mode(int mx, int mu, int mg, int mode, int soft, KSel* out)
 {
-    // soft constraints are built into the block kernel only
-    if (soft) return select_block_max(mx, mu, mg, out);
-    if (mode != OQP_MODE_ROBUST) return select_kernel_max(mx, mu, mg, out);
+    if (soft || mode != OQP_MODE_ROBUST) return select_kernel_max(mx, mu, mg, out);
     const int v = pick_variant_max(mx, mu, mg);
     if (v < 0) return -1;
     int nx, nu, ng;
@@ -727,8 +725,7 @@ static int solve_shape(const oqp_dims* d, int cond_N, int mode, int soft, SolveS
         dims_max(d, &mx, &mu, &mg);
         if (select_for_mode(mx, mu, mg, mode, soft, &sh->ks))
             return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d%s", i,
-                        mode == OQP_MODE_ROBUST ? " (robust mode: one-wave variants only)"
-                                                : (soft ? " (soft constraints: block kernel only)" : ""));
+                        mode == OQP_MODE_ROBUST ? " (robust mode: one-wave variants only)" : "");
         sh->onx = sh->ks.nx;
         sh->onu = sh->ks.nu;
         sh->ong = sh->ks.ng;
@@ -799,8 +796,8 @@ struct Plan {
     int n_soft;
 };
 
-// A batch with slacks anywhere: FP64 delta formulation from a cold start,
-// without condensing.
+// A batch with slacks anywhere (every instance then takes the soft builds):
+// FP64 delta formulation from a cold start, without condensing.
 static int batch_soft(const oqp_dims* const* dims, int count, const oqp_arg* arg, int* soft)
 {
     *soft = 0;

@@ -52,10 +52,12 @@ struct Ipm {
     // factorization by an array algorithm (QR) instead of the Cholesky factor
     // of the normal matrix (Section 4.2, mode robust)
     static constexpr bool ROBUST = KM == KM_ROBUST;
+    // soft constraints (Section 2.2): slack pairs on the soft layout
+    static constexpr bool SOFT = KM == KM_SOFT;
     // arithmetic type of the factorization and of the right-hand-side sweeps
     // (FP32 in the mixed path; pivots, residuals and refinement stay FP64)
     using TS = typename std::conditional<MIXED, float, double>::type;
-    static constexpr Layout Lo = make_layout(NX, NU, NG);
+    static constexpr Layout Lo = make_layout(NX, NU, NG, SOFT);
     static constexpr int NZ = NX + NU;
     static constexpr int NC = NZ + NG;
     static constexpr int NV = NX + NG;
@@ -217,6 +219,109 @@ struct Ipm {
             lo = 0.0;
             hi = 0.0;
         }
+    }
+
+    // ------------------------------------------------------------------
+    // Soft constraints (soft build).  A soft slot holds a slack pair
+    // (s^l, s^u): the lower row reads G z + s^l, the upper row -G z + s^u,
+    // each with a bound row s >= ls (multiplier lam_s, slack t_s).  The pair
+    // is eliminated from the Newton system per slot: with D = Z + w + w_s and
+    // g_s = r_s - e - e_s (e_s = (lam_s rd_s - rm_s) / t_s), the slot enters
+    // the Riccati recursion with weight w (Z + w_s) / D and term e + w g_s /
+    // D, and pass B recovers ds^l = -(g_s^l + w_l G dz) / D_l, ds^u =
+    // -(g_s^u - w_u G dz) / D_u.  The slot values travel in the prefetch
+    // records of the passes like the rows' (NCS = 1 placeholder otherwise).
+    // ------------------------------------------------------------------
+    static constexpr int NCS = SOFT ? NCT : 1;
+    struct SoftA {  // pass A: data, iterate and last step of a slot
+        double sm, Zl, Zu, zl, zu, lls, lus, sl, su, lsl, lsu, tsl, tsu, dsl, dsu, dlsl, dlsu, dtsl, dtsu;
+    };
+    struct SoftOutA {  // pass A outputs: updated iterate and slack residuals
+        double sm, sl, su, lsl, lsu, tsl, tsu, rsl, rsu, rdsl, rdsu;
+    };
+    struct SoftR {  // passes B, C: what the elimination of a right-hand side reads
+        double sm, Zl, Zu, lsl, lsu, tsl, tsu, rsl, rsu, rdsl, rdsu, alsl, alsu, atsl, atsu;
+    };
+    struct SoftOutB {  // pass B outputs: slack steps and bound-row steps
+        double sm, dsl, dsu, dlsl, dlsu, dtsl, dtsu;
+    };
+
+    __device__ __forceinline__ void load_softA(SoftA& q, const double* d, const double* ir, const double* w, int c,
+                                               bool upd) const
+    {
+        q = SoftA{};
+        if (c >= NC) return;
+        q.sm = d[Lo.D_sm + c];
+        if (q.sm == 0.0) return;
+        q.Zl = d[Lo.D_Zl + c];
+        q.Zu = d[Lo.D_Zu + c];
+        q.zl = d[Lo.D_zl + c];
+        q.zu = d[Lo.D_zu + c];
+        q.lls = d[Lo.D_lls + c];
+        q.lus = d[Lo.D_lus + c];
+        q.sl = ir[Lo.I_sl + c];
+        q.su = ir[Lo.I_su + c];
+        q.lsl = ir[Lo.I_lsl + c];
+        q.lsu = ir[Lo.I_lsu + c];
+        q.tsl = ir[Lo.I_tsl + c];
+        q.tsu = ir[Lo.I_tsu + c];
+        if (upd) {
+            q.dsl = w[Lo.W_dsl + c];
+            q.dsu = w[Lo.W_dsu + c];
+            q.dlsl = w[Lo.W_dlsl + c];
+            q.dlsu = w[Lo.W_dlsu + c];
+            q.dtsl = w[Lo.W_dtsl + c];
+            q.dtsu = w[Lo.W_dtsu + c];
+        }
+    }
+
+    __device__ __forceinline__ void load_softR(SoftR& q, int rmode, const double* d, const double* ir,
+                                               const double* w, int c) const
+    {
+        q = SoftR{};
+        if (c >= NC) return;
+        q.sm = d[Lo.D_sm + c];
+        if (q.sm == 0.0) return;
+        q.Zl = d[Lo.D_Zl + c];
+        q.Zu = d[Lo.D_Zu + c];
+        q.lsl = ir[Lo.I_lsl + c];
+        q.lsu = ir[Lo.I_lsu + c];
+        q.tsl = ir[Lo.I_tsl + c];
+        q.tsu = ir[Lo.I_tsu + c];
+        q.rsl = w[Lo.W_rsl + c];
+        q.rsu = w[Lo.W_rsu + c];
+        q.rdsl = w[Lo.W_rdsl + c];
+        q.rdsu = w[Lo.W_rdsu + c];
+        if (rmode == RM_CORRECTOR) {
+            q.alsl = w[Lo.W_alsl + c];
+            q.alsu = w[Lo.W_alsu + c];
+            q.atsl = w[Lo.W_atsl + c];
+            q.atsu = w[Lo.W_atsu + c];
+        }
+    }
+
+    // Elimination of a soft slot for a right-hand side: turns the row terms
+    // el, eu into el + wl g_l / D_l, eu + wu g_u / D_u and returns D, g_s
+    // and the bound rows' r_m (per rmode, as rm_value for the rows).
+    __device__ __forceinline__ void soft_rhs(const SoftR& q, int rmode, double shift, double wl, double wu,
+                                             double& el, double& eu, double& Dl, double& gl, double& Du,
+                                             double& gu, double& rmsl, double& rmsu) const
+    {
+        rmsl = q.lsl * q.tsl - shift;
+        rmsu = q.lsu * q.tsu - shift;
+        if (rmode == RM_CORRECTOR) {
+            rmsl += q.alsl * q.atsl;
+            rmsu += q.alsu * q.atsu;
+        }
+        const double itsl = rcp_nr(q.tsl), itsu = rcp_nr(q.tsu);
+        const double esl = (q.lsl * q.rdsl - rmsl) * itsl;
+        const double esu = (q.lsu * q.rdsu - rmsu) * itsu;
+        Dl = q.Zl + wl + q.lsl * itsl;
+        Du = q.Zu + wu + q.lsu * itsu;
+        gl = q.rsl - el - esl;
+        gu = q.rsu - eu - esu;
+        el += wl * gl * rcp_nr(Dl);
+        eu += wu * gu * rcp_nr(Du);
     }
 
     // ------------------------------------------------------------------
@@ -447,6 +552,7 @@ struct Ipm {
         double g, z, dz, b, pi, dpi;
         double m[NCT], lo[NCT], hi[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
         double dll[NCT], dlu[NCT], dtl[NCT], dtu[NCT];
+        SoftA sf[NCS];
     };
 
     __device__ __forceinline__ void loadA(PreA& p, int n, bool upd) const
@@ -486,6 +592,7 @@ struct Ipm {
                     p.dtu[t] = w[Lo.W_dtu + c];
                 }
             }
+            if constexpr (SOFT) load_softA(p.sf[t], d, ir, w, c, upd);
         }
     }
 
@@ -496,6 +603,7 @@ struct Ipm {
     struct OutA {
         double z, pi, rg, rb, dinv, mv;
         double ll[NCT], lu[NCT], tl[NCT], tu[NCT], rdl[NCT], rdu[NCT], m[NCT];
+        SoftOutA so[NCS];
     };
 
     __device__ __forceinline__ void flushA(int n, bool upd, bool factor, const OutA& o) const
@@ -519,6 +627,22 @@ struct Ipm {
                 }
                 w[Lo.W_rdl + c] = o.rdl[t];
                 w[Lo.W_rdu + c] = o.rdu[t];
+                if constexpr (SOFT) {
+                    if (o.so[t].sm != 0.0) {
+                        if (upd) {
+                            ir[Lo.I_sl + c] = o.so[t].sl;
+                            ir[Lo.I_su + c] = o.so[t].su;
+                            ir[Lo.I_lsl + c] = o.so[t].lsl;
+                            ir[Lo.I_lsu + c] = o.so[t].lsu;
+                            ir[Lo.I_tsl + c] = o.so[t].tsl;
+                            ir[Lo.I_tsu + c] = o.so[t].tsu;
+                        }
+                        w[Lo.W_rsl + c] = o.so[t].rsl;
+                        w[Lo.W_rsu + c] = o.so[t].rsu;
+                        w[Lo.W_rdsl + c] = o.so[t].rdsl;
+                        w[Lo.W_rdsu + c] = o.so[t].rdsu;
+                    }
+                }
             }
         }
         if (lane < NZ) w[Lo.W_rg + lane] = o.rg;
@@ -570,6 +694,22 @@ struct Ipm {
                     lu[t] = fmax(lu[t] + alpha * p.dlu[t], P.lam_min);
                     tl[t] = fmax(tl[t] + alpha * p.dtl[t], P.t_min);
                     tu[t] = fmax(tu[t] + alpha * p.dtu[t], P.t_min);
+                }
+            }
+            // slack pairs after the step (clamped like the rows)
+            SoftA sa[NCS];
+            if constexpr (SOFT) {
+#pragma unroll
+                for (int t = 0; t < NCT; ++t) {
+                    sa[t] = p.sf[t];
+                    if (upd && sa[t].sm != 0.0) {
+                        sa[t].sl += alpha * sa[t].dsl;
+                        sa[t].su += alpha * sa[t].dsu;
+                        sa[t].lsl = fmax(sa[t].lsl + alpha * sa[t].dlsl, P.lam_min);
+                        sa[t].lsu = fmax(sa[t].lsu + alpha * sa[t].dlsu, P.lam_min);
+                        sa[t].tsl = fmax(sa[t].tsl + alpha * sa[t].dtsl, P.t_min);
+                        sa[t].tsu = fmax(sa[t].tsu + alpha * sa[t].dtsu, P.t_min);
+                    }
                 }
             }
             if (n < N) flushA(n + 1, upd, factor, o);  // outputs of the previous stage
@@ -634,6 +774,7 @@ struct Ipm {
             for (int t = 0; t < NCT; ++t) {
                 const int c = slot(t);
                 double e = 0.0, wsum = 0.0, rdl = 0.0, rdu = 0.0;
+                if constexpr (SOFT) o.so[t] = SoftOutA{};
                 if (c < NC) {
                     if (m[t] != 0.0) {
                         if (absf) {
@@ -651,6 +792,11 @@ struct Ipm {
                             }
                             rdl = -gz + tl[t] + lo[t];
                             rdu = gz + tu[t] - hi[t];
+                            if constexpr (SOFT) {
+                                // a soft row holds its slack: G z + s^l, -G z + s^u
+                                rdl -= sa[t].sl;
+                                rdu -= sa[t].su;
+                            }
                             md = nmax(md, nmax(fabs(rdl), fabs(rdu)));
                         }
                         const double a1 = ll[t] * tl[t], a2 = lu[t] * tu[t];
@@ -663,6 +809,40 @@ struct Ipm {
                         const double ml = absf ? -ll[t] - shift * itl : ll[t] - shift * itl;
                         const double mu_ = absf ? -lu[t] - shift * itu : lu[t] - shift * itu;
                         e = (wl * rdl - ml) - (wu * rdu - mu_);
+                        if constexpr (SOFT) {
+                            const SoftA& q = sa[t];
+                            SoftOutA& so = o.so[t];
+                            if (q.sm != 0.0) {
+                                // slack rows: stationarity r_s = Z s + z - lam_row -
+                                // lam_s, bound rows rd_s = -s + t_s + ls and their
+                                // complementarity; then the elimination
+                                so.sm = 1.0;
+                                so.rsl = q.Zl * q.sl + q.zl - ll[t] - q.lsl;
+                                so.rsu = q.Zu * q.su + q.zu - lu[t] - q.lsu;
+                                so.rdsl = -q.sl + q.tsl + q.lls;
+                                so.rdsu = -q.su + q.tsu + q.lus;
+                                mg = nmax(mg, nmax(fabs(so.rsl), fabs(so.rsu)));
+                                md = nmax(md, nmax(fabs(so.rdsl), fabs(so.rdsu)));
+                                const double a3 = q.lsl * q.tsl, a4 = q.lsu * q.tsu;
+                                mm = nmax(mm, nmax(a3, a4));
+                                slt += a3 + a4;
+                                const double itsl = rcp_nr(q.tsl), itsu = rcp_nr(q.tsu);
+                                const double wsl = q.lsl * itsl, wsu = q.lsu * itsu;
+                                const double esl = wsl * so.rdsl - (q.lsl - shift * itsl);
+                                const double esu = wsu * so.rdsu - (q.lsu - shift * itsu);
+                                const double iDl = rcp_nr(q.Zl + wl + wsl), iDu = rcp_nr(q.Zu + wu + wsu);
+                                const double el = wl * rdl - ml, eu = wu * rdu - mu_;
+                                const double gl = so.rsl - el - esl, gu = so.rsu - eu - esu;
+                                e = (el + wl * gl * iDl) - (eu + wu * gu * iDu);
+                                wsum = wl * (q.Zl + wsl) * iDl + wu * (q.Zu + wsu) * iDu;
+                                so.sl = q.sl;
+                                so.su = q.su;
+                                so.lsl = q.lsl;
+                                so.lsu = q.lsu;
+                                so.tsl = q.tsl;
+                                so.tsu = q.tsu;
+                            }
+                        }
                     }
                     s.e[c] = e;
                     s.ws[c] = wsum;
@@ -820,6 +1000,7 @@ struct Ipm {
         double dinv, rg, rb;
         double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
         double a1[NCT], a2[NCT], a3[NCT], a4[NCT];
+        SoftR sr[NCS];
     };
 
     __device__ __forceinline__ void loadC(PreC& p, int n, int rmode, int og, int ob, int odl, int odu) const
@@ -836,6 +1017,10 @@ struct Ipm {
         p.rg = lane < NZ ? w[og + lane] : 0.0;
         p.rb = (n < N && lane < NX) ? w[ob + lane] : 0.0;
         load_slots_rm(rmode, d, ir, w, odl, odu, p.m, p.rdl, p.rdu, p.ll, p.lu, p.tl, p.tu, p.a1, p.a2, p.a3, p.a4);
+        if constexpr (SOFT) {
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) load_softR(p.sr[t], rmode, d, ir, w, slot(t));
+        }
     }
 
     __device__ __forceinline__ void flushC(int n, double mv) const
@@ -872,6 +1057,15 @@ struct Ipm {
                              rml, rmu);
                     const double itl = rcp_nr(p.tl[t]), itu = rcp_nr(p.tu[t]);
                     e = (p.ll[t] * p.rdl[t] - rml) * itl - (p.lu[t] * p.rdu[t] - rmu) * itu;
+                    if constexpr (SOFT) {
+                        if (p.sr[t].sm != 0.0) {
+                            double el = (p.ll[t] * p.rdl[t] - rml) * itl, eu = (p.lu[t] * p.rdu[t] - rmu) * itu;
+                            double Dl, gl, Du, gu, rmsl, rmsu;
+                            soft_rhs(p.sr[t], rmode, shift, p.ll[t] * itl, p.lu[t] * itu, el, eu, Dl, gl, Du, gu, rmsl,
+                                     rmsu);
+                            e = el - eu;
+                        }
+                    }
                 }
                 if (c < NC) s.e[c] = e;
                 if (t == 0) e0 = e;
@@ -914,6 +1108,7 @@ struct Ipm {
         double zc, pic;  // current z_n, pi_{n+1} (absolute formulation: step = solution - iterate)
         double m[NCT], rdl[NCT], rdu[NCT], ll[NCT], lu[NCT], tl[NCT], tu[NCT];
         double a1[NCT], a2[NCT], a3[NCT], a4[NCT];
+        SoftR sr[NCS];
     };
 
     __device__ __forceinline__ void loadB(PreB& p, int n, int rmode, int ob, int odl, int odu) const
@@ -939,11 +1134,16 @@ struct Ipm {
         }
         if constexpr (NG > 0) fetch<NG, NZ, EGr>(p.G, d + Lo.D_G, p.sG);
         load_slots_rm(rmode, d, ir, w, odl, odu, p.m, p.rdl, p.rdu, p.ll, p.lu, p.tl, p.tu, p.a1, p.a2, p.a3, p.a4);
+        if constexpr (SOFT) {
+#pragma unroll
+            for (int t = 0; t < NCT; ++t) load_softR(p.sr[t], rmode, d, ir, w, slot(t));
+        }
     }
 
     struct OutB {
         double dz, dpi;
         double dll[NCT], dlu[NCT], dtl[NCT], dtu[NCT];
+        SoftOutB so[NCS];
     };
 
     __device__ __forceinline__ void flushB(int n, const OutB& o, int oz, int opi, int oll, int olu, int otl,
@@ -960,6 +1160,20 @@ struct Ipm {
                 w[olu + c] = o.dlu[t];
                 w[otl + c] = o.dtl[t];
                 w[otu + c] = o.dtu[t];
+                if constexpr (SOFT) {
+                    if (o.so[t].sm != 0.0) {
+                        // the affine step keeps only what the corrector reads
+                        const bool aff = oll == Lo.W_all;
+                        if (!aff) {
+                            w[Lo.W_dsl + c] = o.so[t].dsl;
+                            w[Lo.W_dsu + c] = o.so[t].dsu;
+                        }
+                        w[(aff ? Lo.W_alsl : Lo.W_dlsl) + c] = o.so[t].dlsl;
+                        w[(aff ? Lo.W_alsu : Lo.W_dlsu) + c] = o.so[t].dlsu;
+                        w[(aff ? Lo.W_atsl : Lo.W_dtsl) + c] = o.so[t].dtsl;
+                        w[(aff ? Lo.W_atsu : Lo.W_dtsu) + c] = o.so[t].dtsu;
+                    }
+                }
             }
         }
     }
@@ -1025,6 +1239,11 @@ struct Ipm {
                 rm_value(rmode, shift, ll[t], lu[t], tl[t], tu[t], p.a1[t], p.a2[t], p.a3[t], p.a4[t], rml[t],
                          rmu[t]);
             }
+            SoftR sq[NCS];
+            if constexpr (SOFT) {
+#pragma unroll
+                for (int t = 0; t < NCT; ++t) sq[t] = p.sr[t];
+            }
             if (n > 0) flushB(n - 1, o, oz, opi, oll, olu, otl, otu);
             if (n < N) loadB(p, n + 1, rmode, ob, odl, odu);
             wsync();
@@ -1077,6 +1296,7 @@ struct Ipm {
             for (int t = 0; t < NCT; ++t) {
                 const int c = slot(t);
                 double dll = 0.0, dlu = 0.0, dtl = 0.0, dtu = 0.0;
+                if constexpr (SOFT) o.so[t] = SoftOutB{};
                 if (c < NC && m[t] != 0.0) {
                     double gdz;
                     if (c < NZ) {
@@ -1087,8 +1307,35 @@ struct Ipm {
 #pragma unroll
                         for (int k = 0; k < NZ; ++k) gdz += s.G[r + k * LDG] * s.z[k];
                     }
-                    dtl = gdz - rdl[t];
-                    dtu = -gdz - rdu[t];
+                    if constexpr (SOFT) {
+                        double dsl = 0.0, dsu = 0.0;
+                        if (sq[t].sm != 0.0) {
+                            // slack steps and the steps of their bound rows
+                            const SoftR& q = sq[t];
+                            const double itl = rcp_nr(tl[t]), itu = rcp_nr(tu[t]);
+                            const double wl = ll[t] * itl, wu = lu[t] * itu;
+                            double el = (ll[t] * rdl[t] - rml[t]) * itl, eu = (lu[t] * rdu[t] - rmu[t]) * itu;
+                            double Dl, gl, Du, gu, rmsl, rmsu;
+                            soft_rhs(q, rmode, shift, wl, wu, el, eu, Dl, gl, Du, gu, rmsl, rmsu);
+                            dsl = -(gl + wl * gdz) * rcp_nr(Dl);
+                            dsu = -(gu - wu * gdz) * rcp_nr(Du);
+                            const double dtsl = dsl - q.rdsl, dtsu = dsu - q.rdsu;
+                            const double dlsl = -(rmsl + q.lsl * dtsl) * rcp_nr(q.tsl);
+                            const double dlsu = -(rmsu + q.lsu * dtsu) * rcp_nr(q.tsu);
+                            if (dlsl < 0.0) amin = fmin(amin, -q.lsl * __builtin_amdgcn_rcp(dlsl));
+                            if (dlsu < 0.0) amin = fmin(amin, -q.lsu * __builtin_amdgcn_rcp(dlsu));
+                            if (dtsl < 0.0) amin = fmin(amin, -q.tsl * __builtin_amdgcn_rcp(dtsl));
+                            if (dtsu < 0.0) amin = fmin(amin, -q.tsu * __builtin_amdgcn_rcp(dtsu));
+                            s1 += q.lsl * dtsl + dlsl * q.tsl + q.lsu * dtsu + dlsu * q.tsu;
+                            s2 += dlsl * dtsl + dlsu * dtsu;
+                            o.so[t] = SoftOutB{1.0, dsl, dsu, dlsl, dlsu, dtsl, dtsu};
+                        }
+                        dtl = gdz + dsl - rdl[t];
+                        dtu = -gdz + dsu - rdu[t];
+                    } else {
+                        dtl = gdz - rdl[t];
+                        dtu = -gdz - rdu[t];
+                    }
                     dll = -(rml[t] + ll[t] * dtl) * rcp_nr(tl[t]);
                     dlu = -(rmu[t] + lu[t] * dtu) * rcp_nr(tu[t]);
                     if (ABS) {
@@ -1401,6 +1648,17 @@ struct Ipm {
                 ir[Lo.I_lu + c] = on ? 1.0 : 0.0;
                 ir[Lo.I_tl + c] = on ? (warm == 1 ? fmax(gz - lo, 1.0) : fmax(-lo, 1.0)) : 0.0;
                 ir[Lo.I_tu + c] = on ? (warm == 1 ? fmax(hi - gz, 1.0) : fmax(hi, 1.0)) : 0.0;
+                if constexpr (SOFT) {
+                    // slacks s = 0 (cold start only), bound rows t_s = max(s -
+                    // ls, 1), lam_s = 1; slots without slacks hold zeros
+                    const bool sf = d[Lo.D_sm + c] != 0.0;
+                    ir[Lo.I_sl + c] = 0.0;
+                    ir[Lo.I_su + c] = 0.0;
+                    ir[Lo.I_lsl + c] = sf ? 1.0 : 0.0;
+                    ir[Lo.I_lsu + c] = sf ? 1.0 : 0.0;
+                    ir[Lo.I_tsl + c] = sf ? fmax(-d[Lo.D_lls + c], 1.0) : 0.0;
+                    ir[Lo.I_tsu + c] = sf ? fmax(-d[Lo.D_lus + c], 1.0) : 0.0;
+                }
             }
         }
         __syncthreads();
@@ -1421,6 +1679,16 @@ struct Ipm {
                 o[Lo.I_lu + c] = w[Lo.W_dlu + c];
                 o[Lo.I_tl + c] = w[Lo.W_dtl + c];
                 o[Lo.I_tu + c] = w[Lo.W_dtu + c];
+                if constexpr (SOFT) {
+                    if (Dp(n)[Lo.D_sm + c] != 0.0) {
+                        o[Lo.I_sl + c] = w[Lo.W_dsl + c];
+                        o[Lo.I_su + c] = w[Lo.W_dsu + c];
+                        o[Lo.I_lsl + c] = w[Lo.W_dlsl + c];
+                        o[Lo.I_lsu + c] = w[Lo.W_dlsu + c];
+                        o[Lo.I_tsl + c] = w[Lo.W_dtsl + c];
+                        o[Lo.I_tsu + c] = w[Lo.W_dtsu + c];
+                    }
+                }
             }
         }
     }

@@ -1,5 +1,6 @@
-"""GPU parity of soft constraints (Section 2.2) against the oracle: the block
-kernel's soft build, called through the C-ABI.
+"""GPU parity of soft constraints (Section 2.2) against the oracle: the soft
+builds of the one-wave kernel and of the block kernel, called through the
+C-ABI.
 
 * the Newton step at random interior iterates (slack blocks included) on
   tiny random soft QPs: every block element by element, 1e-9;
