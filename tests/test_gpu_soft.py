@@ -62,15 +62,30 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b)))) if b.size else 0.0
 
 
-def test_soft_newton_step_matches_oracle():
+@pytest.fixture
+def wave_bound():
+    L = B.lib()
+    old = L.oqp_get_wave_max()
+    yield L
+    L.oqp_set_wave_max(old)
+
+
+@pytest.mark.parametrize("wmax", [24, 0])
+def test_soft_newton_step_matches_oracle(wmax, wave_bound):
+    """wmax 24: the one-wave kernel's soft build; 0: every instance on the
+    block kernel's soft build."""
+    wave_bound.oqp_set_wave_max(wmax)
     qps, its = [], []
     for seed in range(48):
         qp, rng = soft_tiny(seed, nx_range=(1, 6), nu_range=(0, 4), ng_max=3,
                             x0_mode=["box", "free", "eliminated"][seed % 3])
         qps.append(qp)
         its.append(random_interior_iterate_soft(qp, rng))
-    say("soft Newton step x48 vs oracle")
+    say(f"soft Newton step x48 vs oracle, wave bound {wmax}")
     b = B.Batch(qps, B.default_arg()).load()
+    groups = {b.variant(i)[0] for i in range(len(qps))}
+    nv = B.lib().oqp_variant_count()
+    assert (max(groups) >= nv) if wmax == 0 else (min(groups) < nv)
     for i, it in enumerate(its):
         b.set_iterate(i, it)
     b.newton(0.3).fetch().sync()
