@@ -464,8 +464,8 @@ def main():
                     help="run only a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        sys.exit("bench.py: this build measures one GPU only (--gpus 1). Instances are independent; "
-                 "the multi-GPU design shards the batch by estimated cost with no exchange.")
+        sys.exit("bench.py: the benchmark runs on one GPU only (--gpus 1); instances are independent, "
+                 "and a multi-GPU run would shard the batch by estimated cost with no exchange.")
 
     import numpy as np
     import torch
