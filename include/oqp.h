@@ -65,8 +65,18 @@ extern "C" {
                             step); stat.res holds the residual norms of the returned point */
 #define OQP_MODE_ROBUST 3 /* FP64, delta formulation, Riccati factors from an array algorithm (QR of
                              [chol(Phi)'; U]) instead of the Cholesky factor of the normal matrix
-                             Phi + U'U (mode "robust" of Section 4.2); batch only, for stage blocks
-                             covered by a one-wave variant (nx + nu up to 24 after padding) */
+                             Phi + U'U (mode "robust" of Section 4.2), and up to ir_max (default 4)
+                             refinement steps on the prediction-centering-correction direction;
+                             batch only, for stage blocks covered by a one-wave variant (nx + nu up
+                             to 24 after padding) */
+#define OQP_MODE_BALANCE 4 /* FP64, delta formulation (mode "balance" of Section 4.2): Cholesky
+                              factors whose accuracy is checked each iteration by the refinement
+                              residual of the predictor step; when it exceeds
+                              ir_tol * max(1, ||r||_inf) the iteration is factored again with the
+                              array algorithm of OQP_MODE_ROBUST (oqp_stat.qr_refactors counts
+                              them), and up to ir_max (default 2) refinement steps run on the
+                              prediction-centering-correction direction; batch only, same stage
+                              blocks as OQP_MODE_ROBUST */
 
 typedef struct oqp_dims oqp_dims;
 typedef struct oqp_qp oqp_qp;
@@ -106,6 +116,7 @@ typedef struct {
                           from a cold start by the FP64 kernel */
     double mu;         /* duality measure lam't / n_c at the returned iterate */
     double res[4];     /* inf-norms of r_g, r_b, r_d and lam .* t (eq:alg:pdipm:delta) */
+    int qr_refactors;  /* balance mode: iterations factored again with the array algorithm */
 } oqp_stat;
 
 /* ---- dims (Section 2.2: per-stage nx, nu, nbu, nbx, ng) ---------------- */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "liboqp.so")
 OK, PENDING = 0, 1
 EINVAL, ENOMEM, EDEVICE, EBUSY, ESTATE = -1, -2, -3, -4, -5
 SUCCESS, MAX_ITER, MIN_STEP, NAN = 0, 1, 2, 3
-MODE_F64, MODE_MIXED, MODE_ABS, MODE_ROBUST = 0, 1, 2, 3
+MODE_F64, MODE_MIXED, MODE_ABS, MODE_ROBUST, MODE_BALANCE = 0, 1, 2, 3, 4
 
 _P = ct.POINTER(ct.c_double)
 _PI = ct.POINTER(ct.c_int)
@@ -42,7 +42,7 @@ class Arg(ct.Structure):
 
 class Stat(ct.Structure):
     _fields_ = [("status", ct.c_int), ("iters", ct.c_int), ("ir_steps", ct.c_int), ("fell_back_f64", ct.c_int),
-                ("mu", ct.c_double), ("res", ct.c_double * 4)]
+                ("mu", ct.c_double), ("res", ct.c_double * 4), ("qr_refactors", ct.c_int)]
 
 
 class ServerCfg(ct.Structure):
@@ -289,6 +289,7 @@ class Result:
     res: np.ndarray
     sol: dict
     fell_back_f64: int = 0
+    qr_refactors: int = 0
 
 
 def _sizes(qp):
@@ -384,7 +385,8 @@ class Batch:
 
     def result(self, i: int) -> Result:
         st = self.stat(i)
-        return Result(st.status, st.iters, st.ir_steps, st.mu, np.array(st.res[:]), self.solution(i), st.fell_back_f64)
+        return Result(st.status, st.iters, st.ir_steps, st.mu, np.array(st.res[:]), self.solution(i), st.fell_back_f64,
+                      st.qr_refactors)
 
     def results(self) -> List[Result]:
         return [self.result(i) for i in range(len(self.qps))]
@@ -613,7 +615,7 @@ class Server:
     def result(self, ticket) -> Result:
         st = self.poll(ticket)
         return Result(st.status, st.iters, st.ir_steps, st.mu, np.array(st.res[:]), self.solution(ticket),
-                      st.fell_back_f64)
+                      st.fell_back_f64, st.qr_refactors)
 
     def release(self, ticket):
         _check(lib().oqp_server_release(self.h, ticket))

@@ -438,7 +438,9 @@ extern "C" void oqp_arg_default(oqp_arg* a, int mode)
 {
     if (!a) return;
     std::memset(a, 0, sizeof(*a));
-    a->mode = (mode == OQP_MODE_MIXED || mode == OQP_MODE_ABS || mode == OQP_MODE_ROBUST) ? mode : OQP_MODE_F64;
+    a->mode = (mode == OQP_MODE_MIXED || mode == OQP_MODE_ABS || mode == OQP_MODE_ROBUST || mode == OQP_MODE_BALANCE)
+                  ? mode
+                  : OQP_MODE_F64;
     const double tol = a->mode == OQP_MODE_MIXED ? 1e-6 : 1e-8;
     a->tol_stat = a->tol_eq = a->tol_ineq = a->tol_comp = tol;
     a->iter_max = 100;
@@ -448,7 +450,9 @@ extern "C" void oqp_arg_default(oqp_arg* a, int mode)
     a->t_min = 1e-16;
     a->reg_prim = 0.0;
     a->corr_ratio = 10.0;
-    a->ir_max = a->mode == OQP_MODE_MIXED ? 4 : 0;
+    // refinement steps: a few in balance mode, more in robust mode (Section
+    // 4.2), as many on the mixed path
+    a->ir_max = (a->mode == OQP_MODE_MIXED || a->mode == OQP_MODE_ROBUST) ? 4 : (a->mode == OQP_MODE_BALANCE ? 2 : 0);
     a->ir_tol = 1e-10;
     a->warm_start = 0;
     a->cond_N = 0;
@@ -457,7 +461,8 @@ extern "C" void oqp_arg_default(oqp_arg* a, int mode)
 int check_arg(const oqp_arg* a)
 {
     if (!a) return fail(OQP_EINVAL, "NULL oqp_arg");
-    if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED && a->mode != OQP_MODE_ABS && a->mode != OQP_MODE_ROBUST)
+    if (a->mode != OQP_MODE_F64 && a->mode != OQP_MODE_MIXED && a->mode != OQP_MODE_ABS && a->mode != OQP_MODE_ROBUST &&
+        a->mode != OQP_MODE_BALANCE)
         return fail(OQP_EINVAL, "unknown mode %d", a->mode);
     if (a->iter_max < 0 || !(a->gamma > 0.0 && a->gamma <= 1.0) || a->warm_start < 0 || a->warm_start > 2 ||
         a->ir_max < 0 || a->cond_N < 0 || (a->warm_start != 0 && a->cond_N != 0))
@@ -708,7 +713,7 @@ static constexpr size_t kMaxCondLds = 64 * 1024;
 // the instance whatever the one-wave bound.
 static int select_for_mode(int mx, int mu, int mg, int mode, int soft, KSel* out)
 {
-    if (soft || mode != OQP_MODE_ROBUST) return select_kernel_max(mx, mu, mg, out);
+    if (soft || (mode != OQP_MODE_ROBUST && mode != OQP_MODE_BALANCE)) return select_kernel_max(mx, mu, mg, out);
     const int v = pick_variant_max(mx, mu, mg);
     if (v < 0) return -1;
     int nx, nu, ng;
@@ -725,7 +730,9 @@ static int solve_shape(const oqp_dims* d, int cond_N, int mode, int soft, SolveS
         dims_max(d, &mx, &mu, &mg);
         if (select_for_mode(mx, mu, mg, mode, soft, &sh->ks))
             return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d%s", i,
-                        mode == OQP_MODE_ROBUST ? " (robust mode: one-wave variants only)" : "");
+                        (mode == OQP_MODE_ROBUST || mode == OQP_MODE_BALANCE)
+                            ? " (robust and balance modes: one-wave variants only)"
+                            : "");
         sh->onx = sh->ks.nx;
         sh->onu = sh->ks.nu;
         sh->ong = sh->ks.ng;
@@ -1279,6 +1286,7 @@ int kernel_build(int mode)
     if (mode == OQP_MODE_MIXED) return oqp::KM_MIXED;
     if (mode == OQP_MODE_ABS) return oqp::KM_ABS;
     if (mode == OQP_MODE_ROBUST) return oqp::KM_ROBUST;
+    if (mode == OQP_MODE_BALANCE) return oqp::KM_BALANCE;
     return oqp::KM_F64;
 }
 
@@ -1437,6 +1445,7 @@ extern "C" int oqp_batch_get_stat(const oqp_batch* b, int i, oqp_stat* st)
     st->iters = d.iters;
     st->ir_steps = d.ir_steps;
     st->fell_back_f64 = d.fell_back;
+    st->qr_refactors = d.qr_refactors;
     st->mu = d.mu;
     for (int k = 0; k < 4; ++k) st->res[k] = d.res[k];
     return OQP_OK;

@@ -1745,6 +1745,7 @@ struct Blk {
             st->iters = k;
             st->ir_steps = ir_steps;
             st->fell_back = fell_back;
+            st->qr_refactors = 0;
             st->mu = mu;
             st->res[0] = ng;
             st->res[1] = nb;

@@ -54,6 +54,13 @@ struct Ipm {
     static constexpr bool ROBUST = KM == KM_ROBUST;
     // soft constraints (Section 2.2): slack pairs on the soft layout
     static constexpr bool SOFT = KM == KM_SOFT;
+    // Cholesky factors checked each iteration by the refinement residual of
+    // the predictor step, the array algorithm when they are not accurate
+    // enough (Section 4.2, mode balance)
+    static constexpr bool BALANCE = KM == KM_BALANCE;
+    // FP64 refinement of the prediction-centering-correction direction
+    // (mixed path; modes balance and robust, Section 4.2)
+    static constexpr bool REFINE = MIXED || ROBUST || BALANCE;
     // arithmetic type of the factorization and of the right-hand-side sweeps
     // (FP32 in the mixed path; pivots, residuals and refinement stay FP64)
     using TS = typename std::conditional<MIXED, float, double>::type;
@@ -663,7 +670,8 @@ struct Ipm {
     // With absf (absolute formulation, Section 3.2) the right-hand side is
     // built from the data alone, -[g; b; d; r_m - 2 Lam T e]: the residual
     // matrix-vector products are skipped and their norms are not formed.
-    __device__ __forceinline__ bool passA(bool upd, double alpha, double shift, bool factor, bool absf, double& o_g,
+    __device__ __forceinline__ bool passA(bool upd, double alpha, double shift, bool factor, bool absf, bool qr,
+                                          double& o_g,
                                           double& o_b, double& o_d, double& o_m, double& o_lt) const
     {
         Smem& s = S();
@@ -881,7 +889,15 @@ struct Ipm {
                 }
                 if (n < N) trmm_LtF(s.Lx[nxt]);
                 wsync();
-                if constexpr (!ROBUST) {
+                // the array algorithm (robust build; balance build when this
+                // iteration's Cholesky factors were not accurate enough)
+                // factors M = Phi + V'V without forming V'V
+                if constexpr (BALANCE) {
+                    if (!qr) {
+                        if (n < N || NG > 0) syrk_VtV(n < N ? 0 : NX);
+                        wsync();
+                    }
+                } else if constexpr (!ROBUST) {
                     if (n < N || NG > 0) syrk_VtV(n < N ? 0 : NX);
                     wsync();
                 }
@@ -890,8 +906,9 @@ struct Ipm {
                 double dinv;
                 fact_ok = cholesky(rowL, dinv) && fact_ok;
                 if constexpr (ROBUST) {
-                    // M = Phi + V'V factored without forming V'V
                     if (n < N || NG > 0) qr_update(rowL, dinv, n < N ? 0 : NX);
+                } else if constexpr (BALANCE) {
+                    if (qr && (n < N || NG > 0)) qr_update(rowL, dinv, n < N ? 0 : NX);
                 }
                 if (lane < NZ) {
 #pragma unroll
@@ -1582,18 +1599,22 @@ struct Ipm {
         return wave_min(amin);
     }
 
-    // Iterative refinement of the step at the given offsets (mixed path).
-    // Stops when ||r_ir|| <= ir_tol * max(1, ||r||), when it stops
-    // decreasing, or after ir_max corrections.  Updates amax, s1, s2.
-    __device__ __forceinline__ int refine(int rmode, double shift, double rnorm, int oz, int opi, int oll, int olu,
-                                          int otl, int otu, double& amax, double& s1, double& s2) const
+    // Iterative refinement of the step at the given offsets.  Stops when
+    // ||r_ir|| <= ir_tol * max(1, ||r||), when it stops decreasing, or after
+    // max_steps corrections.  Updates amax, s1, s2; nir0 returns the
+    // residual norm of the unrefined step (the balance build's accuracy
+    // check of the factors).
+    __device__ __forceinline__ int refine(int rmode, double shift, double rnorm, int max_steps, int oz, int opi,
+                                          int oll, int olu, int otl, int otu, double& amax, double& s1, double& s2,
+                                          double& nir0) const
     {
         int steps = 0;
         double prev = HUGE_VAL;
-        for (int it = 0; it <= P.ir_max; ++it) {
+        for (int it = 0; it <= max_steps; ++it) {
             const double nir = passR(rmode, shift, oz, opi, oll, olu, otl, otu);
             __syncthreads();
-            if (!(nir > P.ir_tol * rnorm) || !(nir < prev) || it == P.ir_max) break;
+            if (it == 0) nir0 = nir;
+            if (!(nir > P.ir_tol * rnorm) || !(nir < prev) || it == max_steps) break;
             prev = nir;
             passC(RM_IR, 0.0, Lo.W_irg, Lo.W_irb, Lo.W_irdl, Lo.W_irdu);
             __syncthreads();
@@ -1715,11 +1736,15 @@ struct Ipm {
         // returned iterate; it reuses the single call site of pass A
         bool final_pass = false;
         int k_exit = 0;
+        // balance build: the iteration is factored with the array algorithm
+        // (after its Cholesky factors failed the accuracy check)
+        bool qr = false, refactor = false;
+        int qr_refactors = 0;
         for (k = 0;; ++k) {
             // residuals at the (updated) iterate; factorization unless the
             // last step was rejected as too short
             const bool fact_ok =
-                passA(upd, alpha, shift0, !rejected && !final_pass, absf && !final_pass, ng, nb, nd, nm, slt);
+                passA(upd, alpha, shift0, !rejected && !final_pass, absf && !final_pass, qr, ng, nb, nd, nm, slt);
             __syncthreads();
             mu = slt * inv2nc;
             if (final_pass) {
@@ -1769,11 +1794,15 @@ struct Ipm {
                     break;
                 }
             }
+            if constexpr (BALANCE) {
+                // a breakdown of the Cholesky factorization fails the check too
+                if (!fact_ok && !qr && !newton_mode) refactor = true;
+            }
             // round 0: predictor (affine step; in Newton mode the step itself)
             // round 1: Mehrotra corrector; round 2: predictor-centering step
             // when the conditional corrector is rejected (Section 4.2)
             double amax = HUGE_VAL, mu_aff = 0.0, smu = 0.0;
-            for (int round = 0; round < 3; ++round) {
+            for (int round = 0; round < 3 && !refactor; ++round) {
                 const int rmode = round == 1 ? RM_CORRECTOR : RM_SHIFT;
                 const double shift = round == 0 ? shift0 : smu;
                 const bool aff = round == 0 && !newton_mode;
@@ -1786,14 +1815,24 @@ struct Ipm {
                 const int otl = aff ? Lo.W_atl : Lo.W_dtl, otu = aff ? Lo.W_atu : Lo.W_dtu;
                 amax = passB(rmode, shift, Lo.W_rb, Lo.W_rdl, Lo.W_rdu, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, s1, s2);
                 __syncthreads();
-                if constexpr (MIXED) {
+                if constexpr (REFINE) {
                     // refinement of the prediction-centering-correction
                     // direction (Section 4.2); the affine predictor only
                     // feeds the centering parameter and the corrector
-                    // right-hand side and is used unrefined
-                    if (round > 0 || newton_mode || nc == 0) {
+                    // right-hand side and is used unrefined.  Balance build:
+                    // the predictor's residual checks the accuracy of this
+                    // iteration's Cholesky factors
+                    const bool dir = round > 0 || newton_mode || nc == 0;
+                    const bool check = BALANCE && !qr && !newton_mode && round == 0;
+                    if (dir || check) {
                         const double rnorm = fmax(1.0, fmax(fmax(ng, nb), fmax(nd, nm)));
-                        ir_steps += refine(rmode, shift, rnorm, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, amax, s1, s2);
+                        double nir0 = 0.0;
+                        ir_steps += refine(rmode, shift, rnorm, dir ? P.ir_max : 0, Lo.W_dz, Lo.W_dpi, oll, olu, otl,
+                                           otu, amax, s1, s2, nir0);
+                        if (check && !(nir0 <= P.ir_tol * rnorm)) {
+                            refactor = true;
+                            break;
+                        }
                     }
                 }
                 if (newton_mode || nc == 0) break;
@@ -1808,6 +1847,19 @@ struct Ipm {
                 } else {
                     break;
                 }
+            }
+            if constexpr (BALANCE) {
+                if (refactor) {
+                    // start the iteration over (no step taken) with the array
+                    // algorithm; the next iteration starts with Cholesky again
+                    refactor = false;
+                    qr = true;
+                    upd = false;
+                    ++qr_refactors;
+                    --k;
+                    continue;
+                }
+                qr = false;
             }
             if (newton_mode) break;
             alpha = fmin(1.0, P.gamma * amax);
@@ -1826,6 +1878,7 @@ struct Ipm {
             st->iters = k;
             st->ir_steps = ir_steps;
             st->fell_back = fell_back;
+            st->qr_refactors = qr_refactors;
             st->mu = mu;
             st->res[0] = ng;
             st->res[1] = nb;
@@ -1840,7 +1893,7 @@ struct Ipm {
 __host__ __device__ constexpr int ipm_max_waves(int nz, bool mixed) { return (nz > 24 || (mixed && nz > 16)) ? 1 : 2; }
 
 template <int NX, int NU, int NG, int KM>
-__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, ipm_max_waves(NX + NU, KM == KM_MIXED)))) void ipm_kernel(const InstDesc* __restrict__ desc, int count,
+__global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, ipm_max_waves(NX + NU, KM == KM_MIXED || KM == KM_BALANCE)))) void ipm_kernel(const InstDesc* __restrict__ desc, int count,
                                                     const double* __restrict__ data, double* __restrict__ iter,
                                                     double* __restrict__ work, double* __restrict__ step_out,
                                                     DevStat* __restrict__ stat, KParams P)

@@ -8,7 +8,7 @@ namespace oqp {
                                                  DevStat*, KParams, hipStream_t);
 #define OQP_EXTERN(x, u, g) \
     OQP_EXTERN1(x, u, g, KM_F64) OQP_EXTERN1(x, u, g, KM_MIXED) OQP_EXTERN1(x, u, g, KM_ABS) OQP_EXTERN1(x, u, g, KM_ROBUST) \
-    OQP_EXTERN1(x, u, g, KM_SOFT)
+    OQP_EXTERN1(x, u, g, KM_SOFT) OQP_EXTERN1(x, u, g, KM_BALANCE)
 OQP_VARIANTS(OQP_EXTERN)
 #undef OQP_EXTERN
 #undef OQP_EXTERN1
@@ -18,13 +18,13 @@ typedef void (*launch_fn)(const InstDesc*, int, const double*, double*, double*,
 
 struct Variant {
     int NX, NU, NG;
-    launch_fn fn[5];  // indexed by kernel build (KM_F64, KM_MIXED, KM_ABS, KM_ROBUST, KM_SOFT)
+    launch_fn fn[6];  // indexed by kernel build (KM_F64, KM_MIXED, KM_ABS, KM_ROBUST, KM_SOFT, KM_BALANCE)
 };
 
 #define OQP_ENTRY(x, u, g) \
     {x, u, g,              \
      {&launch_ipm<x, u, g, KM_F64>, &launch_ipm<x, u, g, KM_MIXED>, &launch_ipm<x, u, g, KM_ABS>, &launch_ipm<x, u, g, KM_ROBUST>, \
-      &launch_ipm<x, u, g, KM_SOFT>}},
+      &launch_ipm<x, u, g, KM_SOFT>, &launch_ipm<x, u, g, KM_BALANCE>}},
 static const Variant kVariants[] = {OQP_VARIANTS(OQP_ENTRY)};
 #undef OQP_ENTRY
 
@@ -41,7 +41,7 @@ int variant_launch(int v, int km, const InstDesc* desc, int count, const double*
                    double* step, DevStat* stat, const KParams& P, void* stream)
 {
     if (count <= 0) return 0;
-    if (km < KM_F64 || km > KM_SOFT) return -1;
+    if (km < KM_F64 || km > KM_BALANCE) return -1;
     kVariants[v].fn[km](desc, count, data, iter, work, step, stat, P, (hipStream_t)stream);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -196,6 +196,8 @@ struct DevStat {
     int32_t fell_back;  // the mixed path handed the instance to the FP64 kernel
     double mu;
     double res[4];  // inf-norms of r_g, r_b, r_d, lam.*t at the returned iterate
+    int32_t qr_refactors;  // balance build: iterations factored again with the array algorithm
+    int32_t pad;
 };
 
 // Solver arguments passed by value to every launch.
@@ -213,8 +215,9 @@ enum { KMODE_SOLVE = 0, KMODE_NEWTON = 1, KMODE_FALLBACK = 2 };
 // Compiled kernel builds: FP64 delta formulation, mixed (FP32 factorization
 // and sweeps, FP64 refinement), FP64 absolute formulation, FP64 with the
 // QR-based (array algorithm) factorization, FP64 delta formulation with
-// soft constraints (block kernel, soft layout).
-enum { KM_F64 = 0, KM_MIXED = 1, KM_ABS = 2, KM_ROBUST = 3, KM_SOFT = 4 };
+// soft constraints (soft layout), FP64 Cholesky checked by its refinement
+// residual with the array algorithm as fallback (one-wave kernel).
+enum { KM_F64 = 0, KM_MIXED = 1, KM_ABS = 2, KM_ROBUST = 3, KM_SOFT = 4, KM_BALANCE = 5 };
 enum { ST_SUCCESS = 0, ST_MAX_ITER = 1, ST_MIN_STEP = 2, ST_NAN = 3, ST_FALLBACK = 4 };
 
 }  // namespace oqp

@@ -404,8 +404,8 @@ extern "C" int oqp_server_init(const oqp_server_cfg* cfg, const oqp_arg* arg, vo
     if (rc) return rc;
     rc = check_arg(arg);
     if (rc) return rc;
-    if (arg->cond_N != 0 || arg->warm_start != 0 || arg->mode == OQP_MODE_ROBUST)
-        return fail(OQP_EINVAL, "oqp_server_init: partial condensing, warm start and robust mode are batch options");
+    if (arg->cond_N != 0 || arg->warm_start != 0 || arg->mode == OQP_MODE_ROBUST || arg->mode == OQP_MODE_BALANCE)
+        return fail(OQP_EINVAL, "oqp_server_init: partial condensing, warm start, robust and balance modes are batch options");
     if (!host_mem || !dev_mem || !streams || !out) return fail(OQP_EINVAL, "oqp_server_init: NULL argument");
     if (nstreams < 2 || nstreams > OQP_SERVER_MAX_STREAMS)
         return fail(OQP_EINVAL, "oqp_server_init: need 2..%d streams", OQP_SERVER_MAX_STREAMS);
@@ -545,6 +545,7 @@ extern "C" int oqp_server_poll(const oqp_server* s, uint64_t ticket, oqp_stat* s
         st->iters = r.stat.iters;
         st->ir_steps = r.stat.ir_steps;
         st->fell_back_f64 = r.stat.fell_back;
+        st->qr_refactors = r.stat.qr_refactors;
         st->mu = r.stat.mu;
         for (int k = 0; k < 4; ++k) st->res[k] = r.stat.res[k];
     }
@@ -672,6 +673,7 @@ extern "C" int oqp_server_replay(oqp_server* s, const void* const* packed, const
                 o.iters = r.stat.iters;
                 o.ir_steps = r.stat.ir_steps;
                 o.fell_back_f64 = r.stat.fell_back;
+                o.qr_refactors = r.stat.qr_refactors;
                 o.mu = r.stat.mu;
                 for (int k = 0; k < 4; ++k) o.res[k] = r.stat.res[k];
             }

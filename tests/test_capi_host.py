@@ -114,8 +114,12 @@ def test_batch_size_and_plan_errors():
     assert L.oqp_batch_bytes(arr1, 1, ct.byref(B.default_arg()), ct.byref(hb), ct.byref(db)) == B.OK
     assert L.oqp_batch_bytes(arr1, 1, ct.byref(rob), ct.byref(hb), ct.byref(db)) == B.EINVAL
     assert b"robust" in L.oqp_last_error()
+    bal = B.default_arg(B.MODE_BALANCE)   # balance mode: the same one-wave variants
+    assert bal.mode == B.MODE_BALANCE and bal.ir_max == 2 and rob.ir_max == 4
+    assert L.oqp_batch_bytes(arr, 3, ct.byref(bal), ct.byref(hb), ct.byref(db)) == B.OK
+    assert L.oqp_batch_bytes(arr1, 1, ct.byref(bal), ct.byref(hb), ct.byref(db)) == B.EINVAL
     unknown = B.default_arg()
-    unknown.mode = 4
+    unknown.mode = 5
     assert L.oqp_batch_bytes(arr, 3, ct.byref(unknown), ct.byref(hb), ct.byref(db)) == B.EINVAL
     assert L.oqp_batch_bytes(arr, 0, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.EINVAL
 
