@@ -12,6 +12,8 @@ Further legs on the same line (context, not the headline):
     horizon (condensing and expansion inside the timed solve);
   * abs: the same batch in the absolute formulation (mode speed_abs);
   * robust: the same batch with the QR-based factorization (mode robust);
+  * balance: the same batch with checked Cholesky factors and the QR-based
+    factorization as fallback (mode balance);
   * warm: the next receding-horizon problem of every solved instance, cold
     and warm-started from the shifted solution;
   * soft: the same batch with soft position boxes (every instance
@@ -248,10 +250,14 @@ def leg_abs(B, torch, np, qps, steps):
             "kkt_res_p50": float(np.median(res)) if res.size else None, "tol_comp_on_mu": 1e-8}
 
 
-def leg_robust(B, torch, np, qps, steps):
+def leg_robust(B, torch, np, qps, steps, mode=None):
     """The headline batch with the QR-based factorization (mode robust):
-    same iterations as the Cholesky path, factors from an array algorithm."""
-    b = B.Batch(qps, B.default_arg(B.MODE_ROBUST)).load().sync()
+    same iterations as the Cholesky path, factors from an array algorithm,
+    refinement of the prediction-centering-correction direction; or (mode
+    balance) with Cholesky factors checked by the predictor's refinement
+    residual and refactored with the array algorithm when the check fails."""
+    mode = B.MODE_ROBUST if mode is None else mode
+    b = B.Batch(qps, B.default_arg(mode)).load().sync()
     b.solve()
     torch.cuda.synchronize()
     ms = []
@@ -269,7 +275,8 @@ def leg_robust(B, torch, np, qps, steps):
     med = float(np.median(ms))
     del b
     return {"value": round(ok / (med * 1e-3), 1), "unit": "solves/s", "ms_per_step": round(med, 3), "solves_ok": ok,
-            "iters_p50": float(np.percentile(iters, 50)), "iters_max": int(iters.max())}
+            "iters_p50": float(np.percentile(iters, 50)), "iters_max": int(iters.max()),
+            "ir_steps": int(sum(x.ir_steps for x in stats)), "qr_refactors": int(sum(x.qr_refactors for x in stats))}
 
 
 def _median_solve_ms(b, torch, np, steps):
@@ -584,6 +591,8 @@ def main():
     if args.robust_steps > 0:
         log("bench: QR-based factorization (robust mode) leg")
         line["robust"] = leg_robust(B, torch, np, qps, args.robust_steps)
+        log("bench: balance mode")
+        line["balance"] = leg_robust(B, torch, np, qps, args.robust_steps, B.MODE_BALANCE)
     if args.abs_steps > 0:
         log("bench: absolute-formulation leg")
         line["abs"] = leg_abs(B, torch, np, qps, args.abs_steps)
