@@ -946,7 +946,7 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
     prob_t p;
     int rc = prob_build(qp, &p);
     if (rc) return rc;
-    if (p.nsoft > 0 && (arg->warm_start != 0 || arg->abs_form != 0)) { prob_free(&p); return ORC_EINVAL; }
+    if (p.nsoft > 0 && arg->abs_form != 0) { prob_free(&p); return ORC_EINVAL; }
     ivec_t v, r, d, dc;
     ivec_alloc(&p, &v); ivec_alloc(&p, &r); ivec_alloc(&p, &d); ivec_alloc(&p, &dc);
     int nc = p.ncon, nsf = p.nsoft;
@@ -956,9 +956,10 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
     /* Initial point.  Cold start: y = 0, pi = 0, t = max(C y - d, 1), lam = 1
      * (slacks s = 0, their bounds' t = max(s - ls, 1), lam = 1).
      * Warm start (Section 4.2) from the iterate passed in `sol`: with a primal
-     * guess, y is the guess and the rest is set as in the cold start at that
-     * y; with a primal and dual guess, every block is the guess, multipliers
-     * and slacks clamped below as in the iterate update. */
+     * guess, y and the slacks s are the guess and the rest is set as in the
+     * cold start at that point; with a primal and dual guess, every block is
+     * the guess, multipliers and slacks clamped below as in the iterate
+     * update. */
     if (arg->warm_start != 0) ivec_from_user(&p, sol, &v);
     if (arg->warm_start == 2) {
         for (int i = 0; i < nc; ++i) {
@@ -966,6 +967,12 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
             if (v.lu[i] < arg->lam_min) v.lu[i] = arg->lam_min;
             if (v.tl[i] < arg->t_min) v.tl[i] = arg->t_min;
             if (v.tu[i] < arg->t_min) v.tu[i] = arg->t_min;
+        }
+        for (int i = 0; i < nsf; ++i) {
+            if (v.lsl[i] < arg->lam_min) v.lsl[i] = arg->lam_min;
+            if (v.lsu[i] < arg->lam_min) v.lsu[i] = arg->lam_min;
+            if (v.tsl[i] < arg->t_min) v.tsl[i] = arg->t_min;
+            if (v.tsu[i] < arg->t_min) v.tsu[i] = arg->t_min;
         }
     } else {
         if (arg->warm_start == 0)
@@ -978,18 +985,22 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
                 int c = p.coff[n] + k;
                 double gz = 0.0;
                 for (int j = 0; j < s->nz; ++j) gz += s->G[IX(k, j, s->nc)] * z[j];
-                double tl0 = gz - s->lo[k], tu0 = s->hi[k] - gz;
+                /* slacks of a soft row: zero, or the guess */
+                const int js = s->srow[k];
+                const int J = js >= 0 ? p.soff[n] + js : 0;
+                const double sl0 = (js >= 0 && arg->warm_start == 1) ? v.sl[J] : 0.0;
+                const double su0 = (js >= 0 && arg->warm_start == 1) ? v.su[J] : 0.0;
+                double tl0 = gz + sl0 - s->lo[k], tu0 = s->hi[k] - gz + su0;
                 v.tl[c] = tl0 > 1.0 ? tl0 : 1.0;
                 v.tu[c] = tu0 > 1.0 ? tu0 : 1.0;
                 v.ll[c] = 1.0;
                 v.lu[c] = 1.0;
-                const int js = s->srow[k];
                 if (js >= 0) {
-                    const int J = p.soff[n] + js;
-                    v.sl[J] = 0.0;
-                    v.su[J] = 0.0;
-                    v.tsl[J] = -s->lls[js] > 1.0 ? -s->lls[js] : 1.0;
-                    v.tsu[J] = -s->lus[js] > 1.0 ? -s->lus[js] : 1.0;
+                    const double tsl0 = sl0 - s->lls[js], tsu0 = su0 - s->lus[js];
+                    v.sl[J] = sl0;
+                    v.su[J] = su0;
+                    v.tsl[J] = tsl0 > 1.0 ? tsl0 : 1.0;
+                    v.tsu[J] = tsu0 > 1.0 ? tsu0 : 1.0;
                     v.lsl[J] = 1.0;
                     v.lsu[J] = 1.0;
                 }

@@ -172,8 +172,6 @@ def test_no_soft_rows_is_the_hard_problem():
 def test_soft_rejections():
     sq, _ = soft_tiny(5)
     with pytest.raises(ValueError):
-        O.solve(sq, O.Arg(warm_start=1))
-    with pytest.raises(ValueError):
         O.solve(sq, O.Arg(abs_form=1))
     bad = sq.copy()
     n = next(i for i in range(bad.N + 1) if len(bad.idxs[i]))
@@ -182,3 +180,67 @@ def test_soft_rejections():
         getattr(bad, k)[n] = np.concatenate([getattr(bad, k)[n], getattr(bad, k)[n][:1]])
     with pytest.raises(ValueError):
         O.solve(bad)  # a row softened twice
+
+
+# ---------------------------------------------------------------------------
+# Warm start with slacks (Section 4.2): the primal guess includes s^l, s^u
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_soft_initial_point_matches_definition(seed):
+    """iter_max = 0 returns the initial point: cold start (y' = 0), primal
+    guess (y' = [y; s] kept, lam = 1, pi = 0, t = max(C'y' - d', 1) over every
+    one-sided row of the augmented QP), primal-dual guess (kept, clamped)."""
+    qp, rng = soft_tiny(400 + seed, ng_max=2)
+    dq = DenseSoftQp(qp)
+    guess = random_interior_iterate_soft(qp, rng, scale=0.7)
+    if guess["lam_sl"].size:
+        guess["lam_sl"][0] = 0.0   # below the clamps
+        guess["t_su"][-1] = -0.5
+    for warm in (0, 1, 2):
+        r = O.solve(qp, O.Arg.with_tol(1e-8, iter_max=0, warm_start=warm), guess=guess if warm else None)
+        if warm == 2:
+            for k in ALL:
+                want = np.maximum(guess[k], 1e-16) if k.startswith(("lam", "t_")) else guess[k]
+                assert np.array_equal(r.sol[k], want), (warm, k)
+            continue
+        y0, _, _, _ = dq.stack(guess) if warm == 1 else (np.zeros(dq.nv), None, None, None)
+        got = np.concatenate([dq.base.y_from(r.sol["u"], r.sol["x"]), r.sol["s_l"], r.sol["s_u"]])
+        assert np.array_equal(got, y0), warm
+        assert np.all(r.sol["pi"] == 0.0)
+        lam = np.concatenate([r.sol[k] for k in ("lam_l", "lam_u", "lam_sl", "lam_su")])
+        t = np.concatenate([r.sol[k] for k in ("t_l", "t_u", "t_sl", "t_su")])
+        assert np.all(lam == 1.0)
+        assert np.allclose(t, np.maximum(dq.Cin @ y0 - dq.d, 1.0), rtol=0, atol=1e-14), warm
+
+
+def test_soft_primal_dual_guess_at_the_solution_exits_at_once():
+    sq = W.mass_spring_chain8_soft(222)
+    cold = O.solve(sq, O.Arg.with_tol(1e-10))
+    assert cold.status == O.SUCCESS
+    again = O.solve(sq, O.Arg.with_tol(1e-10, warm_start=2), guess=cold.sol)
+    assert again.status == O.SUCCESS and again.iters == 0
+    for k in ALL:
+        assert np.array_equal(again.sol[k], np.maximum(cold.sol[k], 1e-16) if k.startswith(("lam", "t_"))
+                              else cold.sol[k]), k
+
+
+@pytest.mark.parametrize("warm", [1, 2])
+def test_soft_warm_started_solves_reach_the_cold_minimiser(warm):
+    for i in (0, 222, 350):
+        sq = W.mass_spring_chain8_soft(i)
+        cold = O.solve(sq, O.Arg.with_tol(1e-10))
+        rng = np.random.default_rng(i)
+        guess = {k: v + 0.05 * rng.standard_normal(v.shape) for k, v in cold.sol.items()}
+        for k in guess:
+            if k.startswith(("lam", "t_")):
+                guess[k] = np.maximum(guess[k], 1.0)
+        ws = O.solve(sq, O.Arg.with_tol(1e-10, warm_start=warm), guess=guess)
+        assert ws.status == O.SUCCESS, (i, warm)
+        y = np.concatenate([ws.sol[k] for k in ("u", "x", "s_l", "s_u")])
+        yc = np.concatenate([cold.sol[k] for k in ("u", "x", "s_l", "s_u")])
+        # instance 0 has a weakly active input bound (lam and t both ~0 at
+        # the solution): there two KKT points at lam t <= 1e-10 can differ
+        # by ~sqrt(1e-10) in that input
+        assert np.max(np.abs(y - yc)) / max(1.0, np.max(np.abs(yc))) < 1e-5, (i, warm)
+        assert O.kkt_res(sq, ws.sol) <= 1e-10
