@@ -239,7 +239,10 @@ int oqp_batch_get_sol(const oqp_batch* batch, int i, double* u, double* x, doubl
  * eliminated with its bounds row by row (the Riccati recursion sees the row
  * weight w (Z + w_s) / (Z + w + w_s), the slack step follows from the state
  * and input step), cost linear in the number of slacks.  Such a batch needs
- * arg.mode OQP_MODE_F64, warm_start 0 and cond_N 0 (OQP_EINVAL otherwise);
+ * arg.mode OQP_MODE_F64 and cond_N 0 (OQP_EINVAL otherwise); a warm start's
+ * guess includes the slack blocks (oqp_batch_set_soft_iterate, or the last
+ * solution): warm_start = 1 keeps u, x, s^l, s^u and sets the rest by the
+ * cold-start rule at that point, 2 keeps every block, clamped below;
  * the server and oqp_pack take no slacks.  The duality measure and
  * oqp_stat.res count the slack rows: r_g includes the slack stationarity
  * rows, r_d the slack bounds, lam .* t their complementarity.

@@ -804,15 +804,15 @@ struct Plan {
 };
 
 // A batch with slacks anywhere (every instance then takes the soft builds):
-// FP64 delta formulation from a cold start, without condensing.
+// FP64 delta formulation, without condensing.
 static int batch_soft(const oqp_dims* const* dims, int count, const oqp_arg* arg, int* soft)
 {
     *soft = 0;
     for (int i = 0; i < count; ++i)
         if (dims[i] && dims_soft(dims[i])) *soft = 1;
     if (!*soft) return OQP_OK;
-    if (arg->mode != OQP_MODE_F64 || arg->warm_start != 0 || arg->cond_N != 0)
-        return fail(OQP_EINVAL, "batch: soft constraints need the FP64 mode, a cold start and no condensing");
+    if (arg->mode != OQP_MODE_F64 || arg->cond_N != 0)
+        return fail(OQP_EINVAL, "batch: soft constraints need the FP64 mode and no condensing");
     for (int i = 0; i < count; ++i)
         if (dims[i] && check_soft_dims(dims[i], "batch")) return OQP_EINVAL;
     return OQP_OK;
@@ -1409,8 +1409,6 @@ extern "C" int oqp_batch_set_arg(oqp_batch* b, const oqp_arg* a)
     if (rc) return rc;
     if (a->mode != b->arg.mode) return fail(OQP_EINVAL, "oqp_batch_set_arg: mode cannot change");
     if (a->cond_N != b->arg.cond_N) return fail(OQP_EINVAL, "oqp_batch_set_arg: cond_N cannot change");
-    if (b->soft && a->warm_start != 0)
-        return fail(OQP_EINVAL, "oqp_batch_set_arg: no warm start on a batch with soft constraints");
     b->arg = *a;
     return OQP_OK;
 }

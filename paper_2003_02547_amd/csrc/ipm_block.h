@@ -1559,6 +1559,17 @@ struct Blk {
                 ir[Lo.I_lu + c] = on ? fmax(ir[Lo.I_lu + c], P.lam_min) : 0.0;
                 ir[Lo.I_tl + c] = on ? fmax(ir[Lo.I_tl + c], P.t_min) : 0.0;
                 ir[Lo.I_tu + c] = on ? fmax(ir[Lo.I_tu + c], P.t_min) : 0.0;
+                if constexpr (SOFT) {
+                    const bool sf = d[Lo.D_sm + c] != 0.0;
+                    if (!sf) {
+                        ir[Lo.I_sl + c] = 0.0;
+                        ir[Lo.I_su + c] = 0.0;
+                    }
+                    ir[Lo.I_lsl + c] = sf ? fmax(ir[Lo.I_lsl + c], P.lam_min) : 0.0;
+                    ir[Lo.I_lsu + c] = sf ? fmax(ir[Lo.I_lsu + c], P.lam_min) : 0.0;
+                    ir[Lo.I_tsl + c] = sf ? fmax(ir[Lo.I_tsl + c], P.t_min) : 0.0;
+                    ir[Lo.I_tsu + c] = sf ? fmax(ir[Lo.I_tsu + c], P.t_min) : 0.0;
+                }
                 continue;
             }
             double gz = 0.0;
@@ -1574,15 +1585,22 @@ struct Blk {
             ir[Lo.I_tl + c] = on ? (warm == 1 ? fmax(gz - lo, 1.0) : fmax(-lo, 1.0)) : 0.0;
             ir[Lo.I_tu + c] = on ? (warm == 1 ? fmax(hi - gz, 1.0) : fmax(hi, 1.0)) : 0.0;
             if constexpr (SOFT) {
-                // slacks s = 0 (cold start only), bound rows t_s = max(s - ls,
-                // 1), lam_s = 1; slots without slacks hold zeros
+                // slacks s = 0, or (primal guess) the guess: the soft rows' t =
+                // max(G z + s^l - lo, 1) and max(hi - G z + s^u, 1), the bound rows
+                // t_s = max(s - ls, 1), lam_s = 1; slots without slacks hold zeros
                 const bool sf = d[Lo.D_sm + c] != 0.0;
-                ir[Lo.I_sl + c] = 0.0;
-                ir[Lo.I_su + c] = 0.0;
+                const double sl0 = (sf && warm == 1) ? ir[Lo.I_sl + c] : 0.0;
+                const double su0 = (sf && warm == 1) ? ir[Lo.I_su + c] : 0.0;
+                if (sf && warm == 1) {
+                    ir[Lo.I_tl + c] = fmax(gz + sl0 - lo, 1.0);
+                    ir[Lo.I_tu + c] = fmax(hi - gz + su0, 1.0);
+                }
+                ir[Lo.I_sl + c] = sl0;
+                ir[Lo.I_su + c] = su0;
                 ir[Lo.I_lsl + c] = sf ? 1.0 : 0.0;
                 ir[Lo.I_lsu + c] = sf ? 1.0 : 0.0;
-                ir[Lo.I_tsl + c] = sf ? fmax(-d[Lo.D_lls + c], 1.0) : 0.0;
-                ir[Lo.I_tsu + c] = sf ? fmax(-d[Lo.D_lus + c], 1.0) : 0.0;
+                ir[Lo.I_tsl + c] = sf ? fmax(sl0 - d[Lo.D_lls + c], 1.0) : 0.0;
+                ir[Lo.I_tsu + c] = sf ? fmax(su0 - d[Lo.D_lus + c], 1.0) : 0.0;
             }
         }
         __threadfence_block();

@@ -395,6 +395,13 @@ def receding_step(qp: OcpQp, sol: dict):
              "pi": np.concatenate([pi[1:], pi[-1:]]).ravel()}
     for k in ("lam_l", "lam_u", "t_l", "t_u"):
         guess[k] = np.maximum(np.asarray(sol[k], dtype=np.float64), 1.0)
+    # slack blocks (soft constraints): kept in place like the row blocks
+    for k in ("s_l", "s_u"):
+        if k in sol:
+            guess[k] = np.asarray(sol[k], dtype=np.float64).copy()
+    for k in ("lam_sl", "lam_su", "t_sl", "t_su"):
+        if k in sol:
+            guess[k] = np.maximum(np.asarray(sol[k], dtype=np.float64), 1.0)
     return nxt, guess
 
 

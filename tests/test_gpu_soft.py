@@ -217,8 +217,66 @@ def test_soft_edge_cases_and_mixed_batch():
 
 def test_soft_batch_rejects_other_modes():
     qp = W.mass_spring_chain8_soft(0)
-    for kw in (dict(mode=B.MODE_MIXED), dict(mode=B.MODE_ABS), dict(mode=B.MODE_ROBUST), dict(warm_start=1),
+    for kw in (dict(mode=B.MODE_MIXED), dict(mode=B.MODE_ABS), dict(mode=B.MODE_ROBUST), dict(mode=B.MODE_BALANCE),
                dict(cond_N=5)):
         mode = kw.pop("mode", B.MODE_F64)
         with pytest.raises(B.OqpError):
             B.Batch([qp], B.default_arg(mode, **kw))
+
+
+# ---------------------------------------------------------------------------
+# warm start with slacks (Section 4.2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("wmax", [24, 0])
+def test_soft_initial_point_parity(wmax, wave_bound):
+    """iter_max = 0: the cold start, a primal guess (slacks included) and a
+    primal-dual guess equal the oracle's initial points, one-wave (24) and
+    block (0) kernels."""
+    wave_bound.oqp_set_wave_max(wmax)
+    qps, guesses = [], []
+    for seed in range(8):
+        qp, rng = soft_tiny(500 + seed, nx_range=(1, 5), nu_range=(1, 3), ng_max=2)
+        g = random_interior_iterate_soft(qp, rng, scale=0.7)
+        if g["lam_sl"].size:
+            g["lam_sl"][0] = 0.0   # below the clamps
+            g["t_su"][-1] = -0.5
+        qps.append(qp)
+        guesses.append(g)
+    say(f"soft warm start initial point parity, wave bound {wmax}")
+    for warm in (0, 1, 2):
+        b = B.Batch(qps, B.default_arg(iter_max=0, warm_start=warm)).load()
+        for i in range(len(qps)):
+            if warm:
+                b.set_iterate(i, guesses[i])
+        b.solve().fetch().sync()
+        for i, q in enumerate(qps):
+            ref = O.solve(q, O.Arg.with_tol(1e-8, iter_max=0, warm_start=warm), guess=guesses[i] if warm else None)
+            got = b.solution(i)
+            for k in ALL:
+                assert rel(got[k], ref.sol[k]) <= 1e-14, (warm, i, k, rel(got[k], ref.sol[k]))
+
+
+def test_soft_receding_horizon_warm_solves_follow_the_oracle():
+    """The next receding-horizon problem of each solved soft 8-mass instance
+    (x_0 <- x_1), warm-started from the shifted solution with its slacks:
+    the oracle's warm-started iterations, the KKT tolerance, fewer
+    iterations than cold starts."""
+    qps = [W.mass_spring_chain8_soft(i) for i in range(64)] + [W.mass_spring_chain8_soft(222)]
+    say("soft receding horizon, warm (primal-dual guess) vs oracle")
+    first = B.solve(qps, B.default_arg())
+    assert all(r.status == B.SUCCESS for r in first)
+    nxt, guesses = zip(*[W.receding_step(q, r.sol) for q, r in zip(qps, first)])
+    b = B.Batch(list(nxt), B.default_arg(warm_start=2)).load()
+    for i, g in enumerate(guesses):
+        b.set_iterate(i, g)
+    b.solve().fetch().sync()
+    warm = b.results()
+    cold = B.solve(list(nxt), B.default_arg())
+    assert sum(r.iters for r in warm) < sum(r.iters for r in cold)
+    for i in list(range(0, 64, 9)) + [64]:
+        ref = O.solve(nxt[i], O.Arg.with_tol(1e-8, warm_start=2), guess=guesses[i])
+        assert warm[i].status == ref.status == O.SUCCESS, i
+        assert abs(warm[i].iters - ref.iters) <= 1, (i, warm[i].iters, ref.iters)
+        assert O.kkt_res(nxt[i], warm[i].sol) <= 1e-8 * 1.01, i
+        assert rel(primal(warm[i].sol), primal(ref.sol)) <= 1e-6, i

@@ -1,6 +1,6 @@
 """Host side of soft constraints in the C-ABI (no GPU): slack counts in the
 dims, the soft setters and getters with their validation, the batch sizing
-rules of a batch with slacks (FP64 mode, cold start, no condensing; the
+rules of a batch with slacks (FP64 mode, no condensing, warm starts allowed; the
 soft records larger than the hard ones) and the packer's refusal."""
 import ctypes as ct
 
@@ -79,9 +79,10 @@ def test_soft_batch_sizing_rules():
     rc, _, ds = _bytes([soft], B.default_arg())
     assert rc == B.OK and ds > dh                  # slack blocks in every record
     for arg in (B.default_arg(B.MODE_MIXED), B.default_arg(B.MODE_ABS), B.default_arg(B.MODE_ROBUST),
-                B.default_arg(warm_start=1), B.default_arg(cond_N=5)):
+                B.default_arg(B.MODE_BALANCE), B.default_arg(cond_N=5)):
         assert _bytes([soft], arg)[0] == B.EINVAL
         assert _bytes([hard, soft], arg)[0] == B.EINVAL   # one soft instance makes the batch soft
+    assert _bytes([soft], B.default_arg(warm_start=2))[0] == B.OK   # warm starts take slack guesses
     # a hard QP in a soft batch takes the soft records too
     rc, _, dm = _bytes([hard, soft], B.default_arg())
     assert rc == B.OK and dm >= 2 * ds - 4096
