@@ -15,7 +15,8 @@ Further legs on the same line (context, not the headline):
   * balance: the same batch with checked Cholesky factors and the QR-based
     factorization as fallback (mode balance);
   * warm: the next receding-horizon problem of every solved instance, cold
-    and warm-started from the shifted solution;
+    and warm-started from the shifted solution (warm_soft: the same with soft
+    position boxes, slacks in the guess);
   * soft: the same batch with soft position boxes (every instance
     solvable), the same with and without slacks on the block kernel (the
     cost of the slack elimination), and the uneven batch with its first x0
@@ -599,6 +600,9 @@ def main():
     if args.warm_steps > 0:
         log("bench: receding-horizon warm-start leg")
         line["warm"] = leg_warm(B, W, torch, np, qps, args.warm_steps)
+        log("bench: receding-horizon leg with soft position boxes")
+        line["warm_soft"] = leg_warm(B, W, torch, np, [W.mass_spring_chain8_soft(i) for i in range(len(qps))],
+                                     args.warm_steps)
     log("bench: single-instance latency (4 masses, N = 10)")
     line["single"] = leg_single(B, W, torch, np, 20)
     if args.soft_steps > 0:
