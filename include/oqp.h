@@ -243,7 +243,9 @@ int oqp_batch_get_sol(const oqp_batch* batch, int i, double* u, double* x, doubl
  * guess includes the slack blocks (oqp_batch_set_soft_iterate, or the last
  * solution): warm_start = 1 keeps u, x, s^l, s^u and sets the rest by the
  * cold-start rule at that point, 2 keeps every block, clamped below;
- * the server and oqp_pack take no slacks.  The duality measure and
+ * packed requests with slacks take the soft builds too (a kernel group of
+ * their own in the server, which must run in the FP64 mode).  The duality
+ * measure and
  * oqp_stat.res count the slack rows: r_g includes the slack stationarity
  * rows, r_d the slack bounds, lam .* t their complementarity.
  *
@@ -341,14 +343,16 @@ int oqp_batch_get_step(const oqp_batch* batch, int i, double* du, double* dx, do
 /* ---- packed requests ------------------------------------------------------ */
 /* A QP packed once into a relocatable blob in the device record layout of the
  * kernel variant that covers its stage sizes (header, per-stage sizes,
- * constraint slot map, stage records).  The blob is what a serving client
- * hands to oqp_server_submit.  OQP_EINVAL if no variant covers the QP. */
+ * constraint slot map, slack slot map, stage records; the soft layout when
+ * the QP has slacks).  The blob is what a serving client hands to
+ * oqp_server_submit.  OQP_EINVAL if no variant covers the QP. */
 int oqp_pack_bytes(const oqp_qp* qp, size_t* bytes);
 /* Pack into mem (64-byte aligned, at least oqp_pack_bytes).  Keep the blob in
  * page-locked memory for asynchronous uploads. */
 int oqp_pack(const oqp_qp* qp, void* mem, size_t bytes);
 /* Device bytes a packed request occupies while admitted (data, iterate and
- * workspace records: its HBM footprint) and its kernel variant. */
+ * workspace records: its HBM footprint) and its kernel group (plus the
+ * number of kernel groups when the request has slacks). */
 int oqp_pack_footprint(const void* packed, size_t* dev_bytes, int* variant);
 
 /* ---- continuous-batching server (device-resident IPM state) --------------- */
@@ -407,6 +411,10 @@ int oqp_server_poll(const oqp_server* server, uint64_t ticket, oqp_stat* stat);
 int oqp_server_latency(const oqp_server* server, uint64_t ticket, double* seconds);
 /* Solution of a finished request (layout as oqp_batch_get_sol); copies the
  * padded iterate from the device on streams[0] and waits for that copy. */
+/* Slack blocks of a finished request with slacks (user layout as for
+ * oqp_batch_get_soft_sol); a request without slacks writes nothing. */
+int oqp_server_get_soft_sol(oqp_server* server, uint64_t ticket, double* s_l, double* s_u, double* lam_sl,
+                            double* lam_su, double* t_sl, double* t_su);
 int oqp_server_get_sol(oqp_server* server, uint64_t ticket, double* u, double* x, double* pi, double* lam_l,
                        double* lam_u, double* t_l, double* t_u);
 /* Free a finished request's device block and slot; the ticket becomes invalid. */

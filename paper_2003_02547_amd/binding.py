@@ -81,6 +81,7 @@ def lib():
         "oqp_batch_set_soft_iterate": (ct.c_int, [_V, ct.c_int, _P, _P, _P, _P, _P, _P]),
         "oqp_batch_get_soft_step": (ct.c_int, [_V, ct.c_int, _P, _P, _P, _P, _P, _P]),
         "oqp_batch_nsoft": (ct.c_int, [_V, ct.c_int]),
+        "oqp_server_get_soft_sol": (ct.c_int, [_V, ct.c_uint64, _P, _P, _P, _P, _P, _P]),
         "oqp_qp_bytes": (ct.c_size_t, [_V]),
         "oqp_qp_init": (ct.c_int, [_V, _V, ct.c_size_t, ct.POINTER(_V)]),
         "oqp_qp_set_dyn": (ct.c_int, [_V, ct.c_int, _P, ct.c_int, _P, ct.c_int, _P]),
@@ -608,9 +609,16 @@ class Server:
         return v.value
 
     def solution(self, ticket) -> dict:
-        v, sz = _sol_buffers(self._tickets[ticket].qp)
+        qp = self._tickets[ticket].qp
+        v, sz = _sol_buffers(qp)
         _check(lib().oqp_server_get_sol(self.h, ticket, *[_p(v[k]) for k in _KEYS]))
-        return {k: v[k][:sz[k]].copy() for k in _KEYS}
+        out = {k: v[k][:sz[k]].copy() for k in _KEYS}
+        if _has_soft(qp):
+            ns = int(sum(len(j) for j in qp.idxs))
+            sv = {k: np.zeros(max(ns, 1)) for k in SOFT_KEYS}
+            _check(lib().oqp_server_get_soft_sol(self.h, ticket, *[_p(sv[k]) for k in SOFT_KEYS]))
+            out.update({k: sv[k][:ns].copy() for k in SOFT_KEYS})
+        return out
 
     def result(self, ticket) -> Result:
         st = self.poll(ticket)
@@ -679,4 +687,5 @@ EXPORTED = [
     "oqp_pcond_dims_bytes", "oqp_pcond_dims", "oqp_batch_fetch_cond", "oqp_batch_get_cond_qp",
     "oqp_batch_set_streams", "oqp_batch_release", "oqp_dims_set_soft", "oqp_qp_set_soft", "oqp_qp_get_soft",
     "oqp_batch_get_soft_sol", "oqp_batch_set_soft_iterate", "oqp_batch_get_soft_step", "oqp_batch_nsoft",
+    "oqp_server_get_soft_sol",
 ] + ["oqp_sol_get_" + g for g in SOL_FIELDS]

@@ -1541,25 +1541,29 @@ extern "C" int oqp_batch_set_iterate(oqp_batch* b, int i, const double* u, const
     return OQP_OK;
 }
 
-// Slack blocks of instance i between its iterate records in `region` and
-// the user layout (stage by stage in idxs order).
-static void soft_user_copy(const oqp_batch* b, int i, double* region, bool to_user, double* const vals[6])
+// Slack blocks between N+1 iterate records (soft layout L) at rec and the
+// user layout (stage by stage in idxs order); soft: ns per stage (N+1
+// entries), then the device slot of every slack.
+void soft_iterate_copy(const int* soft, int N, const Layout& L, double* rec, bool to_user, double* const vals[6])
 {
-    const Inst& in = b->inst[i];
-    const Layout L = orig_layout(in);
-    const int* nsv = b->soft_pool + in.soft_off;
-    const int* cs = nsv + in.oN + 1;
+    const int* cs = soft + N + 1;
     const int offs[6] = {L.I_sl, L.I_su, L.I_lsl, L.I_lsu, L.I_tsl, L.I_tsu};
     int o = 0;
-    for (int n = 0; n <= in.oN; ++n) {
-        double* r = region + in.oiter + (int64_t)n * L.IREC;
-        for (int j = 0; j < nsv[n]; ++j, ++o)
+    for (int n = 0; n <= N; ++n) {
+        double* r = rec + (int64_t)n * L.IREC;
+        for (int j = 0; j < soft[n]; ++j, ++o)
             for (int f = 0; f < 6; ++f) {
                 if (!vals[f]) continue;
                 if (to_user) vals[f][o] = r[offs[f] + cs[o]];
                 else r[offs[f] + cs[o]] = vals[f][o];
             }
     }
+}
+
+static void soft_user_copy(const oqp_batch* b, int i, double* region, bool to_user, double* const vals[6])
+{
+    const Inst& in = b->inst[i];
+    soft_iterate_copy(b->soft_pool + in.soft_off, in.oN, orig_layout(in), region + in.oiter, to_user, vals);
 }
 
 extern "C" int oqp_batch_get_soft_sol(const oqp_batch* b, int i, double* s_l, double* s_u, double* lam_sl,

@@ -76,5 +76,6 @@ oqp::KParams make_params(const oqp_arg& a, int mode, double tau);
 // sslots (may be NULL): device slot of each slack, stage by stage in idxs order
 int pack_records(const oqp_qp* q, const oqp::Layout& L, double* dst, int* slots, int* sslots = nullptr);
 bool dims_soft(const oqp_dims* d);
+void soft_iterate_copy(const int* soft, int N, const oqp::Layout& L, double* rec, bool to_user, double* const vals[6]);
 void iterate_user_copy(const int* dims5, int N, const int* slots, const oqp::Layout& L, double* rec, bool to_user,
                        double* u, double* x, double* pi, double* ll, double* lu, double* tl, double* tu);

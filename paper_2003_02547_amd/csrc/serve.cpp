@@ -40,10 +40,12 @@ struct PackHdr {
     int32_t variant;  // kernel group
     int32_t N;
     int32_t nc;
-    int32_t nx, nu, ng, pad;  // padded stage sizes of the records
+    int32_t nx, nu, ng, soft;  // padded stage sizes of the records; soft layout
     int64_t data_doubles, iter_doubles, work_doubles;
     int64_t dims_off, slots_off, data_off;
     int64_t total;
+    int64_t soft_off;  // soft layout: ns per stage, then the device slot of each slack
+    int32_t nsoft, pad;
 };
 
 size_t dev_footprint(const PackHdr* h)
@@ -58,7 +60,8 @@ int read_hdr(const void* packed, const PackHdr** out)
     if ((uintptr_t)packed % 8) return fail(OQP_EINVAL, "packed request not 8-byte aligned");
     const PackHdr* h = (const PackHdr*)packed;
     if (h->magic != kPackMagic) return fail(OQP_EINVAL, "not a packed request (bad magic)");
-    if (h->variant < 0 || h->variant >= group_count()) return fail(OQP_EINVAL, "packed request: bad kernel group");
+    // kernel groups: one per kernel choice, and again for the soft builds
+    if (h->variant < 0 || h->variant >= 2 * group_count()) return fail(OQP_EINVAL, "packed request: bad kernel group");
     *out = h;
     return OQP_OK;
 }
@@ -248,7 +251,7 @@ int launch_group(oqp_server* s, int v, int gi, int k)
         d.iter = (int64_t)((q.dev_off + db) / sizeof(double));
         d.work = (int64_t)((q.dev_off + db + ib) / sizeof(double));
         d.N = h->N;
-        d.nc = h->nc;
+        d.nc = h->nc + h->nsoft;  // one-sided rows / 2: constraint rows and slack bounds
         d.index = cnt;
         d.pad = 0;
         d.nx = h->nx;
@@ -272,13 +275,15 @@ int launch_group(oqp_server* s, int v, int gi, int k)
     g.next = -1;
     hipError_t e = hipMemcpyAsync(g.ddesc, g.hdesc, sizeof(InstDesc) * cnt, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "server: descriptor upload: %s", hipGetErrorString(e));
-    const int km = kernel_build(s->arg.mode);
+    // groups at and above group_count() hold requests with slacks
+    const int kg = v % group_count();
+    const int km = v >= group_count() ? oqp::KM_SOFT : kernel_build(s->arg.mode);
     oqp::KParams P = make_params(s->arg, oqp::KMODE_SOLVE, 0.0);
-    if (group_launch(v, km, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
+    if (group_launch(kg, km, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
         return fail(OQP_EDEVICE, "server: kernel launch failed for group %d", v);
     if (km == oqp::KM_MIXED) {
         P.mode = oqp::KMODE_FALLBACK;
-        if (group_launch(v, oqp::KM_F64, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
+        if (group_launch(kg, oqp::KM_F64, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
             return fail(OQP_EDEVICE, "server: fallback launch failed for group %d", v);
     }
     e = hipMemcpyAsync(g.hstat, g.dstat, sizeof(DevStat) * cnt, hipMemcpyDeviceToHost, st);
@@ -302,12 +307,18 @@ int launch_group(oqp_server* s, int v, int gi, int k)
 static void pack_sizes(const oqp_qp* q, const KSel& ks, PackHdr* h)
 {
     const oqp_dims* d = q->dims;
-    const Layout L = oqp::make_layout(ks.nx, ks.nu, ks.ng);
-    int nc = 0;
-    for (int n = 0; n <= d->N; ++n) nc += d->nbu[n] + d->nbx[n] + d->ng[n];
+    const bool soft = dims_soft(d);
+    const Layout L = oqp::make_layout(ks.nx, ks.nu, ks.ng, soft);
+    int nc = 0, ns = 0;
+    for (int n = 0; n <= d->N; ++n) {
+        nc += d->nbu[n] + d->nbx[n] + d->ng[n];
+        ns += d->ns[n];
+    }
     std::memset(h, 0, sizeof(*h));
     h->magic = kPackMagic;
-    h->variant = ks.group;
+    h->variant = ks.group + (soft ? group_count() : 0);
+    h->soft = soft ? 1 : 0;
+    h->nsoft = ns;
     h->N = d->N;
     h->nc = nc;
     h->nx = ks.nx;
@@ -321,6 +332,8 @@ static void pack_sizes(const oqp_qp* q, const KSel& ks, PackHdr* h)
     o = align_up(o + sizeof(int) * 5 * (d->N + 1), 64);
     h->slots_off = (int64_t)o;
     o = align_up(o + sizeof(int) * (nc + 1), 64);
+    h->soft_off = (int64_t)o;
+    o = align_up(o + sizeof(int) * (soft ? d->N + 1 + ns : 1), 64);
     h->data_off = (int64_t)o;
     o = align_up(o + sizeof(double) * h->data_doubles, 64);
     h->total = (int64_t)o;
@@ -329,7 +342,6 @@ static void pack_sizes(const oqp_qp* q, const KSel& ks, PackHdr* h)
 extern "C" int oqp_pack_bytes(const oqp_qp* qp, size_t* bytes)
 {
     if (!qp || !bytes) return fail(OQP_EINVAL, "oqp_pack_bytes: NULL argument");
-    if (dims_soft(qp->dims)) return fail(OQP_EINVAL, "oqp_pack_bytes: soft constraints are solved in batches only");
     KSel ks;
     if (select_kernel(qp->dims, &ks)) return fail(OQP_EINVAL, "oqp_pack_bytes: no kernel covers the stage sizes");
     PackHdr h;
@@ -342,7 +354,6 @@ extern "C" int oqp_pack(const oqp_qp* qp, void* mem, size_t bytes)
 {
     if (!qp || !mem) return fail(OQP_EINVAL, "oqp_pack: NULL argument");
     if ((uintptr_t)mem % 64) return fail(OQP_EINVAL, "oqp_pack: memory not 64-byte aligned");
-    if (dims_soft(qp->dims)) return fail(OQP_EINVAL, "oqp_pack: soft constraints are solved in batches only");
     KSel ks;
     if (select_kernel(qp->dims, &ks)) return fail(OQP_EINVAL, "oqp_pack: no kernel covers the stage sizes");
     PackHdr h;
@@ -360,7 +371,11 @@ extern "C" int oqp_pack(const oqp_qp* qp, void* mem, size_t bytes)
         dims5[3 * (d->N + 1) + n] = d->nbx[n];
         dims5[4 * (d->N + 1) + n] = d->ng[n];
     }
-    return pack_records(qp, oqp::make_layout(h.nx, h.nu, h.ng), (double*)(b + h.data_off), (int*)(b + h.slots_off));
+    int* soft = (int*)(b + h.soft_off);
+    if (h.soft)
+        for (int n = 0; n <= d->N; ++n) soft[n] = d->ns[n];
+    return pack_records(qp, oqp::make_layout(h.nx, h.nu, h.ng, h.soft != 0), (double*)(b + h.data_off),
+                        (int*)(b + h.slots_off), h.soft ? soft + d->N + 1 : nullptr);
 }
 
 extern "C" int oqp_pack_footprint(const void* packed, size_t* dev_bytes, int* variant)
@@ -485,6 +500,8 @@ extern "C" int oqp_server_submit(oqp_server* s, const void* packed, uint64_t* ti
     const PackHdr* h;
     int rc = read_hdr(packed, &h);
     if (rc) return rc;
+    if (h->soft && s->arg.mode != OQP_MODE_F64)
+        return fail(OQP_EINVAL, "oqp_server_submit: requests with slacks need a server in the FP64 mode");
     const size_t need = dev_footprint(h);
     if (need > s->arena_bytes) return fail(OQP_ENOMEM, "oqp_server_submit: request needs %zu device bytes, arena %zu",
                                            need, s->arena_bytes);
@@ -581,7 +598,34 @@ extern "C" int oqp_server_get_sol(oqp_server* s, uint64_t ticket, double* u, dou
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_server_get_sol: %s", hipGetErrorString(e));
     iterate_user_copy((const int*)((const char*)h + h->dims_off), h->N, (const int*)((const char*)h + h->slots_off),
-                      oqp::make_layout(h->nx, h->nu, h->ng), s->staging, true, u, x, pi, lam_l, lam_u, t_l, t_u);
+                      oqp::make_layout(h->nx, h->nu, h->ng, h->soft != 0), s->staging, true, u, x, pi, lam_l, lam_u,
+                      t_l, t_u);
+    return OQP_OK;
+}
+
+// Slack blocks of a finished request (after oqp_server_get_sol, from the
+// same staged iterate); a request without slacks writes nothing.
+extern "C" int oqp_server_get_soft_sol(oqp_server* s, uint64_t ticket, double* s_l, double* s_u, double* lam_sl,
+                                       double* lam_su, double* t_sl, double* t_su)
+{
+    if (!s) return fail(OQP_EINVAL, "oqp_server_get_soft_sol: NULL server");
+    const int slot = ticket_slot(s, ticket);
+    if (slot < 0) return fail(OQP_EINVAL, "oqp_server_get_soft_sol: unknown ticket");
+    Request& r = s->req[slot];
+    if (r.state != RQ_DONE) return fail(OQP_ESTATE, "oqp_server_get_soft_sol: request not finished");
+    const PackHdr* h = r.hdr;
+    if (!h->soft) return OQP_OK;
+    const size_t bytes = sizeof(double) * h->iter_doubles;
+    if (bytes > s->cfg.staging_bytes)
+        return fail(OQP_ENOMEM, "oqp_server_get_soft_sol: iterate %zu bytes > staging %zu", bytes, s->cfg.staging_bytes);
+    const size_t db = align_up(sizeof(double) * h->data_doubles, 256);
+    hipStream_t st = s->streams[0];
+    hipError_t e = hipMemcpyAsync(s->staging, s->arena + r.dev_off + db, bytes, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(OQP_EDEVICE, "oqp_server_get_soft_sol: %s", hipGetErrorString(e));
+    double* const v[6] = {s_l, s_u, lam_sl, lam_su, t_sl, t_su};
+    soft_iterate_copy((const int*)((const char*)h + h->soft_off), h->N, oqp::make_layout(h->nx, h->nu, h->ng, true),
+                      s->staging, true, v);
     return OQP_OK;
 }
 

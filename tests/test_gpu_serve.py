@@ -187,3 +187,42 @@ def test_server_errors():
             srv.poll(t)  # stale ticket
     finally:
         srv.close()
+
+
+def test_soft_requests_served_in_mix_equal_alone():
+    """Requests with slacks (soft constraints, Section 2.2) take a kernel
+    group of their own and the soft builds; served among requests without
+    slacks, each equals its solve alone in a batch of one, slack blocks
+    included, and reaches the oracle's KKT tolerance."""
+    qps = [W.random_uneven_soft(i) for i in range(8)] + [W.mass_spring_chain8_soft(i) for i in (0, 222)]
+    qps += mixed_pool()[10:18]
+    nsoft = 10
+    arg = B.default_arg()
+    packed = [B.Packed(q, pinned=True) for q in qps]
+    say(f"serve mix with slacks: {len(qps)} requests, {nsoft} with slacks")
+    srv = B.Server(arg, dev_bytes=512 << 20, nstreams=4, max_launch=8)
+    try:
+        order = list(np.random.default_rng(9).permutation(len(qps)))
+        tickets = serve_all(srv, packed, order, spacing_s=0.0005)
+        assert srv.stats()["completed"] == len(qps)
+        for i, t in tickets.items():
+            st = srv.poll(t)
+            got = srv.solution(t)
+            alone = B.solve([qps[i]], arg)[0]
+            assert st.status == alone.status and st.iters == alone.iters, (i, st.status, alone.status)
+            for k in alone.sol:
+                assert np.array_equal(got[k], alone.sol[k]), (i, k)
+            if i < nsoft:
+                assert st.status == B.SUCCESS and "s_l" in got, i
+                assert O.kkt_res(qps[i], got) <= 1e-8 * 1.01, i
+        for t in tickets.values():
+            srv.release(t)
+    finally:
+        srv.close()
+    # requests with slacks need a server in the FP64 mode
+    mixed = B.Server(B.default_arg(B.MODE_MIXED), dev_bytes=64 << 20, nstreams=2)
+    try:
+        with pytest.raises(B.OqpError):
+            mixed.submit(packed[0])
+    finally:
+        mixed.close()

@@ -1,7 +1,7 @@
 """Host side of soft constraints in the C-ABI (no GPU): slack counts in the
 dims, the soft setters and getters with their validation, the batch sizing
 rules of a batch with slacks (FP64 mode, no condensing, warm starts allowed; the
-soft records larger than the hard ones) and the packer's refusal."""
+soft records larger than the hard ones) and packed requests with slacks."""
 import ctypes as ct
 
 import numpy as np
@@ -88,10 +88,17 @@ def test_soft_batch_sizing_rules():
     assert rc == B.OK and dm >= 2 * ds - 4096
 
 
-def test_packer_refuses_slacks():
-    q = B.Qp(W.mass_spring_chain8_soft(1))
-    size = ct.c_size_t()
-    assert B.lib().oqp_pack_bytes(q.h, ct.byref(size)) == B.EINVAL
+def test_packed_requests_with_slacks():
+    """A packed request with slacks takes the soft layout (a larger
+    footprint) and a kernel group of its own, offset by the number of
+    groups; without slacks it is what it was."""
+    L = B.lib()
+    hard, soft = B.Packed(W.mass_spring_chain8(1)), B.Packed(W.mass_spring_chain8_soft(1))
+    ngroups = L.oqp_variant_count() + 6
+    assert hard.variant < ngroups and soft.variant == hard.variant + ngroups
+    assert soft.footprint > hard.footprint and soft.nbytes > hard.nbytes
+    none = B.Packed(W.soften(W.mass_spring_chain8(1), lambda n, q: [], 1.0, 1.0, 1.0, 1.0))
+    assert none.variant == hard.variant and none.footprint == hard.footprint
 
 
 def test_soft_workloads():
