@@ -405,18 +405,22 @@ def leg_large(B, W, torch, np, perfmodel, count, steps):
 def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_seconds, per_req_seconds, log):
     """Continuous-batching server, native real-time replay of Poisson
     arrivals over a pool of pre-packed uneven instances (page-locked host
-    memory; each request's data is uploaded on admission)."""
+    memory; each request's data is uploaded on admission); also the same
+    pool with first x0 draws and soft state boxes."""
     pool = [W.random_uneven(100000 + i) for i in range(pool_n)]
     packed = [B.Packed(q, pinned=True) for q in pool]
-    dev_bytes = int(min(64 << 30, 2 * sum(p.footprint for p in packed) + (1 << 30)))
+    # the same draws with their first x0 and soft state boxes (no redraw)
+    packed_soft = [B.Packed(W.random_uneven_soft(100000 + i), pinned=True) for i in range(pool_n)]
+    dev_bytes = int(min(64 << 30, 2 * sum(p.footprint for p in packed_soft) + (1 << 30)))
     tol = dict(tol_stat=KKT_OK, tol_eq=KKT_OK, tol_ineq=KKT_OK, tol_comp=KKT_OK)
 
-    def run(mode, max_launch, rate, seconds, seed):
+    def run(mode, max_launch, rate, seconds, seed, pk=None):
+        pk = packed if pk is None else pk
         srv = B.Server(B.default_arg(mode, **tol), dev_bytes=dev_bytes, nstreams=5, max_launch=max_launch,
                        max_requests=4096, max_groups=1024)
         try:
             times, idx = W.serving_stream(rate, seconds, pool_n, seed=seed)
-            lat, stats, wall = srv.replay([packed[i] for i in idx], times, timeout=120.0)
+            lat, stats, wall = srv.replay([pk[i] for i in idx], times, timeout=120.0)
             c = srv.stats()
         finally:
             srv.close()
@@ -434,6 +438,8 @@ def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_secon
     for name, mode, ml in (("f64", B.MODE_F64, 256), ("mixed", B.MODE_MIXED, 256)):
         log(f"bench: serve {name} at {rate:.0f} req/s for {sus_seconds:.0f} s")
         out[name] = run(mode, ml, rate, sus_seconds, 3)
+    log(f"bench: serve f64 with soft state boxes (first x0 draws) at {rate:.0f} req/s for {sus_seconds:.0f} s")
+    out["f64_soft"] = run(B.MODE_F64, 256, rate, sus_seconds, 3, packed_soft)
     # plain per-request FP64 path (one launch per request): same offered rate
     # over a shorter window, since it saturates far below that rate
     log(f"bench: serve f64_per_request at {rate:.0f} req/s for {per_req_seconds:.2f} s")
