@@ -92,20 +92,22 @@ struct Ipm {
     static_assert(NV < WAVE, "reflector broadcast buffer");
 
     struct Smem {
+        // vectors read with wave-uniform addresses first: their offsets fit
+        // the short offset fields of paired LDS reads
+        alignas(16) double col[2 * WAVE];  // Cholesky column pair (interleaved) / reflector broadcast
+        double z[WAVE];           // z_n or dz_n
+        double t1[WAVE], t2[WAVE];
+        double rb[WAVE];          // r_b of the stage
+        double xn[2][WAVE];       // x_{n+1} / dx_{n+1}, by parity
+        double pin[2][WAVE];      // pi_{n+1}, by parity
+        double pn[2][WAVE];       // p_{n+1}, by parity
+        double e[NCT * WAVE];     // reduced-gradient terms per constraint slot
+        double ws[NCT * WAVE];    // barrier weights per constraint slot
         double M[LDZ * NZP];      // stage matrix / factor (column-major)
         double Lx[2][LDX * NXP];  // L_{n+1} (lower, zero strict upper), by stage parity
         double F[LDX * NZP];      // [B A] of the stage
         double V[LDV * NZP];      // [U; sqrt(w) G]
         double G[LDG * NZP];      // general rows of the stage
-        double z[WAVE];           // z_n or dz_n
-        double rb[WAVE];          // r_b of the stage
-        double t1[WAVE], t2[WAVE];
-        double e[NCT * WAVE];     // reduced-gradient terms per constraint slot
-        double ws[NCT * WAVE];    // barrier weights per constraint slot
-        double xn[2][WAVE];       // x_{n+1} / dx_{n+1}, by parity
-        double pin[2][WAVE];      // pi_{n+1}, by parity
-        double pn[2][WAVE];       // p_{n+1}, by parity
-        double col[WAVE];         // Cholesky column broadcast
         double Lst[LDZ * NZP];    // factor of the last stage, staged for the copy out
     };
 
@@ -418,33 +420,50 @@ struct Ipm {
         }
         bool ok = true;
         // Updates are not masked: lane i only ever needs r[k] for k <= i, and
-        // the entries above the diagonal absorb harmless garbage.
+        // the entries above the diagonal absorb harmless garbage.  Columns are
+        // taken two at a time: column j + 1 is factored as soon as column j
+        // has updated it, and the rest of the trailing block receives both
+        // columns' updates in column order (the same operations as one column
+        // at a time), with one LDS exchange of the pair.
 #pragma unroll
-        for (int j = 0; j < NZ; ++j) {
-            const double piv = MIXED ? bcast(dd, j) : bcast(r[j], j);
+        for (int j = 0; j < NZ; j += 2) {
+            double piv = MIXED ? bcast(dd, j) : bcast(r[j], j);
             ok = ok && (piv > 0.0);
-            const double inv = rsqrt_nr(piv);
-            const double lij = MIXED ? rnd(r[j] * inv) : r[j] * inv;
+            double inv = rsqrt_nr(piv);
+            const double l0 = MIXED ? rnd(r[j] * inv) : r[j] * inv;
             if (lane == j) {
                 dinv = inv;
                 r[j] = piv * inv;  // sqrt(pivot)
             } else if (lane > j) {
-                r[j] = lij;
-                if constexpr (MIXED) dd -= lij * lij;
+                r[j] = l0;
+                if constexpr (MIXED) dd -= l0 * l0;
             }
-            if (j + 1 < NZ) {
-                s.col[lane] = lij;
-                // the entries needed by the next two columns go through the
-                // scalar unit (critical path), the rest through LDS
-                const double l1 = bcast(lij, j + 1);
-                r[j + 1] = (double)((TS)r[j + 1] - (TS)lij * (TS)l1);
-                if (j + 2 < NZ) {
-                    const double l2 = bcast(lij, j + 2);
-                    r[j + 2] = (double)((TS)r[j + 2] - (TS)lij * (TS)l2);
-                }
+            if (j + 1 == NZ) break;
+            // the entries needed by the next columns go through the scalar
+            // unit (critical path), the rest through LDS
+            r[j + 1] = (double)((TS)r[j + 1] - (TS)l0 * (TS)bcast(l0, j + 1));
+            piv = MIXED ? bcast(dd, j + 1) : bcast(r[j + 1], j + 1);
+            ok = ok && (piv > 0.0);
+            inv = rsqrt_nr(piv);
+            const double l1 = MIXED ? rnd(r[j + 1] * inv) : r[j + 1] * inv;
+            if (lane == j + 1) {
+                dinv = inv;
+                r[j + 1] = piv * inv;
+            } else if (lane > j + 1) {
+                r[j + 1] = l1;
+                if constexpr (MIXED) dd -= l1 * l1;
+            }
+            if (j + 2 < NZ) {
+                s.col[2 * lane] = l0;
+                s.col[2 * lane + 1] = l1;
+                r[j + 2] = (double)((TS)r[j + 2] - (TS)l0 * (TS)bcast(l0, j + 2));
+                r[j + 2] = (double)((TS)r[j + 2] - (TS)l1 * (TS)bcast(l1, j + 2));
                 wsync();
 #pragma unroll
-                for (int k = j + 3; k < NZ; ++k) r[k] = (double)((TS)r[k] - (TS)lij * (TS)s.col[k]);
+                for (int k = j + 3; k < NZ; ++k) {
+                    r[k] = (double)((TS)r[k] - (TS)l0 * (TS)s.col[2 * k]);
+                    r[k] = (double)((TS)r[k] - (TS)l1 * (TS)s.col[2 * k + 1]);
+                }
                 wsync();
             }
         }
