@@ -52,10 +52,13 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the one-wave kernel's sources and compile flags."""
+    from paper_2003_02547_amd import build as _build
     h = hashlib.sha256()
     for f in ("ipm_kernel.h", "dev_common.h", "layout.h"):
         with open(os.path.join(ROOT, "paper_2003_02547_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(_build.FLAGS + _build.ONE_WAVE_FLAGS).encode())
     return h.hexdigest()[:16]
 
 
