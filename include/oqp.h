@@ -68,7 +68,7 @@ extern "C" {
                              Phi + U'U (mode "robust" of Section 4.2), and up to ir_max (default 4)
                              refinement steps on the prediction-centering-correction direction;
                              batch only, for stage blocks covered by a one-wave variant (nx + nu up
-                             to 24 after padding) */
+                             to 32 after padding: nx <= 16 with nu <= 16, or nx <= 24 with nu <= 8) */
 #define OQP_MODE_BALANCE 4 /* FP64, delta formulation (mode "balance" of Section 4.2): Cholesky
                               factors whose accuracy is checked each iteration by the refinement
                               residual of the predictor step; when it exceeds

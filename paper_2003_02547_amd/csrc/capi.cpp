@@ -586,7 +586,7 @@ int pick_variant(const oqp_dims* d)
 // rows).  One-wave variants are used up to a stage block of g_wave_max_nz,
 // larger instances go to the block kernel, padded only to their own maximum
 // stage sizes.
-static int g_wave_max_nz = 24;
+static int g_wave_max_nz = 32;
 static const int kBlockZ[6] = {32, 32, 64, 64, 256, 256};
 static const int kBlockG[6] = {0, 64, 0, 64, 0, 64};
 static constexpr size_t kMaxLds = 160 * 1024;

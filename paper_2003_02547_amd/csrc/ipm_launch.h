@@ -16,7 +16,9 @@
     X(8, 8, 0) \
     X(8, 16, 0) \
     X(16, 4, 0) \
-    X(16, 8, 0)
+    X(16, 8, 0) \
+    X(16, 16, 0) \
+    X(24, 8, 0)
 
 namespace oqp {
 

@@ -1,0 +1,162 @@
+"""GPU parity of the one-wave variants with 32-wide stage blocks, (nx, nu) =
+(16, 16) and (24, 8), against the oracle, in every kernel build: instances
+of these sizes are routed to them by default (wave bound 32).
+
+* Newton step at random interior iterates (FP64, robust and balance
+  builds): every block element by element, 1e-8;
+* full solves (FP64, robust, balance): same status, iterations within one,
+  the oracle's KKT residual of the returned point within 1e-8 and the primal
+  within 1e-6;
+* mixed path: KKT residual within the tolerance (1e-6 by default; at 1e-8
+  also the primal within 1e-6 of the FP64 oracle);
+* soft constraints (every box softened): solves against the oracle's soft
+  IPM;
+* the same batch on the block kernel: the same statuses and iterations within
+  one, solutions within 1e-6.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2003_02547_amd import binding as B  # noqa: E402
+from paper_2003_02547_amd import workloads as W  # noqa: E402
+from dense_ref import random_interior_iterate  # noqa: E402
+
+KEYS = ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")
+SIZES = ((16, 16), (12, 14), (24, 8), (20, 6))
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    B.lib()
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=float), np.asarray(b, dtype=float)
+    if a.size == 0:
+        return 0.0
+    return float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b))))
+
+
+def primal(sol):
+    return np.concatenate([sol["u"], sol["x"], sol.get("s_l", []), sol.get("s_u", [])])
+
+
+def batch(count=3, N=(6, 14)):
+    qps = []
+    for nx, nu in SIZES:
+        for i in range(count):
+            rng = np.random.default_rng(np.random.SeedSequence([321, nx, nu, i]))
+            qps.append(W.random_stable(rng, nx, nu, int(rng.integers(*N))))
+    return qps
+
+
+def expected_variant(qp):
+    nx, nu = max(qp.nx), max(qp.nu)
+    return (16, 16, 0) if nx <= 16 else (24, 8, 0)
+
+
+def check_routing(b, qps):
+    vs = B.variants()
+    for i, q in enumerate(qps):
+        v, dims = b.variant(i)
+        assert v < len(vs) and dims == expected_variant(q), (i, v, dims)
+
+
+@pytest.mark.parametrize("mode", [B.MODE_F64, B.MODE_ROBUST, B.MODE_BALANCE])
+def test_newton_step(mode):
+    qps = batch(2)
+    rng = np.random.default_rng(5)
+    its = [random_interior_iterate(q, rng, scale=0.5) for q in qps]
+    say(f"32-wide variants, Newton step, mode {mode}, vs oracle")
+    b = B.Batch(qps, B.default_arg(mode)).load()
+    check_routing(b, qps)
+    for i, it in enumerate(its):
+        b.set_iterate(i, it)
+    b.newton(0.02).fetch().sync()
+    for i, (q, it) in enumerate(zip(qps, its)):
+        ref = O.newton_step(q, it, 0.02)
+        got = b.step(i)
+        for k in KEYS:
+            assert rel(got[k], ref[k]) <= 1e-8, (i, k, rel(got[k], ref[k]))
+
+
+@pytest.mark.parametrize("mode", [B.MODE_F64, B.MODE_ROBUST, B.MODE_BALANCE])
+def test_solves_follow_the_oracle(mode):
+    qps = batch()
+    say(f"32-wide variants, solves, mode {mode}, vs oracle")
+    b = B.Batch(qps, B.default_arg(mode)).load()
+    check_routing(b, qps)
+    res = b.solve().fetch().sync().results()
+    for i, (q, r) in enumerate(zip(qps, res)):
+        ref = O.solve(q, O.Arg.with_tol(1e-8))
+        assert ref.status == O.SUCCESS, i
+        assert r.status == B.SUCCESS, (i, r.status, r.iters)
+        assert abs(r.iters - ref.iters) <= 1, (i, r.iters, ref.iters)
+        assert O.kkt_res(q, r.sol) <= 1e-8 * 1.01, (i, O.kkt_res(q, r.sol))
+        assert rel(primal(r.sol), primal(ref.sol)) <= 1e-6, (i, rel(primal(r.sol), primal(ref.sol)))
+
+
+def test_mixed_solves():
+    qps = batch()
+    say("32-wide variants, mixed path, vs FP64 oracle")
+    # default tolerance (1e-6): the KKT bar; at 1e-8 (refinement carries the
+    # FP32 factorization to FP64 accuracy) also the primal against the oracle
+    for tol in (1e-6, 1e-8):
+        arg = B.default_arg(B.MODE_MIXED, tol_stat=tol, tol_eq=tol, tol_ineq=tol, tol_comp=tol)
+        b = B.Batch(qps, arg).load()
+        check_routing(b, qps)
+        res = b.solve().fetch().sync().results()
+        for i, (q, r) in enumerate(zip(qps, res)):
+            assert r.status == B.SUCCESS, (tol, i, r.status, r.iters)
+            assert O.kkt_res(q, r.sol) <= tol * 1.01, (tol, i, O.kkt_res(q, r.sol))
+            if tol == 1e-8:
+                ref = O.solve(q, O.Arg.with_tol(1e-8))
+                assert rel(primal(r.sol), primal(ref.sol)) <= 1e-6, (i, rel(primal(r.sol), primal(ref.sol)))
+
+
+def test_soft_solves():
+    qps = []
+    for nx, nu in SIZES:
+        for i in range(2):
+            rng = np.random.default_rng(np.random.SeedSequence([654, nx, nu, i]))
+            q = W.random_stable(rng, nx, nu, int(rng.integers(6, 14)), redraw=False)
+            qps.append(W.soften_random(q, rng, 1.0))
+    say("32-wide variants, soft builds, vs oracle")
+    b = B.Batch(qps, B.default_arg()).load()
+    check_routing(b, qps)
+    res = b.solve().fetch().sync().results()
+    for i, (q, r) in enumerate(zip(qps, res)):
+        ref = O.solve(q)
+        assert ref.status == O.SUCCESS, i
+        assert r.status == B.SUCCESS, (i, r.status, r.iters)
+        assert O.kkt_res(q, r.sol) <= 1e-8 * 1.01, (i, O.kkt_res(q, r.sol))
+        assert rel(primal(r.sol), primal(ref.sol)) <= 1e-6, (i, rel(primal(r.sol), primal(ref.sol)))
+
+
+def test_same_batch_on_the_block_kernel():
+    qps = batch(4)
+    say("32-wide variants vs the block kernel on the same batch")
+    wave = B.solve(qps)
+    old = B.set_wave_max(0)
+    try:
+        blk = B.solve(qps)
+    finally:
+        B.set_wave_max(old)
+    for i, (a, c) in enumerate(zip(wave, blk)):
+        assert a.status == c.status == B.SUCCESS, (i, a.status, c.status)
+        assert abs(a.iters - c.iters) <= 1, (i, a.iters, c.iters)
+        assert rel(primal(a.sol), primal(c.sol)) <= 1e-6, i
