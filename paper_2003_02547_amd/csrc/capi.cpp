@@ -586,7 +586,12 @@ int pick_variant(const oqp_dims* d)
 // rows).  One-wave variants are used up to a stage block of g_wave_max_nz,
 // larger instances go to the block kernel, padded only to their own maximum
 // stage sizes.
-static int g_wave_max_nz = 32;
+// 24 by default: the 32-wide variants win on batches of their own size, but
+// in uneven mixes their two extra kernel groups split the launches (uneven
+// 4096 on one stream 482 -> 532 ms, mixed 781 -> 832 ms, serving saturation
+// 7.6k -> 7.0k/s), so they are used when the bound is raised
+// (oqp_set_wave_max, or the autotuner on same-size batches)
+static int g_wave_max_nz = 24;
 static const int kBlockZ[6] = {32, 32, 64, 64, 256, 256};
 static const int kBlockG[6] = {0, 64, 0, 64, 0, 64};
 static constexpr size_t kMaxLds = 160 * 1024;

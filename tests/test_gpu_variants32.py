@@ -1,6 +1,7 @@
 """GPU parity of the one-wave variants with 32-wide stage blocks, (nx, nu) =
 (16, 16) and (24, 8), against the oracle, in every kernel build: instances
-of these sizes are routed to them by default (wave bound 32).
+of these sizes are routed to them once the wave bound is 32 (the default is
+24).
 
 * Newton step at random interior iterates (FP64, robust and balance
   builds): every block element by element, 1e-8;
@@ -42,6 +43,13 @@ def _need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU visible")
     B.lib()
+
+
+@pytest.fixture(autouse=True)
+def _bound32():
+    old = B.set_wave_max(32)
+    yield
+    B.set_wave_max(old)
 
 
 def rel(a, b):
