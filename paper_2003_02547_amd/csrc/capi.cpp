@@ -770,19 +770,41 @@ extern "C" int oqp_set_wave_max(int nz)
 
 extern "C" int oqp_get_wave_max(void) { return g_wave_max_nz; }
 
-// Launch the instances [desc, desc + count) of kernel group g.
+// A block-kernel instance whose LDS block exceeds half of a CU's LDS keeps
+// the CU to itself; the others can share it two by two.
+static constexpr size_t kLdsHalf = kMaxLds / 2;
+
+static bool lds_big(const InstDesc& d)
+{
+    return (size_t)oqp::block_lds_bytes(d.nx, d.nu, d.ng) > kLdsHalf;
+}
+
+// Launch the instances [desc, desc + count) of kernel group g.  A block
+// group's launch takes the LDS size of its largest instance, so a leading
+// run of instances needing more than half a CU's LDS (the batch orders them
+// first) is launched on its own and the rest in a second launch on the same
+// stream, sized so that two of its workgroups share a CU.
 int group_launch(int g, int km, const InstDesc* desc, const InstDesc* hdesc, int count, const double* data,
                  double* iter, double* work, double* step, DevStat* stat, const oqp::KParams& P, void* stream)
 {
     const int nv = oqp::variant_count();
     if (g < nv) return oqp::variant_launch(g, km, desc, count, data, iter, work, step, stat, P, stream);
-    size_t lds = 0;
-    for (int i = 0; i < count; ++i) {
-        const size_t b = (size_t)oqp::block_lds_bytes(hdesc[i].nx, hdesc[i].nu, hdesc[i].ng);
-        if (b > lds) lds = b;
+    int split = 0;
+    while (split < count && lds_big(hdesc[split])) ++split;
+    if (split == count) split = 0;
+    const int parts[3] = {0, split, count};
+    for (int p = split > 0 ? 0 : 1; p < 2; ++p) {
+        const int lo = parts[p], hi = parts[p + 1];
+        size_t lds = 0;
+        for (int i = lo; i < hi; ++i) {
+            const size_t b = (size_t)oqp::block_lds_bytes(hdesc[i].nx, hdesc[i].nu, hdesc[i].ng);
+            if (b > lds) lds = b;
+        }
+        const int rc = oqp::block_launch(kBlockZ[g - nv], kBlockG[g - nv], km, desc + lo, hi - lo, data, iter, work,
+                                         step, stat, P, lds, stream);
+        if (rc) return rc;
     }
-    return oqp::block_launch(kBlockZ[g - nv], kBlockG[g - nv], km, desc, count, data, iter, work, step, stat, P,
-                             lds, stream);
+    return 0;
 }
 
 // relative cost of an instance, for ordering a launch largest first
@@ -1032,9 +1054,17 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
         int k = 0;
         for (int i = 0; i < count; ++i)
             if (b->inst[i].variant == v) order[k++] = i;
+        // block groups: instances needing more than half a CU's LDS first
+        // (group_launch gives them a launch of their own)
+        const bool blk = v >= oqp::variant_count();
         std::stable_sort(order, order + k, [&](int x, int y) {
             const Inst& a = b->inst[x];
             const Inst& c = b->inst[y];
+            if (blk) {
+                const bool ba = (size_t)oqp::block_lds_bytes(a.nx, a.nu, a.ng) > kLdsHalf;
+                const bool bc = (size_t)oqp::block_lds_bytes(c.nx, c.nu, c.ng) > kLdsHalf;
+                if (ba != bc) return ba;
+            }
             return inst_cost(a.N, a.nx, a.nu) > inst_cost(c.N, c.nx, c.nu);
         });
         for (int q = 0; q < k; ++q) {
