@@ -780,17 +780,20 @@ static bool lds_big(const InstDesc& d)
 }
 
 // Launch the instances [desc, desc + count) of kernel group g.  A block
-// group's launch takes the LDS size of its largest instance, so a leading
-// run of instances needing more than half a CU's LDS (the batch orders them
-// first) is launched on its own and the rest in a second launch on the same
-// stream, sized so that two of its workgroups share a CU.
+// group's launch takes the LDS size of its largest instance; with split_lds
+// (a batch, which orders them first) a leading run of instances needing more
+// than half a CU's LDS is launched on its own and the rest in a second launch
+// on the same stream, sized so that two of its workgroups share a CU.  The
+// server keeps one launch: its requests come in arrival order, and a launch
+// of a few large ones would hold up the rest of the stream.
 int group_launch(int g, int km, const InstDesc* desc, const InstDesc* hdesc, int count, const double* data,
-                 double* iter, double* work, double* step, DevStat* stat, const oqp::KParams& P, void* stream)
+                 double* iter, double* work, double* step, DevStat* stat, const oqp::KParams& P, void* stream,
+                 bool split_lds)
 {
     const int nv = oqp::variant_count();
     if (g < nv) return oqp::variant_launch(g, km, desc, count, data, iter, work, step, stat, P, stream);
     int split = 0;
-    while (split < count && lds_big(hdesc[split])) ++split;
+    while (split_lds && split < count && lds_big(hdesc[split])) ++split;
     if (split == count) split = 0;
     const int parts[3] = {0, split, count};
     for (int p = split > 0 ? 0 : 1; p < 2; ++p) {
@@ -1361,7 +1364,7 @@ static int launch_all(oqp_batch* b, const oqp::KParams& P)
             if (b->vcount[v] == 0) continue;
             int rc = group_launch(v, pass == 0 ? km : oqp::KM_F64, b->ddesc + b->vstart[v], b->hdesc + b->vstart[v],
                                   b->vcount[v], b->ddata, b->diter, b->dwork, b->dstep, b->dstat, Pp,
-                                  group_stream(b, v));
+                                  group_stream(b, v), true);
             if (rc) return fail(OQP_EDEVICE, "kernel launch failed for group %d", v);
         }
     }

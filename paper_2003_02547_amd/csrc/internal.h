@@ -58,7 +58,8 @@ int select_kernel(const oqp_dims* d, KSel* out);
 // km: kernel build (oqp::KM_F64, KM_MIXED, KM_ABS, KM_ROBUST, KM_SOFT)
 int group_launch(int g, int km, const oqp::InstDesc* desc, const oqp::InstDesc* hdesc, int count,
                  const double* data, double* iter, double* work, double* step, oqp::DevStat* stat,
-                 const oqp::KParams& P, void* stream);
+                 const oqp::KParams& P, void* stream,
+                 bool split_lds = false);
 double inst_cost(int N, int nx, int nu);
 // kernel build of a solver mode
 int kernel_build(int mode);
