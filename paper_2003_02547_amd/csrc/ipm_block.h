@@ -1782,9 +1782,11 @@ struct Blk {
 // whose whole register file they needed to avoid spilling.
 __host__ __device__ constexpr int block_waves(int zm, int gm) { return (zm >= 64 || (zm == 32 && gm == 0)) ? 2 : 1; }
 
-// ZM > 64 selects the global-memory mode.
-template <int KM, int ZM, int GM>
-__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(block_waves(ZM, GM), block_waves(ZM, GM)))) void ipm_block_kernel(
+// ZM > 64 selects the global-memory mode; WV overrides the register budget
+// (64-wide blocks with general rows at one wave per SIMD, for launches whose
+// LDS keeps a CU to one workgroup anyway: that build spills nothing).
+template <int KM, int ZM, int GM, int WV = block_waves(ZM, GM)>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(WV, WV))) void ipm_block_kernel(
     const InstDesc* __restrict__ desc, int count, const double* __restrict__ data, double* __restrict__ iter,
     double* __restrict__ work, double* __restrict__ step_out, DevStat* __restrict__ stat, KParams P)
 {

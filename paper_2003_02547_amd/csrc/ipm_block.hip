@@ -7,10 +7,21 @@
 
 namespace oqp {
 
+// LDS above half of a CU's 160 KB: one workgroup per CU whatever the
+// register budget
+static constexpr size_t kLdsHalfCU = 80 * 1024;
+
 template <int KM, int ZM, int GM>
 static int launch_block_t(const InstDesc* desc, int count, const double* data, double* iter, double* work,
                           double* step, DevStat* stat, const KParams& P, size_t lds_bytes, hipStream_t stream)
 {
+    if constexpr (ZM == 64 && GM == 64) {
+        if (lds_bytes > kLdsHalfCU) {
+            hipLaunchKernelGGL((ipm_block_kernel<KM, ZM, GM, 1>), dim3(count), dim3(BT), lds_bytes, stream, desc,
+                               count, data, iter, work, step, stat, P);
+            return hipGetLastError() == hipSuccess ? 0 : -1;
+        }
+    }
     hipLaunchKernelGGL((ipm_block_kernel<KM, ZM, GM>), dim3(count), dim3(BT), lds_bytes, stream, desc, count, data,
                        iter, work, step, stat, P);
     return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -10,6 +10,11 @@ int block_launch_soft(int zm, int gm, const InstDesc* desc, int count, const dou
                       double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream)
 {
     hipStream_t s = (hipStream_t)stream;
+    if (zm == 64 && gm == 64 && lds_bytes > 80 * 1024) {  // one workgroup per CU: the build that spills nothing
+        hipLaunchKernelGGL((ipm_block_kernel<KM_SOFT, 64, 64, 1>), dim3(count), dim3(BT), lds_bytes, s, desc, count,
+                           data, iter, work, step, stat, P);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
 #define OQP_BLK_SOFT(Z, G)                                                                                          \
     if (zm == Z && gm == G) {                                                                                       \
         hipLaunchKernelGGL((ipm_block_kernel<KM_SOFT, Z, G>), dim3(count), dim3(BT), lds_bytes, s, desc, count,    \
