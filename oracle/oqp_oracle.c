@@ -61,6 +61,15 @@ typedef struct {
     double alpha_min, gamma, lam_min, t_min, reg_prim, corr_ratio;
     int warm_start; /* 0 cold; 1 primal guess (u, x); 2 primal and dual guess (Section 4.2) */
     int abs_form;   /* 1: absolute formulation (eq:alg:pdipm:abs), exit on the duality measure */
+    /* Iterative refinement of the prediction-centering-correction direction
+     * (Section 3.4; Section 4.2 refines that direction "in case this is not
+     * accurate enough"): up to ir_max corrections, each solving the Newton
+     * system again with the refinement residual K d + r as right-hand side,
+     * until ||K d + r||_inf <= ir_tol * max(1, largest residual norm at the
+     * iterate).  A correction that does not lower the refinement residual is
+     * taken back.  ir_max = 0: no refinement (mode speed). */
+    int ir_max;
+    double ir_tol;
 } orc_arg;
 
 /* An iterate, a step or a residual in the user layout: u (sum nu), x (sum nx),
@@ -872,6 +881,66 @@ static void set_rm(const prob_t *p, const ivec_t *v, const ivec_t *aff, double s
     }
 }
 
+
+/* Refinement residual of eq:alg:itref at iterate v for step d and
+ * right-hand side r (r_g, r_b, r_d in r->y, r->pi, r->ll/lu; r_m in
+ * r->tl/tu):  o = K d + r.  Returns ||o||_inf.  Problems without slacks. */
+static double ir_apply(const prob_t *p, const ivec_t *v, const ivec_t *d, const ivec_t *r, ivec_t *o)
+{
+    kkt_apply(p, d, 1, r->y, r->pi, r->ll, r->lu, o->y, o->pi, o->ll, o->lu);
+    for (int i = 0; i < p->ncon; ++i) {
+        o->tl[i] = v->tl[i] * d->ll[i] + v->ll[i] * d->tl[i] + r->tl[i];
+        o->tu[i] = v->tu[i] * d->lu[i] + v->lu[i] * d->tu[i] + r->tu[i];
+    }
+    double m = max2(inf_norm(o->y, p->nv), inf_norm(o->pi, p->neq));
+    m = max2(m, max2(inf_norm(o->ll, p->ncon), inf_norm(o->lu, p->ncon)));
+    return max2(m, max2(inf_norm(o->tl, p->ncon), inf_norm(o->tu, p->ncon)));
+}
+
+/* d += s * e on every block (problems without slacks) */
+static void step_axpy(const prob_t *p, double s, const ivec_t *e, ivec_t *d)
+{
+    for (int i = 0; i < p->nv; ++i) d->y[i] += s * e->y[i];
+    for (int i = 0; i < p->neq; ++i) d->pi[i] += s * e->pi[i];
+    for (int i = 0; i < p->ncon; ++i) {
+        d->ll[i] += s * e->ll[i];
+        d->lu[i] += s * e->lu[i];
+        d->tl[i] += s * e->tl[i];
+        d->tu[i] += s * e->tu[i];
+    }
+}
+
+/* Iterative refinement (Section 3.4) of the step d solving K d = -r with
+ * the factorization f: each correction e solves K e = -(K d + r) with the
+ * same factors.  Stops when ||K d + r||_inf <= tol, after max_steps
+ * corrections, or when a correction did not lower the residual (that
+ * correction is then taken back).  Returns the corrections kept. */
+static int refine_step(const prob_t *p, const fac_t *f, const ivec_t *v, const ivec_t *r, int max_steps, double tol,
+                       ivec_t *d)
+{
+    ivec_t ri, e;
+    ivec_alloc(p, &ri);
+    ivec_alloc(p, &e);
+    int kept = 0;
+    double prev = HUGE_VAL;
+    for (int it = 0;; ++it) {
+        double nr = ir_apply(p, v, d, r, &ri);
+        if (it > 0 && !(nr < prev)) {
+            step_axpy(p, -1.0, &e, d);
+            --kept;
+            break;
+        }
+        if (nr <= tol || it == max_steps) break;
+        prev = nr;
+        newton_solve(p, f, v, &ri, &e);
+        step_axpy(p, 1.0, &e, d);
+        ++kept;
+    }
+    ivec_free(&ri);
+    ivec_free(&e);
+    return kept;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Public entry points                                                      */
 /* ------------------------------------------------------------------------ */
@@ -936,17 +1005,61 @@ int orc_newton_step(const orc_qp *qp, const orc_vec *it, double tau, double reg,
     return rc ? ORC_NAN : 0;
 }
 
+/* Newton step of orc_newton_step (delta formulation, no slacks) followed by
+ * up to ir_max refinement corrections (Section 3.4) until ||K d + r||_inf <=
+ * ir_tol * max(1, largest residual norm at the iterate); the factorization
+ * takes the regularization reg, the refinement residual the matrix K without
+ * it (Section 4.2: the effect of the regularization can be offset by
+ * refinement).  *kept: the corrections kept. */
+int orc_newton_step_ir(const orc_qp *qp, const orc_vec *it, double tau, double reg, int ir_max, double ir_tol,
+                       orc_vec *step, int *kept)
+{
+    prob_t p;
+    int rc = prob_build(qp, &p);
+    if (rc) return rc;
+    if (p.nsoft > 0 || ir_max < 0) { prob_free(&p); return ORC_EINVAL; }
+    ivec_t v, r, d;
+    ivec_alloc(&p, &v); ivec_alloc(&p, &r); ivec_alloc(&p, &d);
+    ivec_from_user(&p, it, &v);
+    residuals(&p, &v, &r);
+    double norms[4];
+    norms_at(&p, &v, &r, norms);
+    set_rm(&p, &v, NULL, tau, &r);
+    double *wl = (double *)xcalloc((size_t)p.ncon, sizeof(double));
+    double *wu = (double *)xcalloc((size_t)p.ncon, sizeof(double));
+    barrier_weights(&p, &v, wl, wu);
+    fac_t f;
+    memset(&f, 0, sizeof(f));
+    rc = factorize(&p, wl, wu, reg, &f);
+    if (rc == 0) {
+        newton_solve(&p, &f, &v, &r, &d);
+        const double tol = ir_tol * max2(1.0, max2(max2(norms[0], norms[1]), max2(norms[2], norms[3])));
+        int k = refine_step(&p, &f, &v, &r, ir_max, tol, &d);
+        if (kept) *kept = k;
+        ivec_to_user(&p, &d, step);
+    }
+    fac_free(&f);
+    free(wl); free(wu);
+    ivec_free(&v); ivec_free(&r); ivec_free(&d);
+    prob_free(&p);
+    return rc ? ORC_NAN : 0;
+}
+
 /* The IPM.  On return `sol` holds the final iterate; iters, the number of
  * iterations taken; res_norms the four residual inf-norms at the final
  * iterate; mu_out the final duality measure.  The return value is the
- * solver status (>= 0) or a usage error (< 0).  Problems with slacks take
- * the delta formulation from a cold start only. */
-int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, double *res_norms, double *mu_out)
+ * solver status (>= 0) or a usage error (< 0); ir_steps (may be NULL) the
+ * refinement corrections kept in total.  Problems with slacks take the delta
+ * formulation without refinement. */
+int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, double *res_norms, double *mu_out,
+              int *ir_steps)
 {
     prob_t p;
     int rc = prob_build(qp, &p);
     if (rc) return rc;
     if (p.nsoft > 0 && arg->abs_form != 0) { prob_free(&p); return ORC_EINVAL; }
+    /* refinement: delta formulation without slacks */
+    if (arg->ir_max < 0 || (arg->ir_max > 0 && (p.nsoft > 0 || arg->abs_form != 0))) { prob_free(&p); return ORC_EINVAL; }
     ivec_t v, r, d, dc;
     ivec_alloc(&p, &v); ivec_alloc(&p, &r); ivec_alloc(&p, &d); ivec_alloc(&p, &dc);
     int nc = p.ncon, nsf = p.nsoft;
@@ -1008,7 +1121,7 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
         }
     }
 
-    int status = ORC_MAX_ITER, k = 0;
+    int status = ORC_MAX_ITER, k = 0, ir_total = 0;
     double norms[4] = {0, 0, 0, 0}, mu = 0.0;
     const int absf = arg->abs_form != 0;
     for (k = 0;; ++k) {
@@ -1033,6 +1146,9 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
         }
         if (k >= arg->iter_max) { status = ORC_MAX_ITER; break; }
 
+        /* refinement tolerance relative to the residuals at this iterate */
+        const int refine = arg->ir_max > 0;
+        const double ir_tol = arg->ir_tol * max2(1.0, max2(max2(norms[0], norms[1]), max2(norms[2], norms[3])));
         barrier_weights(&p, &v, wl, wu);
         fac_t f;
         memset(&f, 0, sizeof(f));
@@ -1052,6 +1168,7 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
             set_rm(&p, &v, &d, sigma * mu, &r);
             if (absf) newton_solve_abs(&p, &f, &v, &r, &dc);
             else newton_solve(&p, &f, &v, &r, &dc);
+            if (refine) ir_total += refine_step(&p, &f, &v, &r, arg->ir_max, ir_tol, &dc);
             double a_c = max_step(&p, &v, &dc);
             if (a_c > 1.0) a_c = 1.0;
             double mu_c = mu_after(&p, &v, &dc, a_c);
@@ -1060,6 +1177,7 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
                 set_rm(&p, &v, NULL, sigma * mu, &r);
                 if (absf) newton_solve_abs(&p, &f, &v, &r, &dc);
                 else newton_solve(&p, &f, &v, &r, &dc);
+                if (refine) ir_total += refine_step(&p, &f, &v, &r, arg->ir_max, ir_tol, &dc);
             }
             step = &dc;
         }
@@ -1110,6 +1228,7 @@ int orc_solve(const orc_qp *qp, const orc_arg *arg, orc_vec *sol, int *iters, do
             status = ORC_NAN;
     }
     if (iters) *iters = k;
+    if (ir_steps) *ir_steps = ir_total;
     if (res_norms) for (int i = 0; i < 4; ++i) res_norms[i] = norms[i];
     if (mu_out) *mu_out = mu;
     ivec_to_user(&p, &v, sol);

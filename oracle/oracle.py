@@ -53,7 +53,7 @@ class _Arg(ct.Structure):
                 ("tol_comp", ct.c_double), ("iter_max", ct.c_int), ("alpha_min", ct.c_double),
                 ("gamma", ct.c_double), ("lam_min", ct.c_double), ("t_min", ct.c_double),
                 ("reg_prim", ct.c_double), ("corr_ratio", ct.c_double), ("warm_start", ct.c_int),
-                ("abs_form", ct.c_int)]
+                ("abs_form", ct.c_int), ("ir_max", ct.c_int), ("ir_tol", ct.c_double)]
 
 
 SOFT_NAMES = ("s_l", "s_u", "lam_sl", "lam_su", "t_sl", "t_su")
@@ -72,13 +72,16 @@ def _load():
         if not os.path.exists(_LIB):
             build()
         lib = ct.CDLL(_LIB)
-        lib.orc_solve.argtypes = [ct.POINTER(_Qp), ct.POINTER(_Arg), ct.POINTER(_Vec), _PI, _P, _P]
+        lib.orc_solve.argtypes = [ct.POINTER(_Qp), ct.POINTER(_Arg), ct.POINTER(_Vec), _PI, _P, _P, _PI]
         lib.orc_solve.restype = ct.c_int
         lib.orc_residuals.argtypes = [ct.POINTER(_Qp), ct.POINTER(_Vec), ct.POINTER(_Vec), _P, _P]
         lib.orc_residuals.restype = ct.c_int
         lib.orc_newton_step.argtypes = [ct.POINTER(_Qp), ct.POINTER(_Vec), ct.c_double, ct.c_double, ct.c_int,
                                         ct.POINTER(_Vec)]
         lib.orc_newton_step.restype = ct.c_int
+        lib.orc_newton_step_ir.argtypes = [ct.POINTER(_Qp), ct.POINTER(_Vec), ct.c_double, ct.c_double, ct.c_int,
+                                           ct.c_double, ct.POINTER(_Vec), _PI]
+        lib.orc_newton_step_ir.restype = ct.c_int
         lib.orc_ir_residual.argtypes = [ct.POINTER(_Qp), ct.POINTER(_Vec), ct.POINTER(_Vec),
                                         ct.POINTER(_Vec), ct.POINTER(_Vec)]
         lib.orc_ir_residual.restype = ct.c_int
@@ -102,11 +105,16 @@ class Arg:
     corr_ratio: float = 10.0
     warm_start: int = 0  # 0 cold; 1 primal guess; 2 primal and dual guess (Section 4.2)
     abs_form: int = 0    # 1: absolute formulation (eq:alg:pdipm:abs), exit on the duality measure
+    # refinement of the prediction-centering-correction direction (Sections
+    # 3.4 and 4.2): up to ir_max corrections per direction, until the
+    # refinement residual is within ir_tol * max(1, residual norms); 0: none
+    ir_max: int = 0
+    ir_tol: float = 1e-10
 
     def _c(self):
         return _Arg(self.tol_stat, self.tol_eq, self.tol_ineq, self.tol_comp, int(self.iter_max),
                     self.alpha_min, self.gamma, self.lam_min, self.t_min, self.reg_prim, self.corr_ratio,
-                    int(self.warm_start), int(self.abs_form))
+                    int(self.warm_start), int(self.abs_form), int(self.ir_max), float(self.ir_tol))
 
     @staticmethod
     def with_tol(tol: float, **kw) -> "Arg":
@@ -212,6 +220,7 @@ class Result:
     res: np.ndarray   # inf-norms: stat, eq, ineq, comp
     mu: float
     sol: dict         # u, x, pi, lam_l, lam_u, t_l, t_u (and the slack blocks)
+    ir_steps: int = 0  # refinement corrections kept in total
 
 
 def solve(qp, arg: Arg | None = None, guess: dict | None = None) -> Result:
@@ -224,15 +233,16 @@ def solve(qp, arg: Arg | None = None, guess: dict | None = None) -> Result:
     if guess is not None:
         sol.set(**{k: guess[k] for k in Vec.names if k in guess})
     it = ct.c_int(0)
+    irs = ct.c_int(0)
     res = np.zeros(4)
     mu = ct.c_double(0.0)
     a = arg._c()
     sv = sol.c()
     st = lib.orc_solve(ct.byref(pk.c), ct.byref(a), ct.byref(sv), ct.byref(it),
-                       res.ctypes.data_as(_P), ct.byref(mu))
+                       res.ctypes.data_as(_P), ct.byref(mu), ct.byref(irs))
     if st < 0:
         raise ValueError(f"oracle rejected the problem (code {st})")
-    return Result(st, it.value, res, mu.value, sol.view())
+    return Result(st, it.value, res, mu.value, sol.view(), irs.value)
 
 
 def _vec_from(pk, d):
@@ -274,6 +284,24 @@ def newton_step(qp, iterate: dict, tau: float = 0.0, reg: float = 0.0, abs_form:
     if rc != 0:
         raise ValueError(f"oracle Newton step failed (code {rc})")
     return out.view()
+
+
+def newton_step_refined(qp, iterate: dict, tau: float = 0.0, reg: float = 0.0, ir_max: int = 4,
+                        ir_tol: float = 1e-10):
+    """Newton step of eq:alg:pdipm:delta with iterative refinement (Section
+    3.4): factorization with regularization reg, up to ir_max corrections
+    against the unregularized matrix.  Returns (step, corrections kept)."""
+    lib = _load()
+    pk = _Packed(qp)
+    it = _vec_from(pk, iterate)
+    out = Vec.like(pk)
+    kept = ct.c_int(0)
+    itc, outc = it.c(), out.c()
+    rc = lib.orc_newton_step_ir(ct.byref(pk.c), ct.byref(itc), ct.c_double(tau), ct.c_double(reg), int(ir_max),
+                                ct.c_double(ir_tol), ct.byref(outc), ct.byref(kept))
+    if rc != 0:
+        raise ValueError(f"oracle Newton step failed (code {rc})")
+    return out.view(), kept.value
 
 
 def ir_residual(qp, iterate: dict, step: dict, rhs: dict) -> dict:
