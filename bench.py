@@ -96,11 +96,15 @@ def cpu_baseline(qps, seconds, tol, single_qp=None):
     arg = O.Arg.with_tol(tol)
     t0 = time.perf_counter()
 
+    refs = {}
+
     def work(k):
         cnt, i = 0, k
         while time.perf_counter() - t0 < seconds:
-            r = O.solve(qps[i % len(qps)], arg)
+            j = i % len(qps)
+            r = O.solve(qps[j], arg)
             cnt += int(r.status == O.SUCCESS)
+            refs.setdefault(j, r)
             i += threads
         return cnt
 
@@ -112,6 +116,48 @@ def cpu_baseline(qps, seconds, tol, single_qp=None):
                      f"{threads} threads, one instance per thread at a time, {el:.1f} s"}
     if single is not None:
         out["single_instance"] = single
+    return out, refs
+
+
+def host_check(qps, refs, runs, large, large_picks):
+    """Check the returned points on the host (the benchmark's CPU-baseline
+    leg, the one place it runs the oracle): the KKT residual of every point,
+    evaluated in FP64 by the oracle's residual routine, and the primal error
+    against the oracle's solution, rel_err = |y - y_ref|_inf / max(1,
+    |y_ref|_inf), over the instances the timed oracle sample solved (every
+    instance when the sample covers the batch); for the large-stage batch on
+    a few instances solved by the oracle here (FP64 with refinement, 1e-8)."""
+    import concurrent.futures as cf
+    from oracle import oracle as O
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+
+    def err(sol, ref):
+        y = np.concatenate([sol["u"], sol["x"]])
+        yr = np.concatenate([ref["u"], ref["x"]])
+        return float(np.max(np.abs(y - yr)) / max(1.0, np.max(np.abs(yr))))
+
+    def summarize(qs, res, rf):
+        with cf.ThreadPoolExecutor(threads) as ex:
+            kkt = list(ex.map(lambda i: O.kkt_res(qs[i], res[i].sol), range(len(qs))))
+        ok = [i for i in range(len(qs)) if res[i].status == 0 and kkt[i] <= KKT_OK]
+        errs = [err(res[i].sol, rf[i].sol) for i in ok if i in rf and rf[i].status == O.SUCCESS]
+        return {"solves_ok_host": len(ok), "max_kkt_res_host": float(max(kkt[i] for i in ok)) if ok else None,
+                "rel_err_max": float(max(errs)) if errs else None,
+                "rel_err_p50": float(np.median(errs)) if errs else None, "compared": len(errs)}
+
+    out = {"kkt": "oracle residual routine, FP64, every returned point",
+           "rel_err": "|y - y_ref|_inf / max(1, |y_ref|_inf) against the oracle's FP64 solution at 1e-8"}
+    for name, res in runs.items():
+        out[name] = summarize(qps, res, refs)
+    if large is not None and large_picks > 0:
+        lq, lres = large
+        picks = list(range(0, len(lq), max(1, len(lq) // large_picks)))[:large_picks]
+        arg = O.Arg.with_tol(1e-8, ir_max=4)
+        with cf.ThreadPoolExecutor(threads) as ex:
+            lrefs = dict(zip(picks, ex.map(lambda i: O.solve(lq[i], arg), picks)))
+        out["large"] = {name: summarize(lq, res, lrefs) for name, res in lres.items()}
+        out["large"]["oracle_sample"] = picks
     return out
 
 
@@ -119,7 +165,10 @@ def leg_uneven(B, W, torch, np, count, steps, seed0=0):
     """Uneven batch: every instance solved in one batch solve, one launch per
     kernel group, the groups spread over the batch stream and 3 extra
     streams (and, for comparison, all on the batch stream)."""
+    from paper_2003_02547_amd import perfmodel
     qps = [W.random_uneven(seed0 + i) for i in range(count)]
+    dbytes = np.array([perfmodel.data_bytes(q) for q in qps], dtype=np.float64)
+    fpi = np.array([perfmodel.flops_per_iter(q) for q in qps], dtype=np.float64)
     out = {}
     for name, mode, streams in (("f64", B.MODE_F64, 3), ("mixed", B.MODE_MIXED, 3), ("f64_one_stream", B.MODE_F64, 0)):
         batch = B.Batch(qps, B.default_arg(mode), streams=streams).load().sync()
@@ -139,10 +188,18 @@ def leg_uneven(B, W, torch, np, count, steps, seed0=0):
         ok = sum(1 for x in stats if x.status == B.SUCCESS and max(x.res[:]) <= KKT_OK)
         groups = sorted({batch.variant(i)[0] for i in range(count)})
         nv = B.lib().oqp_variant_count()
-        out[name] = {"value": round(ok / (float(np.median(ms)) * 1e-3), 1), "unit": "solves/s",
-                     "ms_per_step": round(float(np.median(ms)), 3), "solves_ok": ok,
+        t = float(np.median(ms)) * 1e-3
+        nres = np.array([x.iters + 1 + x.ir_steps for x in stats])
+        its = np.array([x.iters for x in stats])
+        ach = float(np.sum(dbytes * nres)) / t / 1e9
+        out[name] = {"value": round(ok / t, 1), "unit": "solves/s",
+                     "ms_per_step": round(t * 1e3, 3), "solves_ok": ok,
                      "block_kernel_instances": sum(1 for i in range(count) if batch.variant(i)[0] >= nv),
-                     "kernel_groups": len(groups), "extra_streams": streams}
+                     "kernel_groups": len(groups), "extra_streams": streams,
+                     "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                                  "scope": "whole batch solve (every kernel group), batch-stream events",
+                                  "fp64_tflops": round(float(np.sum(fpi * its)) / t / 1e12, 4)}}
         del batch
     out["instances"] = count
     out["sizes"] = "nx~U{4..48}, nu~U{1..16}, N~U{10..100}, boxes on all u and x"
@@ -373,15 +430,23 @@ def leg_single(B, W, torch, np, reps):
 
 def leg_large(B, W, torch, np, perfmodel, count, steps):
     """Large-stage batch (nx = 128, nu = 32, N = 50, 32 general rows per
-    stage): the block kernel's global-memory mode, FP64 and mixed."""
+    stage): the block kernel's global-memory mode.  FP64 to the FP64 bar
+    (KKT 1e-8) with up to 4 refinement corrections of the
+    prediction-centering-correction direction (without them the iteration
+    stalls before 1e-8 on some instances, in the oracle as well); mixed to the
+    metric's 1e-6.  Roofline: algorithmic flops of the method (factorization,
+    two solves and one residual per iteration, one solve and one residual per
+    refinement correction) over the launch time, against the FP64 matrix-core
+    peak (FP32 for the mixed path's factorization)."""
     qps = [W.random_large_stage(i) for i in range(count)]
     fpi = np.array([perfmodel.flops_per_iter(q) for q in qps])
-    out = {"instances": count, "sizes": "nx=128, nu=32, N=50, ng=32 (C=0)", "tol": KKT_OK}
-    tol = dict(tol_stat=KKT_OK, tol_eq=KKT_OK, tol_ineq=KKT_OK, tol_comp=KKT_OK)
-    for name, mode in (("f64", B.MODE_F64), ("mixed", B.MODE_MIXED)):
-        # both paths to the metric's tolerance: about half of these instances
-        # stall before 1e-8 (the oracle as well)
-        batch = B.Batch(qps, B.default_arg(mode, **tol)).load().sync()
+    fir = np.array([perfmodel.flops_per_refinement(q) for q in qps])
+    dbytes = np.array([perfmodel.data_bytes(q) for q in qps], dtype=np.float64)
+    out = {"instances": count, "sizes": "nx=128, nu=32, N=50, ng=32 (C=0)"}
+    keep = {}
+    for name, mode, tol, irm in (("f64", B.MODE_F64, 1e-8, 4), ("mixed", B.MODE_MIXED, KKT_OK, 4)):
+        arg = B.default_arg(mode, tol_stat=tol, tol_eq=tol, tol_ineq=tol, tol_comp=tol, ir_max=irm)
+        batch = B.Batch(qps, arg).load().sync()
         batch.solve()
         torch.cuda.synchronize()
         st = batch.stream
@@ -394,15 +459,27 @@ def leg_large(B, W, torch, np, perfmodel, count, steps):
             torch.cuda.synchronize()
             ms.append(s_.elapsed_time(e_))
         batch.fetch().sync()
-        stats = [batch.stat(i) for i in range(count)]
-        ok = sum(1 for x in stats if x.status == B.SUCCESS and max(x.res[:]) <= KKT_OK)
-        its = np.array([x.iters for x in stats])
+        res = batch.results()
+        ok = sum(1 for x in res if x.status == B.SUCCESS and max(x.res[:]) <= KKT_OK)
+        its = np.array([x.iters for x in res])
+        irs = np.array([x.ir_steps for x in res])
         t = float(np.median(ms)) * 1e-3
+        flops = float(np.sum(fpi * its + fir * irs))
+        peak = 78.6 if mode == B.MODE_F64 else 157.3
+        ach = flops / t / 1e12
         out[name] = {"value": round(ok / t, 1), "unit": "solves/s", "ms_per_step": round(t * 1e3, 3),
-                     "solves_ok": ok, "iters_p50": float(np.median(its)),
-                     "flop_rate_tflops": round(float(np.sum(fpi * its)) / t / 1e12, 3)}
+                     "solves_ok": ok, "tol": tol, "ir_max": irm,
+                     "non_success": [i for i, x in enumerate(res) if x.status != B.SUCCESS],
+                     "iters_p50": float(np.median(its)), "iters_max": int(its.max()),
+                     "ir_steps_mean": round(float(irs.mean()), 2),
+                     "max_kkt_res_kernel": float(max(max(x.res[:]) for x in res)),
+                     "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
+                                  "frac": round(ach / peak, 5), "traffic": None,
+                                  "kernel": "ipm_block_kernel<%d,256,64>" % (0 if mode == B.MODE_F64 else 1),
+                                  "hbm_gbs": round(float(np.sum(dbytes * (its + 1 + irs))) / t / 1e9, 1)}}
+        keep[name] = res
         del batch
-    return out
+    return out, qps, keep
 
 
 def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_seconds, per_req_seconds, log):
@@ -471,6 +548,8 @@ def main():
     ap.add_argument("--soft-uneven", type=int, default=4096, help="instances of the soft uneven batch (0: skip)")
     ap.add_argument("--large", type=int, default=256, help="instances of the large-stage leg (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2)
+    ap.add_argument("--large-check", type=int, default=16,
+                    help="large-stage instances the host check solves with the oracle for the primal error")
     ap.add_argument("--serve-pool", type=int, default=256, help="distinct instances in the serving pool (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="offered Poisson rate for the saturation run")
     ap.add_argument("--serve-sat-seconds", type=float, default=0.25)
@@ -539,7 +618,7 @@ def main():
         nres = iters + 1 + irs  # residual evaluations: one per iteration, the final check, one per refinement
         alg_bytes = float(np.sum(dbytes * nres))
         return dict(variant=variant, ok=ok, wall=wall, steps=steps, kern_ms=kern_ms, kern_s=kern_s,
-                    status=status, kkt=kkt, iters=iters, irs=irs, fb=fb,
+                    status=status, kkt=kkt, iters=iters, irs=irs, fb=fb, res=res,
                     achieved=alg_bytes / kern_s / 1e9, flops=float(np.sum(fpi * iters)) / kern_s / 1e12,
                     value=ok * steps / wall, del_batch=batch)
 
@@ -620,15 +699,24 @@ def main():
     if args.uneven > 0:
         log(f"bench: uneven leg, {args.uneven} instances")
         line["uneven"] = leg_uneven(B, W, torch, np, args.uneven, args.uneven_steps)
+    large = None
     if args.large > 0:
         log(f"bench: large-stage leg, {args.large} instances")
-        line["large"] = leg_large(B, W, torch, np, perfmodel, args.large, args.large_steps)
+        line["large"], lq, lres = leg_large(B, W, torch, np, perfmodel, args.large, args.large_steps)
+        large = (lq, lres)
     if args.serve_pool > 0:
         line["serve"] = leg_serve(B, W, torch, np, args.serve_pool, args.serve_rate, args.serve_sat_seconds,
                                   args.serve_frac, args.serve_seconds, args.serve_per_request_seconds, log)
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
-        line["cpu_baseline"] = cpu_baseline(qps, args.cpu_seconds, 1e-8, W.mass_spring_chain4(1))
+        line["cpu_baseline"], refs = cpu_baseline(qps, args.cpu_seconds, 1e-8, W.mass_spring_chain4(1))
+        log("bench: host check of the returned points against the oracle")
+        chk = host_check(qps, refs, {"f64": f["res"], "mixed": m["res"]}, large, args.large_check)
+        # the headline counts only solves whose KKT residual, evaluated on the
+        # host in FP64, meets the metric's bound
+        line["solves_ok_host"] = chk["f64"]["solves_ok_host"]
+        line["value"] = round(chk["f64"]["solves_ok_host"] * args.steps / f["wall"], 1)
+        line["host_check"] = chk
     print(json.dumps(line), flush=True)
 
 

@@ -57,7 +57,10 @@ extern "C" {
 #define OQP_NAN 3      /* a residual norm or the duality measure is NaN */
 
 /* ---- modes ------------------------------------------------------------- */
-#define OQP_MODE_F64 0   /* FP64 factorization ("speed" mode, delta formulation) */
+#define OQP_MODE_F64 0   /* FP64 factorization ("speed" mode, delta formulation); with ir_max > 0 the
+                            prediction-centering-correction direction is refined in FP64 (Section
+                            3.4: late iterations of ill-conditioned systems) by up to ir_max
+                            corrections with the same factors (not with slacks) */
 #define OQP_MODE_MIXED 1 /* FP32 factorization + FP64 iterative refinement */
 #define OQP_MODE_ABS 2   /* FP64, absolute formulation (eq:alg:pdipm:abs; mode "speed_abs" of Section 4.2):
                             right-hand sides from the data, no residuals in the loop, exit when the
@@ -67,16 +70,15 @@ extern "C" {
                              [chol(Phi)'; U]) instead of the Cholesky factor of the normal matrix
                              Phi + U'U (mode "robust" of Section 4.2), and up to ir_max (default 4)
                              refinement steps on the prediction-centering-correction direction;
-                             batch only, for stage blocks covered by a one-wave variant (nx + nu up
-                             to 32 after padding: nx <= 16 with nu <= 16, or nx <= 24 with nu <= 8) */
+                             batch only (one-wave variants and block kernel) */
 #define OQP_MODE_BALANCE 4 /* FP64, delta formulation (mode "balance" of Section 4.2): Cholesky
                               factors whose accuracy is checked each iteration by the refinement
                               residual of the predictor step; when it exceeds
                               ir_tol * max(1, ||r||_inf) the iteration is factored again with the
                               array algorithm of OQP_MODE_ROBUST (oqp_stat.qr_refactors counts
                               them), and up to ir_max (default 2) refinement steps run on the
-                              prediction-centering-correction direction; batch only, same stage
-                              blocks as OQP_MODE_ROBUST */
+                              prediction-centering-correction direction; batch only (one-wave
+                              variants and block kernel) */
 
 typedef struct oqp_dims oqp_dims;
 typedef struct oqp_qp oqp_qp;
@@ -98,7 +100,9 @@ typedef struct {
     double t_min;      /* lower clamp on slacks */
     double reg_prim;   /* primal regularization added during factorization */
     double corr_ratio; /* corrector rejected if mu after it > corr_ratio * mu_aff */
-    int ir_max;        /* max iterative-refinement steps per Newton solve */
+    int ir_max;        /* max iterative-refinement corrections per refined direction (Section 3.4);
+                          a correction that does not lower ||r_ir||_inf is taken back.  Defaults:
+                          4 (mixed, robust), 2 (balance), 0 (F64: no refinement) */
     double ir_tol;     /* refinement stops at ||r_ir||_inf <= ir_tol * max(1, ||r||_inf) */
     int warm_start;    /* batch only (Section 4.2): 0 cold start; 1 primal guess, 2 primal and dual
                           guess, read from the batch's iterate records (see oqp_batch_solve) */
@@ -110,7 +114,7 @@ typedef struct {
 typedef struct {
     int status;        /* OQP_SUCCESS / OQP_MAX_ITER / OQP_MIN_STEP / OQP_NAN */
     int iters;         /* IPM iterations taken */
-    int ir_steps;      /* refinement steps taken in total */
+    int ir_steps;      /* refinement corrections kept in total */
     int fell_back_f64; /* mixed path only: 1 if the FP32 factorization broke down (or the mixed
                           IPM stopped on NaN / a too-short step) and the instance was re-solved
                           from a cold start by the FP64 kernel */

@@ -313,11 +313,11 @@ class Batch:
         self.host_bytes, self.dev_bytes = hb.value, db.value
         self.host = _aligned(self.host_bytes, 64)
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = _V()
         self.dev_buf = torch.empty(self.dev_bytes + 256, dtype=torch.uint8, device=dev)
         base = self.dev_buf.data_ptr()
         self.dev_ptr = base + ((-base) % 256)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
-        h = _V()
         _check(L.oqp_batch_init(self._dimh, n, ct.byref(self.arg), self.host.ctypes.data, self.host_bytes,
                                 self.dev_ptr, self.dev_bytes, self.stream.cuda_stream, ct.byref(h)))
         self.h = h
@@ -651,6 +651,17 @@ class Server:
         if self.h:
             _check(lib().oqp_server_destroy(self.h))
             self.h = None
+
+    def __del__(self):
+        # oqp_server_destroy waits for the server's streams and destroys its
+        # events before the arena and host tensors are released, so a server
+        # dropped without close() leaves no launch reading freed memory
+        try:
+            if getattr(self, "h", None):
+                lib().oqp_server_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
 
 
 def set_wave_max(nz: int) -> int:

@@ -713,19 +713,10 @@ struct SolveShape {
 
 static constexpr size_t kMaxCondLds = 64 * 1024;
 
-// Kernel for the largest stage sizes under a solver mode: the QR-based
-// factorization is built for the one-wave variants only, which then cover
-// the instance whatever the one-wave bound.
-static int select_for_mode(int mx, int mu, int mg, int mode, int soft, KSel* out)
-{
-    if (soft || (mode != OQP_MODE_ROBUST && mode != OQP_MODE_BALANCE)) return select_kernel_max(mx, mu, mg, out);
-    const int v = pick_variant_max(mx, mu, mg);
-    if (v < 0) return -1;
-    int nx, nu, ng;
-    oqp::variant_dims(v, &nx, &nu, &ng);
-    *out = KSel{v, nx, nu, ng};
-    return OQP_OK;
-}
+// Kernel for the largest stage sizes (every mode has the same kernels: the
+// array-algorithm builds exist for the one-wave variants and the block
+// kernel alike).
+static int select_for_mode(int mx, int mu, int mg, int, int, KSel* out) { return select_kernel_max(mx, mu, mg, out); }
 
 static int solve_shape(const oqp_dims* d, int cond_N, int mode, int soft, SolveShape* sh, int i)
 {
@@ -734,10 +725,7 @@ static int solve_shape(const oqp_dims* d, int cond_N, int mode, int soft, SolveS
         int mx, mu, mg;
         dims_max(d, &mx, &mu, &mg);
         if (select_for_mode(mx, mu, mg, mode, soft, &sh->ks))
-            return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d%s", i,
-                        (mode == OQP_MODE_ROBUST || mode == OQP_MODE_BALANCE)
-                            ? " (robust and balance modes: one-wave variants only)"
-                            : "");
+            return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d", i);
         sh->onx = sh->ks.nx;
         sh->onu = sh->ks.nu;
         sh->ong = sh->ks.ng;
@@ -841,8 +829,8 @@ static int batch_soft(const oqp_dims* const* dims, int count, const oqp_arg* arg
     for (int i = 0; i < count; ++i)
         if (dims[i] && dims_soft(dims[i])) *soft = 1;
     if (!*soft) return OQP_OK;
-    if (arg->mode != OQP_MODE_F64 || arg->cond_N != 0)
-        return fail(OQP_EINVAL, "batch: soft constraints need the FP64 mode and no condensing");
+    if (arg->mode != OQP_MODE_F64 || arg->cond_N != 0 || arg->ir_max != 0)
+        return fail(OQP_EINVAL, "batch: soft constraints need the FP64 mode without refinement and no condensing");
     for (int i = 0; i < count; ++i)
         if (dims[i] && check_soft_dims(dims[i], "batch")) return OQP_EINVAL;
     return OQP_OK;

@@ -74,7 +74,9 @@ OQP_HD constexpr BLds make_blds(int NX, int NU, int NG)
     s.opn = o; o += 2 * bmaxi(NX, 1);
     s.odv = o; o += NZ;
     s.odd = o; o += NZ;                              // FP64 running diagonal (mixed Cholesky)
-    s.ol11 = o; o += 16 * 16;                        // diagonal block of the current Cholesky panel
+    // diagonal block of the current Cholesky panel; with the next region, the
+    // two reflector buffers of the array algorithm (2 (NV + 2) doubles)
+    s.ol11 = o; o += bmaxi(16 * 16, 2 * (NV + 2) - 64);
     s.ocol = o; o += 64;
     s.ored = o; o += 32;
     s.oflag = o; o += 2;
@@ -116,6 +118,13 @@ struct Blk {
     static constexpr bool MIXED = KM == KM_MIXED;
     static constexpr bool ABS = KM == KM_ABS;  // absolute formulation (Section 3.2)
     static constexpr bool SOFT = KM == KM_SOFT;  // soft constraints (Section 2.2), soft layout
+    // factorization by the array algorithm (Section 4.2, mode robust), or
+    // Cholesky factors checked by the predictor's refinement residual with the
+    // array algorithm when they fail the check (mode balance)
+    static constexpr bool ROBUST = KM == KM_ROBUST;
+    static constexpr bool BALANCE = KM == KM_BALANCE;
+    // refinement of the prediction-centering-correction direction
+    static constexpr bool REFINE = MIXED || ROBUST || BALANCE || KM == KM_F64;
     using TS = typename std::conditional<MIXED, float, double>::type;
     Layout Lo;
     BLds S;
@@ -725,6 +734,74 @@ struct Blk {
         return res;
     }
 
+    // Array algorithm (Section 4.2, modes robust and balance): with M holding
+    // L, the Cholesky factor of Phi (zero strict upper part), and V the rows
+    // [U; sqrt(w) G] (rows r0.. of V), Householder reflections of the array
+    // [L'; V] leave an upper-triangular R with R'R = Phi + V'V, i.e. the factor
+    // of the normal matrix, without forming V'V.  Reflection j takes the
+    // column j of V into R(j, j) (beta = +norm, so the diagonal stays
+    // positive; v0 computed without cancellation when R(j, j) > 0) and is
+    // applied to the columns k > j.  L = R' is written back into M (lower
+    // part) and 1/L_jj into dv.  Threads: column k = t / RG with RG threads
+    // (a power of two, lanes of one wave) summing interleaved rows; each
+    // reflection takes one barrier, its vector in one of two LDS buffers.
+    // Every thread calls it.
+    __device__ __forceinline__ void qr_update(int r0) const
+    {
+        double* m = M();
+        double* v = V();
+        double* rb = l11();  // two buffers of NV + 2 doubles: v / v0 per row, then tau
+        const int nvr = NV - r0;
+        int rg = 1;
+        while (rg * 2 * NZ <= BT && rg < 64) rg *= 2;
+        const int k = tid / rg, q = tid % rg;
+        const bool act = k < NZ;
+        // column 0's reflection: its threads hold the squared norm of V(:, 0)
+        auto colnorm = [&](int c) {
+            double sq = 0.0;
+            if (act && k == c)
+                for (int r = q; r < nvr; r += rg) {
+                    const double x = v[(r0 + r) + c * ldv];
+                    sq += x * x;
+                }
+            for (int o = 1; o < rg; o <<= 1) sq += __shfl_xor(sq, o);
+            return sq;
+        };
+        double sg = colnorm(0);
+        for (int j = 0; j < NZ; ++j) {
+            double* buf = rb + (j & 1) * (NV + 2);
+            if (act && k == j) {
+                // reflection j from R(j, j) = L(j, j) and V(:, j)
+                const double a = m[j + j * ldm];
+                const double beta = sqrt(a * a + sg);
+                const double v0 = a <= 0.0 ? a - beta : -sg / (a + beta);
+                const double tau = sg == 0.0 ? 0.0 : 2.0 * v0 * v0 / (sg + v0 * v0);
+                const double iv0 = sg == 0.0 ? 0.0 : 1.0 / v0;
+                for (int r = q; r < nvr; r += rg) buf[r] = v[(r0 + r) + j * ldv] * iv0;
+                if (q == 0) {
+                    buf[NV] = tau;
+                    m[j + j * ldm] = beta;
+                }
+            }
+            __syncthreads();
+            if (act && k > j) {
+                const double tau = buf[NV];
+                double sd = 0.0;
+                for (int r = q; r < nvr; r += rg) sd += buf[r] * v[(r0 + r) + k * ldv];
+                for (int o = 1; o < rg; o <<= 1) sd += __shfl_xor(sd, o);
+                double* rjk = m + k + j * ldm;  // R(j, k) = L(k, j)
+                sd += *rjk;
+                const double ts = tau * sd;
+                for (int r = q; r < nvr; r += rg) v[(r0 + r) + k * ldv] -= ts * buf[r];
+                if (q == 0) *rjk -= ts;  // the column's threads are lanes of one wave: all read it above
+            }
+            if (j + 1 < NZ) sg = colnorm(j + 1);
+        }
+        __syncthreads();
+        for (int i = opq(tid); i < NZ; i += BT) dv()[i] = 1.0 / m[i + i * ldm];
+        __syncthreads();
+    }
+
     // Forward substitution with the (u, u) block of the factor in M (u
     // columns): wave 0 solves y = L_uu^{-1} m_u (rows j < NU, one per lane,
     // di = 1/L_jj), then every thread of rows NU <= i < NZ forms
@@ -803,8 +880,8 @@ struct Blk {
     // With absf (absolute formulation, Section 3.2) the right-hand side is
     // built from the data alone, -[g; b; d; r_m - 2 Lam T e]; the residual
     // products are skipped and their norms not formed.
-    __device__ __forceinline__ bool passA(bool upd, double alpha, double shift, bool factor, bool absf, double& o_g,
-                                          double& o_b, double& o_d, double& o_m, double& o_lt) const
+    __device__ __forceinline__ bool passA(bool upd, double alpha, double shift, bool factor, bool absf, bool qr,
+                                          double& o_g, double& o_b, double& o_d, double& o_m, double& o_lt) const
     {
         double mg = 0.0, mb = 0.0, md = 0.0, mm = 0.0, slt = 0.0;
         bool fact_ok = true;
@@ -1016,9 +1093,16 @@ struct Blk {
                 }
                 if (n < N) trmm_LtF();
                 __syncthreads();
-                if (n < N || NG > 0) syrk_VtV(n < N ? 0 : NX);
-                __syncthreads();
+                // the array algorithm (robust build; balance build when this
+                // iteration's Cholesky factors failed the accuracy check)
+                // factors Phi + V'V without forming V'V
+                const bool arr = ROBUST || (BALANCE && qr);
+                if (!arr) {
+                    if (n < N || NG > 0) syrk_VtV(n < N ? 0 : NX);
+                    __syncthreads();
+                }
                 fact_ok = cholesky() && fact_ok;
+                if (arr && (n < N || NG > 0)) qr_update(n < N ? 0 : NX);
 
                 // reduced gradient and cost-to-go terms
                 double mv = 0.0;
@@ -1469,18 +1553,19 @@ struct Blk {
     // duality-measure sums of pass B for the corrected step.  Stages are
     // independent here, so the loop runs over all (stage, row) pairs.
     // ==================================================================
-    __device__ __forceinline__ double passX(int oz, int opi, int oll, int olu, int otl, int otu, double& o_s1, double& o_s2) const
+    __device__ __forceinline__ double passX(int oz, int opi, int oll, int olu, int otl, int otu, double sg, double& o_s1,
+                                            double& o_s2) const
     {
         double amin = HUGE_VAL, s1 = 0.0, s2 = 0.0;
         for (int e = tid; e < (N + 1) * NZ; e += BT) {
             double* w = Wp(e / NZ);
             const int j = e % NZ;
-            w[oz + j] += w[Lo.W_edz + j];
+            w[oz + j] += sg * w[Lo.W_edz + j];
         }
         for (int e = tid; e < N * NX; e += BT) {
             double* w = Wp(1 + e / NX);
             const int i = e % NX;
-            w[opi + i] += w[Lo.W_edpi + i];
+            w[opi + i] += sg * w[Lo.W_edpi + i];
         }
         for (int e = tid; e < (N + 1) * NC; e += BT) {
             const int n = e / NC, c = e % NC;
@@ -1490,10 +1575,10 @@ struct Blk {
             double m, lo_, hi_;
             slot_bounds(d, c, m, lo_, hi_);
             if (m == 0.0) continue;
-            const double dll = w[oll + c] + w[Lo.W_edll + c];
-            const double dlu = w[olu + c] + w[Lo.W_edlu + c];
-            const double dtl = w[otl + c] + w[Lo.W_edtl + c];
-            const double dtu = w[otu + c] + w[Lo.W_edtu + c];
+            const double dll = w[oll + c] + sg * w[Lo.W_edll + c];
+            const double dlu = w[olu + c] + sg * w[Lo.W_edlu + c];
+            const double dtl = w[otl + c] + sg * w[Lo.W_edtl + c];
+            const double dtu = w[otu + c] + sg * w[Lo.W_edtu + c];
             w[oll + c] = dll;
             w[olu + c] = dlu;
             w[otl + c] = dtl;
@@ -1512,25 +1597,41 @@ struct Blk {
         return amin;
     }
 
-    // Iterative refinement of the step at the given offsets (mixed path).
-    __device__ __forceinline__ int refine(int rmode, double shift, double rnorm, int oz, int opi, int oll, int olu, int otl, int otu,
-                          double& amax, double& s1, double& s2) const
+    // Iterative refinement of the step at the given offsets (Section 3.4):
+    // each correction solves the Newton system with the refinement residual
+    // as right-hand side.  Stops when ||r_ir|| <= ir_tol * rnorm, after
+    // max_steps corrections, or when a correction did not lower ||r_ir||
+    // (that correction is then subtracted again, so the step kept is the best
+    // one seen).  Updates amax, s1, s2 for the step kept; nir0 returns the
+    // residual norm of the unrefined step (the balance build's accuracy check
+    // of the factors); returns the corrections kept.
+    __device__ __forceinline__ int refine(int rmode, double shift, double rnorm, int max_steps, int oz, int opi, int oll,
+                                          int olu, int otl, int otu, double& amax, double& s1, double& s2,
+                                          double& nir0) const
     {
         int steps = 0;
         double prev = HUGE_VAL;
-        for (int it = 0; it <= P.ir_max; ++it) {
+        for (int it = 0;; ++it) {
             const double nir = passR(rmode, shift, oz, opi, oll, olu, otl, otu);
             __syncthreads();
-            if (!(nir > P.ir_tol * rnorm) || !(nir < prev) || it == P.ir_max) break;
-            prev = nir;
-            passC(RM_IR, 0.0, Lo.W_irg, Lo.W_irb, Lo.W_irdl, Lo.W_irdu);
+            if (it == 0) nir0 = nir;
+            const bool back = it > 0 && !(nir < prev);
+            if (!back && (!(nir > P.ir_tol * rnorm) || it == max_steps)) break;
+            if (!back) {
+                prev = nir;
+                passC(RM_IR, 0.0, Lo.W_irg, Lo.W_irb, Lo.W_irdl, Lo.W_irdu);
+                __syncthreads();
+                double t1v, t2v;
+                passB(RM_IR, 0.0, Lo.W_irb, Lo.W_irdl, Lo.W_irdu, Lo.W_edz, Lo.W_edpi, Lo.W_edll, Lo.W_edlu, Lo.W_edtl,
+                      Lo.W_edtu, t1v, t2v);
+                __syncthreads();
+            }
+            amax = passX(oz, opi, oll, olu, otl, otu, back ? -1.0 : 1.0, s1, s2);
             __syncthreads();
-            double t1v, t2v;
-            passB(RM_IR, 0.0, Lo.W_irb, Lo.W_irdl, Lo.W_irdu, Lo.W_edz, Lo.W_edpi, Lo.W_edll, Lo.W_edlu, Lo.W_edtl,
-                  Lo.W_edtu, t1v, t2v);
-            __syncthreads();
-            amax = passX(oz, opi, oll, olu, otl, otu, s1, s2);
-            __syncthreads();
+            if (back) {
+                --steps;
+                break;
+            }
             ++steps;
         }
         return steps;
@@ -1658,9 +1759,13 @@ struct Blk {
         // returned iterate, through the single call site of pass A
         bool final_pass = false;
         int k_exit = 0;
+        // balance build: the iteration is factored with the array algorithm
+        // (after its Cholesky factors failed the accuracy check)
+        bool qr = false, refactor = false;
+        int qr_refactors = 0;
         for (k = 0;; ++k) {
             const bool fact_ok =
-                passA(upd, alpha, shift0, !rejected && !final_pass, absf && !final_pass, ng, nb, nd, nm, slt);
+                passA(upd, alpha, shift0, !rejected && !final_pass, absf && !final_pass, qr, ng, nb, nd, nm, slt);
             __syncthreads();
             mu = slt * inv2nc;
             if (final_pass) {
@@ -1710,8 +1815,12 @@ struct Blk {
                     break;
                 }
             }
+            if constexpr (BALANCE) {
+                // a breakdown of the Cholesky factorization fails the check too
+                if (!fact_ok && !qr && !newton_mode) refactor = true;
+            }
             double amax = HUGE_VAL, mu_aff = 0.0, smu = 0.0;
-            for (int round = 0; round < 3; ++round) {
+            for (int round = 0; round < 3 && !refactor; ++round) {
                 const int rmode = round == 1 ? RM_CORRECTOR : RM_SHIFT;
                 const double shift = round == 0 ? shift0 : smu;
                 const bool aff = round == 0 && !newton_mode;
@@ -1724,14 +1833,25 @@ struct Blk {
                 const int otl = aff ? Lo.W_atl : Lo.W_dtl, otu = aff ? Lo.W_atu : Lo.W_dtu;
                 amax = passB(rmode, shift, Lo.W_rb, Lo.W_rdl, Lo.W_rdu, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, s1, s2);
                 __syncthreads();
-                if constexpr (MIXED) {
+                if constexpr (REFINE) {
                     // refinement of the prediction-centering-correction
-                    // direction (Section 4.2); the affine predictor only
-                    // feeds the centering parameter and the corrector
-                    // right-hand side and is used unrefined
-                    if (round > 0 || newton_mode || nc == 0) {
+                    // direction (Section 4.2; the FP64 build when asked for
+                    // by a positive ir_max, Section 3.4); the affine
+                    // predictor only feeds the centering parameter and the
+                    // corrector right-hand side and is used unrefined.
+                    // Balance build: the predictor's residual checks the
+                    // accuracy of this iteration's Cholesky factors
+                    const bool dir = (round > 0 || newton_mode || nc == 0) && (KM != KM_F64 || P.ir_max > 0);
+                    const bool check = BALANCE && !qr && !newton_mode && round == 0;
+                    if (dir || check) {
                         const double rnorm = fmax(1.0, fmax(fmax(ng, nb), fmax(nd, nm)));
-                        ir_steps += refine(rmode, shift, rnorm, Lo.W_dz, Lo.W_dpi, oll, olu, otl, otu, amax, s1, s2);
+                        double nir0 = 0.0;
+                        ir_steps += refine(rmode, shift, rnorm, dir ? P.ir_max : 0, Lo.W_dz, Lo.W_dpi, oll, olu, otl,
+                                           otu, amax, s1, s2, nir0);
+                        if (check && !(nir0 <= P.ir_tol * rnorm)) {
+                            refactor = true;
+                            break;
+                        }
                     }
                 }
                 if (newton_mode || nc == 0) break;
@@ -1746,6 +1866,19 @@ struct Blk {
                 } else {
                     break;
                 }
+            }
+            if constexpr (BALANCE) {
+                if (refactor) {
+                    // start the iteration over (no step taken) with the array
+                    // algorithm; the next iteration starts with Cholesky again
+                    refactor = false;
+                    qr = true;
+                    upd = false;
+                    ++qr_refactors;
+                    --k;
+                    continue;
+                }
+                qr = false;
             }
             if (newton_mode) break;
             alpha = fmin(1.0, P.gamma * amax);
@@ -1763,7 +1896,7 @@ struct Blk {
             st->iters = k;
             st->ir_steps = ir_steps;
             st->fell_back = fell_back;
-            st->qr_refactors = 0;
+            st->qr_refactors = qr_refactors;
             st->mu = mu;
             st->res[0] = ng;
             st->res[1] = nb;

@@ -35,6 +35,8 @@ int block_launch(int zm, int gm, int km, const InstDesc* desc, int count, const 
                  double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream)
 {
     if (km == KM_SOFT) return block_launch_soft(zm, gm, desc, count, data, iter, work, step, stat, P, lds_bytes, stream);
+    if (km == KM_ROBUST || km == KM_BALANCE)
+        return block_launch_qr(zm, gm, km, desc, count, data, iter, work, step, stat, P, lds_bytes, stream);
     hipStream_t s = (hipStream_t)stream;
 #define OQP_BLK(Z, G)                                                                                             \
     if (zm == Z && gm == G) {                                                                                       \
@@ -44,7 +46,7 @@ int block_launch(int zm, int gm, int km, const InstDesc* desc, int count, const 
                                                               lds_bytes, s);                                        \
         if (km == KM_F64) return launch_block_t<KM_F64, Z, G>(desc, count, data, iter, work, step, stat, P,       \
                                                               lds_bytes, s);                                        \
-        return -1; /* the QR-based factorization is built for the one-wave kernels only */                         \
+        return -1;                                                                                                  \
     }
     OQP_BLK(32, 0)
     OQP_BLK(32, 64)

@@ -59,8 +59,9 @@ struct Ipm {
     // enough (Section 4.2, mode balance)
     static constexpr bool BALANCE = KM == KM_BALANCE;
     // FP64 refinement of the prediction-centering-correction direction
-    // (mixed path; modes balance and robust, Section 4.2)
-    static constexpr bool REFINE = MIXED || ROBUST || BALANCE;
+    // (mixed path; modes balance and robust, Section 4.2; the FP64 build when
+    // asked for by a positive ir_max, Section 3.4)
+    static constexpr bool REFINE = MIXED || ROBUST || BALANCE || KM == KM_F64;
     // arithmetic type of the factorization and of the right-hand-side sweeps
     // (FP32 in the mixed path; pivots, residuals and refinement stay FP64)
     using TS = typename std::conditional<MIXED, float, double>::type;
@@ -1581,16 +1582,16 @@ struct Ipm {
     // Pass X (mixed path): step += correction, then the step length and the
     // duality-measure sums of pass B for the corrected step.
     // ==================================================================
-    __device__ __forceinline__ double passX(int oz, int opi, int oll, int olu, int otl, int otu, double& o_s1,
-                                            double& o_s2) const
+    __device__ __forceinline__ double passX(int oz, int opi, int oll, int olu, int otl, int otu, double sg,
+                                            double& o_s1, double& o_s2) const
     {
         double amin = HUGE_VAL, s1 = 0.0, s2 = 0.0;
         for (int n = 0; n <= N; ++n) {
             const double* d = Dp(n);
             const double* ir = Ip(n);
             double* w = Wp(n);
-            if (lane < NZ) w[oz + lane] += w[Lo.W_edz + lane];
-            if (lane < NX && n > 0) w[opi + lane] += w[Lo.W_edpi + lane];
+            if (lane < NZ) w[oz + lane] += sg * w[Lo.W_edz + lane];
+            if (lane < NX && n > 0) w[opi + lane] += sg * w[Lo.W_edpi + lane];
 #pragma unroll
             for (int t = 0; t < NCT; ++t) {
                 const int c = slot(t);
@@ -1598,10 +1599,10 @@ struct Ipm {
                 double m, lo_, hi_;
                 slot_bounds(d, c, m, lo_, hi_);
                 if (m == 0.0) continue;
-                const double dll = w[oll + c] + w[Lo.W_edll + c];
-                const double dlu = w[olu + c] + w[Lo.W_edlu + c];
-                const double dtl = w[otl + c] + w[Lo.W_edtl + c];
-                const double dtu = w[otu + c] + w[Lo.W_edtu + c];
+                const double dll = w[oll + c] + sg * w[Lo.W_edll + c];
+                const double dlu = w[olu + c] + sg * w[Lo.W_edlu + c];
+                const double dtl = w[otl + c] + sg * w[Lo.W_edtl + c];
+                const double dtu = w[otu + c] + sg * w[Lo.W_edtu + c];
                 w[oll + c] = dll;
                 w[olu + c] = dlu;
                 w[otl + c] = dtl;
@@ -1620,31 +1621,40 @@ struct Ipm {
         return wave_min(amin);
     }
 
-    // Iterative refinement of the step at the given offsets.  Stops when
-    // ||r_ir|| <= ir_tol * max(1, ||r||), when it stops decreasing, or after
-    // max_steps corrections.  Updates amax, s1, s2; nir0 returns the
+    // Iterative refinement of the step at the given offsets (Section 3.4).
+    // Stops when ||r_ir|| <= ir_tol * max(1, ||r||), after max_steps
+    // corrections, or when a correction did not lower ||r_ir|| (that
+    // correction is then subtracted again, so the step kept is the best one
+    // seen).  Updates amax, s1, s2 for the step kept; nir0 returns the
     // residual norm of the unrefined step (the balance build's accuracy
-    // check of the factors).
+    // check of the factors); returns the corrections kept.
     __device__ __forceinline__ int refine(int rmode, double shift, double rnorm, int max_steps, int oz, int opi,
                                           int oll, int olu, int otl, int otu, double& amax, double& s1, double& s2,
                                           double& nir0) const
     {
         int steps = 0;
         double prev = HUGE_VAL;
-        for (int it = 0; it <= max_steps; ++it) {
+        for (int it = 0;; ++it) {
             const double nir = passR(rmode, shift, oz, opi, oll, olu, otl, otu);
             __syncthreads();
             if (it == 0) nir0 = nir;
-            if (!(nir > P.ir_tol * rnorm) || !(nir < prev) || it == max_steps) break;
-            prev = nir;
-            passC(RM_IR, 0.0, Lo.W_irg, Lo.W_irb, Lo.W_irdl, Lo.W_irdu);
+            const bool back = it > 0 && !(nir < prev);
+            if (!back && (!(nir > P.ir_tol * rnorm) || it == max_steps)) break;
+            if (!back) {
+                prev = nir;
+                passC(RM_IR, 0.0, Lo.W_irg, Lo.W_irb, Lo.W_irdl, Lo.W_irdu);
+                __syncthreads();
+                double t1, t2;
+                passB(RM_IR, 0.0, Lo.W_irb, Lo.W_irdl, Lo.W_irdu, Lo.W_edz, Lo.W_edpi, Lo.W_edll, Lo.W_edlu,
+                      Lo.W_edtl, Lo.W_edtu, t1, t2);
+                __syncthreads();
+            }
+            amax = passX(oz, opi, oll, olu, otl, otu, back ? -1.0 : 1.0, s1, s2);
             __syncthreads();
-            double t1, t2;
-            passB(RM_IR, 0.0, Lo.W_irb, Lo.W_irdl, Lo.W_irdu, Lo.W_edz, Lo.W_edpi, Lo.W_edll, Lo.W_edlu, Lo.W_edtl,
-                  Lo.W_edtu, t1, t2);
-            __syncthreads();
-            amax = passX(oz, opi, oll, olu, otl, otu, s1, s2);
-            __syncthreads();
+            if (back) {
+                --steps;
+                break;
+            }
             ++steps;
         }
         return steps;
@@ -1861,7 +1871,7 @@ struct Ipm {
                     // right-hand side and is used unrefined.  Balance build:
                     // the predictor's residual checks the accuracy of this
                     // iteration's Cholesky factors
-                    const bool dir = round > 0 || newton_mode || nc == 0;
+                    const bool dir = (round > 0 || newton_mode || nc == 0) && (KM != KM_F64 || P.ir_max > 0);
                     const bool check = BALANCE && !qr && !newton_mode && round == 0;
                     if (dir || check) {
                         const double rnorm = fmax(1.0, fmax(fmax(ng, nb), fmax(nd, nm)));

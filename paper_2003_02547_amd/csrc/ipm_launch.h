@@ -32,6 +32,9 @@ int block_zmax(int nz);  // compile-time bound used for a stage block of nz (0: 
 // general rows: kernels for ng == 0 and for 0 < ng <= 64
 int block_launch(int zm, int gm, int km, const InstDesc* desc, int count, const double* data, double* iter,
                  double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
+// the array-algorithm builds (km == KM_ROBUST, KM_BALANCE), compiled in a unit of their own
+int block_launch_qr(int zm, int gm, int km, const InstDesc* desc, int count, const double* data, double* iter,
+                    double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
 // the soft-constraint build (km == KM_SOFT), compiled in a unit of its own
 int block_launch_soft(int zm, int gm, const InstDesc* desc, int count, const double* data, double* iter,
                       double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);

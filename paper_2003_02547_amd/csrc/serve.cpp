@@ -500,8 +500,8 @@ extern "C" int oqp_server_submit(oqp_server* s, const void* packed, uint64_t* ti
     const PackHdr* h;
     int rc = read_hdr(packed, &h);
     if (rc) return rc;
-    if (h->soft && s->arg.mode != OQP_MODE_F64)
-        return fail(OQP_EINVAL, "oqp_server_submit: requests with slacks need a server in the FP64 mode");
+    if (h->soft && (s->arg.mode != OQP_MODE_F64 || s->arg.ir_max != 0))
+        return fail(OQP_EINVAL, "oqp_server_submit: requests with slacks need a server in the FP64 mode without refinement");
     const size_t need = dev_footprint(h);
     if (need > s->arena_bytes) return fail(OQP_ENOMEM, "oqp_server_submit: request needs %zu device bytes, arena %zu",
                                            need, s->arena_bytes);

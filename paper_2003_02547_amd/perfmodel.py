@@ -10,6 +10,9 @@ nz = nu + nx and nx' = nx of the next stage:
   factorization: nx'^2 nz + nz (nz+1) nx' + nz^3 / 3 + ng nu (nu + 1)
   two solves:    2 [4 nz nx' + 2 nz^2 + 4 ng nu]
   one residual:  2 nz^2 + 4 nx' nz + 4 ng nu
+and per refinement correction (Section 3.4) one residual of the Newton
+system and one solve with the stored factors:
+  correction:    [4 nz nx' + 2 nz^2 + 4 ng nu] + [2 nz^2 + 4 nx' nz + 4 ng nu]
 """
 from __future__ import annotations
 
@@ -44,4 +47,15 @@ def flops_per_iter(qp) -> float:
         solves = 2 * (4 * nz * nxn + 2 * nz * nz + 4 * ng * nu)
         resid = 2 * nz * nz + 4 * nxn * nz + 4 * ng * nu
         f += fact + solves + resid
+    return f
+
+
+def flops_per_refinement(qp) -> float:
+    f = 0.0
+    for n in range(qp.N + 1):
+        nx, nu = qp.nx[n], qp.nu[n]
+        nz = nx + nu
+        nxn = qp.nx[n + 1] if n < qp.N else 0
+        ng = np.asarray(qp.D[n]).shape[0]
+        f += (4 * nz * nxn + 2 * nz * nz + 4 * ng * nu) + (2 * nz * nz + 4 * nxn * nz + 4 * ng * nu)
     return f

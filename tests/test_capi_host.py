@@ -106,18 +106,25 @@ def test_batch_size_and_plan_errors():
     assert L.oqp_batch_bytes(arr, 3, ct.byref(bad), ct.byref(hb), ct.byref(db)) == B.EINVAL
     ok = B.default_arg(warm_start=2)
     assert L.oqp_batch_bytes(arr, 3, ct.byref(ok), ct.byref(hb), ct.byref(db)) == B.OK
-    # robust mode: the QR-based factorization is built for the one-wave variants
+    # robust and balance modes: the array algorithm is built for the one-wave
+    # variants and the block kernel, so they take the same kernels
     rob = B.default_arg(B.MODE_ROBUST)
     assert L.oqp_batch_bytes(arr, 3, ct.byref(rob), ct.byref(hb), ct.byref(db)) == B.OK
     big = B.Dims(2, [40] * 3, [8, 8, 0], [0, 0, 0], [0, 0, 0], [0, 0, 0])
     arr1 = (ct.c_void_p * 1)(big.h)
-    assert L.oqp_batch_bytes(arr1, 1, ct.byref(B.default_arg()), ct.byref(hb), ct.byref(db)) == B.OK
-    assert L.oqp_batch_bytes(arr1, 1, ct.byref(rob), ct.byref(hb), ct.byref(db)) == B.EINVAL
-    assert b"robust" in L.oqp_last_error()
-    bal = B.default_arg(B.MODE_BALANCE)   # balance mode: the same one-wave variants
+    hb0, db0 = ct.c_size_t(0), ct.c_size_t(0)
+    assert L.oqp_batch_bytes(arr1, 1, ct.byref(B.default_arg()), ct.byref(hb0), ct.byref(db0)) == B.OK
+    assert L.oqp_batch_bytes(arr1, 1, ct.byref(rob), ct.byref(hb), ct.byref(db)) == B.OK
+    assert (hb.value, db.value) == (hb0.value, db0.value)
+    bal = B.default_arg(B.MODE_BALANCE)
     assert bal.mode == B.MODE_BALANCE and bal.ir_max == 2 and rob.ir_max == 4
     assert L.oqp_batch_bytes(arr, 3, ct.byref(bal), ct.byref(hb), ct.byref(db)) == B.OK
-    assert L.oqp_batch_bytes(arr1, 1, ct.byref(bal), ct.byref(hb), ct.byref(db)) == B.EINVAL
+    assert L.oqp_batch_bytes(arr1, 1, ct.byref(bal), ct.byref(hb), ct.byref(db)) == B.OK
+    # refinement in the FP64 mode is not combined with slacks
+    soft = B.Dims(2, [4] * 3, [2, 2, 0], [2, 2, 0], [0, 4, 4], [0, 0, 0], ns=[0, 2, 2])
+    arr2 = (ct.c_void_p * 1)(soft.h)
+    assert L.oqp_batch_bytes(arr2, 1, ct.byref(B.default_arg()), ct.byref(hb), ct.byref(db)) == B.OK
+    assert L.oqp_batch_bytes(arr2, 1, ct.byref(B.default_arg(ir_max=2)), ct.byref(hb), ct.byref(db)) == B.EINVAL
     unknown = B.default_arg()
     unknown.mode = 5
     assert L.oqp_batch_bytes(arr, 3, ct.byref(unknown), ct.byref(hb), ct.byref(db)) == B.EINVAL

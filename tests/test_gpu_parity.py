@@ -17,6 +17,7 @@ torch = pytest.importorskip("torch")
 from oracle import oracle as O  # noqa: E402
 from paper_2003_02547_amd import binding as B  # noqa: E402
 from paper_2003_02547_amd import workloads as W  # noqa: E402
+from oracle_pool import kkt_many, solve_many  # noqa: E402
 from dense_ref import random_interior_iterate  # noqa: E402
 
 KEYS = ("u", "x", "pi", "lam_l", "lam_u", "t_l", "t_u")
@@ -155,25 +156,60 @@ def test_solve_tiny_random_with_general_rows():
         assert primal_err(r.sol, ref.sol) <= PRIMAL_TOL
 
 
-def test_solve_chain8_full_batch_sampled():
+# Instances of the 8-mass batch whose QP is infeasible as drawn (350 is
+# certified infeasible by an LP; on 222 the oracle fails as well)
+CHAIN8_INFEASIBLE = [222, 350]
+
+
+def test_solve_chain8_full_batch_every_instance():
     """The benchmark workload (1024 instances, nx=16, nu=7, N=30) in the
-    launch configuration the benchmark times; every instance must converge,
-    sampled instances are compared with the oracle."""
+    launch configuration the benchmark times, every instance compared with
+    the oracle run with the same arguments: the same two instances fail on
+    both sides, every other one converges with a host-evaluated KKT residual
+    <= 1e-8 and an iteration count within one of the oracle's.  Two points
+    that both meet KKT 1e-8 can differ by more than 1e-6 where the problem's
+    conditioning amplifies the residual (up to ~1.5e-5 on this batch: each
+    side is that close to the exact minimiser), so the primal error against
+    the oracle is stated and held to 1e-4 here; the 1e-6 primal bar is checked
+    below at a tighter tolerance."""
     qps = [W.mass_spring_chain8(i) for i in range(1024)]
-    say("solve: chain8 x1024")
+    say("solve: chain8 x1024, every instance vs the oracle")
     b = B.Batch(qps).load().solve().fetch().sync()
     res = b.results()
-    st = np.array([r.status for r in res])
-    bad = np.flatnonzero(st != B.SUCCESS)
-    # the batch is used as drawn: a few x0 make the QP infeasible (an LP
-    # certifies it); the oracle must fail on exactly those as well
-    assert len(bad) <= 4, bad
-    for i in bad:
-        assert O.solve(qps[i]).status != O.SUCCESS, i
-    good = np.flatnonzero(st == B.SUCCESS)
-    assert max(np.max(res[i].res) for i in good) <= KKT_TOL
-    sample = [i for i in [0, 1, 17, 255, 511, 700, 1000, 1023] if i not in bad]
-    _check_solves(qps, res, sample=sample)
+    bad = [i for i, r in enumerate(res) if r.status != B.SUCCESS]
+    assert bad == CHAIN8_INFEASIBLE, bad
+    refs = solve_many(qps, range(1024), O.Arg.with_tol(KKT_TOL))
+    assert [i for i in range(1024) if refs[i].status != O.SUCCESS] == CHAIN8_INFEASIBLE
+    good = [i for i in range(1024) if i not in CHAIN8_INFEASIBLE]
+    kkt = kkt_many(qps, [r.sol for r in res], good)
+    worst = max(kkt, key=kkt.get)
+    assert kkt[worst] <= KKT_TOL + 1e-12, (worst, kkt[worst])
+    it_diff = {i: abs(refs[i].iters - res[i].iters) for i in good}
+    assert max(it_diff.values()) <= 1, max(it_diff.items(), key=lambda kv: kv[1])
+    err = {i: primal_err(res[i].sol, refs[i].sol) for i in good}
+    worst = max(err, key=err.get)
+    say(f"chain8 x1024: max primal rel err vs oracle {err[worst]:.2e} (instance {worst})")
+    assert err[worst] <= 1e-4, (worst, err[worst])
+    assert sum(e > PRIMAL_TOL for e in err.values()) <= 10
+
+
+def test_chain8_full_batch_primal_error_at_1e10():
+    """The 1e-6 primal bar against the exact minimiser: every feasible
+    instance of the batch solved to KKT 1e-10 on the GPU is within 1e-6 of the
+    oracle's solution at 1e-12 (its distance to the minimiser is far below
+    that)."""
+    qps = [W.mass_spring_chain8(i) for i in range(1024)]
+    say("solve: chain8 x1024 to 1e-10 vs the oracle at 1e-12")
+    tight = B.default_arg(tol_stat=1e-10, tol_eq=1e-10, tol_ineq=1e-10, tol_comp=1e-10)
+    res = B.solve(qps, tight)
+    good = [i for i in range(1024) if i not in CHAIN8_INFEASIBLE]
+    assert all(res[i].status == B.SUCCESS for i in good), [i for i in good if res[i].status != B.SUCCESS]
+    refs = solve_many(qps, good, O.Arg.with_tol(1e-12))
+    assert all(refs[i].status == O.SUCCESS for i in good)
+    err = {i: primal_err(res[i].sol, refs[i].sol) for i in good}
+    worst = max(err, key=err.get)
+    say(f"chain8 x1024 at 1e-10: max primal rel err vs exact {err[worst]:.2e} (instance {worst})")
+    assert err[worst] <= PRIMAL_TOL, (worst, err[worst])
 
 
 def test_batch_invariance_bitwise():
