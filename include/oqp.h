@@ -195,6 +195,25 @@ int oqp_batch_bytes(const oqp_dims* const* dims, int count, const oqp_arg* arg, 
  * smaller than oqp_batch_bytes reports.  The dims objects are copied. */
 int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_arg* arg, void* host_mem, size_t host_bytes,
                    void* dev_mem, size_t dev_bytes, void* stream, oqp_batch** out);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): oqp_batch_init
+ * without the caller's device buffer.  The batch's device records
+ * (descriptors, problem data, iterates, workspace, statuses) go to a static
+ * region of OQP_STATIC_DEV_BYTES bytes inside the library's code object, one
+ * per GPU, held until the process ends; the caller still passes the host
+ * buffer (host_bytes from oqp_batch_bytes) and the stream, and the rest of the
+ * batch calls are unchanged.  Nothing is allocated: no hipMalloc or hipFree,
+ * here or in the later calls (oqp_batch_set_streams, which creates events, is
+ * the one call to leave out).  OQP_ENOMEM, with a message naming both sizes,
+ * when the batch needs more device bytes than the region holds.  Every batch
+ * created this way on a GPU shares that GPU's region: a new one overwrites the
+ * previous one's device records, so use one at a time per GPU; calls whose
+ * work overlaps on one GPU race.  The region keeps what the last batch left;
+ * the batch writes every record it reads before reading it, as with a caller
+ * buffer. */
+#define OQP_STATIC_DEV_BYTES (128u << 20)
+int oqp_batch_init_static(const oqp_dims* const* dims, int count, const oqp_arg* arg, void* host_mem,
+                          size_t host_bytes, void* stream, oqp_batch** out);
 /* Pack the QPs (one per instance, dims matching) into the device layout and
  * enqueue the host-to-device copy.  Asynchronous on the batch stream; the host
  * buffer must stay untouched until oqp_batch_sync. */

@@ -98,6 +98,8 @@ def lib():
         "oqp_pcond_dims": (ct.c_int, [_V, ct.c_int, _V, ct.c_size_t, ct.POINTER(_V)]),
         "oqp_batch_fetch_cond": (ct.c_int, [_V]),
         "oqp_batch_set_streams": (ct.c_int, [_V, ct.POINTER(_V), ct.c_int]),
+        "oqp_batch_init_static": (ct.c_int, [ct.POINTER(_V), ct.c_int, ct.POINTER(Arg), _V, ct.c_size_t, _V,
+                                             ct.POINTER(_V)]),
         "oqp_batch_release": (ct.c_int, [_V]),
         "oqp_batch_get_cond_qp": (ct.c_int, [_V, ct.c_int, _V]),
         "oqp_arg_default": (None, [ct.POINTER(Arg), ct.c_int]),
@@ -300,7 +302,11 @@ def _sizes(qp):
 class Batch:
     """A batch of OCP QPs solved on the current CUDA (HIP) device and stream."""
 
-    def __init__(self, qps: Sequence, arg: Arg | None = None, device=None, stream=None, streams: int = 0):
+    def __init__(self, qps: Sequence, arg: Arg | None = None, device=None, stream=None, streams: int = 0,
+                 static: bool = False):
+        """static=True: the batch's device records go to the library's static
+        device region (oqp_batch_init_static) instead of a device buffer
+        allocated here; one such batch at a time per GPU, no extra streams."""
         import torch
         L = lib()
         self.qps = list(qps)
@@ -315,11 +321,19 @@ class Batch:
         dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         h = _V()
-        self.dev_buf = torch.empty(self.dev_bytes + 256, dtype=torch.uint8, device=dev)
-        base = self.dev_buf.data_ptr()
-        self.dev_ptr = base + ((-base) % 256)
-        _check(L.oqp_batch_init(self._dimh, n, ct.byref(self.arg), self.host.ctypes.data, self.host_bytes,
-                                self.dev_ptr, self.dev_bytes, self.stream.cuda_stream, ct.byref(h)))
+        if static:
+            if streams:
+                raise ValueError("a batch in the static device region takes no extra streams")
+            self.dev_buf, self.dev_ptr = None, None
+            with torch.cuda.device(dev):
+                _check(L.oqp_batch_init_static(self._dimh, n, ct.byref(self.arg), self.host.ctypes.data,
+                                               self.host_bytes, self.stream.cuda_stream, ct.byref(h)))
+        else:
+            self.dev_buf = torch.empty(self.dev_bytes + 256, dtype=torch.uint8, device=dev)
+            base = self.dev_buf.data_ptr()
+            self.dev_ptr = base + ((-base) % 256)
+            _check(L.oqp_batch_init(self._dimh, n, ct.byref(self.arg), self.host.ctypes.data, self.host_bytes,
+                                    self.dev_ptr, self.dev_bytes, self.stream.cuda_stream, ct.byref(h)))
         self.h = h
         self._qph = None
         self.aux = []
@@ -698,5 +712,5 @@ EXPORTED = [
     "oqp_pcond_dims_bytes", "oqp_pcond_dims", "oqp_batch_fetch_cond", "oqp_batch_get_cond_qp",
     "oqp_batch_set_streams", "oqp_batch_release", "oqp_dims_set_soft", "oqp_qp_set_soft", "oqp_qp_get_soft",
     "oqp_batch_get_soft_sol", "oqp_batch_set_soft_iterate", "oqp_batch_get_soft_step", "oqp_batch_nsoft",
-    "oqp_server_get_soft_sol",
+    "oqp_server_get_soft_sol", "oqp_batch_init_static",
 ] + ["oqp_sol_get_" + g for g in SOL_FIELDS]

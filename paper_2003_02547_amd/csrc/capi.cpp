@@ -1134,6 +1134,25 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
     return OQP_OK;
 }
 
+extern "C" int oqp_batch_init_static(const oqp_dims* const* dims, int count, const oqp_arg* arg, void* host_mem,
+                                     size_t host_bytes, void* stream, oqp_batch** out)
+{
+    int rc = check_arg(arg);
+    if (rc) return rc;
+    if (!host_mem || !out) return fail(OQP_EINVAL, "oqp_batch_init_static: NULL argument");
+    Plan pl;
+    rc = make_plan(dims, count, arg, &pl);
+    if (rc) return rc;
+    void* region = nullptr;
+    size_t cap = 0;
+    rc = static_dev_region(&region, &cap);
+    if (rc) return rc;
+    if (pl.dev_bytes > cap)
+        return fail(OQP_ENOMEM, "oqp_batch_init_static: the batch needs %zu device bytes, the static region holds %zu",
+                    pl.dev_bytes, cap);
+    return oqp_batch_init(dims, count, arg, host_mem, host_bytes, region, cap, stream, out);
+}
+
 static inline const int* inst_dims(const oqp_batch* b, const Inst& in, int which)
 {
     return b->dims_pool + in.dims_off + which * (in.oN + 1);

@@ -69,6 +69,9 @@ bool batch_dims_match(const oqp_batch* b, int i, const oqp_dims* dims);
 bool server_dims_match(const oqp_server* s, uint64_t ticket, const oqp_dims* dims);
 
 int fail(int code, const char* fmt, ...);
+// this device's copy of the library's static device region (scratch.hip):
+// its device address and size
+int static_dev_region(void** ptr, size_t* bytes);
 size_t align_up(size_t v, size_t a);
 int check_arg(const oqp_arg* a);
 int pick_variant(const oqp_dims* d);
