@@ -128,6 +128,8 @@ def host_check(qps, refs, runs, large, large_picks):
     instance when the sample covers the batch); for the large-stage batch on
     a few instances solved by the oracle here (FP64 with refinement, 1e-8)."""
     import concurrent.futures as cf
+
+    import numpy as np
     from oracle import oracle as O
 
     threads = max(1, min(16, os.cpu_count() or 1))
@@ -482,7 +484,8 @@ def leg_large(B, W, torch, np, perfmodel, count, steps):
     return out, qps, keep
 
 
-def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_seconds, per_req_seconds, log):
+def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_seconds, per_req_seconds, log,
+              iter_block=4):
     """Continuous-batching server, native real-time replay of Poisson
     arrivals over a pool of pre-packed uneven instances (page-locked host
     memory; each request's data is uploaded on admission); also the same
@@ -494,10 +497,10 @@ def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_secon
     dev_bytes = int(min(64 << 30, 2 * sum(p.footprint for p in packed_soft) + (1 << 30)))
     tol = dict(tol_stat=KKT_OK, tol_eq=KKT_OK, tol_ineq=KKT_OK, tol_comp=KKT_OK)
 
-    def run(mode, max_launch, rate, seconds, seed, pk=None):
+    def run(mode, max_launch, rate, seconds, seed, pk=None, iter_block=0):
         pk = packed if pk is None else pk
         srv = B.Server(B.default_arg(mode, **tol), dev_bytes=dev_bytes, nstreams=5, max_launch=max_launch,
-                       max_requests=4096, max_groups=1024)
+                       max_requests=4096, max_groups=1024, iter_block=iter_block)
         try:
             times, idx = W.serving_stream(rate, seconds, pool_n, seed=seed)
             lat, stats, wall = srv.replay([pk[i] for i in idx], times, timeout=120.0)
@@ -515,9 +518,16 @@ def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_secon
     sat = run(B.MODE_F64, 256, offered, sat_seconds, 2)
     rate = max(10.0, round(sus_frac * sat["served_per_s"], -1))
     out = {"pool": pool_n, "saturated_f64": sat, "sustained_rate_per_s": rate}
+    # iteration blocks: launches of at most `iter_block` IPM iterations, new
+    # arrivals join unfinished requests at the block boundaries
+    log(f"bench: serve saturation with iteration blocks of {iter_block}")
+    out["iter_block"] = iter_block
+    out["saturated_f64_blocks"] = run(B.MODE_F64, 256, offered, sat_seconds, 2, iter_block=iter_block)
     for name, mode, ml in (("f64", B.MODE_F64, 256), ("mixed", B.MODE_MIXED, 256)):
         log(f"bench: serve {name} at {rate:.0f} req/s for {sus_seconds:.0f} s")
         out[name] = run(mode, ml, rate, sus_seconds, 3)
+    log(f"bench: serve f64 with iteration blocks at {rate:.0f} req/s for {sus_seconds:.0f} s")
+    out["f64_blocks"] = run(B.MODE_F64, 256, rate, sus_seconds, 3, iter_block=iter_block)
     log(f"bench: serve f64 with soft state boxes (first x0 draws) at {rate:.0f} req/s for {sus_seconds:.0f} s")
     out["f64_soft"] = run(B.MODE_F64, 256, rate, sus_seconds, 3, packed_soft)
     # plain per-request FP64 path (one launch per request): same offered rate
@@ -556,6 +566,8 @@ def main():
     ap.add_argument("--serve-frac", type=float, default=0.5, help="sustained rate as a fraction of saturated throughput")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-per-request-seconds", type=float, default=0.2)
+    ap.add_argument("--serve-iter-block", type=int, default=4,
+                    help="IPM iterations per launch in the iteration-block serving runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -706,7 +718,8 @@ def main():
         large = (lq, lres)
     if args.serve_pool > 0:
         line["serve"] = leg_serve(B, W, torch, np, args.serve_pool, args.serve_rate, args.serve_sat_seconds,
-                                  args.serve_frac, args.serve_seconds, args.serve_per_request_seconds, log)
+                                  args.serve_frac, args.serve_seconds, args.serve_per_request_seconds, log,
+                                  args.serve_iter_block)
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         line["cpu_baseline"], refs = cpu_baseline(qps, args.cpu_seconds, 1e-8, W.mass_spring_chain4(1))

@@ -396,6 +396,11 @@ typedef struct {
     int max_launch;       /* requests per kernel launch (1 = one launch per request) */
     int max_groups;       /* launches in flight at once */
     size_t staging_bytes; /* host staging for oqp_server_get_sol: the largest padded iterate */
+    int iter_block;       /* 0: each launch solves its requests to the end; K > 0 (FP64 mode): each
+                             launch runs at most K IPM iterations, and a request that needs more
+                             is queued again (ahead of new arrivals) and continues from its
+                             device-resident iterate in a later launch, so arrivals join at
+                             iteration-block boundaries; results are bitwise the same */
 } oqp_server_cfg;
 
 typedef struct {
@@ -463,6 +468,17 @@ int oqp_server_replay(oqp_server* server, const void* const* packed, const doubl
  * wide and applies to batches and packed requests created after the call. */
 int oqp_set_wave_max(int nz); /* 0..64; 0 sends every instance to the block kernel */
 int oqp_get_wave_max(void);
+/* Variants allowed (bit v for variant v, all by default): an instance whose
+ * cheapest covering variant is masked out goes to the block kernel.  Process
+ * wide, like the wave bound (the schedule autotuner sets it per kernel
+ * group). */
+int oqp_set_variant_mask(unsigned mask);
+unsigned oqp_get_variant_mask(void);
+/* Batches launch a block-kernel group's instances that need more than half a
+ * CU's LDS apart from the rest, so the rest can share CUs two by two (1, the
+ * default), or every group in one launch (0).  OQP_EINVAL for other values. */
+int oqp_set_lds_split(int on);
+int oqp_get_lds_split(void);
 /* Kernel group of instance i (a variant index < oqp_variant_count(), or a
  * block-kernel build at or above it) and its padded stage sizes. */
 int oqp_batch_variant(const oqp_batch* batch, int i, int* nx_pad, int* nu_pad, int* ng_pad);

@@ -47,7 +47,7 @@ class Stat(ct.Structure):
 
 class ServerCfg(ct.Structure):
     _fields_ = [("max_requests", ct.c_int), ("max_launch", ct.c_int), ("max_groups", ct.c_int),
-                ("staging_bytes", ct.c_size_t)]
+                ("staging_bytes", ct.c_size_t), ("iter_block", ct.c_int)]
 
 
 class Counters(ct.Structure):
@@ -100,6 +100,10 @@ def lib():
         "oqp_batch_set_streams": (ct.c_int, [_V, ct.POINTER(_V), ct.c_int]),
         "oqp_batch_init_static": (ct.c_int, [ct.POINTER(_V), ct.c_int, ct.POINTER(Arg), _V, ct.c_size_t, _V,
                                              ct.POINTER(_V)]),
+        "oqp_set_variant_mask": (ct.c_int, [ct.c_uint]),
+        "oqp_get_variant_mask": (ct.c_uint, []),
+        "oqp_set_lds_split": (ct.c_int, [ct.c_int]),
+        "oqp_get_lds_split": (ct.c_int, []),
         "oqp_batch_release": (ct.c_int, [_V]),
         "oqp_batch_get_cond_qp": (ct.c_int, [_V, ct.c_int, _V]),
         "oqp_arg_default": (None, [ct.POINTER(Arg), ct.c_int]),
@@ -712,5 +716,6 @@ EXPORTED = [
     "oqp_pcond_dims_bytes", "oqp_pcond_dims", "oqp_batch_fetch_cond", "oqp_batch_get_cond_qp",
     "oqp_batch_set_streams", "oqp_batch_release", "oqp_dims_set_soft", "oqp_qp_set_soft", "oqp_qp_get_soft",
     "oqp_batch_get_soft_sol", "oqp_batch_set_soft_iterate", "oqp_batch_get_soft_step", "oqp_batch_nsoft",
-    "oqp_server_get_soft_sol", "oqp_batch_init_static",
+    "oqp_server_get_soft_sol", "oqp_batch_init_static", "oqp_set_variant_mask", "oqp_get_variant_mask",
+    "oqp_set_lds_split", "oqp_get_lds_split",
 ] + ["oqp_sol_get_" + g for g in SOL_FIELDS]

@@ -592,6 +592,12 @@ int pick_variant(const oqp_dims* d)
 // 7.6k -> 7.0k/s), so they are used when the bound is raised
 // (oqp_set_wave_max, or the autotuner on same-size batches)
 static int g_wave_max_nz = 24;
+// one-wave variants allowed (bit v: variant v); the others' instances go to
+// the block kernel (set by the schedule autotuner per kernel group)
+static unsigned g_variant_mask = ~0u;
+// batches launch the block-group instances needing more than half a CU's LDS
+// apart from the rest (off: one launch per group)
+static int g_lds_split = 1;
 static const int kBlockZ[6] = {32, 32, 64, 64, 256, 256};
 static const int kBlockG[6] = {0, 64, 0, 64, 0, 64};
 static constexpr size_t kMaxLds = 160 * 1024;
@@ -617,7 +623,7 @@ static int select_kernel_max(int mx, int mu, int mg, KSel* out)
     if (v >= 0) {
         int nx, nu, ng;
         oqp::variant_dims(v, &nx, &nu, &ng);
-        if (nx + nu <= g_wave_max_nz) {
+        if (nx + nu <= g_wave_max_nz && ((g_variant_mask >> v) & 1u)) {
             *out = KSel{v, nx, nu, ng};
             return OQP_OK;
         }
@@ -758,6 +764,23 @@ extern "C" int oqp_set_wave_max(int nz)
 
 extern "C" int oqp_get_wave_max(void) { return g_wave_max_nz; }
 
+extern "C" int oqp_set_variant_mask(unsigned mask)
+{
+    g_variant_mask = mask;
+    return OQP_OK;
+}
+
+extern "C" unsigned oqp_get_variant_mask(void) { return g_variant_mask; }
+
+extern "C" int oqp_set_lds_split(int on)
+{
+    if (on != 0 && on != 1) return fail(OQP_EINVAL, "oqp_set_lds_split: 0 or 1");
+    g_lds_split = on;
+    return OQP_OK;
+}
+
+extern "C" int oqp_get_lds_split(void) { return g_lds_split; }
+
 // A block-kernel instance whose LDS block exceeds half of a CU's LDS keeps
 // the CU to itself; the others can share it two by two.
 static constexpr size_t kLdsHalf = kMaxLds / 2;
@@ -781,7 +804,7 @@ int group_launch(int g, int km, const InstDesc* desc, const InstDesc* hdesc, int
     const int nv = oqp::variant_count();
     if (g < nv) return oqp::variant_launch(g, km, desc, count, data, iter, work, step, stat, P, stream);
     int split = 0;
-    while (split_lds && split < count && lds_big(hdesc[split])) ++split;
+    while (split_lds && g_lds_split && split < count && lds_big(hdesc[split])) ++split;
     if (split == count) split = 0;
     const int parts[3] = {0, split, count};
     for (int p = split > 0 ? 0 : 1; p < 2; ++p) {
@@ -1075,11 +1098,11 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
             ds.N = in.N;
             ds.nc = in.nc + in.nsoft;  // one-sided rows / 2: constraint rows and slack bounds
             ds.index = i;
-            ds.pad = 0;
+            ds.resume = 0;
             ds.nx = in.nx;
             ds.nu = in.nu;
             ds.ng = in.ng;
-            ds.pad2 = 0;
+            ds.itcap = 0;
         }
     }
     // original records: the solved ones, or (condensing) regions of their own
@@ -1364,6 +1387,7 @@ static int launch_all(oqp_batch* b, const oqp::KParams& P)
             // FP64 kernels pick up the instances the mixed kernels handed over
             // (from a cold start)
             Pp.mode = oqp::KMODE_FALLBACK;
+            Pp.ir_max = 0;  // the fallback is the plain FP64 path (no refinement)
             Pp.warm = 0;
         }
         for (int k = 0; k < b->nvar; ++k) {

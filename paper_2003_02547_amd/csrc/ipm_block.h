@@ -36,7 +36,13 @@ constexpr int BGMAX = 64;  // general rows per stage supported by the block kern
 // LDS plan (offsets in doubles) for padded stage sizes NX, NU, NG.
 struct BLds {
     int ldm, ldf, ldg, ldx, ldv;  // odd leading dimensions: column-strided access spreads over the banks
-    int oM, oF, oG, oLx, oV, oz, orb, ot1, ot2, oe, ows, oxn, opin, opn, odv, odd, ol11, ocol, ored, oflag, total;
+    int oM, oF, oG, oLx, oV, oz, orb, ot1, ot2, oe, ows, oxn, opin, opn, odv, odd, ol11, ocol, ored, oflag;
+    // global-memory mode, stage matrix held in registers (stage blocks up to
+    // 160): a panel of 16 rows of V, the column panel of the factor below the
+    // diagonal tile, the diagonal tile, and one chunk (16 rows) of L_{n+1} and
+    // F that the V panel is built from
+    int ldu, oUp, oPn, oDg, oCA, oCB;
+    int total;
 };
 
 OQP_HD constexpr int bmaxi(int a, int b) { return a > b ? a : b; }
@@ -80,6 +86,13 @@ OQP_HD constexpr BLds make_blds(int NX, int NU, int NG)
     s.ocol = o; o += 64;
     s.ored = o; o += 32;
     s.oflag = o; o += 2;
+    s.ldu = NZ | 1;
+    const bool tiles = gl && NZ <= 160;
+    s.oUp = o; o += tiles ? 16 * s.ldu : 0;
+    s.oPn = o; o += tiles ? NZ * 17 : 0;
+    s.oDg = o; o += tiles ? 16 * 17 : 0;
+    s.oCA = o; o += tiles ? 16 * 17 : 0;
+    s.oCB = o; o += tiles ? 16 * s.ldu : 0;
     s.total = o;
     return s;
 }
@@ -144,6 +157,7 @@ struct Blk {
     mutable const double* cLx;
     mutable const double* cXC;
     mutable double* cV;
+    mutable const double* cH;  // global-memory mode: H of the current stage (data record)
 
     __device__ __forceinline__ Blk(const InstDesc& ds, const double* d, double* i, double* w, const KParams& P_)
         : Lo(make_layout(ds.nx, ds.nu, ds.ng, SOFT)), S(make_blds(ds.nx, ds.nu, ds.ng)), NX(ds.nx), NU(ds.nu), NG(ds.ng),
@@ -165,7 +179,7 @@ struct Blk {
             ldv = S.ldv;
         }
         cM = cV = nullptr;
-        cF = cG = cLx = cXC = nullptr;
+        cF = cG = cLx = cXC = cH = nullptr;
     }
 
     __device__ __forceinline__ const double* Dp(int n) const { return dat + (size_t)n * Lo.SREC; }
@@ -393,7 +407,7 @@ struct Blk {
     // in first; the factor then stays there) with L_{n+1} read from the next
     // stage's record; pass R reads H in place; passes B and C read the u
     // columns of this stage's factor and the x columns of the next one's.
-    __device__ __forceinline__ void stage_A(int n) const
+    __device__ __forceinline__ void stage_A(int n, bool qr) const
     {
         if constexpr (GL) {
             const double* d = Dp(n);
@@ -402,8 +416,11 @@ struct Blk {
             cG = d + Lo.D_G;
             cLx = n < N ? Wp(n + 1) + Lo.W_L + NU + NU * NZ : cM;
             cV = Wp(n) + Lo.W_V;
-            const double* h = d + Lo.D_H;
-            for (int e = opq(tid); e < NZ * NZ; e += BT) cM[e] = h[e];
+            cH = d + Lo.D_H;
+            // the stage matrix is built in the factor record, from a copy of H,
+            // unless it is held in registers
+            if (!use_tiles(qr))
+                for (int e = opq(tid); e < NZ * NZ; e += BT) cM[e] = cH[e];
         }
     }
     __device__ __forceinline__ void stage_R(int n) const
@@ -802,6 +819,314 @@ struct Blk {
         __syncthreads();
     }
 
+    // ------------------------------------------------------------------
+    // Global-memory mode with the stage matrix in registers (stage blocks up
+    // to 160, FP64 and mixed builds): the lower 16 x 16 tiles of
+    // M = Phi + V'V are matrix-core accumulators spread over the four waves
+    // (tile t in row-major lower order belongs to wave t mod 4), so the
+    // products and the Cholesky factorization never go through global memory
+    // until the factor itself is written out.
+    //   * M starts as H (read from the data record) plus the box weights;
+    //   * V is formed 16 rows at a time in LDS: rows of U = L_{n+1}' F from
+    //     chunks of 16 rows of L_{n+1} and F staged in LDS (the next chunk's
+    //     loads in flight while the current one is multiplied), then the rows
+    //     sqrt(w) G; each panel updates every tile of M (M += Vp' Vp);
+    //   * right-looking Cholesky by 16-column panels: the diagonal tile is
+    //     factored on wave 0 (one row per lane), the tiles below it are
+    //     solved against it one row per thread in LDS, the panel column is
+    //     written to the stage's factor record, and the trailing tiles are
+    //     updated on the matrix cores from that LDS panel.
+    // Mixed path: FP32 operands and accumulators, the running diagonal of
+    // every row in FP64 (the pivots) as in the other factorizations.
+    // ------------------------------------------------------------------
+    static constexpr int RT = 14;  // tiles per wave: 4 x 14 >= 55, the lower tiles of a 160-wide block
+    static constexpr bool TILES = GL && !ROBUST;
+    using V4 = TS __attribute__((ext_vector_type(4)));
+
+    __device__ __forceinline__ static V4 mfma4(TS a, TS b, V4 c)
+    {
+        if constexpr (MIXED)
+            return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+        else
+            return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // tile row of accumulator register r of this lane (column: lane % 16)
+    __device__ __forceinline__ int arow(int r) const { return MIXED ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4); }
+    // (balance build: not in an iteration factored with the array
+    // algorithm, which needs V in the stage's workspace block)
+    __device__ __forceinline__ bool use_tiles(bool qr) const { return TILES && NZ <= 160 && !(BALANCE && qr); }
+
+    // Factor the stage matrix of stage n (n < N: with the rows of U; NG > 0:
+    // with the rows sqrt(w) G) into the factor record cM; 1/L_ii to dv.
+    // Returns false (in every thread) when a pivot is not positive.
+    __device__ __forceinline__ bool factor_tiles(int n, const double* hd) const
+    {
+        const int TMt = (NZ + 15) >> 4, NTt = TMt * (TMt + 1) / 2;
+        const int l16 = lane & 15, lk = lane >> 4;
+        const int ldu = S.ldu;
+        double* up = blds() + S.oUp;  // Vp[k][j], k < 16, ld ldu
+        double* lp = blds() + S.oPn;  // panel column below the diagonal tile: [row][q], ld 17
+        double* dg = blds() + S.oDg;  // diagonal tile [row][q], ld 17
+        double* ca = blds() + S.oCA;  // chunk of L_{n+1}: [k][i], k < 16, ld 17
+        double* cb = blds() + S.oCB;  // chunk of F: [k][j], k < 16, ld ldu
+        double* dd = ddv();           // running FP64 diagonal (mixed path)
+        const double* wv = wsv();
+        V4 acc[RT];
+        // tiles of this wave (wave-uniform: scalar registers)
+        const int w0 = __builtin_amdgcn_readfirstlane(wid);
+        int tI[RT], tJ[RT];
+#pragma unroll
+        for (int s = 0; s < RT; ++s) {
+            const int t = w0 + 4 * s;
+            int ti = 0;
+            while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+            tI[s] = t < NTt ? ti : -1;
+            tJ[s] = t < NTt ? t - ti * (ti + 1) / 2 : -1;
+        }
+        // ---- M = H + diag(box weights) + reg I ----
+#pragma unroll
+        for (int s = 0; s < RT; ++s) {
+            const int t = w0 + 4 * s;
+            const int ti = tI[s], tj = tJ[s];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * ti + arow(r), c = 16 * tj + l16;
+                double v = 0.0;
+                if (t < NTt) {
+                    if (row < NZ && c < NZ) v = hd[row + c * NZ];
+                    if (row == c) v += row < NZ ? wv[row] + P.reg_prim : 1.0;
+                }
+                acc[s][r] = (TS)v;
+            }
+        }
+        if constexpr (MIXED) {
+            // FP64 running diagonal (the pivots): M_ii in FP64, the squares of
+            // V's columns added panel by panel below
+            for (int i = opq(tid); i < NZ; i += BT) dd[i] = hd[i + i * NZ] + wv[i] + P.reg_prim;
+        }
+        // ---- M += V'V, 16 rows of V at a time ----
+        const int npu = n < N ? (NX + 15) >> 4 : 0, npg = (NG + 15) >> 4;
+        constexpr int KC = 16;                         // rows of L_{n+1} and F per chunk
+        constexpr int CA = 16 * KC / BT;               // L_{n+1} chunk elements per thread
+        constexpr int CB = (KC * 160 + BT - 1) / BT;  // F chunk elements per thread
+        for (int pnl = 0; pnl < npu + npg; ++pnl) {
+            if (pnl < npu) {
+                // U rows 16 pnl ..: U(r, j) = sum_{l >= r} L(l, r) F(l, j); output
+                // tile columns jt = wid, wid + 4, wid + 8 of the panel
+                V4 ua[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) ua[q] = V4{0, 0, 0, 0};
+                const int l_first = 16 * pnl;
+                const int nch = (NX - l_first + KC - 1) / KC;
+                double pa[CA], pb[CB];
+                // element idx of a chunk: row kk = idx mod KC (contiguous in
+                // the column-major records), column idx / KC
+                auto fetch_chunk = [&](int l0) {
+#pragma unroll
+                    for (int e = 0; e < CA; ++e) {
+                        const int idx = tid + BT * e;
+                        const int kk = idx % KC, i = idx / KC;
+                        const int l = l0 + kk;
+                        pa[e] = (l < NX && l_first + i < NX) ? cLx[l + (l_first + i) * ldx] : 0.0;
+                    }
+#pragma unroll
+                    for (int e = 0; e < CB; ++e) {
+                        const int idx = tid + BT * e;
+                        const int kk = idx % KC, j = idx / KC;
+                        const int l = l0 + kk;
+                        pb[e] = (j < NZ && l < NX) ? cF[l + j * ldf] : 0.0;
+                    }
+                };
+                fetch_chunk(l_first);
+                for (int c = 0; c < nch; ++c) {
+                    __syncthreads();  // the previous chunk has been read
+#pragma unroll
+                    for (int e = 0; e < CA; ++e) {
+                        const int idx = tid + BT * e;
+                        ca[(idx % KC) * 17 + idx / KC] = pa[e];
+                    }
+#pragma unroll
+                    for (int e = 0; e < CB; ++e) {
+                        const int idx = tid + BT * e;
+                        const int kk = idx % KC, j = idx / KC;
+                        if (j < NZ) cb[kk * ldu + j] = pb[e];
+                    }
+                    __syncthreads();
+                    if (c + 1 < nch) fetch_chunk(l_first + KC * (c + 1));
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const int jt = w0 + 4 * q;
+                        if (jt < TMt) {
+                            const int j = min(16 * jt + l16, NZ - 1);
+#pragma unroll
+                            for (int k4 = 0; k4 < KC / 4; ++k4) {
+                                const int kk = 4 * k4 + lk;
+                                const TS a = (TS)ca[kk * 17 + l16];
+                                const TS b = (16 * jt + l16 < NZ) ? (TS)cb[kk * ldu + j] : (TS)0;
+                                ua[q] = mfma4(a, b, ua[q]);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();  // the previous panel's products are done with up
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int jt = w0 + 4 * q;
+                    if (jt < TMt) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int j = 16 * jt + l16;
+                            if (j < NZ) up[arow(r) * ldu + j] = (double)ua[q][r];
+                        }
+                    }
+                }
+            } else {
+                // rows sqrt(w) G of general rows 16 (pnl - npu) ..
+                const int g0 = 16 * (pnl - npu);
+                __syncthreads();
+                for (int e = tid; e < 16 * NZ; e += BT) {
+                    const int kk = e / NZ, j = e % NZ, g = g0 + kk;
+                    up[kk * ldu + j] = g < NG ? sqrt(wv[NZ + g]) * cG[g + j * ldg] : 0.0;
+                }
+            }
+            __syncthreads();
+            if constexpr (MIXED) {
+                for (int i = opq(tid); i < NZ; i += BT) {
+                    double sq = 0.0;
+#pragma unroll
+                    for (int kk = 0; kk < 16; ++kk) sq += up[kk * ldu + i] * up[kk * ldu + i];
+                    dd[i] += sq;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < RT; ++s) {
+                if (tI[s] >= 0) {
+                    const int ti = tI[s], tj = tJ[s];
+                    const int i = min(16 * ti + l16, NZ - 1), j = min(16 * tj + l16, NZ - 1);
+                    const bool iv = 16 * ti + l16 < NZ, jv = 16 * tj + l16 < NZ;
+#pragma unroll
+                    for (int k4 = 0; k4 < 4; ++k4) {
+                        const int kk = 4 * k4 + lk;
+                        const TS a = iv ? (TS)up[kk * ldu + i] : (TS)0;
+                        const TS b = jv ? (TS)up[kk * ldu + j] : (TS)0;
+                        acc[s] = mfma4(a, b, acc[s]);
+                    }
+                }
+            }
+        }
+        // ---- Cholesky by 16-column panels ----
+        bool ok = true;
+        double* fm = cM;
+        for (int p = 0; p < TMt; ++p) {
+            __syncthreads();  // the previous panel's trailing products are done with dg / pn
+            // the tiles of column p to LDS
+#pragma unroll
+            for (int s = 0; s < RT; ++s) {
+                if (tI[s] >= 0) {
+                    const int ti = tI[s], tj = tJ[s];
+                    if (tj == p) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int rr = arow(r);
+                            if (ti == p) dg[rr * 17 + l16] = (double)acc[s][r];
+                            else if (16 * ti + rr < NZ) lp[(16 * ti + rr) * 17 + l16] = (double)acc[s][r];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const int p0 = 16 * p, pw = min(16, NZ - p0);
+            // diagonal tile on wave 0: lane q holds row p0 + q
+            if (wid == 0) {
+                double r[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) r[q] = (lane < 16) ? dg[lane * 17 + q] : 0.0;
+                double d = (MIXED && lane < pw) ? dd[p0 + lane] : 1.0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    if (q >= pw) continue;
+                    const double piv = MIXED ? bcast(d, q) : bcast(r[q], q);
+                    ok = ok && (piv > 0.0);
+                    const double inv = rsqrt_nr(piv);
+                    const double lij = MIXED ? rnd(r[q] * inv) : r[q] * inv;
+                    if (lane == q) {
+                        dv()[p0 + q] = inv;
+                        r[q] = piv * inv;
+                    } else if (lane > q) {
+                        r[q] = lij;
+                        if constexpr (MIXED) d -= lij * lij;
+                    } else {
+                        r[q] = 0.0;
+                    }
+#pragma unroll
+                    for (int q2 = q + 1; q2 < 16; ++q2)
+                        if (q2 < pw) r[q2] = (double)((TS)r[q2] - (TS)lij * (TS)bcast(lij, q2));
+                }
+                if (lane < 16) {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) dg[lane * 17 + q] = r[q];
+                }
+            }
+            __syncthreads();
+            // rows below: L21 = M21 L11^{-T}, one row per thread
+            for (int i = p0 + 16 + opq(tid); i < NZ; i += BT) {
+                double r[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) r[q] = MIXED ? rnd(lp[i * 17 + q]) : lp[i * 17 + q];
+                double d = MIXED ? dd[i] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    if (q >= pw) continue;
+                    TS a = (TS)r[q];
+#pragma unroll
+                    for (int c = 0; c < q; ++c) a -= (TS)r[c] * (TS)dg[q * 17 + c];
+                    r[q] = MIXED ? rnd((double)a * dv()[p0 + q]) : (double)a * dv()[p0 + q];
+                    if constexpr (MIXED) d -= r[q] * r[q];
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) lp[i * 17 + q] = r[q];
+                if constexpr (MIXED) dd[i] = d;
+            }
+            __syncthreads();
+            // panel column to the factor record (zeros above the diagonal tile)
+            for (int i = opq(tid); i < NZ; i += BT) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    if (q >= pw) continue;
+                    double v = 0.0;
+                    if (i >= p0 + 16) v = lp[i * 17 + q];
+                    else if (i >= p0 && i - p0 >= q) v = dg[(i - p0) * 17 + q];
+                    fm[i + (p0 + q) * NZ] = v;
+                }
+            }
+            // trailing tiles (i, j), p < j <= i: M_ij -= L_ip L_jp'
+#pragma unroll
+            for (int s = 0; s < RT; ++s) {
+                if (tI[s] >= 0) {
+                    const int ti = tI[s], tj = tJ[s];
+                    if (tj > p) {
+                        const int i = 16 * ti + l16, j = 16 * tj + l16;
+                        const bool iv = i < NZ, jv = j < NZ;
+#pragma unroll
+                        for (int k4 = 0; k4 < 4; ++k4) {
+                            const int kk = 4 * k4 + lk;
+                            const TS a = iv ? -(TS)lp[i * 17 + kk] : (TS)0;
+                            const TS b = jv ? (TS)lp[j * 17 + kk] : (TS)0;
+                            acc[s] = mfma4(a, b, acc[s]);
+                        }
+                    }
+                }
+            }
+        }
+        if (wid == 0 && lane == 0) flag()[0] = 1.0;
+        __syncthreads();
+        if (wid == 0 && !ok && lane == 0) flag()[0] = 0.0;
+        __syncthreads();
+        const bool res = flag()[0] != 0.0;
+        __syncthreads();
+        return res;
+    }
+
     // Forward substitution with the (u, u) block of the factor in M (u
     // columns): wave 0 solves y = L_uu^{-1} m_u (rows j < NU, one per lane,
     // di = 1/L_jj), then every thread of rows NU <= i < NZ forms
@@ -891,7 +1216,7 @@ struct Blk {
         for (int n = N; n >= 0; --n) {
             const int cur = n & 1, nxt = cur ^ 1;
             commit(pre, M(), F(), G());
-            stage_A(n);
+            stage_A(n, qr);
             const double* d = Dp(n);
             double* ir = Ip(n);
             double* w = Wp(n);
@@ -967,7 +1292,7 @@ struct Blk {
             if (absf) {
                 if (j < NZ) rg = g;
             } else if (j < NZ) {
-                const double* mh = M();
+                const double* mh = use_tiles(qr) ? cH : M();
                 const double* zv = z();
                 double acc = g + dot<double>(mh + j, ldm, zv, 1, NZ);
                 if (n < N) acc += dot<double>(F() + j * ldf, 1, pin(nxt), 1, NX);
@@ -1079,7 +1404,9 @@ struct Blk {
             if (n < N && j < NX) w[Lo.W_rb + j] = rb;
             __syncthreads();
 
-            if (factor) {
+            if (factor && use_tiles(qr)) {
+                fact_ok = factor_tiles(n, cH) && fact_ok;
+            } else if (factor) {
                 // Phi = H + diag(box weights) + reg I ; V = [L_{n+1}' F ; sqrt(w_g) G]
                 if (j < NZ) M()[j + j * ldm] += wsv()[j] + P.reg_prim;
                 {
@@ -1103,6 +1430,8 @@ struct Blk {
                 }
                 fact_ok = cholesky() && fact_ok;
                 if (arr && (n < N || NG > 0)) qr_update(n < N ? 0 : NX);
+            }
+            if (factor) {
 
                 // reduced gradient and cost-to-go terms
                 double mv = 0.0;
@@ -1641,9 +1970,8 @@ struct Blk {
     // Initial point (P.warm), as in the one-wave kernel: cold start, primal
     // guess (y kept, the rest as in the cold start at that y), or primal and
     // dual guess (kept, multipliers and slacks clamped below).
-    __device__ __forceinline__ void init() const
+    __device__ __forceinline__ void init(int warm) const
     {
-        const int warm = P.warm;
         if (warm == 0)
             for (int e = tid; e < (N + 1) * NZ; e += BT) Ip(e / NZ)[Lo.I_z + e % NZ] = 0.0;
         if (warm != 2)
@@ -1742,11 +2070,16 @@ struct Blk {
     // ------------------------------------------------------------------
     // Driver (same iteration logic as the one-wave kernel).
     // ------------------------------------------------------------------
-    __device__ __forceinline__ void run(DevStat* st, double* step_out, int fell_back) const
+    // resume: continue from the iterate records (a primal-dual warm start:
+    // the launch that stopped there left them as the next iteration would
+    // find them); itcap > 0: at most itcap iterations in this launch
+    // (iteration blocks of the server)
+    __device__ __forceinline__ void run(DevStat* st, double* step_out, int fell_back, int resume, int itcap) const
     {
         const bool newton_mode = P.mode == KMODE_NEWTON;
         const bool absf = ABS;
-        if (!newton_mode) init();
+        if (!newton_mode) init(resume ? 2 : P.warm);
+        const int cap = itcap > 0 ? min(P.iter_max, itcap) : P.iter_max;
         int status = ST_MAX_ITER, k = 0;
         double ng = 0, nb = 0, nd = 0, nm = 0, mu = 0.0, slt = 0.0;
         const double inv2nc = nc > 0 ? 1.0 / (2.0 * nc) : 0.0;
@@ -1765,7 +2098,8 @@ struct Blk {
         int qr_refactors = 0;
         for (k = 0;; ++k) {
             const bool fact_ok =
-                passA(upd, alpha, shift0, !rejected && !final_pass, absf && !final_pass, qr, ng, nb, nd, nm, slt);
+                passA(upd, alpha, shift0, !rejected && !final_pass && (newton_mode || k < cap), absf && !final_pass, qr,
+                      ng, nb, nd, nm, slt);
             __syncthreads();
             mu = slt * inv2nc;
             if (final_pass) {
@@ -1794,7 +2128,7 @@ struct Blk {
                     status = ST_NAN;
                     break;
                 }
-                if (mu <= P.tol_comp || k >= P.iter_max) {
+                if (mu <= P.tol_comp || k >= cap) {
                     status = mu <= P.tol_comp ? ST_SUCCESS : ST_MAX_ITER;
                     final_pass = true;
                     k_exit = k;
@@ -1810,7 +2144,7 @@ struct Blk {
                     status = ST_SUCCESS;
                     break;
                 }
-                if (k >= P.iter_max) {
+                if (k >= cap) {
                     status = ST_MAX_ITER;
                     break;
                 }
@@ -1912,8 +2246,13 @@ struct Blk {
 // 64-wide builds then spill part of their stage prefetch registers to
 // scratch (FP64: 155 registers, 616 B per lane) and still gain: the uneven
 // batch of 4096 runs 13 % faster (mixed path 7 %) than at one wave per SIMD,
-// whose whole register file they needed to avoid spilling.
-__host__ __device__ constexpr int block_waves(int zm, int gm) { return (zm >= 64 || (zm == 32 && gm == 0)) ? 2 : 1; }
+// whose whole register file they needed to avoid spilling.  The
+// global-memory mode takes one wave per SIMD: its stage matrix sits in
+// matrix-core accumulators (the whole register file of the wave).
+__host__ __device__ constexpr int block_waves(int zm, int gm)
+{
+    return zm > 64 ? 1 : ((zm == 64 || (zm == 32 && gm == 0)) ? 2 : 1);
+}
 
 // ZM > 64 selects the global-memory mode; WV overrides the register budget
 // (64-wide blocks with general rows at one wave per SIMD, for launches whose
@@ -1932,7 +2271,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(WV, WV))) vo
         fell_back = 1;
     }
     const Blk<KM, ZM, GM, (ZM > 64)> ipm(ds, data, iter, work, P);
-    ipm.run(stat + ds.index, step_out + ds.iter, fell_back);
+    ipm.run(stat + ds.index, step_out + ds.iter, fell_back, ds.resume, ds.itcap);
 }
 
 }  // namespace oqp

@@ -1666,9 +1666,8 @@ struct Ipm {
     // Section 4.2) y is kept and the rest set as in the cold start at that y;
     // with a primal and dual guess everything is kept, multipliers and
     // slacks clamped below as in the iterate update.
-    __device__ __forceinline__ void init() const
+    __device__ __forceinline__ void init(int warm) const
     {
-        const int warm = P.warm;
         for (int n = 0; n <= N; ++n) {
             const double* d = Dp(n);
             double* ir = Ip(n);
@@ -1768,11 +1767,16 @@ struct Ipm {
     // Newton step at the stored iterate with r_m = lam.*t - tau.  Every pass
     // has a single call site so that its code is emitted once.
     // ------------------------------------------------------------------
-    __device__ __forceinline__ void run(DevStat* st, double* step_out, int fell_back) const
+    // resume: continue from the iterate records (a primal-dual warm start:
+    // the launch that stopped there left them as the next iteration would
+    // find them); itcap > 0: at most itcap iterations in this launch
+    // (iteration blocks of the server)
+    __device__ __forceinline__ void run(DevStat* st, double* step_out, int fell_back, int resume, int itcap) const
     {
         const bool newton_mode = P.mode == KMODE_NEWTON;
         const bool absf = ABS;
-        if (!newton_mode) init();
+        if (!newton_mode) init(resume ? 2 : P.warm);
+        const int cap = itcap > 0 ? min(P.iter_max, itcap) : P.iter_max;
         int status = ST_MAX_ITER, k = 0;
         double ng = 0, nb = 0, nd = 0, nm = 0, mu = 0.0, slt = 0.0;
         const double inv2nc = nc > 0 ? 1.0 / (2.0 * nc) : 0.0;
@@ -1793,7 +1797,8 @@ struct Ipm {
             // residuals at the (updated) iterate; factorization unless the
             // last step was rejected as too short
             const bool fact_ok =
-                passA(upd, alpha, shift0, !rejected && !final_pass, absf && !final_pass, qr, ng, nb, nd, nm, slt);
+                passA(upd, alpha, shift0, !rejected && !final_pass && (newton_mode || k < cap), absf && !final_pass, qr,
+                      ng, nb, nd, nm, slt);
             __syncthreads();
             mu = slt * inv2nc;
             if (final_pass) {
@@ -1822,7 +1827,7 @@ struct Ipm {
                     status = ST_NAN;
                     break;
                 }
-                if (mu <= P.tol_comp || k >= P.iter_max) {
+                if (mu <= P.tol_comp || k >= cap) {
                     status = mu <= P.tol_comp ? ST_SUCCESS : ST_MAX_ITER;
                     final_pass = true;
                     k_exit = k;
@@ -1838,7 +1843,7 @@ struct Ipm {
                     status = ST_SUCCESS;
                     break;
                 }
-                if (k >= P.iter_max) {
+                if (k >= cap) {
                     status = ST_MAX_ITER;
                     break;
                 }
@@ -1958,7 +1963,7 @@ __global__ __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, ipm_max
         fell_back = 1;
     }
     const S ipm(data + ds.data, iter + ds.iter, work + ds.work, ds.N, ds.nc, P);
-    ipm.run(stat + ds.index, step_out + ds.iter, fell_back);
+    ipm.run(stat + ds.index, step_out + ds.iter, fell_back, ds.resume, ds.itcap);
 }
 
 template <int NX, int NU, int NG, int KM>

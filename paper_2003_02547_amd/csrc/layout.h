@@ -159,9 +159,9 @@ struct InstDesc {
     int32_t N;      // horizon
     int32_t nc;     // number of two-sided constraints (box + general)
     int32_t index;  // position of the instance in the caller's batch
-    int32_t pad;
+    int32_t resume; // 1: continue from the iterate records (iteration blocks of the server)
     int32_t nx, nu, ng;  // padded stage sizes (read by the runtime-sized block kernel)
-    int32_t pad2;
+    int32_t itcap;  // > 0: at most this many iterations in this launch
 };
 
 // Partial condensing (Section 3.5), one descriptor per instance.  Offsets

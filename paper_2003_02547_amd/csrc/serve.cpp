@@ -18,6 +18,7 @@
 // launch slot, destroyed by oqp_server_destroy.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 
@@ -86,6 +87,9 @@ struct Request {
     int64_t tag;       // caller's index (replay)
     int64_t t_submit, t_done;
     DevStat stat;
+    int resume;        // iteration blocks: the request continues from its iterate records
+    int iters_done;    // iteration blocks: iterations and refinement corrections so far
+    int ir_done;
 };
 
 struct Group {
@@ -138,6 +142,7 @@ int check_cfg(const oqp_server_cfg* c)
         return fail(OQP_EINVAL, "server cfg: max_requests, max_launch and max_groups must be >= 1");
     if (c->max_requests > (1 << 20) || c->max_launch > 65536 || c->max_groups > 4096)
         return fail(OQP_EINVAL, "server cfg: sizes too large");
+    if (c->iter_block < 0) return fail(OQP_EINVAL, "server cfg: iter_block must be >= 0");
     return OQP_OK;
 }
 
@@ -185,18 +190,36 @@ int retire(oqp_server* s, int* ncompleted)
             }
             if (e != hipSuccess) return fail(OQP_EDEVICE, "server: hipEventQuery: %s", hipGetErrorString(e));
             const int64_t t = now_ns();
+            int finished = 0;
             for (int j = 0; j < g.count; ++j) {
-                Request& r = s->req[g.req[j]];
+                const int slot = g.req[j];
+                Request& r = s->req[slot];
                 r.stat = g.hstat[j];
+                r.iters_done += r.stat.iters;
+                r.ir_done += r.stat.ir_steps;
+                r.stat.iters = r.iters_done;
+                r.stat.ir_steps = r.ir_done;
+                if (s->cfg.iter_block > 0 && r.stat.status == oqp::ST_MAX_ITER && r.iters_done < s->arg.iter_max) {
+                    // iteration block used up: queue again, ahead of the
+                    // requests that have not started
+                    r.state = RQ_QUEUED;
+                    r.resume = 1;
+                    r.next = s->q_head;
+                    s->q_head = slot;
+                    if (s->q_tail < 0) s->q_tail = slot;
+                    ++s->queued;
+                    continue;
+                }
                 r.state = RQ_DONE;
                 r.t_done = t;
-                s->done_ring[(s->done_head + s->done_len) % s->cfg.max_requests] = g.req[j];
+                s->done_ring[(s->done_head + s->done_len) % s->cfg.max_requests] = slot;
                 ++s->done_len;
+                ++finished;
             }
             s->running -= g.count;
-            s->done += g.count;
-            s->completed += g.count;
-            if (ncompleted) *ncompleted += g.count;
+            s->done += finished;
+            s->completed += finished;
+            if (ncompleted) *ncompleted += finished;
             g.busy = 0;
             s->sq_head[k] = g.next;
             --s->sq_len[k];
@@ -253,14 +276,18 @@ int launch_group(oqp_server* s, int v, int gi, int k)
         d.N = h->N;
         d.nc = h->nc + h->nsoft;  // one-sided rows / 2: constraint rows and slack bounds
         d.index = cnt;
-        d.pad = 0;
+        d.resume = q.resume;
         d.nx = h->nx;
         d.nu = h->nu;
         d.ng = h->ng;
-        d.pad2 = 0;
-        hipError_t e = hipMemcpyAsync(s->arena + q.dev_off, (const char*)h + h->data_off,
-                                      sizeof(double) * h->data_doubles, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return fail(OQP_EDEVICE, "server: request upload: %s", hipGetErrorString(e));
+        // iteration blocks: at most iter_block iterations, within what is
+        // left of the request's iteration limit
+        d.itcap = s->cfg.iter_block > 0 ? std::min(s->cfg.iter_block, s->arg.iter_max - q.iters_done) : 0;
+        if (!q.resume) {
+            hipError_t e = hipMemcpyAsync(s->arena + q.dev_off, (const char*)h + h->data_off,
+                                          sizeof(double) * h->data_doubles, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) return fail(OQP_EDEVICE, "server: request upload: %s", hipGetErrorString(e));
+        }
         q.state = RQ_RUNNING;
         q.group = gi;
         q.gpos = cnt;
@@ -283,6 +310,7 @@ int launch_group(oqp_server* s, int v, int gi, int k)
         return fail(OQP_EDEVICE, "server: kernel launch failed for group %d", v);
     if (km == oqp::KM_MIXED) {
         P.mode = oqp::KMODE_FALLBACK;
+        P.ir_max = 0;  // the fallback is the plain FP64 path (no refinement)
         if (group_launch(kg, oqp::KM_F64, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
             return fail(OQP_EDEVICE, "server: fallback launch failed for group %d", v);
     }
@@ -399,6 +427,7 @@ extern "C" void oqp_server_cfg_default(oqp_server_cfg* c)
     c->max_launch = 256;
     c->max_groups = 256;
     c->staging_bytes = (size_t)16 << 20;
+    c->iter_block = 0;
 }
 
 extern "C" int oqp_server_bytes(const oqp_server_cfg* cfg, size_t* host_bytes, size_t* dev_fixed_bytes)
@@ -421,6 +450,8 @@ extern "C" int oqp_server_init(const oqp_server_cfg* cfg, const oqp_arg* arg, vo
     if (rc) return rc;
     if (arg->cond_N != 0 || arg->warm_start != 0 || arg->mode == OQP_MODE_ROBUST || arg->mode == OQP_MODE_BALANCE)
         return fail(OQP_EINVAL, "oqp_server_init: partial condensing, warm start, robust and balance modes are batch options");
+    if (cfg->iter_block > 0 && arg->mode != OQP_MODE_F64)
+        return fail(OQP_EINVAL, "oqp_server_init: iteration blocks need the FP64 mode");
     if (!host_mem || !dev_mem || !streams || !out) return fail(OQP_EINVAL, "oqp_server_init: NULL argument");
     if (nstreams < 2 || nstreams > OQP_SERVER_MAX_STREAMS)
         return fail(OQP_EINVAL, "oqp_server_init: need 2..%d streams", OQP_SERVER_MAX_STREAMS);
@@ -523,6 +554,9 @@ extern "C" int oqp_server_submit(oqp_server* s, const void* packed, uint64_t* ti
     r.tag = 0;
     r.t_submit = now_ns();
     r.t_done = 0;
+    r.resume = 0;
+    r.iters_done = 0;
+    r.ir_done = 0;
     if (s->q_tail < 0) s->q_head = slot; else s->req[s->q_tail].next = slot;
     s->q_tail = slot;
     ++s->queued;

@@ -226,3 +226,45 @@ def test_soft_requests_served_in_mix_equal_alone():
             mixed.submit(packed[0])
     finally:
         mixed.close()
+
+
+@pytest.mark.parametrize("block", [1, 3])
+def test_iteration_blocks_equal_alone(block):
+    """Iteration blocks: each launch runs at most `block` IPM iterations and
+    the unfinished requests are launched again (with the ones that arrived
+    meanwhile) from their device-resident iterates.  Statuses, iteration
+    counts (summed over the launches) and solutions are bitwise those of the
+    request solved alone in one launch; requests that stop at the iteration
+    limit stop there too."""
+    qps = mixed_pool()
+    arg = B.default_arg(B.MODE_F64)
+    packed = [B.Packed(q, pinned=True) for q in qps]
+    say(f"serve with iteration blocks of {block}: {len(qps)} requests")
+    srv = B.Server(arg, dev_bytes=512 << 20, nstreams=4, max_launch=8, iter_block=block)
+    try:
+        order = list(np.random.default_rng(7).permutation(len(qps)))
+        tickets = serve_all(srv, packed, order, spacing_s=0.0005)
+        s = srv.stats()
+        assert s["completed"] == len(qps)
+        # more launches than a whole-solve server needs: requests come back
+        assert s["launches"] >= max(r.iters for r in B.solve(qps, arg)) // block
+        check_same_as_alone(srv, qps, tickets, arg)
+        for t in tickets.values():
+            srv.release(t)
+    finally:
+        srv.close()
+    # the iteration limit is kept across launches
+    lim = B.default_arg(B.MODE_F64, iter_max=5)
+    srv = B.Server(lim, dev_bytes=256 << 20, nstreams=3, max_launch=8, iter_block=block)
+    try:
+        tickets = serve_all(srv, packed[:8], list(range(8)))
+        check_same_as_alone(srv, qps[:8], tickets, lim)
+        for i, t in tickets.items():
+            assert srv.poll(t).iters <= 5
+    finally:
+        srv.close()
+
+
+def test_iteration_blocks_need_fp64_mode():
+    with pytest.raises(B.OqpError):
+        B.Server(B.default_arg(B.MODE_MIXED), dev_bytes=64 << 20, nstreams=2, iter_block=2)
