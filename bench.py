@@ -51,27 +51,39 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the one-wave kernel's sources and compile flags."""
+KERNEL_SOURCES = {
+    # family -> (sources under csrc/, one-wave compile flags)
+    "wave": (("ipm_kernel.h", "dev_common.h", "layout.h"), True),
+    "block": (("ipm_block.h", "dev_common.h", "layout.h"), False),
+    "batch": (("ipm_kernel.h", "ipm_block.h", "dev_common.h", "layout.h", "capi.cpp"), True),
+}
+
+
+def kernel_source_hash(family="wave"):
+    """Hash of a kernel family's sources and compile flags: the one-wave
+    kernel, the block kernel, or a whole batch solve (both kernels and the
+    launch code)."""
     from paper_2003_02547_amd import build as _build
+    files, one_wave = KERNEL_SOURCES[family]
     h = hashlib.sha256()
-    for f in ("ipm_kernel.h", "dev_common.h", "layout.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2003_02547_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    h.update(" ".join(_build.FLAGS + _build.ONE_WAVE_FLAGS).encode())
+    h.update(" ".join(_build.FLAGS + (_build.ONE_WAVE_FLAGS if one_wave else [])).encode())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(variant_key, launches_per_step):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def traffic_from_profile(key):
+    """HBM bytes per launch (per batch solve for a whole-batch record) from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    rec = t.get(variant_key)
-    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+    rec = t.get(key)
+    if not rec or rec.get("kernel_hash") != kernel_source_hash(rec.get("family", "wave")):
         return None
     return rec.get("bytes_per_launch")
 
@@ -193,13 +205,17 @@ def leg_uneven(B, W, torch, np, count, steps, seed0=0):
         t = float(np.median(ms)) * 1e-3
         nres = np.array([x.iters + 1 + x.ir_steps for x in stats])
         its = np.array([x.iters for x in stats])
-        ach = float(np.sum(dbytes * nres)) / t / 1e9
+        alg = float(np.sum(dbytes * nres))
+        ach = alg / t / 1e9
+        tkey = "uneven_%d_%s_batch" % (count, name) if seed0 == 0 else None
         out[name] = {"value": round(ok / t, 1), "unit": "solves/s",
                      "ms_per_step": round(t * 1e3, 3), "solves_ok": ok,
                      "block_kernel_instances": sum(1 for i in range(count) if batch.variant(i)[0] >= nv),
                      "kernel_groups": len(groups), "extra_streams": streams,
                      "roofline": {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
+                                  "frac": round(ach / HBM_PEAK_GBS, 5),
+                                  "traffic": traffic_from_profile(tkey) if tkey else None,
+                                  "alg_bytes": alg,
                                   "scope": "whole batch solve (every kernel group), batch-stream events",
                                   "fp64_tflops": round(float(np.sum(fpi * its)) / t / 1e12, 4)}}
         del batch
@@ -467,16 +483,20 @@ def leg_large(B, W, torch, np, perfmodel, count, steps):
         irs = np.array([x.ir_steps for x in res])
         t = float(np.median(ms)) * 1e-3
         flops = float(np.sum(fpi * its + fir * irs))
+        fell = sum(1 for x in res if x.fell_back_f64)
         peak = 78.6 if mode == B.MODE_F64 else 157.3
         ach = flops / t / 1e12
         out[name] = {"value": round(ok / t, 1), "unit": "solves/s", "ms_per_step": round(t * 1e3, 3),
                      "solves_ok": ok, "tol": tol, "ir_max": irm,
                      "non_success": [i for i, x in enumerate(res) if x.status != B.SUCCESS],
                      "iters_p50": float(np.median(its)), "iters_max": int(its.max()),
-                     "ir_steps_mean": round(float(irs.mean()), 2),
+                     "ir_steps_mean": round(float(irs.mean()), 2), "fell_back_f64": fell,
                      "max_kkt_res_kernel": float(max(max(x.res[:]) for x in res)),
                      "roofline": {"bound": "mfma", "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s",
-                                  "frac": round(ach / peak, 5), "traffic": None,
+                                  "frac": round(ach / peak, 5),
+                                  "traffic": traffic_from_profile("ipm_block_kernel<0,256,64>")
+                                  if mode == B.MODE_F64 and count == 256 else None,
+                                  "alg_flops": flops,
                                   "kernel": "ipm_block_kernel<%d,256,64>" % (0 if mode == B.MODE_F64 else 1),
                                   "hbm_gbs": round(float(np.sum(dbytes * (its + 1 + irs))) / t / 1e9, 1)}}
         keep[name] = res
@@ -630,7 +650,7 @@ def main():
         nres = iters + 1 + irs  # residual evaluations: one per iteration, the final check, one per refinement
         alg_bytes = float(np.sum(dbytes * nres))
         return dict(variant=variant, ok=ok, wall=wall, steps=steps, kern_ms=kern_ms, kern_s=kern_s,
-                    status=status, kkt=kkt, iters=iters, irs=irs, fb=fb, res=res,
+                    status=status, kkt=kkt, iters=iters, irs=irs, fb=fb, res=res, alg_bytes=alg_bytes,
                     achieved=alg_bytes / kern_s / 1e9, flops=float(np.sum(fpi * iters)) / kern_s / 1e12,
                     value=ok * steps / wall, del_batch=batch)
 
@@ -643,7 +663,7 @@ def main():
         log("bench: FP64 path with iter_max 20 (context: the batch time follows its slowest instance)")
         f20 = time_path(B.MODE_F64, args.iter20_steps, 1, iter_max=20)
     vkey = "ipm_kernel<%d,%d,%d>" % f["variant"]
-    traffic = traffic_from_profile(vkey, 1)
+    traffic = traffic_from_profile(vkey)
     okmask = f["status"] == B.SUCCESS
     line = {
         "metric": METRIC,
@@ -661,7 +681,8 @@ def main():
         "config": {"workload": "mass_spring_8masses_x1024", "instances": args.instances, "nx": 16, "nu": 7,
                    "N": 30, "path": "f64", "kernel": vkey},
         "roofline": {"bound": "hbm", "achieved": round(f["achieved"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(f["achieved"] / HBM_PEAK_GBS, 5), "traffic": traffic},
+                     "frac": round(f["achieved"] / HBM_PEAK_GBS, 5), "traffic": traffic,
+                     "alg_bytes": f["alg_bytes"]},
         "kernel_ms": round(float(np.mean(f["kern_ms"])), 4),
         "fp64_tflops": round(f["flops"], 4),
         "solves_ok": f["ok"],

@@ -116,8 +116,10 @@ typedef struct {
     int iters;         /* IPM iterations taken */
     int ir_steps;      /* refinement corrections kept in total */
     int fell_back_f64; /* mixed path only: 1 if the FP32 factorization broke down (or the mixed
-                          IPM stopped on NaN / a too-short step) and the instance was re-solved
-                          from a cold start by the FP64 kernel */
+                          IPM stopped on NaN / a too-short step) and the FP64 kernel finished the
+                          instance: from the mixed iterate when that is finite (iters and
+                          ir_steps then count both kernels, at most iter_max iterations in all),
+                          else from a cold start */
     double mu;         /* duality measure lam't / n_c at the returned iterate */
     double res[4];     /* inf-norms of r_g, r_b, r_d and lam .* t (eq:alg:pdipm:delta) */
     int qr_refactors;  /* balance mode: iterations factored again with the array algorithm */

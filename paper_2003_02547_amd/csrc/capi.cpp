@@ -1385,7 +1385,7 @@ static int launch_all(oqp_batch* b, const oqp::KParams& P)
         if (pass == 1) {
             if (!(km == oqp::KM_MIXED && P.mode == oqp::KMODE_SOLVE)) break;
             // FP64 kernels pick up the instances the mixed kernels handed over
-            // (from a cold start)
+            // (from their iterate when it is finite, else from a cold start)
             Pp.mode = oqp::KMODE_FALLBACK;
             Pp.ir_max = 0;  // the fallback is the plain FP64 path (no refinement)
             Pp.warm = 0;

@@ -2074,7 +2074,10 @@ struct Blk {
     // the launch that stopped there left them as the next iteration would
     // find them); itcap > 0: at most itcap iterations in this launch
     // (iteration blocks of the server)
-    __device__ __forceinline__ void run(DevStat* st, double* step_out, int fell_back, int resume, int itcap) const
+    // it0, ir0: iterations and refinement steps done before this launch on
+    // the same instance (a mixed solve continued by the FP64 kernel)
+    __device__ __forceinline__ void run(DevStat* st, double* step_out, int fell_back, int resume, int itcap, int it0,
+                                        int ir0) const
     {
         const bool newton_mode = P.mode == KMODE_NEWTON;
         const bool absf = ABS;
@@ -2225,10 +2228,17 @@ struct Blk {
             k = 0;
         }
         if (MIXED && !newton_mode && (status == ST_NAN || status == ST_MIN_STEP)) status = ST_FALLBACK;
+        // a finite iterate is handed over as it is: the FP64 kernel continues
+        // the solve from it instead of starting over
+        if (MIXED && status == ST_FALLBACK)
+            fell_back = (__builtin_isfinite(ng) && __builtin_isfinite(nb) && __builtin_isfinite(nd) &&
+                         __builtin_isfinite(nm) && __builtin_isfinite(mu))
+                            ? FB_RESUME
+                            : FB_COLD;
         if (tid == 0) {
             st->status = status;
-            st->iters = k;
-            st->ir_steps = ir_steps;
+            st->iters = it0 + k;
+            st->ir_steps = ir0 + ir_steps;
             st->fell_back = fell_back;
             st->qr_refactors = qr_refactors;
             st->mu = mu;
@@ -2265,13 +2275,22 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(WV, WV))) vo
     const int b = blockIdx.x;
     if (b >= count) return;
     const InstDesc ds = desc[b];
-    int fell_back = 0;
+    int fell_back = FB_NONE, resume = ds.resume, itcap = ds.itcap, it0 = 0, ir0 = 0;
     if (P.mode == KMODE_FALLBACK) {
-        if (stat[ds.index].status != ST_FALLBACK) return;
-        fell_back = 1;
+        // only instances the mixed kernel handed over, continued from their
+        // iterate within the remaining iteration budget
+        const DevStat s0 = stat[ds.index];
+        if (s0.status != ST_FALLBACK) return;
+        fell_back = FB_DONE;
+        if (s0.fell_back == FB_RESUME) {
+            resume = 1;
+            it0 = s0.iters;
+            ir0 = s0.ir_steps;
+            itcap = max(1, P.iter_max - it0);
+        }
     }
     const Blk<KM, ZM, GM, (ZM > 64)> ipm(ds, data, iter, work, P);
-    ipm.run(stat + ds.index, step_out + ds.iter, fell_back, ds.resume, ds.itcap);
+    ipm.run(stat + ds.index, step_out + ds.iter, fell_back, resume, itcap, it0, ir0);
 }
 
 }  // namespace oqp

@@ -193,7 +193,7 @@ struct DevStat {
     int32_t status;
     int32_t iters;
     int32_t ir_steps;
-    int32_t fell_back;  // the mixed path handed the instance to the FP64 kernel
+    int32_t fell_back;  // the mixed path handed the instance to the FP64 kernel (FB_*)
     double mu;
     double res[4];  // inf-norms of r_g, r_b, r_d, lam.*t at the returned iterate
     int32_t qr_refactors;  // balance build: iterations factored again with the array algorithm
@@ -219,5 +219,10 @@ enum { KMODE_SOLVE = 0, KMODE_NEWTON = 1, KMODE_FALLBACK = 2 };
 // residual with the array algorithm as fallback (one-wave kernel).
 enum { KM_F64 = 0, KM_MIXED = 1, KM_ABS = 2, KM_ROBUST = 3, KM_SOFT = 4, KM_BALANCE = 5 };
 enum { ST_SUCCESS = 0, ST_MAX_ITER = 1, ST_MIN_STEP = 2, ST_NAN = 3, ST_FALLBACK = 4 };
+// DevStat.fell_back: 0 solved by the launch's own kernel, 1 finished by the
+// FP64 kernel; between the mixed launch and the FP64 one, a handed-over
+// instance holds FB_RESUME (its iterate is finite: the FP64 kernel continues
+// from it) or FB_COLD (it starts the FP64 solve over)
+enum { FB_NONE = 0, FB_DONE = 1, FB_COLD = 2, FB_RESUME = 3 };
 
 }  // namespace oqp

@@ -311,6 +311,7 @@ int launch_group(oqp_server* s, int v, int gi, int k)
     if (km == oqp::KM_MIXED) {
         P.mode = oqp::KMODE_FALLBACK;
         P.ir_max = 0;  // the fallback is the plain FP64 path (no refinement)
+        P.warm = 0;    // a handed-over iterate is resumed; any other starts cold
         if (group_launch(kg, oqp::KM_F64, g.ddesc, g.hdesc, cnt, base, base, base, base, g.dstat, P, st))
             return fail(OQP_EDEVICE, "server: fallback launch failed for group %d", v);
     }
