@@ -9,7 +9,9 @@ to the KKT tolerance), FP64 path; the mixed path is timed beside it.
 
 Further legs on the same line (context, not the headline):
   * pcond: the same batch solved through partial condensing to a shorter
-    horizon (condensing and expansion inside the timed solve);
+    horizon (condensing and expansion inside the timed solve); N2 = 1 is full
+    condensing, solved by the wide-stage kernel (dense Cholesky of the
+    condensed Hessian);
   * abs: the same batch in the absolute formulation (mode speed_abs);
   * robust: the same batch with the QR-based factorization (mode robust);
   * balance: the same batch with checked Cholesky factors and the QR-based
@@ -568,7 +570,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uneven", type=int, default=4096, help="instances of the uneven leg (0: skip)")
     ap.add_argument("--uneven-steps", type=int, default=3)
-    ap.add_argument("--pcond", default="5,10,15", help="condensed horizons for the partial-condensing leg (0: skip)")
+    ap.add_argument("--pcond", default="1,5,10,15", help="condensed horizons for the partial-condensing leg (0: skip)")
     ap.add_argument("--pcond-steps", type=int, default=5)
     ap.add_argument("--warm-steps", type=int, default=5, help="timed solves of the warm-start leg (0: skip)")
     ap.add_argument("--abs-steps", type=int, default=5, help="timed solves of the absolute-formulation leg (0: skip)")

@@ -107,7 +107,8 @@ typedef struct {
     int warm_start;    /* batch only (Section 4.2): 0 cold start; 1 primal guess, 2 primal and dual
                           guess, read from the batch's iterate records (see oqp_batch_solve) */
     int cond_N;        /* batch only: solve after partial condensing to this horizon
-                          (Section 3.5; min(cond_N, N) stages per instance); 0 = off */
+                          (Section 3.5; min(cond_N, N) stages per instance; 1 = full
+                          condensing into one stage of every input); 0 = off */
 } oqp_arg;
 
 /* Per-instance result. */
@@ -229,7 +230,8 @@ int oqp_batch_load(oqp_batch* batch, const oqp_qp* const* qps);
  * that copy holds, the last fetched solution).  warm_start = 1 keeps u, x and
  * sets the rest as in the cold start at that point; 2 keeps all blocks,
  * clamping multipliers and slacks below at lam_min and t_min.  The mixed
- * path's FP64 fallback always starts cold.  Not combinable with cond_N. */
+ * path's FP64 fallback continues from the mixed iterate when it is finite.
+ * Not combinable with cond_N. */
 int oqp_batch_solve(oqp_batch* batch);
 /* Extra streams (default priority, caller-owned, at most OQP_BATCH_MAX_AUX)
  * for running kernel groups concurrently: a solve then forks from the batch
@@ -461,13 +463,19 @@ int oqp_server_replay(oqp_server* server, const void* const* packed, const doubl
                       double timeout_s, double* latency, oqp_stat* stat, double* wall_s);
 
 /* ---- kernels and introspection ---------------------------------------------- */
-/* Two kernel families solve an instance: one-wave kernels compiled for fixed
- * padded stage sizes (the "variants"), and a 256-thread block kernel with
- * runtime stage sizes (stage blocks nu + nx up to 64, up to 64 general rows per
- * stage).  An instance goes to the cheapest covering variant when that
+/* Kernel families: one-wave kernels compiled for fixed padded stage sizes
+ * (the "variants"); a 256-thread block kernel with runtime stage sizes (stage
+ * blocks nu + nx up to 256, at most 64 inputs and 64 general rows per stage);
+ * and, for batches, a wide-stage kernel for stages beyond those limits (any
+ * sizes whose LDS vectors fit a CU; FP64 delta formulation only, ir_max 0, no
+ * slacks: other modes refuse such instances with OQP_EINVAL), which is what
+ * full condensing (cond_N = 1, Section 3.5) produces: its stage-0
+ * factorization is the dense Cholesky factorization of the condensed Hessian
+ * (Section 3.3).  An instance goes to the cheapest covering variant when that
  * variant's stage block nx_pad + nu_pad is at most the wave bound, else to the
- * block kernel, padded only to its own largest stage.  The bound is process
- * wide and applies to batches and packed requests created after the call. */
+ * block kernel, padded only to its own largest stage, else to the wide-stage
+ * kernel.  The bound is process wide and applies to batches and packed
+ * requests created after the call. */
 int oqp_set_wave_max(int nz); /* 0..64; 0 sends every instance to the block kernel */
 int oqp_get_wave_max(void);
 /* Variants allowed (bit v for variant v, all by default): an instance whose
@@ -481,8 +489,9 @@ unsigned oqp_get_variant_mask(void);
  * default), or every group in one launch (0).  OQP_EINVAL for other values. */
 int oqp_set_lds_split(int on);
 int oqp_get_lds_split(void);
-/* Kernel group of instance i (a variant index < oqp_variant_count(), or a
- * block-kernel build at or above it) and its padded stage sizes. */
+/* Kernel group of instance i (a variant index < oqp_variant_count(); the six
+ * block-kernel builds follow; oqp_variant_count() + 6 is the wide-stage
+ * kernel) and its padded stage sizes. */
 int oqp_batch_variant(const oqp_batch* batch, int i, int* nx_pad, int* nu_pad, int* ng_pad);
 /* Number of compiled one-wave variants and the stage sizes of variant v. */
 int oqp_variant_count(void);

@@ -32,7 +32,8 @@ ONE_WAVE_FLAGS = ["-O2", "-fno-unroll-loops", "-mllvm", "-disable-lsr"]
 
 def sources():
     units = sorted(glob.glob(os.path.join(CSRC, "ipm_v*.hip"))) + [os.path.join(CSRC, f)
-                                                                    for f in ("ipm_block.hip", "ipm_block_soft.hip", "ipm_block_qr.hip")]
+                                                                    for f in ("ipm_block.hip", "ipm_block_soft.hip", "ipm_block_qr.hip",
+                                                                              "ipm_wide.hip")]
     return units + [os.path.join(CSRC, f) for f in ("ipm_registry.hip", "pcond.hip", "scratch.hip", "capi.cpp", "serve.cpp", "sol.cpp")]
 
 

@@ -481,6 +481,7 @@ struct Inst {
     int variant;    // kernel group (see select_kernel)
     int nx, nu, ng; // padded stage sizes of the device records
     int N;          // horizon of the solved QP
+    int nuN;        // inputs of its terminal stage (unpadded)
     int nc;
     int dims_off;   // into dims pool: 5 * (oN+1) ints (nx, nu, nbu, nbx, ng) of the original QP
     int slot_off;   // into slot pool: per-stage user constraint -> padded slot (original records)
@@ -582,10 +583,11 @@ int pick_variant(const oqp_dims* d)
 }
 
 // Kernel groups: 0..variant_count()-1 are the one-wave variants; the block
-// kernel builds follow (stage-block bound 32 or 64, without or with general
-// rows).  One-wave variants are used up to a stage block of g_wave_max_nz,
-// larger instances go to the block kernel, padded only to their own maximum
-// stage sizes.
+// kernel builds follow (stage-block bound 32, 64 or 256, without or with
+// general rows), then the wide-stage kernel (batches only: stages beyond the
+// block kernel's limits).  One-wave variants are used up to a stage block of
+// g_wave_max_nz, larger instances go to the block kernel, padded only to
+// their own maximum stage sizes.
 // 24 by default: the 32-wide variants win on batches of their own size, but
 // in uneven mixes their two extra kernel groups split the launches (uneven
 // 4096 on one stream 482 -> 532 ms, mixed 781 -> 832 ms, serving saturation
@@ -602,7 +604,9 @@ static const int kBlockZ[6] = {32, 32, 64, 64, 256, 256};
 static const int kBlockG[6] = {0, 64, 0, 64, 0, 64};
 static constexpr size_t kMaxLds = 160 * 1024;
 
-int group_count() { return oqp::variant_count() + 6; }
+// the wide-stage kernel's group follows the block kernel builds
+int group_count() { return oqp::variant_count() + 7; }
+static int wide_group() { return oqp::variant_count() + 6; }
 
 static void dims_max(const oqp_dims* d, int* mx, int* mu, int* mg)
 {
@@ -717,21 +721,34 @@ struct SolveShape {
     int onx, onu, ong;
 };
 
-static constexpr size_t kMaxCondLds = 64 * 1024;
+static constexpr size_t kMaxCondLds = 160 * 1024;
 
 // Kernel for the largest stage sizes (every mode has the same kernels: the
 // array-algorithm builds exist for the one-wave variants and the block
-// kernel alike).
-static int select_for_mode(int mx, int mu, int mg, int, int, KSel* out) { return select_kernel_max(mx, mu, mg, out); }
-
-static int solve_shape(const oqp_dims* d, int cond_N, int mode, int soft, SolveShape* sh, int i)
+// kernel alike).  Stages beyond the block kernel's limits go to the
+// wide-stage kernel: FP64 delta formulation without refinement, no slacks.
+static int select_for_mode(int mx, int mu, int mg, const oqp_arg* a, int soft, KSel* out)
 {
+    if (select_kernel_max(mx, mu, mg, out) == OQP_OK) return OQP_OK;
+    if (a->mode != OQP_MODE_F64 || a->ir_max != 0 || soft) return -1;
+    if (mx < 1) mx = 1;
+    if ((size_t)oqp::wide_lds_bytes(mx, mu, mg) > kMaxLds) return -1;
+    *out = KSel{wide_group(), mx, mu, mg};
+    return OQP_OK;
+}
+
+static int solve_shape(const oqp_dims* d, const oqp_arg* arg, int soft, SolveShape* sh, int i)
+{
+    const int cond_N = arg->cond_N;
     if (cond_N <= 0) {
         sh->N = d->N;
         int mx, mu, mg;
         dims_max(d, &mx, &mu, &mg);
-        if (select_for_mode(mx, mu, mg, mode, soft, &sh->ks))
-            return fail(OQP_EINVAL, "batch: no kernel covers the stage sizes of instance %d", i);
+        if (select_for_mode(mx, mu, mg, arg, soft, &sh->ks))
+            return fail(OQP_EINVAL,
+                        "batch: no kernel covers the stage sizes of instance %d (stages beyond the block kernel's "
+                        "limits need the FP64 mode without refinement)",
+                        i);
         sh->onx = sh->ks.nx;
         sh->onu = sh->ks.nu;
         sh->ong = sh->ks.ng;
@@ -747,8 +764,10 @@ static int solve_shape(const oqp_dims* d, int cond_N, int mode, int soft, SolveS
         if (c.ng > cg) cg = c.ng;
     }
     sh->N = N2;
-    if (select_for_mode(cx, cu, cg, mode, 0, &sh->ks))
-        return fail(OQP_EINVAL, "batch: no kernel covers the condensed stage sizes of instance %d (nx %d, nu %d, ng %d)",
+    if (select_for_mode(cx, cu, cg, arg, 0, &sh->ks))
+        return fail(OQP_EINVAL,
+                    "batch: no kernel covers the condensed stage sizes of instance %d (nx %d, nu %d, ng %d; stages "
+                    "beyond the block kernel's limits need the FP64 mode without refinement)",
                     i, cx, cu, cg);
     if ((size_t)oqp::cond_lds_bytes(sh->onx, sh->onu, sh->ks.nx + sh->ks.nu) > kMaxCondLds)
         return fail(OQP_EINVAL, "batch: condensed stage of instance %d too large for the condensing kernel", i);
@@ -803,6 +822,15 @@ int group_launch(int g, int km, const InstDesc* desc, const InstDesc* hdesc, int
 {
     const int nv = oqp::variant_count();
     if (g < nv) return oqp::variant_launch(g, km, desc, count, data, iter, work, step, stat, P, stream);
+    if (g == wide_group()) {
+        if (km != oqp::KM_F64) return -1;  // FP64 only (the plan refuses other modes)
+        size_t lds = 0;
+        for (int i = 0; i < count; ++i) {
+            const size_t b = (size_t)oqp::wide_lds_bytes(hdesc[i].nx, hdesc[i].nu, hdesc[i].ng);
+            if (b > lds) lds = b;
+        }
+        return oqp::wide_launch(desc, count, data, iter, work, step, stat, P, lds, stream);
+    }
     int split = 0;
     while (split_lds && g_lds_split && split < count && lds_big(hdesc[split])) ++split;
     if (split == count) split = 0;
@@ -874,7 +902,7 @@ static int make_plan(const oqp_dims* const* dims, int count, const oqp_arg* arg,
         const oqp_dims* d = dims[i];
         if (!d) return fail(OQP_EINVAL, "batch: dims[%d] is NULL", i);
         SolveShape sh;
-        int rc = solve_shape(d, cond_N, arg->mode, soft, &sh, i);
+        int rc = solve_shape(d, arg, soft, &sh, i);
         if (rc) return rc;
         const Layout L = oqp::make_layout(sh.ks.nx, sh.ks.nu, sh.ks.ng, soft);
         if (soft) {
@@ -1019,13 +1047,14 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
         Inst& in = b->inst[i];
         const oqp_dims* d = dims[i];
         SolveShape sh;
-        solve_shape(d, arg->cond_N, arg->mode, pl.soft, &sh, i);
+        solve_shape(d, arg, pl.soft, &sh, i);
         const KSel& ks = sh.ks;
         in.variant = ks.group;
         in.nx = ks.nx;
         in.nu = ks.nu;
         in.ng = ks.ng;
         in.N = sh.N;
+        in.nuN = d->nu[d->N];  // the condensed terminal stage keeps the original one's inputs
         in.oN = d->N;
         in.onx = sh.onx;
         in.onu = sh.onu;
@@ -1103,6 +1132,8 @@ extern "C" int oqp_batch_init(const oqp_dims* const* dims, int count, const oqp_
             ds.nu = in.nu;
             ds.ng = in.ng;
             ds.itcap = 0;
+            ds.nuN = in.nuN;
+            ds.pad = 0;
         }
     }
     // original records: the solved ones, or (condensing) regions of their own

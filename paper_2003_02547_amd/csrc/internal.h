@@ -39,6 +39,10 @@ int block_lds_bytes(int nx, int nu, int ng);
 int block_zmax(int nz);
 int block_launch(int zm, int gm, int km, const InstDesc* desc, int count, const double* data, double* iter,
                  double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
+// wide-stage kernel (stages beyond the block kernel's limits; FP64)
+int wide_lds_bytes(int nx, int nu, int ng);
+int wide_launch(const InstDesc* desc, int count, const double* data, double* iter, double* work, double* step,
+                DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
 // partial condensing (expand = 0: original data -> condensed data records;
 // expand = 1: condensed iterate -> original-layout iterate records)
 int cond_lds_bytes(int onx, int onu, int cnz);

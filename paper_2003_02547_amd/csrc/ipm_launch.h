@@ -39,4 +39,10 @@ int block_launch_qr(int zm, int gm, int km, const InstDesc* desc, int count, con
 int block_launch_soft(int zm, int gm, const InstDesc* desc, int count, const double* data, double* iter,
                       double* work, double* step, DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
 
+// wide-stage kernel (FP64 solve and Newton step; any stage sizes, one
+// workgroup per instance, stage matrices in the workspace records)
+int wide_lds_bytes(int nx, int nu, int ng);
+int wide_launch(const InstDesc* desc, int count, const double* data, double* iter, double* work, double* step,
+                DevStat* stat, const KParams& P, size_t lds_bytes, void* stream);
+
 }  // namespace oqp

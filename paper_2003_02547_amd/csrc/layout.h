@@ -127,8 +127,9 @@ OQP_HD constexpr Layout make_layout(int NX, int NU, int NG, bool soft = false)
     L.W_L = o; o += NZ * NZ;
     L.W_dinv = o; o += NZ;
     // [L_{n+1}' F; sqrt(w) G] of the stage, used only by the global-memory
-    // mode of the block kernel (stage blocks above 64)
-    L.W_V = o; o += NX + NU > 64 ? (NX + NG) * NZ : 0;
+    // mode of the block kernel (stage blocks above 64) and by the wide-stage
+    // kernel (also for more than 64 general rows)
+    L.W_V = o; o += (NX + NU > 64 || NG > 64) ? (NX + NG) * NZ : 0;
     {
         const int ns = soft ? NC : 0;
         L.W_rsl = o; o += ns;
@@ -162,6 +163,8 @@ struct InstDesc {
     int32_t resume; // 1: continue from the iterate records (iteration blocks of the server)
     int32_t nx, nu, ng;  // padded stage sizes (read by the runtime-sized block kernel)
     int32_t itcap;  // > 0: at most this many iterations in this launch
+    int32_t nuN;    // inputs of the terminal stage (0: the wide-stage kernel skips its padded input block)
+    int32_t pad;
 };
 
 // Partial condensing (Section 3.5), one descriptor per instance.  Offsets

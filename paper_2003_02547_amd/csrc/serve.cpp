@@ -283,6 +283,8 @@ int launch_group(oqp_server* s, int v, int gi, int k)
         // iteration blocks: at most iter_block iterations, within what is
         // left of the request's iteration limit
         d.itcap = s->cfg.iter_block > 0 ? std::min(s->cfg.iter_block, s->arg.iter_max - q.iters_done) : 0;
+        d.nuN = h->nu;  // padded size: the server's kernels read the whole block
+        d.pad = 0;
         if (!q.resume) {
             hipError_t e = hipMemcpyAsync(s->arena + q.dev_off, (const char*)h + h->data_off,
                                           sizeof(double) * h->data_doubles, hipMemcpyHostToDevice, st);

@@ -87,12 +87,19 @@ def test_batch_size_and_plan_errors():
     rc = L.oqp_batch_init(arr, 3, ct.byref(arg), host.ctypes.data, hb.value - 1, ct.c_void_p(256), db.value,
                           None, ct.byref(h))
     assert rc == B.ENOMEM
-    # stage sizes beyond every kernel: more than 256 rows per stage block, or
-    # more than 64 inputs, or more than 64 general rows
+    # stage sizes beyond the block kernel (more than 256 rows per stage block,
+    # more than 64 inputs, or more than 64 general rows): the wide-stage
+    # kernel, FP64 without refinement only; LDS bounds what it takes
     for nx, nu, ng in ((250, 10, 0), (80, 70, 0), (40, 8, 70)):
         big = B.Dims(2, [nx] * 3, [nu, nu, 0], [0, 0, 0], [0, 0, 0], [ng, ng, 0])
         arr1 = (ct.c_void_p * 1)(big.h)
-        assert L.oqp_batch_bytes(arr1, 1, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.EINVAL, (nx, nu, ng)
+        assert L.oqp_batch_bytes(arr1, 1, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.OK, (nx, nu, ng)
+        for other in (B.default_arg(B.MODE_MIXED), B.default_arg(B.MODE_ROBUST), B.default_arg(ir_max=2)):
+            rc = L.oqp_batch_bytes(arr1, 1, ct.byref(other), ct.byref(hb), ct.byref(db))
+            assert rc == B.EINVAL and b"FP64 mode without refinement" in L.oqp_last_error(), (nx, nu, ng)
+    huge = B.Dims(1, [4000] * 2, [8, 0], [0, 0], [0, 0], [0, 0])
+    arr1 = (ct.c_void_p * 1)(huge.h)
+    assert L.oqp_batch_bytes(arr1, 1, ct.byref(arg), ct.byref(hb), ct.byref(db)) == B.EINVAL
     # a large stage block is accepted (global-memory mode of the block kernel)
     ok = B.Dims(2, [128] * 3, [32, 32, 0], [0, 0, 0], [0, 0, 0], [32, 32, 0])
     arr1 = (ct.c_void_p * 1)(ok.h)

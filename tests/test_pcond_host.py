@@ -57,8 +57,10 @@ def test_condensing_batch_plan():
     assert db.value != d0 and hb.value != h0
     # negative horizon
     assert L.oqp_batch_bytes(arr, 2, ct.byref(B.default_arg(cond_N=-1)), ct.byref(hb), ct.byref(db)) == B.EINVAL
-    # one block of 30 stages: 210 inputs, beyond every kernel
-    rc = L.oqp_batch_bytes(arr, 2, ct.byref(B.default_arg(cond_N=1)), ct.byref(hb), ct.byref(db))
+    # full condensing (one block of 30 stages: 210 inputs, 232 general rows):
+    # the wide-stage kernel, FP64 only
+    assert L.oqp_batch_bytes(arr, 2, ct.byref(B.default_arg(cond_N=1)), ct.byref(hb), ct.byref(db)) == B.OK
+    rc = L.oqp_batch_bytes(arr, 2, ct.byref(B.default_arg(B.MODE_MIXED, cond_N=1)), ct.byref(hb), ct.byref(db))
     assert rc == B.EINVAL and b"condensed" in L.oqp_last_error()
     # the server does not condense
     cfg = B.ServerCfg()
