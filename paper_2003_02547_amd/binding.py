@@ -306,11 +306,15 @@ def _sizes(qp):
 class Batch:
     """A batch of OCP QPs solved on the current CUDA (HIP) device and stream."""
 
-    def __init__(self, qps: Sequence, arg: Arg | None = None, device=None, stream=None, streams: int = 0,
+    def __init__(self, qps: Sequence, arg: Arg | None = None, device=None, stream=None, streams=0,
                  static: bool = False):
-        """static=True: the batch's device records go to the library's static
-        device region (oqp_batch_init_static) instead of a device buffer
-        allocated here; one such batch at a time per GPU, no extra streams."""
+        """streams: extra streams for concurrent kernel groups, a count (new
+        default-priority streams) or a list of existing torch streams (a
+        caller that keeps a fixed set of streams controls which hardware
+        queues they share).  static=True: the batch's device records go to the
+        library's static device region (oqp_batch_init_static) instead of a
+        device buffer allocated here; one such batch at a time per GPU, no
+        extra streams."""
         import torch
         L = lib()
         self.qps = list(qps)
@@ -341,9 +345,12 @@ class Batch:
         self.h = h
         self._qph = None
         self.aux = []
-        if streams > 0:
+        if isinstance(streams, (list, tuple)):
+            self.aux = list(streams)
+        elif streams > 0:
             # extra streams (default priority) for concurrent kernel groups
             self.aux = [torch.cuda.Stream(device=dev) for _ in range(int(streams))]
+        if self.aux:
             arr = (_V * len(self.aux))(*[s.cuda_stream for s in self.aux])
             _check(L.oqp_batch_set_streams(self.h, arr, len(self.aux)))
 

@@ -24,13 +24,14 @@ def _need_gpu():
     B.lib()
 
 
-@pytest.mark.parametrize("mode", [B.MODE_F64, B.MODE_MIXED])
-def test_extra_streams_bitwise_equal(mode):
+@pytest.mark.parametrize("mode,given", [(B.MODE_F64, False), (B.MODE_MIXED, False), (B.MODE_F64, True)])
+def test_extra_streams_bitwise_equal(mode, given):
     qps = [W.random_uneven(i) for i in range(24)] + [W.mass_spring_chain4(s) for s in range(4)]
-    print(f"extra streams vs one stream, mode {mode}", flush=True)
+    print(f"extra streams vs one stream, mode {mode}, caller's streams {given}", flush=True)
     sys.stdout.flush()
     one = B.Batch(qps, B.default_arg(mode)).load().solve().fetch().sync().results()
-    many = B.Batch(qps, B.default_arg(mode), streams=3)
+    extra = [torch.cuda.Stream() for _ in range(3)] if given else 3
+    many = B.Batch(qps, B.default_arg(mode), streams=extra)
     groups = {many.variant(i)[0] for i in range(len(qps))}
     assert len(groups) >= 4
     res = many.load().solve().fetch().sync().results()
