@@ -99,9 +99,9 @@ struct Ipm {
         double z[WAVE];           // z_n or dz_n
         double t1[WAVE], t2[WAVE];
         double rb[WAVE];          // r_b of the stage
-        double xn[2][WAVE];       // x_{n+1} / dx_{n+1}, by parity
-        double pin[2][WAVE];      // pi_{n+1}, by parity
-        double pn[2][WAVE];       // p_{n+1}, by parity
+        double xn[2][NXP];        // x_{n+1} / dx_{n+1}, by parity
+        double pin[2][NXP];       // pi_{n+1}, by parity
+        double pn[2][NXP];        // p_{n+1}, by parity
         double e[NCT * WAVE];     // reduced-gradient terms per constraint slot
         double ws[NCT * WAVE];    // barrier weights per constraint slot
         double M[LDZ * NZP];      // stage matrix / factor (column-major)
@@ -109,7 +109,6 @@ struct Ipm {
         double F[LDX * NZP];      // [B A] of the stage
         double V[LDV * NZP];      // [U; sqrt(w) G]
         double G[LDG * NZP];      // general rows of the stage
-        double Lst[LDZ * NZP];    // factor of the last stage, staged for the copy out
     };
 
     const double* __restrict__ dat;
@@ -677,12 +676,6 @@ struct Ipm {
         if (lane < NZ) w[Lo.W_rg + lane] = o.rg;
         if (n < N && lane < NX) w[Lo.W_rb + lane] = o.rb;
         if (factor) {
-            // factor staged in LDS (column-major), coalesced copy out
-#pragma unroll
-            for (int t = 0; t < EH; ++t) {
-                const int e = lane + WAVE * t;
-                if (e < NZ * NZ) w[Lo.W_L + e] = s.Lst[(e % NZ) + (e / NZ) * LDZ];
-            }
             if (lane < NZ) w[Lo.W_dinv + lane] = o.dinv;
             if (lane < NU) w[Lo.W_yu + lane] = o.mv;
             else if (lane < NZ) w[Lo.W_pv + lane - NU] = o.mv;
@@ -932,9 +925,14 @@ struct Ipm {
                 } else if constexpr (BALANCE) {
                     if (qr && (n < N || NG > 0)) qr_update(rowL, dinv, n < N ? 0 : NX);
                 }
+                // the factor goes to its record straight from the rows in
+                // registers: lane j stores row j, so every column is one
+                // coalesced store (no LDS staging: the LDS block of an
+                // instance stays small enough for seven instances per CU)
                 if (lane < NZ) {
+                    double* wl = Wp(n) + Lo.W_L + lane;
 #pragma unroll
-                    for (int k = 0; k < NZ; ++k) s.Lst[lane + k * LDZ] = (k <= lane) ? rowL[k] : 0.0;
+                    for (int k = 0; k < NZ; ++k) wl[k * NZ] = (k <= lane) ? rowL[k] : 0.0;
                 }
                 o.dinv = dinv;
 
