@@ -842,6 +842,12 @@ struct Wide {
     }
 };
 
+}  // namespace
+
+// Three workgroups per CU (130 VGPRs).  Forcing four (114 VGPRs, no spills)
+// keeps a whole batch of 1024 fully condensed 8-mass instances resident but
+// makes the solve slower (104 -> 123 ms): more instances' stage matrices
+// compete for the same L2.
 __global__ __launch_bounds__(WT) void ipm_wide_kernel(const InstDesc* __restrict__ desc, int count,
                                                       const double* __restrict__ data, double* __restrict__ iter,
                                                       double* __restrict__ work, double* __restrict__ step_out,
@@ -854,8 +860,6 @@ __global__ __launch_bounds__(WT) void ipm_wide_kernel(const InstDesc* __restrict
     const Wide ipm(ds, data, iter, work, P);
     ipm.run(stat + ds.index, step_out + ds.iter, ds.resume, ds.itcap);
 }
-
-}  // namespace
 
 int wide_lds_bytes(int nx, int nu, int ng) { return (int)sizeof(double) * make_wlds(nx, nu, ng).total; }
 

@@ -113,9 +113,14 @@ __global__ void __launch_bounds__(CT) pcond_condense_kernel(const CondDesc* __re
         const double* rec = odata + D.odata + (int64_t)n * Lo.SREC;
         const double* H = rec + Lo.D_H;
         const double* Gr = rec + Lo.D_G;
+        // E_n = [S_n; Gam_n] is zero in the columns of the inputs of later
+        // stages: only the na active columns (inputs up to this stage, then
+        // the block-start state) take part in W and in the update of H_bar
+        const int nin = off + nu, na = nin + nxs;
         // W = H_n E_n, w = H_n e_n + g_n (rows: u_n then x_n)
-        for (int e = tid; e < nz * CNZ; e += CT) {
-            const int r = e % nz, c = e / nz;
+        for (int e = tid; e < nz * na; e += CT) {
+            const int r = e % nz, a = e / nz;
+            const int c = a < nin ? a : CNU + (a - nin);
             const int hr = r < nu ? r : ONU + (r - nu);
             double acc = (c >= off && c < off + nu) ? H[hr + (c - off) * ONZ] : 0.0;
             for (int i = 0; i < nx; ++i) acc += H[hr + (ONU + i) * ONZ] * G[i + c * ONX];
@@ -131,12 +136,13 @@ __global__ void __launch_bounds__(CT) pcond_condense_kernel(const CondDesc* __re
         // H_bar += E_n' W, g_bar += E_n' w (each thread owns fixed entries;
         // the lower triangle is computed and mirrored, so H_bar is exactly
         // symmetric)
-        for (int e = tid; e < CNZ * CNZ; e += CT) {
-            const int c1 = e % CNZ, c2 = e / CNZ;
-            if (c1 < c2) continue;
+        for (int e = tid; e < na * na; e += CT) {
+            const int a1 = e % na, a2 = e / na;
+            if (a1 < a2) continue;
+            const int c1 = a1 < nin ? a1 : CNU + (a1 - nin), c2 = a2 < nin ? a2 : CNU + (a2 - nin);
             double acc = (c1 >= off && c1 < off + nu) ? W[(c1 - off) + c2 * nz] : 0.0;
             for (int i = 0; i < nx; ++i) acc += G[i + c1 * ONX] * W[(nu + i) + c2 * nz];
-            out[Lc.D_H + e] += acc;
+            out[Lc.D_H + c1 + c2 * CNZ] += acc;
             if (c1 != c2) out[Lc.D_H + c2 + c1 * CNZ] += acc;
         }
         for (int c1 = tid; c1 < CNZ; c1 += CT) {
