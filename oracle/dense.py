@@ -140,10 +140,13 @@ def residuals(dq, v, lam_l, lam_u, t_l, t_u):
 
 
 def solve_dense(dq, tol: float = 1e-8, iter_max: int = 100, gamma: float = 0.995, alpha_min: float = 1e-10,
-                corr_ratio: float = 10.0, clamp: float = 1e-16):
+                corr_ratio: float = 10.0, clamp: float = 1e-16, sigma_pow: float = 3.0, corrector: bool = True):
     """The IPM on the dense QP.  Returns (status, iters, v, lam_l, lam_u,
     t_l, t_u, norms); status 0 success, 1 max iterations, 2 too short a step,
-    3 NaN (the OCP oracle's codes)."""
+    3 NaN (the OCP oracle's codes).  sigma_pow and corrector exist only so
+    that tests can show the trajectory comparison notices a change of the
+    centering rule or a dropped corrector (sigma = (mu_aff / mu)^3 and the
+    conditional corrector are the method)."""
     A, lo, hi = _rows(dq)
     m = A.shape[0]
     v = np.zeros(dq.nv)
@@ -191,12 +194,12 @@ def solve_dense(dq, tol: float = 1e-8, iter_max: int = 100, gamma: float = 0.995
         aff = step(lam_l * t_l, lam_u * t_u)
         a_aff = min(1.0, amax(*aff[1:]))
         mu_aff = max(0.0, mu_at(a_aff, *aff[1:])) if m > 0 else 0.0
-        sigma_mu = (mu_aff / mu) ** 3 * mu if mu > 0 else 0.0
+        sigma_mu = (mu_aff / mu) ** sigma_pow * mu if mu > 0 else 0.0
         # corrector, rejected for the predictor-centering step when it raises
         # the duality measure too much (Section 4.2)
         st = step(lam_l * t_l + aff[1] * aff[3] - sigma_mu, lam_u * t_u + aff[2] * aff[4] - sigma_mu)
         a_c = min(1.0, amax(*st[1:]))
-        if m > 0 and mu_at(a_c, *st[1:]) > corr_ratio * mu_aff:
+        if not corrector or (m > 0 and mu_at(a_c, *st[1:]) > corr_ratio * mu_aff):
             st = step(lam_l * t_l - sigma_mu, lam_u * t_u - sigma_mu)
         a = min(1.0, gamma * amax(*st[1:]))
         dv, dll, dlu, dtl, dtu = st

@@ -9,7 +9,11 @@ fix, on the CPU:
   general rows) along that trajectory;
 * the dense IPM reaches the OCP oracle's minimiser (an independent solver:
   classical Riccati recursion on the uncondensed QP), and it fails where the
-  OCP oracle fails.
+  OCP oracle fails;
+* where both start from the same point, the dense IPM's iterates equal the
+  OCP oracle's iteration by iteration: an independent implementation of the
+  iteration control (initial point, centering rule, conditional corrector,
+  step rule, clamps) pins the OCP oracle's, and a changed rule in it shows.
 """
 import numpy as np
 import pytest
@@ -123,3 +127,42 @@ def test_dense_ipm_reaches_the_ocp_minimiser():
         assert abs(it - ref.iters) <= 1, (k, it, ref.iters)
         assert rel(sol["u"], ref.sol["u"]) <= 1e-7, (k, rel(sol["u"], ref.sol["u"]))
         assert rel(sol["x"], ref.sol["x"]) <= 1e-7, (k, rel(sol["x"], ref.sol["x"]))
+
+
+def trajectory_cases():
+    """QPs whose cold start satisfies the dynamics (b = 0, x0 as an
+    equal-limit box): the OCP IPM and the dense IPM then start from the same
+    point, and in exact arithmetic their Newton steps are the same step, so
+    the two iterate sequences coincide up to rounding."""
+    rng = lambda s: np.random.default_rng(np.random.SeedSequence([77, s]))
+    return [W.mass_spring_chain4(1), W.mass_spring_chain8(3), W.random_stable(rng(1), 6, 3, 8),
+            W.random_stable(rng(2), 5, 3, 6, ng=2)]
+
+
+def test_iteration_control_pinned_by_the_dense_ipm():
+    """The OCP oracle's iteration control (initial point, sigma = (mu_aff /
+    mu)^3, the conditional corrector, the step rule, the clamps) against an
+    independent implementation of the same rules on the dense QP: the
+    primal iterates after k = 1..8 iterations agree to rounding."""
+    for q in trajectory_cases():
+        dq = D.condense_dense(q)
+        for k in (1, 2, 3, 5, 8):
+            _, _, v, *_ = D.solve_dense(dq, tol=1e-14, iter_max=k)
+            sol = D.expand_dense(q, v)
+            ref = O.solve(q, O.Arg.with_tol(1e-14, iter_max=k))
+            assert rel(sol["u"], ref.sol["u"]) <= 1e-9, (k, rel(sol["u"], ref.sol["u"]))
+            assert rel(sol["x"], ref.sol["x"]) <= 1e-9, (k, rel(sol["x"], ref.sol["x"]))
+
+
+@pytest.mark.parametrize("change", [{"sigma_pow": 2.0}, {"corrector": False}, {"gamma": 0.9}])
+def test_trajectory_comparison_notices_a_changed_rule(change):
+    """The comparison above is sharp: a different centering power, a dropped
+    corrector or another fraction to the boundary moves the dense iterates
+    away from the OCP oracle's within a few iterations."""
+    worst = 0.0
+    for q in trajectory_cases():
+        dq = D.condense_dense(q)
+        _, _, v, *_ = D.solve_dense(dq, tol=1e-14, iter_max=3, **change)
+        ref = O.solve(q, O.Arg.with_tol(1e-14, iter_max=3))
+        worst = max(worst, rel(D.expand_dense(q, v)["u"], ref.sol["u"]))
+    assert worst > 1e-6, worst
