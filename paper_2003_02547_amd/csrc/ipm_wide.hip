@@ -82,18 +82,25 @@ __device__ __forceinline__ int opq(int v)
     return v;
 }
 
+// sum_{k < n} a[k sa] b[k sb]: eight loads of each operand issued before
+// their products, so that eight memory round trips overlap (the stage
+// records mostly come from HBM: a dependent chain would pay one trip each)
 __device__ __forceinline__ double dot(const double* a, int sa, const double* b, int sb, int n)
 {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int k = 0;
-    for (; k + 4 <= n; k += 4) {
-        s0 += a[k * sa] * b[k * sb];
-        s1 += a[(k + 1) * sa] * b[(k + 1) * sb];
-        s2 += a[(k + 2) * sa] * b[(k + 2) * sb];
-        s3 += a[(k + 3) * sa] * b[(k + 3) * sb];
+    for (; k + 8 <= n; k += 8) {
+        double av[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            av[u] = a[(k + u) * sa];
+            bv[u] = b[(k + u) * sb];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += av[u] * bv[u];
     }
-    for (; k < n; ++k) s0 += a[k * sa] * b[k * sb];
-    return (s0 + s1) + (s2 + s3);
+    for (; k < n; ++k) s[0] += a[k * sa] * b[k * sb];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 struct Wide {
@@ -229,13 +236,22 @@ struct Wide {
             const double* pa = A + min(i, m - 1) * sai;
             const double* pb = B + min(j, n - 1) * sbj;
             V4 acc = {0.0, 0.0, 0.0, 0.0};
-            for (int k0 = 0; k0 < K; k0 += 4) {
-                const int k = k0 + lk;
-                const int kc = min(k, K - 1);
-                const double av = pa[kc * sak], bv = pb[kc * sbk];
-                const bool kv = k < K;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64((iv && kv) ? av : 0.0, (jv && kv) ? bv : 0.0, acc, 0, 0,
-                                                           0);
+            // K in chunks of 16: the chunk's eight operand loads are issued
+            // before its four matrix-core steps
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                double av[4], bv[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int kc = min(k0 + 4 * q + lk, K - 1);
+                    av[q] = pa[kc * sak];
+                    bv[q] = pb[kc * sbk];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool kv = k0 + 4 * q + lk < K;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64((iv && kv) ? av[q] : 0.0, (jv && kv) ? bv[q] : 0.0, acc,
+                                                               0, 0, 0);
+                }
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -353,13 +369,21 @@ struct Wide {
             const int pw = min(PW, n - p0);
             const int p1 = p0 + pw;
             if (wid == 0) {
+                // the block's row of this lane and its pivot inverse are
+                // loaded first, then the substitution runs from registers
                 const bool act = lane < pw;
                 const int i = p0 + min(lane, pw - 1);
+                double lr[PW];
+#pragma unroll
+                for (int q = 0; q < PW; ++q) lr[q] = (act && q < pw) ? L[i + (p0 + q) * ld] : 0.0;
+                const double dl = act ? dinv[i] : 1.0;
                 double v = act ? x[i] : 0.0;
-                for (int q = 0; q < pw; ++q) {
-                    const double xq = bcast(v, q) * dinv[p0 + q];
+#pragma unroll
+                for (int q = 0; q < PW; ++q) {
+                    if (q >= pw) break;
+                    const double xq = bcast(v, q) * bcast(dl, q);
                     if (lane == q) v = xq;
-                    else if (lane > q && act) v -= L[i + (p0 + q) * ld] * xq;
+                    else if (lane > q && act) v -= lr[q] * xq;
                 }
                 if (act) x[i] = v;
             }
@@ -378,11 +402,17 @@ struct Wide {
             if (wid == 0) {
                 const bool act = lane < pw;
                 const int i = p0 + min(lane, pw - 1);
+                double lc[PW];
+#pragma unroll
+                for (int q = 0; q < PW; ++q) lc[q] = (act && q < pw) ? L[(p0 + q) + i * ld] : 0.0;
+                const double dl = act ? dinv[i] : 1.0;
                 double v = act ? x[i] : 0.0;
-                for (int q = pw - 1; q >= 0; --q) {
-                    const double xq = bcast(v, q) * dinv[p0 + q];
+#pragma unroll
+                for (int q = PW - 1; q >= 0; --q) {
+                    if (q >= pw) continue;
+                    const double xq = bcast(v, q) * bcast(dl, q);
                     if (lane == q) v = xq;
-                    else if (lane < q) v -= L[(p0 + q) + i * ld] * xq;
+                    else if (lane < q) v -= lc[q] * xq;
                 }
                 if (act) x[i] = v;
             }

@@ -133,17 +133,32 @@ __global__ void __launch_bounds__(CT) pcond_condense_kernel(const CondDesc* __re
             w[r] = acc;
         }
         __syncthreads();
-        // H_bar += E_n' W, g_bar += E_n' w (each thread owns fixed entries;
-        // the lower triangle is computed and mirrored, so H_bar is exactly
-        // symmetric)
-        for (int e = tid; e < na * na; e += CT) {
-            const int a1 = e % na, a2 = e / na;
-            if (a1 < a2) continue;
-            const int c1 = a1 < nin ? a1 : CNU + (a1 - nin), c2 = a2 < nin ? a2 : CNU + (a2 - nin);
-            double acc = (c1 >= off && c1 < off + nu) ? W[(c1 - off) + c2 * nz] : 0.0;
-            for (int i = 0; i < nx; ++i) acc += G[i + c1 * ONX] * W[(nu + i) + c2 * nz];
-            out[Lc.D_H + c1 + c2 * CNZ] += acc;
-            if (c1 != c2) out[Lc.D_H + c2 + c1 * CNZ] += acc;
+        // H_bar += E_n' W on the lower triangle (mirrored once at the end of
+        // the block, so H_bar is exactly symmetric), g_bar += E_n' w.  Each
+        // thread updates four entries per round: their four loads of H_bar
+        // are in flight together
+        for (int e0 = tid; e0 < na * na; e0 += 4 * CT) {
+            int ix[4];
+            double cur[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = e0 + q * CT;
+                const int a1 = e % na, a2 = e / na;
+                ix[q] = -1;
+                if (e < na * na && a1 >= a2) {
+                    const int c1 = a1 < nin ? a1 : CNU + (a1 - nin), c2 = a2 < nin ? a2 : CNU + (a2 - nin);
+                    ix[q] = c1 + c2 * CNZ;
+                }
+                cur[q] = ix[q] >= 0 ? out[Lc.D_H + ix[q]] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (ix[q] < 0) continue;
+                const int c1 = ix[q] % CNZ, c2 = ix[q] / CNZ;
+                double acc = (c1 >= off && c1 < off + nu) ? W[(c1 - off) + c2 * nz] : 0.0;
+                for (int i = 0; i < nx; ++i) acc += G[i + c1 * ONX] * W[(nu + i) + c2 * nz];
+                out[Lc.D_H + ix[q]] = cur[q] + acc;
+            }
         }
         for (int c1 = tid; c1 < CNZ; c1 += CT) {
             double acc = (c1 >= off && c1 < off + nu) ? w[c1 - off] : 0.0;
@@ -217,6 +232,13 @@ __global__ void __launch_bounds__(CT) pcond_condense_kernel(const CondDesc* __re
         double* t = G; G = Gn; Gn = t;
         t = g; g = gn; gn = t;
         off += nu;
+    }
+    // upper triangle of H_bar from the lower one (the padded unit diagonal
+    // has no off-diagonal entries)
+    __syncthreads();
+    for (int e = tid; e < CNZ * CNZ; e += CT) {
+        const int r = e % CNZ, c = e / CNZ;
+        if (r < c) out[Lc.D_H + e] = out[Lc.D_H + c + r * CNZ];
     }
     // condensed dynamics: the map at the block end
     if (b < D.N2) {
