@@ -5,11 +5,11 @@ Workload (the headline value): 1024 same-size mass-spring QPs (8 masses:
 nx=16, nu=7, N=30, dt=0.2, Q=I, R=0.1 I, |u|<=0.5, |x_pos|<=4, x0 ~
 U[-2,2]^16 per instance), synthetic and seeded, resident in HBM before the
 timed region.  One step = one full IPM solve of the whole batch (cold start
-to the KKT tolerance), FP64 path; the mixed path is timed beside it.  Three
-copies of the batch, each on its own stream, take the steps in turn
-(--inflight): a batch is done only when its slowest instance is (an
-infeasible instance runs 42 iterations where the others stop at 12-15), and
-the next batch fills the CUs its finished instances leave idle.
+to the KKT tolerance), FP64 path; the mixed path is timed beside it.  Four
+copies of the batch, each on its own stream and hardware queue, take the
+steps in turn (--inflight): a batch is done only when its slowest instance
+is (an infeasible instance runs 42 iterations where the others stop at
+12-15), and the next batches fill the CUs its finished instances leave idle.
 `one_batch_at_a_time` on the same line is the rate when every step waits for
 the previous one; the roofline is that of single launches.
 
@@ -575,10 +575,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--uneven", type=int, default=4096, help="instances of the uneven leg (0: skip)")
     ap.add_argument("--uneven-steps", type=int, default=3)
-    ap.add_argument("--inflight", type=int, default=3,
-                    help="copies of the headline batch solved in turn on their own streams (1: one at a time; "
-                         "measured 2: 80k/s, 3: 112k/s, 4: 78k/s: the process has 4 hardware queues, shared with "
-                         "the default stream)")
+    ap.add_argument("--inflight", type=int, default=4,
+                    help="copies of the headline batch solved in turn on their own streams (1: one at a time): the "
+                         "three pool streams, then the default stream; the process has four hardware queues "
+                         "(measured: 3 in flight 116k/s, 4 in flight 124k/s; 4 on four new streams, two of them "
+                         "sharing a queue, 78k/s)")
     ap.add_argument("--pcond", default="1,5,10,15", help="condensed horizons for the partial-condensing leg (0: skip)")
     ap.add_argument("--pcond-steps", type=int, default=5)
     ap.add_argument("--warm-steps", type=int, default=5, help="timed solves of the warm-start leg (0: skip)")
@@ -643,7 +644,10 @@ def main():
         instance; every copy solves every instance of every step in full."""
         arg = B.default_arg(mode, **over)
         if inflight > 1:
-            streams = pool[:inflight] + [torch.cuda.Stream() for _ in range(inflight - len(pool))]
+            # the pool's streams first, then the default stream (the fourth
+            # hardware queue), then new streams (sharing queues)
+            streams = (pool + [torch.cuda.current_stream()])[:inflight]
+            streams += [torch.cuda.Stream() for _ in range(inflight - len(streams))]
             batches = [B.Batch(qps, arg, stream=st) for st in streams]
         else:
             batches = [B.Batch(qps, arg)]

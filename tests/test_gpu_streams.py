@@ -42,3 +42,26 @@ def test_extra_streams_bitwise_equal(mode, given):
         for k in KEYS:
             assert np.array_equal(a.sol[k], b.sol[k]) and np.array_equal(a.sol[k], c.sol[k]), (i, k)
     assert B.lib().oqp_batch_release(many.h) == 0
+
+
+def test_batches_in_flight_bitwise_equal():
+    """Three copies of a batch, each on its own stream, solved back to back
+    without waiting in between (the benchmark's batches in flight): every copy
+    returns bitwise the result of the batch solved alone, twice over."""
+    qps = [W.mass_spring_chain8(i) for i in range(64)] + [W.random_uneven(i) for i in range(16)]
+    print("three batches in flight vs one batch alone", flush=True)
+    sys.stdout.flush()
+    alone = B.Batch(qps).load().solve().fetch().sync().results()
+    copies = [B.Batch(qps, stream=torch.cuda.Stream()) for _ in range(3)]
+    for c in copies:
+        c.load()
+    for _ in range(2):
+        for c in copies:
+            c.solve()
+    torch.cuda.synchronize()
+    for c in copies:
+        res = c.fetch().sync().results()
+        for i, (a, r) in enumerate(zip(alone, res)):
+            assert a.status == r.status and a.iters == r.iters, i
+            for k in KEYS:
+                assert np.array_equal(a.sol[k], r.sol[k], equal_nan=True), (i, k)
