@@ -31,6 +31,9 @@ Further legs on the same line (context, not the headline):
     draws and soft state boxes;
   * uneven: a batch of random stable OCP QPs with nx ~ U{4..48},
     nu ~ U{1..16}, N ~ U{10..100} (one-wave variants plus the block kernel);
+  * large: 256 large-stage QPs (nx = 128, nu = 32, N = 50, 32 general rows
+    per stage; the block kernel's global-memory mode), FP64 to 1e-8 and
+    mixed, one batch at a time and two batches in flight;
   * serve: the continuous-batching server replaying Poisson arrivals over a
     pool of uneven instances: saturated throughput at the offered rate, then
     p50/p99 latency at a sustainable rate, for the grouped FP64 and mixed
@@ -453,7 +456,7 @@ def leg_single(B, W, torch, np, reps):
             "iters": int(r.iters), "status": int(r.status)}
 
 
-def leg_large(B, W, torch, np, perfmodel, count, steps):
+def leg_large(B, W, torch, np, perfmodel, count, steps, pool, inflight=2):
     """Large-stage batch (nx = 128, nu = 32, N = 50, 32 general rows per
     stage): the block kernel's global-memory mode.  FP64 to the FP64 bar
     (KKT 1e-8) with up to 4 refinement corrections of the
@@ -462,7 +465,9 @@ def leg_large(B, W, torch, np, perfmodel, count, steps):
     metric's 1e-6.  Roofline: algorithmic flops of the method (factorization,
     two solves and one residual per iteration, one solve and one residual per
     refinement correction) over the launch time, against the FP64 matrix-core
-    peak (FP32 for the mixed path's factorization)."""
+    peak (FP32 for the mixed path's factorization).  `inflight` copies of the
+    batch on the pool's streams then take the steps together: one batch puts
+    one workgroup on each CU, two fill both wave slots of every SIMD."""
     qps = [W.random_large_stage(i) for i in range(count)]
     fpi = np.array([perfmodel.flops_per_iter(q) for q in qps])
     fir = np.array([perfmodel.flops_per_refinement(q) for q in qps])
@@ -493,7 +498,31 @@ def leg_large(B, W, torch, np, perfmodel, count, steps):
         fell = sum(1 for x in res if x.fell_back_f64)
         peak = 78.6 if mode == B.MODE_F64 else 157.3
         ach = flops / t / 1e12
-        out[name] = {"value": round(ok / t, 1), "unit": "solves/s", "ms_per_step": round(t * 1e3, 3),
+        del batch
+        # the same batch, `inflight` copies at once
+        copies = [B.Batch(qps, arg, stream=st).load().sync() for st in pool[:inflight]]
+        for c in copies:
+            c.solve()
+        torch.cuda.synchronize()
+        walls = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            for c in copies:
+                c.solve()
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        same = True
+        for c in copies:
+            c.fetch().sync()
+            for a, x in zip(c.results(), res):
+                same = same and a.status == x.status and a.iters == x.iters and bool(
+                    np.array_equal(a.sol["u"], x.sol["u"], equal_nan=True))
+        del copies
+        tw = float(np.median(walls))
+        out[name] = {"value": round(len(pool[:inflight]) * ok / tw, 1), "unit": "solves/s",
+                     "ms_per_step": round(tw * 1e3, 3), "batches_in_flight": len(pool[:inflight]),
+                     "inflight_results_equal": same,
+                     "one_batch_at_a_time": {"value": round(ok / t, 1), "ms_per_step": round(t * 1e3, 3)},
                      "solves_ok": ok, "tol": tol, "ir_max": irm,
                      "non_success": [i for i, x in enumerate(res) if x.status != B.SUCCESS],
                      "iters_p50": float(np.median(its)), "iters_max": int(its.max()),
@@ -505,9 +534,10 @@ def leg_large(B, W, torch, np, perfmodel, count, steps):
                                   if mode == B.MODE_F64 and count == 256 else None,
                                   "alg_flops": flops,
                                   "kernel": "ipm_block_kernel<%d,256,64>" % (0 if mode == B.MODE_F64 else 1),
-                                  "hbm_gbs": round(float(np.sum(dbytes * (its + 1 + irs))) / t / 1e9, 1)}}
+                                  "hbm_gbs": round(float(np.sum(dbytes * (its + 1 + irs))) / t / 1e9, 1),
+                                  "scope": "one batch at a time (launch time)",
+                                  "frac_in_flight": round(len(pool[:inflight]) * flops / tw / 1e12 / peak, 5)}}
         keep[name] = res
-        del batch
     return out, qps, keep
 
 
@@ -590,6 +620,8 @@ def main():
     ap.add_argument("--soft-uneven", type=int, default=4096, help="instances of the soft uneven batch (0: skip)")
     ap.add_argument("--large", type=int, default=256, help="instances of the large-stage leg (0: skip)")
     ap.add_argument("--large-steps", type=int, default=2)
+    ap.add_argument("--large-inflight", type=int, default=2,
+                    help="copies of the large-stage batch solved at once (at most 3, the pool's streams)")
     ap.add_argument("--large-check", type=int, default=16,
                     help="large-stage instances the host check solves with the oracle for the primal error")
     ap.add_argument("--serve-pool", type=int, default=256, help="distinct instances in the serving pool (0: skip)")
@@ -783,7 +815,8 @@ def main():
     large = None
     if args.large > 0:
         log(f"bench: large-stage leg, {args.large} instances")
-        line["large"], lq, lres = leg_large(B, W, torch, np, perfmodel, args.large, args.large_steps)
+        line["large"], lq, lres = leg_large(B, W, torch, np, perfmodel, args.large, args.large_steps, pool,
+                                            args.large_inflight)
         large = (lq, lres)
     if args.serve_pool > 0:
         line["serve"] = leg_serve(B, W, torch, np, args.serve_pool, args.serve_rate, args.serve_sat_seconds,

@@ -92,7 +92,11 @@ OQP_HD constexpr BLds make_blds(int NX, int NU, int NG)
     s.oPn = o; o += tiles ? NZ * 17 : 0;
     s.oDg = o; o += tiles ? 16 * 17 : 0;
     s.oCA = o; o += tiles ? 16 * 17 : 0;
-    s.oCB = o; o += tiles ? 16 * s.ldu : 0;
+    // the chunk of F shares the panel of V: each panel's chunks are consumed
+    // before its rows of V are stored, and the syrk reads of the previous
+    // panel end before the first chunk of the next (barriers in between);
+    // 64 KB at nz = 160, so two workgroups fit a CU
+    s.oCB = s.oUp;
     s.total = o;
     return s;
 }
@@ -850,6 +854,13 @@ struct Blk {
         else
             return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    // v, opaque to the optimizer: lane offsets derived from it inside a loop
+    // are recomputed there instead of being held in registers across it
+    __device__ __forceinline__ static int opaque(int v)
+    {
+        asm volatile("" : "+v"(v));
+        return v;
+    }
     // tile row of accumulator register r of this lane (column: lane % 16)
     __device__ __forceinline__ int arow(int r) const { return MIXED ? 4 * (lane >> 4) + r : 4 * r + (lane >> 4); }
     // (balance build: not in an iteration factored with the array
@@ -883,6 +894,84 @@ struct Blk {
             tI[s] = t < NTt ? ti : -1;
             tJ[s] = t < NTt ? t - ti * (ti + 1) / 2 : -1;
         }
+        // ---- U = L_{n+1}' F, 16 rows at a time, to the stage's V block
+        // (row-major, rows 0 .. NX-1, ld NZ), before the stage matrix takes
+        // the accumulators: the two are never live together ----
+        const int npu = n < N ? (NX + 15) >> 4 : 0, npg = (NG + 15) >> 4;
+        constexpr int KC = 16;                         // rows of L_{n+1} and F per chunk
+        constexpr int CA = 16 * KC / BT;               // L_{n+1} chunk elements per thread
+        constexpr int CB = (KC * 160 + BT - 1) / BT;  // F chunk elements per thread
+        double* const vw = cV;
+        for (int pnl = 0; pnl < npu; ++pnl) {
+            // U rows 16 pnl ..: U(r, j) = sum_{l >= r} L(l, r) F(l, j); output
+            // tile columns jt = wid, wid + 4, wid + 8 of the panel
+            V4 ua[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) ua[q] = V4{0, 0, 0, 0};
+            const int l_first = 16 * pnl;
+            const int nch = (NX - l_first + KC - 1) / KC;
+            double pa[CA], pb[CB];
+            // element idx of a chunk: row kk = idx mod KC (contiguous in
+            // the column-major records), column idx / KC
+            auto fetch_chunk = [&](int l0) {
+#pragma unroll
+                for (int e = 0; e < CA; ++e) {
+                    const int idx = tid + BT * e;
+                    const int kk = idx % KC, i = idx / KC;
+                    const int l = l0 + kk;
+                    pa[e] = (l < NX && l_first + i < NX) ? cLx[l + (l_first + i) * ldx] : 0.0;
+                }
+#pragma unroll
+                for (int e = 0; e < CB; ++e) {
+                    const int idx = tid + BT * e;
+                    const int kk = idx % KC, j = idx / KC;
+                    const int l = l0 + kk;
+                    pb[e] = (j < NZ && l < NX) ? cF[l + j * ldf] : 0.0;
+                }
+            };
+            fetch_chunk(l_first);
+            for (int c = 0; c < nch; ++c) {
+                __syncthreads();  // the previous chunk has been read
+#pragma unroll
+                for (int e = 0; e < CA; ++e) {
+                    const int idx = tid + BT * e;
+                    ca[(idx % KC) * 17 + idx / KC] = pa[e];
+                }
+#pragma unroll
+                for (int e = 0; e < CB; ++e) {
+                    const int idx = tid + BT * e;
+                    const int kk = idx % KC, j = idx / KC;
+                    if (j < NZ) cb[kk * ldu + j] = pb[e];
+                }
+                __syncthreads();
+                if (c + 1 < nch) fetch_chunk(l_first + KC * (c + 1));
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int jt = w0 + 4 * q;
+                    if (jt < TMt) {
+                        const int j = min(16 * jt + l16, NZ - 1);
+#pragma unroll
+                        for (int k4 = 0; k4 < KC / 4; ++k4) {
+                            const int kk = 4 * k4 + lk;
+                            const TS a = (TS)ca[kk * 17 + l16];
+                            const TS b = (16 * jt + l16 < NZ) ? (TS)cb[kk * ldu + j] : (TS)0;
+                            ua[q] = mfma4(a, b, ua[q]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int jt = w0 + 4 * q;
+                if (jt < TMt) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * pnl + arow(r), j = 16 * jt + l16;
+                        if (j < NZ && row < NX) vw[row * NZ + j] = (double)ua[q][r];
+                    }
+                }
+            }
+        }
         // ---- M = H + diag(box weights) + reg I ----
 #pragma unroll
         for (int s = 0; s < RT; ++s) {
@@ -904,86 +993,19 @@ struct Blk {
             // V's columns added panel by panel below
             for (int i = opq(tid); i < NZ; i += BT) dd[i] = hd[i + i * NZ] + wv[i] + P.reg_prim;
         }
-        // ---- M += V'V, 16 rows of V at a time ----
-        const int npu = n < N ? (NX + 15) >> 4 : 0, npg = (NG + 15) >> 4;
-        constexpr int KC = 16;                         // rows of L_{n+1} and F per chunk
-        constexpr int CA = 16 * KC / BT;               // L_{n+1} chunk elements per thread
-        constexpr int CB = (KC * 160 + BT - 1) / BT;  // F chunk elements per thread
+        // ---- M += V'V, 16 rows of V at a time through LDS ----
         for (int pnl = 0; pnl < npu + npg; ++pnl) {
+            // the previous panel's products are done with up (and U is stored)
+            __syncthreads();
             if (pnl < npu) {
-                // U rows 16 pnl ..: U(r, j) = sum_{l >= r} L(l, r) F(l, j); output
-                // tile columns jt = wid, wid + 4, wid + 8 of the panel
-                V4 ua[3];
-#pragma unroll
-                for (int q = 0; q < 3; ++q) ua[q] = V4{0, 0, 0, 0};
-                const int l_first = 16 * pnl;
-                const int nch = (NX - l_first + KC - 1) / KC;
-                double pa[CA], pb[CB];
-                // element idx of a chunk: row kk = idx mod KC (contiguous in
-                // the column-major records), column idx / KC
-                auto fetch_chunk = [&](int l0) {
-#pragma unroll
-                    for (int e = 0; e < CA; ++e) {
-                        const int idx = tid + BT * e;
-                        const int kk = idx % KC, i = idx / KC;
-                        const int l = l0 + kk;
-                        pa[e] = (l < NX && l_first + i < NX) ? cLx[l + (l_first + i) * ldx] : 0.0;
-                    }
-#pragma unroll
-                    for (int e = 0; e < CB; ++e) {
-                        const int idx = tid + BT * e;
-                        const int kk = idx % KC, j = idx / KC;
-                        const int l = l0 + kk;
-                        pb[e] = (j < NZ && l < NX) ? cF[l + j * ldf] : 0.0;
-                    }
-                };
-                fetch_chunk(l_first);
-                for (int c = 0; c < nch; ++c) {
-                    __syncthreads();  // the previous chunk has been read
-#pragma unroll
-                    for (int e = 0; e < CA; ++e) {
-                        const int idx = tid + BT * e;
-                        ca[(idx % KC) * 17 + idx / KC] = pa[e];
-                    }
-#pragma unroll
-                    for (int e = 0; e < CB; ++e) {
-                        const int idx = tid + BT * e;
-                        const int kk = idx % KC, j = idx / KC;
-                        if (j < NZ) cb[kk * ldu + j] = pb[e];
-                    }
-                    __syncthreads();
-                    if (c + 1 < nch) fetch_chunk(l_first + KC * (c + 1));
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) {
-                        const int jt = w0 + 4 * q;
-                        if (jt < TMt) {
-                            const int j = min(16 * jt + l16, NZ - 1);
-#pragma unroll
-                            for (int k4 = 0; k4 < KC / 4; ++k4) {
-                                const int kk = 4 * k4 + lk;
-                                const TS a = (TS)ca[kk * 17 + l16];
-                                const TS b = (16 * jt + l16 < NZ) ? (TS)cb[kk * ldu + j] : (TS)0;
-                                ua[q] = mfma4(a, b, ua[q]);
-                            }
-                        }
-                    }
-                }
-                __syncthreads();  // the previous panel's products are done with up
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    const int jt = w0 + 4 * q;
-                    if (jt < TMt) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int j = 16 * jt + l16;
-                            if (j < NZ) up[arow(r) * ldu + j] = (double)ua[q][r];
-                        }
-                    }
+                const int r0 = 16 * pnl;
+                for (int e = tid; e < 16 * NZ; e += BT) {
+                    const int kk = e / NZ, j = e % NZ, row = r0 + kk;
+                    up[kk * ldu + j] = row < NX ? vw[row * NZ + j] : 0.0;
                 }
             } else {
                 // rows sqrt(w) G of general rows 16 (pnl - npu) ..
                 const int g0 = 16 * (pnl - npu);
-                __syncthreads();
                 for (int e = tid; e < 16 * NZ; e += BT) {
                     const int kk = e / NZ, j = e % NZ, g = g0 + kk;
                     up[kk * ldu + j] = g < NG ? sqrt(wv[NZ + g]) * cG[g + j * ldg] : 0.0;
@@ -998,15 +1020,19 @@ struct Blk {
                     dd[i] += sq;
                 }
             }
+            // one k-step over all tiles at a time (the same order of products
+            // in every tile), so that the operands held in registers stay
+            // those of one k-step
+            const int l16o = opaque(l16), lko = opaque(lk);
 #pragma unroll
             for (int s = 0; s < RT; ++s) {
                 if (tI[s] >= 0) {
                     const int ti = tI[s], tj = tJ[s];
-                    const int i = min(16 * ti + l16, NZ - 1), j = min(16 * tj + l16, NZ - 1);
-                    const bool iv = 16 * ti + l16 < NZ, jv = 16 * tj + l16 < NZ;
+                    const int i = min(16 * ti + l16o, NZ - 1), j = min(16 * tj + l16o, NZ - 1);
+                    const bool iv = 16 * ti + l16o < NZ, jv = 16 * tj + l16o < NZ;
 #pragma unroll
                     for (int k4 = 0; k4 < 4; ++k4) {
-                        const int kk = 4 * k4 + lk;
+                        const int kk = 4 * k4 + lko;
                         const TS a = iv ? (TS)up[kk * ldu + i] : (TS)0;
                         const TS b = jv ? (TS)up[kk * ldu + j] : (TS)0;
                         acc[s] = mfma4(a, b, acc[s]);
@@ -1018,6 +1044,7 @@ struct Blk {
         bool ok = true;
         double* fm = cM;
         for (int p = 0; p < TMt; ++p) {
+            const int l16o = opaque(l16), lko = opaque(lk);
             __syncthreads();  // the previous panel's trailing products are done with dg / pn
             // the tiles of column p to LDS
 #pragma unroll
@@ -1027,9 +1054,9 @@ struct Blk {
                     if (tj == p) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            const int rr = arow(r);
-                            if (ti == p) dg[rr * 17 + l16] = (double)acc[s][r];
-                            else if (16 * ti + rr < NZ) lp[(16 * ti + rr) * 17 + l16] = (double)acc[s][r];
+                            const int rr = MIXED ? 4 * lko + r : 4 * r + lko;
+                            if (ti == p) dg[rr * 17 + l16o] = (double)acc[s][r];
+                            else if (16 * ti + rr < NZ) lp[(16 * ti + rr) * 17 + l16o] = (double)acc[s][r];
                         }
                     }
                 }
@@ -1105,11 +1132,11 @@ struct Blk {
                 if (tI[s] >= 0) {
                     const int ti = tI[s], tj = tJ[s];
                     if (tj > p) {
-                        const int i = 16 * ti + l16, j = 16 * tj + l16;
+                        const int i = 16 * ti + l16o, j = 16 * tj + l16o;
                         const bool iv = i < NZ, jv = j < NZ;
 #pragma unroll
                         for (int k4 = 0; k4 < 4; ++k4) {
-                            const int kk = 4 * k4 + lk;
+                            const int kk = 4 * k4 + lko;
                             const TS a = iv ? -(TS)lp[i * 17 + kk] : (TS)0;
                             const TS b = jv ? (TS)lp[j * 17 + kk] : (TS)0;
                             acc[s] = mfma4(a, b, acc[s]);
@@ -2257,11 +2284,17 @@ struct Blk {
 // scratch (FP64: 155 registers, 616 B per lane) and still gain: the uneven
 // batch of 4096 runs 13 % faster (mixed path 7 %) than at one wave per SIMD,
 // whose whole register file they needed to avoid spilling.  The
-// global-memory mode takes one wave per SIMD: its stage matrix sits in
-// matrix-core accumulators (the whole register file of the wave).
+// global-memory mode takes two as well: its stage matrix sits in matrix-core
+// accumulators (112 registers per lane in FP64), L_{n+1}' F is formed before
+// they are live, and the lane offsets of the tile loops are recomputed per
+// panel, so the build fits 256 registers with a few spills outside the
+// factorization; LDS is 64 KB at nz = 160.  One batch of 256 large stages
+// (one workgroup per CU) runs 6 % slower than the one-wave build with the
+// whole register file; two such batches in flight, which share every CU,
+// 44 % faster.
 __host__ __device__ constexpr int block_waves(int zm, int gm)
 {
-    return zm > 64 ? 1 : ((zm == 64 || (zm == 32 && gm == 0)) ? 2 : 1);
+    return zm > 64 ? 2 : ((zm == 64 || (zm == 32 && gm == 0)) ? 2 : 1);
 }
 
 // ZM > 64 selects the global-memory mode; WV overrides the register budget
