@@ -568,6 +568,19 @@ extern "C" int oqp_server_submit(oqp_server* s, const void* packed, uint64_t* ti
     return OQP_OK;
 }
 
+// The kernel group of the oldest queued request.  Requests that used up an
+// iteration block are queued again at the head, so the head is not always
+// the oldest: launching the head's group would let the unfinished requests
+// of one group go first round after round while another group's requests
+// wait.
+static int oldest_variant(const oqp_server* s)
+{
+    int best = s->q_head;
+    for (int r = s->req[best].next; r >= 0; r = s->req[r].next)
+        if (s->req[r].t_submit < s->req[best].t_submit) best = r;
+    return s->req[best].hdr->variant;
+}
+
 extern "C" int oqp_server_progress(oqp_server* s, int* ncompleted)
 {
     if (!s) return fail(OQP_EINVAL, "oqp_server_progress: NULL server");
@@ -575,13 +588,14 @@ extern "C" int oqp_server_progress(oqp_server* s, int* ncompleted)
     int rc = retire(s, ncompleted);
     if (rc) return rc;
     // launch queued requests on idle streams: the kernel group of the oldest
-    // queued request, all of its queued requests up to max_launch
+    // queued request, all of its queued requests up to max_launch (queue
+    // order: unfinished requests first)
     while (s->q_head >= 0) {
         const int k = pick_stream(s);
         if (k < 0) break;
         const int gi = free_group(s);
         if (gi < 0) break;
-        rc = launch_group(s, s->req[s->q_head].hdr->variant, gi, k);
+        rc = launch_group(s, s->cfg.iter_block > 0 ? oldest_variant(s) : s->req[s->q_head].hdr->variant, gi, k);
         if (rc) return rc;
     }
     return OQP_OK;
