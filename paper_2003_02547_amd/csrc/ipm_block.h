@@ -844,6 +844,13 @@ struct Blk {
     // every row in FP64 (the pivots) as in the other factorizations.
     // ------------------------------------------------------------------
     static constexpr int RT = 14;  // tiles per wave: 4 x 14 >= 55, the lower tiles of a 160-wide block
+    // sequential triangular sweeps of wave 0 (forward and backward
+    // substitution with a diagonal block): factor entries loaded PCH columns
+    // at a time, ahead of the dependent steps.  The global-memory mode reads
+    // the factor from HBM/L2 (16 at a time: 3 % on the large-stage batch);
+    // the LDS-resident builds load one per step (16 at a time cost them
+    // registers and 6 % on the uneven batch).
+    static constexpr int PCH = GL ? 16 : 1;
     static constexpr bool TILES = GL && !ROBUST;
     using V4 = TS __attribute__((ext_vector_type(4)));
 
@@ -1166,10 +1173,23 @@ struct Blk {
         mv = rnd(mv);
         if (wid == 0) {
             double v = mv;
-            for (int j = 0; j < NU; ++j) {
-                const double y = rnd(bcast(v, j) * bcast(di, j));
-                if (lane == j) v = y;
-                else if (lane > j && lane < NU) v = (double)((TS)v - (TS)m[lane + j * ldm] * (TS)y);
+            // PCH columns of the factor at a time, their loads issued
+            // together ahead of the dependent steps
+            for (int j0 = 0; j0 < NU; j0 += PCH) {
+                double lc[PCH];
+#pragma unroll
+                for (int q = 0; q < PCH; ++q) {
+                    const int j = j0 + q;
+                    lc[q] = (j < NU && lane > j && lane < NU) ? m[lane + j * ldm] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < PCH; ++q) {
+                    const int j = j0 + q;
+                    if (j >= NU) break;
+                    const double y = rnd(bcast(v, j) * bcast(di, j));
+                    if (lane == j) v = y;
+                    else if (lane > j && lane < NU) v = (double)((TS)v - (TS)lc[q] * (TS)y);
+                }
             }
             if (lane < NU) yv[lane] = v;
         }
@@ -1190,10 +1210,23 @@ struct Blk {
             const int bn = min(64, n - b0);
             if (wid == 0) {
                 double v = lane < bn ? rnd(x[b0 + lane]) : 0.0;
-                for (int c = 0; c < bn; ++c) {
-                    const double y = rnd(bcast(v, c) * di[b0 + c]);
-                    if (lane == c) v = y;
-                    else if (lane > c && lane < bn) v = (double)((TS)v - (TS)L[(b0 + lane) + (b0 + c) * ld] * (TS)y);
+                // PCH columns at a time, their loads issued together
+                for (int c0 = 0; c0 < bn; c0 += PCH) {
+                    double lc[PCH], dc[PCH];
+#pragma unroll
+                    for (int q = 0; q < PCH; ++q) {
+                        const int c = c0 + q;
+                        lc[q] = (c < bn && lane > c && lane < bn) ? L[(b0 + lane) + (b0 + c) * ld] : 0.0;
+                        dc[q] = c < bn ? di[b0 + c] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < PCH; ++q) {
+                        const int c = c0 + q;
+                        if (c >= bn) break;
+                        const double y = rnd(bcast(v, c) * dc[q]);
+                        if (lane == c) v = y;
+                        else if (lane > c && lane < bn) v = (double)((TS)v - (TS)lc[q] * (TS)y);
+                    }
                 }
                 if (lane < bn) x[b0 + lane] = v;
             }
@@ -1210,10 +1243,24 @@ struct Blk {
             const int b0 = max(0, b1 - 64), bn = b1 - b0;
             if (wid == 0) {
                 double v = lane < bn ? rnd(x[b0 + lane]) : 0.0;
-                for (int c = bn - 1; c >= 0; --c) {
-                    const double xv = rnd(bcast(v, c) * di[b0 + c]);
-                    if (lane == c) v = xv;
-                    else if (lane < c) v = (double)((TS)v - (TS)L[(b0 + c) + (b0 + lane) * ld] * (TS)xv);
+                // PCH rows of L at a time (from the last), their loads
+                // issued together
+                for (int c1 = bn; c1 > 0; c1 -= PCH) {
+                    double lc[PCH], dc[PCH];
+#pragma unroll
+                    for (int q = 0; q < PCH; ++q) {
+                        const int c = c1 - 1 - q;
+                        lc[q] = (c >= 0 && lane < c) ? L[(b0 + c) + (b0 + lane) * ld] : 0.0;
+                        dc[q] = c >= 0 ? di[b0 + c] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < PCH; ++q) {
+                        const int c = c1 - 1 - q;
+                        if (c < 0) break;
+                        const double xv = rnd(bcast(v, c) * dc[q]);
+                        if (lane == c) v = xv;
+                        else if (lane < c) v = (double)((TS)v - (TS)lc[q] * (TS)xv);
+                    }
                 }
                 if (lane < bn) x[b0 + lane] = v;
             }
@@ -1696,10 +1743,23 @@ struct Blk {
                 const double* x = xn(cur);
                 double v = 0.0;
                 if (lane < NU) v = (double)((TS)yu + dot<TS>(mu + NU + lane * ldm, 1, x, 1, NX));
-                for (int c = NU - 1; c >= 0; --c) {
-                    const double xv = rnd(bcast(v, c) * bcast(di, c));
-                    if (lane == c) v = xv;
-                    else if (lane < c) v = (double)((TS)v - (TS)mu[c + lane * ldm] * (TS)xv);
+                // PCH rows of L_uu at a time (from the last), their loads
+                // issued together
+                for (int c1 = NU; c1 > 0; c1 -= PCH) {
+                    double lc[PCH];
+#pragma unroll
+                    for (int q = 0; q < PCH; ++q) {
+                        const int c = c1 - 1 - q;
+                        lc[q] = (c >= 0 && lane < c) ? mu[c + lane * ldm] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < PCH; ++q) {
+                        const int c = c1 - 1 - q;
+                        if (c < 0) break;
+                        const double xv = rnd(bcast(v, c) * bcast(di, c));
+                        if (lane == c) v = xv;
+                        else if (lane < c) v = (double)((TS)v - (TS)lc[q] * (TS)xv);
+                    }
                 }
                 if (lane < NU) {
                     z()[lane] = -v;
