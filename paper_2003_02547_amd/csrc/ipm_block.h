@@ -233,6 +233,25 @@ struct Blk {
     {
         T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
         int k = 0;
+        if constexpr (GL) {
+            // global-memory mode (operands in HBM/L2): 16 loads issued
+            // together, the sums taken in the same order as below
+            for (; k + 16 <= n; k += 16) {
+                double av[16], bv[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    av[q] = a[(k + q) * sa];
+                    bv[q] = b[(k + q) * sb];
+                }
+#pragma unroll
+                for (int q = 0; q < 16; q += 4) {
+                    s0 += (T)av[q] * (T)bv[q];
+                    s1 += (T)av[q + 1] * (T)bv[q + 1];
+                    s2 += (T)av[q + 2] * (T)bv[q + 2];
+                    s3 += (T)av[q + 3] * (T)bv[q + 3];
+                }
+            }
+        }
 #pragma unroll 2
         for (; k + 4 <= n; k += 4) {
             const double a0 = a[k * sa], a1 = a[(k + 1) * sa], a2 = a[(k + 2) * sa], a3 = a[(k + 3) * sa];
