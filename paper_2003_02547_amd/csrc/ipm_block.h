@@ -1023,19 +1023,31 @@ struct Blk {
         for (int pnl = 0; pnl < npu + npg; ++pnl) {
             // the previous panel's products are done with up (and U is stored)
             __syncthreads();
+            // all of a thread's loads issued before its LDS stores (element
+            // offsets recomputed per panel, not held across the loop)
+            constexpr int EV = (16 * 160 + BT - 1) / BT;
+            const int tdo = opaque(tid);
+            double vv[EV];
             if (pnl < npu) {
                 const int r0 = 16 * pnl;
-                for (int e = tid; e < 16 * NZ; e += BT) {
-                    const int kk = e / NZ, j = e % NZ, row = r0 + kk;
-                    up[kk * ldu + j] = row < NX ? vw[row * NZ + j] : 0.0;
+#pragma unroll
+                for (int t = 0; t < EV; ++t) {
+                    const int e = tdo + BT * t, kk = e / NZ, j = e % NZ, row = r0 + kk;
+                    vv[t] = (e < 16 * NZ && row < NX) ? vw[row * NZ + j] : 0.0;
                 }
             } else {
                 // rows sqrt(w) G of general rows 16 (pnl - npu) ..
                 const int g0 = 16 * (pnl - npu);
-                for (int e = tid; e < 16 * NZ; e += BT) {
-                    const int kk = e / NZ, j = e % NZ, g = g0 + kk;
-                    up[kk * ldu + j] = g < NG ? sqrt(wv[NZ + g]) * cG[g + j * ldg] : 0.0;
+#pragma unroll
+                for (int t = 0; t < EV; ++t) {
+                    const int e = tdo + BT * t, kk = e / NZ, j = e % NZ, g = g0 + kk;
+                    vv[t] = (e < 16 * NZ && g < NG) ? sqrt(wv[NZ + g]) * cG[g + j * ldg] : 0.0;
                 }
+            }
+#pragma unroll
+            for (int t = 0; t < EV; ++t) {
+                const int e = tdo + BT * t;
+                if (e < 16 * NZ) up[(e / NZ) * ldu + e % NZ] = vv[t];
             }
             __syncthreads();
             if constexpr (MIXED) {
