@@ -500,27 +500,29 @@ def leg_large(B, W, torch, np, perfmodel, count, steps, pool, inflight=2):
         ach = flops / t / 1e12
         del batch
         # the same batch, `inflight` copies at once
-        copies = [B.Batch(qps, arg, stream=st).load().sync() for st in pool[:inflight]]
-        for c in copies:
-            c.solve()
-        torch.cuda.synchronize()
-        walls = []
-        for _ in range(steps):
-            t0 = time.perf_counter()
+        nb, tw, same = 1, t, True
+        if inflight > 1:
+            copies = [B.Batch(qps, arg, stream=st).load().sync() for st in pool[:inflight]]
+            nb = len(copies)
             for c in copies:
                 c.solve()
             torch.cuda.synchronize()
-            walls.append(time.perf_counter() - t0)
-        same = True
-        for c in copies:
-            c.fetch().sync()
-            for a, x in zip(c.results(), res):
-                same = same and a.status == x.status and a.iters == x.iters and bool(
-                    np.array_equal(a.sol["u"], x.sol["u"], equal_nan=True))
-        del copies
-        tw = float(np.median(walls))
-        out[name] = {"value": round(len(pool[:inflight]) * ok / tw, 1), "unit": "solves/s",
-                     "ms_per_step": round(tw * 1e3, 3), "batches_in_flight": len(pool[:inflight]),
+            walls = []
+            for _ in range(steps):
+                t0 = time.perf_counter()
+                for c in copies:
+                    c.solve()
+                torch.cuda.synchronize()
+                walls.append(time.perf_counter() - t0)
+            for c in copies:
+                c.fetch().sync()
+                for a, x in zip(c.results(), res):
+                    same = same and a.status == x.status and a.iters == x.iters and bool(
+                        np.array_equal(a.sol["u"], x.sol["u"], equal_nan=True))
+            del copies
+            tw = float(np.median(walls))
+        out[name] = {"value": round(nb * ok / tw, 1), "unit": "solves/s",
+                     "ms_per_step": round(tw * 1e3, 3), "batches_in_flight": nb,
                      "inflight_results_equal": same,
                      "one_batch_at_a_time": {"value": round(ok / t, 1), "ms_per_step": round(t * 1e3, 3)},
                      "solves_ok": ok, "tol": tol, "ir_max": irm,
@@ -536,7 +538,7 @@ def leg_large(B, W, torch, np, perfmodel, count, steps, pool, inflight=2):
                                   "kernel": "ipm_block_kernel<%d,256,64>" % (0 if mode == B.MODE_F64 else 1),
                                   "hbm_gbs": round(float(np.sum(dbytes * (its + 1 + irs))) / t / 1e9, 1),
                                   "scope": "one batch at a time (launch time)",
-                                  "frac_in_flight": round(len(pool[:inflight]) * flops / tw / 1e12 / peak, 5)}}
+                                  "frac_in_flight": round(nb * flops / tw / 1e12 / peak, 5)}}
         keep[name] = res
     return out, qps, keep
 
