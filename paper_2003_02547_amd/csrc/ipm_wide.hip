@@ -89,6 +89,17 @@ __device__ __forceinline__ double dot(const double* a, int sa, const double* b, 
 {
     double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int k = 0;
+    // 16 loads issued together, the sums taken in the order of the loop below
+    for (; k + 16 <= n; k += 16) {
+        double av[16], bv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            av[u] = a[(k + u) * sa];
+            bv[u] = b[(k + u) * sb];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s[u & 7] += av[u] * bv[u];
+    }
     for (; k + 8 <= n; k += 8) {
         double av[8], bv[8];
 #pragma unroll
