@@ -122,3 +122,27 @@ def test_global_mode_batch_invariance_bitwise():
         assert alone.status == full[i].status and alone.iters == full[i].iters
         for k in KEYS:
             assert np.array_equal(full[i].sol[k], alone.sol[k]), (i, k)
+
+
+def test_global_mode_workgroups_sharing_a_cu_bitwise():
+    """More global-mode instances than CUs in one launch, and two such
+    batches in flight on two streams: workgroups then share CUs (the build
+    takes two waves per SIMD); every instance returns bitwise the result it
+    has when solved alone."""
+    distinct = [medium(i) for i in range(16)]
+    qps = [distinct[i % 16] for i in range(320)]
+    say("global mode: 2 x 320 instances in flight vs each instance alone")
+    alone = [B.solve([q])[0] for q in distinct]
+    copies = [B.Batch(qps, stream=torch.cuda.Stream()) for _ in range(2)]
+    for c in copies:
+        c.load()
+    for c in copies:
+        c.solve()
+    torch.cuda.synchronize()
+    for c in copies:
+        res = c.fetch().sync().results()
+        for i, r in enumerate(res):
+            a = alone[i % 16]
+            assert r.status == a.status and r.iters == a.iters, i
+            for k in KEYS:
+                assert np.array_equal(r.sol[k], a.sol[k], equal_nan=True), (i, k)
