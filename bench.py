@@ -37,7 +37,9 @@ Further legs on the same line (context, not the headline):
   * serve: the continuous-batching server replaying Poisson arrivals over a
     pool of uneven instances: saturated throughput at the offered rate, then
     p50/p99 latency at a sustainable rate, for the grouped FP64 and mixed
-    paths and the plain per-request FP64 path (one launch per request).
+    paths and the plain per-request FP64 path (one launch per request), and
+    the grouped FP64 path offered its saturated throughput as a steady stream
+    (the largest sustained rate).
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
 (algorithmic bytes / kernel time from HIP events on the launch stream) and
@@ -587,6 +589,13 @@ def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_secon
         out[name] = run(mode, ml, rate, sus_seconds, 3)
     log(f"bench: serve f64 with iteration blocks at {rate:.0f} req/s for {sus_seconds:.0f} s")
     out["f64_blocks"] = run(B.MODE_F64, 256, rate, sus_seconds, 3, iter_block=iter_block)
+    # the largest sustained rate: the saturated throughput offered as a
+    # steady Poisson stream (latency stays bounded when it is sustained)
+    top = max(10.0, round(sat["served_per_s"], -1))
+    out["sustained_max_rate_per_s"] = top
+    log(f"bench: serve f64 at the saturated rate, {top:.0f} req/s for {sus_seconds:.0f} s (plain and in iteration blocks)")
+    out["f64_at_saturated_rate"] = run(B.MODE_F64, 256, top, sus_seconds, 4)
+    out["f64_blocks_at_saturated_rate"] = run(B.MODE_F64, 256, top, sus_seconds, 4, iter_block=iter_block)
     log(f"bench: serve f64 with soft state boxes (first x0 draws) at {rate:.0f} req/s for {sus_seconds:.0f} s")
     out["f64_soft"] = run(B.MODE_F64, 256, rate, sus_seconds, 3, packed_soft)
     # plain per-request FP64 path (one launch per request): same offered rate
