@@ -546,7 +546,7 @@ def leg_large(B, W, torch, np, perfmodel, count, steps, pool, inflight=2):
 
 
 def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_seconds, per_req_seconds, log,
-              iter_block=4):
+              iter_block=4, nstreams=5):
     """Continuous-batching server, native real-time replay of Poisson
     arrivals over a pool of pre-packed uneven instances (page-locked host
     memory; each request's data is uploaded on admission); also the same
@@ -560,7 +560,7 @@ def leg_serve(B, W, torch, np, pool_n, offered, sat_seconds, sus_frac, sus_secon
 
     def run(mode, max_launch, rate, seconds, seed, pk=None, iter_block=0):
         pk = packed if pk is None else pk
-        srv = B.Server(B.default_arg(mode, **tol), dev_bytes=dev_bytes, nstreams=5, max_launch=max_launch,
+        srv = B.Server(B.default_arg(mode, **tol), dev_bytes=dev_bytes, nstreams=nstreams, max_launch=max_launch,
                        max_requests=4096, max_groups=1024, iter_block=iter_block)
         try:
             times, idx = W.serving_stream(rate, seconds, pool_n, seed=seed)
@@ -641,6 +641,8 @@ def main():
     ap.add_argument("--serve-frac", type=float, default=0.5, help="sustained rate as a fraction of saturated throughput")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--serve-per-request-seconds", type=float, default=0.2)
+    ap.add_argument("--serve-streams", type=int, default=5,
+                    help="server streams (one for solution fetches, the rest for launches)")
     ap.add_argument("--serve-iter-block", type=int, default=4,
                     help="IPM iterations per launch in the iteration-block serving runs")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -832,7 +834,7 @@ def main():
     if args.serve_pool > 0:
         line["serve"] = leg_serve(B, W, torch, np, args.serve_pool, args.serve_rate, args.serve_sat_seconds,
                                   args.serve_frac, args.serve_seconds, args.serve_per_request_seconds, log,
-                                  args.serve_iter_block)
+                                  args.serve_iter_block, args.serve_streams)
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline (~{args.cpu_seconds:.0f} s)")
         line["cpu_baseline"], refs = cpu_baseline(qps, args.cpu_seconds, 1e-8, W.mass_spring_chain4(1))
