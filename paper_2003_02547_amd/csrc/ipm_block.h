@@ -345,21 +345,23 @@ struct Blk {
     __device__ __forceinline__ void fetch(Pre& p) const
     {
         if constexpr (GL) return;
+        // element offsets recomputed per stage, not held across the loop
+        const int tdo = opaque(tid);
 #pragma unroll
         for (int t = 0; t < EA; ++t) {
-            const int e = tid + BT * t;
+            const int e = tdo + BT * t;
             const double* src = e < p.na1 ? p.sa : p.sa2;
             p.a[t] = e < p.na ? src[e] : 0.0;
         }
 #pragma unroll
         for (int t = 0; t < EF; ++t) {
-            const int e = tid + BT * t;
+            const int e = tdo + BT * t;
             p.f[t] = e < p.nf ? p.sf[e] : 0.0;
         }
         if constexpr (GM > 0) {
 #pragma unroll
             for (int t = 0; t < EG; ++t) {
-                const int e = tid + BT * t;
+                const int e = tdo + BT * t;
                 p.g[t] = e < p.ng ? p.sg[e] : 0.0;
             }
         }
@@ -368,29 +370,30 @@ struct Blk {
     __device__ __forceinline__ void commit(const Pre& p, double* da, double* df, double* dg) const
     {
         if constexpr (GL) return;
+        const int tdo = opaque(tid);
         {
-            Walk q(NZ, tid);
+            Walk q(NZ, tdo);
 #pragma unroll
             for (int t = 0; t < EA; ++t) {
-                const int e = tid + BT * t;
+                const int e = tdo + BT * t;
                 if (e < p.na) da[q.r + q.c * ldm] = p.a[t];
                 q.next();
             }
         }
         {
-            Walk q(NX, tid);
+            Walk q(NX, tdo);
 #pragma unroll
             for (int t = 0; t < EF; ++t) {
-                const int e = tid + BT * t;
+                const int e = tdo + BT * t;
                 if (e < p.nf) df[q.r + q.c * ldf] = p.f[t];
                 q.next();
             }
         }
         if constexpr (GM > 0) {
-            Walk q(NG, tid);
+            Walk q(NG, tdo);
 #pragma unroll
             for (int t = 0; t < EG; ++t) {
-                const int e = tid + BT * t;
+                const int e = tdo + BT * t;
                 if (e < p.ng) dg[q.r + q.c * ldg] = p.g[t];
                 q.next();
             }
@@ -2370,11 +2373,11 @@ struct Blk {
 
 // Waves per SIMD the register budget is sized for: two, so that two
 // instances share a CU and hide each other's latency, wherever LDS allows it,
-// except stage blocks up to 32 with general rows (one wave, no spills).  The
-// 64-wide builds then spill part of their stage prefetch registers to
-// scratch (FP64: 155 registers, 616 B per lane) and still gain: the uneven
-// batch of 4096 runs 13 % faster (mixed path 7 %) than at one wave per SIMD,
-// whose whole register file they needed to avoid spilling.  The
+// except stage blocks up to 32 with general rows (one wave).  The uneven
+// batch of 4096 runs 13 % faster (mixed path 7 %) than at one wave per SIMD.
+// The 64-wide builds without general rows fit 256 registers with no spill
+// once the stage prefetch recomputes its element offsets per stage (they
+// had spilled 172-273 registers to scratch).  The
 // global-memory mode takes two as well: its stage matrix sits in matrix-core
 // accumulators (112 registers per lane in FP64), L_{n+1}' F is formed before
 // they are live, and the lane offsets of the tile loops are recomputed per
