@@ -2371,13 +2371,14 @@ struct Blk {
     }
 };
 
-// Waves per SIMD the register budget is sized for: two, so that two
-// instances share a CU and hide each other's latency, wherever LDS allows it,
-// except stage blocks up to 32 with general rows (one wave).  The uneven
-// batch of 4096 runs 13 % faster (mixed path 7 %) than at one wave per SIMD.
-// The 64-wide builds without general rows fit 256 registers with no spill
-// once the stage prefetch recomputes its element offsets per stage (they
-// had spilled 172-273 registers to scratch).  The
+// Waves per SIMD the register budget is sized for: two in every build, so
+// that two instances share a CU and hide each other's latency wherever LDS
+// allows it.  The uneven batch of 4096 runs 13 % faster (mixed path 7 %)
+// than at one wave per SIMD.  The stage prefetch recomputes its element
+// offsets per stage, so the 32- and 64-wide builds fit 256 registers with no
+// spill (with general rows at 64: 4-26; they had spilled up to 410); the
+// 32-wide build with general rows, one wave per SIMD before, runs the
+// 8-mass batch condensed to 15 stages 33 % faster at two.  The
 // global-memory mode takes two as well: its stage matrix sits in matrix-core
 // accumulators (112 registers per lane in FP64), L_{n+1}' F is formed before
 // they are live, and the lane offsets of the tile loops are recomputed per
@@ -2388,7 +2389,7 @@ struct Blk {
 // 44 % faster.
 __host__ __device__ constexpr int block_waves(int zm, int gm)
 {
-    return zm > 64 ? 2 : ((zm == 64 || (zm == 32 && gm == 0)) ? 2 : 1);
+    return 2;
 }
 
 // ZM > 64 selects the global-memory mode; WV overrides the register budget
